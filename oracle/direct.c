@@ -1,0 +1,143 @@
+/*
+ * ORACLE -- test infrastructure only.  Nothing in the product library links,
+ * calls or includes this file; only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg load the shared object built from it.
+ *
+ * Plain, slow, obviously correct CPU double-precision sums:
+ *
+ *   oracle_stokeslet_direct   free-space point sum with the self term
+ *                             excluded (Introduction, eq. stokes_stress_sum
+ *                             with the 3D Stokeslet of eq.
+ *                             stokeslet_def_deriv):
+ *                               u_j(x_b) = sum_{a != b} S_jl(x_b - x_a) f_{a,l},
+ *                               S_jl(y) = (1/8pi) (delta_jl/r + y_j y_l / r^3).
+ *
+ *   oracle_stokeslet_ewald_real
+ *                             the real-space half of the classical Hasimoto
+ *                             (Gaussian) Ewald split of the periodic sum
+ *                             (eq. periodic_sum, split eq. hasimoto-split),
+ *                             written through the general residual formula
+ *                             (eq. res_stokeslet / Soffdiag) with the Gaussian
+ *                             window phi_G(r) = (xi/sqrt(pi)) exp(-xi^2 r^2),
+ *                             whose erfc-like function is Phi_G(r) = erfc(xi r):
+ *                               S_R = (1/8pi)[(erfc(xi r) - 2 xi r e^{-xi^2 r^2}/sqrt(pi)) delta/r
+ *                                           + (erfc(xi r) + 2 xi r e^{-xi^2 r^2}/sqrt(pi)) y y^T / r^3].
+ *                             The Fourier half and the self term live in
+ *                             ewald.py.
+ *
+ * Conventions: points and forces are row-major (n,3) arrays; targets are a
+ * list of source indices (the target is also a source, and the pair a == b is
+ * skipped).  A pair of distinct but coincident points (r == 0) contributes
+ * nothing -- the paper does not define it.  Sums are Neumaier-compensated.
+ */
+#include <math.h>
+#include <stdint.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+static inline void neumaier_add(double *s, double *c, double v)
+{
+    double t = *s + v;
+    if (fabs(*s) >= fabs(v))
+        *c += (*s - t) + v;
+    else
+        *c += (v - t) + *s;
+    *s = t;
+}
+
+void oracle_stokeslet_direct(const double *x, const double *f, int64_t n,
+                             const int64_t *tgt, int64_t m, double *u)
+{
+    const double c8 = 1.0 / (8.0 * M_PI);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < m; ++t) {
+        const int64_t b = tgt[t];
+        const double xb0 = x[3 * b], xb1 = x[3 * b + 1], xb2 = x[3 * b + 2];
+        double s0 = 0, s1 = 0, s2 = 0, c0 = 0, c1 = 0, c2 = 0;
+        for (int64_t a = 0; a < n; ++a) {
+            if (a == b)
+                continue;
+            const double y0 = xb0 - x[3 * a], y1 = xb1 - x[3 * a + 1], y2 = xb2 - x[3 * a + 2];
+            const double r2 = y0 * y0 + y1 * y1 + y2 * y2;
+            if (r2 == 0.0)
+                continue;
+            const double r = sqrt(r2);
+            const double ir = 1.0 / r;
+            const double ir3 = ir * ir * ir;
+            const double f0 = f[3 * a], f1 = f[3 * a + 1], f2 = f[3 * a + 2];
+            const double yf = y0 * f0 + y1 * f1 + y2 * f2;
+            neumaier_add(&s0, &c0, c8 * (f0 * ir + yf * y0 * ir3));
+            neumaier_add(&s1, &c1, c8 * (f1 * ir + yf * y1 * ir3));
+            neumaier_add(&s2, &c2, c8 * (f2 * ir + yf * y2 * ir3));
+        }
+        u[3 * t] = s0 + c0;
+        u[3 * t + 1] = s1 + c1;
+        u[3 * t + 2] = s2 + c2;
+    }
+}
+
+/*
+ * Real-space Ewald part on the unit cell [0,1)^3.  Requires rc <= 1/2, so the
+ * minimum image of a difference vector is the only image that can lie within
+ * rc (every other image is at least 1/2 away in some coordinate).  The pair
+ * (a == b, image 0) is skipped.
+ */
+int oracle_stokeslet_ewald_real(const double *x, const double *f, int64_t n,
+                                const int64_t *tgt, int64_t m, double xi, double rc,
+                                double *u)
+{
+    if (!(rc > 0.0 && rc <= 0.5) || !(xi > 0.0))
+        return -1;
+    const double c8 = 1.0 / (8.0 * M_PI);
+    const double two_over_sqrtpi = 2.0 / sqrt(M_PI);
+    const double rc2 = rc * rc;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < m; ++t) {
+        const int64_t b = tgt[t];
+        const double xb0 = x[3 * b], xb1 = x[3 * b + 1], xb2 = x[3 * b + 2];
+        double s0 = 0, s1 = 0, s2 = 0, c0 = 0, c1 = 0, c2 = 0;
+        for (int64_t a = 0; a < n; ++a) {
+            if (a == b)
+                continue;
+            double y0 = xb0 - x[3 * a], y1 = xb1 - x[3 * a + 1], y2 = xb2 - x[3 * a + 2];
+            y0 -= nearbyint(y0);
+            y1 -= nearbyint(y1);
+            y2 -= nearbyint(y2);
+            const double r2 = y0 * y0 + y1 * y1 + y2 * y2;
+            if (r2 >= rc2 || r2 == 0.0)
+                continue;
+            const double r = sqrt(r2);
+            const double e = erfc(xi * r);
+            const double g = two_over_sqrtpi * xi * r * exp(-xi * xi * r2);
+            const double sdiag = e - g, soffd = e + g;
+            const double f0 = f[3 * a], f1 = f[3 * a + 1], f2 = f[3 * a + 2];
+            const double yf = y0 * f0 + y1 * f1 + y2 * f2;
+            const double a1 = c8 * sdiag / r, a2 = c8 * soffd * yf / (r2 * r);
+            neumaier_add(&s0, &c0, a1 * f0 + a2 * y0);
+            neumaier_add(&s1, &c1, a1 * f1 + a2 * y1);
+            neumaier_add(&s2, &c2, a1 * f2 + a2 * y2);
+        }
+        u[3 * t] = s0 + c0;
+        u[3 * t + 1] = s1 + c1;
+        u[3 * t + 2] = s2 + c2;
+    }
+    return 0;
+}
+
+int oracle_num_threads(void)
+{
+    int nt = 1;
+#pragma omp parallel
+    {
+#pragma omp master
+        {
+#ifdef _OPENMP
+            extern int omp_get_num_threads(void);
+            nt = omp_get_num_threads();
+#endif
+        }
+    }
+    return nt;
+}
