@@ -1,0 +1,166 @@
+/*
+ * dmk_stokes.h -- C ABI of the MI355X (gfx950) DMK Stokeslet library.
+ *
+ * Computes the 3D Stokeslet point sums of the paper's Introduction
+ * (eq. stokes_stress_sum with the Stokeslet of eq. stokeslet_def_deriv,
+ * viscosity 1):
+ *
+ *   free space:  u_j(x_b) = sum_{a != b} S_jl(x_b - x_a) f_{a,l},
+ *   periodic:    u_j(x_b) = sum_a sum_{p in Z^3}* S_jl(x_b - x_a + p) f_{a,l}
+ *                on the unit cell [0,1)^3 (eq. periodic_sum), with the k = 0
+ *                Fourier term dropped: zero mean flow (eq. ewald_far and the
+ *                remark after it);
+ *
+ *   S_jl(y) = (1/8pi) (delta_jl / |y| + y_j y_l / |y|^3),
+ *
+ * by the dual-space multilevel kernel-splitting method with the prolate
+ * (PSWF) splitting of the biharmonic kernel (Sec. "The DMK method", split of
+ * eqs. biharmonicks/bsplitdef, residual kernel eq. res_stokeslet, parameters
+ * of Table tab:params).  A pair of distinct but coincident points contributes
+ * nothing.
+ *
+ * Memory: every array argument of the plan/eval calls is a DEVICE pointer
+ * (hipMalloc'd or a torch CUDA tensor's data pointer) owned by the caller.
+ * The plan copies and reorders what it needs, so `points` may be freed once
+ * dmk_stokes_plan returns.  dmk_stokes_eval only enqueues work on the plan's
+ * stream and returns; `forces` and `velocities` must stay valid until the
+ * stream reaches that point.  Host-only diagnostics take host pointers.
+ *
+ * Errors: every call returns a dmk_status; on failure no plan is created
+ * (*out is set to NULL) and dmk_last_error() describes the cause in a
+ * thread-local string.  Calls never throw across the ABI.
+ */
+#ifndef DMK_STOKES_H
+#define DMK_STOKES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dmk_plan_s* dmk_plan_t;
+
+typedef enum {
+    DMK_OK = 0,
+    DMK_ERR_ARG = -1,          /* null / non-device pointer, n < 1, n_rhs < 1, bad option */
+    DMK_ERR_UNSUPPORTED = -2,  /* dim != 3 */
+    DMK_ERR_DOMAIN = -3,       /* periodic point outside [0,1)^3 */
+    DMK_ERR_NONFINITE = -4,    /* NaN or Inf among the points */
+    DMK_ERR_TOL = -5,          /* tol outside [1e-12, 1e-3] (mixed precision: [1e-7, 1e-3]) */
+    DMK_ERR_OOM = -6,          /* device allocation failed or exceeds opts.mem_cap_bytes */
+    DMK_ERR_HIP = -7           /* a HIP runtime call failed */
+} dmk_status;
+
+typedef enum { DMK_PREC_FP64 = 0, DMK_PREC_MIXED = 1 } dmk_precision;
+
+typedef struct {
+    int precision;        /* dmk_precision */
+    int leaf_size;        /* maximum points per leaf; 0 = the tolerance's default */
+    void* stream;         /* hipStream_t for all work of the plan; NULL = null stream */
+    size_t mem_cap_bytes; /* refuse plans whose device buffers exceed this; 0 = no cap */
+} dmk_opts;
+
+typedef struct {
+    /* parameters (Table tab:params, Stokeslet, PSWF columns) */
+    double tol, c;
+    int q, p, n1, nper, leaf_size;
+    int deg_P, deg_Q;           /* degrees of the near-field radial polynomials */
+    /* tree */
+    int levels;                 /* deepest level + 1 */
+    int periodic;
+    int64_t n_points, n_boxes, n_leaves, n_nonempty_boxes, n_nonempty_leaves;
+    int64_t near_pairs;         /* sum over near-list entries of |target leaf| * |source leaf| */
+    int64_t n_senders, n_receivers;
+    double center[3], box_len;  /* unit box <-> input coordinates */
+    size_t device_bytes;
+    double plan_ms;             /* wall time of the plan call */
+} dmk_plan_info;
+
+/*
+ * Builds a plan: parameters and tables for `tol`, the level-restricted
+ * adaptive octree of the points, neighbour lists and device buffers.
+ *   points    device, (n,3) row-major float64.  Free space: any finite
+ *             coordinates (mapped to the unit box by their bounding cube).
+ *             Periodic: inside the unit cell [0,1)^3.
+ *   n         number of points (sources = targets), >= 1
+ *   dim       must be 3
+ *   periodic  0 = free space, 1 = periodic unit cell
+ *   tol       requested relative l2 accuracy, in [1e-12, 1e-3]; the plan uses
+ *             the Table tab:params row with the largest tolerance <= tol
+ *   out       receives the plan (NULL on failure)
+ * Synchronises the stream once (tree sizes are needed on the host).
+ */
+int dmk_stokes_plan(const double* points, int64_t n, int dim, int periodic, double tol, dmk_plan_t* out);
+
+/* As dmk_stokes_plan with options (opts may be NULL = defaults). */
+int dmk_stokes_plan_ex(const double* points, int64_t n, int dim, int periodic, double tol, const dmk_opts* opts,
+                       dmk_plan_t* out);
+
+/*
+ * Evaluates the sums for n_rhs force vectors on the plan's points.
+ *   forces      device, (n_rhs, n, 3) float64, caller's point order
+ *   velocities  device, (n_rhs, n, 3) float64, overwritten
+ * Stream-ordered, no host synchronisation; several calls on one plan must
+ * not overlap (they share the plan's work buffers).
+ */
+int dmk_stokes_eval(dmk_plan_t plan, const double* forces, int n_rhs, double* velocities);
+
+/* Fills *info (host struct) with the plan's parameters and statistics. */
+int dmk_stokes_plan_info(dmk_plan_t plan, dmk_plan_info* info);
+
+/*
+ * Tree export for checks (host arrays, each sized by dmk_plan_info):
+ *   leaf_level[L], leaf_coord[3L] (integer box coordinates at that level),
+ *   leaf_count[L] for all L = n_leaves leaves (empty ones included), and
+ *   point_leaf[n]: index of the leaf holding each point (caller's order).
+ * Any pointer may be NULL to skip that array.  Synchronises the stream.
+ */
+int dmk_stokes_tree_leaves(dmk_plan_t plan, int32_t* leaf_level, int64_t* leaf_coord, int64_t* leaf_count,
+                           int64_t* point_leaf);
+
+/* Releases the plan and its device memory (NULL-safe). */
+void dmk_stokes_destroy(dmk_plan_t plan);
+
+/* Thread-local description of the last failure of this thread. */
+const char* dmk_last_error(void);
+
+/* ---- host-only diagnostics (no GPU needed; host pointers) ------------------ */
+
+/* Parameters the plan would use for tol (other fields zero). */
+int dmk_stokes_params(double tol, dmk_plan_info* info);
+
+/*
+ * Window and near-field radial functions at unit scale for tol, at n radii:
+ *   out[4i+0] = phi(rho)            (eq. wfunc_prol_G)
+ *   out[4i+1] = Phi(rho)            (eq. def_erfc_like_fcn)
+ *   out[4i+2] = P(rho^2), out[4i+3] = Q(rho^2), the polynomial fits with
+ *     S_R(y) = S(y) - [P(s) I + Q(s) y y^T]/(4 pi),  s = |y|^2 < 1
+ *     (eq. res_stokeslet/Soffdiag rearranged).
+ */
+int dmk_stokes_radial(double tol, const double* rho, int64_t n, double* out);
+
+/* Window transform and biharmonic mollifier (eq. gammaB_in_phi) at n wave
+ * numbers: out[2i] = phihat(k), out[2i+1] = gammahat(k). */
+int dmk_stokes_mollifier(double tol, const double* k, int64_t n, double* out);
+
+/* ---- device stage entry point ------------------------------------------------ */
+
+/*
+ * Residual-kernel sums by brute force over all sources, at scale r_lambda:
+ *   out[i] = sum_a S_R^{r_lambda}(t_i - s_a) f_a   (pairs with r = 0 skipped),
+ * S_R as in eq. res_stokeslet evaluated at r / r_lambda (the scaling remark
+ * of Sec. "The Stokes kernels"), with the same device pair routine as the
+ * near field of dmk_stokes_eval.
+ *   targets (m,3), sources (ns,3), forces (ns,3), out (m,3): device float64
+ *   stream: hipStream_t or NULL.  Stream-ordered.
+ */
+int dmk_stokes_residual_sum(const double* targets, int64_t m, const double* sources, const double* forces,
+                            int64_t ns, double r_lambda, double tol, void* stream, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMK_STOKES_H */

@@ -1,0 +1,210 @@
+"""ctypes binding of libdmk_stokes.so (argument marshalling only).
+
+Every computation runs in the HIP library; torch is used only to own device
+memory and to name the stream.  Importing works without a GPU (host-only
+diagnostics are callable); plan/eval raise if the library or a GPU is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(HERE, "libdmk_stokes.so")
+
+DMK_OK = 0
+STATUS = {0: "DMK_OK", -1: "DMK_ERR_ARG", -2: "DMK_ERR_UNSUPPORTED", -3: "DMK_ERR_DOMAIN",
+          -4: "DMK_ERR_NONFINITE", -5: "DMK_ERR_TOL", -6: "DMK_ERR_OOM", -7: "DMK_ERR_HIP"}
+PREC_FP64, PREC_MIXED = 0, 1
+
+SYMBOLS = ["dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_eval", "dmk_stokes_plan_info",
+           "dmk_stokes_tree_leaves", "dmk_stokes_destroy", "dmk_last_error", "dmk_stokes_params",
+           "dmk_stokes_radial", "dmk_stokes_mollifier", "dmk_stokes_residual_sum"]
+
+
+class DMKError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("leaf_size", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("mem_cap_bytes", ctypes.c_size_t)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("c", ctypes.c_double), ("q", ctypes.c_int), ("p", ctypes.c_int),
+                ("n1", ctypes.c_int), ("nper", ctypes.c_int), ("leaf_size", ctypes.c_int),
+                ("deg_P", ctypes.c_int), ("deg_Q", ctypes.c_int), ("levels", ctypes.c_int),
+                ("periodic", ctypes.c_int), ("n_points", ctypes.c_int64), ("n_boxes", ctypes.c_int64),
+                ("n_leaves", ctypes.c_int64), ("n_nonempty_boxes", ctypes.c_int64),
+                ("n_nonempty_leaves", ctypes.c_int64), ("near_pairs", ctypes.c_int64),
+                ("n_senders", ctypes.c_int64), ("n_receivers", ctypes.c_int64),
+                ("center", ctypes.c_double * 3), ("box_len", ctypes.c_double),
+                ("device_bytes", ctypes.c_size_t), ("plan_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if name == "center" else v
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO_PATH):
+            raise RuntimeError(f"{SO_PATH} is missing: run paper_2509_21471_amd.build.build() first")
+        L = ctypes.CDLL(SO_PATH)
+        vp, dp, i64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int64
+        L.dmk_stokes_plan.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(vp)]
+        L.dmk_stokes_plan_ex.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                         ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+        L.dmk_stokes_eval.argtypes = [vp, vp, ctypes.c_int, vp]
+        L.dmk_stokes_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+        L.dmk_stokes_tree_leaves.argtypes = [vp, vp, vp, vp, vp]
+        L.dmk_stokes_destroy.argtypes = [vp]
+        L.dmk_stokes_destroy.restype = None
+        L.dmk_last_error.argtypes = []
+        L.dmk_last_error.restype = ctypes.c_char_p
+        L.dmk_stokes_params.argtypes = [ctypes.c_double, ctypes.POINTER(PlanInfo)]
+        L.dmk_stokes_radial.argtypes = [ctypes.c_double, dp, i64, dp]
+        L.dmk_stokes_mollifier.argtypes = [ctypes.c_double, dp, i64, dp]
+        L.dmk_stokes_residual_sum.argtypes = [vp, i64, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp]
+        for s in SYMBOLS:
+            if s not in ("dmk_stokes_destroy", "dmk_last_error"):
+                getattr(L, s).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != DMK_OK:
+        raise DMKError(rc, lib().dmk_last_error().decode())
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ---- host-only diagnostics ------------------------------------------------------
+def params(tol: float) -> dict:
+    info = PlanInfo()
+    _check(lib().dmk_stokes_params(float(tol), ctypes.byref(info)))
+    return info.as_dict()
+
+
+def radial(tol: float, rho) -> np.ndarray:
+    rho = np.ascontiguousarray(rho, dtype=np.float64).ravel()
+    out = np.zeros((rho.size, 4))
+    _check(lib().dmk_stokes_radial(float(tol), _dp(rho), rho.size, _dp(out)))
+    return out
+
+
+def mollifier(tol: float, k) -> np.ndarray:
+    k = np.ascontiguousarray(k, dtype=np.float64).ravel()
+    out = np.zeros((k.size, 2))
+    _check(lib().dmk_stokes_mollifier(float(tol), _dp(k), k.size, _dp(out)))
+    return out
+
+
+# ---- device entry points --------------------------------------------------------
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the DMK library runs on gfx950 only")
+    return torch
+
+
+def _dev_f64(t, shape_last=3):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.asarray(t, dtype=np.float64))
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        t = t.to(device="cuda", dtype=torch.float64).contiguous()
+    if t.shape[-1] != shape_last:
+        raise ValueError(f"last dimension must be {shape_last}")
+    return t
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A DMK plan over device points (sources = targets)."""
+
+    def __init__(self, points, periodic: bool = False, tol: float = 1e-6, precision: int = PREC_FP64,
+                 leaf_size: int = 0, stream=None, mem_cap_bytes: int = 0):
+        torch = _torch()
+        pts = _dev_f64(points)
+        self.n = int(pts.shape[0])
+        self.stream = stream
+        opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), int(mem_cap_bytes))
+        h = ctypes.c_void_p()
+        _check(lib().dmk_stokes_plan_ex(ctypes.c_void_p(pts.data_ptr()), self.n, 3, int(bool(periodic)),
+                                        float(tol), ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self._torch = torch
+
+    def eval(self, forces, out=None):
+        torch = self._torch
+        f = _dev_f64(forces)
+        n_rhs = 1 if f.dim() == 2 else int(f.shape[0])
+        if f.shape[-2] != self.n:
+            raise ValueError("forces must have shape (n,3) or (n_rhs,n,3)")
+        if out is None:
+            out = torch.empty_like(f)
+        _check(lib().dmk_stokes_eval(self._h, ctypes.c_void_p(f.data_ptr()), n_rhs,
+                                     ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def info(self) -> dict:
+        info = PlanInfo()
+        _check(lib().dmk_stokes_plan_info(self._h, ctypes.byref(info)))
+        return info.as_dict()
+
+    def tree_leaves(self):
+        info = self.info()
+        L = int(info["n_leaves"])
+        lev = np.zeros(L, dtype=np.int32)
+        crd = np.zeros((L, 3), dtype=np.int64)
+        cnt = np.zeros(L, dtype=np.int64)
+        pl = np.zeros(self.n, dtype=np.int64)
+        _check(lib().dmk_stokes_tree_leaves(self._h, lev.ctypes.data, crd.ctypes.data, cnt.ctypes.data,
+                                            pl.ctypes.data))
+        return lev, crd, cnt, pl
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().dmk_stokes_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def residual_sum(targets, sources, forces, r_lambda: float, tol: float, stream=None):
+    torch = _torch()
+    t = _dev_f64(targets)
+    s = _dev_f64(sources)
+    f = _dev_f64(forces)
+    out = torch.empty_like(t)
+    _check(lib().dmk_stokes_residual_sum(ctypes.c_void_p(t.data_ptr()), int(t.shape[0]),
+                                         ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                                         int(s.shape[0]), float(r_lambda), float(tol), _stream_ptr(stream),
+                                         ctypes.c_void_p(out.data_ptr())))
+    return out

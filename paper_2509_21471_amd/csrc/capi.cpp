@@ -1,0 +1,833 @@
+// C ABI: plan construction (tree, lists, buffers) and the evaluation pass.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dmk_stokes.h"
+#include "dmk_kernels.hpp"
+#include "kernel_math.hpp"
+#include "tree.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(DMK_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+
+bool is_device_ptr(const void* p)
+{
+    if (!p)
+        return false;
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+// device allocation registry with an optional cap
+struct DevMem {
+    std::vector<void*> ptrs;
+    size_t total = 0, cap = 0;
+    bool oom = false;
+    template <class T>
+    T* alloc(size_t count)
+    {
+        if (count == 0)
+            count = 1;
+        const size_t bytes = count * sizeof(T);
+        if (cap && total + bytes > cap) {
+            oom = true;
+            return nullptr;
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            oom = true;
+            return nullptr;
+        }
+        ptrs.push_back(p);
+        total += bytes;
+        return (T*)p;
+    }
+    ~DevMem()
+    {
+        for (void* p : ptrs)
+            (void)hipFree(p);
+    }
+};
+
+template <class T>
+hipError_t upload(T* dst, const std::vector<T>& src)
+{
+    if (src.empty())
+        return hipSuccess;
+    return hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+struct dmk_plan_s {
+    dmk::Params prm;
+    const dmk::Tables* tab = nullptr;
+    hipStream_t stream = nullptr;
+    int precision = 0;
+    int64_t n = 0;
+    bool periodic = false;
+    double center[3] = {0, 0, 0}, box_len = 1.0;
+    dmk::Tree tree;
+    DevMem mem;
+    double plan_ms = 0;
+
+    // points
+    int* perm = nullptr;       // sorted position -> caller index
+    double *x = nullptr, *y = nullptr, *z = nullptr;
+    // tables on device
+    double *cheb_t = nullptr, *cheb_w = nullptr, *up = nullptr, *down = nullptr;
+    dmk::cplx *e_half = nullptr, *e_full = nullptr, *g_half = nullptr, *g_full = nullptr;
+    dmk::cplx *r_e_half = nullptr, *r_e_full = nullptr, *r_g_half = nullptr, *r_g_full = nullptr;
+    double *wdiff = nullptr, *wroot = nullptr;
+    int root_mh = 0, root_mf = 0;
+    dmk::RadialPoly poly;
+    // far-field structure
+    int nf = 0;                       // non-empty boxes (far-field slots)
+    int root_fid = 0;
+    std::vector<int> box_fid;         // box id -> fid or -1
+    dmk::LeafDesc* leaves = nullptr;  // non-empty leaves
+    int nleaf = 0;
+    struct LevelLists {
+        int nparent = 0;
+        int* child_fid = nullptr;     // 8 per parent
+        int* parent_fid = nullptr;
+    };
+    std::vector<LevelLists> lev;
+    int nsend = 0, nrecv = 0;
+    int* send_fid = nullptr;          // sender slot -> fid
+    int* recv_fid = nullptr;          // receiver slot -> fid
+    dmk::RecvDesc* recv = nullptr;
+    int* e_src = nullptr;
+    int8_t* e_off = nullptr;
+    // near field
+    dmk::NearLeaf* nleaves = nullptr;
+    dmk::NearEntryDev* nentries = nullptr;
+    dmk::NearWork* nwork = nullptr;
+    int n_nwork = 0;
+    double* cbbox = nullptr;
+    // work buffers
+    double* fs = nullptr;             // sorted forces [3][n]
+    double* u = nullptr;              // sorted velocities [3][n]
+    double *Q = nullptr, *V = nullptr;
+    dmk::cplx *Phi = nullptr, *Psi = nullptr;
+    void *s1 = nullptr, *s2 = nullptr;
+    dmk::cplx *phi_root = nullptr, *psi_root = nullptr;
+    double* cst = nullptr;
+    size_t H = 0, Hroot = 0;
+    std::vector<int> leaf_box;        // leaf index (all leaves) -> box id
+};
+
+namespace {
+
+int validate_common(int dim, double tol, const dmk_opts* opts)
+{
+    if (dim != 3)
+        return fail(DMK_ERR_UNSUPPORTED, "only dim = 3 is supported");
+    if (!(tol >= 1e-12 * (1 - 1e-9) && tol <= 1e-3 * (1 + 1e-9)))
+        return fail(DMK_ERR_TOL, "tol must lie in [1e-12, 1e-3]");
+    if (opts) {
+        if (opts->precision != DMK_PREC_FP64 && opts->precision != DMK_PREC_MIXED)
+            return fail(DMK_ERR_ARG, "unknown precision");
+        if (opts->precision == DMK_PREC_MIXED && tol < 1e-7 * (1 - 1e-9))
+            return fail(DMK_ERR_TOL, "mixed precision needs tol >= 1e-7");
+        if (opts->leaf_size < 0)
+            return fail(DMK_ERR_ARG, "leaf_size must be >= 0");
+    }
+    return DMK_OK;
+}
+
+// Contracts the leading axis of every (slot, component) tensor.
+void contract(dmk_plan_t P, const void* X, long xs, const int* xmap, int xkind, const void* M, int mc, void* Y,
+              long ys, const int* ymap, int ymode, int K, int R, int N, int nslots)
+{
+    dmk::ContractArgs a;
+    a.X = X;
+    a.xstride = xs;
+    a.xmap = xmap;
+    a.xkind = xkind;
+    a.M = M;
+    a.mcplx = mc;
+    a.Y = Y;
+    a.ystride = ys;
+    a.ymap = ymap;
+    a.ymode = ymode;
+    a.K = K;
+    a.R = R;
+    a.N = N;
+    a.nslots = nslots;
+    dmk::launch_contract(a, P->stream);
+}
+
+int build_plan(dmk_plan_t P, const double* points)
+{
+    using namespace dmk;
+    hipStream_t st = P->stream;
+    const int64_t n = P->n;
+    // ---- bounding box and finiteness ----
+    const int nblk = (int)std::min<int64_t>(1024, (n + 255) / 256);
+    double* part = P->mem.alloc<double>((size_t)nblk * 8);
+    if (!part)
+        return fail(DMK_ERR_OOM, "device allocation failed");
+    launch_bbox(points, n, part, nblk, st);
+    std::vector<double> hp((size_t)nblk * 8);
+    HIPCHK(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, bad = 0;
+    for (int b = 0; b < nblk; ++b) {
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], hp[8 * b + d]);
+            hi[d] = std::max(hi[d], hp[8 * b + 3 + d]);
+        }
+        bad += hp[8 * b + 6];
+    }
+    if (bad > 0)
+        return fail(DMK_ERR_NONFINITE, "points contain NaN or Inf");
+    double inv_len;
+    if (P->periodic) {
+        for (int d = 0; d < 3; ++d)
+            if (lo[d] < 0.0 || hi[d] >= 1.0)
+                return fail(DMK_ERR_DOMAIN, "periodic points must lie in [0,1)^3");
+        P->center[0] = P->center[1] = P->center[2] = 0.5;
+        P->box_len = 1.0;
+    } else {
+        double ext = 0;
+        for (int d = 0; d < 3; ++d) {
+            P->center[d] = 0.5 * (lo[d] + hi[d]);
+            ext = std::max(ext, hi[d] - lo[d]);
+        }
+        if (ext <= 0)
+            ext = 1.0;
+        // slightly larger cube so that all unit coordinates lie in [-1/2, 1/2)
+        P->box_len = ext * (1.0 + 1e-9);
+    }
+    inv_len = 1.0 / P->box_len;
+    // ---- Morton keys and sort ----
+    uint64_t* k0 = P->mem.alloc<uint64_t>(n);
+    uint64_t* k1 = P->mem.alloc<uint64_t>(n);
+    int* i0 = P->mem.alloc<int>(n);
+    P->perm = P->mem.alloc<int>(n);
+    const size_t tb = sort_temp_bytes(n);
+    void* tmp = P->mem.alloc<char>(tb);
+    if (P->mem.oom)
+        return fail(DMK_ERR_OOM, "device allocation failed");
+    launch_morton(points, n, P->center[0], P->center[1], P->center[2], inv_len, k0, i0, st);
+    launch_sort(tmp, tb, k0, k1, i0, P->perm, n, 3 * kKeyBits, st);
+    std::vector<uint64_t> keys(n);
+    HIPCHK(hipMemcpyAsync(keys.data(), k1, n * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    // ---- tree ----
+    const int ns = P->prm.ns;
+    build_tree(keys.data(), n, ns, P->periodic, &P->tree);
+    const Tree& T = P->tree;
+    // ---- sorted points ----
+    P->x = P->mem.alloc<double>(n);
+    P->y = P->mem.alloc<double>(n);
+    P->z = P->mem.alloc<double>(n);
+    if (P->mem.oom)
+        return fail(DMK_ERR_OOM, "device allocation failed");
+    launch_gather_points(points, n, P->perm, P->center[0], P->center[1], P->center[2], inv_len, P->x, P->y, P->z,
+                         st);
+    // ---- far-field slots ----
+    const int nb = (int)T.boxes.size();
+    P->box_fid.assign(nb, -1);
+    P->nf = 0;
+    for (int i = 0; i < nb; ++i)
+        if (T.boxes[i].end > T.boxes[i].start)
+            P->box_fid[i] = P->nf++;
+    P->root_fid = P->box_fid[0];
+    auto center = [&](const Box& B, double* c) {
+        const double h = 1.0 / (double)(1ll << B.level);
+        c[0] = -0.5 + (B.ix + 0.5) * h;
+        c[1] = -0.5 + (B.iy + 0.5) * h;
+        c[2] = -0.5 + (B.iz + 0.5) * h;
+    };
+    std::vector<LeafDesc> hl;
+    P->leaf_box.clear();
+    for (int i = 0; i < nb; ++i) {
+        const Box& B = T.boxes[i];
+        if (!B.leaf)
+            continue;
+        P->leaf_box.push_back(i);
+        if (B.end == B.start)
+            continue;
+        LeafDesc d;
+        d.fid = P->box_fid[i];
+        d.level = B.level;
+        d.start = B.start;
+        d.end = B.end;
+        double c[3];
+        center(B, c);
+        d.cx = c[0];
+        d.cy = c[1];
+        d.cz = c[2];
+        hl.push_back(d);
+    }
+    P->nleaf = (int)hl.size();
+    P->leaves = P->mem.alloc<LeafDesc>(hl.size());
+    // per-level parent lists (non-empty, non-leaf)
+    P->lev.assign(T.max_level + 1, {});
+    for (int l = 0; l < T.max_level; ++l) {
+        std::vector<int> cf, pf;
+        for (int i = T.level_start[l]; i < T.level_start[l + 1]; ++i) {
+            const Box& B = T.boxes[i];
+            if (B.leaf || B.end == B.start)
+                continue;
+            pf.push_back(P->box_fid[i]);
+            for (int d = 0; d < 8; ++d)
+                cf.push_back(B.child[d] >= 0 ? P->box_fid[B.child[d]] : -1);
+        }
+        P->lev[l].nparent = (int)pf.size();
+        P->lev[l].child_fid = P->mem.alloc<int>(cf.size());
+        P->lev[l].parent_fid = P->mem.alloc<int>(pf.size());
+        if (P->mem.oom)
+            return fail(DMK_ERR_OOM, "device allocation failed");
+        HIPCHK(upload(P->lev[l].child_fid, cf));
+        HIPCHK(upload(P->lev[l].parent_fid, pf));
+    }
+    // senders / receivers (difference-kernel exchange lists)
+    std::vector<int> send_slot(nb, -1), sfid, rfid, esrc;
+    std::vector<int8_t> eoff;
+    std::vector<RecvDesc> rd;
+    for (int i = 0; i < nb; ++i)
+        for (const FarEntry& e : T.incoming[i])
+            if (send_slot[e.src] < 0) {
+                send_slot[e.src] = (int)sfid.size();
+                sfid.push_back(P->box_fid[e.src]);
+            }
+    for (int i = 0; i < nb; ++i) {
+        if (T.incoming[i].empty())
+            continue;
+        RecvDesc r;
+        r.slot = (int)rfid.size();
+        r.level = T.boxes[i].level;
+        r.ebeg = (int)esrc.size();
+        for (const FarEntry& e : T.incoming[i]) {
+            esrc.push_back(send_slot[e.src]);
+            eoff.push_back(e.ox);
+            eoff.push_back(e.oy);
+            eoff.push_back(e.oz);
+        }
+        r.eend = (int)esrc.size();
+        rfid.push_back(P->box_fid[i]);
+        rd.push_back(r);
+    }
+    P->nsend = (int)sfid.size();
+    P->nrecv = (int)rfid.size();
+    P->send_fid = P->mem.alloc<int>(sfid.size());
+    P->recv_fid = P->mem.alloc<int>(rfid.size());
+    P->recv = P->mem.alloc<RecvDesc>(rd.size());
+    P->e_src = P->mem.alloc<int>(esrc.size());
+    P->e_off = P->mem.alloc<int8_t>(eoff.size());
+    // near field: chunks of 64 sorted points per non-empty leaf
+    std::vector<int> leaf_cbase(nb, -1);
+    std::vector<int64_t> cstart;
+    std::vector<int> clen;
+    for (int li = 0; li < (int)T.leaves.size(); ++li) {
+        const Box& B = T.boxes[T.leaves[li]];
+        leaf_cbase[T.leaves[li]] = (int)cstart.size();
+        for (int64_t s = B.start; s < B.end; s += 64) {
+            cstart.push_back(s);
+            clen.push_back((int)std::min<int64_t>(64, B.end - s));
+        }
+    }
+    std::vector<NearLeaf> nlv;
+    std::vector<NearEntryDev> nent;
+    std::vector<NearWork> nwk;
+    for (int li = 0; li < (int)T.leaves.size(); ++li) {
+        const Box& B = T.boxes[T.leaves[li]];
+        NearLeaf L;
+        L.tstart = B.start;
+        L.tend = B.end;
+        L.level = B.level;
+        L.cbase = leaf_cbase[T.leaves[li]];
+        L.ebeg = (int)nent.size();
+        for (const NearEntry& e : T.near[li]) {
+            const Box& S = T.boxes[e.src];
+            NearEntryDev d;
+            d.sstart = S.start;
+            d.send = S.end;
+            d.cbase = leaf_cbase[e.src];
+            d.sx = e.sx;
+            d.sy = e.sy;
+            d.sz = e.sz;
+            d.lambda = e.lambda;
+            nent.push_back(d);
+        }
+        L.eend = (int)nent.size();
+        const int nch = (int)((B.end - B.start + 63) / 64);
+        for (int c = 0; c < nch; ++c)
+            nwk.push_back(NearWork{li, c});
+        nlv.push_back(L);
+    }
+    P->n_nwork = (int)nwk.size();
+    P->nleaves = P->mem.alloc<NearLeaf>(nlv.size());
+    P->nentries = P->mem.alloc<NearEntryDev>(nent.size());
+    P->nwork = P->mem.alloc<NearWork>(nwk.size());
+    P->cbbox = P->mem.alloc<double>(cstart.size() * 6);
+    int64_t* d_cstart = P->mem.alloc<int64_t>(cstart.size());
+    int* d_clen = P->mem.alloc<int>(clen.size());
+    // tables
+    const Tables& TB = *P->tab;
+    const int p = P->prm.p, q = P->prm.q, n1 = P->prm.n1;
+    std::vector<double> ct(p), cw(p);
+    for (int a = 0; a < p; ++a) {
+        ct[a] = TB.cheb_t[a];
+        cw[a] = ((a & 1) ? -1.0 : 1.0) * std::sin((2.0 * a + 1) * kPi / (2.0 * p));
+    }
+    P->cheb_t = P->mem.alloc<double>(p);
+    P->cheb_w = P->mem.alloc<double>(p);
+    P->up = P->mem.alloc<double>(TB.up.size());
+    P->down = P->mem.alloc<double>(TB.down.size());
+    auto cup = [&](const std::vector<std::complex<double>>& v) {
+        cplx* d = P->mem.alloc<cplx>(v.size());
+        if (d)
+            (void)hipMemcpy(d, v.data(), v.size() * sizeof(cplx), hipMemcpyHostToDevice);
+        return d;
+    };
+    P->e_half = cup(TB.e_half);
+    P->e_full = cup(TB.e_full);
+    P->g_half = cup(TB.g_half);
+    P->g_full = cup(TB.g_full);
+    if (P->periodic) {
+        P->r_e_half = cup(TB.p_e_half);
+        P->r_e_full = cup(TB.p_e_full);
+        P->r_g_half = cup(TB.p_g_half);
+        P->r_g_full = cup(TB.p_g_full);
+        P->root_mh = TB.per_m + 1;
+        P->root_mf = 2 * TB.per_m + 1;
+    } else {
+        P->r_e_half = cup(TB.r_e_half);
+        P->r_e_full = cup(TB.r_e_full);
+        P->r_g_half = cup(TB.r_g_half);
+        P->r_g_full = cup(TB.r_g_full);
+        P->root_mh = TB.root_m + 1;
+        P->root_mf = 2 * TB.root_m + 1;
+    }
+    const std::vector<double>& wr = P->periodic ? TB.wper : TB.wroot;
+    P->wdiff = P->mem.alloc<double>(TB.wdiff.size());
+    P->wroot = P->mem.alloc<double>(wr.size());
+    // work buffers
+    P->H = (size_t)q * n1 * n1;
+    P->Hroot = (size_t)P->root_mh * P->root_mf * P->root_mf;
+    const size_t p3 = (size_t)p * p * p;
+    P->fs = P->mem.alloc<double>(3 * n);
+    P->u = P->mem.alloc<double>(3 * n);
+    P->Q = P->mem.alloc<double>((size_t)P->nf * 3 * p3);
+    P->V = P->mem.alloc<double>((size_t)P->nf * 3 * p3);
+    P->Phi = P->mem.alloc<cplx>((size_t)P->nsend * 3 * P->H);
+    P->Psi = P->mem.alloc<cplx>((size_t)P->nrecv * 3 * P->H);
+    // scratch: largest intermediate of any stage, per (slot, component)
+    size_t per = 0;
+    per = std::max(per, (size_t)p * p * q * 16);                 // outgoing stage 1
+    per = std::max(per, (size_t)p * q * n1 * 16);                // outgoing stage 2
+    per = std::max(per, (size_t)n1 * n1 * p * 16);               // incoming stage 1
+    per = std::max(per, (size_t)n1 * p * p * 16);                // incoming stage 2
+    per = std::max(per, (size_t)8 * p3 * 8);                     // merge/interp stages
+    int maxslots = std::max(P->nsend, P->nrecv);
+    for (auto& L : P->lev)
+        maxslots = std::max(maxslots, L.nparent);
+    maxslots = std::max(maxslots, 1);
+    size_t per_root = 0;
+    {
+        const size_t mh = P->root_mh, mf = P->root_mf;
+        per_root = std::max({(size_t)p * p * mh, (size_t)p * mh * mf, mf * mf * (size_t)p, mf * (size_t)p * p}) * 16;
+    }
+    const size_t sbytes = std::max(per * 3 * (size_t)maxslots, per_root * 3);
+    P->s1 = P->mem.alloc<char>(sbytes);
+    P->s2 = P->mem.alloc<char>(sbytes);
+    P->phi_root = P->mem.alloc<cplx>(3 * P->Hroot);
+    P->psi_root = P->mem.alloc<cplx>(3 * P->Hroot);
+    P->cst = P->mem.alloc<double>(3);
+    if (P->mem.oom)
+        return fail(DMK_ERR_OOM, "device allocation failed (or above mem_cap_bytes)");
+    HIPCHK(upload(P->leaves, hl));
+    HIPCHK(upload(P->send_fid, sfid));
+    HIPCHK(upload(P->recv_fid, rfid));
+    HIPCHK(upload(P->recv, rd));
+    HIPCHK(upload(P->e_src, esrc));
+    HIPCHK(upload(P->e_off, eoff));
+    HIPCHK(upload(P->nleaves, nlv));
+    HIPCHK(upload(P->nentries, nent));
+    HIPCHK(upload(P->nwork, nwk));
+    HIPCHK(upload(d_cstart, cstart));
+    HIPCHK(upload(d_clen, clen));
+    HIPCHK(upload(P->cheb_t, ct));
+    HIPCHK(upload(P->cheb_w, cw));
+    HIPCHK(upload(P->up, TB.up));
+    HIPCHK(upload(P->down, TB.down));
+    HIPCHK(upload(P->wdiff, TB.wdiff));
+    HIPCHK(upload(P->wroot, wr));
+    launch_chunk_bbox(P->x, P->y, P->z, d_cstart, d_clen, (int)cstart.size(), P->cbbox, st);
+    // radial polynomials
+    if (TB.fits.P.a.size() > 48 || TB.fits.Q.a.size() > 48)
+        return fail(DMK_ERR_UNSUPPORTED, "radial fit degree too high");
+    P->poly.nP = (int)TB.fits.P.a.size();
+    P->poly.nQ = (int)TB.fits.Q.a.size();
+    for (int k = 0; k < 48; ++k) {
+        P->poly.P[k] = k < P->poly.nP ? TB.fits.P.a[k] : 0.0;
+        P->poly.Q[k] = k < P->poly.nQ ? TB.fits.Q.a[k] : 0.0;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    return DMK_OK;
+}
+
+int eval_one(dmk_plan_t P, const double* f, double* vel)
+{
+    using namespace dmk;
+    hipStream_t st = P->stream;
+    const int64_t n = P->n;
+    const int p = P->prm.p, q = P->prm.q, n1 = P->prm.n1;
+    const long p3 = (long)p * p * p, p2 = (long)p * p;
+    const Tree& T = P->tree;
+    launch_gather_forces(f, n, P->perm, P->fs, st);
+    // Step 2a: proxy charges of the leaves
+    launch_anterp(p, P->leaves, P->nleaf, P->x, P->y, P->z, P->fs, n, P->cheb_t, P->cheb_w, P->Q, st);
+    // Step 2b: merge children into parents, finest level first
+    for (int l = T.max_level - 1; l >= 0; --l) {
+        const auto& L = P->lev[l];
+        if (!L.nparent)
+            continue;
+        launch_merge_stage1(p, L.child_fid, L.nparent, P->Q, P->up, (double*)P->s1, st);
+        contract(P, P->s1, 4 * p3, nullptr, X_REAL, P->up, 0, P->s2, 2 * p3, nullptr, Y_STORE_REAL, 2 * p,
+                 2 * p * p, p, L.nparent);
+        contract(P, P->s2, 2 * p3, nullptr, X_REAL, P->up, 0, P->Q, p3, L.parent_fid, Y_STORE_REAL, 2 * p, p * p, p,
+                 L.nparent);
+    }
+    // outgoing plane waves of the senders
+    const long H = (long)P->H;
+    contract(P, P->Q, p3, P->send_fid, X_REAL, P->e_half, 1, P->s1, p2 * q, nullptr, Y_STORE_CPLX, p, p * p, q,
+             P->nsend);
+    contract(P, P->s1, p2 * q, nullptr, X_CPLX, P->e_full, 1, P->s2, (long)p * q * n1, nullptr, Y_STORE_CPLX, p,
+             p * q, n1, P->nsend);
+    contract(P, P->s2, (long)p * q * n1, nullptr, X_CPLX, P->e_full, 1, P->Phi, H, nullptr, Y_STORE_CPLX, p, q * n1,
+             n1, P->nsend);
+    // Step 3b: translation with the difference-kernel symbol
+    launch_translate(q, n1, P->recv, P->nrecv, P->e_src, P->e_off, P->Phi, P->wdiff, P->Psi, st);
+    // incoming plane waves -> proxy potentials
+    launch_zero(P->V, (size_t)P->nf * 3 * p3, st);
+    contract(P, P->Psi, H, nullptr, X_CPLX, P->g_half, 1, P->s1, (long)n1 * n1 * p, nullptr, Y_STORE_CPLX, q,
+             n1 * n1, p, P->nrecv);
+    contract(P, P->s1, (long)n1 * n1 * p, nullptr, X_CPLX, P->g_full, 1, P->s2, (long)n1 * p * p, nullptr,
+             Y_STORE_CPLX, n1, n1 * p, p, P->nrecv);
+    contract(P, P->s2, (long)n1 * p * p, nullptr, X_CPLX, P->g_full, 1, P->V, p3, P->recv_fid, Y_ADD_REALPART, n1,
+             p * p, p, P->nrecv);
+    // Step 3a: root convolution with the (truncated or periodic) mollified kernel
+    {
+        const int mh = P->root_mh, mf = P->root_mf;
+        const long Hr = (long)P->Hroot;
+        const int rf = P->root_fid;
+        const double* Qr = P->Q + (size_t)rf * 3 * p3;
+        double* Vr = P->V + (size_t)rf * 3 * p3;
+        contract(P, Qr, p3, nullptr, X_REAL, P->r_e_half, 1, P->s1, p2 * mh, nullptr, Y_STORE_CPLX, p, p * p, mh, 1);
+        contract(P, P->s1, p2 * mh, nullptr, X_CPLX, P->r_e_full, 1, P->s2, (long)p * mh * mf, nullptr, Y_STORE_CPLX,
+                 p, p * mh, mf, 1);
+        contract(P, P->s2, (long)p * mh * mf, nullptr, X_CPLX, P->r_e_full, 1, P->phi_root, Hr, nullptr,
+                 Y_STORE_CPLX, p, mh * mf, mf, 1);
+        launch_root_symbol(mh, mf, P->phi_root, P->wroot, P->psi_root, st);
+        contract(P, P->psi_root, Hr, nullptr, X_CPLX, P->r_g_half, 1, P->s1, (long)mf * mf * p, nullptr,
+                 Y_STORE_CPLX, mh, mf * mf, p, 1);
+        contract(P, P->s1, (long)mf * mf * p, nullptr, X_CPLX, P->r_g_full, 1, P->s2, (long)mf * p * p, nullptr,
+                 Y_STORE_CPLX, mf, mf * p, p, 1);
+        contract(P, P->s2, (long)mf * p * p, nullptr, X_CPLX, P->r_g_full, 1, Vr, p3, nullptr, Y_ADD_REALPART, mf,
+                 p * p, p, 1);
+        if (!P->periodic)
+            launch_sum_root(Qr, (int)p3, 1.0 / (4.0 * kPi * (1.0 + std::sqrt(3.0))), P->cst, st);
+    }
+    // downward interpolation, coarsest level first
+    for (int l = 0; l < T.max_level; ++l) {
+        const auto& L = P->lev[l];
+        if (!L.nparent)
+            continue;
+        contract(P, P->V, p3, L.parent_fid, X_REAL, P->down, 0, P->s1, 2 * p3, nullptr, Y_STORE_REAL, p, p * p,
+                 2 * p, L.nparent);
+        contract(P, P->s1, 2 * p3, nullptr, X_REAL, P->down, 0, P->s2, 4 * p3, nullptr, Y_STORE_REAL, p, 2 * p * p,
+                 2 * p, L.nparent);
+        launch_interp_stage3(p, L.child_fid, L.nparent, (const double*)P->s2, P->down, P->V, st);
+    }
+    // far field at the points, then the near field (Step 4) and self term
+    launch_leaf_eval(p, P->leaves, P->nleaf, P->x, P->y, P->z, n, P->cheb_t, P->cheb_w, P->V, P->u, st);
+    launch_near(P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x, P->y, P->z, P->fs, n, P->poly,
+                -P->tab->phi0 / (2.0 * kPi), P->u, st);
+    launch_finalize(P->u, n, P->perm, 1.0 / P->box_len, P->periodic ? nullptr : P->cst, vel, st);
+    return DMK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dmk_last_error(void) { return g_err.c_str(); }
+
+int dmk_stokes_params(double tol, dmk_plan_info* info)
+{
+    if (!info)
+        return fail(DMK_ERR_ARG, "info is NULL");
+    std::memset(info, 0, sizeof(*info));
+    dmk::Params prm;
+    if (!dmk::select_params(tol, &prm))
+        return fail(DMK_ERR_TOL, "tol must lie in [1e-12, 1e-3]");
+    const dmk::Tables* T = dmk::get_tables(tol);
+    info->tol = prm.tol;
+    info->c = prm.c;
+    info->q = prm.q;
+    info->p = prm.p;
+    info->n1 = prm.n1;
+    info->nper = prm.nper;
+    info->leaf_size = prm.ns;
+    info->deg_P = (int)T->fits.P.a.size() - 1;
+    info->deg_Q = (int)T->fits.Q.a.size() - 1;
+    return DMK_OK;
+}
+
+int dmk_stokes_radial(double tol, const double* rho, int64_t n, double* out)
+{
+    if (!rho || !out || n < 0)
+        return fail(DMK_ERR_ARG, "bad arguments");
+    const dmk::Tables* T = dmk::get_tables(tol);
+    if (!T)
+        return fail(DMK_ERR_TOL, "tol must lie in [1e-12, 1e-3]");
+    dmk::Prolate w(T->prm.c);
+    for (int64_t i = 0; i < n; ++i) {
+        const double r = rho[i];
+        out[4 * i] = w.phi(r);
+        out[4 * i + 1] = w.Phi(r);
+        const double s = r * r;
+        out[4 * i + 2] = s < 1.0 ? T->fits.P.eval(s) : 0.0;
+        out[4 * i + 3] = s < 1.0 ? T->fits.Q.eval(s) : 0.0;
+    }
+    return DMK_OK;
+}
+
+int dmk_stokes_mollifier(double tol, const double* k, int64_t n, double* out)
+{
+    if (!k || !out || n < 0)
+        return fail(DMK_ERR_ARG, "bad arguments");
+    dmk::Params prm;
+    if (!dmk::select_params(tol, &prm))
+        return fail(DMK_ERR_TOL, "tol must lie in [1e-12, 1e-3]");
+    dmk::Prolate w(prm.c);
+    for (int64_t i = 0; i < n; ++i) {
+        out[2 * i] = w.phihat(k[i]);
+        out[2 * i + 1] = w.gammahat(k[i]);
+    }
+    return DMK_OK;
+}
+
+int dmk_stokes_plan_ex(const double* points, int64_t n, int dim, int periodic, double tol, const dmk_opts* opts,
+                       dmk_plan_t* out)
+{
+    if (!out)
+        return fail(DMK_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!points)
+        return fail(DMK_ERR_ARG, "points is NULL");
+    if (n < 1)
+        return fail(DMK_ERR_ARG, "n must be >= 1");
+    if (n > (int64_t)2000000000)
+        return fail(DMK_ERR_ARG, "n too large");
+    int rc = validate_common(dim, tol, opts);
+    if (rc != DMK_OK)
+        return rc;
+    if (periodic != 0 && periodic != 1)
+        return fail(DMK_ERR_ARG, "periodic must be 0 or 1");
+    if (!is_device_ptr(points))
+        return fail(DMK_ERR_ARG, "points must be a device pointer");
+    const auto t0 = std::chrono::steady_clock::now();
+    dmk_plan_t P = new (std::nothrow) dmk_plan_s();
+    if (!P)
+        return fail(DMK_ERR_OOM, "host allocation failed");
+    if (!dmk::select_params(tol, &P->prm)) {
+        delete P;
+        return fail(DMK_ERR_TOL, "tol must lie in [1e-12, 1e-3]");
+    }
+    P->tab = dmk::get_tables(tol);
+    if (opts) {
+        P->stream = (hipStream_t)opts->stream;
+        P->precision = opts->precision;
+        if (opts->leaf_size > 0)
+            P->prm.ns = opts->leaf_size;
+        P->mem.cap = opts->mem_cap_bytes;
+    }
+    P->n = n;
+    P->periodic = periodic != 0;
+    rc = build_plan(P, points);
+    if (rc != DMK_OK) {
+        (void)hipStreamSynchronize(P->stream);
+        delete P;
+        return rc;
+    }
+    P->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = P;
+    return DMK_OK;
+}
+
+int dmk_stokes_plan(const double* points, int64_t n, int dim, int periodic, double tol, dmk_plan_t* out)
+{
+    return dmk_stokes_plan_ex(points, n, dim, periodic, tol, nullptr, out);
+}
+
+int dmk_stokes_eval(dmk_plan_t plan, const double* forces, int n_rhs, double* velocities)
+{
+    if (!plan)
+        return fail(DMK_ERR_ARG, "plan is NULL");
+    if (n_rhs < 1)
+        return fail(DMK_ERR_ARG, "n_rhs must be >= 1");
+    if (!is_device_ptr(forces) || !is_device_ptr(velocities))
+        return fail(DMK_ERR_ARG, "forces and velocities must be device pointers");
+    for (int r = 0; r < n_rhs; ++r) {
+        const int rc = eval_one(plan, forces + (size_t)r * 3 * plan->n, velocities + (size_t)r * 3 * plan->n);
+        if (rc != DMK_OK)
+            return rc;
+    }
+    HIPCHK(hipGetLastError());
+    return DMK_OK;
+}
+
+int dmk_stokes_plan_info(dmk_plan_t plan, dmk_plan_info* info)
+{
+    if (!plan || !info)
+        return fail(DMK_ERR_ARG, "plan or info is NULL");
+    std::memset(info, 0, sizeof(*info));
+    const dmk_plan_s& P = *plan;
+    info->tol = P.prm.tol;
+    info->c = P.prm.c;
+    info->q = P.prm.q;
+    info->p = P.prm.p;
+    info->n1 = P.prm.n1;
+    info->nper = P.prm.nper;
+    info->leaf_size = P.prm.ns;
+    info->deg_P = P.poly.nP - 1;
+    info->deg_Q = P.poly.nQ - 1;
+    info->levels = P.tree.max_level + 1;
+    info->periodic = P.periodic;
+    info->n_points = P.n;
+    info->n_boxes = (int64_t)P.tree.boxes.size();
+    info->n_leaves = (int64_t)P.leaf_box.size();
+    info->n_nonempty_boxes = P.nf;
+    info->n_nonempty_leaves = P.nleaf;
+    info->near_pairs = P.tree.n_near_pairs;
+    info->n_senders = P.nsend;
+    info->n_receivers = P.nrecv;
+    for (int d = 0; d < 3; ++d)
+        info->center[d] = P.center[d];
+    info->box_len = P.box_len;
+    info->device_bytes = P.mem.total;
+    info->plan_ms = P.plan_ms;
+    return DMK_OK;
+}
+
+int dmk_stokes_tree_leaves(dmk_plan_t plan, int32_t* leaf_level, int64_t* leaf_coord, int64_t* leaf_count,
+                           int64_t* point_leaf)
+{
+    if (!plan)
+        return fail(DMK_ERR_ARG, "plan is NULL");
+    const dmk_plan_s& P = *plan;
+    const auto& B = P.tree.boxes;
+    for (size_t li = 0; li < P.leaf_box.size(); ++li) {
+        const dmk::Box& b = B[P.leaf_box[li]];
+        if (leaf_level)
+            leaf_level[li] = b.level;
+        if (leaf_coord) {
+            leaf_coord[3 * li] = b.ix;
+            leaf_coord[3 * li + 1] = b.iy;
+            leaf_coord[3 * li + 2] = b.iz;
+        }
+        if (leaf_count)
+            leaf_count[li] = b.end - b.start;
+    }
+    if (point_leaf) {
+        std::vector<int> perm(P.n);
+        HIPCHK(hipMemcpyAsync(perm.data(), P.perm, P.n * sizeof(int), hipMemcpyDeviceToHost, P.stream));
+        HIPCHK(hipStreamSynchronize(P.stream));
+        for (size_t li = 0; li < P.leaf_box.size(); ++li) {
+            const dmk::Box& b = B[P.leaf_box[li]];
+            for (int64_t i = b.start; i < b.end; ++i)
+                point_leaf[perm[i]] = (int64_t)li;
+        }
+    }
+    return DMK_OK;
+}
+
+void dmk_stokes_destroy(dmk_plan_t plan)
+{
+    if (!plan)
+        return;
+    (void)hipStreamSynchronize(plan->stream);
+    delete plan;
+}
+
+int dmk_stokes_residual_sum(const double* targets, int64_t m, const double* sources, const double* forces,
+                            int64_t ns, double r_lambda, double tol, void* stream, double* out)
+{
+    if (m < 0 || ns < 0 || !(r_lambda > 0))
+        return fail(DMK_ERR_ARG, "bad sizes or r_lambda");
+    if (m == 0)
+        return DMK_OK;
+    if (!is_device_ptr(targets) || !is_device_ptr(out) || (ns > 0 && (!is_device_ptr(sources) || !is_device_ptr(forces))))
+        return fail(DMK_ERR_ARG, "arrays must be device pointers");
+    const dmk::Tables* T = dmk::get_tables(tol);
+    if (!T)
+        return fail(DMK_ERR_TOL, "tol must lie in [1e-12, 1e-3]");
+    hipStream_t st = (hipStream_t)stream;
+    DevMem mem;
+    double* tx = mem.alloc<double>(3 * m);
+    double* sx = mem.alloc<double>(3 * std::max<int64_t>(ns, 1));
+    double* sf = mem.alloc<double>(3 * std::max<int64_t>(ns, 1));
+    if (mem.oom)
+        return fail(DMK_ERR_OOM, "device allocation failed");
+    // (k,3) row-major -> SoA by strided 2D copies
+    HIPCHK(hipMemcpy2DAsync(tx, sizeof(double), targets, 3 * sizeof(double), sizeof(double), m,
+                            hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpy2DAsync(tx + m, sizeof(double), targets + 1, 3 * sizeof(double), sizeof(double), m,
+                            hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpy2DAsync(tx + 2 * m, sizeof(double), targets + 2, 3 * sizeof(double), sizeof(double), m,
+                            hipMemcpyDeviceToDevice, st));
+    for (int d = 0; d < 3 && ns > 0; ++d) {
+        HIPCHK(hipMemcpy2DAsync(sx + d * ns, sizeof(double), sources + d, 3 * sizeof(double), sizeof(double), ns,
+                                hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpy2DAsync(sf + d * ns, sizeof(double), forces + d, 3 * sizeof(double), sizeof(double), ns,
+                                hipMemcpyDeviceToDevice, st));
+    }
+    dmk::RadialPoly poly;
+    poly.nP = (int)T->fits.P.a.size();
+    poly.nQ = (int)T->fits.Q.a.size();
+    for (int k = 0; k < 48; ++k) {
+        poly.P[k] = k < poly.nP ? T->fits.P.a[k] : 0.0;
+        poly.Q[k] = k < poly.nQ ? T->fits.Q.a[k] : 0.0;
+    }
+    dmk::launch_residual_direct(tx, tx + m, tx + 2 * m, m, sx, sx + ns, sx + 2 * ns, sf, ns, r_lambda, poly, out,
+                                st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));  // temporaries are freed on return
+    return DMK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Device kernels of the DMK Stokeslet path and their host launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dmk {
+
+struct cplx {
+    double re, im;
+};
+
+// ---- tree construction -----------------------------------------------------
+// per-block partial bounding box / finiteness of (n,3) row-major points
+void launch_bbox(const double* pts, int64_t n, double* partial /*nblk*8*/, int nblk, hipStream_t s);
+// unit-box coordinates, Morton keys (19 bits per dimension), identity index
+void launch_morton(const double* pts, int64_t n, double cx, double cy, double cz, double inv_len,
+                   uint64_t* keys, int* idx, hipStream_t s);
+// sorted SoA unit coordinates
+void launch_gather_points(const double* pts, int64_t n, const int* perm, double cx, double cy, double cz,
+                          double inv_len, double* x, double* y, double* z, hipStream_t s);
+// radix sort of (key, index) pairs; temp storage is allocated by the caller
+size_t sort_temp_bytes(int64_t n);
+void launch_sort(void* temp, size_t temp_bytes, const uint64_t* kin, uint64_t* kout, const int* vin, int* vout,
+                 int64_t n, int end_bit, hipStream_t s);
+// per 64-point chunk bounding boxes (chunk list given as starts/ends)
+void launch_chunk_bbox(const double* x, const double* y, const double* z, const int64_t* cstart,
+                       const int* clen, int nchunk, double* bbox /*nchunk*6*/, hipStream_t s);
+
+// ---- per evaluation --------------------------------------------------------
+// forces (n,3) original order -> sorted SoA fs[3][n]
+void launch_gather_forces(const double* f, int64_t n, const int* perm, double* fs, hipStream_t s);
+
+struct LeafDesc {
+    int fid;          // far-field slot of the leaf
+    int level;
+    int64_t start, end;
+    double cx, cy, cz;
+};
+
+// proxy charges of leaves (Step 2a): Q[fid][j][a][b][c] = sum L_a L_b L_c f_j
+void launch_anterp(int p, const LeafDesc* leaves, int nleaf, const double* x, const double* y, const double* z,
+                   const double* fs, int64_t n, const double* cheb_t, const double* cheb_w, double* Q,
+                   hipStream_t s);
+// far-field value at the leaf's points (final interpolation): u[j][i] = sum V L L L
+void launch_leaf_eval(int p, const LeafDesc* leaves, int nleaf, const double* x, const double* y,
+                      const double* z, int64_t n, const double* cheb_t, const double* cheb_w, const double* V,
+                      double* u, hipStream_t s);
+
+// generic rotating contraction  Y[b][r][n] (+)= sum_k X[b][k][r] * M[n][k]
+// batch b = slot * 3 + component; slot -> array position through optional maps
+enum XKind { X_REAL = 0, X_CPLX = 1 };
+enum YMode { Y_STORE_CPLX = 0, Y_STORE_REAL = 1, Y_ADD_REALPART = 2, Y_ADD_REAL = 3 };
+struct ContractArgs {
+    const void* X;
+    long xstride;       // elements per (slot, component)
+    const int* xmap;    // slot -> array slot (nullptr: identity)
+    int xkind;
+    const void* M;      // N x K matrix
+    int mcplx;          // 1: complex matrix, 0: real matrix
+    void* Y;
+    long ystride;
+    const int* ymap;
+    int ymode;
+    int K, R, N;
+    int nslots;
+};
+void launch_contract(const ContractArgs& a, hipStream_t s);
+
+// merge 8 children into parent (first stage gathers the (2p)^3 child grid):
+// Y[p][B][C][a] = sum_A up[a][A] Qchild(A,B,C); children fids (8 per parent, -1 = none)
+void launch_merge_stage1(int p, const int* child_fid, int nparent, const double* Q, const double* up,
+                         double* Y, hipStream_t s);
+// interpolation last stage: scatter-add Y[A][B][C] into the children's V
+void launch_interp_stage3(int p, const int* child_fid, int nparent, const double* X /*[c][A][B] per parent*/,
+                          const double* down, double* V, hipStream_t s);
+
+// plane-wave translation with the difference-kernel symbol (Step 3b)
+struct RecvDesc {
+    int slot;         // receiver slot in Psi
+    int level;
+    int ebeg, eend;   // entries in the entry arrays
+};
+void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int* e_src /*sender slot*/,
+                      const int8_t* e_off /*3 per entry*/, const cplx* Phi, const double* wdiff, cplx* Psi,
+                      hipStream_t s);
+// root symbol multiply: Psi[j][m] = w(|m|^2) (I - m m^T/|m|^2) Phi[j][m]
+void launch_root_symbol(int mh, int mf, const cplx* Phi, const double* w, cplx* Psi, hipStream_t s);
+
+// near field (Step 4) + self term
+struct NearLeaf {
+    int64_t tstart, tend;
+    int ebeg, eend;
+    int level;
+    int cbase;        // first 64-point chunk of the leaf
+};
+struct NearEntryDev {
+    int64_t sstart, send;
+    int cbase;        // first chunk of the source leaf
+    int8_t sx, sy, sz, lambda;
+};
+struct NearWork {
+    int leaf;
+    int chunk;        // chunk index within the leaf
+};
+struct RadialPoly {
+    int nP, nQ;
+    double P[48], Q[48];
+};
+void launch_near(const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
+                 const double* cbbox, const double* x, const double* y, const double* z, const double* fs,
+                 int64_t n, const RadialPoly& poly, double self_coef, double* u, hipStream_t s);
+
+// brute-force residual sum over all source points (stage entry point)
+void launch_residual_direct(const double* tx, const double* ty, const double* tz, int64_t m, const double* sx,
+                            const double* sy, const double* sz, const double* sf, int64_t ns, double r_lambda,
+                            const RadialPoly& poly, double* u, hipStream_t s);
+
+// out[j] = coef * sum of the root proxy charges (equals coef * net force)
+void launch_sum_root(const double* Qroot, int p3, double coef, double* out, hipStream_t s);
+// u_out[(rhs) n,3 original order] = scale * u[j][i] + cst[j]
+void launch_finalize(const double* u, int64_t n, const int* perm, double scale, const double* cst,
+                     double* vel, hipStream_t s);
+void launch_zero(double* p, size_t count, hipStream_t s);
+
+}  // namespace dmk

@@ -1,0 +1,513 @@
+// Host-side kernel-splitting mathematics (double precision, once per tolerance).
+#include "kernel_math.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+
+namespace dmk {
+
+namespace {
+constexpr double kPi = 3.14159265358979323846;
+
+struct Row {
+    double tol;
+    int q, p, n1, nper, ns;
+};
+// Table "tab:params" (Stokeslet, PSWF split) and the 3D leaf sizes of
+// Sec. "Numerical results".
+const Row kRows[4] = {
+    {1e-3, 10, 12, 19, 3, 600},
+    {1e-6, 17, 23, 33, 5, 1200},
+    {1e-9, 25, 33, 49, 9, 2000},
+    {1e-12, 31, 44, 61, 11, 3000},
+};
+}  // namespace
+
+bool select_params(double tol, Params* out)
+{
+    if (!(tol >= 1e-12 * (1 - 1e-9) && tol <= 1e-3 * (1 + 1e-9)))
+        return false;
+    const double lt = std::log10(tol);
+    int q, p, ns;
+    int hit = -1;
+    for (int i = 0; i < 4; ++i)
+        if (std::fabs(lt - std::log10(kRows[i].tol)) < 1e-9)
+            hit = i;
+    if (hit >= 0) {
+        q = kRows[hit].q;
+        p = kRows[hit].p;
+        ns = kRows[hit].ns;
+    } else {
+        // between rows: the row with the largest tolerance below tol
+        int i = 0;
+        while (i < 3 && kRows[i].tol > tol)
+            ++i;
+        q = kRows[i].q;
+        p = kRows[i].p;
+        ns = kRows[i].ns;
+    }
+    out->tol = tol;
+    out->q = q;
+    out->c = q * kPi / 3.0;
+    out->p = p;
+    // strict truncation |k_i| < K_max / r_{l+1} with h_l = 2 pi/(3 r_l)
+    // (Sec. "Error control and parameter selection") gives |m_i| <= q-1
+    out->n1 = 2 * q - 1;
+    // periodic root k = 2 pi kappa, |k_i| < c
+    out->nper = 2 * ((q + 5) / 6) - 1;
+    out->ns = ns;
+    return true;
+}
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+        double pp = 0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = 0.0;
+            for (int j = 1; j <= n; ++j) {
+                double p2 = p1;
+                p1 = p0;
+                p0 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p2) / j;
+            }
+            pp = n * (z * p0 - p1) / (z * z - 1.0);
+            double dz = p0 / pp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16)
+                break;
+        }
+        {
+            double p0 = 1.0, p1 = 0.0;
+            for (int j = 1; j <= n; ++j) {
+                double p2 = p1;
+                p1 = p0;
+                p0 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p2) / j;
+            }
+            pp = n * (z * p0 - p1) / (z * z - 1.0);
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * pp * pp);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Prolate: the prolate operator L = -d/dx (1-x^2) d/dx + c^2 x^2 is symmetric
+// tridiagonal on the even normalised Legendre functions sqrt(k+1/2) P_k.
+// psi_0 is its eigenvector of smallest eigenvalue (published Legendre-Galerkin
+// approach for prolates; the operator commutes with the band-limited Fourier
+// operator that defines psi_0 in Sec. "Prolate spheroidal wave functions").
+Prolate::Prolate(double c) : c_(c)
+{
+    const int M = (int)(0.6 * c) + 32;
+    std::vector<double> d(M), e(M, 0.0);
+    for (int i = 0; i < M; ++i) {
+        const double k = 2.0 * i;
+        d[i] = k * (k + 1) + c * c * (2 * k * k + 2 * k - 1) / ((2 * k - 1) * (2 * k + 3));
+        if (i + 1 < M)
+            e[i] = c * c * (k + 1) * (k + 2) / ((2 * k + 3) * std::sqrt((2 * k + 1) * (2 * k + 5)));
+    }
+    // smallest eigenvalue by Sturm-sequence bisection
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < M; ++i) {
+        const double rad = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + std::fabs(e[i]);
+        lo = std::min(lo, d[i] - rad);
+        hi = std::max(hi, d[i] + rad);
+    }
+    auto count_below = [&](double x) {
+        int cnt = 0;
+        double q = d[0] - x;
+        if (q < 0)
+            ++cnt;
+        for (int i = 1; i < M; ++i) {
+            if (q == 0.0)
+                q = 1e-300;
+            q = (d[i] - x) - e[i - 1] * e[i - 1] / q;
+            if (q < 0)
+                ++cnt;
+        }
+        return cnt;
+    };
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (count_below(mid) >= 1)
+            hi = mid;
+        else
+            lo = mid;
+        if (hi - lo <= 1e-15 * std::max(1.0, std::fabs(hi)))
+            break;
+    }
+    chi_ = 0.5 * (lo + hi);
+    // inverse iteration (tridiagonal solve without pivoting, slightly shifted)
+    const double shift = chi_ - 1e-10 * std::max(1.0, std::fabs(chi_));
+    std::vector<double> v(M, 1.0), cp(M), dp(M);
+    for (int it = 0; it < 4; ++it) {
+        double b0 = d[0] - shift;
+        cp[0] = e[0] / b0;
+        dp[0] = v[0] / b0;
+        for (int i = 1; i < M; ++i) {
+            const double den = (d[i] - shift) - e[i - 1] * cp[i - 1];
+            cp[i] = (i + 1 < M ? e[i] / den : 0.0);
+            dp[i] = (v[i] - e[i - 1] * dp[i - 1]) / den;
+        }
+        v[M - 1] = dp[M - 1];
+        for (int i = M - 2; i >= 0; --i)
+            v[i] = dp[i] - cp[i] * v[i + 1];
+        double nrm = 0;
+        for (double a : v)
+            nrm += a * a;
+        nrm = std::sqrt(nrm);
+        for (double& a : v)
+            a /= nrm;
+    }
+    beta_.resize(M);
+    // psi(0) > 0: P_{2i}(0) = (-1)^i (2i-1)!!/(2i)!!
+    double psi0 = 0, p0 = 1.0;
+    for (int i = 0; i < M; ++i) {
+        if (i > 0)
+            p0 *= -(2.0 * i - 1) / (2.0 * i);
+        psi0 += v[i] * std::sqrt(2.0 * i + 0.5) * p0;
+    }
+    const double sgn = psi0 > 0 ? 1.0 : -1.0;
+    for (int i = 0; i < M; ++i)
+        beta_[i] = sgn * v[i] * std::sqrt(2.0 * i + 0.5);  // coefficient of plain P_{2i}
+    // int_{-1}^{1} psi = 2 * beta_0 (only P_0 has a nonzero integral)
+    norm_ = 2.0 * beta_[0];
+    std::vector<double> x, w;
+    gauss_legendre(320, x, w);
+    gl_t_.resize(320);
+    gl_w_.resize(320);
+    for (int i = 0; i < 320; ++i) {
+        gl_t_[i] = 0.5 * (x[i] + 1.0);
+        gl_w_[i] = 0.5 * w[i];
+    }
+    gl_phi_.resize(320);
+    for (int i = 0; i < 320; ++i)
+        gl_phi_[i] = gl_w_[i] * phi(gl_t_[i]);
+}
+
+void Prolate::legendre_all(double x, std::vector<double>& P) const
+{
+    const int n = 2 * (int)beta_.size() + 1;
+    P.resize(n + 1);
+    P[0] = 1.0;
+    P[1] = x;
+    for (int j = 1; j < n; ++j)
+        P[j + 1] = ((2.0 * j + 1) * x * P[j] - j * P[j - 1]) / (j + 1);
+}
+
+double Prolate::phi(double r) const
+{
+    r = std::fabs(r);
+    if (r > 1.0)
+        return 0.0;
+    std::vector<double> P;
+    legendre_all(r, P);
+    double s = 0;
+    for (size_t i = 0; i < beta_.size(); ++i)
+        s += beta_[i] * P[2 * i];
+    return s / norm_;
+}
+
+double Prolate::dphi(double r) const
+{
+    const double sg = r < 0 ? -1.0 : 1.0;
+    r = std::fabs(r);
+    if (r > 1.0)
+        return 0.0;
+    std::vector<double> P;
+    legendre_all(r, P);
+    // P'_{n+1} = P'_{n-1} + (2n+1) P_n
+    const int n = (int)P.size();
+    std::vector<double> dP(n, 0.0);
+    dP[0] = 0.0;
+    if (n > 1)
+        dP[1] = 1.0;
+    for (int j = 1; j + 1 < n; ++j)
+        dP[j + 1] = dP[j - 1] + (2.0 * j + 1) * P[j];
+    double s = 0;
+    for (size_t i = 0; i < beta_.size(); ++i)
+        s += beta_[i] * dP[2 * i];
+    return sg * s / norm_;
+}
+
+double Prolate::int_phi(double r) const
+{
+    r = std::min(std::fabs(r), 1.0);
+    std::vector<double> P;
+    legendre_all(r, P);
+    // int_0^r P_0 = r;  int_0^r P_n = (P_{n+1}(r) - P_{n-1}(r))/(2n+1) for even n >= 2
+    double s = beta_[0] * r;
+    for (size_t i = 1; i < beta_.size(); ++i) {
+        const int n = 2 * (int)i;
+        s += beta_[i] * (P[n + 1] - P[n - 1]) / (2.0 * n + 1);
+    }
+    return s / norm_;
+}
+
+double Prolate::Phi(double r) const
+{
+    r = std::fabs(r);
+    if (r >= 1.0)
+        return 0.0;
+    return 1.0 - 2.0 * int_phi(r);
+}
+
+double Prolate::phihat(double k) const
+{
+    double s = 0;
+    for (size_t i = 0; i < gl_t_.size(); ++i)
+        s += gl_phi_[i] * std::cos(k * gl_t_[i]);
+    return 2.0 * s;
+}
+
+double Prolate::dphihat(double k) const
+{
+    double s = 0;
+    for (size_t i = 0; i < gl_t_.size(); ++i)
+        s += gl_phi_[i] * gl_t_[i] * std::sin(k * gl_t_[i]);
+    return -2.0 * s;
+}
+
+double Prolate::gammahat(double k) const
+{
+    return phihat(k) - 0.5 * k * dphihat(k);
+}
+
+double ChebFit::eval(double s) const
+{
+    const double t = 2.0 * s - 1.0;
+    double b1 = 0, b2 = 0;
+    for (int k = (int)a.size() - 1; k >= 1; --k) {
+        const double b0 = 2.0 * t * b1 - b2 + a[k];
+        b2 = b1;
+        b1 = b0;
+    }
+    return t * b1 - b2 + a[0];
+}
+
+RadialFits fit_radial(const Prolate& w, double fit_tol)
+{
+    // E(s) = int_0^1 phi(rho v) dv,  E - G = -rho int_0^1 v phi'(rho v) dv
+    // (integration by parts, no cancellation), Q = (E - G)/s.
+    std::vector<double> gx, gw;
+    gauss_legendre(120, gx, gw);
+    for (size_t i = 0; i < gx.size(); ++i) {
+        gx[i] = 0.5 * (gx[i] + 1.0);
+        gw[i] *= 0.5;
+    }
+    auto PQ = [&](double s, double* P, double* Q) {
+        const double rho = std::sqrt(s);
+        double E = 0, H = 0;
+        for (size_t i = 0; i < gx.size(); ++i) {
+            E += gw[i] * w.phi(rho * gx[i]);
+            H += gw[i] * gx[i] * w.dphi(rho * gx[i]);
+        }
+        const double G = w.phi(rho);
+        *P = E + G;
+        *Q = -H / rho;  // (E-G)/s = -rho H / rho^2
+    };
+    const int N = 96;
+    std::vector<double> fp(N), fq(N);
+    for (int j = 0; j < N; ++j) {
+        const double s = 0.5 * (1.0 + std::cos((2.0 * j + 1) * kPi / (2.0 * N)));
+        PQ(s, &fp[j], &fq[j]);
+    }
+    auto coeffs = [&](const std::vector<double>& f) {
+        std::vector<double> a(N);
+        for (int k = 0; k < N; ++k) {
+            double s = 0;
+            for (int j = 0; j < N; ++j)
+                s += f[j] * std::cos(k * (2.0 * j + 1) * kPi / (2.0 * N));
+            a[k] = (k == 0 ? 1.0 : 2.0) * s / N;
+        }
+        return a;
+    };
+    // keep coefficients up to the point where the series first stays below
+    // the threshold for 8 consecutive terms (beyond it is rounding noise)
+    auto trunc = [&](std::vector<double> a, double scale) {
+        const double thr = std::max(fit_tol, 2e-14) * scale;
+        int d = (int)a.size() - 1;
+        for (int k = 1; k + 8 < (int)a.size(); ++k) {
+            bool small = true;
+            for (int j = k; j < k + 8; ++j)
+                small = small && std::fabs(a[j]) < thr;
+            if (small) {
+                d = k - 1;
+                break;
+            }
+        }
+        a.resize(d + 1);
+        return a;
+    };
+    RadialFits out;
+    double scale = std::fabs(fp[N - 1]);  // ~P(0) = 2 phi(0)
+    for (double v : fp)
+        scale = std::max(scale, std::fabs(v));
+    out.P.a = trunc(coeffs(fp), scale);
+    out.Q.a = trunc(coeffs(fq), scale);
+    out.max_err_P = out.max_err_Q = 0;
+    for (int j = 0; j <= 200; ++j) {
+        const double s = j / 200.0 * (1 - 1e-12) + 1e-12;
+        double P, Q;
+        PQ(s, &P, &Q);
+        out.max_err_P = std::max(out.max_err_P, std::fabs(out.P.eval(s) - P));
+        out.max_err_Q = std::max(out.max_err_Q, std::fabs(out.Q.eval(s) - Q));
+    }
+    return out;
+}
+
+void cheb_nodes(int p, std::vector<double>& t, std::vector<double>& bw)
+{
+    t.resize(p);
+    bw.resize(p);
+    for (int a = 0; a < p; ++a) {
+        const double th = (2.0 * a + 1) * kPi / (2.0 * p);
+        t[a] = std::cos(th);
+        bw[a] = ((a & 1) ? -1.0 : 1.0) * std::sin(th);
+    }
+}
+
+void lagrange_basis(const std::vector<double>& t, const std::vector<double>& bw, double x, double* out)
+{
+    const int p = (int)t.size();
+    for (int a = 0; a < p; ++a)
+        if (x == t[a]) {
+            for (int b = 0; b < p; ++b)
+                out[b] = (a == b) ? 1.0 : 0.0;
+            return;
+        }
+    double den = 0;
+    for (int a = 0; a < p; ++a) {
+        out[a] = bw[a] / (x - t[a]);
+        den += out[a];
+    }
+    for (int a = 0; a < p; ++a)
+        out[a] /= den;
+}
+
+double btrunc_hat(double k, double R)
+{
+    const double x = k * R;
+    if (x >= 0.2)
+        return (1.0 + 0.5 * std::cos(x) - 1.5 * std::sin(x) / x) / (k * k * k * k);
+    // 1 + cos(x)/2 - 3 sin(x)/(2x) = sum_{n>=2} (-1)^n x^{2n} [1/(2 (2n)!) - 3/(2 (2n+1)!)]
+    double acc = 0, f2n = 24.0;  // (2n)! at n = 2
+    double x2 = x * x, xp = 1.0;  // x^{2n-4}
+    for (int n = 2; n < 12; ++n) {
+        if (n > 2)
+            f2n *= (2.0 * n - 1) * (2.0 * n);
+        const double f2n1 = f2n * (2.0 * n + 1);
+        acc += ((n & 1) ? -1.0 : 1.0) * (0.5 / f2n - 1.5 / f2n1) * xp;
+        xp *= x2;
+    }
+    return acc * R * R * R * R;
+}
+
+namespace {
+
+void plane_wave_mats(int p, int mmax, double alpha, const std::vector<double>& t,
+                     std::vector<std::complex<double>>& e_half, std::vector<std::complex<double>>& e_full,
+                     std::vector<std::complex<double>>& g_half, std::vector<std::complex<double>>& g_full)
+{
+    // outgoing: exp(-i alpha m t_a); incoming: exp(+i alpha m t_a) (weight 2 for m1 > 0)
+    const int nh = mmax + 1, nf = 2 * mmax + 1;
+    e_half.resize((size_t)nh * p);
+    e_full.resize((size_t)nf * p);
+    g_half.resize((size_t)p * nh);
+    g_full.resize((size_t)p * nf);
+    for (int m = 0; m < nh; ++m)
+        for (int a = 0; a < p; ++a) {
+            const double ph = alpha * m * t[a];
+            e_half[(size_t)m * p + a] = std::complex<double>(std::cos(ph), -std::sin(ph));
+            g_half[(size_t)a * nh + m] = (m == 0 ? 1.0 : 2.0) * std::complex<double>(std::cos(ph), std::sin(ph));
+        }
+    for (int mi = 0; mi < nf; ++mi)
+        for (int a = 0; a < p; ++a) {
+            const double ph = alpha * (mi - mmax) * t[a];
+            e_full[(size_t)mi * p + a] = std::complex<double>(std::cos(ph), -std::sin(ph));
+            g_full[(size_t)a * nf + mi] = std::complex<double>(std::cos(ph), std::sin(ph));
+        }
+}
+
+Tables* build_tables(double tol)
+{
+    Params prm;
+    if (!select_params(tol, &prm))
+        return nullptr;
+    Tables* T = new Tables();
+    T->prm = prm;
+    Prolate w(prm.c);
+    T->phi0 = w.phi(0.0);
+    T->fits = fit_radial(w, std::min(1e-3 * tol, 1e-13));
+    const int p = prm.p, q = prm.q;
+    std::vector<double> t, bw;
+    cheb_nodes(p, t, bw);
+    T->cheb_t = t;
+    T->up.assign((size_t)p * 2 * p, 0.0);
+    T->down.assign((size_t)2 * p * p, 0.0);
+    std::vector<double> L(p);
+    for (int A = 0; A < 2 * p; ++A) {
+        const double x = A < p ? 0.5 * (t[A] - 1.0) : 0.5 * (t[A - p] + 1.0);
+        lagrange_basis(t, bw, x, L.data());
+        for (int a = 0; a < p; ++a) {
+            T->up[(size_t)a * 2 * p + A] = L[a];
+            T->down[(size_t)A * p + a] = L[a];
+        }
+    }
+    plane_wave_mats(p, q - 1, kPi / 3.0, t, T->e_half, T->e_full, T->g_half, T->g_full);
+    const int m2max = 3 * (q - 1) * (q - 1);
+    T->wdiff.assign(m2max + 1, 0.0);
+    for (int m2 = 1; m2 <= m2max; ++m2) {
+        const double m = std::sqrt((double)m2);
+        T->wdiff[m2] = (w.gammahat(kPi * m / 3.0) - w.gammahat(2.0 * kPi * m / 3.0)) / (12.0 * kPi * kPi * m2);
+    }
+    // free-space root: truncated kernel B^R with R = 1 + sqrt(3) on the unit
+    // box; M_0^R is supported in |x| <= R + 1, differences of root proxy
+    // nodes have |x_i| <= 1, so a trapezoid period P > 3 + sqrt(3) avoids
+    // aliasing.  Modes up to |k_i| <= 1.25 c.
+    T->root_R = 1.0 + std::sqrt(3.0);
+    T->root_period = 5.0;
+    T->root_m = (int)std::ceil(1.25 * prm.c * T->root_period / (2.0 * kPi));
+    plane_wave_mats(p, T->root_m, kPi / T->root_period, t, T->r_e_half, T->r_e_full, T->r_g_half, T->r_g_full);
+    const int r2max = 3 * T->root_m * T->root_m;
+    T->wroot.assign(r2max + 1, 0.0);
+    for (int m2 = 1; m2 <= r2max; ++m2) {
+        const double k = 2.0 * kPi * std::sqrt((double)m2) / T->root_period;
+        const double P3 = T->root_period * T->root_period * T->root_period;
+        T->wroot[m2] = k * k * btrunc_hat(k, T->root_R) * w.gammahat(k) / P3;
+    }
+    // periodic root: Poisson summation over k = 2 pi kappa, k = 0 dropped
+    T->per_m = (prm.nper - 1) / 2;
+    plane_wave_mats(p, T->per_m, kPi, t, T->p_e_half, T->p_e_full, T->p_g_half, T->p_g_full);
+    const int p2max = 3 * T->per_m * T->per_m;
+    T->wper.assign(p2max + 1, 0.0);
+    for (int m2 = 1; m2 <= p2max; ++m2) {
+        const double k = 2.0 * kPi * std::sqrt((double)m2);
+        T->wper[m2] = w.gammahat(k) / (k * k);
+    }
+    return T;
+}
+
+}  // namespace
+
+const Tables* get_tables(double tol)
+{
+    static std::mutex mu;
+    static std::map<double, Tables*> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(tol);
+    if (it != cache.end())
+        return it->second;
+    Tables* T = build_tables(tol);
+    if (T)
+        cache[tol] = T;
+    return T;
+}
+
+}  // namespace dmk

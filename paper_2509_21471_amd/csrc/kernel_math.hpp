@@ -1,0 +1,110 @@
+// Host-side kernel-splitting mathematics for the DMK Stokeslet: parameter
+// selection, the prolate window, the biharmonic mollifier, the radial fits
+// used by the near-field kernel and the level-independent Fourier tables.
+// Everything here runs once per tolerance in double precision.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <vector>
+
+namespace dmk {
+
+// Parameters for one tolerance (Table "tab:params", Stokeslet, PSWF columns;
+// leaf size from Sec. "Numerical results").
+struct Params {
+    double tol;
+    int q;        // 3c/pi
+    double c;     // PSWF bandlimit
+    int p;        // Chebyshev points per dimension on every proxy grid
+    int n1;       // plane-wave modes per dimension, 2q - 1
+    int nper;     // periodic root modes per dimension, 2 ceil(q/6) - 1
+    int ns;       // maximum points per leaf
+};
+
+// Returns false if tol is outside [1e-12, 1e-3].
+bool select_params(double tol, Params* out);
+
+// Zeroth-order prolate spheroidal wave function psi_0^c as an even Legendre
+// series (Legendre-Galerkin form of the prolate differential operator,
+// smallest eigenvalue; sign psi(0) > 0) and the window phi = psi / int psi.
+class Prolate {
+  public:
+    explicit Prolate(double c);
+    double c() const { return c_; }
+    double phi(double r) const;       // |r| <= 1, else 0
+    double dphi(double r) const;
+    double int_phi(double r) const;   // int_0^r phi, r in [0,1]
+    double Phi(double r) const;       // 2 int_r^inf phi = 1 - 2 int_0^r phi
+    double phihat(double k) const;    // int phi(t) e^{-ikt} dt
+    double dphihat(double k) const;
+    double gammahat(double k) const;  // phihat - k phihat'/2
+    double chi() const { return chi_; }
+
+  private:
+    void legendre_all(double x, std::vector<double>& P) const;
+    double c_, chi_, norm_;
+    std::vector<double> beta_;  // coefficient of normalised P_{2i}
+    std::vector<double> gl_t_, gl_w_, gl_phi_;  // Gauss-Legendre on [0,1] for transforms
+};
+
+// Chebyshev series on s in [0,1] (t = 2s-1), evaluated by Clenshaw.
+struct ChebFit {
+    std::vector<double> a;
+    double eval(double s) const;
+};
+
+// Radial functions of the residual Stokeslet at unit scale, written as
+//   S_R(y) = S(y) - [P(s) I + Q(s) y y^T] / (4 pi),  s = |y|^2,  |y| < 1,
+// with E(s) = rho^{-1} int_0^rho phi, G(s) = phi(rho), rho = sqrt(s),
+// P = E + G and Q = (E - G)/s  (rearrangement of eq. res_stokeslet/Soffdiag).
+struct RadialFits {
+    ChebFit P, Q;
+    double max_err_P, max_err_Q;
+};
+RadialFits fit_radial(const Prolate& w, double fit_tol);
+
+// Gauss-Legendre nodes and weights on [-1,1].
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+
+// Chebyshev nodes of the first kind t_a = cos((2a+1) pi / (2p)), a = 0..p-1,
+// and barycentric Lagrange basis evaluation.
+void cheb_nodes(int p, std::vector<double>& t, std::vector<double>& bw);
+void lagrange_basis(const std::vector<double>& t, const std::vector<double>& bw,
+                    double x, double* out);
+
+// Truncated biharmonic symbol in 3D (eq. Btrunc_hat).
+double btrunc_hat(double k, double R);
+
+// All per-tolerance tables, in the layouts the device kernels use.
+struct Tables {
+    Params prm;
+    RadialFits fits;
+    double phi0;                 // phi(0)
+    std::vector<double> cheb_t;  // p nodes
+    // child interpolation: up[a][A] = L_a(child node A), A in [0,2p):
+    // A < p -> lower child (x = (t_A - 1)/2), else upper child (x = (t_{A-p}+1)/2)
+    std::vector<double> up;      // p x 2p
+    std::vector<double> down;    // 2p x p  (down[A][a] = up[a][A])
+    // plane waves at level l: k = h_l m, h_l = 2 pi /(3 r_l), phases (pi/3) m t_a
+    std::vector<std::complex<double>> e_half;   // q  x p : exp(-i pi/3 m t_a), m = 0..q-1
+    std::vector<std::complex<double>> e_full;   // n1 x p : exp(-i pi/3 m t_a), m = -(q-1)..q-1
+    std::vector<std::complex<double>> g_half;   // p x q  : w(m) exp(+i pi/3 m t_a), w = 1 (m=0) or 2
+    std::vector<std::complex<double>> g_full;   // p x n1 : exp(+i pi/3 m t_a)
+    std::vector<double> wdiff;   // by |m|^2: [gammahat(pi|m|/3) - gammahat(2 pi |m|/3)]/(12 pi^2 |m|^2)
+    // free-space root: truncated mollified kernel (eq. Bmollhat_trunc) on a
+    // trapezoid grid of period root_period, modes |m_i| <= root_m
+    double root_period, root_R;
+    int root_m;
+    std::vector<std::complex<double>> r_e_half, r_e_full, r_g_half, r_g_full;
+    std::vector<double> wroot;   // by |m|^2: (1/P^3) k^2 Bhat^R(k) gammahat(k), k = 2 pi |m| / P
+    // periodic root: k = 2 pi kappa, |kappa_i| <= per_m
+    int per_m;
+    std::vector<std::complex<double>> p_e_half, p_e_full, p_g_half, p_g_full;
+    std::vector<double> wper;    // by |kappa|^2: gammahat(2 pi |kappa|) / (4 pi^2 |kappa|^2)
+};
+
+// Builds (and caches per tolerance) the tables.  Returns nullptr on bad tol.
+const Tables* get_tables(double tol);
+
+}  // namespace dmk

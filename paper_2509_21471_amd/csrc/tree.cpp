@@ -1,0 +1,305 @@
+// Adaptive octree construction, 2:1 level restriction and neighbour lists.
+#include "tree.hpp"
+
+#include <algorithm>
+#include <unordered_map>
+
+namespace dmk {
+
+namespace {
+
+inline uint64_t box_key(int level, int64_t ix, int64_t iy, int64_t iz)
+{
+    uint64_t m = 0;
+    for (int b = level - 1; b >= 0; --b)
+        m = (m << 3) | ((uint64_t)((ix >> b) & 1) << 2) | ((uint64_t)((iy >> b) & 1) << 1) | (uint64_t)((iz >> b) & 1);
+    return ((uint64_t)level << 58) | m;
+}
+
+struct Builder {
+    const uint64_t* keys;
+    int64_t n;
+    bool periodic;
+    std::vector<Box> boxes;
+    std::unordered_map<uint64_t, int> lookup;
+
+    int64_t lower_bound(int64_t lo, int64_t hi, uint64_t v) const
+    {
+        return std::lower_bound(keys + lo, keys + hi, v) - keys;
+    }
+
+    int add(int level, int64_t ix, int64_t iy, int64_t iz, int parent, int64_t s, int64_t e)
+    {
+        Box b;
+        b.level = level;
+        b.ix = ix;
+        b.iy = iy;
+        b.iz = iz;
+        b.parent = parent;
+        for (int c = 0; c < 8; ++c)
+            b.child[c] = -1;
+        b.start = s;
+        b.end = e;
+        b.leaf = true;
+        boxes.push_back(b);
+        const int id = (int)boxes.size() - 1;
+        lookup[box_key(level, ix, iy, iz)] = id;
+        return id;
+    }
+
+    void split(int id)
+    {
+        const Box B = boxes[id];
+        const int L = B.level + 1;
+        const int sh = 3 * (kKeyBits - L);
+        const uint64_t base = box_key(B.level, B.ix, B.iy, B.iz) & ((1ull << 58) - 1);
+        int64_t s = B.start;
+        int ch[8];
+        for (int d = 0; d < 8; ++d) {
+            const uint64_t hi_key = ((base << 3) | (uint64_t)d) + 1;
+            const int64_t e = (d == 7) ? B.end : lower_bound(s, B.end, hi_key << sh);
+            const int bx = (d >> 2) & 1, by = (d >> 1) & 1, bz = d & 1;
+            ch[d] = add(L, 2 * B.ix + bx, 2 * B.iy + by, 2 * B.iz + bz, id, s, e);
+            s = e;
+        }
+        Box& Bm = boxes[id];
+        Bm.leaf = false;
+        for (int d = 0; d < 8; ++d)
+            Bm.child[d] = ch[d];
+    }
+
+    // neighbour at offset o of box (L, c); returns false outside the domain
+    bool neighbour(int L, int64_t ix, int64_t iy, int64_t iz, int ox, int oy, int oz, int64_t* nx,
+                   int64_t* ny, int64_t* nz, int* px, int* py, int* pz) const
+    {
+        const int64_t M = (int64_t)1 << L;
+        int64_t c[3] = {ix + ox, iy + oy, iz + oz};
+        int p[3] = {0, 0, 0};
+        for (int k = 0; k < 3; ++k) {
+            if (c[k] < 0 || c[k] >= M) {
+                if (!periodic)
+                    return false;
+                p[k] = c[k] < 0 ? -1 : 1;
+                c[k] -= p[k] * M;
+            }
+        }
+        *nx = c[0];
+        *ny = c[1];
+        *nz = c[2];
+        *px = p[0];
+        *py = p[1];
+        *pz = p[2];
+        return true;
+    }
+
+    int find(int L, int64_t ix, int64_t iy, int64_t iz) const
+    {
+        auto it = lookup.find(box_key(L, ix, iy, iz));
+        return it == lookup.end() ? -1 : it->second;
+    }
+
+    // true if a child (bits cx,cy,cz) of the neighbour at offset o touches the
+    // box itself (closed boxes sharing at least a point)
+    static bool child_touches(int ox, int oy, int oz, int d)
+    {
+        const int c[3] = {(d >> 2) & 1, (d >> 1) & 1, d & 1};
+        const int o[3] = {ox, oy, oz};
+        for (int k = 0; k < 3; ++k) {
+            if (o[k] == 1 && c[k] != 0)
+                return false;
+            if (o[k] == -1 && c[k] != 1)
+                return false;
+        }
+        return true;
+    }
+
+    bool needs_split_for_balance(int id) const
+    {
+        const Box& B = boxes[id];
+        for (int ox = -1; ox <= 1; ++ox)
+            for (int oy = -1; oy <= 1; ++oy)
+                for (int oz = -1; oz <= 1; ++oz) {
+                    if (!ox && !oy && !oz)
+                        continue;
+                    int64_t nx, ny, nz;
+                    int px, py, pz;
+                    if (!neighbour(B.level, B.ix, B.iy, B.iz, ox, oy, oz, &nx, &ny, &nz, &px, &py, &pz))
+                        continue;
+                    const int C = find(B.level, nx, ny, nz);
+                    if (C < 0 || boxes[C].leaf)
+                        continue;
+                    for (int d = 0; d < 8; ++d) {
+                        const int ch = boxes[C].child[d];
+                        if (ch >= 0 && !boxes[ch].leaf && child_touches(ox, oy, oz, d))
+                            return true;
+                    }
+                }
+        return false;
+    }
+};
+
+}  // namespace
+
+void build_tree(const uint64_t* sorted_keys, int64_t n, int ns, bool periodic, Tree* T)
+{
+    Builder b;
+    b.keys = sorted_keys;
+    b.n = n;
+    b.periodic = periodic;
+    b.boxes.reserve(1024);
+    b.add(0, 0, 0, 0, -1, 0, n);
+    // adaptive refinement: split while a box holds more than ns points
+    for (size_t i = 0; i < b.boxes.size(); ++i) {
+        const Box& B = b.boxes[i];
+        if (B.end - B.start > ns && B.level < kMaxLevel)
+            b.split((int)i);
+    }
+    // 2:1 level restriction over vertex adjacency (empty leaves included)
+    for (int pass = 0; pass < 4 * kMaxLevel + 8; ++pass) {
+        std::vector<int> todo;
+        for (size_t i = 0; i < b.boxes.size(); ++i)
+            if (b.boxes[i].leaf && b.boxes[i].level < kMaxLevel && b.needs_split_for_balance((int)i))
+                todo.push_back((int)i);
+        if (todo.empty())
+            break;
+        for (int id : todo)
+            if (b.boxes[id].leaf)
+                b.split(id);
+    }
+    // order by level, Morton order within a level
+    std::vector<int> order(b.boxes.size());
+    for (size_t i = 0; i < order.size(); ++i)
+        order[i] = (int)i;
+    std::vector<uint64_t> kk(b.boxes.size());
+    for (size_t i = 0; i < kk.size(); ++i)
+        kk[i] = box_key(b.boxes[i].level, b.boxes[i].ix, b.boxes[i].iy, b.boxes[i].iz);
+    std::sort(order.begin(), order.end(), [&](int a, int c) { return kk[a] < kk[c]; });
+    std::vector<int> newid(order.size());
+    for (size_t i = 0; i < order.size(); ++i)
+        newid[order[i]] = (int)i;
+    T->boxes.resize(order.size());
+    for (size_t i = 0; i < order.size(); ++i) {
+        Box B = b.boxes[order[i]];
+        if (B.parent >= 0)
+            B.parent = newid[B.parent];
+        for (int d = 0; d < 8; ++d)
+            if (B.child[d] >= 0)
+                B.child[d] = newid[B.child[d]];
+        T->boxes[i] = B;
+    }
+    b.lookup.clear();
+    for (size_t i = 0; i < T->boxes.size(); ++i)
+        b.lookup[box_key(T->boxes[i].level, T->boxes[i].ix, T->boxes[i].iy, T->boxes[i].iz)] = (int)i;
+    b.boxes = T->boxes;
+    T->periodic = periodic;
+    T->n = n;
+    T->max_level = 0;
+    for (const Box& B : T->boxes)
+        T->max_level = std::max(T->max_level, B.level);
+    T->level_start.assign(T->max_level + 2, 0);
+    for (const Box& B : T->boxes)
+        T->level_start[B.level + 1]++;
+    for (int l = 0; l <= T->max_level; ++l)
+        T->level_start[l + 1] += T->level_start[l];
+
+    const int nb = (int)T->boxes.size();
+    // colleagues (same level, sharing a boundary point, incl. itself)
+    T->colleagues.assign(nb, {});
+    for (int i = 0; i < nb; ++i) {
+        const Box& B = T->boxes[i];
+        for (int ox = -1; ox <= 1; ++ox)
+            for (int oy = -1; oy <= 1; ++oy)
+                for (int oz = -1; oz <= 1; ++oz) {
+                    int64_t nx, ny, nz;
+                    int px, py, pz;
+                    if (!b.neighbour(B.level, B.ix, B.iy, B.iz, ox, oy, oz, &nx, &ny, &nz, &px, &py, &pz))
+                        continue;
+                    const int C = b.find(B.level, nx, ny, nz);
+                    if (C >= 0)
+                        T->colleagues[i].push_back(FarEntry{C, (int8_t)ox, (int8_t)oy, (int8_t)oz});
+                }
+    }
+    // difference-kernel exchange (leaf/non-leaf rule): a non-leaf box receives
+    // D_l from every non-empty colleague; a leaf receives D_l only from
+    // non-leaf colleagues.  Adjacent leaves then exchange the residual at the
+    // finer of their two levels directly, and every pair of points telescopes
+    // M_0 + sum D_l + R_lambda = K (or the omitted terms vanish by support).
+    T->incoming.assign(nb, {});
+    for (int i = 0; i < nb; ++i) {
+        const Box& B = T->boxes[i];
+        if (B.end == B.start)
+            continue;
+        for (const FarEntry& e : T->colleagues[i]) {
+            const Box& C = T->boxes[e.src];
+            if (C.end == C.start)
+                continue;
+            if (!B.leaf || !C.leaf)
+                T->incoming[i].push_back(e);
+        }
+    }
+    // near lists: adjacent non-empty leaves at levels L-1, L, L+1
+    T->leaves.clear();
+    T->near.clear();
+    T->n_near_pairs = 0;
+    for (int i = 0; i < nb; ++i) {
+        const Box& B = T->boxes[i];
+        if (!B.leaf || B.end == B.start)
+            continue;
+        std::vector<NearEntry> list;
+        auto add_entry = [&](int S, int px, int py, int pz, int lam) {
+            const Box& Sb = T->boxes[S];
+            if (Sb.end == Sb.start)
+                return;
+            list.push_back(NearEntry{S, (int8_t)px, (int8_t)py, (int8_t)pz, (int8_t)lam});
+            T->n_near_pairs += (B.end - B.start) * (Sb.end - Sb.start);
+        };
+        for (int ox = -1; ox <= 1; ++ox)
+            for (int oy = -1; oy <= 1; ++oy)
+                for (int oz = -1; oz <= 1; ++oz) {
+                    int64_t nx, ny, nz;
+                    int px, py, pz;
+                    if (!b.neighbour(B.level, B.ix, B.iy, B.iz, ox, oy, oz, &nx, &ny, &nz, &px, &py, &pz))
+                        continue;
+                    const int C = b.find(B.level, nx, ny, nz);
+                    if (C < 0)
+                        continue;
+                    if (T->boxes[C].leaf) {
+                        add_entry(C, px, py, pz, B.level);  // colleague leaf
+                    } else {
+                        for (int d = 0; d < 8; ++d) {  // fine neighbours
+                            const int ch = T->boxes[C].child[d];
+                            if (ch >= 0 && T->boxes[ch].leaf && Builder::child_touches(ox, oy, oz, d))
+                                add_entry(ch, px, py, pz, B.level + 1);
+                        }
+                    }
+                }
+        if (B.parent >= 0) {  // coarse neighbours: leaf colleagues of the parent touching B
+            const Box& P = T->boxes[B.parent];
+            const int bx = (int)(B.ix & 1), by = (int)(B.iy & 1), bz = (int)(B.iz & 1);
+            for (const FarEntry& e : T->colleagues[B.parent]) {
+                if (!e.ox && !e.oy && !e.oz)
+                    continue;
+                const Box& C = T->boxes[e.src];
+                if (!C.leaf)
+                    continue;
+                const int o[3] = {e.ox, e.oy, e.oz};
+                const int bb[3] = {bx, by, bz};
+                bool touch = true;
+                for (int k = 0; k < 3; ++k)
+                    if ((o[k] == 1 && bb[k] != 1) || (o[k] == -1 && bb[k] != 0))
+                        touch = false;
+                if (!touch)
+                    continue;
+                // periodic image shift of the parent's colleague
+                int64_t nx, ny, nz;
+                int px, py, pz;
+                b.neighbour(P.level, P.ix, P.iy, P.iz, e.ox, e.oy, e.oz, &nx, &ny, &nz, &px, &py, &pz);
+                add_entry(e.src, px, py, pz, B.level);
+            }
+        }
+        T->leaves.push_back(i);
+        T->near.push_back(std::move(list));
+    }
+}
+
+}  // namespace dmk

@@ -1,0 +1,107 @@
+"""GPU parity: the HIP path against the CPU oracle (direct sum / Ewald sum /
+independent residual-kernel evaluation), through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import splitting as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _dmk():
+    import paper_2509_21471_amd as dmk
+    return dmk
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+@pytest.mark.parametrize("tol,q", [(1e-6, 17), (1e-9, 25)])
+def test_residual_kernel_matches_oracle(dev, tol, q):
+    """Near-field pair routine vs the oracle's residual Stokeslet (eq.
+    res_stokeslet at scale r_lambda), brute force over all pairs."""
+    rng = np.random.default_rng(20)
+    rl = 0.125
+    xt = rng.random((300, 3)) * 0.3
+    xs = np.concatenate([rng.random((700, 3)) * 0.3, xt[:50]])  # includes coincident pairs
+    fs = rng.normal(size=(xs.shape[0], 3))
+    win = S.ProlateWindow(S.prolate_c(q))
+    ref = S.residual_pair_sum(win, xt, xs, fs, rl)
+    got = _dmk().residual_sum(_t(xt), _t(xs), _t(fs), rl, tol).cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"residual kernel tol={tol}: max rel err {err:.2e}")
+    assert err < 1e-11
+
+
+def test_uniform_1e4_matches_direct(dev):
+    x, f = workloads.config("uniform_1e4")
+    dmk = _dmk()
+    plan = dmk.Plan(_t(x), periodic=False, tol=1e-6)
+    u = plan.eval(_t(f)).cpu().numpy()
+    ref = oracle.direct(x, f)
+    err = oracle.rel_l2(u, ref)
+    print("uniform 1e4:", plan.info()["levels"], "levels, rel_l2", err)
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("n,leaf", [(1, 0), (2, 0), (50, 0), (2000, 100), (6000, 64)])
+def test_small_free_space(dev, n, leaf):
+    x, f = workloads.make("uniform", n, seed=30 + n)
+    plan = _dmk().Plan(_t(x), tol=1e-6, leaf_size=leaf)
+    u = plan.eval(_t(f)).cpu().numpy()
+    ref = oracle.direct(x, f)
+    if n == 1:
+        # exact answer 0; DMK leaves the self-term cancellation error, which is
+        # bounded by tol times the self-interaction scale |f| phi(0)/(2 pi)
+        assert np.abs(u).max() < 1e-6 * np.abs(f).max()
+        return
+    err = oracle.rel_l2(u, ref)
+    print(n, leaf, plan.info()["levels"], err)
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-9])
+def test_other_tolerances(dev, tol):
+    x, f = workloads.make("clusters", 8000, seed=41, sigma=0.05)
+    plan = _dmk().Plan(_t(x), tol=tol, leaf_size=150)
+    u = plan.eval(_t(f)).cpu().numpy()
+    err = oracle.rel_l2(u, oracle.direct(x, f))
+    print(tol, plan.info()["levels"], err)
+    assert err < tol
+
+
+def test_periodic_small(dev):
+    from oracle.ewald import ewald
+    x, f = workloads.make("periodic", 3000, seed=50)
+    plan = _dmk().Plan(_t(x), periodic=True, tol=1e-6, leaf_size=150)
+    u = plan.eval(_t(f)).cpu().numpy()
+    t = np.arange(0, 3000, 7)
+    ref = ewald(x, f, t)
+    err = oracle.rel_l2(u[t], ref)
+    print("periodic", plan.info()["levels"], err)
+    assert err < 1e-6
+
+
+def test_tree_invariants(dev):
+    x, f = workloads.make("clusters", 20000, seed=60, sigma=0.03)
+    plan = _dmk().Plan(_t(x), tol=1e-6, leaf_size=200)
+    info = plan.info()
+    lev, crd, cnt, pl = plan.tree_leaves()
+    assert cnt.sum() == x.shape[0]
+    assert np.all(cnt[lev < 19] <= 200)
+    # every point lies in its leaf's box (unit-box coordinates)
+    u = (x - np.array(info["center"])) / info["box_len"] + 0.5
+    h = 1.0 / (1 << lev[pl])
+    lo = crd[pl] * h[:, None]
+    assert np.all(u >= lo - 1e-12) and np.all(u <= lo + h[:, None] + 1e-12)
+    # 2:1 balance between leaves sharing a boundary point (brute force)
+    hs = 1.0 / (1 << lev)
+    blo = crd * hs[:, None]
+    bhi = blo + hs[:, None]
+    for i in range(len(lev)):
+        touch = np.all((blo <= bhi[i] + 1e-15) & (bhi >= blo[i] - 1e-15), axis=1)
+        assert np.all(np.abs(lev[touch] - lev[i]) <= 1), i
