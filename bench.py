@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Benchmark: DMK Stokeslet sum on one MI355X.
+
+A step is one pass of the whole path over the benchmark input: plan (bounding
+box, Morton sort, adaptive level-restricted octree, neighbour lists, device
+buffers; the per-tolerance tables are cached per process) followed by one
+evaluation (all far-field passes, near field, finalize), and the release of
+the previous step's plan.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line (see the field list at the end of main()).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Stokeslet targets/sec at 1e6 pts, 1e-6 rel L2: FP64 vs mixed/batched"
+PEAK_FP64_VECTOR_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+
+
+def near_flops_per_pair(deg_P: int, deg_Q: int) -> int:
+    """Algorithmic flops of one residual-kernel pair (difference 3, r^2 5,
+    rsqrt 1, s 1, y.f 5, the two scalar coefficients 8, update 12, and a
+    degree-d polynomial 2d each)."""
+    return 35 + 2 * (deg_P + deg_Q)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="clusters_1e6")
+    ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--leaf-size", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=int, default=12000)
+    ap.add_argument("--parity-sample", type=int, default=300)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2509_21471_amd as dmk
+    import workloads
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    cfg = workloads.CONFIGS[args.config]
+    tol = args.tol if args.tol is not None else cfg["tol"]
+    periodic = bool(cfg["periodic"])
+    x, f = workloads.make(cfg["kind"], cfg["n"], cfg["seed"], cfg["sigma"])
+    n = x.shape[0]
+    xd = torch.from_numpy(x).to(dev)
+    fd = torch.from_numpy(f).to(dev)
+    out = torch.empty_like(fd)
+    torch.cuda.synchronize()
+    print(f"# input ready: {args.config} n={n} tol={tol}", file=sys.stderr, flush=True)
+
+    def make_plan():
+        return dmk.Plan(xd, periodic=periodic, tol=tol, leaf_size=args.leaf_size, timing=True)
+
+    # warmup (also builds the per-tolerance tables once)
+    for _ in range(args.warmup):
+        p = make_plan()
+        p.eval(fd, out)
+        torch.cuda.synchronize()
+        p.close()
+    print("# warmup done", file=sys.stderr, flush=True)
+
+    # timed region: K full steps (plan + eval)
+    near_ms, phases_acc = [], []
+    prev = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        p = make_plan()
+        if prev is not None:
+            ph = prev.phase_ms()
+            phases_acc.append(ph)
+            near_ms.append(ph["near"])
+            prev.close()
+        p.eval(fd, out)
+        prev = p
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ph = prev.phase_ms()
+    phases_acc.append(ph)
+    near_ms.append(ph["near"])
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    plan = prev
+    info = plan.info()
+    print(f"# timed: {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
+
+    # eval-only rate on the last plan
+    for _ in range(2):
+        plan.eval(fd, out)
+    torch.cuda.synchronize()
+    te0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.eval(fd, out)
+    torch.cuda.synchronize()
+    eval_ms = (time.perf_counter() - te0) * 1e3 / args.steps
+
+    stats = plan.near_stats()
+    fpp = near_flops_per_pair(info["deg_P"], info["deg_Q"])
+    t_near = float(np.mean(near_ms)) * 1e-3
+    achieved = stats["in_support"] * fpp / t_near / 1e12
+    phases = {k: float(np.mean([a[k] for a in phases_acc])) for k in phases_acc[0]}
+
+    result = {
+        "metric": METRIC,
+        "value": n / (ms_per_step * 1e-3),
+        "unit": "targets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.config, "n": n, "kind": cfg["kind"], "sigma": cfg["sigma"],
+                   "periodic": periodic, "tol": tol, "precision": "fp64", "step": "plan+eval",
+                   "leaf_size": info["leaf_size"]},
+        "roofline": {"bound": "alu", "kernel": "k_near", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+                     "near_ms": t_near * 1e3, "pairs_in_support": stats["in_support"],
+                     "pairs_evaluated": stats["evaluated"], "pairs_listed": stats["listed"],
+                     "flops_per_pair": fpp},
+        "eval_only_ms": eval_ms,
+        "eval_only_targets_per_s": n / (eval_ms * 1e-3),
+        "phases_ms": phases,
+        "tree": {k: info[k] for k in ("levels", "n_boxes", "n_nonempty_leaves", "n_senders", "n_receivers",
+                                      "device_bytes", "plan_ms", "p", "n1", "deg_P", "deg_Q")},
+    }
+
+    if not args.no_parity:
+        import oracle
+        idx = workloads.sample_targets(n, args.parity_sample, cfg["seed"])
+        u = out.cpu().numpy()
+        if periodic:
+            from oracle.ewald import ewald
+            ref = ewald(x, f, idx, E=25.0)
+        else:
+            ref = oracle.direct(x, f, idx)
+        result["rel_l2_sampled"] = oracle.rel_l2(u[idx], ref)
+        result["parity_sample"] = int(idx.size)
+
+    if not args.no_cpu_baseline and not periodic:
+        import oracle
+        idx = workloads.sample_targets(n, args.cpu_sample, cfg["seed"] + 1)
+        tc0 = time.perf_counter()
+        oracle.direct(x, f, idx)
+        tc = time.perf_counter() - tc0
+        result["cpu_baseline"] = {"value": idx.size / tc, "unit": "targets/s", "cores": oracle.num_threads(),
+                                  "kind": "oracle",
+                                  "sample": f"{idx.size} seeded targets of the {n}-point input, each summing "
+                                            f"all {n} sources (direct O(N^2) FP64 sum), {tc:.1f} s"}
+    plan.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -60,7 +60,25 @@ typedef struct {
     int leaf_size;        /* maximum points per leaf; 0 = the tolerance's default */
     void* stream;         /* hipStream_t for all work of the plan; NULL = null stream */
     size_t mem_cap_bytes; /* refuse plans whose device buffers exceed this; 0 = no cap */
+    int flags;            /* DMK_FLAG_* bits */
 } dmk_opts;
+
+/* record HIP events around each phase of dmk_stokes_eval (read back with
+ * dmk_stokes_phase_ms) */
+#define DMK_FLAG_PHASE_TIMING 1
+
+/* phases reported by dmk_stokes_phase_ms, in this order */
+#define DMK_PHASE_ANTERP 0     /* force gather + leaf proxy charges (Step 2a) */
+#define DMK_PHASE_MERGE 1      /* upward merge (Step 2b) */
+#define DMK_PHASE_OUTGOING 2   /* outgoing plane waves */
+#define DMK_PHASE_TRANSLATE 3  /* colleague translation + difference symbol (Step 3b) */
+#define DMK_PHASE_INCOMING 4   /* incoming plane waves -> proxy potentials */
+#define DMK_PHASE_ROOT 5       /* root convolution (Step 3a) */
+#define DMK_PHASE_INTERP 6     /* downward interpolation */
+#define DMK_PHASE_LEAF_EVAL 7  /* far field at the points */
+#define DMK_PHASE_NEAR 8       /* residual pair sums + self term (Step 4) */
+#define DMK_PHASE_FINALIZE 9   /* constant, scaling, unpermute */
+#define DMK_NUM_PHASES 10
 
 typedef struct {
     /* parameters (Table tab:params, Stokeslet, PSWF columns) */
@@ -119,6 +137,23 @@ int dmk_stokes_plan_info(dmk_plan_t plan, dmk_plan_info* info);
  */
 int dmk_stokes_tree_leaves(dmk_plan_t plan, int32_t* leaf_level, int64_t* leaf_coord, int64_t* leaf_count,
                            int64_t* point_leaf);
+
+/*
+ * Milliseconds spent in each phase of the most recent dmk_stokes_eval call on
+ * this plan (first right-hand side), out[DMK_NUM_PHASES] host array.  Needs
+ * DMK_FLAG_PHASE_TIMING; synchronises on the recorded events.
+ */
+int dmk_stokes_phase_ms(dmk_plan_t plan, double* out);
+
+/*
+ * Near-field pair statistics of the plan (host int64 outputs, NULL to skip):
+ *   listed     sum over near-list entries of |target leaf| * |source leaf|
+ *   evaluated  pairs left after the 64-point chunk bounding-box pruning
+ *   in_support pairs with 0 < |x_t - x_s + shift| < r_lambda (the residual's
+ *              support, Corollary eq. reskernelproperty)
+ * Runs a counting kernel; synchronises the stream.
+ */
+int dmk_stokes_near_stats(dmk_plan_t plan, int64_t* listed, int64_t* evaluated, int64_t* in_support);
 
 /* Releases the plan and its device memory (NULL-safe). */
 void dmk_stokes_destroy(dmk_plan_t plan);

@@ -21,7 +21,11 @@ PREC_FP64, PREC_MIXED = 0, 1
 
 SYMBOLS = ["dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_eval", "dmk_stokes_plan_info",
            "dmk_stokes_tree_leaves", "dmk_stokes_destroy", "dmk_last_error", "dmk_stokes_params",
-           "dmk_stokes_radial", "dmk_stokes_mollifier", "dmk_stokes_residual_sum"]
+           "dmk_stokes_radial", "dmk_stokes_mollifier", "dmk_stokes_residual_sum", "dmk_stokes_phase_ms",
+           "dmk_stokes_near_stats"]
+PHASES = ["anterp", "merge", "outgoing", "translate", "incoming", "root", "interp", "leaf_eval", "near",
+          "finalize"]
+FLAG_PHASE_TIMING = 1
 
 
 class DMKError(RuntimeError):
@@ -32,7 +36,7 @@ class DMKError(RuntimeError):
 
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("leaf_size", ctypes.c_int), ("stream", ctypes.c_void_p),
-                ("mem_cap_bytes", ctypes.c_size_t)]
+                ("mem_cap_bytes", ctypes.c_size_t), ("flags", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -79,6 +83,8 @@ def lib():
         L.dmk_stokes_radial.argtypes = [ctypes.c_double, dp, i64, dp]
         L.dmk_stokes_mollifier.argtypes = [ctypes.c_double, dp, i64, dp]
         L.dmk_stokes_residual_sum.argtypes = [vp, i64, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp]
+        L.dmk_stokes_phase_ms.argtypes = [vp, dp]
+        L.dmk_stokes_near_stats.argtypes = [vp, vp, vp, vp]
         for s in SYMBOLS:
             if s not in ("dmk_stokes_destroy", "dmk_last_error"):
                 getattr(L, s).restype = ctypes.c_int
@@ -145,12 +151,13 @@ class Plan:
     """A DMK plan over device points (sources = targets)."""
 
     def __init__(self, points, periodic: bool = False, tol: float = 1e-6, precision: int = PREC_FP64,
-                 leaf_size: int = 0, stream=None, mem_cap_bytes: int = 0):
+                 leaf_size: int = 0, stream=None, mem_cap_bytes: int = 0, timing: bool = False):
         torch = _torch()
         pts = _dev_f64(points)
         self.n = int(pts.shape[0])
         self.stream = stream
-        opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), int(mem_cap_bytes))
+        opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), int(mem_cap_bytes),
+                    FLAG_PHASE_TIMING if timing else 0)
         h = ctypes.c_void_p()
         _check(lib().dmk_stokes_plan_ex(ctypes.c_void_p(pts.data_ptr()), self.n, 3, int(bool(periodic)),
                                         float(tol), ctypes.byref(opts), ctypes.byref(h)))
@@ -173,6 +180,16 @@ class Plan:
         info = PlanInfo()
         _check(lib().dmk_stokes_plan_info(self._h, ctypes.byref(info)))
         return info.as_dict()
+
+    def phase_ms(self) -> dict:
+        out = np.zeros(len(PHASES))
+        _check(lib().dmk_stokes_phase_ms(self._h, _dp(out)))
+        return dict(zip(PHASES, out.tolist()))
+
+    def near_stats(self) -> dict:
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().dmk_stokes_near_stats(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"listed": a.value, "evaluated": b.value, "in_support": c.value}
 
     def tree_leaves(self):
         info = self.info()

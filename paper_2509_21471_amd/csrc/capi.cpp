@@ -142,6 +142,16 @@ struct dmk_plan_s {
     double* cst = nullptr;
     size_t H = 0, Hroot = 0;
     std::vector<int> leaf_box;        // leaf index (all leaves) -> box id
+    // phase timing
+    bool timing = false;
+    hipEvent_t ev[DMK_NUM_PHASES + 1] = {};
+    bool ev_recorded = false;
+    ~dmk_plan_s()
+    {
+        for (auto& e : ev)
+            if (e)
+                (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -499,10 +509,15 @@ int build_plan(dmk_plan_t P, const double* points)
     return DMK_OK;
 }
 
-int eval_one(dmk_plan_t P, const double* f, double* vel)
+int eval_one(dmk_plan_t P, const double* f, double* vel, bool record)
 {
     using namespace dmk;
     hipStream_t st = P->stream;
+    auto mark = [&](int k) {
+        if (record)
+            (void)hipEventRecord(P->ev[k], st);
+    };
+    mark(0);
     const int64_t n = P->n;
     const int p = P->prm.p, q = P->prm.q, n1 = P->prm.n1;
     const long p3 = (long)p * p * p, p2 = (long)p * p;
@@ -510,6 +525,7 @@ int eval_one(dmk_plan_t P, const double* f, double* vel)
     launch_gather_forces(f, n, P->perm, P->fs, st);
     // Step 2a: proxy charges of the leaves
     launch_anterp(p, P->leaves, P->nleaf, P->x, P->y, P->z, P->fs, n, P->cheb_t, P->cheb_w, P->Q, st);
+    mark(1);
     // Step 2b: merge children into parents, finest level first
     for (int l = T.max_level - 1; l >= 0; --l) {
         const auto& L = P->lev[l];
@@ -521,6 +537,7 @@ int eval_one(dmk_plan_t P, const double* f, double* vel)
         contract(P, P->s2, 2 * p3, nullptr, X_REAL, P->up, 0, P->Q, p3, L.parent_fid, Y_STORE_REAL, 2 * p, p * p, p,
                  L.nparent);
     }
+    mark(2);
     // outgoing plane waves of the senders
     const long H = (long)P->H;
     contract(P, P->Q, p3, P->send_fid, X_REAL, P->e_half, 1, P->s1, p2 * q, nullptr, Y_STORE_CPLX, p, p * p, q,
@@ -529,8 +546,10 @@ int eval_one(dmk_plan_t P, const double* f, double* vel)
              p * q, n1, P->nsend);
     contract(P, P->s2, (long)p * q * n1, nullptr, X_CPLX, P->e_full, 1, P->Phi, H, nullptr, Y_STORE_CPLX, p, q * n1,
              n1, P->nsend);
+    mark(3);
     // Step 3b: translation with the difference-kernel symbol
     launch_translate(q, n1, P->recv, P->nrecv, P->e_src, P->e_off, P->Phi, P->wdiff, P->Psi, st);
+    mark(4);
     // incoming plane waves -> proxy potentials
     launch_zero(P->V, (size_t)P->nf * 3 * p3, st);
     contract(P, P->Psi, H, nullptr, X_CPLX, P->g_half, 1, P->s1, (long)n1 * n1 * p, nullptr, Y_STORE_CPLX, q,
@@ -539,6 +558,7 @@ int eval_one(dmk_plan_t P, const double* f, double* vel)
              Y_STORE_CPLX, n1, n1 * p, p, P->nrecv);
     contract(P, P->s2, (long)n1 * p * p, nullptr, X_CPLX, P->g_full, 1, P->V, p3, P->recv_fid, Y_ADD_REALPART, n1,
              p * p, p, P->nrecv);
+    mark(5);
     // Step 3a: root convolution with the (truncated or periodic) mollified kernel
     {
         const int mh = P->root_mh, mf = P->root_mf;
@@ -561,6 +581,7 @@ int eval_one(dmk_plan_t P, const double* f, double* vel)
         if (!P->periodic)
             launch_sum_root(Qr, (int)p3, 1.0 / (4.0 * kPi * (1.0 + std::sqrt(3.0))), P->cst, st);
     }
+    mark(6);
     // downward interpolation, coarsest level first
     for (int l = 0; l < T.max_level; ++l) {
         const auto& L = P->lev[l];
@@ -572,11 +593,17 @@ int eval_one(dmk_plan_t P, const double* f, double* vel)
                  2 * p, L.nparent);
         launch_interp_stage3(p, L.child_fid, L.nparent, (const double*)P->s2, P->down, P->V, st);
     }
+    mark(7);
     // far field at the points, then the near field (Step 4) and self term
     launch_leaf_eval(p, P->leaves, P->nleaf, P->x, P->y, P->z, n, P->cheb_t, P->cheb_w, P->V, P->u, st);
+    mark(8);
     launch_near(P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x, P->y, P->z, P->fs, n, P->poly,
                 -P->tab->phi0 / (2.0 * kPi), P->u, st);
+    mark(9);
     launch_finalize(P->u, n, P->perm, 1.0 / P->box_len, P->periodic ? nullptr : P->cst, vel, st);
+    mark(10);
+    if (record)
+        P->ev_recorded = true;
     return DMK_OK;
 }
 
@@ -675,7 +702,15 @@ int dmk_stokes_plan_ex(const double* points, int64_t n, int dim, int periodic, d
         if (opts->leaf_size > 0)
             P->prm.ns = opts->leaf_size;
         P->mem.cap = opts->mem_cap_bytes;
+        P->timing = (opts->flags & DMK_FLAG_PHASE_TIMING) != 0;
     }
+    if (P->timing)
+        for (auto& e : P->ev)
+            if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipGetLastError();
+                delete P;
+                return fail(DMK_ERR_HIP, "hipEventCreate failed");
+            }
     P->n = n;
     P->periodic = periodic != 0;
     rc = build_plan(P, points);
@@ -703,7 +738,8 @@ int dmk_stokes_eval(dmk_plan_t plan, const double* forces, int n_rhs, double* ve
     if (!is_device_ptr(forces) || !is_device_ptr(velocities))
         return fail(DMK_ERR_ARG, "forces and velocities must be device pointers");
     for (int r = 0; r < n_rhs; ++r) {
-        const int rc = eval_one(plan, forces + (size_t)r * 3 * plan->n, velocities + (size_t)r * 3 * plan->n);
+        const int rc = eval_one(plan, forces + (size_t)r * 3 * plan->n, velocities + (size_t)r * 3 * plan->n,
+                                plan->timing && r == 0);
         if (rc != DMK_OK)
             return rc;
     }
@@ -773,6 +809,44 @@ int dmk_stokes_tree_leaves(dmk_plan_t plan, int32_t* leaf_level, int64_t* leaf_c
                 point_leaf[perm[i]] = (int64_t)li;
         }
     }
+    return DMK_OK;
+}
+
+int dmk_stokes_phase_ms(dmk_plan_t plan, double* out)
+{
+    if (!plan || !out)
+        return fail(DMK_ERR_ARG, "plan or out is NULL");
+    if (!plan->timing || !plan->ev_recorded)
+        return fail(DMK_ERR_ARG, "no timed evaluation recorded (DMK_FLAG_PHASE_TIMING)");
+    HIPCHK(hipEventSynchronize(plan->ev[DMK_NUM_PHASES]));
+    for (int k = 0; k < DMK_NUM_PHASES; ++k) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, plan->ev[k], plan->ev[k + 1]));
+        out[k] = ms;
+    }
+    return DMK_OK;
+}
+
+int dmk_stokes_near_stats(dmk_plan_t plan, int64_t* listed, int64_t* evaluated, int64_t* in_support)
+{
+    if (!plan)
+        return fail(DMK_ERR_ARG, "plan is NULL");
+    if (listed)
+        *listed = plan->tree.n_near_pairs;
+    DevMem mem;
+    unsigned long long* d = mem.alloc<unsigned long long>(2);
+    if (!d)
+        return fail(DMK_ERR_OOM, "device allocation failed");
+    HIPCHK(hipMemsetAsync(d, 0, 2 * sizeof(unsigned long long), plan->stream));
+    dmk::launch_near_count(plan->nwork, plan->n_nwork, plan->nleaves, plan->nentries, plan->cbbox, plan->x,
+                           plan->y, plan->z, d, plan->stream);
+    unsigned long long h[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, plan->stream));
+    HIPCHK(hipStreamSynchronize(plan->stream));
+    if (evaluated)
+        *evaluated = (int64_t)h[0];
+    if (in_support)
+        *in_support = (int64_t)h[1];
     return DMK_OK;
 }
 

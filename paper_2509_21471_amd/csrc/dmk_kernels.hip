@@ -762,6 +762,61 @@ void launch_near(const NearWork* work, int nwork, const NearLeaf* leaves, const 
                        self_coef, u);
 }
 
+__global__ __launch_bounds__(64) void k_near_count(const NearWork* __restrict__ work,
+                                                   const NearLeaf* __restrict__ leaves,
+                                                   const NearEntryDev* __restrict__ entries,
+                                                   const double* __restrict__ cbbox, const double* __restrict__ x,
+                                                   const double* __restrict__ y, const double* __restrict__ z,
+                                                   unsigned long long* __restrict__ out)
+{
+    const NearWork w = work[blockIdx.x];
+    const NearLeaf T = leaves[w.leaf];
+    const int64_t i = T.tstart + (int64_t)w.chunk * 64 + threadIdx.x;
+    const bool valid = i < T.tend;
+    const int nt = (int)min((int64_t)64, T.tend - (T.tstart + (int64_t)w.chunk * 64));
+    const double xt = valid ? x[i] : 0.0, yt = valid ? y[i] : 0.0, zt = valid ? z[i] : 0.0;
+    const double* tb = cbbox + 6 * (size_t)(T.cbase + w.chunk);
+    const double tlo[3] = {tb[0], tb[1], tb[2]}, thi[3] = {tb[3], tb[4], tb[5]};
+    unsigned long long ev = 0, in = 0;
+    for (int e = T.ebeg; e < T.eend; ++e) {
+        const NearEntryDev E = entries[e];
+        const double rl = 1.0 / (double)(1ll << E.lambda);
+        const double rl2 = rl * rl;
+        const double sh[3] = {(double)E.sx, (double)E.sy, (double)E.sz};
+        const int nch = (int)((E.send - E.sstart + 63) / 64);
+        for (int k = 0; k < nch; ++k) {
+            const double* sb = cbbox + 6 * (size_t)(E.cbase + k);
+            double gap2 = 0;
+            for (int d = 0; d < 3; ++d) {
+                const double g = fmax(0.0, fmax(sb[d] + sh[d] - thi[d], tlo[d] - (sb[3 + d] + sh[d])));
+                gap2 += g * g;
+            }
+            if (gap2 >= rl2)
+                continue;
+            const int64_t s0 = E.sstart + 64 * (int64_t)k;
+            const int64_t s1 = min(s0 + 64, E.send);
+            if (threadIdx.x == 0)
+                ev += (unsigned long long)(s1 - s0) * nt;
+            for (int64_t j = s0; j < s1 && valid; ++j) {
+                const double dx = xt - (x[j] + sh[0]), dy = yt - (y[j] + sh[1]), dz = zt - (z[j] + sh[2]);
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                in += (r2 < rl2 && r2 > 0.0) ? 1ull : 0ull;
+            }
+        }
+    }
+    atomicAdd(&out[0], ev);
+    atomicAdd(&out[1], in);
+}
+
+void launch_near_count(const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
+                       const double* cbbox, const double* x, const double* y, const double* z,
+                       unsigned long long* out, hipStream_t s)
+{
+    if (nwork == 0)
+        return;
+    hipLaunchKernelGGL(k_near_count, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, out);
+}
+
 __global__ __launch_bounds__(64) void k_residual_direct(const double* __restrict__ tx, const double* __restrict__ ty,
                                                         const double* __restrict__ tz, int64_t m,
                                                         const double* __restrict__ sx, const double* __restrict__ sy,

@@ -112,6 +112,11 @@ void launch_near(const NearWork* work, int nwork, const NearLeaf* leaves, const 
                  const double* cbbox, const double* x, const double* y, const double* z, const double* fs,
                  int64_t n, const RadialPoly& poly, double self_coef, double* u, hipStream_t s);
 
+// pair counts of the near field: out[0] += evaluated pairs, out[1] += pairs in support
+void launch_near_count(const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
+                       const double* cbbox, const double* x, const double* y, const double* z,
+                       unsigned long long* out, hipStream_t s);
+
 // brute-force residual sum over all source points (stage entry point)
 void launch_residual_direct(const double* tx, const double* ty, const double* tz, int64_t m, const double* sx,
                             const double* sy, const double* sz, const double* sf, int64_t ns, double r_lambda,
