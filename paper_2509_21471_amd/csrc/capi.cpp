@@ -195,6 +195,43 @@ void contract(dmk_plan_t P, const void* X, long xs, const int* xmap, int xkind, 
     dmk::launch_contract(a, P->stream);
 }
 
+// Chebyshev series in t -> monomial coefficients in t (long double), both
+// padded to a kernel instantiation length
+bool make_poly(const dmk::Tables& TB, dmk::RadialPoly* poly)
+{
+    const int nmax = (int)std::max(TB.fits.P.a.size(), TB.fits.Q.a.size());
+    const int nd = nmax <= 14 ? 14 : nmax <= 18 ? 18 : nmax <= 21 ? 21 : 24;
+    if (nmax > 24)
+        return false;
+    auto conv = [&](const std::vector<double>& a, double* out) {
+        const int n = (int)a.size();
+        std::vector<long double> tkm1(nd, 0.0L), tk(nd, 0.0L), acc(nd, 0.0L);
+        tkm1[0] = 1.0L;  // T_0
+        if (nd > 1)
+            tk[1] = 1.0L;  // T_1
+        for (int k = 0; k < n; ++k) {
+            const std::vector<long double>& T = (k == 0) ? tkm1 : tk;
+            for (int j = 0; j < nd; ++j)
+                acc[j] += (long double)a[k] * T[j];
+            if (k >= 1) {  // advance: T_{k+1} = 2 t T_k - T_{k-1}
+                std::vector<long double> nx(nd, 0.0L);
+                for (int j = 0; j + 1 < nd; ++j)
+                    nx[j + 1] += 2.0L * tk[j];
+                for (int j = 0; j < nd; ++j)
+                    nx[j] -= tkm1[j];
+                tkm1 = tk;
+                tk = nx;
+            }
+        }
+        for (int j = 0; j < nd; ++j)
+            out[j] = (double)acc[j];
+    };
+    poly->nd = nd;
+    conv(TB.fits.P.a, poly->P);
+    conv(TB.fits.Q.a, poly->Q);
+    return true;
+}
+
 int build_plan(dmk_plan_t P, const double* points)
 {
     using namespace dmk;
@@ -496,14 +533,8 @@ int build_plan(dmk_plan_t P, const double* points)
     HIPCHK(upload(P->wroot, wr));
     launch_chunk_bbox(P->x, P->y, P->z, d_cstart, d_clen, (int)cstart.size(), P->cbbox, st);
     // radial polynomials
-    if (TB.fits.P.a.size() > 48 || TB.fits.Q.a.size() > 48)
+    if (!make_poly(TB, &P->poly))
         return fail(DMK_ERR_UNSUPPORTED, "radial fit degree too high");
-    P->poly.nP = (int)TB.fits.P.a.size();
-    P->poly.nQ = (int)TB.fits.Q.a.size();
-    for (int k = 0; k < 48; ++k) {
-        P->poly.P[k] = k < P->poly.nP ? TB.fits.P.a[k] : 0.0;
-        P->poly.Q[k] = k < P->poly.nQ ? TB.fits.Q.a[k] : 0.0;
-    }
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipGetLastError());
     return DMK_OK;
@@ -760,8 +791,8 @@ int dmk_stokes_plan_info(dmk_plan_t plan, dmk_plan_info* info)
     info->n1 = P.prm.n1;
     info->nper = P.prm.nper;
     info->leaf_size = P.prm.ns;
-    info->deg_P = P.poly.nP - 1;
-    info->deg_Q = P.poly.nQ - 1;
+    info->deg_P = (int)P.tab->fits.P.a.size() - 1;
+    info->deg_Q = (int)P.tab->fits.Q.a.size() - 1;
     info->levels = P.tree.max_level + 1;
     info->periodic = P.periodic;
     info->n_points = P.n;
@@ -891,12 +922,8 @@ int dmk_stokes_residual_sum(const double* targets, int64_t m, const double* sour
                                 hipMemcpyDeviceToDevice, st));
     }
     dmk::RadialPoly poly;
-    poly.nP = (int)T->fits.P.a.size();
-    poly.nQ = (int)T->fits.Q.a.size();
-    for (int k = 0; k < 48; ++k) {
-        poly.P[k] = k < poly.nP ? T->fits.P.a[k] : 0.0;
-        poly.Q[k] = k < poly.nQ ? T->fits.Q.a[k] : 0.0;
-    }
+    if (!make_poly(*T, &poly))
+        return fail(DMK_ERR_UNSUPPORTED, "radial fit degree too high");
     dmk::launch_residual_direct(tx, tx + m, tx + 2 * m, m, sx, sx + ns, sx + 2 * ns, sf, ns, r_lambda, poly, out,
                                 st);
     HIPCHK(hipGetLastError());

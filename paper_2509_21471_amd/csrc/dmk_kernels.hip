@@ -671,47 +671,64 @@ void launch_root_symbol(int mh, int mf, const cplx* Phi, const double* w, cplx* 
 // ---- near field -----------------------------------------------------------------
 // Residual Stokeslet at scale r_l (r < r_l):
 //   S_R(y) f = f/(8 pi r) + (y.f) y/(8 pi r^3) - [P(s) f + Q(s) (y.f) y / r_l^2]/(4 pi r_l),
-// s = r^2 / r_l^2, P, Q Chebyshev series in t = 2s - 1.
-__device__ inline double clenshaw(const double* __restrict__ a, int n, double t)
+// s = r^2 / r_l^2, with P and Q polynomials in t = 2s - 1 (monomial
+// coefficients, Horner; their signs alternate so Horner is as stable as the
+// Chebyshev form).
+__device__ inline double rsqrt_f64(double x)
 {
-    double b1 = 0, b2 = 0;
-    const double t2 = 2.0 * t;
-    for (int k = n - 1; k >= 1; --k) {
-        const double b0 = fma(t2, b1, a[k] - b2);
-        b2 = b1;
-        b1 = b0;
-    }
-    return fma(t, b1, a[0] - b2);
+    // hardware estimate refined by one second-order Newton step:
+    // e = 1 - x y^2,  y <- y + y e (1/2 + 3/8 e)
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
+template <int ND>
+__device__ inline double horner(const double* __restrict__ m, double t)
+{
+    double p = m[ND - 1];
+#pragma unroll
+    for (int k = ND - 2; k >= 0; --k)
+        p = fma(p, t, m[k]);
+    return p;
+}
+
+template <int ND>
 __device__ inline void residual_pair(double dx, double dy, double dz, double fx, double fy, double fz, double rl2,
-                                     double inv_rl2, double cP, double cQ, const RadialPoly& poly, double& u0,
+                                     double tw, double cP, double cQ, const RadialPoly& poly, double& u0,
                                      double& u1, double& u2)
 {
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    const bool in = (r2 < rl2) && (r2 > 0.0);
-    const double r2s = in ? r2 : 0.25 * rl2;
-    const double rinv = rsqrt(r2s);
-    const double t = fma(2.0 * inv_rl2, r2s, -1.0);
-    const double P = clenshaw(poly.P, poly.nP, t);
-    const double Q = clenshaw(poly.Q, poly.nQ, t);
-    const double dot = fma(dx, fx, fma(dy, fy, dz * fz));
-    const double a = in ? fma(kInv8Pi, rinv, -cP * P) : 0.0;
-    const double b = in ? dot * fma(kInv8Pi * rinv, rinv * rinv, -cQ * Q) : 0.0;
-    u0 = fma(a, fx, fma(b, dx, u0));
-    u1 = fma(a, fy, fma(b, dy, u1));
-    u2 = fma(a, fz, fma(b, dz, u2));
+    if (r2 < rl2 && r2 > 0.0) {
+        const double rinv = rsqrt_f64(r2);
+        const double t = fma(r2, tw, -1.0);
+        const double P = horner<ND>(poly.P, t);
+        const double Q = horner<ND>(poly.Q, t);
+        const double dot = fma(dx, fx, fma(dy, fy, dz * fz));
+        const double cr = kInv8Pi * rinv;
+        const double a = fma(-cP, P, cr);
+        const double b = dot * fma(-cQ, Q, cr * rinv * rinv);
+        u0 = fma(a, fx, fma(b, dx, u0));
+        u1 = fma(a, fy, fma(b, dy, u1));
+        u2 = fma(a, fz, fma(b, dz, u2));
+    }
 }
 
+// One wave per 64 targets of a leaf.  Each non-pruned 64-point source chunk of
+// every near-list entry is staged in LDS (periodic shift applied) and read
+// back by broadcast.
+template <int ND>
 __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, const NearLeaf* __restrict__ leaves,
                                              const NearEntryDev* __restrict__ entries, const double* __restrict__ cbbox,
                                              const double* __restrict__ x, const double* __restrict__ y,
                                              const double* __restrict__ z, const double* __restrict__ fs, int64_t n,
                                              RadialPoly poly, double self_coef, double* __restrict__ u)
 {
+    __shared__ double2 S[64][3];
     const NearWork w = work[blockIdx.x];
     const NearLeaf T = leaves[w.leaf];
-    const int64_t i = T.tstart + (int64_t)w.chunk * 64 + threadIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t i = T.tstart + (int64_t)w.chunk * 64 + lane;
     const bool valid = i < T.tend;
     const double xt = valid ? x[i] : 0.0, yt = valid ? y[i] : 0.0, zt = valid ? z[i] : 0.0;
     const double* tb = cbbox + 6 * (size_t)(T.cbase + w.chunk);
@@ -722,6 +739,7 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
         const double rl = 1.0 / (double)(1ll << E.lambda);
         const double rl2 = rl * rl, inv_rl2 = 1.0 / rl2;
         const double cP = 1.0 / (4.0 * kPi * rl), cQ = cP * inv_rl2;
+        const double tw = 2.0 * inv_rl2;
         const double sh[3] = {(double)E.sx, (double)E.sy, (double)E.sz};
         const int nch = (int)((E.send - E.sstart + 63) / 64);
         for (int k = 0; k < nch; ++k) {
@@ -735,12 +753,18 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
             if (gap2 >= rl2)
                 continue;
             const int64_t s0 = E.sstart + 64 * (int64_t)k;
-            const int64_t s1 = min(s0 + 64, E.send);
-            for (int64_t j = s0; j < s1; ++j) {
-                const double dx = xt - (x[j] + sh[0]);
-                const double dy = yt - (y[j] + sh[1]);
-                const double dz = zt - (z[j] + sh[2]);
-                residual_pair(dx, dy, dz, fs[j], fs[n + j], fs[2 * n + j], rl2, inv_rl2, cP, cQ, poly, u0, u1, u2);
+            const int cnt = (int)min((int64_t)64, E.send - s0);
+            __syncthreads();
+            if (lane < cnt) {
+                const int64_t j = s0 + lane;
+                S[lane][0] = make_double2(x[j] + sh[0], y[j] + sh[1]);
+                S[lane][1] = make_double2(z[j] + sh[2], fs[j]);
+                S[lane][2] = make_double2(fs[n + j], fs[2 * n + j]);
+            }
+            __syncthreads();
+            for (int jj = 0; jj < cnt; ++jj) {
+                const double2 a = S[jj][0], b = S[jj][1], c = S[jj][2];
+                residual_pair<ND>(xt - a.x, yt - a.y, zt - b.x, b.y, c.x, c.y, rl2, tw, cP, cQ, poly, u0, u1, u2);
             }
         }
     }
@@ -752,14 +776,28 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
     }
 }
 
+#define DMK_ND_DISPATCH(nd, MACRO) \
+    if (nd <= 14) {                \
+        MACRO(14);                 \
+    } else if (nd <= 18) {         \
+        MACRO(18);                 \
+    } else if (nd <= 21) {         \
+        MACRO(21);                 \
+    } else {                       \
+        MACRO(24);                 \
+    }
+
 void launch_near(const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
                  const double* cbbox, const double* x, const double* y, const double* z, const double* fs, int64_t n,
                  const RadialPoly& poly, double self_coef, double* u, hipStream_t s)
 {
     if (nwork == 0)
         return;
-    hipLaunchKernelGGL(k_near, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, fs, n, poly,
-                       self_coef, u);
+#define L_NEAR(ND)                                                                                               \
+    hipLaunchKernelGGL(k_near<ND>, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, fs, n, poly, \
+                       self_coef, u)
+    DMK_ND_DISPATCH(poly.nd, L_NEAR)
+#undef L_NEAR
 }
 
 __global__ __launch_bounds__(64) void k_near_count(const NearWork* __restrict__ work,
@@ -817,6 +855,7 @@ void launch_near_count(const NearWork* work, int nwork, const NearLeaf* leaves, 
     hipLaunchKernelGGL(k_near_count, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, out);
 }
 
+template <int ND>
 __global__ __launch_bounds__(64) void k_residual_direct(const double* __restrict__ tx, const double* __restrict__ ty,
                                                         const double* __restrict__ tz, int64_t m,
                                                         const double* __restrict__ sx, const double* __restrict__ sy,
@@ -830,8 +869,8 @@ __global__ __launch_bounds__(64) void k_residual_direct(const double* __restrict
     const double cP = 1.0 / (4.0 * kPi * rl), cQ = cP * inv_rl2;
     double u0 = 0, u1 = 0, u2 = 0;
     for (int64_t j = 0; j < ns; ++j)
-        residual_pair(xt - sx[j], yt - sy[j], zt - sz[j], sf[j], sf[ns + j], sf[2 * ns + j], rl2, inv_rl2, cP, cQ,
-                      poly, u0, u1, u2);
+        residual_pair<ND>(xt - sx[j], yt - sy[j], zt - sz[j], sf[j], sf[ns + j], sf[2 * ns + j], rl2, 2.0 * inv_rl2,
+                          cP, cQ, poly, u0, u1, u2);
     if (valid) {
         u[3 * i] = u0;
         u[3 * i + 1] = u1;
@@ -845,8 +884,11 @@ void launch_residual_direct(const double* tx, const double* ty, const double* tz
 {
     if (m == 0)
         return;
-    hipLaunchKernelGGL(k_residual_direct, dim3(nblocks(m, 64)), dim3(64), 0, s, tx, ty, tz, m, sx, sy, sz, sf, ns,
-                       r_lambda, poly, u);
+#define L_RES(ND)                                                                                               \
+    hipLaunchKernelGGL(k_residual_direct<ND>, dim3(nblocks(m, 64)), dim3(64), 0, s, tx, ty, tz, m, sx, sy, sz, sf, \
+                       ns, r_lambda, poly, u)
+    DMK_ND_DISPATCH(poly.nd, L_RES)
+#undef L_RES
 }
 
 // ---- finishing --------------------------------------------------------------------

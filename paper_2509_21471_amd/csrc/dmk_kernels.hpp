@@ -104,9 +104,11 @@ struct NearWork {
     int leaf;
     int chunk;        // chunk index within the leaf
 };
+// P and Q as monomials in t = 2s - 1, both padded with zero leading
+// coefficients to nd terms (nd <= 24)
 struct RadialPoly {
-    int nP, nQ;
-    double P[48], Q[48];
+    int nd;
+    double P[24], Q[24];
 };
 void launch_near(const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
                  const double* cbbox, const double* x, const double* y, const double* z, const double* fs,
