@@ -149,7 +149,8 @@ def main():
         "eval_only_targets_per_s": n / (eval_ms * 1e-3),
         "phases_ms": phases,
         "tree": {k: info[k] for k in ("levels", "n_boxes", "n_nonempty_leaves", "n_senders", "n_receivers",
-                                      "device_bytes", "plan_ms", "p", "n1", "deg_P", "deg_Q")},
+                                      "device_bytes", "plan_ms", "plan_phase_ms", "p", "n1", "deg_P",
+                                      "deg_Q")},
     }
 
     if not args.no_parity:

@@ -94,6 +94,9 @@ typedef struct {
     double center[3], box_len;  /* unit box <-> input coordinates */
     size_t device_bytes;
     double plan_ms;             /* wall time of the plan call */
+    /* wall time of the plan's parts: bounding box, Morton keys + sort + key
+     * download, host octree, host lists, device buffers, uploads + final sync */
+    double plan_phase_ms[6];
 } dmk_plan_info;
 
 /*
@@ -155,8 +158,12 @@ int dmk_stokes_phase_ms(dmk_plan_t plan, double* out);
  */
 int dmk_stokes_near_stats(dmk_plan_t plan, int64_t* listed, int64_t* evaluated, int64_t* in_support);
 
-/* Releases the plan and its device memory (NULL-safe). */
+/* Releases the plan (NULL-safe).  Its device buffers return to the library's
+ * per-process cache and are reused by later plans of similar size. */
 void dmk_stokes_destroy(dmk_plan_t plan);
+
+/* Frees the cached device buffers of destroyed plans (hipFree). */
+void dmk_stokes_release_cached_memory(void);
 
 /* Thread-local description of the last failure of this thread. */
 const char* dmk_last_error(void);
@@ -179,6 +186,17 @@ int dmk_stokes_radial(double tol, const double* rho, int64_t n, double* out);
 /* Window transform and biharmonic mollifier (eq. gammaB_in_phi) at n wave
  * numbers: out[2i] = phihat(k), out[2i+1] = gammahat(k). */
 int dmk_stokes_mollifier(double tol, const double* k, int64_t n, double* out);
+
+/*
+ * Builds the level-restricted octree of host points on the host (same tree
+ * construction as dmk_stokes_plan, keys computed on the CPU) and exports its
+ * leaves like dmk_stokes_tree_leaves.  Arrays hold `cap` leaves; when the tree
+ * has more, returns DMK_ERR_ARG with *n_leaves set so the caller can retry.
+ *   points      host (n,3) float64; leaf_size > 0; periodic 0/1 (points in [0,1)^3)
+ */
+int dmk_stokes_host_tree(const double* points, int64_t n, int leaf_size, int periodic, int64_t cap,
+                         int32_t* leaf_level, int64_t* leaf_coord, int64_t* leaf_count, int64_t* n_leaves,
+                         int64_t* n_near_pairs);
 
 /* ---- device stage entry point ------------------------------------------------ */
 

@@ -22,7 +22,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 SYMBOLS = ["dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_eval", "dmk_stokes_plan_info",
            "dmk_stokes_tree_leaves", "dmk_stokes_destroy", "dmk_last_error", "dmk_stokes_params",
            "dmk_stokes_radial", "dmk_stokes_mollifier", "dmk_stokes_residual_sum", "dmk_stokes_phase_ms",
-           "dmk_stokes_near_stats"]
+           "dmk_stokes_near_stats", "dmk_stokes_release_cached_memory", "dmk_stokes_host_tree"]
 PHASES = ["anterp", "merge", "outgoing", "translate", "incoming", "root", "interp", "leaf_eval", "near",
           "finalize"]
 FLAG_PHASE_TIMING = 1
@@ -48,13 +48,14 @@ class PlanInfo(ctypes.Structure):
                 ("n_nonempty_leaves", ctypes.c_int64), ("near_pairs", ctypes.c_int64),
                 ("n_senders", ctypes.c_int64), ("n_receivers", ctypes.c_int64),
                 ("center", ctypes.c_double * 3), ("box_len", ctypes.c_double),
-                ("device_bytes", ctypes.c_size_t), ("plan_ms", ctypes.c_double)]
+                ("device_bytes", ctypes.c_size_t), ("plan_ms", ctypes.c_double),
+                ("plan_phase_ms", ctypes.c_double * 6)]
 
     def as_dict(self):
         d = {}
         for name, _ in self._fields_:
             v = getattr(self, name)
-            d[name] = list(v) if name == "center" else v
+            d[name] = list(v) if name in ("center", "plan_phase_ms") else v
         return d
 
 
@@ -85,8 +86,11 @@ def lib():
         L.dmk_stokes_residual_sum.argtypes = [vp, i64, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp]
         L.dmk_stokes_phase_ms.argtypes = [vp, dp]
         L.dmk_stokes_near_stats.argtypes = [vp, vp, vp, vp]
+        L.dmk_stokes_host_tree.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, i64, vp, vp, vp, vp, vp]
+        L.dmk_stokes_release_cached_memory.argtypes = []
+        L.dmk_stokes_release_cached_memory.restype = None
         for s in SYMBOLS:
-            if s not in ("dmk_stokes_destroy", "dmk_last_error"):
+            if s not in ("dmk_stokes_destroy", "dmk_last_error", "dmk_stokes_release_cached_memory"):
                 getattr(L, s).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -120,6 +124,23 @@ def mollifier(tol: float, k) -> np.ndarray:
     out = np.zeros((k.size, 2))
     _check(lib().dmk_stokes_mollifier(float(tol), _dp(k), k.size, _dp(out)))
     return out
+
+
+def host_tree(points, leaf_size: int, periodic: bool = False):
+    """Leaves of the octree built on the host: (levels, coords (L,3), counts, near_pairs)."""
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    n = pts.shape[0]
+    nl, npairs = ctypes.c_int64(), ctypes.c_int64()
+    rc = lib().dmk_stokes_host_tree(pts.ctypes.data, n, int(leaf_size), int(bool(periodic)), 0, None, None, None,
+                                    ctypes.byref(nl), ctypes.byref(npairs))
+    cap = nl.value
+    lev = np.zeros(cap, dtype=np.int32)
+    crd = np.zeros((cap, 3), dtype=np.int64)
+    cnt = np.zeros(cap, dtype=np.int64)
+    _check(lib().dmk_stokes_host_tree(pts.ctypes.data, n, int(leaf_size), int(bool(periodic)), cap,
+                                      lev.ctypes.data, crd.ctypes.data, cnt.ctypes.data, ctypes.byref(nl),
+                                      ctypes.byref(npairs)))
+    return lev, crd, cnt, npairs.value
 
 
 # ---- device entry points --------------------------------------------------------

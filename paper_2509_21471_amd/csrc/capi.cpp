@@ -5,6 +5,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -44,9 +46,69 @@ bool is_device_ptr(const void* p)
     return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
+// Process-wide cache of device buffers: destroyed plans hand their buffers
+// back and later plans reuse any cached block of at least the requested size
+// (and at most twice it).  Sizes are rounded to 2 MiB above 1 MiB.
+struct Pool {
+    std::mutex mu;
+    std::multimap<size_t, std::pair<int, void*>> free_blocks;  // size -> (device, ptr)
+    static size_t round(size_t b)
+    {
+        const size_t g = (size_t)2 << 20;
+        return b > ((size_t)1 << 20) ? (b + g - 1) / g * g : (b + 255) / 256 * 256;
+    }
+    void* get(size_t bytes, size_t* got)
+    {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        const size_t want = round(bytes);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            for (auto it = free_blocks.lower_bound(want); it != free_blocks.end() && it->first <= 2 * want; ++it) {
+                if (it->second.first != dev)
+                    continue;
+                void* p = it->second.second;
+                *got = it->first;
+                free_blocks.erase(it);
+                return p;
+            }
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            release_all();
+            if (hipMalloc(&p, want) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+        }
+        *got = want;
+        return p;
+    }
+    void put(void* p, size_t bytes)
+    {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        std::lock_guard<std::mutex> lk(mu);
+        free_blocks.emplace(bytes, std::make_pair(dev, p));
+    }
+    void release_all()
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto& kv : free_blocks)
+            (void)hipFree(kv.second.second);
+        free_blocks.clear();
+    }
+};
+Pool& pool()
+{
+    static Pool* P = new Pool();
+    return *P;
+}
+
 // device allocation registry with an optional cap
 struct DevMem {
-    std::vector<void*> ptrs;
+    std::vector<std::pair<void*, size_t>> ptrs;
     size_t total = 0, cap = 0;
     bool oom = false;
     template <class T>
@@ -59,20 +121,20 @@ struct DevMem {
             oom = true;
             return nullptr;
         }
-        void* p = nullptr;
-        if (hipMalloc(&p, bytes) != hipSuccess) {
-            (void)hipGetLastError();
+        size_t got = 0;
+        void* p = pool().get(bytes, &got);
+        if (!p) {
             oom = true;
             return nullptr;
         }
-        ptrs.push_back(p);
+        ptrs.emplace_back(p, got);
         total += bytes;
         return (T*)p;
     }
     ~DevMem()
     {
-        for (void* p : ptrs)
-            (void)hipFree(p);
+        for (auto& pr : ptrs)
+            pool().put(pr.first, pr.second);
     }
 };
 
@@ -97,14 +159,16 @@ struct dmk_plan_s {
     dmk::Tree tree;
     DevMem mem;
     double plan_ms = 0;
+    double plan_phase[6] = {0, 0, 0, 0, 0, 0};
 
     // points
     int* perm = nullptr;       // sorted position -> caller index
     double *x = nullptr, *y = nullptr, *z = nullptr;
     // tables on device
-    double *cheb_t = nullptr, *cheb_w = nullptr, *up = nullptr, *down = nullptr;
-    dmk::cplx *e_half = nullptr, *e_full = nullptr, *g_half = nullptr, *g_full = nullptr;
-    dmk::cplx *r_e_half = nullptr, *r_e_full = nullptr, *r_g_half = nullptr, *r_g_full = nullptr;
+    double *cheb_t = nullptr, *cheb_w = nullptr;
+    double *merge_mat = nullptr, *interp_mat = nullptr;
+    double *pw_out = nullptr, *pw_in_full = nullptr, *pw_in_half = nullptr;
+    double *r_out = nullptr, *r_in_full = nullptr, *r_in_half = nullptr;
     double *wdiff = nullptr, *wroot = nullptr;
     int root_mh = 0, root_mf = 0;
     dmk::RadialPoly poly;
@@ -173,27 +237,38 @@ int validate_common(int dim, double tol, const dmk_opts* opts)
     return DMK_OK;
 }
 
-// Contracts the leading axis of every (slot, component) tensor.
-void contract(dmk_plan_t P, const void* X, long xs, const int* xmap, int xkind, const void* M, int mc, void* Y,
-              long ys, const int* ymap, int ymode, int K, int R, int N, int nslots)
+// One separable stage over `nslots` (slot, component) tensors.
+void stage(dmk_plan_t P, int mode, int io, const void* X, long xs, const int* xmap, void* Y, long ys,
+           const int* ymap, int accumulate, const double* mat, int Nin, int Nout, int in_off, int out_off, int Kh,
+           int Nh, int R, int nslots, const int* child_fid = nullptr)
 {
-    dmk::ContractArgs a;
+    dmk::StageArgs a;
     a.X = X;
     a.xstride = xs;
     a.xmap = xmap;
-    a.xkind = xkind;
-    a.M = M;
-    a.mcplx = mc;
     a.Y = Y;
     a.ystride = ys;
     a.ymap = ymap;
-    a.ymode = ymode;
-    a.K = K;
+    a.accumulate = accumulate;
+    a.mat = mat;
+    a.Nin = Nin;
+    a.Nout = Nout;
+    a.in_off = in_off;
+    a.out_off = out_off;
+    a.Kh = Kh;
+    a.Nh = Nh;
     a.R = R;
-    a.N = N;
     a.nslots = nslots;
-    dmk::launch_contract(a, P->stream);
+    a.p = P->prm.p;
+    a.child_fid = child_fid;
+    dmk::launch_stage(mode, io, a, P->stream);
 }
+
+// Plane-wave matrices of one grid on the device.
+struct PWDev {
+    int M = 0;
+    double *out = nullptr, *in_full = nullptr, *in_half = nullptr;
+};
 
 // Chebyshev series in t -> monomial coefficients in t (long double), both
 // padded to a kernel instantiation length
@@ -236,6 +311,12 @@ int build_plan(dmk_plan_t P, const double* points)
 {
     using namespace dmk;
     hipStream_t st = P->stream;
+    auto tlast = std::chrono::steady_clock::now();
+    auto lap = [&](int k) {
+        const auto now = std::chrono::steady_clock::now();
+        P->plan_phase[k] += std::chrono::duration<double, std::milli>(now - tlast).count();
+        tlast = now;
+    };
     const int64_t n = P->n;
     // ---- bounding box and finiteness ----
     const int nblk = (int)std::min<int64_t>(1024, (n + 255) / 256);
@@ -275,6 +356,7 @@ int build_plan(dmk_plan_t P, const double* points)
         P->box_len = ext * (1.0 + 1e-9);
     }
     inv_len = 1.0 / P->box_len;
+    lap(0);
     // ---- Morton keys and sort ----
     uint64_t* k0 = P->mem.alloc<uint64_t>(n);
     uint64_t* k1 = P->mem.alloc<uint64_t>(n);
@@ -289,9 +371,11 @@ int build_plan(dmk_plan_t P, const double* points)
     std::vector<uint64_t> keys(n);
     HIPCHK(hipMemcpyAsync(keys.data(), k1, n * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    lap(1);
     // ---- tree ----
     const int ns = P->prm.ns;
     build_tree(keys.data(), n, ns, P->periodic, &P->tree);
+    lap(2);
     const Tree& T = P->tree;
     // ---- sorted points ----
     P->x = P->mem.alloc<double>(n);
@@ -434,6 +518,7 @@ int build_plan(dmk_plan_t P, const double* points)
         nlv.push_back(L);
     }
     P->n_nwork = (int)nwk.size();
+    lap(3);
     P->nleaves = P->mem.alloc<NearLeaf>(nlv.size());
     P->nentries = P->mem.alloc<NearEntryDev>(nent.size());
     P->nwork = P->mem.alloc<NearWork>(nwk.size());
@@ -450,33 +535,23 @@ int build_plan(dmk_plan_t P, const double* points)
     }
     P->cheb_t = P->mem.alloc<double>(p);
     P->cheb_w = P->mem.alloc<double>(p);
-    P->up = P->mem.alloc<double>(TB.up.size());
-    P->down = P->mem.alloc<double>(TB.down.size());
-    auto cup = [&](const std::vector<std::complex<double>>& v) {
-        cplx* d = P->mem.alloc<cplx>(v.size());
+    auto dup = [&](const std::vector<double>& v) {
+        double* d = P->mem.alloc<double>(v.size());
         if (d)
-            (void)hipMemcpy(d, v.data(), v.size() * sizeof(cplx), hipMemcpyHostToDevice);
+            (void)hipMemcpy(d, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);
         return d;
     };
-    P->e_half = cup(TB.e_half);
-    P->e_full = cup(TB.e_full);
-    P->g_half = cup(TB.g_half);
-    P->g_full = cup(TB.g_full);
-    if (P->periodic) {
-        P->r_e_half = cup(TB.p_e_half);
-        P->r_e_full = cup(TB.p_e_full);
-        P->r_g_half = cup(TB.p_g_half);
-        P->r_g_full = cup(TB.p_g_full);
-        P->root_mh = TB.per_m + 1;
-        P->root_mf = 2 * TB.per_m + 1;
-    } else {
-        P->r_e_half = cup(TB.r_e_half);
-        P->r_e_full = cup(TB.r_e_full);
-        P->r_g_half = cup(TB.r_g_half);
-        P->r_g_full = cup(TB.r_g_full);
-        P->root_mh = TB.root_m + 1;
-        P->root_mf = 2 * TB.root_m + 1;
-    }
+    P->merge_mat = dup(TB.merge_mat);
+    P->interp_mat = dup(TB.interp_mat);
+    P->pw_out = dup(TB.pw.out);
+    P->pw_in_full = dup(TB.pw.in_full);
+    P->pw_in_half = dup(TB.pw.in_half);
+    const Tables::PW& rw = P->periodic ? TB.pw_per : TB.pw_root;
+    P->r_out = dup(rw.out);
+    P->r_in_full = dup(rw.in_full);
+    P->r_in_half = dup(rw.in_half);
+    P->root_mh = rw.M + 1;
+    P->root_mf = 2 * rw.M + 1;
     const std::vector<double>& wr = P->periodic ? TB.wper : TB.wroot;
     P->wdiff = P->mem.alloc<double>(TB.wdiff.size());
     P->wroot = P->mem.alloc<double>(wr.size());
@@ -514,6 +589,7 @@ int build_plan(dmk_plan_t P, const double* points)
     P->cst = P->mem.alloc<double>(3);
     if (P->mem.oom)
         return fail(DMK_ERR_OOM, "device allocation failed (or above mem_cap_bytes)");
+    lap(4);
     HIPCHK(upload(P->leaves, hl));
     HIPCHK(upload(P->send_fid, sfid));
     HIPCHK(upload(P->recv_fid, rfid));
@@ -527,8 +603,6 @@ int build_plan(dmk_plan_t P, const double* points)
     HIPCHK(upload(d_clen, clen));
     HIPCHK(upload(P->cheb_t, ct));
     HIPCHK(upload(P->cheb_w, cw));
-    HIPCHK(upload(P->up, TB.up));
-    HIPCHK(upload(P->down, TB.down));
     HIPCHK(upload(P->wdiff, TB.wdiff));
     HIPCHK(upload(P->wroot, wr));
     launch_chunk_bbox(P->x, P->y, P->z, d_cstart, d_clen, (int)cstart.size(), P->cbbox, st);
@@ -537,6 +611,7 @@ int build_plan(dmk_plan_t P, const double* points)
         return fail(DMK_ERR_UNSUPPORTED, "radial fit degree too high");
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipGetLastError());
+    lap(5);
     return DMK_OK;
 }
 
@@ -557,72 +632,76 @@ int eval_one(dmk_plan_t P, const double* f, double* vel, bool record)
     // Step 2a: proxy charges of the leaves
     launch_anterp(p, P->leaves, P->nleaf, P->x, P->y, P->z, P->fs, n, P->cheb_t, P->cheb_w, P->Q, st);
     mark(1);
-    // Step 2b: merge children into parents, finest level first
+    const int h = (p + 1) / 2, M = q - 1;
+    // Step 2b: merge children into parents, finest level first (Q is x-major [a][b][c])
     for (int l = T.max_level - 1; l >= 0; --l) {
         const auto& L = P->lev[l];
         if (!L.nparent)
             continue;
-        launch_merge_stage1(p, L.child_fid, L.nparent, P->Q, P->up, (double*)P->s1, st);
-        contract(P, P->s1, 4 * p3, nullptr, X_REAL, P->up, 0, P->s2, 2 * p3, nullptr, Y_STORE_REAL, 2 * p,
-                 2 * p * p, p, L.nparent);
-        contract(P, P->s2, 2 * p3, nullptr, X_REAL, P->up, 0, P->Q, p3, L.parent_fid, Y_STORE_REAL, 2 * p, p * p, p,
-                 L.nparent);
+        stage(P, ST_SYM_REAL, IO_GATHER8, P->Q, 0, nullptr, P->s1, 4 * p3, nullptr, 0, P->merge_mat, 2 * p, p, 0, 0,
+              p, h, 4 * p * p, L.nparent, L.child_fid);
+        stage(P, ST_SYM_REAL, IO_PLAIN, P->s1, 4 * p3, nullptr, P->s2, 2 * p3, nullptr, 0, P->merge_mat, 2 * p, p, 0,
+              0, p, h, 2 * p * p, L.nparent);
+        stage(P, ST_SYM_REAL, IO_PLAIN, P->s2, 2 * p3, nullptr, P->Q, p3, L.parent_fid, 0, P->merge_mat, 2 * p, p, 0,
+              0, p, h, p * p, L.nparent);
     }
     mark(2);
-    // outgoing plane waves of the senders
+    // outgoing plane waves of the senders: Phi[mx][my][mz], mx >= 0
     const long H = (long)P->H;
-    contract(P, P->Q, p3, P->send_fid, X_REAL, P->e_half, 1, P->s1, p2 * q, nullptr, Y_STORE_CPLX, p, p * p, q,
-             P->nsend);
-    contract(P, P->s1, p2 * q, nullptr, X_CPLX, P->e_full, 1, P->s2, (long)p * q * n1, nullptr, Y_STORE_CPLX, p,
-             p * q, n1, P->nsend);
-    contract(P, P->s2, (long)p * q * n1, nullptr, X_CPLX, P->e_full, 1, P->Phi, H, nullptr, Y_STORE_CPLX, p, q * n1,
-             n1, P->nsend);
+    stage(P, ST_OUT_HALF, IO_PLAIN, P->Q, p3, P->send_fid, P->s1, p2 * q, nullptr, 0, P->pw_out, p, q, 0, 0, h, M + 1,
+          p * p, P->nsend);
+    stage(P, ST_OUT_FULL, IO_PLAIN, P->s1, p2 * q, nullptr, P->s2, (long)p * q * n1, nullptr, 0, P->pw_out, p, n1, 0,
+          M, h, M + 1, p * q, P->nsend);
+    stage(P, ST_OUT_FULL, IO_PLAIN, P->s2, (long)p * q * n1, nullptr, P->Phi, H, nullptr, 0, P->pw_out, p, n1, 0, M,
+          h, M + 1, q * n1, P->nsend);
     mark(3);
-    // Step 3b: translation with the difference-kernel symbol
+    // Step 3b: translation with the difference-kernel symbol -> Psi[mz][my][mx]
     launch_translate(q, n1, P->recv, P->nrecv, P->e_src, P->e_off, P->Phi, P->wdiff, P->Psi, st);
     mark(4);
-    // incoming plane waves -> proxy potentials
+    // incoming plane waves -> proxy potentials, z-major V[c][b][a]
     launch_zero(P->V, (size_t)P->nf * 3 * p3, st);
-    contract(P, P->Psi, H, nullptr, X_CPLX, P->g_half, 1, P->s1, (long)n1 * n1 * p, nullptr, Y_STORE_CPLX, q,
-             n1 * n1, p, P->nrecv);
-    contract(P, P->s1, (long)n1 * n1 * p, nullptr, X_CPLX, P->g_full, 1, P->s2, (long)n1 * p * p, nullptr,
-             Y_STORE_CPLX, n1, n1 * p, p, P->nrecv);
-    contract(P, P->s2, (long)n1 * p * p, nullptr, X_CPLX, P->g_full, 1, P->V, p3, P->recv_fid, Y_ADD_REALPART, n1,
-             p * p, p, P->nrecv);
+    stage(P, ST_IN_FULL, IO_PLAIN, P->Psi, H, nullptr, P->s1, (long)n1 * q * p, nullptr, 0, P->pw_in_full, n1, p, M,
+          0, M + 1, h, n1 * q, P->nrecv);
+    stage(P, ST_IN_FULL, IO_PLAIN, P->s1, (long)n1 * q * p, nullptr, P->s2, (long)q * p * p, nullptr, 0,
+          P->pw_in_full, n1, p, M, 0, M + 1, h, q * p, P->nrecv);
+    stage(P, ST_IN_HALF_REAL, IO_PLAIN, P->s2, (long)q * p * p, nullptr, P->V, p3, P->recv_fid, 1, P->pw_in_half, q,
+          p, 0, 0, q, h, p * p, P->nrecv);
     mark(5);
     // Step 3a: root convolution with the (truncated or periodic) mollified kernel
     {
-        const int mh = P->root_mh, mf = P->root_mf;
+        const int mh = P->root_mh, mf = P->root_mf, RM = mh - 1;
         const long Hr = (long)P->Hroot;
         const int rf = P->root_fid;
         const double* Qr = P->Q + (size_t)rf * 3 * p3;
         double* Vr = P->V + (size_t)rf * 3 * p3;
-        contract(P, Qr, p3, nullptr, X_REAL, P->r_e_half, 1, P->s1, p2 * mh, nullptr, Y_STORE_CPLX, p, p * p, mh, 1);
-        contract(P, P->s1, p2 * mh, nullptr, X_CPLX, P->r_e_full, 1, P->s2, (long)p * mh * mf, nullptr, Y_STORE_CPLX,
-                 p, p * mh, mf, 1);
-        contract(P, P->s2, (long)p * mh * mf, nullptr, X_CPLX, P->r_e_full, 1, P->phi_root, Hr, nullptr,
-                 Y_STORE_CPLX, p, mh * mf, mf, 1);
+        stage(P, ST_OUT_HALF, IO_PLAIN, Qr, p3, nullptr, P->s1, p2 * mh, nullptr, 0, P->r_out, p, mh, 0, 0, h, mh,
+              p * p, 1);
+        stage(P, ST_OUT_FULL, IO_PLAIN, P->s1, p2 * mh, nullptr, P->s2, (long)p * mh * mf, nullptr, 0, P->r_out, p, mf,
+              0, RM, h, mh, p * mh, 1);
+        stage(P, ST_OUT_FULL, IO_PLAIN, P->s2, (long)p * mh * mf, nullptr, P->phi_root, Hr, nullptr, 0, P->r_out, p,
+              mf, 0, RM, h, mh, mh * mf, 1);
         launch_root_symbol(mh, mf, P->phi_root, P->wroot, P->psi_root, st);
-        contract(P, P->psi_root, Hr, nullptr, X_CPLX, P->r_g_half, 1, P->s1, (long)mf * mf * p, nullptr,
-                 Y_STORE_CPLX, mh, mf * mf, p, 1);
-        contract(P, P->s1, (long)mf * mf * p, nullptr, X_CPLX, P->r_g_full, 1, P->s2, (long)mf * p * p, nullptr,
-                 Y_STORE_CPLX, mf, mf * p, p, 1);
-        contract(P, P->s2, (long)mf * p * p, nullptr, X_CPLX, P->r_g_full, 1, Vr, p3, nullptr, Y_ADD_REALPART, mf,
-                 p * p, p, 1);
+        stage(P, ST_IN_FULL, IO_PLAIN, P->psi_root, Hr, nullptr, P->s1, (long)mf * mh * p, nullptr, 0, P->r_in_full,
+              mf, p, RM, 0, mh, h, mf * mh, 1);
+        stage(P, ST_IN_FULL, IO_PLAIN, P->s1, (long)mf * mh * p, nullptr, P->s2, (long)mh * p * p, nullptr, 0,
+              P->r_in_full, mf, p, RM, 0, mh, h, mh * p, 1);
+        stage(P, ST_IN_HALF_REAL, IO_PLAIN, P->s2, (long)mh * p * p, nullptr, Vr, p3, nullptr, 1, P->r_in_half, mh, p,
+              0, 0, mh, h, p * p, 1);
         if (!P->periodic)
             launch_sum_root(Qr, (int)p3, 1.0 / (4.0 * kPi * (1.0 + std::sqrt(3.0))), P->cst, st);
     }
     mark(6);
-    // downward interpolation, coarsest level first
+    // downward interpolation, coarsest level first (V is z-major, all axes alike)
     for (int l = 0; l < T.max_level; ++l) {
         const auto& L = P->lev[l];
         if (!L.nparent)
             continue;
-        contract(P, P->V, p3, L.parent_fid, X_REAL, P->down, 0, P->s1, 2 * p3, nullptr, Y_STORE_REAL, p, p * p,
-                 2 * p, L.nparent);
-        contract(P, P->s1, 2 * p3, nullptr, X_REAL, P->down, 0, P->s2, 4 * p3, nullptr, Y_STORE_REAL, p, 2 * p * p,
-                 2 * p, L.nparent);
-        launch_interp_stage3(p, L.child_fid, L.nparent, (const double*)P->s2, P->down, P->V, st);
+        stage(P, ST_SYM_REAL, IO_PLAIN, P->V, p3, L.parent_fid, P->s1, 2 * p3, nullptr, 0, P->interp_mat, p, 2 * p, 0,
+              0, h, p, p * p, L.nparent);
+        stage(P, ST_SYM_REAL, IO_PLAIN, P->s1, 2 * p3, nullptr, P->s2, 4 * p3, nullptr, 0, P->interp_mat, p, 2 * p, 0,
+              0, h, p, 2 * p * p, L.nparent);
+        stage(P, ST_SYM_REAL, IO_SCATTER8, P->s2, 4 * p3, nullptr, P->V, 0, nullptr, 1, P->interp_mat, p, 2 * p, 0, 0,
+              h, p, 4 * p * p, L.nparent, L.child_fid);
     }
     mark(7);
     // far field at the points, then the near field (Step 4) and self term
@@ -808,6 +887,8 @@ int dmk_stokes_plan_info(dmk_plan_t plan, dmk_plan_info* info)
     info->box_len = P.box_len;
     info->device_bytes = P.mem.total;
     info->plan_ms = P.plan_ms;
+    for (int k = 0; k < 6; ++k)
+        info->plan_phase_ms[k] = P.plan_phase[k];
     return DMK_OK;
 }
 
@@ -881,12 +962,88 @@ int dmk_stokes_near_stats(dmk_plan_t plan, int64_t* listed, int64_t* evaluated, 
     return DMK_OK;
 }
 
+void dmk_stokes_release_cached_memory(void)
+{
+    pool().release_all();
+}
+
 void dmk_stokes_destroy(dmk_plan_t plan)
 {
     if (!plan)
         return;
     (void)hipStreamSynchronize(plan->stream);
     delete plan;
+}
+
+int dmk_stokes_host_tree(const double* points, int64_t n, int leaf_size, int periodic, int64_t cap,
+                         int32_t* leaf_level, int64_t* leaf_coord, int64_t* leaf_count, int64_t* n_leaves,
+                         int64_t* n_near_pairs)
+{
+    if (!points || n < 1 || leaf_size < 1 || !n_leaves || (periodic != 0 && periodic != 1))
+        return fail(DMK_ERR_ARG, "bad arguments");
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            const double v = points[3 * i + d];
+            if (!std::isfinite(v))
+                return fail(DMK_ERR_NONFINITE, "points contain NaN or Inf");
+            lo[d] = std::min(lo[d], v);
+            hi[d] = std::max(hi[d], v);
+        }
+    double c[3], len = 1.0;
+    if (periodic) {
+        for (int d = 0; d < 3; ++d)
+            if (lo[d] < 0.0 || hi[d] >= 1.0)
+                return fail(DMK_ERR_DOMAIN, "periodic points must lie in [0,1)^3");
+        c[0] = c[1] = c[2] = 0.5;
+    } else {
+        double ext = 0;
+        for (int d = 0; d < 3; ++d) {
+            c[d] = 0.5 * (lo[d] + hi[d]);
+            ext = std::max(ext, hi[d] - lo[d]);
+        }
+        len = (ext > 0 ? ext : 1.0) * (1.0 + 1e-9);
+    }
+    std::vector<uint64_t> keys(n);
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t q[3];
+        for (int d = 0; d < 3; ++d) {
+            double g = std::floor(((points[3 * i + d] - c[d]) / len + 0.5) * 524288.0);
+            g = std::min(std::max(g, 0.0), 524287.0);
+            q[d] = (uint64_t)g;
+        }
+        uint64_t k = 0;
+        for (int bt = 18; bt >= 0; --bt)
+            k = (k << 3) | (((q[0] >> bt) & 1) << 2) | (((q[1] >> bt) & 1) << 1) | ((q[2] >> bt) & 1);
+        keys[i] = k;
+    }
+    std::sort(keys.begin(), keys.end());
+    dmk::Tree T;
+    dmk::build_tree(keys.data(), n, leaf_size, periodic != 0, &T);
+    int64_t L = 0;
+    for (const dmk::Box& B : T.boxes)
+        L += B.leaf ? 1 : 0;
+    *n_leaves = L;
+    if (n_near_pairs)
+        *n_near_pairs = T.n_near_pairs;
+    if (L > cap)
+        return fail(DMK_ERR_ARG, "cap smaller than the number of leaves");
+    int64_t li = 0;
+    for (const dmk::Box& B : T.boxes) {
+        if (!B.leaf)
+            continue;
+        if (leaf_level)
+            leaf_level[li] = B.level;
+        if (leaf_coord) {
+            leaf_coord[3 * li] = B.ix;
+            leaf_coord[3 * li + 1] = B.iy;
+            leaf_coord[3 * li + 2] = B.iz;
+        }
+        if (leaf_count)
+            leaf_count[li] = B.end - B.start;
+        ++li;
+    }
+    return DMK_OK;
 }
 
 int dmk_stokes_residual_sum(const double* targets, int64_t m, const double* sources, const double* forces,

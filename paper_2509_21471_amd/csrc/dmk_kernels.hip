@@ -3,6 +3,8 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+
 namespace dmk {
 
 namespace {
@@ -283,9 +285,10 @@ __global__ __launch_bounds__(128) void k_leaf_eval(const LeafDesc* __restrict__ 
     for (int64_t ts = L.start; ts < L.end; ts += 128) {
         const int64_t i = ts + tid;
         const bool valid = i < L.end;
-        const double xi = valid ? (x[i] - L.cx) * sc : 0.0;
+        // V is stored z-major (V[c][b][a]); the outer sum runs over z
+        const double xi = valid ? (z[i] - L.cz) * sc : 0.0;
         const double eta = valid ? (y[i] - L.cy) * sc : 0.0;
-        const double zeta = valid ? (z[i] - L.cz) * sc : 0.0;
+        const double zeta = valid ? (x[i] - L.cx) * sc : 0.0;
         double Lx[P], Lz[P], Ly[P];
         lagrange<P>(xi, ct, cw, Lx);
         lagrange<P>(eta, ct, cw, Ly);
@@ -361,227 +364,230 @@ void launch_leaf_eval(int p, const LeafDesc* leaves, int nleaf, const double* x,
 #undef L_EVAL
 }
 
-// ---- generic rotating contraction -------------------------------------------
-struct cacc {
-    double re, im;
+// ---- separable tensor stages ---------------------------------------------------
+template <int MODE>
+struct StageTraits {
+    static constexpr bool xc = (MODE == ST_OUT_FULL || MODE == ST_IN_FULL || MODE == ST_IN_HALF_REAL);
+    static constexpr bool yc = (MODE == ST_OUT_HALF || MODE == ST_OUT_FULL || MODE == ST_IN_FULL);
+    static constexpr bool fold = (MODE != ST_IN_HALF_REAL);
 };
 
-template <int XC, int MC, int NJ>
-__global__ __launch_bounds__(256) void k_contract(ContractArgs a)
+// 256 threads per 64-row tile: the input slab X[0..Nin)[r0..r0+64) is staged
+// in LDS with all loads in flight, thread (row, g) accumulates the half
+// outputs g, g+4, ... from it, and the output tile Y[r0..r0+64)[0..Nout) is
+// staged in LDS again and written as one contiguous block (or scatter-added to
+// the children's grids, one contiguous run of p per row and child).
+template <int MODE, int IO, int NI>
+__global__ __launch_bounds__(256) void k_stage(StageArgs a)
 {
-    const int lane = threadIdx.x & 63, ng = threadIdx.x >> 6;
+    using Tr = StageTraits<MODE>;
+    constexpr int XE = Tr::xc ? 2 : 1;
+    constexpr int YE = Tr::yc ? 2 : 1;
+    extern __shared__ double smem[];
+    const int nm = a.Nh * a.Kh;
+    double2* smat = (double2*)smem;
+    double* tile = smem + 2 * nm;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < nm; k += 256)
+        smat[k] = make_double2(a.mat[2 * k], a.mat[2 * k + 1]);
     const int slot = blockIdx.y / 3, comp = blockIdx.y % 3;
-    const int xs = a.xmap ? a.xmap[slot] : slot;
-    const int ys = a.ymap ? a.ymap[slot] : slot;
-    const int r = blockIdx.x * 64 + lane;
-    const bool valid = r < a.R;
-    const int K = a.K, R = a.R, N = a.N;
-    cacc acc[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j)
-        acc[j].re = acc[j].im = 0.0;
-    const size_t xoff = ((size_t)xs * 3 + comp) * a.xstride;
-    for (int k = 0; k < K; ++k) {
-        double xr = 0, xi = 0;
-        if (valid) {
-            if (XC) {
-                const cplx v = ((const cplx*)a.X)[xoff + (size_t)k * R + r];
-                xr = v.re;
-                xi = v.im;
-            } else {
-                xr = ((const double*)a.X)[xoff + (size_t)k * R + r];
+    const int R = a.R, Nin = a.Nin, Nout = a.Nout, p = a.p;
+    const int r0 = blockIdx.x * 64;
+    const int nrow = min(64, R - r0);
+    const size_t p3 = (size_t)p * p * p;
+    // ---- input slab ----
+    {
+        const size_t xoff = ((size_t)(a.xmap ? a.xmap[slot] : slot) * 3 + comp) * a.xstride;
+        for (int e = tid; e < Nin * 64; e += 256) {
+            const int k = e >> 6, rr = e & 63;
+            const int r = r0 + rr;
+            double v0 = 0.0, v1 = 0.0;
+            if (rr < nrow) {
+                if (IO == IO_GATHER8) {
+                    const int B = r / (2 * p), C = r % (2 * p);
+                    const int f = a.child_fid[slot * 8 + 4 * (k / p) + 2 * (B / p) + (C / p)];
+                    if (f >= 0)
+                        v0 = ((const double*)a.X)[((size_t)f * 3 + comp) * p3 + ((size_t)(k % p) * p + (B % p)) * p +
+                                                  (C % p)];
+                } else if (XE == 2) {
+                    const double2 v = ((const double2*)a.X)[xoff + (size_t)k * R + r];
+                    v0 = v.x;
+                    v1 = v.y;
+                } else {
+                    v0 = ((const double*)a.X)[xoff + (size_t)k * R + r];
+                }
             }
+            if (XE == 2)
+                ((double2*)tile)[e] = make_double2(v0, v1);
+            else
+                tile[e] = v0;
+        }
+    }
+    __syncthreads();
+    const int lane = tid & 63, g = tid >> 6;
+    double Ur[NI], Ui[NI], Wr[NI], Wi[NI];
+#pragma unroll
+    for (int t = 0; t < NI; ++t)
+        Ur[t] = Ui[t] = Wr[t] = Wi[t] = 0.0;
+    for (int j = 0; j < a.Kh; ++j) {
+        const int k1 = j + a.in_off;
+        const int k2 = Nin - 1 - k1;
+        double x1r, x1i = 0, x2r = 0, x2i = 0;
+        if (XE == 2) {
+            const double2 v1 = ((const double2*)tile)[k1 * 64 + lane];
+            x1r = v1.x;
+            x1i = v1.y;
+            if (Tr::fold && k2 != k1) {
+                const double2 v2 = ((const double2*)tile)[k2 * 64 + lane];
+                x2r = v2.x;
+                x2i = v2.y;
+            }
+        } else {
+            x1r = tile[k1 * 64 + lane];
+            if (k2 != k1)
+                x2r = tile[k2 * 64 + lane];
+        }
+        double er, ei, orr, oi;
+        if (Tr::fold) {
+            er = x1r + x2r;
+            ei = x1i + x2i;
+            orr = x1r - x2r;
+            oi = x1i - x2i;
+        } else {  // half modes: even part <- real, odd part <- imaginary
+            er = x1r;
+            ei = 0;
+            orr = x1i;
+            oi = 0;
         }
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const int nn = ng + 4 * j;
-            if (nn < N) {
-                if (MC) {
-                    const cplx m = ((const cplx*)a.M)[(size_t)nn * K + k];
-                    acc[j].re = fma(xr, m.re, acc[j].re);
-                    acc[j].im = fma(xr, m.im, acc[j].im);
-                    if (XC) {
-                        acc[j].re = fma(-xi, m.im, acc[j].re);
-                        acc[j].im = fma(xi, m.re, acc[j].im);
-                    }
-                } else {
-                    const double m = ((const double*)a.M)[(size_t)nn * K + k];
-                    acc[j].re = fma(xr, m, acc[j].re);
-                    if (XC)
-                        acc[j].im = fma(xi, m, acc[j].im);
+        for (int t = 0; t < NI; ++t) {
+            const int i = g + 4 * t;
+            if (i < a.Nh) {
+                const double2 m = smat[i * a.Kh + j];
+                Ur[t] = fma(m.x, er, Ur[t]);
+                Wr[t] = fma(m.y, orr, Wr[t]);
+                if (Tr::xc && Tr::fold) {
+                    Ui[t] = fma(m.x, ei, Ui[t]);
+                    Wi[t] = fma(m.y, oi, Wi[t]);
                 }
             }
         }
     }
-    if (!valid)
-        return;
-    const size_t yoff = ((size_t)ys * 3 + comp) * a.ystride + (size_t)r * N;
+    __syncthreads();  // input slab consumed; the tile now holds outputs [row][n]
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const int nn = ng + 4 * j;
-        if (nn < N) {
-            switch (a.ymode) {
-            case Y_STORE_CPLX:
-                ((cplx*)a.Y)[yoff + nn] = cplx{acc[j].re, acc[j].im};
-                break;
-            case Y_STORE_REAL:
-                ((double*)a.Y)[yoff + nn] = acc[j].re;
-                break;
-            case Y_ADD_REALPART:
-            case Y_ADD_REAL:
-                ((double*)a.Y)[yoff + nn] += acc[j].re;
-                break;
-            }
+    for (int t = 0; t < NI; ++t) {
+        const int i = g + 4 * t;
+        if (i >= a.Nh)
+            continue;
+        const int n1 = i + a.out_off;
+        const int n2 = Nout - 1 - n1;
+        double y1r, y1i = 0, y2r, y2i = 0;
+        bool two = (n2 != n1);
+        if (MODE == ST_SYM_REAL) {
+            y1r = Ur[t] + Wr[t];
+            y2r = Ur[t] - Wr[t];
+        } else if (MODE == ST_OUT_HALF) {
+            y1r = Ur[t];
+            y1i = -Wr[t];
+            y2r = 0;
+            two = false;
+        } else if (MODE == ST_OUT_FULL) {
+            y1r = Ur[t] + Wi[t];  // U - iW
+            y1i = Ui[t] - Wr[t];
+            y2r = Ur[t] - Wi[t];  // U + iW
+            y2i = Ui[t] + Wr[t];
+        } else if (MODE == ST_IN_FULL) {
+            y1r = Ur[t] - Wi[t];  // U + iW
+            y1i = Ui[t] + Wr[t];
+            y2r = Ur[t] + Wi[t];  // U - iW
+            y2i = Ui[t] - Wr[t];
+        } else {                  // ST_IN_HALF_REAL
+            y1r = Ur[t] - Wr[t];
+            y2r = Ur[t] + Wr[t];
+        }
+        if (YE == 2) {
+            ((double2*)tile)[lane * Nout + n1] = make_double2(y1r, y1i);
+            if (two)
+                ((double2*)tile)[lane * Nout + n2] = make_double2(y2r, y2i);
+        } else {
+            tile[lane * Nout + n1] = y1r;
+            if (two)
+                tile[lane * Nout + n2] = y2r;
         }
     }
-}
-
-template <int XC, int MC>
-static void contract_nj(const ContractArgs& a, hipStream_t s)
-{
-    const int nj = (a.N + 3) / 4;
-    dim3 grid(nblocks(a.R, 64), a.nslots * 3);
-    if (nj <= 4)
-        hipLaunchKernelGGL((k_contract<XC, MC, 4>), grid, dim3(256), 0, s, a);
-    else if (nj <= 8)
-        hipLaunchKernelGGL((k_contract<XC, MC, 8>), grid, dim3(256), 0, s, a);
-    else if (nj <= 12)
-        hipLaunchKernelGGL((k_contract<XC, MC, 12>), grid, dim3(256), 0, s, a);
-    else if (nj <= 16)
-        hipLaunchKernelGGL((k_contract<XC, MC, 16>), grid, dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_contract<XC, MC, 24>), grid, dim3(256), 0, s, a);
-}
-
-void launch_contract(const ContractArgs& a, hipStream_t s)
-{
-    if (a.nslots == 0)
-        return;
-    if (a.xkind == X_CPLX) {
-        if (a.mcplx)
-            contract_nj<1, 1>(a, s);
-        else
-            contract_nj<1, 0>(a, s);
+    __syncthreads();
+    if (IO == IO_SCATTER8) {
+        // rows r = (C, B) of the child grid, output axis A; child (A/p, B/p, C/p)
+        double* Yd = (double*)a.Y;
+        for (int e = tid; e < nrow * Nout; e += 256) {
+            const int rr = e / Nout, A = e % Nout;
+            const int r = r0 + rr;
+            const int C = r / (2 * p), B = r % (2 * p);
+            const int f = a.child_fid[slot * 8 + 4 * (A / p) + 2 * (B / p) + (C / p)];
+            if (f >= 0)
+                Yd[((size_t)f * 3 + comp) * p3 + ((size_t)(C % p) * p + (B % p)) * p + (A % p)] += tile[e];
+        }
     } else {
-        if (a.mcplx)
-            contract_nj<0, 1>(a, s);
+        const size_t yoff = ((size_t)(a.ymap ? a.ymap[slot] : slot) * 3 + comp) * a.ystride * YE +
+                            (size_t)r0 * Nout * YE;
+        double* Yd = (double*)a.Y + yoff;
+        const int cnt = nrow * Nout * YE;
+        if (a.accumulate) {
+            for (int e = tid; e < cnt; e += 256)
+                Yd[e] += tile[e];
+        } else {
+            for (int e = tid; e < cnt; e += 256)
+                Yd[e] = tile[e];
+        }
+    }
+}
+
+template <int MODE, int IO, int NI>
+static void stage_launch(dim3 grid, size_t shm, const StageArgs& a, hipStream_t s)
+{
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void*)k_stage<MODE, IO, NI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_stage<MODE, IO, NI>), grid, dim3(256), shm, s, a);
+}
+
+template <int MODE, int IO>
+static void stage_ni(const StageArgs& a, hipStream_t s)
+{
+    using Tr = StageTraits<MODE>;
+    dim3 grid(nblocks(a.R, 64), a.nslots * 3);
+    const size_t tile = std::max((size_t)a.Nin * 64 * (Tr::xc ? 2 : 1), (size_t)a.Nout * 64 * (Tr::yc ? 2 : 1));
+    const size_t shm = (size_t)a.Nh * a.Kh * sizeof(double2) + tile * sizeof(double);
+    const int ni = (a.Nh + 3) / 4;
+    if (ni <= 4)
+        stage_launch<MODE, IO, 4>(grid, shm, a, s);
+    else if (ni <= 8)
+        stage_launch<MODE, IO, 8>(grid, shm, a, s);
+    else
+        stage_launch<MODE, IO, 12>(grid, shm, a, s);
+}
+
+void launch_stage(int mode, int io, const StageArgs& a, hipStream_t s)
+{
+    if (a.nslots == 0 || a.R == 0)
+        return;
+    switch (mode) {
+    case ST_SYM_REAL:
+        if (io == IO_GATHER8)
+            stage_ni<ST_SYM_REAL, IO_GATHER8>(a, s);
+        else if (io == IO_SCATTER8)
+            stage_ni<ST_SYM_REAL, IO_SCATTER8>(a, s);
         else
-            contract_nj<0, 0>(a, s);
+            stage_ni<ST_SYM_REAL, IO_PLAIN>(a, s);
+        break;
+    case ST_OUT_HALF: stage_ni<ST_OUT_HALF, IO_PLAIN>(a, s); break;
+    case ST_OUT_FULL: stage_ni<ST_OUT_FULL, IO_PLAIN>(a, s); break;
+    case ST_IN_FULL: stage_ni<ST_IN_FULL, IO_PLAIN>(a, s); break;
+    default: stage_ni<ST_IN_HALF_REAL, IO_PLAIN>(a, s); break;
     }
-}
-
-// merge first stage: Y[B][C][a] = sum_A up[a][A] X(A,B,C), X the (2p)^3 grid of
-// the 8 children's proxy charges (absent children contribute zero)
-template <int NJ>
-__global__ __launch_bounds__(256) void k_merge1(int p, const int* __restrict__ child_fid, const double* __restrict__ Q,
-                                                const double* __restrict__ up, double* __restrict__ Y)
-{
-    const int lane = threadIdx.x & 63, ng = threadIdx.x >> 6;
-    const int par = blockIdx.y / 3, comp = blockIdx.y % 3;
-    const int p2 = 2 * p, R = p2 * p2;
-    const int r = blockIdx.x * 64 + lane;
-    const bool valid = r < R;
-    const int B = valid ? r / p2 : 0, C = valid ? r % p2 : 0;
-    const int by = B / p, bz = C / p, b = B % p, c = C % p;
-    const size_t p3 = (size_t)p * p * p;
-    double acc[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j)
-        acc[j] = 0;
-    for (int A = 0; A < p2; ++A) {
-        const int bx = A / p, a = A % p;
-        const int cf = child_fid[par * 8 + 4 * bx + 2 * by + bz];
-        const double xv = (valid && cf >= 0) ? Q[((size_t)cf * 3 + comp) * p3 + ((size_t)a * p + b) * p + c] : 0.0;
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const int nn = ng + 4 * j;
-            if (nn < p)
-                acc[j] = fma(xv, up[(size_t)nn * p2 + A], acc[j]);
-        }
-    }
-    if (!valid)
-        return;
-    double* y = Y + ((size_t)par * 3 + comp) * (size_t)R * p + (size_t)r * p;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const int nn = ng + 4 * j;
-        if (nn < p)
-            y[nn] = acc[j];
-    }
-}
-
-void launch_merge_stage1(int p, const int* child_fid, int nparent, const double* Q, const double* up, double* Y,
-                         hipStream_t s)
-{
-    if (nparent == 0)
-        return;
-    dim3 grid(nblocks(4 * p * p, 64), nparent * 3);
-    const int nj = (p + 3) / 4;
-    if (nj <= 4)
-        hipLaunchKernelGGL(k_merge1<4>, grid, dim3(256), 0, s, p, child_fid, Q, up, Y);
-    else if (nj <= 8)
-        hipLaunchKernelGGL(k_merge1<8>, grid, dim3(256), 0, s, p, child_fid, Q, up, Y);
-    else
-        hipLaunchKernelGGL(k_merge1<12>, grid, dim3(256), 0, s, p, child_fid, Q, up, Y);
-}
-
-// interpolation last stage: out[A][B][C] = sum_c down[C][c] X[c][A][B], added
-// into child (A/p, B/p, C/p) at (A%p, B%p, C%p)
-template <int NJ>
-__global__ __launch_bounds__(256) void k_interp3(int p, const int* __restrict__ child_fid, const double* __restrict__ X,
-                                                 const double* __restrict__ down, double* __restrict__ V)
-{
-    const int lane = threadIdx.x & 63, ng = threadIdx.x >> 6;
-    const int par = blockIdx.y / 3, comp = blockIdx.y % 3;
-    const int p2 = 2 * p, R = p2 * p2;
-    const int r = blockIdx.x * 64 + lane;
-    const bool valid = r < R;
-    const int A = valid ? r / p2 : 0, B = valid ? r % p2 : 0;
-    const size_t p3 = (size_t)p * p * p;
-    const double* x = X + ((size_t)par * 3 + comp) * (size_t)p * R;
-    double acc[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j)
-        acc[j] = 0;
-    for (int c = 0; c < p; ++c) {
-        const double xv = valid ? x[(size_t)c * R + r] : 0.0;
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const int nn = ng + 4 * j;
-            if (nn < p2)
-                acc[j] = fma(xv, down[(size_t)nn * p + c], acc[j]);
-        }
-    }
-    if (!valid)
-        return;
-    const int bx = A / p, a = A % p, by = B / p, b = B % p;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const int C = ng + 4 * j;
-        if (C < p2) {
-            const int bz = C / p, c = C % p;
-            const int cf = child_fid[par * 8 + 4 * bx + 2 * by + bz];
-            if (cf >= 0)
-                V[((size_t)cf * 3 + comp) * p3 + ((size_t)a * p + b) * p + c] += acc[j];
-        }
-    }
-}
-
-void launch_interp_stage3(int p, const int* child_fid, int nparent, const double* X, const double* down, double* V,
-                          hipStream_t s)
-{
-    if (nparent == 0)
-        return;
-    dim3 grid(nblocks(4 * p * p, 64), nparent * 3);
-    const int nj = (2 * p + 3) / 4;
-    if (nj <= 8)
-        hipLaunchKernelGGL(k_interp3<8>, grid, dim3(256), 0, s, p, child_fid, X, down, V);
-    else if (nj <= 12)
-        hipLaunchKernelGGL(k_interp3<12>, grid, dim3(256), 0, s, p, child_fid, X, down, V);
-    else if (nj <= 17)
-        hipLaunchKernelGGL(k_interp3<17>, grid, dim3(256), 0, s, p, child_fid, X, down, V);
-    else
-        hipLaunchKernelGGL(k_interp3<22>, grid, dim3(256), 0, s, p, child_fid, X, down, V);
 }
 
 // ---- translation --------------------------------------------------------------
@@ -623,9 +629,11 @@ __global__ __launch_bounds__(256) void k_translate(int q, int n1, const RecvDesc
     const double dr = (m1 * F[0][0] + m2 * F[1][0] + m3 * F[2][0]) * inv;
     const double di = (m1 * F[0][1] + m2 * F[1][1] + m3 * F[2][1]) * inv;
     const int mv[3] = {m1, m2, m3};
+    // incoming side is stored z-major: Psi[mz][my][mx]
+    const size_t mo = ((size_t)(m3 + q - 1) * n1 + (m2 + q - 1)) * q + m1;
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-        Psi[((size_t)rd.slot * 3 + j) * H + mi] = cplx{w * (F[j][0] - mv[j] * dr), w * (F[j][1] - mv[j] * di)};
+        Psi[((size_t)rd.slot * 3 + j) * H + mo] = cplx{w * (F[j][0] - mv[j] * dr), w * (F[j][1] - mv[j] * di)};
 }
 
 void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int* e_src, const int8_t* e_off,
@@ -658,8 +666,9 @@ __global__ __launch_bounds__(256) void k_root_symbol(int mh, int mf, const cplx*
     const double dr = (m1 * F[0].re + m2 * F[1].re + m3 * F[2].re) * inv;
     const double di = (m1 * F[0].im + m2 * F[1].im + m3 * F[2].im) * inv;
     const int mv[3] = {m1, m2, m3};
+    const size_t mo = ((size_t)(m3 + M) * mf + (m2 + M)) * mh + m1;
     for (int j = 0; j < 3; ++j)
-        Psi[(size_t)j * H + mi] = cplx{ww * (F[j].re - mv[j] * dr), ww * (F[j].im - mv[j] * di)};
+        Psi[(size_t)j * H + mo] = cplx{ww * (F[j].re - mv[j] * dr), ww * (F[j].im - mv[j] * di)};
 }
 
 void launch_root_symbol(int mh, int mf, const cplx* Phi, const double* w, cplx* Psi, hipStream_t s)

@@ -43,38 +43,44 @@ struct LeafDesc {
 void launch_anterp(int p, const LeafDesc* leaves, int nleaf, const double* x, const double* y, const double* z,
                    const double* fs, int64_t n, const double* cheb_t, const double* cheb_w, double* Q,
                    hipStream_t s);
-// far-field value at the leaf's points (final interpolation): u[j][i] = sum V L L L
+// far-field value at the leaf's points (final interpolation): u[j][i] = sum V L L L,
+// V stored z-major: V[fid][j][c][b][a]
 void launch_leaf_eval(int p, const LeafDesc* leaves, int nleaf, const double* x, const double* y,
                       const double* z, int64_t n, const double* cheb_t, const double* cheb_w, const double* V,
                       double* u, hipStream_t s);
 
-// generic rotating contraction  Y[b][r][n] (+)= sum_k X[b][k][r] * M[n][k]
-// batch b = slot * 3 + component; slot -> array position through optional maps
-enum XKind { X_REAL = 0, X_CPLX = 1 };
-enum YMode { Y_STORE_CPLX = 0, Y_STORE_REAL = 1, Y_ADD_REALPART = 2, Y_ADD_REAL = 3 };
-struct ContractArgs {
+// ---- separable tensor stages ------------------------------------------------
+// Every far-field tensor stage contracts the leading axis of a per-(slot,
+// component) tensor X[k][r] and appends the new axis last: Y[r][n].  The 1D
+// operators are centro-symmetric (symmetric Chebyshev nodes, +-m modes), so
+// each stage folds the input pair (k, Nin-1-k) into even/odd parts, applies
+// two half-size real matrices Me, Mo (interleaved per entry in `mat`,
+// Nh x Kh) and unfolds the output pair (n, Nout-1-n).
+enum StageMode {
+    ST_SYM_REAL = 0,      // real -> real, y = U + W / U - W (interpolation)
+    ST_OUT_HALF = 1,      // real nodes -> complex half modes, y = U - iW
+    ST_OUT_FULL = 2,      // complex nodes -> complex +-m modes, y(+m) = U - iW, y(-m) = U + iW
+    ST_IN_FULL = 3,       // complex +-m modes -> complex nodes, y = U + iW / U - iW
+    ST_IN_HALF_REAL = 4   // complex half modes -> real nodes (accumulated), y = U - W / U + W
+};
+enum StageIO { IO_PLAIN = 0, IO_GATHER8 = 1, IO_SCATTER8 = 2 };
+struct StageArgs {
     const void* X;
-    long xstride;       // elements per (slot, component)
-    const int* xmap;    // slot -> array slot (nullptr: identity)
-    int xkind;
-    const void* M;      // N x K matrix
-    int mcplx;          // 1: complex matrix, 0: real matrix
+    long xstride;        // elements per (slot, component)
+    const int* xmap;     // slot -> X slot (nullptr: identity)
     void* Y;
     long ystride;
     const int* ymap;
-    int ymode;
-    int K, R, N;
+    int accumulate;      // add into Y instead of storing (real outputs)
+    const double* mat;   // Nh x Kh pairs (Me, Mo)
+    int Nin, Nout, in_off, out_off;
+    int Kh, Nh;          // folded input / output half lengths
+    int R;               // rows
     int nslots;
+    int p;               // proxy order (gather / scatter addressing)
+    const int* child_fid;// 8 per slot (gather / scatter)
 };
-void launch_contract(const ContractArgs& a, hipStream_t s);
-
-// merge 8 children into parent (first stage gathers the (2p)^3 child grid):
-// Y[p][B][C][a] = sum_A up[a][A] Qchild(A,B,C); children fids (8 per parent, -1 = none)
-void launch_merge_stage1(int p, const int* child_fid, int nparent, const double* Q, const double* up,
-                         double* Y, hipStream_t s);
-// interpolation last stage: scatter-add Y[A][B][C] into the children's V
-void launch_interp_stage3(int p, const int* child_fid, int nparent, const double* X /*[c][A][B] per parent*/,
-                          const double* down, double* V, hipStream_t s);
+void launch_stage(int mode, int io, const StageArgs& a, hipStream_t s);
 
 // plane-wave translation with the difference-kernel symbol (Step 3b)
 struct RecvDesc {
@@ -85,7 +91,7 @@ struct RecvDesc {
 void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int* e_src /*sender slot*/,
                       const int8_t* e_off /*3 per entry*/, const cplx* Phi, const double* wdiff, cplx* Psi,
                       hipStream_t s);
-// root symbol multiply: Psi[j][m] = w(|m|^2) (I - m m^T/|m|^2) Phi[j][m]
+// root symbol multiply: Psi[j][mz][my][mx] = w(|m|^2) (I - m m^T/|m|^2) Phi[j][mx][my][mz]
 void launch_root_symbol(int mh, int mf, const cplx* Phi, const double* w, cplx* Psi, hipStream_t s);
 
 // near field (Step 4) + self term

@@ -435,6 +435,29 @@ void plane_wave_mats(int p, int mmax, double alpha, const std::vector<double>& t
         }
 }
 
+Tables::PW fold_pw(int p, int M, double theta, const std::vector<double>& t)
+{
+    const int h = (p + 1) / 2;
+    Tables::PW w;
+    w.M = M;
+    w.out.resize((size_t)2 * (M + 1) * h);
+    w.in_full.resize((size_t)2 * h * (M + 1));
+    w.in_half.resize((size_t)2 * h * (M + 1));
+    for (int m = 0; m <= M; ++m)
+        for (int j = 0; j < h; ++j) {
+            const double ph = theta * m * t[j];
+            const double c = std::cos(ph), s = std::sin(ph);
+            w.out[2 * ((size_t)m * h + j)] = c;
+            w.out[2 * ((size_t)m * h + j) + 1] = s;
+            w.in_full[2 * ((size_t)j * (M + 1) + m)] = c;
+            w.in_full[2 * ((size_t)j * (M + 1) + m) + 1] = s;
+            const double wm = m == 0 ? 1.0 : 2.0;
+            w.in_half[2 * ((size_t)j * (M + 1) + m)] = wm * c;
+            w.in_half[2 * ((size_t)j * (M + 1) + m) + 1] = wm * s;
+        }
+    return w;
+}
+
 Tables* build_tables(double tol)
 {
     Params prm;
@@ -491,6 +514,25 @@ Tables* build_tables(double tol)
         const double k = 2.0 * kPi * std::sqrt((double)m2);
         T->wper[m2] = w.gammahat(k) / (k * k);
     }
+    // folded stage matrices
+    const int h = (p + 1) / 2;
+    T->pw = fold_pw(p, q - 1, kPi / 3.0, t);
+    T->pw_root = fold_pw(p, T->root_m, kPi / T->root_period, t);
+    T->pw_per = fold_pw(p, T->per_m, kPi, t);
+    T->merge_mat.resize((size_t)2 * h * p);
+    for (int i = 0; i < h; ++i)
+        for (int j = 0; j < p; ++j) {
+            const double a = T->up[(size_t)i * 2 * p + j], b = T->up[(size_t)i * 2 * p + (2 * p - 1 - j)];
+            T->merge_mat[2 * ((size_t)i * p + j)] = 0.5 * (a + b);
+            T->merge_mat[2 * ((size_t)i * p + j) + 1] = 0.5 * (a - b);
+        }
+    T->interp_mat.resize((size_t)2 * p * h);
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < h; ++j) {
+            const double a = T->down[(size_t)i * p + j], b = T->down[(size_t)i * p + (p - 1 - j)];
+            T->interp_mat[2 * ((size_t)i * h + j)] = 0.5 * (a + b);
+            T->interp_mat[2 * ((size_t)i * h + j) + 1] = 0.5 * (a - b);
+        }
     return T;
 }
 

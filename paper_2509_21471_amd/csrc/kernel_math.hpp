@@ -102,6 +102,17 @@ struct Tables {
     int per_m;
     std::vector<std::complex<double>> p_e_half, p_e_full, p_g_half, p_g_full;
     std::vector<double> wper;    // by |kappa|^2: gammahat(2 pi |kappa|) / (4 pi^2 |kappa|^2)
+    // folded stage matrices, (Me, Mo) pairs, row-major Nh x Kh (see the
+    // separable-stage kernel): h = ceil(p/2)
+    struct PW {
+        int M;                    // modes -M..M (half axis 0..M)
+        std::vector<double> out;  // (M+1) x h : cos(th m t_j), sin(th m t_j)
+        std::vector<double> in_full;  // h x (M+1): cos(th m t_i), sin(th m t_i)
+        std::vector<double> in_half;  // h x (M+1): w_m cos, w_m sin, w_0 = 1, w_m = 2
+    };
+    PW pw, pw_root, pw_per;
+    std::vector<double> merge_mat;   // h x p  : (up[i][j] +- up[i][2p-1-j]) / 2
+    std::vector<double> interp_mat;  // p x h  : (down[i][j] +- down[i][p-1-j]) / 2
 };
 
 // Builds (and caches per tolerance) the tables.  Returns nullptr on bad tol.

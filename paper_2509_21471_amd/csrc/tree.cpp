@@ -2,7 +2,6 @@
 #include "tree.hpp"
 
 #include <algorithm>
-#include <unordered_map>
 
 namespace dmk {
 
@@ -16,12 +15,66 @@ inline uint64_t box_key(int level, int64_t ix, int64_t iy, int64_t iz)
     return ((uint64_t)level << 58) | m;
 }
 
+// open-addressing hash map uint64 -> int (keys never equal ~0)
+struct FlatMap {
+    std::vector<uint64_t> k;
+    std::vector<int> v;
+    size_t mask = 0, count = 0;
+    FlatMap() { rehash(1 << 12); }
+    static inline size_t mix(uint64_t x)
+    {
+        x ^= x >> 33;
+        x *= 0xff51afd7ed558ccdull;
+        x ^= x >> 33;
+        x *= 0xc4ceb9fe1a85ec53ull;
+        x ^= x >> 33;
+        return (size_t)x;
+    }
+    void rehash(size_t cap)
+    {
+        std::vector<uint64_t> ok;
+        std::vector<int> ov;
+        ok.swap(k);
+        ov.swap(v);
+        k.assign(cap, ~0ull);
+        v.assign(cap, -1);
+        mask = cap - 1;
+        count = 0;
+        for (size_t i = 0; i < ok.size(); ++i)
+            if (ok[i] != ~0ull)
+                set(ok[i], ov[i]);
+    }
+    void set(uint64_t key, int val)
+    {
+        if (2 * (count + 1) > k.size())
+            rehash(2 * k.size());
+        size_t i = mix(key) & mask;
+        while (k[i] != ~0ull && k[i] != key)
+            i = (i + 1) & mask;
+        if (k[i] == ~0ull)
+            ++count;
+        k[i] = key;
+        v[i] = val;
+    }
+    int get(uint64_t key) const
+    {
+        size_t i = mix(key) & mask;
+        while (k[i] != ~0ull) {
+            if (k[i] == key)
+                return v[i];
+            i = (i + 1) & mask;
+        }
+        return -1;
+    }
+    void clear() { rehash(1 << 12); }
+};
+
 struct Builder {
     const uint64_t* keys;
     int64_t n;
     bool periodic;
     std::vector<Box> boxes;
-    std::unordered_map<uint64_t, int> lookup;
+    FlatMap lookup;
 
     int64_t lower_bound(int64_t lo, int64_t hi, uint64_t v) const
     {
@@ -43,7 +96,7 @@ struct Builder {
         b.leaf = true;
         boxes.push_back(b);
         const int id = (int)boxes.size() - 1;
-        lookup[box_key(level, ix, iy, iz)] = id;
+        lookup.set(box_key(level, ix, iy, iz), id);
         return id;
     }
 
@@ -92,10 +145,27 @@ struct Builder {
         return true;
     }
 
-    int find(int L, int64_t ix, int64_t iy, int64_t iz) const
+    int find(int L, int64_t ix, int64_t iy, int64_t iz) const { return lookup.get(box_key(L, ix, iy, iz)); }
+
+    // Makes sure the box at (L, ix, iy, iz) exists, splitting the leaf that
+    // currently covers that cell (and its descendants on the way) as needed.
+    int ensure(int L, int64_t ix, int64_t iy, int64_t iz)
     {
-        auto it = lookup.find(box_key(L, ix, iy, iz));
-        return it == lookup.end() ? -1 : it->second;
+        int id = find(L, ix, iy, iz);
+        if (id >= 0)
+            return id;
+        int l = L - 1;
+        int anc = -1;
+        while (l >= 0 && (anc = find(l, ix >> (L - l), iy >> (L - l), iz >> (L - l))) < 0)
+            --l;
+        while (l < L) {  // anc is a leaf at level l covering the cell
+            split(anc);
+            ++l;
+            const int sh = L - l;
+            const int d = (int)((((ix >> sh) & 1) << 2) | (((iy >> sh) & 1) << 1) | ((iz >> sh) & 1));
+            anc = boxes[anc].child[d];
+        }
+        return anc;
     }
 
     // true if a child (bits cx,cy,cz) of the neighbour at offset o touches the
@@ -113,29 +183,6 @@ struct Builder {
         return true;
     }
 
-    bool needs_split_for_balance(int id) const
-    {
-        const Box& B = boxes[id];
-        for (int ox = -1; ox <= 1; ++ox)
-            for (int oy = -1; oy <= 1; ++oy)
-                for (int oz = -1; oz <= 1; ++oz) {
-                    if (!ox && !oy && !oz)
-                        continue;
-                    int64_t nx, ny, nz;
-                    int px, py, pz;
-                    if (!neighbour(B.level, B.ix, B.iy, B.iz, ox, oy, oz, &nx, &ny, &nz, &px, &py, &pz))
-                        continue;
-                    const int C = find(B.level, nx, ny, nz);
-                    if (C < 0 || boxes[C].leaf)
-                        continue;
-                    for (int d = 0; d < 8; ++d) {
-                        const int ch = boxes[C].child[d];
-                        if (ch >= 0 && !boxes[ch].leaf && child_touches(ox, oy, oz, d))
-                            return true;
-                    }
-                }
-        return false;
-    }
 };
 
 }  // namespace
@@ -154,17 +201,42 @@ void build_tree(const uint64_t* sorted_keys, int64_t n, int ns, bool periodic, T
         if (B.end - B.start > ns && B.level < kMaxLevel)
             b.split((int)i);
     }
-    // 2:1 level restriction over vertex adjacency (empty leaves included)
-    for (int pass = 0; pass < 4 * kMaxLevel + 8; ++pass) {
-        std::vector<int> todo;
-        for (size_t i = 0; i < b.boxes.size(); ++i)
-            if (b.boxes[i].leaf && b.boxes[i].level < kMaxLevel && b.needs_split_for_balance((int)i))
-                todo.push_back((int)i);
-        if (todo.empty())
-            break;
-        for (int id : todo)
-            if (b.boxes[id].leaf)
-                b.split(id);
+    // 2:1 level restriction over vertex adjacency (empty leaves included).
+    // A leaf at level L must be split when a box at level L+1 touching it has
+    // children, i.e. every box at level L touching a non-leaf box at level L+1
+    // must exist and be split.  Processing non-leaf boxes from the deepest
+    // level upwards settles each level once: splits only create non-leaf boxes
+    // at coarser levels, which are visited later.
+    {
+        int maxl = 0;
+        for (const Box& B : b.boxes)
+            maxl = std::max(maxl, B.level);
+        for (int l = maxl; l >= 1; --l) {
+            // non-leaf boxes at level l (including ones created by splits below)
+            std::vector<int> nl;
+            for (size_t i = 0; i < b.boxes.size(); ++i)
+                if (b.boxes[i].level == l && !b.boxes[i].leaf)
+                    nl.push_back((int)i);
+            for (int id : nl) {
+                const Box C = b.boxes[id];
+                // boxes at level l-1 touching C: the parents' cells of C's
+                // neighbour cells at level l
+                for (int ox = -1; ox <= 1; ++ox)
+                    for (int oy = -1; oy <= 1; ++oy)
+                        for (int oz = -1; oz <= 1; ++oz) {
+                            if (!ox && !oy && !oz)
+                                continue;
+                            int64_t nx, ny, nz;
+                            int px, py, pz;
+                            if (!b.neighbour(l, C.ix, C.iy, C.iz, ox, oy, oz, &nx, &ny, &nz, &px, &py, &pz))
+                                continue;
+                            const int Lc = l - 1;
+                            const int tgt = b.ensure(Lc, nx >> 1, ny >> 1, nz >> 1);
+                            if (b.boxes[tgt].leaf && b.boxes[tgt].level < kMaxLevel)
+                                b.split(tgt);
+                        }
+            }
+        }
     }
     // order by level, Morton order within a level
     std::vector<int> order(b.boxes.size());
@@ -189,7 +261,7 @@ void build_tree(const uint64_t* sorted_keys, int64_t n, int ns, bool periodic, T
     }
     b.lookup.clear();
     for (size_t i = 0; i < T->boxes.size(); ++i)
-        b.lookup[box_key(T->boxes[i].level, T->boxes[i].ix, T->boxes[i].iy, T->boxes[i].iz)] = (int)i;
+        b.lookup.set(box_key(T->boxes[i].level, T->boxes[i].ix, T->boxes[i].iy, T->boxes[i].iz), (int)i);
     b.boxes = T->boxes;
     T->periodic = periodic;
     T->n = n;
