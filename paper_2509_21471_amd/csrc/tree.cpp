@@ -7,11 +7,31 @@ namespace dmk {
 
 namespace {
 
+// bit b of a byte -> bit 3b
+struct Spread {
+    uint32_t t[256];
+    Spread()
+    {
+        for (int v = 0; v < 256; ++v) {
+            uint32_t r = 0;
+            for (int b = 0; b < 8; ++b)
+                r |= (uint32_t)((v >> b) & 1) << (3 * b);
+            t[v] = r;
+        }
+    }
+};
+const Spread kSpread;
+
+inline uint64_t spread3(uint64_t v)
+{
+    return (uint64_t)kSpread.t[v & 255] | ((uint64_t)kSpread.t[(v >> 8) & 255] << 24) |
+           ((uint64_t)kSpread.t[(v >> 16) & 255] << 48);
+}
+
+// level in the top bits, Morton index of the box below (digit per level = 4 bx + 2 by + bz)
 inline uint64_t box_key(int level, int64_t ix, int64_t iy, int64_t iz)
 {
-    uint64_t m = 0;
-    for (int b = level - 1; b >= 0; --b)
-        m = (m << 3) | ((uint64_t)((ix >> b) & 1) << 2) | ((uint64_t)((iy >> b) & 1) << 1) | (uint64_t)((iz >> b) & 1);
+    const uint64_t m = (spread3((uint64_t)ix) << 2) | (spread3((uint64_t)iy) << 1) | spread3((uint64_t)iz);
     return ((uint64_t)level << 58) | m;
 }
 
@@ -259,10 +279,6 @@ void build_tree(const uint64_t* sorted_keys, int64_t n, int ns, bool periodic, T
                 B.child[d] = newid[B.child[d]];
         T->boxes[i] = B;
     }
-    b.lookup.clear();
-    for (size_t i = 0; i < T->boxes.size(); ++i)
-        b.lookup.set(box_key(T->boxes[i].level, T->boxes[i].ix, T->boxes[i].iy, T->boxes[i].iz), (int)i);
-    b.boxes = T->boxes;
     T->periodic = periodic;
     T->n = n;
     T->max_level = 0;
@@ -275,22 +291,56 @@ void build_tree(const uint64_t* sorted_keys, int64_t n, int ns, bool periodic, T
         T->level_start[l + 1] += T->level_start[l];
 
     const int nb = (int)T->boxes.size();
-    // colleagues (same level, sharing a boundary point, incl. itself)
+    // colleagues (same level, sharing a boundary point, incl. itself), top
+    // down: the colleagues of a box are the children of its parent's
+    // colleagues that touch it (offsets in box lengths of its own level)
     T->colleagues.assign(nb, {});
-    for (int i = 0; i < nb; ++i) {
-        const Box& B = T->boxes[i];
+    T->colleagues[0].reserve(27);
+    if (periodic) {
         for (int ox = -1; ox <= 1; ++ox)
             for (int oy = -1; oy <= 1; ++oy)
-                for (int oz = -1; oz <= 1; ++oz) {
-                    int64_t nx, ny, nz;
-                    int px, py, pz;
-                    if (!b.neighbour(B.level, B.ix, B.iy, B.iz, ox, oy, oz, &nx, &ny, &nz, &px, &py, &pz))
-                        continue;
-                    const int C = b.find(B.level, nx, ny, nz);
-                    if (C >= 0)
-                        T->colleagues[i].push_back(FarEntry{C, (int8_t)ox, (int8_t)oy, (int8_t)oz});
-                }
+                for (int oz = -1; oz <= 1; ++oz)
+                    T->colleagues[0].push_back(FarEntry{0, (int8_t)ox, (int8_t)oy, (int8_t)oz});
+    } else {
+        T->colleagues[0].push_back(FarEntry{0, 0, 0, 0});
     }
+    for (int l = 1; l <= T->max_level; ++l) {
+#pragma omp parallel for schedule(static, 64)
+      for (int i = T->level_start[l]; i < T->level_start[l + 1]; ++i) {
+        const Box& B = T->boxes[i];
+        const int bb[3] = {(int)(B.ix & 1), (int)(B.iy & 1), (int)(B.iz & 1)};
+        auto& out = T->colleagues[i];
+        out.reserve(27);
+        for (const FarEntry& e : T->colleagues[B.parent]) {
+            const Box& C = T->boxes[e.src];
+            if (C.leaf)
+                continue;
+            const int oP[3] = {e.ox, e.oy, e.oz};
+            for (int d = 0; d < 8; ++d) {
+                const int cb[3] = {(d >> 2) & 1, (d >> 1) & 1, d & 1};
+                int o[3];
+                bool ok = true;
+                for (int k = 0; k < 3; ++k) {
+                    o[k] = 2 * oP[k] + cb[k] - bb[k];
+                    ok = ok && o[k] >= -1 && o[k] <= 1;
+                }
+                if (ok && C.child[d] >= 0)
+                    out.push_back(FarEntry{C.child[d], (int8_t)o[0], (int8_t)o[1], (int8_t)o[2]});
+            }
+        }
+      }
+    }
+    // periodic image shift of the colleague at offset o of box B
+    auto image = [&](const Box& B, const FarEntry& e, int* px, int* py, int* pz) {
+        const int64_t M = (int64_t)1 << B.level;
+        const int64_t c[3] = {B.ix + e.ox, B.iy + e.oy, B.iz + e.oz};
+        int pp[3];
+        for (int k = 0; k < 3; ++k)
+            pp[k] = c[k] < 0 ? -1 : (c[k] >= M ? 1 : 0);
+        *px = pp[0];
+        *py = pp[1];
+        *pz = pp[2];
+    };
     // difference-kernel exchange (leaf/non-leaf rule): a non-leaf box receives
     // D_l from every non-empty colleague; a leaf receives D_l only from
     // non-leaf colleagues.  Adjacent leaves then exchange the residual at the
@@ -311,40 +361,39 @@ void build_tree(const uint64_t* sorted_keys, int64_t n, int ns, bool periodic, T
     }
     // near lists: adjacent non-empty leaves at levels L-1, L, L+1
     T->leaves.clear();
-    T->near.clear();
-    T->n_near_pairs = 0;
-    for (int i = 0; i < nb; ++i) {
+    for (int i = 0; i < nb; ++i)
+        if (T->boxes[i].leaf && T->boxes[i].end > T->boxes[i].start)
+            T->leaves.push_back(i);
+    const int nl = (int)T->leaves.size();
+    T->near.assign(nl, {});
+    int64_t pairs = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : pairs)
+    for (int li = 0; li < nl; ++li) {
+        const int i = T->leaves[li];
         const Box& B = T->boxes[i];
-        if (!B.leaf || B.end == B.start)
-            continue;
-        std::vector<NearEntry> list;
+        std::vector<NearEntry>& list = T->near[li];
+        list.reserve(64);
         auto add_entry = [&](int S, int px, int py, int pz, int lam) {
             const Box& Sb = T->boxes[S];
             if (Sb.end == Sb.start)
                 return;
             list.push_back(NearEntry{S, (int8_t)px, (int8_t)py, (int8_t)pz, (int8_t)lam});
-            T->n_near_pairs += (B.end - B.start) * (Sb.end - Sb.start);
+            pairs += (B.end - B.start) * (Sb.end - Sb.start);
         };
-        for (int ox = -1; ox <= 1; ++ox)
-            for (int oy = -1; oy <= 1; ++oy)
-                for (int oz = -1; oz <= 1; ++oz) {
-                    int64_t nx, ny, nz;
-                    int px, py, pz;
-                    if (!b.neighbour(B.level, B.ix, B.iy, B.iz, ox, oy, oz, &nx, &ny, &nz, &px, &py, &pz))
-                        continue;
-                    const int C = b.find(B.level, nx, ny, nz);
-                    if (C < 0)
-                        continue;
-                    if (T->boxes[C].leaf) {
-                        add_entry(C, px, py, pz, B.level);  // colleague leaf
-                    } else {
-                        for (int d = 0; d < 8; ++d) {  // fine neighbours
-                            const int ch = T->boxes[C].child[d];
-                            if (ch >= 0 && T->boxes[ch].leaf && Builder::child_touches(ox, oy, oz, d))
-                                add_entry(ch, px, py, pz, B.level + 1);
-                        }
-                    }
+        for (const FarEntry& e : T->colleagues[i]) {
+            int px, py, pz;
+            image(B, e, &px, &py, &pz);
+            const int C = e.src;
+            if (T->boxes[C].leaf) {
+                add_entry(C, px, py, pz, B.level);  // colleague leaf
+            } else {
+                for (int d = 0; d < 8; ++d) {  // fine neighbours
+                    const int ch = T->boxes[C].child[d];
+                    if (ch >= 0 && T->boxes[ch].leaf && Builder::child_touches(e.ox, e.oy, e.oz, d))
+                        add_entry(ch, px, py, pz, B.level + 1);
                 }
+            }
+        }
         if (B.parent >= 0) {  // coarse neighbours: leaf colleagues of the parent touching B
             const Box& P = T->boxes[B.parent];
             const int bx = (int)(B.ix & 1), by = (int)(B.iy & 1), bz = (int)(B.iz & 1);
@@ -363,15 +412,13 @@ void build_tree(const uint64_t* sorted_keys, int64_t n, int ns, bool periodic, T
                 if (!touch)
                     continue;
                 // periodic image shift of the parent's colleague
-                int64_t nx, ny, nz;
                 int px, py, pz;
-                b.neighbour(P.level, P.ix, P.iy, P.iz, e.ox, e.oy, e.oz, &nx, &ny, &nz, &px, &py, &pz);
+                image(P, e, &px, &py, &pz);
                 add_entry(e.src, px, py, pz, B.level);
             }
         }
-        T->leaves.push_back(i);
-        T->near.push_back(std::move(list));
     }
+    T->n_near_pairs = pairs;
 }
 
 }  // namespace dmk
