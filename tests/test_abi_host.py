@@ -1,0 +1,107 @@
+"""C ABI on the CPU: every symbol declared in include/dmk_stokes.h is exported,
+argument validation returns the documented codes before any GPU call, and
+the host tables (prolate window, radial fits, mollifier, parameters) match
+the independent oracle evaluation."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import splitting as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _dmk():
+    import paper_2509_21471_amd as dmk
+    return dmk
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "dmk_stokes.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dmk_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _dmk().lib()
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_dmk().SYMBOLS)
+
+
+@pytest.mark.parametrize("tol,q,p,n1,nper,ns", [(1e-3, 10, 12, 19, 3, 600), (1e-6, 17, 23, 33, 5, 1200),
+                                                 (1e-9, 25, 33, 49, 9, 2000), (1e-12, 31, 44, 61, 11, 3000)])
+def test_parameters_follow_table(tol, q, p, n1, nper, ns):
+    # Table tab:params (Stokeslet, PSWF columns) and the 3D leaf sizes of Sec. "Numerical results"
+    prm = _dmk().params(tol)
+    assert (prm["q"], prm["p"], prm["n1"], prm["nper"], prm["leaf_size"]) == (q, p, n1, nper, ns)
+    assert abs(prm["c"] - q * np.pi / 3) < 1e-14
+    # between rows: the stricter row
+    if tol > 1e-12:
+        assert _dmk().params(tol * 0.5)["p"] > p
+
+
+@pytest.mark.parametrize("tol,q", [(1e-6, 17), (1e-9, 25), (1e-12, 31)])
+def test_window_and_fits_match_oracle(tol, q):
+    win = S.ProlateWindow(S.prolate_c(q))
+    rho = np.concatenate([np.linspace(0.0, 0.999, 97), [1e-4, 0.5, 0.9999]])
+    out = _dmk().radial(tol, rho)
+    assert np.max(np.abs(out[:, 0] - win.phi(rho))) < 2e-13 * win.phi(0.0)
+    assert np.max(np.abs(out[:, 1] - win.Phi(rho))) < 1e-13
+    # P = E + G, Q = (E - G)/s with E = rho^-1 int_0^rho phi, G = phi(rho)
+    r = rho[rho > 1e-3]
+    E = (1.0 - win.Phi(r)) / (2.0 * r)
+    G = win.phi(r)
+    scale = 2 * win.phi(0.0)
+    fit_tol = max(1e-3 * tol, 2e-14) * scale * 20
+    got = _dmk().radial(tol, r)
+    assert np.max(np.abs(got[:, 2] - (E + G))) < fit_tol
+    # Q enters the residual as Q s = E - G (the term Q y y^T / r^2); compare that
+    assert np.max(np.abs(got[:, 3] * r ** 2 - (E - G))) < fit_tol
+
+
+@pytest.mark.parametrize("tol,q", [(1e-6, 17), (1e-9, 25)])
+def test_mollifier_matches_oracle(tol, q):
+    win = S.ProlateWindow(S.prolate_c(q))
+    k = np.linspace(0.0, 2.2 * win.c, 41)
+    got = _dmk().mollifier(tol, k)
+    assert np.max(np.abs(got[:, 0] - win.phihat(k))) < 1e-12
+    assert np.max(np.abs(got[:, 1] - win.gammahat(k))) < 1e-11
+
+
+def test_plan_argument_validation_without_gpu():
+    dmk = _dmk()
+    lib = dmk.lib()
+    out = ctypes.c_void_p()
+    host = (ctypes.c_double * 30)()
+    vp = ctypes.cast(host, ctypes.c_void_p)
+    assert lib.dmk_stokes_plan(None, 10, 3, 0, 1e-6, ctypes.byref(out)) == -1      # NULL points
+    assert lib.dmk_stokes_plan(vp, 0, 3, 0, 1e-6, ctypes.byref(out)) == -1         # n < 1
+    assert lib.dmk_stokes_plan(vp, 10, 2, 0, 1e-6, ctypes.byref(out)) == -2        # dim 2 unsupported
+    assert lib.dmk_stokes_plan(vp, 10, 3, 0, 1e-2, ctypes.byref(out)) == -5        # tol out of range
+    assert lib.dmk_stokes_plan(vp, 10, 3, 0, 1e-13, ctypes.byref(out)) == -5
+    assert lib.dmk_stokes_plan(vp, 10, 3, 2, 1e-6, ctypes.byref(out)) == -1        # periodic flag
+    opts = dmk._lib.Opts(1, 0, None, 0, 0)
+    assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-9, ctypes.byref(opts), ctypes.byref(out)) == -5  # mixed < 1e-7
+    assert lib.dmk_stokes_plan(vp, 10, 3, 0, 1e-6, None) == -1                     # NULL out
+    assert lib.dmk_stokes_plan(vp, 10, 3, 0, 1e-6, ctypes.byref(out)) == -1        # host pointer
+    assert out.value is None
+    assert b"device pointer" in lib.dmk_last_error()
+    assert lib.dmk_stokes_eval(None, None, 1, None) == -1
+    lib.dmk_stokes_destroy(None)
+    info = dmk._lib.PlanInfo()
+    assert lib.dmk_stokes_plan_info(None, ctypes.byref(info)) == -1
+    assert lib.dmk_stokes_params(0.5, ctypes.byref(info)) == -5
+
+
+def test_host_tree_argument_validation():
+    dmk = _dmk()
+    with pytest.raises(dmk.DMKError):
+        dmk.host_tree(np.array([[0.5, 0.5, 1.2]]), 10, periodic=True)   # outside the cell
+    with pytest.raises(dmk.DMKError):
+        dmk.host_tree(np.array([[np.nan, 0.5, 0.2]]), 10)
