@@ -41,6 +41,7 @@ def main():
     ap.add_argument("--config", default="clusters_1e6")
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--leaf-size", type=int, default=0)
+    ap.add_argument("--near-lanes", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=12000)
     ap.add_argument("--parity-sample", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -74,7 +75,8 @@ def main():
     print(f"# input ready: {args.config} n={n} tol={tol}", file=sys.stderr, flush=True)
 
     def make_plan():
-        return dmk.Plan(xd, periodic=periodic, tol=tol, leaf_size=args.leaf_size, timing=True)
+        return dmk.Plan(xd, periodic=periodic, tol=tol, leaf_size=args.leaf_size, timing=True,
+                        near_lanes=args.near_lanes)
 
     # warmup (also builds the per-tolerance tables once)
     for _ in range(args.warmup):

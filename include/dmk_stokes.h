@@ -61,6 +61,8 @@ typedef struct {
     void* stream;         /* hipStream_t for all work of the plan; NULL = null stream */
     size_t mem_cap_bytes; /* refuse plans whose device buffers exceed this; 0 = no cap */
     int flags;            /* DMK_FLAG_* bits */
+    int near_lanes;       /* near field: source lanes per target (1, 2 or 4; a wave then
+                             holds 64, 32 or 16 targets); 0 = automatic */
 } dmk_opts;
 
 /* record HIP events around each phase of dmk_stokes_eval (read back with

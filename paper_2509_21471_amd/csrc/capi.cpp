@@ -178,6 +178,9 @@ struct dmk_plan_s {
     std::vector<int> box_fid;         // box id -> fid or -1
     dmk::LeafDesc* leaves = nullptr;  // non-empty leaves
     int nleaf = 0;
+    double* Ltab = nullptr;           // Lagrange values of the points on their leaf grids
+    dmk::EvalChunk* echunks = nullptr;
+    int n_echunk = 0;
     struct LevelLists {
         int nparent = 0;
         int* child_fid = nullptr;     // 8 per parent
@@ -195,6 +198,7 @@ struct dmk_plan_s {
     dmk::NearEntryDev* nentries = nullptr;
     dmk::NearWork* nwork = nullptr;
     int n_nwork = 0;
+    int near_sg = 4;                  // source lanes per target in the near field
     double* cbbox = nullptr;
     // work buffers
     double* fs = nullptr;             // sorted forces [3][n]
@@ -233,6 +237,8 @@ int validate_common(int dim, double tol, const dmk_opts* opts)
             return fail(DMK_ERR_TOL, "mixed precision needs tol >= 1e-7");
         if (opts->leaf_size < 0)
             return fail(DMK_ERR_ARG, "leaf_size must be >= 0");
+        if (opts->near_lanes != 0 && opts->near_lanes != 1 && opts->near_lanes != 2 && opts->near_lanes != 4)
+            return fail(DMK_ERR_ARG, "near_lanes must be 0, 1, 2 or 4");
     }
     return DMK_OK;
 }
@@ -422,6 +428,13 @@ int build_plan(dmk_plan_t P, const double* points)
     }
     P->nleaf = (int)hl.size();
     P->leaves = P->mem.alloc<LeafDesc>(hl.size());
+    std::vector<EvalChunk> ech;
+    for (const LeafDesc& d : hl)
+        for (int64_t s0 = d.start; s0 < d.end; s0 += 64)
+            ech.push_back(EvalChunk{d.fid, s0, std::min<int64_t>(s0 + 64, d.end)});
+    P->n_echunk = (int)ech.size();
+    P->echunks = P->mem.alloc<EvalChunk>(ech.size());
+    P->Ltab = P->mem.alloc<double>((size_t)n * 3 * lagrange_pad(P->prm.p));
     // per-level parent lists (non-empty, non-leaf)
     P->lev.assign(T.max_level + 1, {});
     for (int l = 0; l < T.max_level; ++l) {
@@ -512,7 +525,8 @@ int build_plan(dmk_plan_t P, const double* points)
             nent.push_back(d);
         }
         L.eend = (int)nent.size();
-        const int nch = (int)((B.end - B.start + 63) / 64);
+        const int tg = 64 / P->near_sg;
+        const int nch = (int)((B.end - B.start + tg - 1) / tg);
         for (int c = 0; c < nch; ++c)
             nwk.push_back(NearWork{li, c});
         nlv.push_back(L);
@@ -591,6 +605,7 @@ int build_plan(dmk_plan_t P, const double* points)
         return fail(DMK_ERR_OOM, "device allocation failed (or above mem_cap_bytes)");
     lap(4);
     HIPCHK(upload(P->leaves, hl));
+    HIPCHK(upload(P->echunks, ech));
     HIPCHK(upload(P->send_fid, sfid));
     HIPCHK(upload(P->recv_fid, rfid));
     HIPCHK(upload(P->recv, rd));
@@ -606,6 +621,7 @@ int build_plan(dmk_plan_t P, const double* points)
     HIPCHK(upload(P->wdiff, TB.wdiff));
     HIPCHK(upload(P->wroot, wr));
     launch_chunk_bbox(P->x, P->y, P->z, d_cstart, d_clen, (int)cstart.size(), P->cbbox, st);
+    launch_lagrange_table(P->prm.p, P->leaves, P->nleaf, P->x, P->y, P->z, P->cheb_t, P->cheb_w, P->Ltab, st);
     // radial polynomials
     if (!make_poly(TB, &P->poly))
         return fail(DMK_ERR_UNSUPPORTED, "radial fit degree too high");
@@ -630,7 +646,7 @@ int eval_one(dmk_plan_t P, const double* f, double* vel, bool record)
     const Tree& T = P->tree;
     launch_gather_forces(f, n, P->perm, P->fs, st);
     // Step 2a: proxy charges of the leaves
-    launch_anterp(p, P->leaves, P->nleaf, P->x, P->y, P->z, P->fs, n, P->cheb_t, P->cheb_w, P->Q, st);
+    launch_anterp(p, P->leaves, P->nleaf, P->Ltab, P->fs, n, P->Q, st);
     mark(1);
     const int h = (p + 1) / 2, M = q - 1;
     // Step 2b: merge children into parents, finest level first (Q is x-major [a][b][c])
@@ -705,9 +721,9 @@ int eval_one(dmk_plan_t P, const double* f, double* vel, bool record)
     }
     mark(7);
     // far field at the points, then the near field (Step 4) and self term
-    launch_leaf_eval(p, P->leaves, P->nleaf, P->x, P->y, P->z, n, P->cheb_t, P->cheb_w, P->V, P->u, st);
+    launch_leaf_eval(p, P->echunks, P->n_echunk, P->Ltab, P->V, n, P->u, st);
     mark(8);
-    launch_near(P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x, P->y, P->z, P->fs, n, P->poly,
+    launch_near(P->near_sg, P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x, P->y, P->z, P->fs, n, P->poly,
                 -P->tab->phi0 / (2.0 * kPi), P->u, st);
     mark(9);
     launch_finalize(P->u, n, P->perm, 1.0 / P->box_len, P->periodic ? nullptr : P->cst, vel, st);
@@ -813,6 +829,8 @@ int dmk_stokes_plan_ex(const double* points, int64_t n, int dim, int periodic, d
             P->prm.ns = opts->leaf_size;
         P->mem.cap = opts->mem_cap_bytes;
         P->timing = (opts->flags & DMK_FLAG_PHASE_TIMING) != 0;
+        if (opts->near_lanes > 0)
+            P->near_sg = opts->near_lanes;
     }
     if (P->timing)
         for (auto& e : P->ev)
@@ -950,7 +968,7 @@ int dmk_stokes_near_stats(dmk_plan_t plan, int64_t* listed, int64_t* evaluated, 
     if (!d)
         return fail(DMK_ERR_OOM, "device allocation failed");
     HIPCHK(hipMemsetAsync(d, 0, 2 * sizeof(unsigned long long), plan->stream));
-    dmk::launch_near_count(plan->nwork, plan->n_nwork, plan->nleaves, plan->nentries, plan->cbbox, plan->x,
+    dmk::launch_near_count(plan->near_sg, plan->nwork, plan->n_nwork, plan->nleaves, plan->nentries, plan->cbbox, plan->x,
                            plan->y, plan->z, d, plan->stream);
     unsigned long long h[2] = {0, 0};
     HIPCHK(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, plan->stream));

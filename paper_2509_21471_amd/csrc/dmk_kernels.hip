@@ -200,133 +200,172 @@ __device__ inline void lagrange(double xi, const double* __restrict__ t, const d
         L[a] = hit >= 0 ? (a == hit ? 1.0 : 0.0) : L[a] * id;
 }
 
-// Proxy charges of one leaf per block; each thread owns output rows (b, c).
+// ---- point <-> proxy grid (MFMA) ---------------------------------------------------
+// Lagrange values of every point on its leaf's proxy grid, computed once per
+// plan: Ltab[i][d][0..PA) (d = x, y, z; PA = p rounded up to 4, zero padded).
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
 template <int P>
-__global__ __launch_bounds__(256) void k_anterp(const LeafDesc* __restrict__ leaves, const double* __restrict__ x,
-                                                const double* __restrict__ y, const double* __restrict__ z,
-                                                const double* __restrict__ fs, int64_t n,
-                                                const double* __restrict__ ct, const double* __restrict__ cw,
-                                                double* __restrict__ Q)
+struct MCfg {
+    static constexpr int PA = (P + 3) / 4 * 4;   // K padding for 16x16x4 steps
+    static constexpr int NK = PA / 4;
+    static constexpr int NT = (P + 15) / 16;     // 16-row tiles over a grid axis
+    static constexpr int RS = PA + 1;            // LDS row stride (odd: conflict-free column reads)
+};
+
+template <int P>
+__global__ __launch_bounds__(256) void k_lagrange_table(const LeafDesc* __restrict__ leaves,
+                                                        const double* __restrict__ x, const double* __restrict__ y,
+                                                        const double* __restrict__ z, const double* __restrict__ ct,
+                                                        const double* __restrict__ cw, double* __restrict__ Ltab)
 {
-    constexpr int CH = P > 36 ? 32 : 64;
-    __shared__ double sL[3][CH][P];
-    __shared__ double sf[CH][3];
+    constexpr int PA = MCfg<P>::PA;
     const LeafDesc L = leaves[blockIdx.x];
-    const double sc = (double)(2ll << L.level);  // 1 / (half box length)
+    const double sc = (double)(2ll << L.level);
     const double cen[3] = {L.cx, L.cy, L.cz};
     const double* crd[3] = {x, y, z};
-    const int tid = threadIdx.x;
-    constexpr int NPAIR = P * P;
-    for (int round = 0; round * 256 < NPAIR; ++round) {
-        const int pair = round * 256 + tid;
-        const bool valid = pair < NPAIR;
-        const int b = valid ? pair / P : 0;
-        const int c = valid ? pair % P : 0;
-        double acc[P][3];
+    for (int64_t i = L.start + threadIdx.x; i < L.end; i += 256) {
+        for (int d = 0; d < 3; ++d) {
+            double Lv[P];
+            lagrange<P>((crd[d][i] - cen[d]) * sc, ct, cw, Lv);
+            double* o = Ltab + ((size_t)i * 3 + d) * PA;
 #pragma unroll
-        for (int a = 0; a < P; ++a)
-            acc[a][0] = acc[a][1] = acc[a][2] = 0.0;
-        for (int64_t cs = L.start; cs < L.end; cs += CH) {
-            __syncthreads();
-            for (int task = tid; task < 3 * CH; task += 256) {
-                const int pt = task % CH, d = task / CH;
-                const int64_t i = cs + pt;
-                double Lv[P];
-                if (i < L.end) {
-                    lagrange<P>((crd[d][i] - cen[d]) * sc, ct, cw, Lv);
-                } else {
-#pragma unroll
-                    for (int a = 0; a < P; ++a)
-                        Lv[a] = 0.0;
-                }
-#pragma unroll
-                for (int a = 0; a < P; ++a)
-                    sL[d][pt][a] = Lv[a];
-                sf[pt][d] = i < L.end ? fs[d * n + i] : 0.0;
-            }
-            __syncthreads();
-            if (valid) {
-                for (int pt = 0; pt < CH; ++pt) {
-                    const double wbc = sL[1][pt][b] * sL[2][pt][c];
-                    const double w0 = wbc * sf[pt][0], w1 = wbc * sf[pt][1], w2 = wbc * sf[pt][2];
-#pragma unroll
-                    for (int a = 0; a < P; ++a) {
-                        const double la = sL[0][pt][a];
-                        acc[a][0] = fma(la, w0, acc[a][0]);
-                        acc[a][1] = fma(la, w1, acc[a][1]);
-                        acc[a][2] = fma(la, w2, acc[a][2]);
-                    }
-                }
-            }
-        }
-        if (valid) {
-            double* q = Q + (size_t)L.fid * 3 * P * P * P;
-#pragma unroll
-            for (int a = 0; a < P; ++a)
-                for (int j = 0; j < 3; ++j)
-                    q[((size_t)j * P + a) * P * P + b * P + c] = acc[a][j];
+            for (int a = 0; a < PA; ++a)
+                o[a] = a < P ? Lv[a] : 0.0;
         }
     }
 }
 
-// Far-field potential at the points of one leaf per block.
+// Proxy charges (Step 2a): Q[j][a][b][c] = sum_pt Lx[pt][a] Ly[pt][b] Lz[pt][c] f_j[pt].
+// A block owns (leaf, a-range, bc-range); each thread owns one row (b, c) and
+// accumulates its a-range and the three components.  The per-point values
+// every thread needs (x Lagrange values, forces) have wave-uniform addresses
+// and arrive through scalar loads; each thread reads only its own y/z values.
 template <int P>
-__global__ __launch_bounds__(128) void k_leaf_eval(const LeafDesc* __restrict__ leaves, const double* __restrict__ x,
-                                                   const double* __restrict__ y, const double* __restrict__ z,
-                                                   int64_t n, const double* __restrict__ ct,
-                                                   const double* __restrict__ cw, const double* __restrict__ V,
-                                                   double* __restrict__ u)
+struct AnterpCfg {
+    static constexpr int NA = P <= 12 ? 1 : (P <= 23 ? 2 : (P <= 33 ? 3 : 4));  // a-ranges
+    static constexpr int NBC = P <= 23 ? 1 : (P <= 33 ? 2 : 4);                 // bc-ranges
+    static constexpr int AR = (P + NA - 1) / NA;
+    static constexpr int BCR = (P * P + NBC - 1) / NBC;
+    static constexpr int threads = ((BCR + 63) / 64) * 64;
+};
+
+template <int P>
+__global__ __launch_bounds__(AnterpCfg<P>::threads) void k_anterp(const LeafDesc* __restrict__ leaves,
+                                                                  const double* __restrict__ Ltab,
+                                                                  const double* __restrict__ fs, int64_t n,
+                                                                  double* __restrict__ Q)
 {
-    __shared__ double sLy[128][P];
+    using C = AnterpCfg<P>;
+    constexpr int PA = MCfg<P>::PA, AR = C::AR;
     const LeafDesc L = leaves[blockIdx.x];
-    const double sc = (double)(2ll << L.level);
-    const double* v = V + (size_t)L.fid * 3 * P * P * P;
+    const int ar = blockIdx.y % C::NA, bcr = blockIdx.y / C::NA;
+    const int a0 = ar * AR;
     const int tid = threadIdx.x;
-    for (int64_t ts = L.start; ts < L.end; ts += 128) {
-        const int64_t i = ts + tid;
-        const bool valid = i < L.end;
-        // V is stored z-major (V[c][b][a]); the outer sum runs over z
-        const double xi = valid ? (z[i] - L.cz) * sc : 0.0;
-        const double eta = valid ? (y[i] - L.cy) * sc : 0.0;
-        const double zeta = valid ? (x[i] - L.cx) * sc : 0.0;
-        double Lx[P], Lz[P], Ly[P];
-        lagrange<P>(xi, ct, cw, Lx);
-        lagrange<P>(eta, ct, cw, Ly);
-        lagrange<P>(zeta, ct, cw, Lz);
+    const int pair = bcr * C::BCR + tid;
+    const bool valid = tid < C::BCR && pair < P * P;
+    const int b = valid ? pair / P : 0;
+    const int c = valid ? pair % P : 0;
+    double acc[AR][3];
 #pragma unroll
-        for (int b = 0; b < P; ++b)
-            sLy[tid][b] = Ly[b];
-        // Lx to LDS as well (reuse the row after y is consumed per a)
-        double u0 = 0, u1 = 0, u2 = 0;
-        for (int a = 0; a < P; ++a) {
-            double la = 0;
+    for (int t = 0; t < AR; ++t)
+        acc[t][0] = acc[t][1] = acc[t][2] = 0.0;
+    const double* f0 = fs;
+    const double* f1 = fs + n;
+    const double* f2 = fs + 2 * n;
+#pragma unroll 2
+    for (int64_t pt = L.start; pt < L.end; ++pt) {
+        const double* Lp = Ltab + (size_t)pt * 3 * PA;
+        const double wbc = Lp[PA + b] * Lp[2 * PA + c];
+        const double w0 = wbc * f0[pt], w1 = wbc * f1[pt], w2 = wbc * f2[pt];
 #pragma unroll
-            for (int aa = 0; aa < P; ++aa)
-                la = (aa == a) ? Lx[aa] : la;
-            double t0 = 0, t1 = 0, t2 = 0;
-            for (int b = 0; b < P; ++b) {
-                const double* v0 = v + ((size_t)a * P + b) * P;
-                double s0 = 0, s1 = 0, s2 = 0;
+        for (int t = 0; t < AR; ++t) {
+            const double la = (a0 + t < P) ? Lp[a0 + t] : 0.0;
+            acc[t][0] = fma(la, w0, acc[t][0]);
+            acc[t][1] = fma(la, w1, acc[t][1]);
+            acc[t][2] = fma(la, w2, acc[t][2]);
+        }
+    }
+    if (valid) {
+        double* q = Q + (size_t)L.fid * 3 * P * P * P;
 #pragma unroll
-                for (int c = 0; c < P; ++c) {
-                    s0 = fma(v0[c], Lz[c], s0);
-                    s1 = fma(v0[(size_t)P * P * P + c], Lz[c], s1);
-                    s2 = fma(v0[(size_t)2 * P * P * P + c], Lz[c], s2);
-                }
-                const double lb = sLy[tid][b];
-                t0 = fma(lb, s0, t0);
-                t1 = fma(lb, s1, t1);
-                t2 = fma(lb, s2, t2);
+        for (int t = 0; t < AR; ++t)
+            if (a0 + t < P)
+                for (int j = 0; j < 3; ++j)
+                    q[((size_t)j * P + a0 + t) * P * P + b * P + c] = acc[t][j];
+    }
+}
+
+// Far-field potential at the points (final interpolation) as MFMA GEMMs:
+// for every z index c, D[b][pt] = sum_a V[j][c][b][a] Lx[pt][a] (V z-major),
+// then u_j[pt] += Lz[pt][c] sum_b Ly[pt][b] D[b][pt].  A block takes 64 points
+// of one leaf (16 per wave); the z-slab of V sits in LDS.
+template <int P>
+__global__ __launch_bounds__(256) void k_leaf_eval(const EvalChunk* __restrict__ chunks,
+                                                   const double* __restrict__ Ltab, const double* __restrict__ V,
+                                                   int64_t n, double* __restrict__ u)
+{
+    constexpr int PA = MCfg<P>::PA, NK = MCfg<P>::NK, NT = MCfg<P>::NT, RS = MCfg<P>::RS;
+    constexpr int PB = 16 * NT;
+    __shared__ double slab[3][PB][RS];
+    const EvalChunk C = chunks[blockIdx.x];
+    const double* v = V + (size_t)C.fid * 3 * P * P * P;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int lr = l & 15, lk = l >> 4;
+    const int64_t i = C.start + 16 * w + lr;
+    const bool valid = i < C.end;
+    const double* Li = Ltab + (size_t)(valid ? i : C.start) * 3 * PA;
+    double bx[NK];
+#pragma unroll
+    for (int s = 0; s < NK; ++s)
+        bx[s] = valid ? Li[4 * s + lk] : 0.0;
+    double wy[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int b = 16 * t + lk + 4 * r;
+            wy[t][r] = (valid && b < P) ? Li[PA + b] : 0.0;
+        }
+    for (int e = tid; e < 3 * PB * RS; e += 256)
+        (&slab[0][0][0])[e] = 0.0;
+    double u0 = 0, u1 = 0, u2 = 0;
+    for (int c = 0; c < P; ++c) {
+        __syncthreads();
+        for (int e = tid; e < 3 * P * P; e += 256) {
+            const int j = e / (P * P), r = e % (P * P);
+            slab[j][r / P][r % P] = v[(size_t)j * P * P * P + (size_t)c * P * P + r];
+        }
+        __syncthreads();
+        const double lz = valid ? Li[2 * PA + c] : 0.0;
+        double X[3] = {0, 0, 0};
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < NK; ++s)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(slab[j][16 * t + lr][4 * s + lk], bx[s], acc, 0, 0, 0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    X[j] = fma(wy[t][r], acc[r], X[j]);
             }
-            u0 = fma(la, t0, u0);
-            u1 = fma(la, t1, u1);
-            u2 = fma(la, t2, u2);
-        }
-        if (valid) {
-            u[i] = u0;
-            u[n + i] = u1;
-            u[2 * n + i] = u2;
-        }
+        u0 = fma(lz, X[0], u0);
+        u1 = fma(lz, X[1], u1);
+        u2 = fma(lz, X[2], u2);
+    }
+    // the four lanes of a point hold disjoint b rows
+    u0 += __shfl_xor(u0, 16);
+    u1 += __shfl_xor(u1, 16);
+    u2 += __shfl_xor(u2, 16);
+    u0 += __shfl_xor(u0, 32);
+    u1 += __shfl_xor(u1, 32);
+    u2 += __shfl_xor(u2, 32);
+    if (valid && lk == 0) {
+        u[i] = u0;
+        u[n + i] = u1;
+        u[2 * n + i] = u2;
     }
 }
 
@@ -341,25 +380,36 @@ __global__ __launch_bounds__(128) void k_leaf_eval(const LeafDesc* __restrict__ 
 
 bool p_supported(int p) { return p == 12 || p == 23 || p == 33 || p == 44; }
 
-void launch_anterp(int p, const LeafDesc* leaves, int nleaf, const double* x, const double* y, const double* z,
-                   const double* fs, int64_t n, const double* cheb_t, const double* cheb_w, double* Q,
-                   hipStream_t s)
+int lagrange_pad(int p) { return (p + 3) / 4 * 4; }
+
+void launch_lagrange_table(int p, const LeafDesc* leaves, int nleaf, const double* x, const double* y,
+                           const double* z, const double* cheb_t, const double* cheb_w, double* Ltab, hipStream_t s)
 {
     if (nleaf == 0)
         return;
-#define L_ANTERP(P) \
-    hipLaunchKernelGGL(k_anterp<P>, dim3(nleaf), dim3(256), 0, s, leaves, x, y, z, fs, n, cheb_t, cheb_w, Q)
+#define L_LT(P) hipLaunchKernelGGL(k_lagrange_table<P>, dim3(nleaf), dim3(256), 0, s, leaves, x, y, z, cheb_t, cheb_w, Ltab)
+    DMK_P_DISPATCH(p, L_LT)
+#undef L_LT
+}
+
+void launch_anterp(int p, const LeafDesc* leaves, int nleaf, const double* Ltab, const double* fs, int64_t n,
+                   double* Q, hipStream_t s)
+{
+    if (nleaf == 0)
+        return;
+#define L_ANTERP(P)                                                                                        \
+    hipLaunchKernelGGL(k_anterp<P>, dim3(nleaf, AnterpCfg<P>::NA * AnterpCfg<P>::NBC), dim3(AnterpCfg<P>::threads), \
+                       0, s, leaves, Ltab, fs, n, Q)
     DMK_P_DISPATCH(p, L_ANTERP)
 #undef L_ANTERP
 }
 
-void launch_leaf_eval(int p, const LeafDesc* leaves, int nleaf, const double* x, const double* y, const double* z,
-                      int64_t n, const double* cheb_t, const double* cheb_w, const double* V, double* u,
-                      hipStream_t s)
+void launch_leaf_eval(int p, const EvalChunk* chunks, int nchunk, const double* Ltab, const double* V, int64_t n,
+                      double* u, hipStream_t s)
 {
-    if (nleaf == 0)
+    if (nchunk == 0)
         return;
-#define L_EVAL(P) hipLaunchKernelGGL(k_leaf_eval<P>, dim3(nleaf), dim3(128), 0, s, leaves, x, y, z, n, cheb_t, cheb_w, V, u)
+#define L_EVAL(P) hipLaunchKernelGGL(k_leaf_eval<P>, dim3(nchunk), dim3(256), 0, s, chunks, Ltab, V, n, u)
     DMK_P_DISPATCH(p, L_EVAL)
 #undef L_EVAL
 }
@@ -723,25 +773,38 @@ __device__ inline void residual_pair(double dx, double dy, double dz, double fx,
     }
 }
 
-// One wave per 64 targets of a leaf.  Each non-pruned 64-point source chunk of
-// every near-list entry is staged in LDS (periodic shift applied) and read
-// back by broadcast.
-template <int ND>
+// One wave per target group of TG = 64/SG points of a leaf; lane (t, s) handles
+// target t against sources s, s+SG, ... of every non-pruned 64-point source
+// chunk (chunks whose bounding box lies within r_lambda of the group's box),
+// staged in LDS with the periodic image shift applied.  The SG partial sums of
+// a target are combined by cross-lane shuffles at the end.
+template <int ND, int SG>
 __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, const NearLeaf* __restrict__ leaves,
                                              const NearEntryDev* __restrict__ entries, const double* __restrict__ cbbox,
                                              const double* __restrict__ x, const double* __restrict__ y,
                                              const double* __restrict__ z, const double* __restrict__ fs, int64_t n,
                                              RadialPoly poly, double self_coef, double* __restrict__ u)
 {
+    constexpr int TG = 64 / SG;
     __shared__ double2 S[64][3];
     const NearWork w = work[blockIdx.x];
     const NearLeaf T = leaves[w.leaf];
     const int lane = threadIdx.x;
-    const int64_t i = T.tstart + (int64_t)w.chunk * 64 + lane;
+    const int tl = lane / SG, sl = lane % SG;
+    const int64_t g0 = T.tstart + (int64_t)w.chunk * TG;
+    const int64_t i = g0 + tl;
     const bool valid = i < T.tend;
     const double xt = valid ? x[i] : 0.0, yt = valid ? y[i] : 0.0, zt = valid ? z[i] : 0.0;
-    const double* tb = cbbox + 6 * (size_t)(T.cbase + w.chunk);
-    const double tlo[3] = {tb[0], tb[1], tb[2]}, thi[3] = {tb[3], tb[4], tb[5]};
+    // bounding box of the target group (wave reduction)
+    double tlo[3] = {valid ? xt : 1e300, valid ? yt : 1e300, valid ? zt : 1e300};
+    double thi[3] = {valid ? xt : -1e300, valid ? yt : -1e300, valid ? zt : -1e300};
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            tlo[d] = fmin(tlo[d], __shfl_xor(tlo[d], off));
+            thi[d] = fmax(thi[d], __shfl_xor(thi[d], off));
+        }
     double u0 = 0, u1 = 0, u2 = 0;
     for (int e = T.ebeg; e < T.eend; ++e) {
         const NearEntryDev E = entries[e];
@@ -771,13 +834,19 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
                 S[lane][2] = make_double2(fs[n + j], fs[2 * n + j]);
             }
             __syncthreads();
-            for (int jj = 0; jj < cnt; ++jj) {
+            for (int jj = sl; jj < cnt; jj += SG) {
                 const double2 a = S[jj][0], b = S[jj][1], c = S[jj][2];
                 residual_pair<ND>(xt - a.x, yt - a.y, zt - b.x, b.y, c.x, c.y, rl2, tw, cP, cQ, poly, u0, u1, u2);
             }
         }
     }
-    if (valid) {
+#pragma unroll
+    for (int off = 1; off < SG; off <<= 1) {
+        u0 += __shfl_xor(u0, off);
+        u1 += __shfl_xor(u1, off);
+        u2 += __shfl_xor(u2, off);
+    }
+    if (valid && sl == 0) {
         const double sc = self_coef * (double)(1ll << T.level);
         u[i] += u0 + sc * fs[i];
         u[n + i] += u1 + sc * fs[n + i];
@@ -796,19 +865,29 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
         MACRO(24);                 \
     }
 
-void launch_near(const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
+void launch_near(int sg, const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
                  const double* cbbox, const double* x, const double* y, const double* z, const double* fs, int64_t n,
                  const RadialPoly& poly, double self_coef, double* u, hipStream_t s)
 {
     if (nwork == 0)
         return;
-#define L_NEAR(ND)                                                                                               \
-    hipLaunchKernelGGL(k_near<ND>, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, fs, n, poly, \
-                       self_coef, u)
+#define L_NEAR_SG(ND, SG)                                                                                           \
+    hipLaunchKernelGGL((k_near<ND, SG>), dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, fs, n, \
+                       poly, self_coef, u)
+#define L_NEAR(ND)               \
+    if (sg == 1) {               \
+        L_NEAR_SG(ND, 1);        \
+    } else if (sg == 2) {        \
+        L_NEAR_SG(ND, 2);        \
+    } else {                     \
+        L_NEAR_SG(ND, 4);        \
+    }
     DMK_ND_DISPATCH(poly.nd, L_NEAR)
 #undef L_NEAR
+#undef L_NEAR_SG
 }
 
+template <int SG>
 __global__ __launch_bounds__(64) void k_near_count(const NearWork* __restrict__ work,
                                                    const NearLeaf* __restrict__ leaves,
                                                    const NearEntryDev* __restrict__ entries,
@@ -816,14 +895,23 @@ __global__ __launch_bounds__(64) void k_near_count(const NearWork* __restrict__ 
                                                    const double* __restrict__ y, const double* __restrict__ z,
                                                    unsigned long long* __restrict__ out)
 {
+    constexpr int TG = 64 / SG;
     const NearWork w = work[blockIdx.x];
     const NearLeaf T = leaves[w.leaf];
-    const int64_t i = T.tstart + (int64_t)w.chunk * 64 + threadIdx.x;
+    const int lane = threadIdx.x;
+    const int tl = lane / SG, sl = lane % SG;
+    const int64_t g0 = T.tstart + (int64_t)w.chunk * TG;
+    const int64_t i = g0 + tl;
     const bool valid = i < T.tend;
-    const int nt = (int)min((int64_t)64, T.tend - (T.tstart + (int64_t)w.chunk * 64));
+    const int nt = (int)min((int64_t)TG, T.tend - g0);
     const double xt = valid ? x[i] : 0.0, yt = valid ? y[i] : 0.0, zt = valid ? z[i] : 0.0;
-    const double* tb = cbbox + 6 * (size_t)(T.cbase + w.chunk);
-    const double tlo[3] = {tb[0], tb[1], tb[2]}, thi[3] = {tb[3], tb[4], tb[5]};
+    double tlo[3] = {valid ? xt : 1e300, valid ? yt : 1e300, valid ? zt : 1e300};
+    double thi[3] = {valid ? xt : -1e300, valid ? yt : -1e300, valid ? zt : -1e300};
+    for (int off = 32; off >= 1; off >>= 1)
+        for (int d = 0; d < 3; ++d) {
+            tlo[d] = fmin(tlo[d], __shfl_xor(tlo[d], off));
+            thi[d] = fmax(thi[d], __shfl_xor(thi[d], off));
+        }
     unsigned long long ev = 0, in = 0;
     for (int e = T.ebeg; e < T.eend; ++e) {
         const NearEntryDev E = entries[e];
@@ -842,9 +930,9 @@ __global__ __launch_bounds__(64) void k_near_count(const NearWork* __restrict__ 
                 continue;
             const int64_t s0 = E.sstart + 64 * (int64_t)k;
             const int64_t s1 = min(s0 + 64, E.send);
-            if (threadIdx.x == 0)
+            if (lane == 0)
                 ev += (unsigned long long)(s1 - s0) * nt;
-            for (int64_t j = s0; j < s1 && valid; ++j) {
+            for (int64_t j = s0 + sl; j < s1 && valid; j += SG) {
                 const double dx = xt - (x[j] + sh[0]), dy = yt - (y[j] + sh[1]), dz = zt - (z[j] + sh[2]);
                 const double r2 = dx * dx + dy * dy + dz * dz;
                 in += (r2 < rl2 && r2 > 0.0) ? 1ull : 0ull;
@@ -855,13 +943,18 @@ __global__ __launch_bounds__(64) void k_near_count(const NearWork* __restrict__ 
     atomicAdd(&out[1], in);
 }
 
-void launch_near_count(const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
+void launch_near_count(int sg, const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
                        const double* cbbox, const double* x, const double* y, const double* z,
                        unsigned long long* out, hipStream_t s)
 {
     if (nwork == 0)
         return;
-    hipLaunchKernelGGL(k_near_count, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, out);
+    if (sg == 1)
+        hipLaunchKernelGGL(k_near_count<1>, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, out);
+    else if (sg == 2)
+        hipLaunchKernelGGL(k_near_count<2>, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, out);
+    else
+        hipLaunchKernelGGL(k_near_count<4>, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, out);
 }
 
 template <int ND>

@@ -39,14 +39,21 @@ struct LeafDesc {
     double cx, cy, cz;
 };
 
-// proxy charges of leaves (Step 2a): Q[fid][j][a][b][c] = sum L_a L_b L_c f_j
-void launch_anterp(int p, const LeafDesc* leaves, int nleaf, const double* x, const double* y, const double* z,
-                   const double* fs, int64_t n, const double* cheb_t, const double* cheb_w, double* Q,
-                   hipStream_t s);
-// far-field value at the leaf's points (final interpolation): u[j][i] = sum V L L L,
-// V stored z-major: V[fid][j][c][b][a]
-void launch_leaf_eval(int p, const LeafDesc* leaves, int nleaf, const double* x, const double* y,
-                      const double* z, int64_t n, const double* cheb_t, const double* cheb_w, const double* V,
+// Lagrange values of each sorted point on its leaf's proxy grid:
+// Ltab[i][d][0..lagrange_pad(p)) for d = x, y, z (zero padded)
+int lagrange_pad(int p);
+void launch_lagrange_table(int p, const LeafDesc* leaves, int nleaf, const double* x, const double* y,
+                           const double* z, const double* cheb_t, const double* cheb_w, double* Ltab, hipStream_t s);
+// proxy charges of leaves (Step 2a): Q[fid][j][a][b][c] = sum_pt L_a L_b L_c f_j
+void launch_anterp(int p, const LeafDesc* leaves, int nleaf, const double* Ltab, const double* fs, int64_t n,
+                   double* Q, hipStream_t s);
+// far-field value at the points (final interpolation), V z-major V[fid][j][c][b][a]:
+// u[j][i] = sum V L L L, over chunks of at most 64 points of one leaf
+struct EvalChunk {
+    int fid;
+    int64_t start, end;
+};
+void launch_leaf_eval(int p, const EvalChunk* chunks, int nchunk, const double* Ltab, const double* V, int64_t n,
                       double* u, hipStream_t s);
 
 // ---- separable tensor stages ------------------------------------------------
@@ -108,7 +115,7 @@ struct NearEntryDev {
 };
 struct NearWork {
     int leaf;
-    int chunk;        // chunk index within the leaf
+    int chunk;        // target group index within the leaf (groups of 64/sg points)
 };
 // P and Q as monomials in t = 2s - 1, both padded with zero leading
 // coefficients to nd terms (nd <= 24)
@@ -116,12 +123,13 @@ struct RadialPoly {
     int nd;
     double P[24], Q[24];
 };
-void launch_near(const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
+// sg: source lanes per target (1, 2, 4); a wave holds 64/sg targets
+void launch_near(int sg, const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
                  const double* cbbox, const double* x, const double* y, const double* z, const double* fs,
                  int64_t n, const RadialPoly& poly, double self_coef, double* u, hipStream_t s);
 
 // pair counts of the near field: out[0] += evaluated pairs, out[1] += pairs in support
-void launch_near_count(const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
+void launch_near_count(int sg, const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
                        const double* cbbox, const double* x, const double* y, const double* z,
                        unsigned long long* out, hipStream_t s);
 
