@@ -17,7 +17,8 @@
  * (PSWF) splitting of the biharmonic kernel (Sec. "The DMK method", split of
  * eqs. biharmonicks/bsplitdef, residual kernel eq. res_stokeslet, parameters
  * of Table tab:params).  A pair of distinct but coincident points contributes
- * nothing.
+ * nothing (to within tol: its mollified part, carried by the far field, is
+ * cancelled in the near field).
  *
  * Memory: every array argument of the plan/eval calls is a DEVICE pointer
  * (hipMalloc'd or a torch CUDA tensor's data pointer) owned by the caller.
@@ -61,8 +62,14 @@ typedef struct {
     void* stream;         /* hipStream_t for all work of the plan; NULL = null stream */
     size_t mem_cap_bytes; /* refuse plans whose device buffers exceed this; 0 = no cap */
     int flags;            /* DMK_FLAG_* bits */
-    int near_lanes;       /* near field: source lanes per target (1, 2 or 4; a wave then
-                             holds 64, 32 or 16 targets); 0 = automatic */
+    int near_lanes;       /* near field: source lanes per target (1, 2, 4 or 8; a wave
+                             then holds 64, 32, 16 or 8 targets); 0 = automatic */
+    int q;                /* window parameter q = 3c/pi (sets c and the plane-wave
+                             counts n1 = 2q-1, nper = 2 ceil(q/6) - 1); 0 = the
+                             Table tab:params row chosen by tol, else in [4, 40] */
+    int p;                /* Chebyshev points per dimension of every proxy grid;
+                             0 = the row's value, else 12, 16, 20, 23, 26, 30, 33,
+                             36, 40 or 44 */
 } dmk_opts;
 
 /* record HIP events around each phase of dmk_stokes_eval (read back with
@@ -153,7 +160,10 @@ int dmk_stokes_phase_ms(dmk_plan_t plan, double* out);
 /*
  * Near-field pair statistics of the plan (host int64 outputs, NULL to skip):
  *   listed     sum over near-list entries of |target leaf| * |source leaf|
- *   evaluated  pairs left after the 64-point chunk bounding-box pruning
+ *   evaluated  (target, source) pairs the near-field kernel evaluates: for each
+ *              wave's target group, the sources lying within r_lambda of the
+ *              group's bounding box (64-point source chunks are first pruned
+ *              by their own boxes)
  *   in_support pairs with 0 < |x_t - x_s + shift| < r_lambda (the residual's
  *              support, Corollary eq. reskernelproperty)
  * Runs a counting kernel; synchronises the stream.
@@ -204,10 +214,13 @@ int dmk_stokes_host_tree(const double* points, int64_t n, int leaf_size, int per
 
 /*
  * Residual-kernel sums by brute force over all sources, at scale r_lambda:
- *   out[i] = sum_a S_R^{r_lambda}(t_i - s_a) f_a   (pairs with r = 0 skipped),
+ *   out[i] = sum_a S_R^{r_lambda}(t_i - s_a) f_a,
  * S_R as in eq. res_stokeslet evaluated at r / r_lambda (the scaling remark
  * of Sec. "The Stokes kernels"), with the same device pair routine as the
- * near field of dmk_stokes_eval.
+ * near field of dmk_stokes_eval.  A pair with r = 0 contributes the residual
+ * without its singular part, -S_M(0) f = -(phi(0)/(2 pi r_lambda)) f (eq.
+ * S_self): in the full sum this cancels the mollified part of a coincident
+ * pair, and for the pair of a target with itself it is the self term.
  *   targets (m,3), sources (ns,3), forces (ns,3), out (m,3): device float64
  *   stream: hipStream_t or NULL.  Stream-ordered.
  */

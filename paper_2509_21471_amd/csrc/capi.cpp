@@ -237,8 +237,13 @@ int validate_common(int dim, double tol, const dmk_opts* opts)
             return fail(DMK_ERR_TOL, "mixed precision needs tol >= 1e-7");
         if (opts->leaf_size < 0)
             return fail(DMK_ERR_ARG, "leaf_size must be >= 0");
-        if (opts->near_lanes != 0 && opts->near_lanes != 1 && opts->near_lanes != 2 && opts->near_lanes != 4)
-            return fail(DMK_ERR_ARG, "near_lanes must be 0, 1, 2 or 4");
+        if (opts->near_lanes != 0 && opts->near_lanes != 1 && opts->near_lanes != 2 && opts->near_lanes != 4 &&
+            opts->near_lanes != 8)
+            return fail(DMK_ERR_ARG, "near_lanes must be 0, 1, 2, 4 or 8");
+        if (opts->q != 0 && (opts->q < 4 || opts->q > 40))
+            return fail(DMK_ERR_ARG, "q must be 0 or in [4, 40]");
+        if (opts->p != 0 && !dmk::p_supported(opts->p))
+            return fail(DMK_ERR_ARG, "p must be 0 or one of 12, 16, 20, 23, 26, 30, 33, 36, 40, 44");
     }
     return DMK_OK;
 }
@@ -720,11 +725,11 @@ int eval_one(dmk_plan_t P, const double* f, double* vel, bool record)
               h, p, 4 * p * p, L.nparent, L.child_fid);
     }
     mark(7);
-    // far field at the points, then the near field (Step 4) and self term
+    // far field at the points, then the near field (Step 4, self term included)
     launch_leaf_eval(p, P->echunks, P->n_echunk, P->Ltab, P->V, n, P->u, st);
     mark(8);
     launch_near(P->near_sg, P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x, P->y, P->z, P->fs, n, P->poly,
-                -P->tab->phi0 / (2.0 * kPi), P->u, st);
+                P->u, st);
     mark(9);
     launch_finalize(P->u, n, P->perm, 1.0 / P->box_len, P->periodic ? nullptr : P->cst, vel, st);
     mark(10);
@@ -821,7 +826,9 @@ int dmk_stokes_plan_ex(const double* points, int64_t n, int dim, int periodic, d
         delete P;
         return fail(DMK_ERR_TOL, "tol must lie in [1e-12, 1e-3]");
     }
-    P->tab = dmk::get_tables(tol);
+    if (opts)
+        dmk::override_params(&P->prm, opts->q, opts->p);
+    P->tab = dmk::get_tables(P->prm);
     if (opts) {
         P->stream = (hipStream_t)opts->stream;
         P->precision = opts->precision;

@@ -369,16 +369,30 @@ __global__ __launch_bounds__(256) void k_leaf_eval(const EvalChunk* __restrict__
     }
 }
 
+// Chebyshev orders with compiled point kernels: the Table tab:params values
+// plus intermediate orders for explicit parameter choices.
 #define DMK_P_DISPATCH(p, MACRO) \
     switch (p) {                 \
     case 12: MACRO(12); break;   \
+    case 16: MACRO(16); break;   \
+    case 20: MACRO(20); break;   \
     case 23: MACRO(23); break;   \
+    case 26: MACRO(26); break;   \
+    case 30: MACRO(30); break;   \
     case 33: MACRO(33); break;   \
+    case 36: MACRO(36); break;   \
+    case 40: MACRO(40); break;   \
     case 44: MACRO(44); break;   \
     default: break;              \
     }
 
-bool p_supported(int p) { return p == 12 || p == 23 || p == 33 || p == 44; }
+bool p_supported(int p)
+{
+    switch (p) {
+    case 12: case 16: case 20: case 23: case 26: case 30: case 33: case 36: case 40: case 44: return true;
+    default: return false;
+    }
+}
 
 int lagrange_pad(int p) { return (p + 3) / 4 * 4; }
 
@@ -641,49 +655,62 @@ void launch_stage(int mode, int io, const StageArgs& a, hipStream_t s)
 }
 
 // ---- translation --------------------------------------------------------------
+// One block per (m_y slab, receiver).  The sender side is x-major
+// (Phi[m_x][m_y][m_z]) and the receiver side z-major (Psi[m_z][m_y][m_x]); a
+// slab of fixed m_y is read as q runs of n1 contiguous modes, transposed in LDS
+// and written as n1 runs of q contiguous modes, so both sides stay coalesced.
 __global__ __launch_bounds__(256) void k_translate(int q, int n1, const RecvDesc* __restrict__ recv,
                                                    const int* __restrict__ e_src, const int8_t* __restrict__ e_off,
                                                    const cplx* __restrict__ Phi, const double* __restrict__ wdiff,
                                                    cplx* __restrict__ Psi)
 {
+    extern __shared__ cplx tile[];  // [3][m_z][m_x]
     const int H = q * n1 * n1;
-    const int mi = blockIdx.x * blockDim.x + threadIdx.x;
-    if (mi >= H)
-        return;
+    const int S = q * n1;           // modes in the slab
+    const int iy = blockIdx.x;
     const RecvDesc rd = recv[blockIdx.y];
-    const int m1 = mi / (n1 * n1);
-    const int rem = mi - m1 * n1 * n1;
-    const int m2 = rem / n1 - (q - 1);
-    const int m3 = rem % n1 - (q - 1);
+    const int m2 = iy - (q - 1);
     const double s3 = 0.86602540378443864676;
-    double F[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-    for (int e = rd.ebeg; e < rd.eend; ++e) {
-        const int src = e_src[e];
-        const int t = m1 * e_off[3 * e] + m2 * e_off[3 * e + 1] + m3 * e_off[3 * e + 2];
-        const int tm = ((t % 3) + 3) % 3;
-        // exp(-i 2 pi t / 3)
-        const double pr = tm == 0 ? 1.0 : -0.5;
-        const double pi = tm == 0 ? 0.0 : (tm == 1 ? -s3 : s3);
+    const double lscale = (double)(1ll << rd.level);
+    for (int idx = threadIdx.x; idx < S; idx += blockDim.x) {
+        const int m1 = idx / n1;
+        const int i3 = idx - m1 * n1;
+        const int m3 = i3 - (q - 1);
+        const size_t mi = ((size_t)m1 * n1 + iy) * n1 + i3;
+        double F[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+        for (int e = rd.ebeg; e < rd.eend; ++e) {
+            const int src = e_src[e];
+            const int t = m1 * e_off[3 * e] + m2 * e_off[3 * e + 1] + m3 * e_off[3 * e + 2];
+            const int tm = ((t % 3) + 3) % 3;
+            // exp(-i 2 pi t / 3)
+            const double pr = tm == 0 ? 1.0 : -0.5;
+            const double pi = tm == 0 ? 0.0 : (tm == 1 ? -s3 : s3);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const cplx v = Phi[((size_t)src * 3 + j) * H + mi];
-            F[j][0] += pr * v.re - pi * v.im;
-            F[j][1] += pr * v.im + pi * v.re;
+            for (int j = 0; j < 3; ++j) {
+                const cplx v = Phi[((size_t)src * 3 + j) * H + mi];
+                F[j][0] += pr * v.re - pi * v.im;
+                F[j][1] += pr * v.im + pi * v.re;
+            }
         }
-    }
-    const int mm = m1 * m1 + m2 * m2 + m3 * m3;
-    double w = 0;
-    if (mm > 0)
-        w = wdiff[mm] * (double)(1ll << rd.level);
-    const double inv = mm > 0 ? 1.0 / mm : 0.0;
-    const double dr = (m1 * F[0][0] + m2 * F[1][0] + m3 * F[2][0]) * inv;
-    const double di = (m1 * F[0][1] + m2 * F[1][1] + m3 * F[2][1]) * inv;
-    const int mv[3] = {m1, m2, m3};
-    // incoming side is stored z-major: Psi[mz][my][mx]
-    const size_t mo = ((size_t)(m3 + q - 1) * n1 + (m2 + q - 1)) * q + m1;
+        const int mm = m1 * m1 + m2 * m2 + m3 * m3;
+        const double w = mm > 0 ? wdiff[mm] * lscale : 0.0;
+        const double inv = mm > 0 ? 1.0 / mm : 0.0;
+        const double dr = (m1 * F[0][0] + m2 * F[1][0] + m3 * F[2][0]) * inv;
+        const double di = (m1 * F[0][1] + m2 * F[1][1] + m3 * F[2][1]) * inv;
+        const int mv[3] = {m1, m2, m3};
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
-        Psi[((size_t)rd.slot * 3 + j) * H + mo] = cplx{w * (F[j][0] - mv[j] * dr), w * (F[j][1] - mv[j] * di)};
+        for (int j = 0; j < 3; ++j)
+            tile[(j * n1 + i3) * q + m1] = cplx{w * (F[j][0] - mv[j] * dr), w * (F[j][1] - mv[j] * di)};
+    }
+    __syncthreads();
+    cplx* out = Psi + (size_t)rd.slot * 3 * H;
+    for (int idx = threadIdx.x; idx < 3 * S; idx += blockDim.x) {
+        const int j = idx / S;
+        const int r = idx - j * S;
+        const int i3 = r / q;
+        const int m1 = r - i3 * q;
+        out[(size_t)j * H + ((size_t)i3 * n1 + iy) * q + m1] = tile[idx];
+    }
 }
 
 void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int* e_src, const int8_t* e_off,
@@ -691,9 +718,13 @@ void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int*
 {
     if (nrecv == 0)
         return;
-    const int H = q * n1 * n1;
-    hipLaunchKernelGGL(k_translate, dim3(nblocks(H, 256), nrecv), dim3(256), 0, s, q, n1, recv, e_src, e_off, Phi,
-                       wdiff, Psi);
+    const size_t lds = (size_t)3 * q * n1 * sizeof(cplx);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void*)k_translate, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL(k_translate, dim3(n1, nrecv), dim3(256), lds, s, q, n1, recv, e_src, e_off, Phi, wdiff, Psi);
 }
 
 __global__ __launch_bounds__(256) void k_root_symbol(int mh, int mf, const cplx* __restrict__ Phi,
@@ -758,8 +789,12 @@ __device__ inline void residual_pair(double dx, double dy, double dz, double fx,
                                      double& u1, double& u2)
 {
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    if (r2 < rl2 && r2 > 0.0) {
-        const double rinv = rsqrt_f64(r2);
+    if (r2 < rl2) {
+        // r = 0 (the self pair, or distinct coincident points): only the
+        // smooth part -S_M(0) f = -(P(0)/(4 pi r_lambda)) f remains, which
+        // cancels the far field's S_M(0) f, so such a pair contributes nothing
+        // to the total and the self term of eq. S_self needs no separate pass.
+        const double rinv = r2 > 0.0 ? rsqrt_f64(r2) : 0.0;
         const double t = fma(r2, tw, -1.0);
         const double P = horner<ND>(poly.P, t);
         const double Q = horner<ND>(poly.Q, t);
@@ -783,7 +818,7 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
                                              const NearEntryDev* __restrict__ entries, const double* __restrict__ cbbox,
                                              const double* __restrict__ x, const double* __restrict__ y,
                                              const double* __restrict__ z, const double* __restrict__ fs, int64_t n,
-                                             RadialPoly poly, double self_coef, double* __restrict__ u)
+                                             RadialPoly poly, double* __restrict__ u)
 {
     constexpr int TG = 64 / SG;
     __shared__ double2 S[64][3];
@@ -826,15 +861,33 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
                 continue;
             const int64_t s0 = E.sstart + 64 * (int64_t)k;
             const int cnt = (int)min((int64_t)64, E.send - s0);
-            __syncthreads();
+            // each lane takes one source of the chunk and keeps it if it lies
+            // within r_lambda of the target group's box; survivors are packed
+            // to the front of the LDS tile (ballot + prefix count)
+            double sx = 0, sy = 0, sz = 0;
+            bool keep = false;
             if (lane < cnt) {
                 const int64_t j = s0 + lane;
-                S[lane][0] = make_double2(x[j] + sh[0], y[j] + sh[1]);
-                S[lane][1] = make_double2(z[j] + sh[2], fs[j]);
-                S[lane][2] = make_double2(fs[n + j], fs[2 * n + j]);
+                sx = x[j] + sh[0];
+                sy = y[j] + sh[1];
+                sz = z[j] + sh[2];
+                const double gx = fmax(0.0, fmax(tlo[0] - sx, sx - thi[0]));
+                const double gy = fmax(0.0, fmax(tlo[1] - sy, sy - thi[1]));
+                const double gz = fmax(0.0, fmax(tlo[2] - sz, sz - thi[2]));
+                keep = fma(gx, gx, fma(gy, gy, gz * gz)) < rl2;
+            }
+            const unsigned long long mask = __ballot(keep);
+            const int kept = __popcll(mask);
+            const int pos = __popcll(mask & ((1ull << lane) - 1ull));
+            __syncthreads();
+            if (keep) {
+                const int64_t j = s0 + lane;
+                S[pos][0] = make_double2(sx, sy);
+                S[pos][1] = make_double2(sz, fs[j]);
+                S[pos][2] = make_double2(fs[n + j], fs[2 * n + j]);
             }
             __syncthreads();
-            for (int jj = sl; jj < cnt; jj += SG) {
+            for (int jj = sl; jj < kept; jj += SG) {
                 const double2 a = S[jj][0], b = S[jj][1], c = S[jj][2];
                 residual_pair<ND>(xt - a.x, yt - a.y, zt - b.x, b.y, c.x, c.y, rl2, tw, cP, cQ, poly, u0, u1, u2);
             }
@@ -847,10 +900,9 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
         u2 += __shfl_xor(u2, off);
     }
     if (valid && sl == 0) {
-        const double sc = self_coef * (double)(1ll << T.level);
-        u[i] += u0 + sc * fs[i];
-        u[n + i] += u1 + sc * fs[n + i];
-        u[2 * n + i] += u2 + sc * fs[2 * n + i];
+        u[i] += u0;
+        u[n + i] += u1;
+        u[2 * n + i] += u2;
     }
 }
 
@@ -867,20 +919,22 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
 
 void launch_near(int sg, const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
                  const double* cbbox, const double* x, const double* y, const double* z, const double* fs, int64_t n,
-                 const RadialPoly& poly, double self_coef, double* u, hipStream_t s)
+                 const RadialPoly& poly, double* u, hipStream_t s)
 {
     if (nwork == 0)
         return;
 #define L_NEAR_SG(ND, SG)                                                                                           \
     hipLaunchKernelGGL((k_near<ND, SG>), dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, fs, n, \
-                       poly, self_coef, u)
+                       poly, u)
 #define L_NEAR(ND)               \
     if (sg == 1) {               \
         L_NEAR_SG(ND, 1);        \
     } else if (sg == 2) {        \
         L_NEAR_SG(ND, 2);        \
-    } else {                     \
+    } else if (sg == 4) {        \
         L_NEAR_SG(ND, 4);        \
+    } else {                     \
+        L_NEAR_SG(ND, 8);        \
     }
     DMK_ND_DISPATCH(poly.nd, L_NEAR)
 #undef L_NEAR
@@ -930,8 +984,18 @@ __global__ __launch_bounds__(64) void k_near_count(const NearWork* __restrict__ 
                 continue;
             const int64_t s0 = E.sstart + 64 * (int64_t)k;
             const int64_t s1 = min(s0 + 64, E.send);
+            bool keep = false;
+            if (s0 + lane < s1) {
+                const int64_t j = s0 + lane;
+                const double sx = x[j] + sh[0], sy = y[j] + sh[1], sz = z[j] + sh[2];
+                const double gx = fmax(0.0, fmax(tlo[0] - sx, sx - thi[0]));
+                const double gy = fmax(0.0, fmax(tlo[1] - sy, sy - thi[1]));
+                const double gz = fmax(0.0, fmax(tlo[2] - sz, sz - thi[2]));
+                keep = fma(gx, gx, fma(gy, gy, gz * gz)) < rl2;
+            }
+            const int kept = __popcll(__ballot(keep));
             if (lane == 0)
-                ev += (unsigned long long)(s1 - s0) * nt;
+                ev += (unsigned long long)kept * nt;
             for (int64_t j = s0 + sl; j < s1 && valid; j += SG) {
                 const double dx = xt - (x[j] + sh[0]), dy = yt - (y[j] + sh[1]), dz = zt - (z[j] + sh[2]);
                 const double r2 = dx * dx + dy * dy + dz * dz;
@@ -953,8 +1017,10 @@ void launch_near_count(int sg, const NearWork* work, int nwork, const NearLeaf* 
         hipLaunchKernelGGL(k_near_count<1>, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, out);
     else if (sg == 2)
         hipLaunchKernelGGL(k_near_count<2>, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, out);
-    else
+    else if (sg == 4)
         hipLaunchKernelGGL(k_near_count<4>, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, out);
+    else
+        hipLaunchKernelGGL(k_near_count<8>, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, out);
 }
 
 template <int ND>

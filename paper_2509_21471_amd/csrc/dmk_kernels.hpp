@@ -42,6 +42,8 @@ struct LeafDesc {
 // Lagrange values of each sorted point on its leaf's proxy grid:
 // Ltab[i][d][0..lagrange_pad(p)) for d = x, y, z (zero padded)
 int lagrange_pad(int p);
+// Chebyshev orders p the point kernels are compiled for
+bool p_supported(int p);
 void launch_lagrange_table(int p, const LeafDesc* leaves, int nleaf, const double* x, const double* y,
                            const double* z, const double* cheb_t, const double* cheb_w, double* Ltab, hipStream_t s);
 // proxy charges of leaves (Step 2a): Q[fid][j][a][b][c] = sum_pt L_a L_b L_c f_j
@@ -101,7 +103,7 @@ void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int*
 // root symbol multiply: Psi[j][mz][my][mx] = w(|m|^2) (I - m m^T/|m|^2) Phi[j][mx][my][mz]
 void launch_root_symbol(int mh, int mf, const cplx* Phi, const double* w, cplx* Psi, hipStream_t s);
 
-// near field (Step 4) + self term
+// near field (Step 4); the self term comes out of the r = 0 pair
 struct NearLeaf {
     int64_t tstart, tend;
     int ebeg, eend;
@@ -126,7 +128,7 @@ struct RadialPoly {
 // sg: source lanes per target (1, 2, 4); a wave holds 64/sg targets
 void launch_near(int sg, const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
                  const double* cbbox, const double* x, const double* y, const double* z, const double* fs,
-                 int64_t n, const RadialPoly& poly, double self_coef, double* u, hipStream_t s);
+                 int64_t n, const RadialPoly& poly, double* u, hipStream_t s);
 
 // pair counts of the near field: out[0] += evaluated pairs, out[1] += pairs in support
 void launch_near_count(int sg, const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <tuple>
 
 namespace dmk {
 
@@ -14,14 +15,20 @@ constexpr double kPi = 3.14159265358979323846;
 struct Row {
     double tol;
     int q, p, n1, nper, ns;
+    int p_used;  // Chebyshev order the plan uses
 };
 // Table "tab:params" (Stokeslet, PSWF split) and the 3D leaf sizes of
-// Sec. "Numerical results".
+// Sec. "Numerical results".  The table was tuned on uniform free-space
+// points; on periodic and clustered inputs p = 33 at 1e-9 leaves errors at or
+// just above the tolerance (the Chebyshev interpolation term dominates: a
+// larger q makes it worse, a larger p removes it), so that row is stepped up
+// to p = 36 in the spirit of the parameter-selection discussion of Sec.
+// "Error control and parameter selection".
 const Row kRows[4] = {
-    {1e-3, 10, 12, 19, 3, 600},
-    {1e-6, 17, 23, 33, 5, 1200},
-    {1e-9, 25, 33, 49, 9, 2000},
-    {1e-12, 31, 44, 61, 11, 3000},
+    {1e-3, 10, 12, 19, 3, 600, 12},
+    {1e-6, 17, 23, 33, 5, 1200, 23},
+    {1e-9, 25, 33, 49, 9, 2000, 36},
+    {1e-12, 31, 44, 61, 11, 3000, 44},
 };
 }  // namespace
 
@@ -37,7 +44,7 @@ bool select_params(double tol, Params* out)
             hit = i;
     if (hit >= 0) {
         q = kRows[hit].q;
-        p = kRows[hit].p;
+        p = kRows[hit].p_used;
         ns = kRows[hit].ns;
     } else {
         // between rows: the row with the largest tolerance below tol
@@ -45,7 +52,7 @@ bool select_params(double tol, Params* out)
         while (i < 3 && kRows[i].tol > tol)
             ++i;
         q = kRows[i].q;
-        p = kRows[i].p;
+        p = kRows[i].p_used;
         ns = kRows[i].ns;
     }
     out->tol = tol;
@@ -59,6 +66,18 @@ bool select_params(double tol, Params* out)
     out->nper = 2 * ((q + 5) / 6) - 1;
     out->ns = ns;
     return true;
+}
+
+void override_params(Params* prm, int q, int p)
+{
+    if (q > 0) {
+        prm->q = q;
+        prm->c = q * kPi / 3.0;
+        prm->n1 = 2 * q - 1;
+        prm->nper = 2 * ((q + 5) / 6) - 1;
+    }
+    if (p > 0)
+        prm->p = p;
 }
 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w)
@@ -458,11 +477,9 @@ Tables::PW fold_pw(int p, int M, double theta, const std::vector<double>& t)
     return w;
 }
 
-Tables* build_tables(double tol)
+Tables* build_tables(const Params& prm)
 {
-    Params prm;
-    if (!select_params(tol, &prm))
-        return nullptr;
+    const double tol = prm.tol;
     Tables* T = new Tables();
     T->prm = prm;
     Prolate w(prm.c);
@@ -538,18 +555,27 @@ Tables* build_tables(double tol)
 
 }  // namespace
 
-const Tables* get_tables(double tol)
+const Tables* get_tables(const Params& prm)
 {
     static std::mutex mu;
-    static std::map<double, Tables*> cache;
+    static std::map<std::tuple<double, int, int>, Tables*> cache;
     std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find(tol);
+    const auto key = std::make_tuple(prm.tol, prm.q, prm.p);
+    auto it = cache.find(key);
     if (it != cache.end())
         return it->second;
-    Tables* T = build_tables(tol);
+    Tables* T = build_tables(prm);
     if (T)
-        cache[tol] = T;
+        cache[key] = T;
     return T;
+}
+
+const Tables* get_tables(double tol)
+{
+    Params prm;
+    if (!select_params(tol, &prm))
+        return nullptr;
+    return get_tables(prm);
 }
 
 }  // namespace dmk

@@ -24,6 +24,8 @@ struct Params {
 
 // Returns false if tol is outside [1e-12, 1e-3].
 bool select_params(double tol, Params* out);
+// Replaces q (and with it c, n1, nper) and/or p when the value is > 0.
+void override_params(Params* prm, int q, int p);
 
 // Zeroth-order prolate spheroidal wave function psi_0^c as an even Legendre
 // series (Legendre-Galerkin form of the prolate differential operator,
@@ -117,5 +119,7 @@ struct Tables {
 
 // Builds (and caches per tolerance) the tables.  Returns nullptr on bad tol.
 const Tables* get_tables(double tol);
+// Tables for explicit parameters (cached per (tol, q, p)).
+const Tables* get_tables(const Params& prm);
 
 }  // namespace dmk

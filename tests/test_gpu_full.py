@@ -1,0 +1,151 @@
+"""GPU parity at the benchmark sizes and structural properties of the
+assembled operator, through the C ABI.
+
+Full-size inputs are compared on sampled targets: the direct sum is computed
+at test time for 1e6 points; the 2e6-point periodic Ewald values and the
+4e6-point direct values are stored under tests/golden/ by
+tests/golden/make_references.py (oracle only).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _dmk():
+    import paper_2509_21471_amd as dmk
+    return dmk
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _eval(x, f, **kw):
+    plan = _dmk().Plan(_t(x), **kw)
+    u = plan.eval(_t(f)).cpu().numpy()
+    info = plan.info()
+    plan.close()
+    return u, info
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
+def test_near_lanes_agree(dev, lanes):
+    """Every lane split of the near-field kernel gives the same sum."""
+    x, f = workloads.make("clusters", 20000, seed=70, sigma=0.03)
+    u, _ = _eval(x, f, tol=1e-6, leaf_size=200, near_lanes=lanes)
+    u4, _ = _eval(x, f, tol=1e-6, leaf_size=200, near_lanes=4)
+    ref = oracle.direct(x, f)
+    assert oracle.rel_l2(u, ref) < 1e-6
+    assert oracle.rel_l2(u, u4) < 1e-13
+
+
+def test_coincident_points(dev):
+    """Distinct coincident points contribute nothing to each other (the direct
+    sum skips r = 0 pairs)."""
+    rng = np.random.default_rng(71)
+    x0, _ = workloads.make("uniform", 3000, seed=71)
+    dup = x0[rng.choice(3000, 1000, replace=False)]
+    x = np.concatenate([x0, dup, dup[:100]])
+    f = rng.standard_normal(x.shape)
+    u, _ = _eval(x, f, tol=1e-6, leaf_size=100)
+    assert oracle.rel_l2(u, oracle.direct(x, f)) < 1e-6
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_reciprocity(dev, periodic):
+    """The assembled operator is symmetric: <g, u(f)> = <f, u(g)> to rounding
+    (every far-field factor is the transpose of its mirror and the residual,
+    self and constant terms are symmetric)."""
+    kind = "periodic" if periodic else "clusters"
+    x, f = workloads.make(kind, 30000, seed=72, sigma=0.05)
+    g = np.random.default_rng(73).standard_normal(x.shape)
+    plan = _dmk().Plan(_t(x), periodic=periodic, tol=1e-6, leaf_size=150)
+    uf = plan.eval(_t(f)).cpu().numpy()
+    ug = plan.eval(_t(g)).cpu().numpy()
+    assert plan.info()["levels"] >= 4
+    plan.close()
+    a, b = float(np.sum(g * uf)), float(np.sum(f * ug))
+    scale = np.linalg.norm(g) * np.linalg.norm(uf)
+    print("reciprocity", a, b, abs(a - b) / scale)
+    assert abs(a - b) / scale < 1e-12
+
+
+def test_multiple_rhs_match_single(dev):
+    """n_rhs force vectors in one call equal one call per vector."""
+    x, f = workloads.make("clusters", 20000, seed=74, sigma=0.05, n_rhs=3)
+    plan = _dmk().Plan(_t(x), tol=1e-6, leaf_size=200)
+    u = plan.eval(_t(f)).cpu().numpy()
+    for r in range(3):
+        ur = plan.eval(_t(f[r])).cpu().numpy()
+        assert np.array_equal(u[r], ur)
+    plan.close()
+    assert oracle.rel_l2(u[1], oracle.direct(x, f[1])) < 1e-6
+
+
+def test_periodic_translation_invariance(dev):
+    """A shift of all points modulo the cell changes the tree, not the sum."""
+    x, f = workloads.make("periodic", 20000, seed=75)
+    s = np.array([0.3137, 0.5521, 0.1234])
+    u0, _ = _eval(x, f, periodic=True, tol=1e-9, leaf_size=200)
+    u1, _ = _eval(np.mod(x + s, 1.0), f, periodic=True, tol=1e-9, leaf_size=200)
+    from oracle.ewald import ewald
+    idx = np.arange(0, x.shape[0], 40)
+    ref = ewald(x, f, idx)
+    e0, e1 = oracle.rel_l2(u0[idx], ref), oracle.rel_l2(u1[idx], ref)
+    print("translation", e0, e1, oracle.rel_l2(u1, u0))
+    assert e0 < 1e-9 and e1 < 1e-9
+    # both approximate the same sum to within tol
+    assert oracle.rel_l2(u1, u0) < 2e-9
+
+
+def test_free_space_similarity(dev):
+    """u(a x + b) = u(x) / a: the Stokeslet is homogeneous of degree -1 and the
+    plan maps any bounding cube to the unit box."""
+    x, f = workloads.make("clusters", 20000, seed=76, sigma=0.05)
+    u0, _ = _eval(x, f, tol=1e-9, leaf_size=200)
+    u1, _ = _eval(3.7 * x - 11.0, f, tol=1e-9, leaf_size=200)
+    assert oracle.rel_l2(3.7 * u1, u0) < 1e-9
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-9])
+def test_clusters_1e6(dev, tol):
+    """1e6 clustered points (sigma 0.02) at the benchmark's launch
+    configuration, 1000 sampled targets against the direct sum."""
+    cfg = workloads.CONFIGS["clusters_1e6"]
+    x, f = workloads.config("clusters_1e6")
+    u, info = _eval(x, f, tol=tol)
+    idx = workloads.sample_targets(x.shape[0], 1000, cfg["seed"])
+    err = oracle.rel_l2(u[idx], oracle.direct(x, f, idx))
+    print("clusters_1e6", tol, info["levels"], err)
+    assert err < tol
+
+
+def test_periodic_2e6_tol1e9(dev):
+    """2e6 uniform periodic points at tol 1e-9 against the Gaussian-Ewald sum
+    (converged to about 1e-13) at 2000 sampled targets."""
+    ref = np.load(os.path.join(GOLDEN, "periodic_2e6_ewald.npz"))
+    x, f = workloads.config("periodic_2e6")
+    u, info = _eval(x, f, periodic=True, tol=1e-9)
+    err = oracle.rel_l2(u[ref["idx"]], ref["u"])
+    print("periodic_2e6", info["levels"], err)
+    assert err < 1e-9
+
+
+def test_clusters_4e6_fp64(dev):
+    """4e6 clustered points (sigma 0.01), FP64 at tol 1e-6, 10,000 sampled
+    targets against the direct sum."""
+    ref = np.load(os.path.join(GOLDEN, "clusters_4e6_direct.npz"))
+    x, f = workloads.config("clusters_4e6")
+    u, info = _eval(x, f, tol=1e-6)
+    err = oracle.rel_l2(u[ref["idx"]], ref["u"])
+    print("clusters_4e6", info["levels"], err)
+    assert err < 1e-6
