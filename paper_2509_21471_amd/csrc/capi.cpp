@@ -530,6 +530,9 @@ int build_plan(dmk_plan_t P, const double* points)
             nent.push_back(d);
         }
         L.eend = (int)nent.size();
+        // the near-field kernel restarts its source queue when lambda changes
+        std::stable_sort(nent.begin() + L.ebeg, nent.end(),
+                         [](const NearEntryDev& a, const NearEntryDev& b) { return a.lambda < b.lambda; });
         const int tg = 64 / P->near_sg;
         const int nch = (int)((B.end - B.start + tg - 1) / tg);
         for (int c = 0; c < nch; ++c)

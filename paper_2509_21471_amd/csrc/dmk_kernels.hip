@@ -659,7 +659,7 @@ void launch_stage(int mode, int io, const StageArgs& a, hipStream_t s)
 // (Phi[m_x][m_y][m_z]) and the receiver side z-major (Psi[m_z][m_y][m_x]); a
 // slab of fixed m_y is read as q runs of n1 contiguous modes, transposed in LDS
 // and written as n1 runs of q contiguous modes, so both sides stay coalesced.
-__global__ __launch_bounds__(256) void k_translate(int q, int n1, const RecvDesc* __restrict__ recv,
+__global__ __launch_bounds__(256) void k_translate(int q, int n1, int nrecv, const RecvDesc* __restrict__ recv,
                                                    const int* __restrict__ e_src, const int8_t* __restrict__ e_off,
                                                    const cplx* __restrict__ Phi, const double* __restrict__ wdiff,
                                                    cplx* __restrict__ Psi)
@@ -667,8 +667,17 @@ __global__ __launch_bounds__(256) void k_translate(int q, int n1, const RecvDesc
     extern __shared__ cplx tile[];  // [3][m_z][m_x]
     const int H = q * n1 * n1;
     const int S = q * n1;           // modes in the slab
-    const int iy = blockIdx.x;
-    const RecvDesc rd = recv[blockIdx.y];
+    // Blocks go round-robin over the 8 XCDs; give each XCD a contiguous run
+    // of (slab, receiver) pairs with the receiver fastest, so that receivers
+    // adjacent in Morton order -- which share most of their colleagues -- read
+    // the same sender slabs through the same L2.
+    const int total = n1 * nrecv;
+    const int per = (total + 7) / 8;
+    const int lg = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (lg >= total)
+        return;
+    const int iy = lg / nrecv;
+    const RecvDesc rd = recv[lg - iy * nrecv];
     const int m2 = iy - (q - 1);
     const double s3 = 0.86602540378443864676;
     const double lscale = (double)(1ll << rd.level);
@@ -724,7 +733,9 @@ void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int*
         (void)hipFuncSetAttribute((const void*)k_translate, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL(k_translate, dim3(n1, nrecv), dim3(256), lds, s, q, n1, recv, e_src, e_off, Phi, wdiff, Psi);
+    const int total = n1 * nrecv;
+    hipLaunchKernelGGL(k_translate, dim3(((total + 7) / 8) * 8), dim3(256), lds, s, q, n1, nrecv, recv, e_src, e_off,
+                       Phi, wdiff, Psi);
 }
 
 __global__ __launch_bounds__(256) void k_root_symbol(int mh, int mf, const cplx* __restrict__ Phi,
@@ -809,10 +820,14 @@ __device__ inline void residual_pair(double dx, double dy, double dz, double fx,
 }
 
 // One wave per target group of TG = 64/SG points of a leaf; lane (t, s) handles
-// target t against sources s, s+SG, ... of every non-pruned 64-point source
-// chunk (chunks whose bounding box lies within r_lambda of the group's box),
-// staged in LDS with the periodic image shift applied.  The SG partial sums of
-// a target are combined by cross-lane shuffles at the end.
+// target t against every SG-th queued source.  Source leaves of the near list
+// are walked in 64-point chunks: a chunk whose bounding box lies farther than
+// r_lambda from the group's box is skipped, and of the rest each source is kept
+// only if it lies within r_lambda of that box.  Kept sources (with the periodic
+// image shift applied) go into a 128-slot LDS ring, which is drained 64 at a
+// time so that every pass keeps all lanes busy; the ring is also drained when
+// lambda changes (entries are sorted by lambda per leaf) and at the end.  The SG
+// partial sums of a target are combined by cross-lane shuffles.
 template <int ND, int SG>
 __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, const NearLeaf* __restrict__ leaves,
                                              const NearEntryDev* __restrict__ entries, const double* __restrict__ cbbox,
@@ -821,7 +836,8 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
                                              RadialPoly poly, double* __restrict__ u)
 {
     constexpr int TG = 64 / SG;
-    __shared__ double2 S[64][3];
+    constexpr int RING = 128;
+    __shared__ double2 S[RING][3];
     const NearWork w = work[blockIdx.x];
     const NearLeaf T = leaves[w.leaf];
     const int lane = threadIdx.x;
@@ -841,12 +857,31 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
             thi[d] = fmax(thi[d], __shfl_xor(thi[d], off));
         }
     double u0 = 0, u1 = 0, u2 = 0;
+    int head = 0, cnt = 0, cur = -1;
+    double rl2 = 0, tw = 0, cP = 0, cQ = 0;
+    auto drain = [&](int m) {
+        for (int jj = sl; jj < m; jj += SG) {
+            const int q = (head + jj) & (RING - 1);
+            const double2 a = S[q][0], b = S[q][1], c = S[q][2];
+            residual_pair<ND>(xt - a.x, yt - a.y, zt - b.x, b.y, c.x, c.y, rl2, tw, cP, cQ, poly, u0, u1, u2);
+        }
+        head = (head + m) & (RING - 1);
+        cnt -= m;
+    };
     for (int e = T.ebeg; e < T.eend; ++e) {
         const NearEntryDev E = entries[e];
-        const double rl = 1.0 / (double)(1ll << E.lambda);
-        const double rl2 = rl * rl, inv_rl2 = 1.0 / rl2;
-        const double cP = 1.0 / (4.0 * kPi * rl), cQ = cP * inv_rl2;
-        const double tw = 2.0 * inv_rl2;
+        if (E.lambda != cur) {
+            if (cnt > 0) {
+                __syncthreads();
+                drain(cnt);
+            }
+            cur = E.lambda;
+            const double rl = 1.0 / (double)(1ll << cur);
+            rl2 = rl * rl;
+            tw = 2.0 / rl2;
+            cP = 1.0 / (4.0 * kPi * rl);
+            cQ = cP / rl2;
+        }
         const double sh[3] = {(double)E.sx, (double)E.sy, (double)E.sz};
         const int nch = (int)((E.send - E.sstart + 63) / 64);
         for (int k = 0; k < nch; ++k) {
@@ -860,13 +895,10 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
             if (gap2 >= rl2)
                 continue;
             const int64_t s0 = E.sstart + 64 * (int64_t)k;
-            const int cnt = (int)min((int64_t)64, E.send - s0);
-            // each lane takes one source of the chunk and keeps it if it lies
-            // within r_lambda of the target group's box; survivors are packed
-            // to the front of the LDS tile (ballot + prefix count)
+            const int ccnt = (int)min((int64_t)64, E.send - s0);
             double sx = 0, sy = 0, sz = 0;
             bool keep = false;
-            if (lane < cnt) {
+            if (lane < ccnt) {
                 const int64_t j = s0 + lane;
                 sx = x[j] + sh[0];
                 sy = y[j] + sh[1];
@@ -878,20 +910,26 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
             }
             const unsigned long long mask = __ballot(keep);
             const int kept = __popcll(mask);
+            if (kept == 0)
+                continue;
             const int pos = __popcll(mask & ((1ull << lane) - 1ull));
             __syncthreads();
             if (keep) {
                 const int64_t j = s0 + lane;
-                S[pos][0] = make_double2(sx, sy);
-                S[pos][1] = make_double2(sz, fs[j]);
-                S[pos][2] = make_double2(fs[n + j], fs[2 * n + j]);
+                const int q = (head + cnt + pos) & (RING - 1);
+                S[q][0] = make_double2(sx, sy);
+                S[q][1] = make_double2(sz, fs[j]);
+                S[q][2] = make_double2(fs[n + j], fs[2 * n + j]);
             }
+            cnt += kept;
             __syncthreads();
-            for (int jj = sl; jj < kept; jj += SG) {
-                const double2 a = S[jj][0], b = S[jj][1], c = S[jj][2];
-                residual_pair<ND>(xt - a.x, yt - a.y, zt - b.x, b.y, c.x, c.y, rl2, tw, cP, cQ, poly, u0, u1, u2);
-            }
+            if (cnt >= 64)
+                drain(64);
         }
+    }
+    if (cnt > 0) {
+        __syncthreads();
+        drain(cnt);
     }
 #pragma unroll
     for (int off = 1; off < SG; off <<= 1) {
