@@ -26,11 +26,42 @@ METRIC = "Stokeslet targets/sec at 1e6 pts, 1e-6 rel L2: FP64 vs mixed/batched"
 PEAK_FP64_VECTOR_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 
 
+def nd_bucket(deg_P: int, deg_Q: int) -> int:
+    """Compiled Horner degree the near-field kernel is instantiated with."""
+    d = max(deg_P, deg_Q) + 1  # coefficient count
+    return 14 if d <= 14 else 18 if d <= 18 else 21 if d <= 21 else 24
+
+
 def near_flops_per_pair(deg_P: int, deg_Q: int) -> int:
     """Algorithmic flops of one residual-kernel pair (difference 3, r^2 5,
     rsqrt 1, s 1, y.f 5, the two scalar coefficients 8, update 12, and a
     degree-d polynomial 2d each)."""
     return 35 + 2 * (deg_P + deg_Q)
+
+
+def near_traffic(config: str, tol: float, precision: str, kernel: str):
+    """HBM bytes per launch of the near-field kernel from the committed
+    rocprofv3 summary of this workload, or None when there is none or the
+    near-field source section changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"k_near_{config}_{precision}.md")
+    if not os.path.exists(path) or abs(tol - workloads_tol(config)) > 0:
+        return None
+    m = re.search(r'^\{"kernel".*\}$', open(path).read(), re.M)
+    if not m:
+        return None
+    rec = json.loads(m.group(0))
+    src = open(os.path.join(ROOT, "paper_2509_21471_amd", "csrc", "dmk_kernels.hip")).read()
+    sec = src[src.index("// ---- near field"):src.index("// ---- finishing")]
+    if hashlib.sha256(sec.encode()).hexdigest() != rec["near_section_sha256"] or rec["kernel"] != kernel:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
+def workloads_tol(config: str) -> float:
+    import workloads
+    return workloads.CONFIGS[config]["tol"]
 
 
 def copy_calibration(mib: int):
@@ -47,6 +78,47 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_calibration_bytes": n * 8, "launches": 3}), flush=True)
 
 
+def multi_rhs_variant(args, dev, parity: bool) -> dict:
+    """One plan on 2e6 uniform points with 32 force vectors: evaluation rate in
+    target-vectors per second with the near field batched over 8 vectors, and
+    the same plan with one vector per near-field pass."""
+    import torch
+
+    import paper_2509_21471_amd as dmk
+    import workloads
+    name = "uniform_2e6_rhs32"
+    cfg = workloads.CONFIGS[name]
+    x, f = workloads.config(name)
+    n, k = x.shape[0], f.shape[0]
+    xd = torch.from_numpy(x).to(dev)
+    fd = torch.from_numpy(f).to(dev)
+    out = torch.empty_like(fd)
+    res = {"workload": name, "n": n, "n_rhs": k, "tol": cfg["tol"], "precision": "fp64"}
+    for batch in (8, 1):
+        plan = dmk.Plan(xd, tol=cfg["tol"], rhs_batch=batch)
+        plan.eval(fd, out)
+        torch.cuda.synchronize()
+        reps = 2
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.eval(fd, out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        res[f"rhs_batch_{batch}"] = {"eval_ms": ms, "target_rhs_per_s": n * k / (ms * 1e-3)}
+        plan.close()
+    res["batching_speedup"] = res["rhs_batch_1"]["eval_ms"] / res["rhs_batch_8"]["eval_ms"]
+    if parity:
+        import oracle
+        idx = workloads.sample_targets(n, 200, cfg["seed"])
+        u = out[k - 1].cpu().numpy()
+        res["rel_l2_sampled_last_rhs"] = oracle.rel_l2(u[idx], oracle.direct(x, f[k - 1], idx))
+    print(f"# multi-rhs: {res['rhs_batch_8']['eval_ms']:.1f} ms for {k} vectors "
+          f"(unbatched {res['rhs_batch_1']['eval_ms']:.1f} ms)", file=sys.stderr, flush=True)
+    del fd, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +132,8 @@ def main():
     ap.add_argument("--parity-sample", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the multi-right-hand-side (and other) variant measurements")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes three times (the "
                          "reference kernel for scaling HBM byte counters) and exit")
@@ -146,6 +220,10 @@ def main():
     achieved = stats["in_support"] * fpp / t_near / 1e12
     phases = {k: float(np.mean([a[k] for a in phases_acc])) for k in phases_acc[0]}
 
+    near_kernel = f"dmk::k_near<{nd_bucket(info['deg_P'], info['deg_Q'])}, {info['near_lanes']}>"
+    traffic = None
+    if args.leaf_size == 0:
+        traffic = near_traffic(args.config, tol, "fp64", near_kernel)
     result = {
         "metric": METRIC,
         "value": n / (ms_per_step * 1e-3),
@@ -163,7 +241,8 @@ def main():
                    "periodic": periodic, "tol": tol, "precision": "fp64", "step": "plan+eval",
                    "leaf_size": info["leaf_size"]},
         "roofline": {"bound": "alu", "kernel": "k_near", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
+                     "traffic": traffic, "traffic_unit": "bytes/launch",
                      "near_ms": t_near * 1e3, "pairs_in_support": stats["in_support"],
                      "pairs_evaluated": stats["evaluated"], "pairs_listed": stats["listed"],
                      "flops_per_pair": fpp},
@@ -174,6 +253,9 @@ def main():
                                       "device_bytes", "plan_ms", "plan_phase_ms", "p", "n1", "deg_P",
                                       "deg_Q")},
     }
+
+    if not args.no_variants:
+        result["variants"] = {"multi_rhs": multi_rhs_variant(args, dev, not args.no_parity)}
 
     if not args.no_parity:
         import oracle

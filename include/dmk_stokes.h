@@ -70,6 +70,10 @@ typedef struct {
     int p;                /* Chebyshev points per dimension of every proxy grid;
                              0 = the row's value, else 12, 16, 20, 23, 26, 30, 33,
                              36, 40 or 44 */
+    int rhs_batch;        /* force vectors evaluated together by one near-field pass
+                             (the pair geometry and radial polynomials are shared):
+                             1, 2, 4 or 8; 0 = 8.  Sets the size of the plan's
+                             force/velocity work buffers (48 bytes per point each) */
 } dmk_opts;
 
 /* record HIP events around each phase of dmk_stokes_eval (read back with
@@ -106,6 +110,8 @@ typedef struct {
     /* wall time of the plan's parts: bounding box, Morton keys + sort + key
      * download, host octree, host lists, device buffers, uploads + final sync */
     double plan_phase_ms[6];
+    int near_lanes;             /* source lanes per target of the near-field kernel */
+    int precision;              /* dmk_precision of the plan */
 } dmk_plan_info;
 
 /*
@@ -132,8 +138,10 @@ int dmk_stokes_plan_ex(const double* points, int64_t n, int dim, int periodic, d
  * Evaluates the sums for n_rhs force vectors on the plan's points.
  *   forces      device, (n_rhs, n, 3) float64, caller's point order
  *   velocities  device, (n_rhs, n, 3) float64, overwritten
- * Stream-ordered, no host synchronisation; several calls on one plan must
- * not overlap (they share the plan's work buffers).
+ * The vectors are taken in batches of up to dmk_opts.rhs_batch: the far-field
+ * passes run per vector, the near field once per batch.  Stream-ordered, no
+ * host synchronisation; several calls on one plan must not overlap (they share
+ * the plan's work buffers).
  */
 int dmk_stokes_eval(dmk_plan_t plan, const double* forces, int n_rhs, double* velocities);
 
@@ -152,8 +160,10 @@ int dmk_stokes_tree_leaves(dmk_plan_t plan, int32_t* leaf_level, int64_t* leaf_c
 
 /*
  * Milliseconds spent in each phase of the most recent dmk_stokes_eval call on
- * this plan (first right-hand side), out[DMK_NUM_PHASES] host array.  Needs
- * DMK_FLAG_PHASE_TIMING; synchronises on the recorded events.
+ * this plan, out[DMK_NUM_PHASES] host array: the far-field phases of its first
+ * force vector, the near field and finish of its first batch of vectors
+ * (dmk_opts.rhs_batch).  Needs DMK_FLAG_PHASE_TIMING; synchronises on the
+ * recorded events.
  */
 int dmk_stokes_phase_ms(dmk_plan_t plan, double* out);
 

@@ -37,7 +37,7 @@ class DMKError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("leaf_size", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("mem_cap_bytes", ctypes.c_size_t), ("flags", ctypes.c_int), ("near_lanes", ctypes.c_int),
-                ("q", ctypes.c_int), ("p", ctypes.c_int)]
+                ("q", ctypes.c_int), ("p", ctypes.c_int), ("rhs_batch", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -50,7 +50,7 @@ class PlanInfo(ctypes.Structure):
                 ("n_senders", ctypes.c_int64), ("n_receivers", ctypes.c_int64),
                 ("center", ctypes.c_double * 3), ("box_len", ctypes.c_double),
                 ("device_bytes", ctypes.c_size_t), ("plan_ms", ctypes.c_double),
-                ("plan_phase_ms", ctypes.c_double * 6)]
+                ("plan_phase_ms", ctypes.c_double * 6), ("near_lanes", ctypes.c_int), ("precision", ctypes.c_int)]
 
     def as_dict(self):
         d = {}
@@ -174,13 +174,13 @@ class Plan:
 
     def __init__(self, points, periodic: bool = False, tol: float = 1e-6, precision: int = PREC_FP64,
                  leaf_size: int = 0, stream=None, mem_cap_bytes: int = 0, timing: bool = False,
-                 near_lanes: int = 0, q: int = 0, p: int = 0):
+                 near_lanes: int = 0, q: int = 0, p: int = 0, rhs_batch: int = 0):
         torch = _torch()
         pts = _dev_f64(points)
         self.n = int(pts.shape[0])
         self.stream = stream
         opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), int(mem_cap_bytes),
-                    FLAG_PHASE_TIMING if timing else 0, int(near_lanes), int(q), int(p))
+                    FLAG_PHASE_TIMING if timing else 0, int(near_lanes), int(q), int(p), int(rhs_batch))
         h = ctypes.c_void_p()
         _check(lib().dmk_stokes_plan_ex(ctypes.c_void_p(pts.data_ptr()), self.n, 3, int(bool(periodic)),
                                         float(tol), ctypes.byref(opts), ctypes.byref(h)))

@@ -212,7 +212,10 @@ struct dmk_plan_s {
     std::vector<int> leaf_box;        // leaf index (all leaves) -> box id
     // phase timing
     bool timing = false;
-    hipEvent_t ev[DMK_NUM_PHASES + 1] = {};
+    // ev[0..10]: phase boundaries; ev[11]: start of the near field (the far
+    // field of the batch's other vectors runs between ev[8] and ev[11])
+    hipEvent_t ev[DMK_NUM_PHASES + 2] = {};
+    int rhs_batch = 8;                // force vectors per near-field pass
     bool ev_recorded = false;
     ~dmk_plan_s()
     {
@@ -242,6 +245,9 @@ int validate_common(int dim, double tol, const dmk_opts* opts)
             return fail(DMK_ERR_ARG, "near_lanes must be 0, 1, 2, 4 or 8");
         if (opts->q != 0 && (opts->q < 4 || opts->q > 40))
             return fail(DMK_ERR_ARG, "q must be 0 or in [4, 40]");
+        if (opts->rhs_batch != 0 && opts->rhs_batch != 1 && opts->rhs_batch != 2 && opts->rhs_batch != 4 &&
+            opts->rhs_batch != 8)
+            return fail(DMK_ERR_ARG, "rhs_batch must be 0, 1, 2, 4 or 8");
         if (opts->p != 0 && !dmk::p_supported(opts->p))
             return fail(DMK_ERR_ARG, "p must be 0 or one of 12, 16, 20, 23, 26, 30, 33, 36, 40, 44");
     }
@@ -530,9 +536,6 @@ int build_plan(dmk_plan_t P, const double* points)
             nent.push_back(d);
         }
         L.eend = (int)nent.size();
-        // the near-field kernel restarts its source queue when lambda changes
-        std::stable_sort(nent.begin() + L.ebeg, nent.end(),
-                         [](const NearEntryDev& a, const NearEntryDev& b) { return a.lambda < b.lambda; });
         const int tg = 64 / P->near_sg;
         const int nch = (int)((B.end - B.start + tg - 1) / tg);
         for (int c = 0; c < nch; ++c)
@@ -581,8 +584,8 @@ int build_plan(dmk_plan_t P, const double* points)
     P->H = (size_t)q * n1 * n1;
     P->Hroot = (size_t)P->root_mh * P->root_mf * P->root_mf;
     const size_t p3 = (size_t)p * p * p;
-    P->fs = P->mem.alloc<double>(3 * n);
-    P->u = P->mem.alloc<double>(3 * n);
+    P->fs = P->mem.alloc<double>(3 * n * (size_t)P->rhs_batch);
+    P->u = P->mem.alloc<double>(3 * n * (size_t)P->rhs_batch);
     P->Q = P->mem.alloc<double>((size_t)P->nf * 3 * p3);
     P->V = P->mem.alloc<double>((size_t)P->nf * 3 * p3);
     P->Phi = P->mem.alloc<cplx>((size_t)P->nsend * 3 * P->H);
@@ -608,7 +611,7 @@ int build_plan(dmk_plan_t P, const double* points)
     P->s2 = P->mem.alloc<char>(sbytes);
     P->phi_root = P->mem.alloc<cplx>(3 * P->Hroot);
     P->psi_root = P->mem.alloc<cplx>(3 * P->Hroot);
-    P->cst = P->mem.alloc<double>(3);
+    P->cst = P->mem.alloc<double>(3 * (size_t)P->rhs_batch);
     if (P->mem.oom)
         return fail(DMK_ERR_OOM, "device allocation failed (or above mem_cap_bytes)");
     lap(4);
@@ -639,7 +642,11 @@ int build_plan(dmk_plan_t P, const double* points)
     return DMK_OK;
 }
 
-int eval_one(dmk_plan_t P, const double* f, double* vel, bool record)
+// Far field of force vector r of the current batch (sorted forces at
+// fs + 3nr): every pass from the proxy charges to the potential at the points
+// (u + 3nr, overwritten).  The work buffers are shared, so the passes of the
+// batch's vectors run one vector after the other.
+void far_field(dmk_plan_t P, int r, bool record)
 {
     using namespace dmk;
     hipStream_t st = P->stream;
@@ -647,14 +654,15 @@ int eval_one(dmk_plan_t P, const double* f, double* vel, bool record)
         if (record)
             (void)hipEventRecord(P->ev[k], st);
     };
-    mark(0);
     const int64_t n = P->n;
+    const double* fs = P->fs + (size_t)r * 3 * n;
+    double* u = P->u + (size_t)r * 3 * n;
+    double* cst = P->cst + 3 * r;
     const int p = P->prm.p, q = P->prm.q, n1 = P->prm.n1;
     const long p3 = (long)p * p * p, p2 = (long)p * p;
     const Tree& T = P->tree;
-    launch_gather_forces(f, n, P->perm, P->fs, st);
     // Step 2a: proxy charges of the leaves
-    launch_anterp(p, P->leaves, P->nleaf, P->Ltab, P->fs, n, P->Q, st);
+    launch_anterp(p, P->leaves, P->nleaf, P->Ltab, fs, n, P->Q, st);
     mark(1);
     const int h = (p + 1) / 2, M = q - 1;
     // Step 2b: merge children into parents, finest level first (Q is x-major [a][b][c])
@@ -712,7 +720,7 @@ int eval_one(dmk_plan_t P, const double* f, double* vel, bool record)
         stage(P, ST_IN_HALF_REAL, IO_PLAIN, P->s2, (long)mh * p * p, nullptr, Vr, p3, nullptr, 1, P->r_in_half, mh, p,
               0, 0, mh, h, p * p, 1);
         if (!P->periodic)
-            launch_sum_root(Qr, (int)p3, 1.0 / (4.0 * kPi * (1.0 + std::sqrt(3.0))), P->cst, st);
+            launch_sum_root(Qr, (int)p3, 1.0 / (4.0 * kPi * (1.0 + std::sqrt(3.0))), cst, st);
     }
     mark(6);
     // downward interpolation, coarsest level first (V is z-major, all axes alike)
@@ -728,16 +736,39 @@ int eval_one(dmk_plan_t P, const double* f, double* vel, bool record)
               h, p, 4 * p * p, L.nparent, L.child_fid);
     }
     mark(7);
-    // far field at the points, then the near field (Step 4, self term included)
-    launch_leaf_eval(p, P->echunks, P->n_echunk, P->Ltab, P->V, n, P->u, st);
+    // far field at the points
+    launch_leaf_eval(p, P->echunks, P->n_echunk, P->Ltab, P->V, n, u, st);
     mark(8);
-    launch_near(P->near_sg, P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x, P->y, P->z, P->fs, n, P->poly,
-                P->u, st);
-    mark(9);
-    launch_finalize(P->u, n, P->perm, 1.0 / P->box_len, P->periodic ? nullptr : P->cst, vel, st);
-    mark(10);
+}
+
+// Evaluates nb (1, 2, 4 or 8) force vectors: gather, far field per vector,
+// one near-field pass for the whole batch (Step 4, self term included), then
+// the constant, scaling and unpermutation per vector.  Phase events cover the
+// first vector's far field and the batch's near field and finish.
+int eval_batch(dmk_plan_t P, const double* f, int nb, double* vel, bool record)
+{
+    using namespace dmk;
+    hipStream_t st = P->stream;
+    const int64_t n = P->n;
     if (record)
+        (void)hipEventRecord(P->ev[0], st);
+    for (int r = 0; r < nb; ++r)
+        launch_gather_forces(f + (size_t)r * 3 * n, n, P->perm, P->fs + (size_t)r * 3 * n, st);
+    for (int r = 0; r < nb; ++r)
+        far_field(P, r, record && r == 0);
+    if (record)
+        (void)hipEventRecord(P->ev[DMK_NUM_PHASES + 1], st);
+    launch_near(P->near_sg, nb, P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x, P->y, P->z, P->fs, n,
+                P->poly, P->u, st);
+    if (record)
+        (void)hipEventRecord(P->ev[9], st);
+    for (int r = 0; r < nb; ++r)
+        launch_finalize(P->u + (size_t)r * 3 * n, n, P->perm, 1.0 / P->box_len,
+                        P->periodic ? nullptr : P->cst + 3 * r, vel + (size_t)r * 3 * n, st);
+    if (record) {
+        (void)hipEventRecord(P->ev[10], st);
         P->ev_recorded = true;
+    }
     return DMK_OK;
 }
 
@@ -841,6 +872,8 @@ int dmk_stokes_plan_ex(const double* points, int64_t n, int dim, int periodic, d
         P->timing = (opts->flags & DMK_FLAG_PHASE_TIMING) != 0;
         if (opts->near_lanes > 0)
             P->near_sg = opts->near_lanes;
+        if (opts->rhs_batch > 0)
+            P->rhs_batch = opts->rhs_batch;
     }
     if (P->timing)
         for (auto& e : P->ev)
@@ -875,11 +908,16 @@ int dmk_stokes_eval(dmk_plan_t plan, const double* forces, int n_rhs, double* ve
         return fail(DMK_ERR_ARG, "n_rhs must be >= 1");
     if (!is_device_ptr(forces) || !is_device_ptr(velocities))
         return fail(DMK_ERR_ARG, "forces and velocities must be device pointers");
-    for (int r = 0; r < n_rhs; ++r) {
-        const int rc = eval_one(plan, forces + (size_t)r * 3 * plan->n, velocities + (size_t)r * 3 * plan->n,
-                                plan->timing && r == 0);
+    for (int r = 0; r < n_rhs;) {
+        // largest supported batch that fits the remaining vectors
+        int nb = plan->rhs_batch;
+        while (nb > n_rhs - r)
+            nb >>= 1;
+        const int rc = eval_batch(plan, forces + (size_t)r * 3 * plan->n, nb, velocities + (size_t)r * 3 * plan->n,
+                                  plan->timing && r == 0);
         if (rc != DMK_OK)
             return rc;
+        r += nb;
     }
     HIPCHK(hipGetLastError());
     return DMK_OK;
@@ -917,6 +955,8 @@ int dmk_stokes_plan_info(dmk_plan_t plan, dmk_plan_info* info)
     info->plan_ms = P.plan_ms;
     for (int k = 0; k < 6; ++k)
         info->plan_phase_ms[k] = P.plan_phase[k];
+    info->near_lanes = P.near_sg;
+    info->precision = P.precision;
     return DMK_OK;
 }
 
@@ -961,7 +1001,10 @@ int dmk_stokes_phase_ms(dmk_plan_t plan, double* out)
     HIPCHK(hipEventSynchronize(plan->ev[DMK_NUM_PHASES]));
     for (int k = 0; k < DMK_NUM_PHASES; ++k) {
         float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, plan->ev[k], plan->ev[k + 1]));
+        if (k == DMK_PHASE_NEAR)
+            HIPCHK(hipEventElapsedTime(&ms, plan->ev[DMK_NUM_PHASES + 1], plan->ev[k + 1]));
+        else
+            HIPCHK(hipEventElapsedTime(&ms, plan->ev[k], plan->ev[k + 1]));
         out[k] = ms;
     }
     return DMK_OK;

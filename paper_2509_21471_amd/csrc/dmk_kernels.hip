@@ -200,6 +200,22 @@ __device__ inline void lagrange(double xi, const double* __restrict__ t, const d
         L[a] = hit >= 0 ? (a == hit ? 1.0 : 0.0) : L[a] * id;
 }
 
+// ---- block order ----------------------------------------------------------------
+// Workgroups are handed to the 8 XCDs round-robin, and each XCD has its own L2.
+// xcd_block() renumbers the blocks of a 1D grid of xcd_grid(total) so that each
+// XCD runs a contiguous range of [0, total): neighbouring work items (here,
+// receivers adjacent in Morton order) then read shared data through the same
+// L2.  Padding blocks get -1 and must return.  Only for work of even cost per
+// block: on the point kernels a contiguous range puts whole clusters on one
+// XCD and the imbalance outweighs the cache gain.
+__device__ inline int xcd_block(int total)
+{
+    const int per = (total + 7) / 8;
+    const int lg = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    return lg < total ? lg : -1;
+}
+inline unsigned xcd_grid(int total) { return (unsigned)(((total + 7) / 8) * 8); }
+
 // ---- point <-> proxy grid (MFMA) ---------------------------------------------------
 // Lagrange values of every point on its leaf's proxy grid, computed once per
 // plan: Ltab[i][d][0..PA) (d = x, y, z; PA = p rounded up to 4, zero padded).
@@ -251,15 +267,20 @@ struct AnterpCfg {
 };
 
 template <int P>
-__global__ __launch_bounds__(AnterpCfg<P>::threads) void k_anterp(const LeafDesc* __restrict__ leaves,
+__global__ __launch_bounds__(AnterpCfg<P>::threads) void k_anterp(const LeafDesc* __restrict__ leaves, int nleaf,
                                                                   const double* __restrict__ Ltab,
                                                                   const double* __restrict__ fs, int64_t n,
                                                                   double* __restrict__ Q)
 {
     using C = AnterpCfg<P>;
     constexpr int PA = MCfg<P>::PA, AR = C::AR;
-    const LeafDesc L = leaves[blockIdx.x];
-    const int ar = blockIdx.y % C::NA, bcr = blockIdx.y / C::NA;
+    constexpr int G = C::NA * C::NBC;
+    const int lb = blockIdx.x;
+    if (lb >= nleaf * G)
+        return;
+    const LeafDesc L = leaves[lb / G];
+    const int gi = lb % G;
+    const int ar = gi % C::NA, bcr = gi / C::NA;
     const int a0 = ar * AR;
     const int tid = threadIdx.x;
     const int pair = bcr * C::BCR + tid;
@@ -301,7 +322,7 @@ __global__ __launch_bounds__(AnterpCfg<P>::threads) void k_anterp(const LeafDesc
 // then u_j[pt] += Lz[pt][c] sum_b Ly[pt][b] D[b][pt].  A block takes 64 points
 // of one leaf (16 per wave); the z-slab of V sits in LDS.
 template <int P>
-__global__ __launch_bounds__(256) void k_leaf_eval(const EvalChunk* __restrict__ chunks,
+__global__ __launch_bounds__(256) void k_leaf_eval(const EvalChunk* __restrict__ chunks, int nchunk,
                                                    const double* __restrict__ Ltab, const double* __restrict__ V,
                                                    int64_t n, double* __restrict__ u)
 {
@@ -412,8 +433,8 @@ void launch_anterp(int p, const LeafDesc* leaves, int nleaf, const double* Ltab,
     if (nleaf == 0)
         return;
 #define L_ANTERP(P)                                                                                        \
-    hipLaunchKernelGGL(k_anterp<P>, dim3(nleaf, AnterpCfg<P>::NA * AnterpCfg<P>::NBC), dim3(AnterpCfg<P>::threads), \
-                       0, s, leaves, Ltab, fs, n, Q)
+    hipLaunchKernelGGL(k_anterp<P>, dim3(nleaf * AnterpCfg<P>::NA * AnterpCfg<P>::NBC),           \
+                       dim3(AnterpCfg<P>::threads), 0, s, leaves, nleaf, Ltab, fs, n, Q)
     DMK_P_DISPATCH(p, L_ANTERP)
 #undef L_ANTERP
 }
@@ -423,7 +444,8 @@ void launch_leaf_eval(int p, const EvalChunk* chunks, int nchunk, const double* 
 {
     if (nchunk == 0)
         return;
-#define L_EVAL(P) hipLaunchKernelGGL(k_leaf_eval<P>, dim3(nchunk), dim3(256), 0, s, chunks, Ltab, V, n, u)
+#define L_EVAL(P) \
+    hipLaunchKernelGGL(k_leaf_eval<P>, dim3(nchunk), dim3(256), 0, s, chunks, nchunk, Ltab, V, n, u)
     DMK_P_DISPATCH(p, L_EVAL)
 #undef L_EVAL
 }
@@ -672,9 +694,8 @@ __global__ __launch_bounds__(256) void k_translate(int q, int n1, int nrecv, con
     // adjacent in Morton order -- which share most of their colleagues -- read
     // the same sender slabs through the same L2.
     const int total = n1 * nrecv;
-    const int per = (total + 7) / 8;
-    const int lg = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-    if (lg >= total)
+    const int lg = xcd_block(total);
+    if (lg < 0)
         return;
     const int iy = lg / nrecv;
     const RecvDesc rd = recv[lg - iy * nrecv];
@@ -734,7 +755,7 @@ void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int*
         attr = true;
     }
     const int total = n1 * nrecv;
-    hipLaunchKernelGGL(k_translate, dim3(((total + 7) / 8) * 8), dim3(256), lds, s, q, n1, nrecv, recv, e_src, e_off,
+    hipLaunchKernelGGL(k_translate, dim3(xcd_grid(total)), dim3(256), lds, s, q, n1, nrecv, recv, e_src, e_off,
                        Phi, wdiff, Psi);
 }
 
@@ -819,25 +840,55 @@ __device__ inline void residual_pair(double dx, double dy, double dz, double fx,
     }
 }
 
+// The same pair for NR force vectors: the geometry, the square root and both
+// radial polynomials are shared, only the projections onto the forces repeat.
+// v holds the source as (x, y, z, f_0, ..., f_{NR-1}) (already shifted).
+template <int ND, int NR>
+__device__ inline void residual_pair_multi(double xt, double yt, double zt, const double* v, double rl2, double tw,
+                                           double cP, double cQ, const RadialPoly& poly, double (&u)[NR][3])
+{
+    const double dx = xt - v[0], dy = yt - v[1], dz = zt - v[2];
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    if (r2 < rl2) {
+        const double rinv = r2 > 0.0 ? rsqrt_f64(r2) : 0.0;
+        const double t = fma(r2, tw, -1.0);
+        const double P = horner<ND>(poly.P, t);
+        const double Q = horner<ND>(poly.Q, t);
+        const double cr = kInv8Pi * rinv;
+        const double a = fma(-cP, P, cr);
+        const double bq = fma(-cQ, Q, cr * rinv * rinv);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const double fx = v[3 + 3 * r], fy = v[4 + 3 * r], fz = v[5 + 3 * r];
+            const double b = fma(dx, fx, fma(dy, fy, dz * fz)) * bq;
+            u[r][0] = fma(a, fx, fma(b, dx, u[r][0]));
+            u[r][1] = fma(a, fy, fma(b, dy, u[r][1]));
+            u[r][2] = fma(a, fz, fma(b, dz, u[r][2]));
+        }
+    }
+}
+
 // One wave per target group of TG = 64/SG points of a leaf; lane (t, s) handles
 // target t against every SG-th queued source.  Source leaves of the near list
 // are walked in 64-point chunks: a chunk whose bounding box lies farther than
 // r_lambda from the group's box is skipped, and of the rest each source is kept
 // only if it lies within r_lambda of that box.  Kept sources (with the periodic
-// image shift applied) go into a 128-slot LDS ring, which is drained 64 at a
-// time so that every pass keeps all lanes busy; the ring is also drained when
-// lambda changes (entries are sorted by lambda per leaf) and at the end.  The SG
-// partial sums of a target are combined by cross-lane shuffles.
-template <int ND, int SG>
-__global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, const NearLeaf* __restrict__ leaves,
+// image shift applied, and the NR force vectors of the batch) are packed into
+// LDS and evaluated at once.  Every batch size visits sources in the same
+// order, so a force vector's result does not depend on how it was batched.
+// The SG partial sums of a target are combined by cross-lane shuffles.
+// Forces and outputs are [NR][3][n].
+template <int ND, int SG, int NR>
+__global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, int nwork,
+                                             const NearLeaf* __restrict__ leaves,
                                              const NearEntryDev* __restrict__ entries, const double* __restrict__ cbbox,
                                              const double* __restrict__ x, const double* __restrict__ y,
                                              const double* __restrict__ z, const double* __restrict__ fs, int64_t n,
                                              RadialPoly poly, double* __restrict__ u)
 {
     constexpr int TG = 64 / SG;
-    constexpr int RING = 128;
-    __shared__ double2 S[RING][3];
+    constexpr int W2 = (3 + 3 * NR + 1) / 2;  // double2 per staged source
+    __shared__ double2 S[64][W2];
     const NearWork w = work[blockIdx.x];
     const NearLeaf T = leaves[w.leaf];
     const int lane = threadIdx.x;
@@ -856,32 +907,17 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
             tlo[d] = fmin(tlo[d], __shfl_xor(tlo[d], off));
             thi[d] = fmax(thi[d], __shfl_xor(thi[d], off));
         }
-    double u0 = 0, u1 = 0, u2 = 0;
-    int head = 0, cnt = 0, cur = -1;
-    double rl2 = 0, tw = 0, cP = 0, cQ = 0;
-    auto drain = [&](int m) {
-        for (int jj = sl; jj < m; jj += SG) {
-            const int q = (head + jj) & (RING - 1);
-            const double2 a = S[q][0], b = S[q][1], c = S[q][2];
-            residual_pair<ND>(xt - a.x, yt - a.y, zt - b.x, b.y, c.x, c.y, rl2, tw, cP, cQ, poly, u0, u1, u2);
-        }
-        head = (head + m) & (RING - 1);
-        cnt -= m;
-    };
+    double acc[NR][3];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+        acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
     for (int e = T.ebeg; e < T.eend; ++e) {
         const NearEntryDev E = entries[e];
-        if (E.lambda != cur) {
-            if (cnt > 0) {
-                __syncthreads();
-                drain(cnt);
-            }
-            cur = E.lambda;
-            const double rl = 1.0 / (double)(1ll << cur);
-            rl2 = rl * rl;
-            tw = 2.0 / rl2;
-            cP = 1.0 / (4.0 * kPi * rl);
-            cQ = cP / rl2;
-        }
+        const double rl = 1.0 / (double)(1ll << E.lambda);
+        const double rl2 = rl * rl;
+        const double tw = 2.0 / rl2;
+        const double cP = 1.0 / (4.0 * kPi * rl);
+        const double cQ = cP / rl2;
         const double sh[3] = {(double)E.sx, (double)E.sy, (double)E.sz};
         const int nch = (int)((E.send - E.sstart + 63) / 64);
         for (int k = 0; k < nch; ++k) {
@@ -916,31 +952,47 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
             __syncthreads();
             if (keep) {
                 const int64_t j = s0 + lane;
-                const int q = (head + cnt + pos) & (RING - 1);
-                S[q][0] = make_double2(sx, sy);
-                S[q][1] = make_double2(sz, fs[j]);
-                S[q][2] = make_double2(fs[n + j], fs[2 * n + j]);
+                double v[2 * W2];
+                v[0] = sx;
+                v[1] = sy;
+                v[2] = sz;
+#pragma unroll
+                for (int c = 0; c < 3 * NR; ++c)
+                    v[3 + c] = fs[(size_t)c * n + j];
+                if (2 * W2 > 3 + 3 * NR)
+                    v[2 * W2 - 1] = 0.0;
+#pragma unroll
+                for (int c = 0; c < W2; ++c)
+                    S[pos][c] = make_double2(v[2 * c], v[2 * c + 1]);
             }
-            cnt += kept;
             __syncthreads();
-            if (cnt >= 64)
-                drain(64);
+            for (int jj = sl; jj < kept; jj += SG) {
+                double v[2 * W2];
+#pragma unroll
+                for (int c = 0; c < W2; ++c) {
+                    const double2 t2 = S[jj][c];
+                    v[2 * c] = t2.x;
+                    v[2 * c + 1] = t2.y;
+                }
+                residual_pair_multi<ND, NR>(xt, yt, zt, v, rl2, tw, cP, cQ, poly, acc);
+            }
         }
     }
-    if (cnt > 0) {
-        __syncthreads();
-        drain(cnt);
-    }
 #pragma unroll
-    for (int off = 1; off < SG; off <<= 1) {
-        u0 += __shfl_xor(u0, off);
-        u1 += __shfl_xor(u1, off);
-        u2 += __shfl_xor(u2, off);
-    }
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int off = 1; off < SG; off <<= 1) {
+            acc[r][0] += __shfl_xor(acc[r][0], off);
+            acc[r][1] += __shfl_xor(acc[r][1], off);
+            acc[r][2] += __shfl_xor(acc[r][2], off);
+        }
     if (valid && sl == 0) {
-        u[i] += u0;
-        u[n + i] += u1;
-        u[2 * n + i] += u2;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            u[(size_t)(3 * r) * n + i] += acc[r][0];
+            u[(size_t)(3 * r + 1) * n + i] += acc[r][1];
+            u[(size_t)(3 * r + 2) * n + i] += acc[r][2];
+        }
     }
 }
 
@@ -955,32 +1007,39 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
         MACRO(24);                 \
     }
 
-void launch_near(int sg, const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
-                 const double* cbbox, const double* x, const double* y, const double* z, const double* fs, int64_t n,
-                 const RadialPoly& poly, double* u, hipStream_t s)
+void launch_near(int sg, int nr, const NearWork* work, int nwork, const NearLeaf* leaves,
+                 const NearEntryDev* entries, const double* cbbox, const double* x, const double* y, const double* z,
+                 const double* fs, int64_t n, const RadialPoly& poly, double* u, hipStream_t s)
 {
     if (nwork == 0)
         return;
-#define L_NEAR_SG(ND, SG)                                                                                           \
-    hipLaunchKernelGGL((k_near<ND, SG>), dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, fs, n, \
-                       poly, u)
-#define L_NEAR(ND)               \
-    if (sg == 1) {               \
-        L_NEAR_SG(ND, 1);        \
-    } else if (sg == 2) {        \
-        L_NEAR_SG(ND, 2);        \
-    } else if (sg == 4) {        \
-        L_NEAR_SG(ND, 4);        \
-    } else {                     \
-        L_NEAR_SG(ND, 8);        \
+#define L_NEAR_K(ND, SG, NR)                                                                                      \
+    hipLaunchKernelGGL((k_near<ND, SG, NR>), dim3(nwork), dim3(64), 0, s, work, nwork, leaves, entries, cbbox, x, \
+                       y, z, fs, n, poly, u)
+    // batches of several force vectors always use 4 source lanes per target
+#define L_NEAR(ND)                   \
+    if (nr == 2) {                   \
+        L_NEAR_K(ND, 4, 2);          \
+    } else if (nr == 4) {            \
+        L_NEAR_K(ND, 4, 4);          \
+    } else if (nr == 8) {            \
+        L_NEAR_K(ND, 4, 8);          \
+    } else if (sg == 1) {            \
+        L_NEAR_K(ND, 1, 1);          \
+    } else if (sg == 2) {            \
+        L_NEAR_K(ND, 2, 1);          \
+    } else if (sg == 4) {            \
+        L_NEAR_K(ND, 4, 1);          \
+    } else {                         \
+        L_NEAR_K(ND, 8, 1);          \
     }
     DMK_ND_DISPATCH(poly.nd, L_NEAR)
 #undef L_NEAR
-#undef L_NEAR_SG
+#undef L_NEAR_K
 }
 
 template <int SG>
-__global__ __launch_bounds__(64) void k_near_count(const NearWork* __restrict__ work,
+__global__ __launch_bounds__(64) void k_near_count(const NearWork* __restrict__ work, int nwork,
                                                    const NearLeaf* __restrict__ leaves,
                                                    const NearEntryDev* __restrict__ entries,
                                                    const double* __restrict__ cbbox, const double* __restrict__ x,
@@ -1052,13 +1111,17 @@ void launch_near_count(int sg, const NearWork* work, int nwork, const NearLeaf* 
     if (nwork == 0)
         return;
     if (sg == 1)
-        hipLaunchKernelGGL(k_near_count<1>, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, out);
+        hipLaunchKernelGGL(k_near_count<1>, dim3(nwork), dim3(64), 0, s, work, nwork, leaves, entries, cbbox,
+                           x, y, z, out);
     else if (sg == 2)
-        hipLaunchKernelGGL(k_near_count<2>, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, out);
+        hipLaunchKernelGGL(k_near_count<2>, dim3(nwork), dim3(64), 0, s, work, nwork, leaves, entries, cbbox,
+                           x, y, z, out);
     else if (sg == 4)
-        hipLaunchKernelGGL(k_near_count<4>, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, out);
+        hipLaunchKernelGGL(k_near_count<4>, dim3(nwork), dim3(64), 0, s, work, nwork, leaves, entries, cbbox,
+                           x, y, z, out);
     else
-        hipLaunchKernelGGL(k_near_count<8>, dim3(nwork), dim3(64), 0, s, work, leaves, entries, cbbox, x, y, z, out);
+        hipLaunchKernelGGL(k_near_count<8>, dim3(nwork), dim3(64), 0, s, work, nwork, leaves, entries, cbbox,
+                           x, y, z, out);
 }
 
 template <int ND>

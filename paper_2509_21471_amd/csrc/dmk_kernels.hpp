@@ -126,9 +126,10 @@ struct RadialPoly {
     double P[24], Q[24];
 };
 // sg: source lanes per target (1, 2, 4); a wave holds 64/sg targets
-void launch_near(int sg, const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,
-                 const double* cbbox, const double* x, const double* y, const double* z, const double* fs,
-                 int64_t n, const RadialPoly& poly, double* u, hipStream_t s);
+// forces and outputs [nr][3][n]; nr in {1, 2, 4, 8}
+void launch_near(int sg, int nr, const NearWork* work, int nwork, const NearLeaf* leaves,
+                 const NearEntryDev* entries, const double* cbbox, const double* x, const double* y, const double* z,
+                 const double* fs, int64_t n, const RadialPoly& poly, double* u, hipStream_t s);
 
 // pair counts of the near field: out[0] += evaluated pairs, out[1] += pairs in support
 void launch_near_count(int sg, const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,

@@ -89,14 +89,16 @@ def test_plan_argument_validation_without_gpu():
     assert lib.dmk_stokes_plan(vp, 10, 3, 0, 1e-2, ctypes.byref(out)) == -5        # tol out of range
     assert lib.dmk_stokes_plan(vp, 10, 3, 0, 1e-13, ctypes.byref(out)) == -5
     assert lib.dmk_stokes_plan(vp, 10, 3, 2, 1e-6, ctypes.byref(out)) == -1        # periodic flag
-    opts = dmk._lib.Opts(1, 0, None, 0, 0, 0, 0, 0)
+    opts = dmk._lib.Opts(1, 0, None, 0, 0, 0, 0, 0, 0)
     assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-9, ctypes.byref(opts), ctypes.byref(out)) == -5  # mixed < 1e-7
-    bad_p = dmk._lib.Opts(0, 0, None, 0, 0, 0, 0, 35)
+    bad_p = dmk._lib.Opts(0, 0, None, 0, 0, 0, 0, 35, 0)
     assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-6, ctypes.byref(bad_p), ctypes.byref(out)) == -1  # p not compiled
-    bad_q = dmk._lib.Opts(0, 0, None, 0, 0, 0, 41, 0)
+    bad_q = dmk._lib.Opts(0, 0, None, 0, 0, 0, 41, 0, 0)
     assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-6, ctypes.byref(bad_q), ctypes.byref(out)) == -1  # q too large
-    bad_lanes = dmk._lib.Opts(0, 0, None, 0, 0, 3, 0, 0)
+    bad_lanes = dmk._lib.Opts(0, 0, None, 0, 0, 3, 0, 0, 0)
     assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-6, ctypes.byref(bad_lanes), ctypes.byref(out)) == -1
+    bad_batch = dmk._lib.Opts(0, 0, None, 0, 0, 0, 0, 0, 3)
+    assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-6, ctypes.byref(bad_batch), ctypes.byref(out)) == -1
     assert lib.dmk_stokes_plan(vp, 10, 3, 0, 1e-6, None) == -1                     # NULL out
     assert lib.dmk_stokes_plan(vp, 10, 3, 0, 1e-6, ctypes.byref(out)) == -1        # host pointer
     assert out.value is None

@@ -79,16 +79,18 @@ def test_reciprocity(dev, periodic):
     assert abs(a - b) / scale < 1e-12
 
 
-def test_multiple_rhs_match_single(dev):
-    """n_rhs force vectors in one call equal one call per vector."""
-    x, f = workloads.make("clusters", 20000, seed=74, sigma=0.05, n_rhs=3)
-    plan = _dmk().Plan(_t(x), tol=1e-6, leaf_size=200)
+@pytest.mark.parametrize("n_rhs,batch", [(3, 0), (13, 0), (5, 4), (6, 2)])
+def test_multiple_rhs_match_single(dev, n_rhs, batch):
+    """n_rhs force vectors in one call (near field in batches of 8, 4, 2, 1
+    vectors) equal one call per vector, bit for bit."""
+    x, f = workloads.make("clusters", 20000, seed=74, sigma=0.05, n_rhs=n_rhs)
+    plan = _dmk().Plan(_t(x), tol=1e-6, leaf_size=200, rhs_batch=batch)
     u = plan.eval(_t(f)).cpu().numpy()
-    for r in range(3):
+    for r in range(n_rhs):
         ur = plan.eval(_t(f[r])).cpu().numpy()
-        assert np.array_equal(u[r], ur)
+        assert np.array_equal(u[r], ur), r
     plan.close()
-    assert oracle.rel_l2(u[1], oracle.direct(x, f[1])) < 1e-6
+    assert oracle.rel_l2(u[n_rhs - 1], oracle.direct(x, f[n_rhs - 1])) < 1e-6
 
 
 def test_periodic_translation_invariance(dev):

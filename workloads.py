@@ -118,10 +118,12 @@ CONFIGS = {
     "clusters_1e6": dict(kind="clusters", n=1_000_000, seed=2, sigma=0.02, periodic=False, tol=1e-6),
     "periodic_2e6": dict(kind="periodic", n=2_000_000, seed=3, sigma=0.0, periodic=True, tol=1e-9),
     "clusters_4e6": dict(kind="clusters", n=4_000_000, seed=4, sigma=0.01, periodic=False, tol=1e-6),
+    # one plan, 32 force vectors (forces shaped (32, N, 3))
+    "uniform_2e6_rhs32": dict(kind="uniform", n=2_000_000, seed=5, sigma=0.0, periodic=False, tol=1e-6, n_rhs=32),
 }
 
 
 def config(name: str):
     c = CONFIGS[name]
-    x, f = make(c["kind"], c["n"], c["seed"], c["sigma"])
+    x, f = make(c["kind"], c["n"], c["seed"], c["sigma"], c.get("n_rhs", 1))
     return x, f
