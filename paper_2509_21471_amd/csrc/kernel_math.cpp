@@ -484,7 +484,7 @@ Tables* build_tables(const Params& prm)
     T->prm = prm;
     Prolate w(prm.c);
     T->phi0 = w.phi(0.0);
-    T->fits = fit_radial(w, std::min(1e-3 * tol, 1e-13));
+    T->fits = fit_radial(w, 1e-3 * tol);
     const int p = prm.p, q = prm.q;
     std::vector<double> t, bw;
     cheb_nodes(p, t, bw);

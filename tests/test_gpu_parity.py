@@ -39,7 +39,8 @@ def test_residual_kernel_matches_oracle(dev, tol, q):
     got = _dmk().residual_sum(_t(xt), _t(xs), _t(fs), rl, tol).cpu().numpy()
     err = np.abs(got - ref).max() / np.abs(ref).max()
     print(f"residual kernel tol={tol}: max rel err {err:.2e}")
-    assert err < 1e-11
+    # the radial polynomials are fitted to 1e-3 tol of their scale
+    assert err < 20 * 1e-3 * tol
 
 
 def test_uniform_1e4_matches_direct(dev):
