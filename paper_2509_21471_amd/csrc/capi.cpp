@@ -203,10 +203,13 @@ struct dmk_plan_s {
     // work buffers
     double* fs = nullptr;             // sorted forces [3][n]
     double* u = nullptr;              // sorted velocities [3][n]
-    double *Q = nullptr, *V = nullptr;
-    dmk::cplx *Phi = nullptr, *Psi = nullptr;
+    // far-field buffers hold double (FP64 plans) or float (mixed precision)
+    bool f32 = false;
+    size_t es = 8;                    // bytes per real element of Q, V, Phi, Psi, s1, s2
+    void *Q = nullptr, *V = nullptr;
+    void *Phi = nullptr, *Psi = nullptr;
     void *s1 = nullptr, *s2 = nullptr;
-    dmk::cplx *phi_root = nullptr, *psi_root = nullptr;
+    void *phi_root = nullptr, *psi_root = nullptr;
     double* cst = nullptr;
     size_t H = 0, Hroot = 0;
     std::vector<int> leaf_box;        // leaf index (all leaves) -> box id
@@ -278,6 +281,7 @@ void stage(dmk_plan_t P, int mode, int io, const void* X, long xs, const int* xm
     a.nslots = nslots;
     a.p = P->prm.p;
     a.child_fid = child_fid;
+    a.f32 = P->f32 ? 1 : 0;
     dmk::launch_stage(mode, io, a, P->stream);
 }
 
@@ -441,8 +445,8 @@ int build_plan(dmk_plan_t P, const double* points)
     P->leaves = P->mem.alloc<LeafDesc>(hl.size());
     std::vector<EvalChunk> ech;
     for (const LeafDesc& d : hl)
-        for (int64_t s0 = d.start; s0 < d.end; s0 += 64)
-            ech.push_back(EvalChunk{d.fid, s0, std::min<int64_t>(s0 + 64, d.end)});
+        for (int64_t s0 = d.start; s0 < d.end; s0 += kEvalChunk)
+            ech.push_back(EvalChunk{d.fid, s0, std::min<int64_t>(s0 + kEvalChunk, d.end)});
     P->n_echunk = (int)ech.size();
     P->echunks = P->mem.alloc<EvalChunk>(ech.size());
     P->Ltab = P->mem.alloc<double>((size_t)n * 3 * lagrange_pad(P->prm.p));
@@ -586,17 +590,18 @@ int build_plan(dmk_plan_t P, const double* points)
     const size_t p3 = (size_t)p * p * p;
     P->fs = P->mem.alloc<double>(3 * n * (size_t)P->rhs_batch);
     P->u = P->mem.alloc<double>(3 * n * (size_t)P->rhs_batch);
-    P->Q = P->mem.alloc<double>((size_t)P->nf * 3 * p3);
-    P->V = P->mem.alloc<double>((size_t)P->nf * 3 * p3);
-    P->Phi = P->mem.alloc<cplx>((size_t)P->nsend * 3 * P->H);
-    P->Psi = P->mem.alloc<cplx>((size_t)P->nrecv * 3 * P->H);
+    const size_t es = P->es, cs = 2 * P->es;  // real / complex element bytes
+    P->Q = P->mem.alloc<char>((size_t)P->nf * 3 * p3 * es);
+    P->V = P->mem.alloc<char>((size_t)P->nf * 3 * p3 * es);
+    P->Phi = P->mem.alloc<char>((size_t)P->nsend * 3 * P->H * cs);
+    P->Psi = P->mem.alloc<char>((size_t)P->nrecv * 3 * P->H * cs);
     // scratch: largest intermediate of any stage, per (slot, component)
     size_t per = 0;
-    per = std::max(per, (size_t)p * p * q * 16);                 // outgoing stage 1
-    per = std::max(per, (size_t)p * q * n1 * 16);                // outgoing stage 2
-    per = std::max(per, (size_t)n1 * n1 * p * 16);               // incoming stage 1
-    per = std::max(per, (size_t)n1 * p * p * 16);                // incoming stage 2
-    per = std::max(per, (size_t)8 * p3 * 8);                     // merge/interp stages
+    per = std::max(per, (size_t)p * p * q * cs);                 // outgoing stage 1
+    per = std::max(per, (size_t)p * q * n1 * cs);                // outgoing stage 2
+    per = std::max(per, (size_t)n1 * n1 * p * cs);               // incoming stage 1
+    per = std::max(per, (size_t)n1 * p * p * cs);                // incoming stage 2
+    per = std::max(per, (size_t)8 * p3 * es);                    // merge/interp stages
     int maxslots = std::max(P->nsend, P->nrecv);
     for (auto& L : P->lev)
         maxslots = std::max(maxslots, L.nparent);
@@ -604,13 +609,13 @@ int build_plan(dmk_plan_t P, const double* points)
     size_t per_root = 0;
     {
         const size_t mh = P->root_mh, mf = P->root_mf;
-        per_root = std::max({(size_t)p * p * mh, (size_t)p * mh * mf, mf * mf * (size_t)p, mf * (size_t)p * p}) * 16;
+        per_root = std::max({(size_t)p * p * mh, (size_t)p * mh * mf, mf * mf * (size_t)p, mf * (size_t)p * p}) * cs;
     }
     const size_t sbytes = std::max(per * 3 * (size_t)maxslots, per_root * 3);
     P->s1 = P->mem.alloc<char>(sbytes);
     P->s2 = P->mem.alloc<char>(sbytes);
-    P->phi_root = P->mem.alloc<cplx>(3 * P->Hroot);
-    P->psi_root = P->mem.alloc<cplx>(3 * P->Hroot);
+    P->phi_root = P->mem.alloc<char>(3 * P->Hroot * cs);
+    P->psi_root = P->mem.alloc<char>(3 * P->Hroot * cs);
     P->cst = P->mem.alloc<double>(3 * (size_t)P->rhs_batch);
     if (P->mem.oom)
         return fail(DMK_ERR_OOM, "device allocation failed (or above mem_cap_bytes)");
@@ -662,7 +667,7 @@ void far_field(dmk_plan_t P, int r, bool record)
     const long p3 = (long)p * p * p, p2 = (long)p * p;
     const Tree& T = P->tree;
     // Step 2a: proxy charges of the leaves
-    launch_anterp(p, P->leaves, P->nleaf, P->Ltab, fs, n, P->Q, st);
+    launch_anterp(p, P->leaves, P->nleaf, P->Ltab, fs, n, P->Q, P->f32, st);
     mark(1);
     const int h = (p + 1) / 2, M = q - 1;
     // Step 2b: merge children into parents, finest level first (Q is x-major [a][b][c])
@@ -688,10 +693,10 @@ void far_field(dmk_plan_t P, int r, bool record)
           h, M + 1, q * n1, P->nsend);
     mark(3);
     // Step 3b: translation with the difference-kernel symbol -> Psi[mz][my][mx]
-    launch_translate(q, n1, P->recv, P->nrecv, P->e_src, P->e_off, P->Phi, P->wdiff, P->Psi, st);
+    launch_translate(q, n1, P->recv, P->nrecv, P->e_src, P->e_off, P->Phi, P->wdiff, P->Psi, P->f32, st);
     mark(4);
     // incoming plane waves -> proxy potentials, z-major V[c][b][a]
-    launch_zero(P->V, (size_t)P->nf * 3 * p3, st);
+    launch_zero(P->V, (size_t)P->nf * 3 * p3 * P->es, st);
     stage(P, ST_IN_FULL, IO_PLAIN, P->Psi, H, nullptr, P->s1, (long)n1 * q * p, nullptr, 0, P->pw_in_full, n1, p, M,
           0, M + 1, h, n1 * q, P->nrecv);
     stage(P, ST_IN_FULL, IO_PLAIN, P->s1, (long)n1 * q * p, nullptr, P->s2, (long)q * p * p, nullptr, 0,
@@ -704,15 +709,15 @@ void far_field(dmk_plan_t P, int r, bool record)
         const int mh = P->root_mh, mf = P->root_mf, RM = mh - 1;
         const long Hr = (long)P->Hroot;
         const int rf = P->root_fid;
-        const double* Qr = P->Q + (size_t)rf * 3 * p3;
-        double* Vr = P->V + (size_t)rf * 3 * p3;
+        const char* Qr = (const char*)P->Q + (size_t)rf * 3 * p3 * P->es;
+        char* Vr = (char*)P->V + (size_t)rf * 3 * p3 * P->es;
         stage(P, ST_OUT_HALF, IO_PLAIN, Qr, p3, nullptr, P->s1, p2 * mh, nullptr, 0, P->r_out, p, mh, 0, 0, h, mh,
               p * p, 1);
         stage(P, ST_OUT_FULL, IO_PLAIN, P->s1, p2 * mh, nullptr, P->s2, (long)p * mh * mf, nullptr, 0, P->r_out, p, mf,
               0, RM, h, mh, p * mh, 1);
         stage(P, ST_OUT_FULL, IO_PLAIN, P->s2, (long)p * mh * mf, nullptr, P->phi_root, Hr, nullptr, 0, P->r_out, p,
               mf, 0, RM, h, mh, mh * mf, 1);
-        launch_root_symbol(mh, mf, P->phi_root, P->wroot, P->psi_root, st);
+        launch_root_symbol(mh, mf, P->phi_root, P->wroot, P->psi_root, P->f32, st);
         stage(P, ST_IN_FULL, IO_PLAIN, P->psi_root, Hr, nullptr, P->s1, (long)mf * mh * p, nullptr, 0, P->r_in_full,
               mf, p, RM, 0, mh, h, mf * mh, 1);
         stage(P, ST_IN_FULL, IO_PLAIN, P->s1, (long)mf * mh * p, nullptr, P->s2, (long)mh * p * p, nullptr, 0,
@@ -720,7 +725,7 @@ void far_field(dmk_plan_t P, int r, bool record)
         stage(P, ST_IN_HALF_REAL, IO_PLAIN, P->s2, (long)mh * p * p, nullptr, Vr, p3, nullptr, 1, P->r_in_half, mh, p,
               0, 0, mh, h, p * p, 1);
         if (!P->periodic)
-            launch_sum_root(Qr, (int)p3, 1.0 / (4.0 * kPi * (1.0 + std::sqrt(3.0))), cst, st);
+            launch_sum_root(Qr, (int)p3, 1.0 / (4.0 * kPi * (1.0 + std::sqrt(3.0))), cst, P->f32, st);
     }
     mark(6);
     // downward interpolation, coarsest level first (V is z-major, all axes alike)
@@ -737,7 +742,7 @@ void far_field(dmk_plan_t P, int r, bool record)
     }
     mark(7);
     // far field at the points
-    launch_leaf_eval(p, P->echunks, P->n_echunk, P->Ltab, P->V, n, u, st);
+    launch_leaf_eval(p, P->echunks, P->n_echunk, P->Ltab, P->V, n, u, P->f32, st);
     mark(8);
 }
 
@@ -866,6 +871,8 @@ int dmk_stokes_plan_ex(const double* points, int64_t n, int dim, int periodic, d
     if (opts) {
         P->stream = (hipStream_t)opts->stream;
         P->precision = opts->precision;
+        P->f32 = opts->precision == DMK_PREC_MIXED;
+        P->es = P->f32 ? 4 : 8;
         if (opts->leaf_size > 0)
             P->prm.ns = opts->leaf_size;
         P->mem.cap = opts->mem_cap_bytes;

@@ -14,6 +14,19 @@ constexpr double kInv8Pi = 1.0 / (8.0 * kPi);
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 }  // namespace
 
+// Far-field storage: double (FP64 plans) or float (mixed-precision plans).
+// Arithmetic is FP64 either way; loads widen and stores round.
+template <typename S>
+struct Store;
+template <>
+struct Store<double> {
+    using cx = double2;
+};
+template <>
+struct Store<float> {
+    using cx = float2;
+};
+
 // =============================================================================
 // tree construction
 // =============================================================================
@@ -266,11 +279,11 @@ struct AnterpCfg {
     static constexpr int threads = ((BCR + 63) / 64) * 64;
 };
 
-template <int P>
+template <int P, typename S>
 __global__ __launch_bounds__(AnterpCfg<P>::threads) void k_anterp(const LeafDesc* __restrict__ leaves, int nleaf,
                                                                   const double* __restrict__ Ltab,
                                                                   const double* __restrict__ fs, int64_t n,
-                                                                  double* __restrict__ Q)
+                                                                  S* __restrict__ Q)
 {
     using C = AnterpCfg<P>;
     constexpr int PA = MCfg<P>::PA, AR = C::AR;
@@ -308,12 +321,12 @@ __global__ __launch_bounds__(AnterpCfg<P>::threads) void k_anterp(const LeafDesc
         }
     }
     if (valid) {
-        double* q = Q + (size_t)L.fid * 3 * P * P * P;
+        S* q = Q + (size_t)L.fid * 3 * P * P * P;
 #pragma unroll
         for (int t = 0; t < AR; ++t)
             if (a0 + t < P)
                 for (int j = 0; j < 3; ++j)
-                    q[((size_t)j * P + a0 + t) * P * P + b * P + c] = acc[t][j];
+                    q[((size_t)j * P + a0 + t) * P * P + b * P + c] = (S)acc[t][j];
     }
 }
 
@@ -321,16 +334,17 @@ __global__ __launch_bounds__(AnterpCfg<P>::threads) void k_anterp(const LeafDesc
 // for every z index c, D[b][pt] = sum_a V[j][c][b][a] Lx[pt][a] (V z-major),
 // then u_j[pt] += Lz[pt][c] sum_b Ly[pt][b] D[b][pt].  A block takes 64 points
 // of one leaf (16 per wave); the z-slab of V sits in LDS.
-template <int P>
-__global__ __launch_bounds__(256) void k_leaf_eval(const EvalChunk* __restrict__ chunks, int nchunk,
-                                                   const double* __restrict__ Ltab, const double* __restrict__ V,
-                                                   int64_t n, double* __restrict__ u)
+template <int P, typename S>
+__global__ __launch_bounds__(kEvalChunk * 4) void k_leaf_eval(const EvalChunk* __restrict__ chunks, int nchunk,
+                                                              const double* __restrict__ Ltab,
+                                                              const S* __restrict__ V, int64_t n,
+                                                              double* __restrict__ u)
 {
     constexpr int PA = MCfg<P>::PA, NK = MCfg<P>::NK, NT = MCfg<P>::NT, RS = MCfg<P>::RS;
     constexpr int PB = 16 * NT;
     __shared__ double slab[3][PB][RS];
     const EvalChunk C = chunks[blockIdx.x];
-    const double* v = V + (size_t)C.fid * 3 * P * P * P;
+    const S* v = V + (size_t)C.fid * 3 * P * P * P;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int lr = l & 15, lk = l >> 4;
     const int64_t i = C.start + 16 * w + lr;
@@ -348,14 +362,14 @@ __global__ __launch_bounds__(256) void k_leaf_eval(const EvalChunk* __restrict__
             const int b = 16 * t + lk + 4 * r;
             wy[t][r] = (valid && b < P) ? Li[PA + b] : 0.0;
         }
-    for (int e = tid; e < 3 * PB * RS; e += 256)
+    for (int e = tid; e < 3 * PB * RS; e += kEvalChunk * 4)
         (&slab[0][0][0])[e] = 0.0;
     double u0 = 0, u1 = 0, u2 = 0;
     for (int c = 0; c < P; ++c) {
         __syncthreads();
-        for (int e = tid; e < 3 * P * P; e += 256) {
+        for (int e = tid; e < 3 * P * P; e += kEvalChunk * 4) {
             const int j = e / (P * P), r = e % (P * P);
-            slab[j][r / P][r % P] = v[(size_t)j * P * P * P + (size_t)c * P * P + r];
+            slab[j][r / P][r % P] = (double)v[(size_t)j * P * P * P + (size_t)c * P * P + r];
         }
         __syncthreads();
         const double lz = valid ? Li[2 * PA + c] : 0.0;
@@ -428,24 +442,33 @@ void launch_lagrange_table(int p, const LeafDesc* leaves, int nleaf, const doubl
 }
 
 void launch_anterp(int p, const LeafDesc* leaves, int nleaf, const double* Ltab, const double* fs, int64_t n,
-                   double* Q, hipStream_t s)
+                   void* Q, bool f32, hipStream_t s)
 {
     if (nleaf == 0)
         return;
-#define L_ANTERP(P)                                                                                        \
-    hipLaunchKernelGGL(k_anterp<P>, dim3(nleaf * AnterpCfg<P>::NA * AnterpCfg<P>::NBC),           \
-                       dim3(AnterpCfg<P>::threads), 0, s, leaves, nleaf, Ltab, fs, n, Q)
+#define L_ANTERP(P)                                                                                               \
+    if (f32)                                                                                                      \
+        hipLaunchKernelGGL((k_anterp<P, float>), dim3(nleaf * AnterpCfg<P>::NA * AnterpCfg<P>::NBC),            \
+                           dim3(AnterpCfg<P>::threads), 0, s, leaves, nleaf, Ltab, fs, n, (float*)Q);             \
+    else                                                                                                          \
+        hipLaunchKernelGGL((k_anterp<P, double>), dim3(nleaf * AnterpCfg<P>::NA * AnterpCfg<P>::NBC),           \
+                           dim3(AnterpCfg<P>::threads), 0, s, leaves, nleaf, Ltab, fs, n, (double*)Q)
     DMK_P_DISPATCH(p, L_ANTERP)
 #undef L_ANTERP
 }
 
-void launch_leaf_eval(int p, const EvalChunk* chunks, int nchunk, const double* Ltab, const double* V, int64_t n,
-                      double* u, hipStream_t s)
+void launch_leaf_eval(int p, const EvalChunk* chunks, int nchunk, const double* Ltab, const void* V, int64_t n,
+                      double* u, bool f32, hipStream_t s)
 {
     if (nchunk == 0)
         return;
-#define L_EVAL(P) \
-    hipLaunchKernelGGL(k_leaf_eval<P>, dim3(nchunk), dim3(256), 0, s, chunks, nchunk, Ltab, V, n, u)
+#define L_EVAL(P)                                                                                                 \
+    if (f32)                                                                                                      \
+        hipLaunchKernelGGL((k_leaf_eval<P, float>), dim3(nchunk), dim3(kEvalChunk * 4), 0, s, chunks, nchunk, Ltab, \
+                           (const float*)V, n, u);                                                                \
+    else                                                                                                          \
+        hipLaunchKernelGGL((k_leaf_eval<P, double>), dim3(nchunk), dim3(kEvalChunk * 4), 0, s, chunks, nchunk,    \
+                           Ltab, (const double*)V, n, u)
     DMK_P_DISPATCH(p, L_EVAL)
 #undef L_EVAL
 }
@@ -463,7 +486,7 @@ struct StageTraits {
 // outputs g, g+4, ... from it, and the output tile Y[r0..r0+64)[0..Nout) is
 // staged in LDS again and written as one contiguous block (or scatter-added to
 // the children's grids, one contiguous run of p per row and child).
-template <int MODE, int IO, int NI>
+template <int MODE, int IO, int NI, typename S>
 __global__ __launch_bounds__(256) void k_stage(StageArgs a)
 {
     using Tr = StageTraits<MODE>;
@@ -493,14 +516,14 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
                     const int B = r / (2 * p), C = r % (2 * p);
                     const int f = a.child_fid[slot * 8 + 4 * (k / p) + 2 * (B / p) + (C / p)];
                     if (f >= 0)
-                        v0 = ((const double*)a.X)[((size_t)f * 3 + comp) * p3 + ((size_t)(k % p) * p + (B % p)) * p +
-                                                  (C % p)];
+                        v0 = (double)((const S*)a.X)[((size_t)f * 3 + comp) * p3 +
+                                                     ((size_t)(k % p) * p + (B % p)) * p + (C % p)];
                 } else if (XE == 2) {
-                    const double2 v = ((const double2*)a.X)[xoff + (size_t)k * R + r];
-                    v0 = v.x;
-                    v1 = v.y;
+                    const typename Store<S>::cx v = ((const typename Store<S>::cx*)a.X)[xoff + (size_t)k * R + r];
+                    v0 = (double)v.x;
+                    v1 = (double)v.y;
                 } else {
-                    v0 = ((const double*)a.X)[xoff + (size_t)k * R + r];
+                    v0 = (double)((const S*)a.X)[xoff + (size_t)k * R + r];
                 }
             }
             if (XE == 2)
@@ -604,40 +627,51 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
     __syncthreads();
     if (IO == IO_SCATTER8) {
         // rows r = (C, B) of the child grid, output axis A; child (A/p, B/p, C/p)
-        double* Yd = (double*)a.Y;
+        S* Yd = (S*)a.Y;
         for (int e = tid; e < nrow * Nout; e += 256) {
             const int rr = e / Nout, A = e % Nout;
             const int r = r0 + rr;
             const int C = r / (2 * p), B = r % (2 * p);
             const int f = a.child_fid[slot * 8 + 4 * (A / p) + 2 * (B / p) + (C / p)];
-            if (f >= 0)
-                Yd[((size_t)f * 3 + comp) * p3 + ((size_t)(C % p) * p + (B % p)) * p + (A % p)] += tile[e];
+            if (f >= 0) {
+                S& y = Yd[((size_t)f * 3 + comp) * p3 + ((size_t)(C % p) * p + (B % p)) * p + (A % p)];
+                y = (S)((double)y + tile[e]);
+            }
         }
     } else {
         const size_t yoff = ((size_t)(a.ymap ? a.ymap[slot] : slot) * 3 + comp) * a.ystride * YE +
                             (size_t)r0 * Nout * YE;
-        double* Yd = (double*)a.Y + yoff;
+        S* Yd = (S*)a.Y + yoff;
         const int cnt = nrow * Nout * YE;
         if (a.accumulate) {
             for (int e = tid; e < cnt; e += 256)
-                Yd[e] += tile[e];
+                Yd[e] = (S)((double)Yd[e] + tile[e]);
         } else {
             for (int e = tid; e < cnt; e += 256)
-                Yd[e] = tile[e];
+                Yd[e] = (S)tile[e];
         }
     }
+}
+
+template <int MODE, int IO, int NI, typename S>
+static void stage_launch_t(dim3 grid, size_t shm, const StageArgs& a, hipStream_t s)
+{
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void*)k_stage<MODE, IO, NI, S>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_stage<MODE, IO, NI, S>), grid, dim3(256), shm, s, a);
 }
 
 template <int MODE, int IO, int NI>
 static void stage_launch(dim3 grid, size_t shm, const StageArgs& a, hipStream_t s)
 {
-    static bool attr = false;
-    if (!attr) {
-        (void)hipFuncSetAttribute((const void*)k_stage<MODE, IO, NI>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
-        attr = true;
-    }
-    hipLaunchKernelGGL((k_stage<MODE, IO, NI>), grid, dim3(256), shm, s, a);
+    if (a.f32)
+        stage_launch_t<MODE, IO, NI, float>(grid, shm, a, s);
+    else
+        stage_launch_t<MODE, IO, NI, double>(grid, shm, a, s);
 }
 
 template <int MODE, int IO>
@@ -681,14 +715,16 @@ void launch_stage(int mode, int io, const StageArgs& a, hipStream_t s)
 // (Phi[m_x][m_y][m_z]) and the receiver side z-major (Psi[m_z][m_y][m_x]); a
 // slab of fixed m_y is read as q runs of n1 contiguous modes, transposed in LDS
 // and written as n1 runs of q contiguous modes, so both sides stay coalesced.
+template <typename S>
 __global__ __launch_bounds__(256) void k_translate(int q, int n1, int nrecv, const RecvDesc* __restrict__ recv,
                                                    const int* __restrict__ e_src, const int8_t* __restrict__ e_off,
-                                                   const cplx* __restrict__ Phi, const double* __restrict__ wdiff,
-                                                   cplx* __restrict__ Psi)
+                                                   const typename Store<S>::cx* __restrict__ Phi,
+                                                   const double* __restrict__ wdiff,
+                                                   typename Store<S>::cx* __restrict__ Psi)
 {
     extern __shared__ cplx tile[];  // [3][m_z][m_x]
     const int H = q * n1 * n1;
-    const int S = q * n1;           // modes in the slab
+    const int NS = q * n1;          // modes in the slab
     // Blocks go round-robin over the 8 XCDs; give each XCD a contiguous run
     // of (slab, receiver) pairs with the receiver fastest, so that receivers
     // adjacent in Morton order -- which share most of their colleagues -- read
@@ -702,7 +738,7 @@ __global__ __launch_bounds__(256) void k_translate(int q, int n1, int nrecv, con
     const int m2 = iy - (q - 1);
     const double s3 = 0.86602540378443864676;
     const double lscale = (double)(1ll << rd.level);
-    for (int idx = threadIdx.x; idx < S; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < NS; idx += blockDim.x) {
         const int m1 = idx / n1;
         const int i3 = idx - m1 * n1;
         const int m3 = i3 - (q - 1);
@@ -717,9 +753,10 @@ __global__ __launch_bounds__(256) void k_translate(int q, int n1, int nrecv, con
             const double pi = tm == 0 ? 0.0 : (tm == 1 ? -s3 : s3);
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const cplx v = Phi[((size_t)src * 3 + j) * H + mi];
-                F[j][0] += pr * v.re - pi * v.im;
-                F[j][1] += pr * v.im + pi * v.re;
+                const typename Store<S>::cx v = Phi[((size_t)src * 3 + j) * H + mi];
+                const double vr = (double)v.x, vi = (double)v.y;
+                F[j][0] += pr * vr - pi * vi;
+                F[j][1] += pr * vi + pi * vr;
             }
         }
         const int mm = m1 * m1 + m2 * m2 + m3 * m3;
@@ -733,34 +770,44 @@ __global__ __launch_bounds__(256) void k_translate(int q, int n1, int nrecv, con
             tile[(j * n1 + i3) * q + m1] = cplx{w * (F[j][0] - mv[j] * dr), w * (F[j][1] - mv[j] * di)};
     }
     __syncthreads();
-    cplx* out = Psi + (size_t)rd.slot * 3 * H;
-    for (int idx = threadIdx.x; idx < 3 * S; idx += blockDim.x) {
-        const int j = idx / S;
-        const int r = idx - j * S;
+    typename Store<S>::cx* out = Psi + (size_t)rd.slot * 3 * H;
+    for (int idx = threadIdx.x; idx < 3 * NS; idx += blockDim.x) {
+        const int j = idx / NS;
+        const int r = idx - j * NS;
         const int i3 = r / q;
         const int m1 = r - i3 * q;
-        out[(size_t)j * H + ((size_t)i3 * n1 + iy) * q + m1] = tile[idx];
+        const cplx t = tile[idx];
+        out[(size_t)j * H + ((size_t)i3 * n1 + iy) * q + m1] = {(S)t.re, (S)t.im};
     }
 }
 
 void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int* e_src, const int8_t* e_off,
-                      const cplx* Phi, const double* wdiff, cplx* Psi, hipStream_t s)
+                      const void* Phi, const double* wdiff, void* Psi, bool f32, hipStream_t s)
 {
     if (nrecv == 0)
         return;
     const size_t lds = (size_t)3 * q * n1 * sizeof(cplx);
+    const int total = n1 * nrecv;
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void*)k_translate, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipFuncSetAttribute((const void*)k_translate<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        (void)hipFuncSetAttribute((const void*)k_translate<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
         attr = true;
     }
-    const int total = n1 * nrecv;
-    hipLaunchKernelGGL(k_translate, dim3(xcd_grid(total)), dim3(256), lds, s, q, n1, nrecv, recv, e_src, e_off,
-                       Phi, wdiff, Psi);
+    if (f32)
+        hipLaunchKernelGGL(k_translate<float>, dim3(xcd_grid(total)), dim3(256), lds, s, q, n1, nrecv, recv, e_src,
+                           e_off, (const float2*)Phi, wdiff, (float2*)Psi);
+    else
+        hipLaunchKernelGGL(k_translate<double>, dim3(xcd_grid(total)), dim3(256), lds, s, q, n1, nrecv, recv, e_src,
+                           e_off, (const double2*)Phi, wdiff, (double2*)Psi);
 }
 
-__global__ __launch_bounds__(256) void k_root_symbol(int mh, int mf, const cplx* __restrict__ Phi,
-                                                     const double* __restrict__ w, cplx* __restrict__ Psi)
+template <typename S>
+__global__ __launch_bounds__(256) void k_root_symbol(int mh, int mf, const typename Store<S>::cx* __restrict__ Phi,
+                                                     const double* __restrict__ w,
+                                                     typename Store<S>::cx* __restrict__ Psi)
 {
     const int H = mh * mf * mf;
     const int mi = blockIdx.x * blockDim.x + threadIdx.x;
@@ -771,23 +818,31 @@ __global__ __launch_bounds__(256) void k_root_symbol(int mh, int mf, const cplx*
     const int rem = mi - m1 * mf * mf;
     const int m2 = rem / mf - M, m3 = rem % mf - M;
     const int mm = m1 * m1 + m2 * m2 + m3 * m3;
-    cplx F[3];
-    for (int j = 0; j < 3; ++j)
-        F[j] = Phi[(size_t)j * H + mi];
+    double Fr[3], Fi[3];
+    for (int j = 0; j < 3; ++j) {
+        const typename Store<S>::cx v = Phi[(size_t)j * H + mi];
+        Fr[j] = (double)v.x;
+        Fi[j] = (double)v.y;
+    }
     const double ww = mm > 0 ? w[mm] : 0.0;
     const double inv = mm > 0 ? 1.0 / mm : 0.0;
-    const double dr = (m1 * F[0].re + m2 * F[1].re + m3 * F[2].re) * inv;
-    const double di = (m1 * F[0].im + m2 * F[1].im + m3 * F[2].im) * inv;
+    const double dr = (m1 * Fr[0] + m2 * Fr[1] + m3 * Fr[2]) * inv;
+    const double di = (m1 * Fi[0] + m2 * Fi[1] + m3 * Fi[2]) * inv;
     const int mv[3] = {m1, m2, m3};
     const size_t mo = ((size_t)(m3 + M) * mf + (m2 + M)) * mh + m1;
     for (int j = 0; j < 3; ++j)
-        Psi[(size_t)j * H + mo] = cplx{ww * (F[j].re - mv[j] * dr), ww * (F[j].im - mv[j] * di)};
+        Psi[(size_t)j * H + mo] = {(S)(ww * (Fr[j] - mv[j] * dr)), (S)(ww * (Fi[j] - mv[j] * di))};
 }
 
-void launch_root_symbol(int mh, int mf, const cplx* Phi, const double* w, cplx* Psi, hipStream_t s)
+void launch_root_symbol(int mh, int mf, const void* Phi, const double* w, void* Psi, bool f32, hipStream_t s)
 {
     const int H = mh * mf * mf;
-    hipLaunchKernelGGL(k_root_symbol, dim3(nblocks(H, 256)), dim3(256), 0, s, mh, mf, Phi, w, Psi);
+    if (f32)
+        hipLaunchKernelGGL(k_root_symbol<float>, dim3(nblocks(H, 256)), dim3(256), 0, s, mh, mf, (const float2*)Phi,
+                           w, (float2*)Psi);
+    else
+        hipLaunchKernelGGL(k_root_symbol<double>, dim3(nblocks(H, 256)), dim3(256), 0, s, mh, mf,
+                           (const double2*)Phi, w, (double2*)Psi);
 }
 
 // ---- near field -----------------------------------------------------------------
@@ -1161,14 +1216,15 @@ void launch_residual_direct(const double* tx, const double* ty, const double* tz
 }
 
 // ---- finishing --------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_sum_root(const double* __restrict__ Q, int p3, double coef,
+template <typename S>
+__global__ __launch_bounds__(256) void k_sum_root(const S* __restrict__ Q, int p3, double coef,
                                                   double* __restrict__ out)
 {
     __shared__ double sh[256];
     for (int j = 0; j < 3; ++j) {
         double s = 0;
         for (int k = threadIdx.x; k < p3; k += 256)
-            s += Q[(size_t)j * p3 + k];
+            s += (double)Q[(size_t)j * p3 + k];
         sh[threadIdx.x] = s;
         __syncthreads();
         for (int st = 128; st > 0; st >>= 1) {
@@ -1182,9 +1238,12 @@ __global__ __launch_bounds__(256) void k_sum_root(const double* __restrict__ Q, 
     }
 }
 
-void launch_sum_root(const double* Qroot, int p3, double coef, double* out, hipStream_t s)
+void launch_sum_root(const void* Qroot, int p3, double coef, double* out, bool f32, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sum_root, dim3(1), dim3(256), 0, s, Qroot, p3, coef, out);
+    if (f32)
+        hipLaunchKernelGGL(k_sum_root<float>, dim3(1), dim3(256), 0, s, (const float*)Qroot, p3, coef, out);
+    else
+        hipLaunchKernelGGL(k_sum_root<double>, dim3(1), dim3(256), 0, s, (const double*)Qroot, p3, coef, out);
 }
 
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ u, int64_t n, const int* __restrict__ perm,
@@ -1207,18 +1266,19 @@ void launch_finalize(const double* u, int64_t n, const int* perm, double scale, 
     hipLaunchKernelGGL(k_finalize, dim3(nblocks(n, 256)), dim3(256), 0, s, u, n, perm, scale, cst, vel);
 }
 
-__global__ __launch_bounds__(256) void k_zero(double* __restrict__ p, size_t count)
+__global__ __launch_bounds__(256) void k_zero(uint32_t* __restrict__ p, size_t count)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = 0.0;
+        p[i] = 0u;
 }
 
-void launch_zero(double* p, size_t count, hipStream_t s)
+void launch_zero(void* p, size_t bytes, hipStream_t s)
 {
+    const size_t count = bytes / 4;
     if (count == 0)
         return;
     const unsigned nb = (unsigned)std::min<size_t>((count + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_zero, dim3(nb), dim3(256), 0, s, p, count);
+    hipLaunchKernelGGL(k_zero, dim3(nb), dim3(256), 0, s, (uint32_t*)p, count);
 }
 
 }  // namespace dmk

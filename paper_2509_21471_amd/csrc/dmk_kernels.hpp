@@ -48,15 +48,17 @@ void launch_lagrange_table(int p, const LeafDesc* leaves, int nleaf, const doubl
                            const double* z, const double* cheb_t, const double* cheb_w, double* Ltab, hipStream_t s);
 // proxy charges of leaves (Step 2a): Q[fid][j][a][b][c] = sum_pt L_a L_b L_c f_j
 void launch_anterp(int p, const LeafDesc* leaves, int nleaf, const double* Ltab, const double* fs, int64_t n,
-                   double* Q, hipStream_t s);
+                   void* Q, bool f32, hipStream_t s);
 // far-field value at the points (final interpolation), V z-major V[fid][j][c][b][a]:
-// u[j][i] = sum V L L L, over chunks of at most 64 points of one leaf
+// u[j][i] = sum V L L L, over chunks of at most kEvalChunk points of one leaf
+// (one block of 4 kEvalChunk threads per chunk)
+constexpr int kEvalChunk = 256;
 struct EvalChunk {
     int fid;
     int64_t start, end;
 };
-void launch_leaf_eval(int p, const EvalChunk* chunks, int nchunk, const double* Ltab, const double* V, int64_t n,
-                      double* u, hipStream_t s);
+void launch_leaf_eval(int p, const EvalChunk* chunks, int nchunk, const double* Ltab, const void* V, int64_t n,
+                      double* u, bool f32, hipStream_t s);
 
 // ---- separable tensor stages ------------------------------------------------
 // Every far-field tensor stage contracts the leading axis of a per-(slot,
@@ -88,6 +90,7 @@ struct StageArgs {
     int nslots;
     int p;               // proxy order (gather / scatter addressing)
     const int* child_fid;// 8 per slot (gather / scatter)
+    int f32;             // X and Y hold float (else double); arithmetic is FP64
 };
 void launch_stage(int mode, int io, const StageArgs& a, hipStream_t s);
 
@@ -97,11 +100,12 @@ struct RecvDesc {
     int level;
     int ebeg, eend;   // entries in the entry arrays
 };
+// Phi / Psi hold complex float (f32) or complex double
 void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int* e_src /*sender slot*/,
-                      const int8_t* e_off /*3 per entry*/, const cplx* Phi, const double* wdiff, cplx* Psi,
+                      const int8_t* e_off /*3 per entry*/, const void* Phi, const double* wdiff, void* Psi, bool f32,
                       hipStream_t s);
 // root symbol multiply: Psi[j][mz][my][mx] = w(|m|^2) (I - m m^T/|m|^2) Phi[j][mx][my][mz]
-void launch_root_symbol(int mh, int mf, const cplx* Phi, const double* w, cplx* Psi, hipStream_t s);
+void launch_root_symbol(int mh, int mf, const void* Phi, const double* w, void* Psi, bool f32, hipStream_t s);
 
 // near field (Step 4); the self term comes out of the r = 0 pair
 struct NearLeaf {
@@ -142,10 +146,11 @@ void launch_residual_direct(const double* tx, const double* ty, const double* tz
                             const RadialPoly& poly, double* u, hipStream_t s);
 
 // out[j] = coef * sum of the root proxy charges (equals coef * net force)
-void launch_sum_root(const double* Qroot, int p3, double coef, double* out, hipStream_t s);
+void launch_sum_root(const void* Qroot, int p3, double coef, double* out, bool f32, hipStream_t s);
 // u_out[(rhs) n,3 original order] = scale * u[j][i] + cst[j]
 void launch_finalize(const double* u, int64_t n, const int* perm, double scale, const double* cst,
                      double* vel, hipStream_t s);
-void launch_zero(double* p, size_t count, hipStream_t s);
+// zero `bytes` (a multiple of 4) at p
+void launch_zero(void* p, size_t bytes, hipStream_t s);
 
 }  // namespace dmk

@@ -151,3 +151,35 @@ def test_clusters_4e6_fp64(dev):
     err = oracle.rel_l2(u[ref["idx"]], ref["u"])
     print("clusters_4e6", info["levels"], err)
     assert err < 1e-6
+
+
+@pytest.mark.parametrize("name,tol", [("uniform", 1e-6), ("clusters", 1e-6), ("periodic", 1e-6), ("clusters", 1e-7)])
+def test_mixed_precision(dev, name, tol):
+    """Mixed precision (FP32 far-field storage, FP64 arithmetic, FP64 near
+    field): within tol of the oracle and close to the FP64 plan."""
+    periodic = name == "periodic"
+    x, f = workloads.make(name, 20000, seed=77, sigma=0.05)
+    u64, _ = _eval(x, f, periodic=periodic, tol=tol, leaf_size=200)
+    u32, info = _eval(x, f, periodic=periodic, tol=tol, leaf_size=200, precision=1)
+    assert info["precision"] == 1
+    if periodic:
+        from oracle.ewald import ewald
+        idx = np.arange(0, x.shape[0], 40)
+        ref = ewald(x, f, idx)
+    else:
+        idx = np.arange(x.shape[0])
+        ref = oracle.direct(x, f)
+    e32, e64 = oracle.rel_l2(u32[idx], ref), oracle.rel_l2(u64[idx], ref)
+    print(name, tol, "mixed", e32, "fp64", e64, "mixed vs fp64", oracle.rel_l2(u32, u64))
+    assert e32 < tol
+
+
+def test_clusters_4e6_mixed(dev):
+    """4e6 clustered points (sigma 0.01), mixed precision at tol 1e-6, 10,000
+    sampled targets against the direct sum."""
+    ref = np.load(os.path.join(GOLDEN, "clusters_4e6_direct.npz"))
+    x, f = workloads.config("clusters_4e6")
+    u, info = _eval(x, f, tol=1e-6, precision=1)
+    err = oracle.rel_l2(u[ref["idx"]], ref["u"])
+    print("clusters_4e6 mixed", info["levels"], err)
+    assert err < 1e-6
