@@ -6,6 +6,8 @@ box, Morton sort, adaptive level-restricted octree, neighbour lists, device
 buffers; the per-tolerance tables are cached per process) followed by one
 evaluation (all far-field passes, near field, finalize), and the release of
 the previous step's plan.  Inputs are resident in HBM before timing starts.
+Steps are pipelined: plans are built with DMK_FLAG_CONCURRENT_PLAN, so the
+host part of step k+1's plan overlaps step k's evaluation on the GPU.
 
 Prints one JSON line (see the field list at the end of main()).
 """
@@ -168,61 +170,59 @@ def main():
     torch.cuda.synchronize()
     print(f"# input ready: {args.config} n={n} tol={tol}", file=sys.stderr, flush=True)
 
-    def make_plan():
+    def make_plan(prec):
         return dmk.Plan(xd, periodic=periodic, tol=tol, leaf_size=args.leaf_size, timing=True,
-                        near_lanes=args.near_lanes)
+                        near_lanes=args.near_lanes, precision=prec, concurrent=True)
 
-    # warmup (also builds the per-tolerance tables once)
-    for _ in range(args.warmup):
-        p = make_plan()
-        p.eval(fd, out)
+    def timed_steps(prec):
+        """Warmup, K timed plan+eval steps, then K eval-only repetitions on the
+        last plan.  Returns the measurements and the last plan (open)."""
+        for _ in range(args.warmup):
+            p = make_plan(prec)
+            p.eval(fd, out)
+            torch.cuda.synchronize()
+            p.close()
+        near_ms, phases_acc = [], []
+        prev = None
         torch.cuda.synchronize()
-        p.close()
-    print("# warmup done", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            p = make_plan(prec)
+            if prev is not None:
+                ph = prev.phase_ms()
+                phases_acc.append(ph)
+                near_ms.append(ph["near"])
+                prev.close()
+            p.eval(fd, out)
+            prev = p
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ph = prev.phase_ms()
+        phases_acc.append(ph)
+        near_ms.append(ph["near"])
+        ms_step = (t1 - t0) * 1e3 / args.steps
+        for _ in range(2):
+            prev.eval(fd, out)
+        torch.cuda.synchronize()
+        te0 = time.perf_counter()
+        for _ in range(args.steps):
+            prev.eval(fd, out)
+        torch.cuda.synchronize()
+        ms_eval = (time.perf_counter() - te0) * 1e3 / args.steps
+        phases = {k: float(np.mean([a[k] for a in phases_acc])) for k in phases_acc[0]}
+        return ms_step, ms_eval, phases, float(np.mean(near_ms)), prev
 
-    # timed region: K full steps (plan + eval)
-    near_ms, phases_acc = [], []
-    prev = None
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        p = make_plan()
-        if prev is not None:
-            ph = prev.phase_ms()
-            phases_acc.append(ph)
-            near_ms.append(ph["near"])
-            prev.close()
-        p.eval(fd, out)
-        prev = p
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ph = prev.phase_ms()
-    phases_acc.append(ph)
-    near_ms.append(ph["near"])
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    plan = prev
+    ms_per_step, eval_ms, phases, near_mean, plan = timed_steps(dmk.PREC_FP64)
     info = plan.info()
-    print(f"# timed: {ms_per_step:.2f} ms/step", file=sys.stderr, flush=True)
-
-    # eval-only rate on the last plan
-    for _ in range(2):
-        plan.eval(fd, out)
-    torch.cuda.synchronize()
-    te0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.eval(fd, out)
-    torch.cuda.synchronize()
-    eval_ms = (time.perf_counter() - te0) * 1e3 / args.steps
-
+    print(f"# timed: {ms_per_step:.2f} ms/step, eval {eval_ms:.2f} ms", file=sys.stderr, flush=True)
     stats = plan.near_stats()
     fpp = near_flops_per_pair(info["deg_P"], info["deg_Q"])
-    t_near = float(np.mean(near_ms)) * 1e-3
+    t_near = near_mean * 1e-3
     achieved = stats["in_support"] * fpp / t_near / 1e12
-    phases = {k: float(np.mean([a[k] for a in phases_acc])) for k in phases_acc[0]}
 
-    near_kernel = f"dmk::k_near<{nd_bucket(info['deg_P'], info['deg_Q'])}, {info['near_lanes']}>"
+    near_kernel = f"dmk::k_near<{nd_bucket(info['deg_P'], info['deg_Q'])}, {info['near_lanes']}, 1>"
     traffic = None
-    if args.leaf_size == 0:
+    if args.leaf_size == 0 and args.near_lanes == 0:
         traffic = near_traffic(args.config, tol, "fp64", near_kernel)
     result = {
         "metric": METRIC,
@@ -254,20 +254,34 @@ def main():
                                       "deg_Q")},
     }
 
+    u64 = out.cpu().numpy()
+    plan.close()
     if not args.no_variants:
-        result["variants"] = {"multi_rhs": multi_rhs_variant(args, dev, not args.no_parity)}
+        mixed = {}
+        m_step, m_eval, m_phases, m_near, mplan = timed_steps(dmk.PREC_MIXED)
+        mixed = {"precision": "mixed (FP32 far-field storage, FP64 arithmetic)", "workload": args.config,
+                 "ms_per_step": m_step, "targets_per_s": n / (m_step * 1e-3), "eval_only_ms": m_eval,
+                 "eval_only_targets_per_s": n / (m_eval * 1e-3), "phases_ms": m_phases,
+                 "device_bytes": mplan.info()["device_bytes"],
+                 "speedup_vs_fp64_step": ms_per_step / m_step, "speedup_vs_fp64_eval": eval_ms / m_eval}
+        u32 = out.cpu().numpy()
+        mplan.close()
+        print(f"# mixed: {m_step:.2f} ms/step, eval {m_eval:.2f} ms", file=sys.stderr, flush=True)
+        result["variants"] = {"mixed": mixed, "multi_rhs": multi_rhs_variant(args, dev, not args.no_parity)}
 
     if not args.no_parity:
         import oracle
         idx = workloads.sample_targets(n, args.parity_sample, cfg["seed"])
-        u = out.cpu().numpy()
         if periodic:
             from oracle.ewald import ewald
             ref = ewald(x, f, idx, E=25.0)
         else:
             ref = oracle.direct(x, f, idx)
-        result["rel_l2_sampled"] = oracle.rel_l2(u[idx], ref)
+        result["rel_l2_sampled"] = oracle.rel_l2(u64[idx], ref)
         result["parity_sample"] = int(idx.size)
+        if "variants" in result:
+            result["variants"]["mixed"]["rel_l2_sampled"] = oracle.rel_l2(u32[idx], ref)
+            result["variants"]["mixed"]["rel_l2_vs_fp64"] = oracle.rel_l2(u32, u64)
 
     if not args.no_cpu_baseline and not periodic:
         import oracle
@@ -279,7 +293,6 @@ def main():
                                   "kind": "oracle",
                                   "sample": f"{idx.size} seeded targets of the {n}-point input, each summing "
                                             f"all {n} sources (direct O(N^2) FP64 sum), {tc:.1f} s"}
-    plan.close()
     print(json.dumps(result), flush=True)
 
 

@@ -49,11 +49,17 @@ typedef enum {
     DMK_ERR_UNSUPPORTED = -2,  /* dim != 3 */
     DMK_ERR_DOMAIN = -3,       /* periodic point outside [0,1)^3 */
     DMK_ERR_NONFINITE = -4,    /* NaN or Inf among the points */
-    DMK_ERR_TOL = -5,          /* tol outside [1e-12, 1e-3] (mixed precision: [1e-7, 1e-3]) */
+    DMK_ERR_TOL = -5,          /* tol outside [1e-12, 1e-3] (mixed precision: [1e-6, 1e-3]) */
     DMK_ERR_OOM = -6,          /* device allocation failed or exceeds opts.mem_cap_bytes */
     DMK_ERR_HIP = -7           /* a HIP runtime call failed */
 } dmk_status;
 
+/* FP64: every buffer and operation in double precision.
+ * MIXED: the far-field buffers (proxy charges and potentials, plane-wave
+ * expansions, stage intermediates) are stored as float, halving their memory
+ * and traffic; all arithmetic, the near field, the tree geometry and the
+ * accumulation at the points stay FP64.  Relative errors gain about 1.2e-7, so
+ * MIXED needs tol >= 1e-6. */
 typedef enum { DMK_PREC_FP64 = 0, DMK_PREC_MIXED = 1 } dmk_precision;
 
 typedef struct {
@@ -79,6 +85,12 @@ typedef struct {
 /* record HIP events around each phase of dmk_stokes_eval (read back with
  * dmk_stokes_phase_ms) */
 #define DMK_FLAG_PHASE_TIMING 1
+/* the points are complete when the plan call is made (no writes to them are
+ * pending on any stream): the plan is built on the library's own
+ * non-blocking stream, so its device work and host tree construction overlap
+ * work already queued on opts.stream (e.g. the previous plan's evaluation).
+ * Without the flag the plan is built in order on opts.stream. */
+#define DMK_FLAG_CONCURRENT_PLAN 2
 
 /* phases reported by dmk_stokes_phase_ms, in this order */
 #define DMK_PHASE_ANTERP 0     /* force gather + leaf proxy charges (Step 2a) */
@@ -180,7 +192,8 @@ int dmk_stokes_phase_ms(dmk_plan_t plan, double* out);
  */
 int dmk_stokes_near_stats(dmk_plan_t plan, int64_t* listed, int64_t* evaluated, int64_t* in_support);
 
-/* Releases the plan (NULL-safe).  Its device buffers return to the library's
+/* Releases the plan (NULL-safe).  Waits for the plan's most recent
+ * evaluation to finish; its device buffers then return to the library's
  * per-process cache and are reused by later plans of similar size. */
 void dmk_stokes_destroy(dmk_plan_t plan);
 

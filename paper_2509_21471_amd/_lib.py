@@ -26,6 +26,7 @@ SYMBOLS = ["dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_eval", "dmk_stok
 PHASES = ["anterp", "merge", "outgoing", "translate", "incoming", "root", "interp", "leaf_eval", "near",
           "finalize"]
 FLAG_PHASE_TIMING = 1
+FLAG_CONCURRENT_PLAN = 2
 
 
 class DMKError(RuntimeError):
@@ -174,13 +175,14 @@ class Plan:
 
     def __init__(self, points, periodic: bool = False, tol: float = 1e-6, precision: int = PREC_FP64,
                  leaf_size: int = 0, stream=None, mem_cap_bytes: int = 0, timing: bool = False,
-                 near_lanes: int = 0, q: int = 0, p: int = 0, rhs_batch: int = 0):
+                 near_lanes: int = 0, q: int = 0, p: int = 0, rhs_batch: int = 0, concurrent: bool = False):
         torch = _torch()
         pts = _dev_f64(points)
         self.n = int(pts.shape[0])
         self.stream = stream
         opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), int(mem_cap_bytes),
-                    FLAG_PHASE_TIMING if timing else 0, int(near_lanes), int(q), int(p), int(rhs_batch))
+                    (FLAG_PHASE_TIMING if timing else 0) | (FLAG_CONCURRENT_PLAN if concurrent else 0),
+                    int(near_lanes), int(q), int(p), int(rhs_batch))
         h = ctypes.c_void_p()
         _check(lib().dmk_stokes_plan_ex(ctypes.c_void_p(pts.data_ptr()), self.n, 3, int(bool(periodic)),
                                         float(tol), ctypes.byref(opts), ctypes.byref(h)))

@@ -90,7 +90,8 @@ def test_plan_argument_validation_without_gpu():
     assert lib.dmk_stokes_plan(vp, 10, 3, 0, 1e-13, ctypes.byref(out)) == -5
     assert lib.dmk_stokes_plan(vp, 10, 3, 2, 1e-6, ctypes.byref(out)) == -1        # periodic flag
     opts = dmk._lib.Opts(1, 0, None, 0, 0, 0, 0, 0, 0)
-    assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-9, ctypes.byref(opts), ctypes.byref(out)) == -5  # mixed < 1e-7
+    assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-9, ctypes.byref(opts), ctypes.byref(out)) == -5  # mixed < 1e-6
+    assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 5e-7, ctypes.byref(opts), ctypes.byref(out)) == -5
     bad_p = dmk._lib.Opts(0, 0, None, 0, 0, 0, 0, 35, 0)
     assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-6, ctypes.byref(bad_p), ctypes.byref(out)) == -1  # p not compiled
     bad_q = dmk._lib.Opts(0, 0, None, 0, 0, 0, 41, 0, 0)
