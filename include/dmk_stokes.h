@@ -147,6 +147,23 @@ int dmk_stokes_plan_ex(const double* points, int64_t n, int dim, int periodic, d
                        dmk_plan_t* out);
 
 /*
+ * Builds one plan over n_problems independent problems (each its own free-space
+ * sum, or its own periodic unit cell), evaluated together: every pass of
+ * dmk_stokes_eval covers all problems in one launch per stage.
+ *   points      device, (n,3) row-major float64, the problems concatenated:
+ *               problem b is points[offsets[b] .. offsets[b+1])
+ *   offsets     HOST array of n_problems + 1 int64: offsets[0] = 0, strictly
+ *               increasing (every problem has at least one point), n = offsets[n_problems]
+ *   n_problems  in [1, 2^20]
+ * Each problem gets its own bounding cube and octree (a forest); points of
+ * different problems never interact.  forces / velocities of dmk_stokes_eval
+ * follow the same concatenated order.  Other arguments as dmk_stokes_plan_ex;
+ * plan_info reports the forest (center/box_len: problem 0).
+ */
+int dmk_stokes_plan_batch(const double* points, const int64_t* offsets, int n_problems, int dim, int periodic,
+                          double tol, const dmk_opts* opts, dmk_plan_t* out);
+
+/*
  * Evaluates the sums for n_rhs force vectors on the plan's points.
  *   forces      device, (n_rhs, n, 3) float64, caller's point order
  *   velocities  device, (n_rhs, n, 3) float64, overwritten

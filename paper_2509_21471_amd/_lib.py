@@ -19,7 +19,7 @@ STATUS = {0: "DMK_OK", -1: "DMK_ERR_ARG", -2: "DMK_ERR_UNSUPPORTED", -3: "DMK_ER
           -4: "DMK_ERR_NONFINITE", -5: "DMK_ERR_TOL", -6: "DMK_ERR_OOM", -7: "DMK_ERR_HIP"}
 PREC_FP64, PREC_MIXED = 0, 1
 
-SYMBOLS = ["dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_eval", "dmk_stokes_plan_info",
+SYMBOLS = ["dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_plan_batch", "dmk_stokes_eval", "dmk_stokes_plan_info",
            "dmk_stokes_tree_leaves", "dmk_stokes_destroy", "dmk_last_error", "dmk_stokes_params",
            "dmk_stokes_radial", "dmk_stokes_mollifier", "dmk_stokes_residual_sum", "dmk_stokes_phase_ms",
            "dmk_stokes_near_stats", "dmk_stokes_release_cached_memory", "dmk_stokes_host_tree"]
@@ -75,6 +75,8 @@ def lib():
         L.dmk_stokes_plan.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(vp)]
         L.dmk_stokes_plan_ex.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                          ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+        L.dmk_stokes_plan_batch.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                            ctypes.POINTER(Opts), ctypes.POINTER(vp)]
         L.dmk_stokes_eval.argtypes = [vp, vp, ctypes.c_int, vp]
         L.dmk_stokes_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
         L.dmk_stokes_tree_leaves.argtypes = [vp, vp, vp, vp, vp]
@@ -175,7 +177,10 @@ class Plan:
 
     def __init__(self, points, periodic: bool = False, tol: float = 1e-6, precision: int = PREC_FP64,
                  leaf_size: int = 0, stream=None, mem_cap_bytes: int = 0, timing: bool = False,
-                 near_lanes: int = 0, q: int = 0, p: int = 0, rhs_batch: int = 0, concurrent: bool = False):
+                 near_lanes: int = 0, q: int = 0, p: int = 0, rhs_batch: int = 0, concurrent: bool = False,
+                 offsets=None):
+        """offsets (host int sequence, n_problems + 1 entries) makes a batched
+        plan over independent problems (dmk_stokes_plan_batch)."""
         torch = _torch()
         pts = _dev_f64(points)
         self.n = int(pts.shape[0])
@@ -184,8 +189,17 @@ class Plan:
                     (FLAG_PHASE_TIMING if timing else 0) | (FLAG_CONCURRENT_PLAN if concurrent else 0),
                     int(near_lanes), int(q), int(p), int(rhs_batch))
         h = ctypes.c_void_p()
-        _check(lib().dmk_stokes_plan_ex(ctypes.c_void_p(pts.data_ptr()), self.n, 3, int(bool(periodic)),
-                                        float(tol), ctypes.byref(opts), ctypes.byref(h)))
+        if offsets is None:
+            _check(lib().dmk_stokes_plan_ex(ctypes.c_void_p(pts.data_ptr()), self.n, 3, int(bool(periodic)),
+                                            float(tol), ctypes.byref(opts), ctypes.byref(h)))
+        else:
+            off = np.ascontiguousarray(offsets, dtype=np.int64)
+            if off.ndim != 1 or off.size < 2 or off[-1] != self.n:
+                raise ValueError("offsets must hold n_problems + 1 entries ending at n")
+            _check(lib().dmk_stokes_plan_batch(ctypes.c_void_p(pts.data_ptr()),
+                                               off.ctypes.data_as(ctypes.c_void_p), int(off.size - 1), 3,
+                                               int(bool(periodic)), float(tol), ctypes.byref(opts),
+                                               ctypes.byref(h)))
         self._h = h
         self._torch = torch
 

@@ -196,7 +196,16 @@ struct dmk_plan_s {
     dmk::RadialPoly poly;
     // far-field structure
     int nf = 0;                       // non-empty boxes (far-field slots)
-    int root_fid = 0;
+    // independent problems of a batched plan (one problem for dmk_stokes_plan)
+    int nprob = 1;
+    std::vector<int64_t> offsets;     // point ranges of the problems, caller's order
+    int64_t* d_off = nullptr;
+    int* pid = nullptr;               // problem of each point (NULL for one problem)
+    double* geo = nullptr;            // per problem: centre (3), 1 / cube side
+    double* scale = nullptr;          // per problem: 1 / cube side (velocity scaling)
+    std::vector<double> h_center, h_len;
+    std::vector<int> root_fid;        // far-field slot of each problem's root
+    int* d_root_fid = nullptr;
     std::vector<int> box_fid;         // box id -> fid or -1
     dmk::LeafDesc* leaves = nullptr;  // non-empty leaves
     int nleaf = 0;
@@ -372,63 +381,111 @@ int build_plan(dmk_plan_t P, const double* points)
         tlast = now;
     };
     const int64_t n = P->n;
-    // ---- bounding box and finiteness ----
-    const int nblk = (int)std::min<int64_t>(1024, (n + 255) / 256);
-    double* part = P->mem.alloc<double>((size_t)nblk * 8);
-    if (!part)
-        return fail(DMK_ERR_OOM, "device allocation failed");
-    launch_bbox(points, n, part, nblk, st);
-    std::vector<double> hp((size_t)nblk * 8);
-    HIPCHK(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, bad = 0;
-    for (int b = 0; b < nblk; ++b) {
+    const int np = P->nprob;
+    // ---- bounding boxes and finiteness (per problem) ----
+    std::vector<double> hp;
+    if (np == 1) {
+        const int nblk = (int)std::min<int64_t>(1024, (n + 255) / 256);
+        double* part = P->mem.alloc<double>((size_t)nblk * 8);
+        if (!part)
+            return fail(DMK_ERR_OOM, "device allocation failed");
+        launch_bbox(points, n, part, nblk, st);
+        std::vector<double> hb((size_t)nblk * 8);
+        HIPCHK(hipMemcpyAsync(hb.data(), part, hb.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        hp.assign(8, 0.0);
         for (int d = 0; d < 3; ++d) {
-            lo[d] = std::min(lo[d], hp[8 * b + d]);
-            hi[d] = std::max(hi[d], hp[8 * b + 3 + d]);
+            hp[d] = 1e300;
+            hp[3 + d] = -1e300;
         }
-        bad += hp[8 * b + 6];
-    }
-    if (bad > 0)
-        return fail(DMK_ERR_NONFINITE, "points contain NaN or Inf");
-    double inv_len;
-    if (P->periodic) {
-        for (int d = 0; d < 3; ++d)
-            if (lo[d] < 0.0 || hi[d] >= 1.0)
-                return fail(DMK_ERR_DOMAIN, "periodic points must lie in [0,1)^3");
-        P->center[0] = P->center[1] = P->center[2] = 0.5;
-        P->box_len = 1.0;
+        for (int b = 0; b < nblk; ++b) {
+            for (int d = 0; d < 3; ++d) {
+                hp[d] = std::min(hp[d], hb[8 * b + d]);
+                hp[3 + d] = std::max(hp[3 + d], hb[8 * b + 3 + d]);
+            }
+            hp[6] += hb[8 * b + 6];
+        }
     } else {
-        double ext = 0;
-        for (int d = 0; d < 3; ++d) {
-            P->center[d] = 0.5 * (lo[d] + hi[d]);
-            ext = std::max(ext, hi[d] - lo[d]);
-        }
-        if (ext <= 0)
-            ext = 1.0;
-        // slightly larger cube so that all unit coordinates lie in [-1/2, 1/2)
-        P->box_len = ext * (1.0 + 1e-9);
+        P->d_off = P->mem.alloc<int64_t>(np + 1);
+        double* part = P->mem.alloc<double>((size_t)np * 8);
+        P->pid = P->mem.alloc<int>(n);
+        if (P->mem.oom)
+            return fail(DMK_ERR_OOM, "device allocation failed");
+        HIPCHK(upload(P->d_off, P->offsets, st));
+        launch_bbox_seg(points, P->d_off, np, part, st);
+        launch_fill_pid(P->d_off, np, n, P->pid, st);
+        hp.resize((size_t)np * 8);
+        HIPCHK(hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
     }
-    inv_len = 1.0 / P->box_len;
+    P->h_center.assign(3 * (size_t)np, 0.5);
+    P->h_len.assign(np, 1.0);
+    std::vector<double> geo(4 * (size_t)np), scl(np);
+    for (int b = 0; b < np; ++b) {
+        const double* lo = &hp[8 * b];
+        const double* hi = &hp[8 * b + 3];
+        if (hp[8 * b + 6] > 0)
+            return fail(DMK_ERR_NONFINITE, "points contain NaN or Inf");
+        if (P->periodic) {
+            for (int d = 0; d < 3; ++d)
+                if (lo[d] < 0.0 || hi[d] >= 1.0)
+                    return fail(DMK_ERR_DOMAIN, "periodic points must lie in [0,1)^3");
+        } else {
+            double ext = 0;
+            for (int d = 0; d < 3; ++d) {
+                P->h_center[3 * b + d] = 0.5 * (lo[d] + hi[d]);
+                ext = std::max(ext, hi[d] - lo[d]);
+            }
+            if (ext <= 0)
+                ext = 1.0;
+            // slightly larger cube so that all unit coordinates lie in [-1/2, 1/2)
+            P->h_len[b] = ext * (1.0 + 1e-9);
+        }
+        for (int d = 0; d < 3; ++d)
+            geo[4 * b + d] = P->h_center[3 * b + d];
+        geo[4 * b + 3] = 1.0 / P->h_len[b];
+        scl[b] = 1.0 / P->h_len[b];
+    }
+    for (int d = 0; d < 3; ++d)
+        P->center[d] = P->h_center[d];
+    P->box_len = P->h_len[0];
+    P->geo = P->mem.alloc<double>(geo.size());
+    P->scale = P->mem.alloc<double>(scl.size());
+    if (P->mem.oom)
+        return fail(DMK_ERR_OOM, "device allocation failed");
+    HIPCHK(upload(P->geo, geo, st));
+    HIPCHK(upload(P->scale, scl, st));
     lap(0);
-    // ---- Morton keys and sort ----
+    // ---- Morton keys and sort (within each problem) ----
     uint64_t* k0 = P->mem.alloc<uint64_t>(n);
     uint64_t* k1 = P->mem.alloc<uint64_t>(n);
     int* i0 = P->mem.alloc<int>(n);
     P->perm = P->mem.alloc<int>(n);
-    const size_t tb = sort_temp_bytes(n);
+    const size_t tb = np == 1 ? sort_temp_bytes(n) : seg_sort_temp_bytes(n, np);
     void* tmp = P->mem.alloc<char>(tb);
     if (P->mem.oom)
         return fail(DMK_ERR_OOM, "device allocation failed");
-    launch_morton(points, n, P->center[0], P->center[1], P->center[2], inv_len, k0, i0, st);
-    launch_sort(tmp, tb, k0, k1, i0, P->perm, n, 3 * kKeyBits, st);
+    launch_morton(points, n, P->pid, P->geo, k0, i0, st);
+    if (np == 1)
+        launch_sort(tmp, tb, k0, k1, i0, P->perm, n, 3 * kKeyBits, st);
+    else
+        launch_seg_sort(tmp, tb, k0, k1, i0, P->perm, n, np, P->d_off, 3 * kKeyBits, st);
     std::vector<uint64_t> keys(n);
     HIPCHK(hipMemcpyAsync(keys.data(), k1, n * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     lap(1);
-    // ---- tree ----
+    // ---- tree (a forest of one octree per problem) ----
     const int ns = P->prm.ns;
-    build_tree(keys.data(), n, ns, P->periodic, &P->tree);
+    std::vector<int> roots(1, 0);
+    if (np == 1) {
+        build_tree(keys.data(), n, ns, P->periodic, &P->tree);
+    } else {
+        std::vector<Tree> parts(np);
+#pragma omp parallel for schedule(dynamic)
+        for (int b = 0; b < np; ++b)
+            build_tree(keys.data() + P->offsets[b], P->offsets[b + 1] - P->offsets[b], ns, P->periodic, &parts[b]);
+        merge_forest(parts, P->offsets, &P->tree, &roots);
+    }
     lap(2);
     const Tree& T = P->tree;
     // ---- sorted points ----
@@ -437,8 +494,7 @@ int build_plan(dmk_plan_t P, const double* points)
     P->z = P->mem.alloc<double>(n);
     if (P->mem.oom)
         return fail(DMK_ERR_OOM, "device allocation failed");
-    launch_gather_points(points, n, P->perm, P->center[0], P->center[1], P->center[2], inv_len, P->x, P->y, P->z,
-                         st);
+    launch_gather_points(points, n, P->perm, P->pid, P->geo, P->x, P->y, P->z, st);
     // ---- far-field slots ----
     const int nb = (int)T.boxes.size();
     P->box_fid.assign(nb, -1);
@@ -446,7 +502,9 @@ int build_plan(dmk_plan_t P, const double* points)
     for (int i = 0; i < nb; ++i)
         if (T.boxes[i].end > T.boxes[i].start)
             P->box_fid[i] = P->nf++;
-    P->root_fid = P->box_fid[0];
+    P->root_fid.clear();
+    for (int r : roots)
+        P->root_fid.push_back(P->box_fid[r]);
     auto center = [&](const Box& B, double* c) {
         const double h = 1.0 / (double)(1ll << B.level);
         c[0] = -0.5 + (B.ix + 0.5) * h;
@@ -647,15 +705,17 @@ int build_plan(dmk_plan_t P, const double* points)
         const size_t mh = P->root_mh, mf = P->root_mf;
         per_root = std::max({(size_t)p * p * mh, (size_t)p * mh * mf, mf * mf * (size_t)p, mf * (size_t)p * p}) * cs;
     }
-    const size_t sbytes = std::max(per * 3 * (size_t)maxslots, per_root * 3);
+    const size_t sbytes = std::max(per * 3 * (size_t)maxslots, per_root * 3 * (size_t)np);
     P->s1 = P->mem.alloc<char>(sbytes);
     P->s2 = P->mem.alloc<char>(sbytes);
-    P->phi_root = P->mem.alloc<char>(3 * P->Hroot * cs);
-    P->psi_root = P->mem.alloc<char>(3 * P->Hroot * cs);
-    P->cst = P->mem.alloc<double>(3 * (size_t)P->rhs_batch);
+    P->phi_root = P->mem.alloc<char>(3 * P->Hroot * cs * np);
+    P->psi_root = P->mem.alloc<char>(3 * P->Hroot * cs * np);
+    P->cst = P->mem.alloc<double>(3 * (size_t)P->rhs_batch * np);
+    P->d_root_fid = P->mem.alloc<int>(np);
     if (P->mem.oom)
         return fail(DMK_ERR_OOM, "device allocation failed (or above mem_cap_bytes)");
     lap(4);
+    HIPCHK(upload(P->d_root_fid, P->root_fid, st));
     HIPCHK(upload(P->leaves, hl, st));
     HIPCHK(upload(P->echunks, ech, st));
     HIPCHK(upload(P->send_fid, sfid, st));
@@ -698,7 +758,7 @@ void far_field(dmk_plan_t P, int r, bool record)
     const int64_t n = P->n;
     const double* fs = P->fs + (size_t)r * 3 * n;
     double* u = P->u + (size_t)r * 3 * n;
-    double* cst = P->cst + 3 * r;
+    double* cst = P->cst + (size_t)3 * P->nprob * r;
     const int p = P->prm.p, q = P->prm.q, n1 = P->prm.n1;
     const long p3 = (long)p * p * p, p2 = (long)p * p;
     const Tree& T = P->tree;
@@ -744,24 +804,23 @@ void far_field(dmk_plan_t P, int r, bool record)
     {
         const int mh = P->root_mh, mf = P->root_mf, RM = mh - 1;
         const long Hr = (long)P->Hroot;
-        const int rf = P->root_fid;
-        const char* Qr = (const char*)P->Q + (size_t)rf * 3 * p3 * P->es;
-        char* Vr = (char*)P->V + (size_t)rf * 3 * p3 * P->es;
-        stage(P, ST_OUT_HALF, IO_PLAIN, Qr, p3, nullptr, P->s1, p2 * mh, nullptr, 0, P->r_out, p, mh, 0, 0, h, mh,
-              p * p, 1);
+        const int nr = P->nprob;  // one root per problem; stage slots map to their far-field slots
+        stage(P, ST_OUT_HALF, IO_PLAIN, P->Q, p3, P->d_root_fid, P->s1, p2 * mh, nullptr, 0, P->r_out, p, mh, 0, 0, h,
+              mh, p * p, nr);
         stage(P, ST_OUT_FULL, IO_PLAIN, P->s1, p2 * mh, nullptr, P->s2, (long)p * mh * mf, nullptr, 0, P->r_out, p, mf,
-              0, RM, h, mh, p * mh, 1);
+              0, RM, h, mh, p * mh, nr);
         stage(P, ST_OUT_FULL, IO_PLAIN, P->s2, (long)p * mh * mf, nullptr, P->phi_root, Hr, nullptr, 0, P->r_out, p,
-              mf, 0, RM, h, mh, mh * mf, 1);
-        launch_root_symbol(mh, mf, P->phi_root, P->wroot, P->psi_root, P->f32, st);
+              mf, 0, RM, h, mh, mh * mf, nr);
+        launch_root_symbol(mh, mf, nr, P->phi_root, P->wroot, P->psi_root, P->f32, st);
         stage(P, ST_IN_FULL, IO_PLAIN, P->psi_root, Hr, nullptr, P->s1, (long)mf * mh * p, nullptr, 0, P->r_in_full,
-              mf, p, RM, 0, mh, h, mf * mh, 1);
+              mf, p, RM, 0, mh, h, mf * mh, nr);
         stage(P, ST_IN_FULL, IO_PLAIN, P->s1, (long)mf * mh * p, nullptr, P->s2, (long)mh * p * p, nullptr, 0,
-              P->r_in_full, mf, p, RM, 0, mh, h, mh * p, 1);
-        stage(P, ST_IN_HALF_REAL, IO_PLAIN, P->s2, (long)mh * p * p, nullptr, Vr, p3, nullptr, 1, P->r_in_half, mh, p,
-              0, 0, mh, h, p * p, 1);
+              P->r_in_full, mf, p, RM, 0, mh, h, mh * p, nr);
+        stage(P, ST_IN_HALF_REAL, IO_PLAIN, P->s2, (long)mh * p * p, nullptr, P->V, p3, P->d_root_fid, 1, P->r_in_half,
+              mh, p, 0, 0, mh, h, p * p, nr);
         if (!P->periodic)
-            launch_sum_root(Qr, (int)p3, 1.0 / (4.0 * kPi * (1.0 + std::sqrt(3.0))), cst, P->f32, st);
+            launch_sum_root(P->Q, P->d_root_fid, nr, (int)p3, 1.0 / (4.0 * kPi * (1.0 + std::sqrt(3.0))), cst, P->f32,
+                            st);
     }
     mark(6);
     // downward interpolation, coarsest level first (V is z-major, all axes alike)
@@ -804,8 +863,8 @@ int eval_batch(dmk_plan_t P, const double* f, int nb, double* vel, bool record)
     if (record)
         (void)hipEventRecord(P->ev[9], st);
     for (int r = 0; r < nb; ++r)
-        launch_finalize(P->u + (size_t)r * 3 * n, n, P->perm, 1.0 / P->box_len,
-                        P->periodic ? nullptr : P->cst + 3 * r, vel + (size_t)r * 3 * n, st);
+        launch_finalize(P->u + (size_t)r * 3 * n, n, P->perm, P->pid, P->scale,
+                        P->periodic ? nullptr : P->cst + (size_t)3 * P->nprob * r, vel + (size_t)r * 3 * n, st);
     if (record) {
         (void)hipEventRecord(P->ev[10], st);
         P->ev_recorded = true;
@@ -874,18 +933,14 @@ int dmk_stokes_mollifier(double tol, const double* k, int64_t n, double* out)
     return DMK_OK;
 }
 
-int dmk_stokes_plan_ex(const double* points, int64_t n, int dim, int periodic, double tol, const dmk_opts* opts,
-                       dmk_plan_t* out)
+namespace {
+
+// Common plan construction for one problem (offsets {0, n}) or a batch.
+int create_plan(const double* points, const std::vector<int64_t>& offsets, int dim, int periodic, double tol,
+                const dmk_opts* opts, dmk_plan_t* out)
 {
-    if (!out)
-        return fail(DMK_ERR_ARG, "out is NULL");
-    *out = nullptr;
-    if (!points)
-        return fail(DMK_ERR_ARG, "points is NULL");
-    if (n < 1)
-        return fail(DMK_ERR_ARG, "n must be >= 1");
-    if (n > (int64_t)2000000000)
-        return fail(DMK_ERR_ARG, "n too large");
+    const int64_t n = offsets.back();
+
     int rc = validate_common(dim, tol, opts);
     if (rc != DMK_OK)
         return rc;
@@ -933,15 +988,56 @@ int dmk_stokes_plan_ex(const double* points, int64_t n, int dim, int periodic, d
             }
     P->n = n;
     P->periodic = periodic != 0;
+    P->nprob = (int)offsets.size() - 1;
+    P->offsets = offsets;
     rc = build_plan(P, points);
     if (rc != DMK_OK) {
-        (void)hipStreamSynchronize(P->stream);
+        (void)hipStreamSynchronize(P->concurrent ? plan_stream() : P->stream);
         delete P;
         return rc;
     }
     P->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = P;
     return DMK_OK;
+}
+
+
+}  // namespace
+
+int dmk_stokes_plan_ex(const double* points, int64_t n, int dim, int periodic, double tol, const dmk_opts* opts,
+                       dmk_plan_t* out)
+{
+    if (!out)
+        return fail(DMK_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!points)
+        return fail(DMK_ERR_ARG, "points is NULL");
+    if (n < 1)
+        return fail(DMK_ERR_ARG, "n must be >= 1");
+    if (n > (int64_t)2000000000)
+        return fail(DMK_ERR_ARG, "n too large");
+    return create_plan(points, {0, n}, dim, periodic, tol, opts, out);
+}
+
+int dmk_stokes_plan_batch(const double* points, const int64_t* offsets, int n_problems, int dim, int periodic,
+                          double tol, const dmk_opts* opts, dmk_plan_t* out)
+{
+    if (!out)
+        return fail(DMK_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!points || !offsets)
+        return fail(DMK_ERR_ARG, "points or offsets is NULL");
+    if (n_problems < 1 || n_problems > (1 << 20))
+        return fail(DMK_ERR_ARG, "n_problems must be in [1, 2^20]");
+    if (offsets[0] != 0)
+        return fail(DMK_ERR_ARG, "offsets[0] must be 0");
+    for (int b = 0; b < n_problems; ++b)
+        if (offsets[b + 1] <= offsets[b])
+            return fail(DMK_ERR_ARG, "every problem needs at least one point (offsets strictly increasing)");
+    if (offsets[n_problems] > (int64_t)2000000000)
+        return fail(DMK_ERR_ARG, "n too large");
+    return create_plan(points, std::vector<int64_t>(offsets, offsets + n_problems + 1), dim, periodic, tol, opts,
+                       out);
 }
 
 int dmk_stokes_plan(const double* points, int64_t n, int dim, int periodic, double tol, dmk_plan_t* out)

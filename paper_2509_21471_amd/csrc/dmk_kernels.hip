@@ -71,6 +71,73 @@ void launch_bbox(const double* pts, int64_t n, double* partial, int nblk, hipStr
     hipLaunchKernelGGL(k_bbox, dim3(nblk), dim3(256), 0, s, pts, n, partial);
 }
 
+// One block per problem: bounding box and non-finite count of the points
+// [off[b], off[b+1]), written to part[8b .. 8b+6].
+__global__ __launch_bounds__(256) void k_bbox_seg(const double* __restrict__ pts, const int64_t* __restrict__ off,
+                                                  double* __restrict__ part)
+{
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    double bad = 0;
+    const int64_t a = off[blockIdx.x], b = off[blockIdx.x + 1];
+    for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x)
+        for (int d = 0; d < 3; ++d) {
+            const double v = pts[3 * i + d];
+            if (!isfinite(v))
+                bad += 1;
+            else {
+                lo[d] = fmin(lo[d], v);
+                hi[d] = fmax(hi[d], v);
+            }
+        }
+    __shared__ double sh[7][256];
+    for (int d = 0; d < 3; ++d) {
+        sh[d][threadIdx.x] = lo[d];
+        sh[3 + d][threadIdx.x] = hi[d];
+    }
+    sh[6][threadIdx.x] = bad;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            for (int d = 0; d < 3; ++d) {
+                sh[d][threadIdx.x] = fmin(sh[d][threadIdx.x], sh[d][threadIdx.x + st]);
+                sh[3 + d][threadIdx.x] = fmax(sh[3 + d][threadIdx.x], sh[3 + d][threadIdx.x + st]);
+            }
+            sh[6][threadIdx.x] += sh[6][threadIdx.x + st];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 7)
+        part[blockIdx.x * 8 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+void launch_bbox_seg(const double* pts, const int64_t* off, int nprob, double* partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bbox_seg, dim3(nprob), dim3(256), 0, s, pts, off, partial);
+}
+
+// Problem index of every point: the b with off[b] <= i < off[b+1].
+__global__ __launch_bounds__(256) void k_fill_pid(const int64_t* __restrict__ off, int nprob, int64_t n,
+                                                  int* __restrict__ pid)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    pid[i] = lo;
+}
+
+void launch_fill_pid(const int64_t* off, int nprob, int64_t n, int* pid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_pid, dim3(nblocks(n, 256)), dim3(256), 0, s, off, nprob, n, pid);
+}
+
 __device__ inline uint64_t spread3(uint64_t v)
 {
     // bit b of v -> bit 3b
@@ -80,14 +147,16 @@ __device__ inline uint64_t spread3(uint64_t v)
     return r;
 }
 
-__global__ __launch_bounds__(256) void k_morton(const double* __restrict__ pts, int64_t n, double cx, double cy,
-                                                double cz, double inv_len, uint64_t* __restrict__ keys,
-                                                int* __restrict__ idx)
+__global__ __launch_bounds__(256) void k_morton(const double* __restrict__ pts, int64_t n,
+                                                const int* __restrict__ pid, const double* __restrict__ geo,
+                                                uint64_t* __restrict__ keys, int* __restrict__ idx)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n)
         return;
-    const double c[3] = {cx, cy, cz};
+    const double* g = geo + 4 * (pid ? pid[i] : 0);
+    const double c[3] = {g[0], g[1], g[2]};
+    const double inv_len = g[3];
     uint64_t q[3];
     for (int d = 0; d < 3; ++d) {
         const double u = (pts[3 * i + d] - c[d]) * inv_len + 0.5;  // [0,1)
@@ -99,31 +168,32 @@ __global__ __launch_bounds__(256) void k_morton(const double* __restrict__ pts, 
     idx[i] = (int)i;
 }
 
-void launch_morton(const double* pts, int64_t n, double cx, double cy, double cz, double inv_len, uint64_t* keys,
-                   int* idx, hipStream_t s)
+void launch_morton(const double* pts, int64_t n, const int* pid, const double* geo, uint64_t* keys, int* idx,
+                   hipStream_t s)
 {
-    hipLaunchKernelGGL(k_morton, dim3(nblocks(n, 256)), dim3(256), 0, s, pts, n, cx, cy, cz, inv_len, keys, idx);
+    hipLaunchKernelGGL(k_morton, dim3(nblocks(n, 256)), dim3(256), 0, s, pts, n, pid, geo, keys, idx);
 }
 
 __global__ __launch_bounds__(256) void k_gather_points(const double* __restrict__ pts, int64_t n,
-                                                       const int* __restrict__ perm, double cx, double cy,
-                                                       double cz, double inv_len, double* __restrict__ x,
+                                                       const int* __restrict__ perm, const int* __restrict__ pid,
+                                                       const double* __restrict__ geo, double* __restrict__ x,
                                                        double* __restrict__ y, double* __restrict__ z)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n)
         return;
     const int64_t o = perm[i];
-    x[i] = (pts[3 * o] - cx) * inv_len;
-    y[i] = (pts[3 * o + 1] - cy) * inv_len;
-    z[i] = (pts[3 * o + 2] - cz) * inv_len;
+    // sorting is per problem, so sorted position i lies in the same problem as input position i
+    const double* g = geo + 4 * (pid ? pid[i] : 0);
+    x[i] = (pts[3 * o] - g[0]) * g[3];
+    y[i] = (pts[3 * o + 1] - g[1]) * g[3];
+    z[i] = (pts[3 * o + 2] - g[2]) * g[3];
 }
 
-void launch_gather_points(const double* pts, int64_t n, const int* perm, double cx, double cy, double cz,
-                          double inv_len, double* x, double* y, double* z, hipStream_t s)
+void launch_gather_points(const double* pts, int64_t n, const int* perm, const int* pid, const double* geo,
+                          double* x, double* y, double* z, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gather_points, dim3(nblocks(n, 256)), dim3(256), 0, s, pts, n, perm, cx, cy, cz, inv_len,
-                       x, y, z);
+    hipLaunchKernelGGL(k_gather_points, dim3(nblocks(n, 256)), dim3(256), 0, s, pts, n, perm, pid, geo, x, y, z);
 }
 
 size_t sort_temp_bytes(int64_t n)
@@ -138,6 +208,22 @@ void launch_sort(void* temp, size_t temp_bytes, const uint64_t* kin, uint64_t* k
                  int64_t n, int end_bit, hipStream_t s)
 {
     (void)hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, kin, kout, vin, vout, (int)n, 0, end_bit, s);
+}
+
+size_t seg_sort_temp_bytes(int64_t n, int nseg)
+{
+    size_t bytes = 0;
+    (void)hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                                      (const int*)nullptr, (int*)nullptr, (int)n, nseg,
+                                                      (const int64_t*)nullptr, (const int64_t*)nullptr, 0, 57);
+    return bytes;
+}
+
+void launch_seg_sort(void* temp, size_t temp_bytes, const uint64_t* kin, uint64_t* kout, const int* vin, int* vout,
+                     int64_t n, int nseg, const int64_t* off, int end_bit, hipStream_t s)
+{
+    (void)hipcub::DeviceSegmentedRadixSort::SortPairs(temp, temp_bytes, kin, kout, vin, vout, (int)n, nseg, off,
+                                                      off + 1, 0, end_bit, s);
 }
 
 __global__ __launch_bounds__(256) void k_chunk_bbox(const double* __restrict__ x, const double* __restrict__ y,
@@ -813,6 +899,8 @@ __global__ __launch_bounds__(256) void k_root_symbol(int mh, int mf, const typen
     const int mi = blockIdx.x * blockDim.x + threadIdx.x;
     if (mi >= H)
         return;
+    Phi += (size_t)blockIdx.y * 3 * H;  // one root per grid row
+    Psi += (size_t)blockIdx.y * 3 * H;
     const int M = (mf - 1) / 2;
     const int m1 = mi / (mf * mf);
     const int rem = mi - m1 * mf * mf;
@@ -834,14 +922,15 @@ __global__ __launch_bounds__(256) void k_root_symbol(int mh, int mf, const typen
         Psi[(size_t)j * H + mo] = {(S)(ww * (Fr[j] - mv[j] * dr)), (S)(ww * (Fi[j] - mv[j] * di))};
 }
 
-void launch_root_symbol(int mh, int mf, const void* Phi, const double* w, void* Psi, bool f32, hipStream_t s)
+void launch_root_symbol(int mh, int mf, int nroot, const void* Phi, const double* w, void* Psi, bool f32,
+                        hipStream_t s)
 {
     const int H = mh * mf * mf;
     if (f32)
-        hipLaunchKernelGGL(k_root_symbol<float>, dim3(nblocks(H, 256)), dim3(256), 0, s, mh, mf, (const float2*)Phi,
-                           w, (float2*)Psi);
+        hipLaunchKernelGGL(k_root_symbol<float>, dim3(nblocks(H, 256), nroot), dim3(256), 0, s, mh, mf,
+                           (const float2*)Phi, w, (float2*)Psi);
     else
-        hipLaunchKernelGGL(k_root_symbol<double>, dim3(nblocks(H, 256)), dim3(256), 0, s, mh, mf,
+        hipLaunchKernelGGL(k_root_symbol<double>, dim3(nblocks(H, 256), nroot), dim3(256), 0, s, mh, mf,
                            (const double2*)Phi, w, (double2*)Psi);
 }
 
@@ -1216,15 +1305,17 @@ void launch_residual_direct(const double* tx, const double* ty, const double* tz
 }
 
 // ---- finishing --------------------------------------------------------------------
+// One block per root: out[3r + j] = coef * sum of root r's proxy charges of component j.
 template <typename S>
-__global__ __launch_bounds__(256) void k_sum_root(const S* __restrict__ Q, int p3, double coef,
-                                                  double* __restrict__ out)
+__global__ __launch_bounds__(256) void k_sum_root(const S* __restrict__ Q, const int* __restrict__ root_fid, int p3,
+                                                  double coef, double* __restrict__ out)
 {
     __shared__ double sh[256];
+    const S* q = Q + (size_t)root_fid[blockIdx.x] * 3 * p3;
     for (int j = 0; j < 3; ++j) {
         double s = 0;
         for (int k = threadIdx.x; k < p3; k += 256)
-            s += (double)Q[(size_t)j * p3 + k];
+            s += (double)q[(size_t)j * p3 + k];
         sh[threadIdx.x] = s;
         __syncthreads();
         for (int st = 128; st > 0; st >>= 1) {
@@ -1233,37 +1324,43 @@ __global__ __launch_bounds__(256) void k_sum_root(const S* __restrict__ Q, int p
             __syncthreads();
         }
         if (threadIdx.x == 0)
-            out[j] = coef * sh[0];
+            out[3 * blockIdx.x + j] = coef * sh[0];
         __syncthreads();
     }
 }
 
-void launch_sum_root(const void* Qroot, int p3, double coef, double* out, bool f32, hipStream_t s)
+void launch_sum_root(const void* Q, const int* root_fid, int nroot, int p3, double coef, double* out, bool f32,
+                     hipStream_t s)
 {
     if (f32)
-        hipLaunchKernelGGL(k_sum_root<float>, dim3(1), dim3(256), 0, s, (const float*)Qroot, p3, coef, out);
+        hipLaunchKernelGGL(k_sum_root<float>, dim3(nroot), dim3(256), 0, s, (const float*)Q, root_fid, p3, coef, out);
     else
-        hipLaunchKernelGGL(k_sum_root<double>, dim3(1), dim3(256), 0, s, (const double*)Qroot, p3, coef, out);
+        hipLaunchKernelGGL(k_sum_root<double>, dim3(nroot), dim3(256), 0, s, (const double*)Q, root_fid, p3, coef,
+                           out);
 }
 
+// vel (caller's order) = scale_b (u + c_b), b the point's problem: scale_b
+// undoes that problem's unit-box map, c_b its free-space constant (or none).
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ u, int64_t n, const int* __restrict__ perm,
-                                                  double scale, const double* __restrict__ cst,
-                                                  double* __restrict__ vel)
+                                                  const int* __restrict__ pid, const double* __restrict__ scale,
+                                                  const double* __restrict__ cst, double* __restrict__ vel)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n)
         return;
     const int64_t o = perm[i];
-    const double c0 = cst ? cst[0] : 0.0, c1 = cst ? cst[1] : 0.0, c2 = cst ? cst[2] : 0.0;
-    vel[3 * o] = scale * (u[i] + c0);
-    vel[3 * o + 1] = scale * (u[n + i] + c1);
-    vel[3 * o + 2] = scale * (u[2 * n + i] + c2);
+    const int b = pid ? pid[i] : 0;
+    const double sc = scale[b];
+    const double c0 = cst ? cst[3 * b] : 0.0, c1 = cst ? cst[3 * b + 1] : 0.0, c2 = cst ? cst[3 * b + 2] : 0.0;
+    vel[3 * o] = sc * (u[i] + c0);
+    vel[3 * o + 1] = sc * (u[n + i] + c1);
+    vel[3 * o + 2] = sc * (u[2 * n + i] + c2);
 }
 
-void launch_finalize(const double* u, int64_t n, const int* perm, double scale, const double* cst, double* vel,
-                     hipStream_t s)
+void launch_finalize(const double* u, int64_t n, const int* perm, const int* pid, const double* scale,
+                     const double* cst, double* vel, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(nblocks(n, 256)), dim3(256), 0, s, u, n, perm, scale, cst, vel);
+    hipLaunchKernelGGL(k_finalize, dim3(nblocks(n, 256)), dim3(256), 0, s, u, n, perm, pid, scale, cst, vel);
 }
 
 __global__ __launch_bounds__(256) void k_zero(uint32_t* __restrict__ p, size_t count)

@@ -14,16 +14,24 @@ struct cplx {
 // ---- tree construction -----------------------------------------------------
 // per-block partial bounding box / finiteness of (n,3) row-major points
 void launch_bbox(const double* pts, int64_t n, double* partial /*nblk*8*/, int nblk, hipStream_t s);
+// per problem b (points [off[b], off[b+1])): partial[8b..8b+6] = lo, hi, non-finite count
+void launch_bbox_seg(const double* pts, const int64_t* off, int nprob, double* partial, hipStream_t s);
+void launch_fill_pid(const int64_t* off, int nprob, int64_t n, int* pid, hipStream_t s);
 // unit-box coordinates, Morton keys (19 bits per dimension), identity index
-void launch_morton(const double* pts, int64_t n, double cx, double cy, double cz, double inv_len,
-                   uint64_t* keys, int* idx, hipStream_t s);
+// geo: per problem (cx, cy, cz, 1/len); pid: problem of each point (NULL: one problem)
+void launch_morton(const double* pts, int64_t n, const int* pid, const double* geo, uint64_t* keys, int* idx,
+                   hipStream_t s);
 // sorted SoA unit coordinates
-void launch_gather_points(const double* pts, int64_t n, const int* perm, double cx, double cy, double cz,
-                          double inv_len, double* x, double* y, double* z, hipStream_t s);
+void launch_gather_points(const double* pts, int64_t n, const int* perm, const int* pid, const double* geo,
+                          double* x, double* y, double* z, hipStream_t s);
 // radix sort of (key, index) pairs; temp storage is allocated by the caller
 size_t sort_temp_bytes(int64_t n);
 void launch_sort(void* temp, size_t temp_bytes, const uint64_t* kin, uint64_t* kout, const int* vin, int* vout,
                  int64_t n, int end_bit, hipStream_t s);
+// radix sort within each segment [off[b], off[b+1])
+size_t seg_sort_temp_bytes(int64_t n, int nseg);
+void launch_seg_sort(void* temp, size_t temp_bytes, const uint64_t* kin, uint64_t* kout, const int* vin, int* vout,
+                     int64_t n, int nseg, const int64_t* off, int end_bit, hipStream_t s);
 // per 64-point chunk bounding boxes (chunk list given as starts/ends)
 void launch_chunk_bbox(const double* x, const double* y, const double* z, const int64_t* cstart,
                        const int* clen, int nchunk, double* bbox /*nchunk*6*/, hipStream_t s);
@@ -105,7 +113,9 @@ void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int*
                       const int8_t* e_off /*3 per entry*/, const void* Phi, const double* wdiff, void* Psi, bool f32,
                       hipStream_t s);
 // root symbol multiply: Psi[j][mz][my][mx] = w(|m|^2) (I - m m^T/|m|^2) Phi[j][mx][my][mz]
-void launch_root_symbol(int mh, int mf, const void* Phi, const double* w, void* Psi, bool f32, hipStream_t s);
+// one root per problem: Phi / Psi hold nroot consecutive [3][H] grids
+void launch_root_symbol(int mh, int mf, int nroot, const void* Phi, const double* w, void* Psi, bool f32,
+                        hipStream_t s);
 
 // near field (Step 4); the self term comes out of the r = 0 pair
 struct NearLeaf {
@@ -146,10 +156,13 @@ void launch_residual_direct(const double* tx, const double* ty, const double* tz
                             const RadialPoly& poly, double* u, hipStream_t s);
 
 // out[j] = coef * sum of the root proxy charges (equals coef * net force)
-void launch_sum_root(const void* Qroot, int p3, double coef, double* out, bool f32, hipStream_t s);
+// out[3r + j] = coef * sum_k Q[root_fid[r]][j][k]
+void launch_sum_root(const void* Q, const int* root_fid, int nroot, int p3, double coef, double* out, bool f32,
+                     hipStream_t s);
 // u_out[(rhs) n,3 original order] = scale * u[j][i] + cst[j]
-void launch_finalize(const double* u, int64_t n, const int* perm, double scale, const double* cst,
-                     double* vel, hipStream_t s);
+// per point of problem b: vel = scale[b] * (u + cst[3b..]) (cst may be NULL), unpermuted
+void launch_finalize(const double* u, int64_t n, const int* perm, const int* pid, const double* scale,
+                     const double* cst, double* vel, hipStream_t s);
 // zero `bytes` (a multiple of 4) at p
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 

@@ -421,4 +421,71 @@ void build_tree(const uint64_t* sorted_keys, int64_t n, int ns, bool periodic, T
     T->n_near_pairs = pairs;
 }
 
+void merge_forest(std::vector<Tree>& parts, const std::vector<int64_t>& offsets, Tree* out, std::vector<int>* roots)
+{
+    const int np = (int)parts.size();
+    Tree& F = *out;
+    F = Tree();
+    F.periodic = np > 0 && parts[0].periodic;
+    int maxl = 0;
+    for (const Tree& t : parts)
+        maxl = std::max(maxl, t.max_level);
+    F.max_level = maxl;
+    // new index of box i of tree t: level-major, problem order within a level
+    std::vector<std::vector<int>> remap(np);
+    std::vector<int> count(maxl + 1, 0);
+    for (const Tree& t : parts)
+        for (int l = 0; l <= t.max_level; ++l)
+            count[l] += t.level_start[l + 1] - t.level_start[l];
+    F.level_start.assign(maxl + 2, 0);
+    for (int l = 0; l <= maxl; ++l)
+        F.level_start[l + 1] = F.level_start[l] + count[l];
+    std::vector<int> fill(F.level_start.begin(), F.level_start.end() - 1);
+    for (int t = 0; t < np; ++t) {
+        const Tree& T = parts[t];
+        remap[t].assign(T.boxes.size(), -1);
+        for (int l = 0; l <= T.max_level; ++l)
+            for (int i = T.level_start[l]; i < T.level_start[l + 1]; ++i)
+                remap[t][i] = fill[l]++;
+    }
+    const int nb = F.level_start[maxl + 1];
+    F.boxes.resize(nb);
+    F.colleagues.resize(nb);
+    F.incoming.resize(nb);
+    roots->assign(np, -1);
+    for (int t = 0; t < np; ++t) {
+        const Tree& T = parts[t];
+        const std::vector<int>& R = remap[t];
+        auto m = [&](int i) { return i < 0 ? -1 : R[i]; };
+        const int64_t off = offsets[t];
+        for (int i = 0; i < (int)T.boxes.size(); ++i) {
+            Box b = T.boxes[i];
+            b.parent = m(b.parent);
+            for (int c = 0; c < 8; ++c)
+                b.child[c] = m(b.child[c]);
+            b.start += off;
+            b.end += off;
+            F.boxes[R[i]] = b;
+            std::vector<FarEntry> col = T.colleagues[i];
+            for (FarEntry& e : col)
+                e.src = R[e.src];
+            F.colleagues[R[i]] = std::move(col);
+            std::vector<FarEntry> inc = T.incoming[i];
+            for (FarEntry& e : inc)
+                e.src = R[e.src];
+            F.incoming[R[i]] = std::move(inc);
+        }
+        for (int li = 0; li < (int)T.leaves.size(); ++li) {
+            F.leaves.push_back(R[T.leaves[li]]);
+            std::vector<NearEntry> nl = T.near[li];
+            for (NearEntry& e : nl)
+                e.src = R[e.src];
+            F.near.push_back(std::move(nl));
+        }
+        (*roots)[t] = R[0];
+        F.n += T.n;
+        F.n_near_pairs += T.n_near_pairs;
+    }
+}
+
 }  // namespace dmk

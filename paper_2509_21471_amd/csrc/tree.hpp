@@ -58,4 +58,10 @@ struct Tree {
 // periodic wrap when `periodic`) differ by at most one level.
 void build_tree(const uint64_t* sorted_keys, int64_t n, int ns, bool periodic, Tree* T);
 
+// Joins the trees of independent problems into one forest.  Problem t's
+// points occupy [offsets[t], offsets[t+1]) of the sorted order.  Boxes are
+// ordered by level (problem order within a level); every index is remapped;
+// lists never cross problems.  roots[t] receives the index of problem t's root.
+void merge_forest(std::vector<Tree>& parts, const std::vector<int64_t>& offsets, Tree* out, std::vector<int>* roots);
+
 }  // namespace dmk

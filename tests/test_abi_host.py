@@ -117,3 +117,29 @@ def test_host_tree_argument_validation():
         dmk.host_tree(np.array([[0.5, 0.5, 1.2]]), 10, periodic=True)   # outside the cell
     with pytest.raises(dmk.DMKError):
         dmk.host_tree(np.array([[np.nan, 0.5, 0.2]]), 10)
+
+
+def test_plan_batch_argument_validation():
+    """dmk_stokes_plan_batch rejects bad offsets before touching the device."""
+    dmk = _dmk()
+    lib = dmk.lib()
+    out = ctypes.c_void_p()
+    host = (ctypes.c_double * 30)()
+    vp = ctypes.cast(host, ctypes.c_void_p)
+
+    def off(*v):
+        a = (ctypes.c_int64 * len(v))(*v)
+        return ctypes.cast(a, ctypes.c_void_p), a
+
+    good, _g = off(0, 4, 10)
+    assert lib.dmk_stokes_plan_batch(vp, None, 2, 3, 0, 1e-6, None, ctypes.byref(out)) == -1
+    bad0, _b0 = off(1, 4, 10)
+    assert lib.dmk_stokes_plan_batch(vp, bad0, 2, 3, 0, 1e-6, None, ctypes.byref(out)) == -1
+    empty, _e = off(0, 4, 4)
+    assert lib.dmk_stokes_plan_batch(vp, empty, 2, 3, 0, 1e-6, None, ctypes.byref(out)) == -1
+    assert b"at least one point" in lib.dmk_last_error()
+    assert lib.dmk_stokes_plan_batch(vp, good, 0, 3, 0, 1e-6, None, ctypes.byref(out)) == -1
+    assert lib.dmk_stokes_plan_batch(vp, good, 2, 2, 0, 1e-6, None, ctypes.byref(out)) == -2
+    assert lib.dmk_stokes_plan_batch(vp, good, 2, 3, 0, 1e-2, None, ctypes.byref(out)) == -5
+    assert lib.dmk_stokes_plan_batch(vp, good, 2, 3, 0, 1e-6, None, ctypes.byref(out)) == -1  # host pointer
+    assert out.value is None

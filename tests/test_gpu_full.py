@@ -183,3 +183,62 @@ def test_clusters_4e6_mixed(dev):
     err = oracle.rel_l2(u[ref["idx"]], ref["u"])
     print("clusters_4e6 mixed", info["levels"], err)
     assert err < 1e-6
+
+
+def _concat(problems):
+    x = np.concatenate([p[0] for p in problems])
+    f = np.concatenate([p[1] for p in problems])
+    off = np.concatenate([[0], np.cumsum([p[0].shape[0] for p in problems])]).astype(np.int64)
+    return x, f, off
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_plan_matches_single_plans(dev, precision):
+    """A batched plan over independent problems gives each problem the result
+    of its own plan (same trees, same arithmetic) and the direct sum."""
+    rng = np.random.default_rng(80)
+    probs = []
+    for i, n in enumerate([1, 7, 300, 2500, 9000, 4000, 60, 12000]):
+        kind = "uniform" if i % 2 else "blob"
+        probs.append(workloads.make(kind, n, seed=800 + i, sigma=0.1))
+    x, f, off = _concat(probs)
+    plan = _dmk().Plan(_t(x), tol=1e-6, leaf_size=200, precision=precision, offsets=off)
+    u = plan.eval(_t(f)).cpu().numpy()
+    info = plan.info()
+    plan.close()
+    assert info["n_points"] == x.shape[0]
+    for b, (xb, fb) in enumerate(probs):
+        ub = u[off[b]:off[b + 1]]
+        us, _ = _eval(xb, fb, tol=1e-6, leaf_size=200, precision=precision)
+        assert oracle.rel_l2(ub, us) < 1e-13 if xb.shape[0] > 1 else np.abs(ub - us).max() < 1e-12
+        if xb.shape[0] > 1:
+            assert oracle.rel_l2(ub, oracle.direct(xb, fb)) < 1e-6
+
+
+def test_batch_plan_periodic(dev):
+    probs = [workloads.make("periodic", n, seed=810 + n) for n in (500, 3000, 1200)]
+    x, f, off = _concat(probs)
+    plan = _dmk().Plan(_t(x), periodic=True, tol=1e-6, leaf_size=150, offsets=off)
+    u = plan.eval(_t(f)).cpu().numpy()
+    plan.close()
+    from oracle.ewald import ewald
+    for b, (xb, fb) in enumerate(probs):
+        idx = np.arange(0, xb.shape[0], 5)
+        assert oracle.rel_l2(u[off[b]:off[b + 1]][idx], ewald(xb, fb, idx)) < 1e-6
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_256_problems(dev, precision):
+    """The 256-problem batch (N log-uniform in [1e3, 1e5], uniform or one
+    Gaussian blob): 50 sampled targets per problem against the direct sum."""
+    probs = workloads.batch_problems()
+    x, f, off = _concat(probs)
+    plan = _dmk().Plan(_t(x), tol=1e-6, precision=precision, offsets=off)
+    u = plan.eval(_t(f)).cpu().numpy()
+    plan.close()
+    errs = []
+    for b, (xb, fb) in enumerate(probs):
+        idx = workloads.sample_targets(xb.shape[0], 50, 5000 + b)
+        errs.append(oracle.rel_l2(u[off[b]:off[b + 1]][idx], oracle.direct(xb, fb, idx)))
+    print("batch 256: max", max(errs), "median", float(np.median(errs)))
+    assert max(errs) < 1e-6
