@@ -91,6 +91,11 @@ typedef struct {
  * work already queued on opts.stream (e.g. the previous plan's evaluation).
  * Without the flag the plan is built in order on opts.stream. */
 #define DMK_FLAG_CONCURRENT_PLAN 2
+/* dmk_stokes_eval captures its launches into a HIP graph the first time it
+ * sees a (forces, n_rhs, velocities) triple and replays that graph, on
+ * opts.stream, for later calls with the same triple (new force values in the
+ * same buffer are picked up).  Phase timing is not recorded in this mode. */
+#define DMK_FLAG_GRAPH 4
 
 /* phases reported by dmk_stokes_phase_ms, in this order */
 #define DMK_PHASE_ANTERP 0     /* force gather + leaf proxy charges (Step 2a) */
@@ -173,6 +178,26 @@ int dmk_stokes_plan_batch(const double* points, const int64_t* offsets, int n_pr
  * the plan's work buffers).
  */
 int dmk_stokes_eval(dmk_plan_t plan, const double* forces, int n_rhs, double* velocities);
+
+/*
+ * Autotuner: picks the leaf size (maximum points per leaf) and the near-field
+ * lane split for this workload by timing plan + evaluation on the caller's
+ * points.  Leaf sizes 0.4, 0.55, 0.75, 1 and 1.35 times the starting size
+ * (opts->leaf_size, else the tolerance's default) are tried with the starting
+ * lane split, then 2 and 8 lanes at the best size; each trial keeps the
+ * faster of two runs.  The choice is cached per process for the workload class
+ * (n and n_problems to the nearest power of two, periodicity, tol, precision,
+ * n_rhs, q, p): a later call for the same class returns at once.
+ *   points, n                as dmk_stokes_plan_ex (device points)
+ *   offsets, n_problems      as dmk_stokes_plan_batch, or offsets = NULL for one problem
+ *   opts                     starting options (may be NULL); copied into *tuned
+ *   n_rhs                    force vectors per evaluation to tune for (1..64)
+ *   tuned                    receives opts with leaf_size and near_lanes set
+ *   best_ms                  receives the best trial's plan + eval milliseconds (may be NULL)
+ * Allocates and frees two (n_rhs, n, 3) device buffers; synchronises opts->stream.
+ */
+int dmk_stokes_autotune(const double* points, int64_t n, const int64_t* offsets, int n_problems, int dim,
+                        int periodic, double tol, const dmk_opts* opts, int n_rhs, dmk_opts* tuned, double* best_ms);
 
 /* Fills *info (host struct) with the plan's parameters and statistics. */
 int dmk_stokes_plan_info(dmk_plan_t plan, dmk_plan_info* info);

@@ -19,7 +19,7 @@ STATUS = {0: "DMK_OK", -1: "DMK_ERR_ARG", -2: "DMK_ERR_UNSUPPORTED", -3: "DMK_ER
           -4: "DMK_ERR_NONFINITE", -5: "DMK_ERR_TOL", -6: "DMK_ERR_OOM", -7: "DMK_ERR_HIP"}
 PREC_FP64, PREC_MIXED = 0, 1
 
-SYMBOLS = ["dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_plan_batch", "dmk_stokes_eval", "dmk_stokes_plan_info",
+SYMBOLS = ["dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_plan_batch", "dmk_stokes_autotune", "dmk_stokes_eval", "dmk_stokes_plan_info",
            "dmk_stokes_tree_leaves", "dmk_stokes_destroy", "dmk_last_error", "dmk_stokes_params",
            "dmk_stokes_radial", "dmk_stokes_mollifier", "dmk_stokes_residual_sum", "dmk_stokes_phase_ms",
            "dmk_stokes_near_stats", "dmk_stokes_release_cached_memory", "dmk_stokes_host_tree"]
@@ -27,6 +27,7 @@ PHASES = ["anterp", "merge", "outgoing", "translate", "incoming", "root", "inter
           "finalize"]
 FLAG_PHASE_TIMING = 1
 FLAG_CONCURRENT_PLAN = 2
+FLAG_GRAPH = 4
 
 
 class DMKError(RuntimeError):
@@ -77,6 +78,9 @@ def lib():
                                          ctypes.POINTER(Opts), ctypes.POINTER(vp)]
         L.dmk_stokes_plan_batch.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                             ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+        L.dmk_stokes_autotune.argtypes = [vp, i64, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                          ctypes.POINTER(Opts), ctypes.c_int, ctypes.POINTER(Opts),
+                                          ctypes.POINTER(ctypes.c_double)]
         L.dmk_stokes_eval.argtypes = [vp, vp, ctypes.c_int, vp]
         L.dmk_stokes_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
         L.dmk_stokes_tree_leaves.argtypes = [vp, vp, vp, vp, vp]
@@ -178,7 +182,7 @@ class Plan:
     def __init__(self, points, periodic: bool = False, tol: float = 1e-6, precision: int = PREC_FP64,
                  leaf_size: int = 0, stream=None, mem_cap_bytes: int = 0, timing: bool = False,
                  near_lanes: int = 0, q: int = 0, p: int = 0, rhs_batch: int = 0, concurrent: bool = False,
-                 offsets=None):
+                 offsets=None, graph: bool = False):
         """offsets (host int sequence, n_problems + 1 entries) makes a batched
         plan over independent problems (dmk_stokes_plan_batch)."""
         torch = _torch()
@@ -186,7 +190,8 @@ class Plan:
         self.n = int(pts.shape[0])
         self.stream = stream
         opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), int(mem_cap_bytes),
-                    (FLAG_PHASE_TIMING if timing else 0) | (FLAG_CONCURRENT_PLAN if concurrent else 0),
+                    (FLAG_PHASE_TIMING if timing else 0) | (FLAG_CONCURRENT_PLAN if concurrent else 0)
+                    | (FLAG_GRAPH if graph else 0),
                     int(near_lanes), int(q), int(p), int(rhs_batch))
         h = ctypes.c_void_p()
         if offsets is None:
@@ -251,6 +256,27 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def autotune(points, periodic: bool = False, tol: float = 1e-6, precision: int = PREC_FP64, offsets=None,
+             n_rhs: int = 1, leaf_size: int = 0, stream=None) -> dict:
+    """dmk_stokes_autotune: the leaf size and near-field lane split to pass to
+    Plan for this workload, and the best trial's plan + eval milliseconds."""
+    pts = _dev_f64(points)
+    n = int(pts.shape[0])
+    opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), 0, 0, 0, 0, 0, 0)
+    tuned = Opts()
+    ms = ctypes.c_double()
+    off = None
+    nprob = 0
+    if offsets is not None:
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        nprob = int(off.size - 1)
+    _check(lib().dmk_stokes_autotune(ctypes.c_void_p(pts.data_ptr()), n,
+                                     None if off is None else off.ctypes.data_as(ctypes.c_void_p), nprob, 3,
+                                     int(bool(periodic)), float(tol), ctypes.byref(opts), int(n_rhs),
+                                     ctypes.byref(tuned), ctypes.byref(ms)))
+    return {"leaf_size": tuned.leaf_size, "near_lanes": tuned.near_lanes, "ms": ms.value}
 
 
 def residual_sum(targets, sources, forces, r_lambda: float, tol: float, stream=None):

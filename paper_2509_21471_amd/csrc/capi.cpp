@@ -8,6 +8,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/dmk_stokes.h"
@@ -251,6 +252,14 @@ struct dmk_plan_s {
     hipEvent_t ev[DMK_NUM_PHASES + 2] = {};
     int rhs_batch = 8;                // force vectors per near-field pass
     bool concurrent = false;          // build on the library's plan stream
+    // DMK_FLAG_GRAPH: evaluation captured once per (forces, n_rhs, velocities)
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const double* g_forces = nullptr;
+    double* g_vel = nullptr;
+    int g_nrhs = 0;
     hipEvent_t done = nullptr;        // end of the most recent eval on `stream`
     bool done_recorded = false;
     bool ev_recorded = false;
@@ -261,6 +270,12 @@ struct dmk_plan_s {
                 (void)hipEventDestroy(e);
         if (done)
             (void)hipEventDestroy(done);
+        if (gexec)
+            (void)hipGraphExecDestroy(gexec);
+        if (graph)
+            (void)hipGraphDestroy(graph);
+        if (cap_stream)
+            (void)hipStreamDestroy(cap_stream);
     }
 };
 
@@ -973,6 +988,7 @@ int create_plan(const double* points, const std::vector<int64_t>& offsets, int d
         if (opts->rhs_batch > 0)
             P->rhs_batch = opts->rhs_batch;
         P->concurrent = (opts->flags & DMK_FLAG_CONCURRENT_PLAN) != 0;
+        P->use_graph = (opts->flags & DMK_FLAG_GRAPH) != 0;
     }
     if (hipEventCreateWithFlags(&P->done, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
@@ -1053,20 +1069,176 @@ int dmk_stokes_eval(dmk_plan_t plan, const double* forces, int n_rhs, double* ve
         return fail(DMK_ERR_ARG, "n_rhs must be >= 1");
     if (!is_device_ptr(forces) || !is_device_ptr(velocities))
         return fail(DMK_ERR_ARG, "forces and velocities must be device pointers");
-    for (int r = 0; r < n_rhs;) {
-        // largest supported batch that fits the remaining vectors
-        int nb = plan->rhs_batch;
-        while (nb > n_rhs - r)
-            nb >>= 1;
-        const int rc = eval_batch(plan, forces + (size_t)r * 3 * plan->n, nb, velocities + (size_t)r * 3 * plan->n,
-                                  plan->timing && r == 0);
+    auto run = [&](bool timing) {
+        for (int r = 0; r < n_rhs;) {
+            // largest supported batch that fits the remaining vectors
+            int nb = plan->rhs_batch;
+            while (nb > n_rhs - r)
+                nb >>= 1;
+            const int rc = eval_batch(plan, forces + (size_t)r * 3 * plan->n, nb,
+                                      velocities + (size_t)r * 3 * plan->n, timing && r == 0);
+            if (rc != DMK_OK)
+                return rc;
+            r += nb;
+        }
+        return (int)DMK_OK;
+    };
+    if (!plan->use_graph) {
+        const int rc = run(plan->timing);
         if (rc != DMK_OK)
             return rc;
-        r += nb;
+    } else {
+        if (!(plan->gexec && plan->g_forces == forces && plan->g_vel == velocities && plan->g_nrhs == n_rhs)) {
+            if (plan->gexec) {
+                (void)hipGraphExecDestroy(plan->gexec);
+                (void)hipGraphDestroy(plan->graph);
+                plan->gexec = nullptr;
+                plan->graph = nullptr;
+            }
+            if (!plan->cap_stream)
+                HIPCHK(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
+            hipStream_t user = plan->stream;
+            plan->stream = plan->cap_stream;
+            HIPCHK(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
+            const int rc = run(false);
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(plan->cap_stream, &g);
+            plan->stream = user;
+            if (rc != DMK_OK) {
+                if (g)
+                    (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess)
+                return fail(DMK_ERR_HIP, std::string("stream capture failed: ") + hipGetErrorString(e));
+            const hipError_t ei = hipGraphInstantiate(&plan->gexec, g, nullptr, nullptr, 0);
+            if (ei != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                plan->gexec = nullptr;
+                return fail(DMK_ERR_HIP, std::string("graph instantiation failed: ") + hipGetErrorString(ei));
+            }
+            plan->graph = g;
+            plan->g_forces = forces;
+            plan->g_vel = velocities;
+            plan->g_nrhs = n_rhs;
+        }
+        HIPCHK(hipGraphLaunch(plan->gexec, plan->stream));
     }
     HIPCHK(hipEventRecord(plan->done, plan->stream));
     plan->done_recorded = true;
     HIPCHK(hipGetLastError());
+    return DMK_OK;
+}
+
+int dmk_stokes_autotune(const double* points, int64_t n, const int64_t* offsets, int n_problems, int dim,
+                        int periodic, double tol, const dmk_opts* opts, int n_rhs, dmk_opts* tuned, double* best_ms)
+{
+    if (!tuned)
+        return fail(DMK_ERR_ARG, "tuned is NULL");
+    if (!points || n < 1 || n_rhs < 1 || n_rhs > 64)
+        return fail(DMK_ERR_ARG, "bad points, n or n_rhs");
+    if (offsets && (n_problems < 1 || offsets[0] != 0 || offsets[n_problems] != n))
+        return fail(DMK_ERR_ARG, "offsets must run from 0 to n");
+    int rc = validate_common(dim, tol, opts);
+    if (rc != DMK_OK)
+        return rc;
+    dmk_opts base{};
+    if (opts)
+        base = *opts;
+    base.flags &= ~(DMK_FLAG_PHASE_TIMING | DMK_FLAG_GRAPH);
+    dmk::Params prm;
+    if (!dmk::select_params(tol, &prm))
+        return fail(DMK_ERR_TOL, "tol must lie in [1e-12, 1e-3]");
+    // cached per workload class: size (powers of 2), problem count, periodicity, tolerance, precision
+    const int nb = offsets ? n_problems : 1;
+    const auto key = std::make_tuple((int)std::lround(std::log2((double)n)), (int)std::lround(std::log2((double)nb)),
+                                     periodic, tol, base.precision, n_rhs, base.q, base.p);
+    static std::mutex mu;
+    static std::map<decltype(key), std::pair<dmk_opts, double>> cache;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            *tuned = base;
+            tuned->leaf_size = it->second.first.leaf_size;
+            tuned->near_lanes = it->second.first.near_lanes;
+            if (best_ms)
+                *best_ms = it->second.second;
+            return DMK_OK;
+        }
+    }
+    double* f = nullptr;
+    double* v = nullptr;
+    const size_t bytes = (size_t)n * 3 * n_rhs * sizeof(double);
+    HIPCHK(hipMalloc((void**)&f, bytes));
+    if (hipMalloc((void**)&v, bytes) != hipSuccess) {
+        (void)hipFree(f);
+        return fail(DMK_ERR_OOM, "autotune buffers");
+    }
+    (void)hipMemset(f, 0, bytes);
+    hipStream_t st = (hipStream_t)base.stream;
+    // one trial: plan + evaluation, wall time (the plan part includes its host work)
+    auto trial = [&](int leaf, int lanes, double* ms) {
+        dmk_opts o = base;
+        o.leaf_size = leaf;
+        o.near_lanes = lanes;
+        double best = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            (void)hipStreamSynchronize(st);
+            const auto t0 = std::chrono::steady_clock::now();
+            dmk_plan_t P = nullptr;
+            const int r = offsets ? dmk_stokes_plan_batch(points, offsets, n_problems, dim, periodic, tol, &o, &P)
+                                  : dmk_stokes_plan_ex(points, n, dim, periodic, tol, &o, &P);
+            if (r != DMK_OK)
+                return r;
+            const int r2 = dmk_stokes_eval(P, f, n_rhs, v);
+            (void)hipStreamSynchronize(st);
+            const auto t1 = std::chrono::steady_clock::now();
+            dmk_stokes_destroy(P);
+            if (r2 != DMK_OK)
+                return r2;
+            best = std::min(best, std::chrono::duration<double, std::milli>(t1 - t0).count());
+        }
+        *ms = best;
+        return (int)DMK_OK;
+    };
+    const int ns0 = opts && opts->leaf_size > 0 ? opts->leaf_size : prm.ns;
+    int best_leaf = ns0, best_lanes = opts && opts->near_lanes > 0 ? opts->near_lanes : 4;
+    double best = 1e300;
+    for (double fac : {0.4, 0.55, 0.75, 1.0, 1.35}) {
+        const int leaf = std::max(32, (int)std::lround(ns0 * fac));
+        double ms = 0;
+        rc = trial(leaf, best_lanes, &ms);
+        if (rc != DMK_OK)
+            break;
+        if (ms < best) {
+            best = ms;
+            best_leaf = leaf;
+        }
+    }
+    for (int lanes : {2, 8}) {
+        if (rc != DMK_OK)
+            break;
+        double ms = 0;
+        rc = trial(best_leaf, lanes, &ms);
+        if (rc == DMK_OK && ms < best) {
+            best = ms;
+            best_lanes = lanes;
+        }
+    }
+    (void)hipFree(f);
+    (void)hipFree(v);
+    if (rc != DMK_OK)
+        return rc;
+    *tuned = base;
+    tuned->leaf_size = best_leaf;
+    tuned->near_lanes = best_lanes;
+    if (opts)
+        tuned->flags = opts->flags;
+    if (best_ms)
+        *best_ms = best;
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = {*tuned, best};
     return DMK_OK;
 }
 

@@ -242,3 +242,52 @@ def test_batch_256_problems(dev, precision):
         errs.append(oracle.rel_l2(u[off[b]:off[b + 1]][idx], oracle.direct(xb, fb, idx)))
     print("batch 256: max", max(errs), "median", float(np.median(errs)))
     assert max(errs) < 1e-6
+
+
+@pytest.mark.parametrize("n_rhs,batched", [(1, False), (3, False), (1, True)])
+def test_graph_replay(dev, n_rhs, batched):
+    """DMK_FLAG_GRAPH: the captured evaluation replays bit-identically to the
+    eager one, with eager work between replays and new force values in the
+    same buffer; a new buffer triggers a new capture."""
+    import torch
+    if batched:
+        probs = [workloads.make("blob", n, seed=900 + n, sigma=0.1) for n in (3000, 800, 6000)]
+        x, f, off = _concat(probs)
+        if n_rhs > 1:
+            f = np.stack([f * (r + 1) for r in range(n_rhs)])
+    else:
+        x, f = workloads.make("clusters", 20000, seed=90, sigma=0.05, n_rhs=n_rhs)
+        off = None
+    pg = _dmk().Plan(_t(x), tol=1e-6, leaf_size=200, graph=True, offsets=off)
+    pe = _dmk().Plan(_t(x), tol=1e-6, leaf_size=200, offsets=off)
+    fd = _t(f)
+    out = torch.empty_like(fd)
+    ref = pe.eval(fd).cpu().numpy()
+    for k in range(4):
+        pg.eval(fd, out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref), k
+        pe.eval(fd * 0.5)  # eager work between replays
+        torch.cuda.synchronize()
+    fd.mul_(-2.0)
+    pg.eval(fd, out)
+    ref2 = pe.eval(fd).cpu().numpy()
+    assert np.array_equal(out.cpu().numpy(), ref2)
+    out2 = torch.empty_like(fd)
+    pg.eval(fd, out2)
+    assert np.array_equal(out2.cpu().numpy(), ref2)
+    pg.close()
+    pe.close()
+
+
+def test_autotune(dev):
+    """The autotuner returns a valid configuration (cached on the second call)
+    whose plan is as accurate as the default one."""
+    x, f = workloads.make("clusters", 30000, seed=95, sigma=0.05)
+    xd = _t(x)
+    t1 = _dmk().autotune(xd, tol=1e-6, leaf_size=300)
+    assert t1["near_lanes"] in (2, 4, 8) and t1["leaf_size"] >= 32 and t1["ms"] > 0
+    t2 = _dmk().autotune(xd, tol=1e-6, leaf_size=300)
+    assert t2 == t1
+    u, _ = _eval(x, f, tol=1e-6, leaf_size=t1["leaf_size"], near_lanes=t1["near_lanes"])
+    assert oracle.rel_l2(u, oracle.direct(x, f)) < 1e-6
