@@ -41,10 +41,11 @@ def near_flops_per_pair(deg_P: int, deg_Q: int) -> int:
     return 35 + 2 * (deg_P + deg_Q)
 
 
-def near_traffic(config: str, tol: float, precision: str, kernel: str):
+def near_traffic(config: str, tol: float, precision: str, kernel: str, leaf_size: int, near_lanes: int):
     """HBM bytes per launch of the near-field kernel from the committed
-    rocprofv3 summary of this workload, or None when there is none or the
-    near-field source section changed since the counters were taken."""
+    rocprofv3 summary of this workload, or None when there is none, it was
+    taken with another leaf size or lane split, or the near-field source
+    section changed since the counters were taken."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", f"k_near_{config}_{precision}.md")
@@ -58,12 +59,96 @@ def near_traffic(config: str, tol: float, precision: str, kernel: str):
     sec = src[src.index("// ---- near field"):src.index("// ---- finishing")]
     if hashlib.sha256(sec.encode()).hexdigest() != rec["near_section_sha256"] or rec["kernel"] != kernel:
         return None
+    if rec.get("leaf_size") != leaf_size or rec.get("near_lanes") != near_lanes:
+        return None
     return rec["hbm_bytes_per_launch"]
 
 
 def workloads_tol(config: str) -> float:
     import workloads
     return workloads.CONFIGS[config]["tol"]
+
+
+def batched_variant(dev, parity: bool) -> dict:
+    """256 independent problems (N log-uniform in [1e3, 1e5], about 5.5e6
+    points): one batched mixed-precision plan + evaluation (autotuned leaf
+    size), against one FP64 plan + evaluation per problem; plus evaluation
+    alone with and without hipGraph replay."""
+    import torch
+
+    import paper_2509_21471_amd as dmk
+    import workloads
+    probs = workloads.batch_problems()
+    x = np.concatenate([p[0] for p in probs])
+    f = np.concatenate([p[1] for p in probs])
+    off = np.concatenate([[0], np.cumsum([p[0].shape[0] for p in probs])]).astype(np.int64)
+    n = x.shape[0]
+    xd = torch.from_numpy(x).to(dev)
+    fd = torch.from_numpy(f).to(dev)
+    out = torch.empty_like(fd)
+    tol = 1e-6
+    tune = dmk.autotune(xd, tol=tol, precision=dmk.PREC_MIXED, offsets=off)
+    res = {"workload": "batch_256", "n_problems": len(probs), "n": n, "tol": tol, "autotuned": tune}
+
+    def batched_step():
+        p = dmk.Plan(xd, tol=tol, precision=dmk.PREC_MIXED, offsets=off, leaf_size=tune["leaf_size"],
+                     near_lanes=tune["near_lanes"])
+        p.eval(fd, out)
+        return p
+
+    batched_step().close()
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        p = batched_step()
+        p.close()
+    torch.cuda.synchronize()
+    ms_b = (time.perf_counter() - t0) * 1e3 / reps
+    u_b = out.cpu().numpy()
+    # one FP64 plan per problem (inputs resident on the device)
+    xs = [xd[off[b]:off[b + 1]] for b in range(len(probs))]
+    fs = [fd[off[b]:off[b + 1]] for b in range(len(probs))]
+    outs = [torch.empty_like(t) for t in fs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(len(probs)):
+        p = dmk.Plan(xs[b], tol=tol)
+        p.eval(fs[b], outs[b])
+        p.close()
+    torch.cuda.synchronize()
+    ms_s = (time.perf_counter() - t0) * 1e3
+    # evaluation alone on one batched plan, eager and replayed
+    evals = {}
+    for graph in (False, True):
+        p = dmk.Plan(xd, tol=tol, precision=dmk.PREC_MIXED, offsets=off, leaf_size=tune["leaf_size"],
+                     near_lanes=tune["near_lanes"], graph=graph)
+        for _ in range(2):
+            p.eval(fd, out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            p.eval(fd, out)
+        torch.cuda.synchronize()
+        evals["graph" if graph else "eager"] = (time.perf_counter() - t0) * 1e3 / 5
+        p.close()
+    res.update({"batched_mixed_ms_per_step": ms_b, "batched_targets_per_s": n / (ms_b * 1e-3),
+                "separate_fp64_ms": ms_s, "separate_fp64_targets_per_s": n / (ms_s * 1e-3),
+                "speedup_batched_vs_separate": ms_s / ms_b, "eval_only_ms": evals})
+    if parity:
+        import oracle
+        errs = []
+        for b in range(0, len(probs), 8):
+            xb, fb = probs[b]
+            idx = workloads.sample_targets(xb.shape[0], 100, 5000 + b)
+            errs.append(oracle.rel_l2(u_b[off[b]:off[b + 1]][idx], oracle.direct(xb, fb, idx)))
+        res["rel_l2_sampled_max"] = max(errs)
+        res["parity_sample"] = "100 targets in each of 32 problems (every 8th)"
+    print(f"# batched: {ms_b:.1f} ms for {len(probs)} problems (separate FP64 plans {ms_s:.1f} ms)",
+          file=sys.stderr, flush=True)
+    del xd, fd, out
+    torch.cuda.empty_cache()
+    return res
 
 
 def copy_calibration(mib: int):
@@ -134,6 +219,8 @@ def main():
     ap.add_argument("--parity-sample", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the tolerance's default leaf size and lane split instead of the autotuner's")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the multi-right-hand-side (and other) variant measurements")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -170,9 +257,17 @@ def main():
     torch.cuda.synchronize()
     print(f"# input ready: {args.config} n={n} tol={tol}", file=sys.stderr, flush=True)
 
+    leaf, lanes = args.leaf_size, args.near_lanes
+    tuned = None
+    if not args.no_autotune and leaf == 0 and lanes == 0:
+        # outside the timed region: picks the leaf size and near-field lane split
+        tuned = dmk.autotune(xd, periodic=periodic, tol=tol)
+        leaf, lanes = tuned["leaf_size"], tuned["near_lanes"]
+        print(f"# autotuned: leaf {leaf}, lanes {lanes} ({tuned['ms']:.1f} ms)", file=sys.stderr, flush=True)
+
     def make_plan(prec):
-        return dmk.Plan(xd, periodic=periodic, tol=tol, leaf_size=args.leaf_size, timing=True,
-                        near_lanes=args.near_lanes, precision=prec, concurrent=True)
+        return dmk.Plan(xd, periodic=periodic, tol=tol, leaf_size=leaf, timing=True,
+                        near_lanes=lanes, precision=prec, concurrent=True)
 
     def timed_steps(prec):
         """Warmup, K timed plan+eval steps, then K eval-only repetitions on the
@@ -221,9 +316,7 @@ def main():
     achieved = stats["in_support"] * fpp / t_near / 1e12
 
     near_kernel = f"dmk::k_near<{nd_bucket(info['deg_P'], info['deg_Q'])}, {info['near_lanes']}, 1>"
-    traffic = None
-    if args.leaf_size == 0 and args.near_lanes == 0:
-        traffic = near_traffic(args.config, tol, "fp64", near_kernel)
+    traffic = near_traffic(args.config, tol, "fp64", near_kernel, info["leaf_size"], info["near_lanes"])
     result = {
         "metric": METRIC,
         "value": n / (ms_per_step * 1e-3),
@@ -239,7 +332,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.config, "n": n, "kind": cfg["kind"], "sigma": cfg["sigma"],
                    "periodic": periodic, "tol": tol, "precision": "fp64", "step": "plan+eval",
-                   "leaf_size": info["leaf_size"]},
+                   "leaf_size": info["leaf_size"], "near_lanes": info["near_lanes"],
+                   "autotuned": tuned is not None},
         "roofline": {"bound": "alu", "kernel": "k_near", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
                      "traffic": traffic, "traffic_unit": "bytes/launch",
@@ -267,7 +361,8 @@ def main():
         u32 = out.cpu().numpy()
         mplan.close()
         print(f"# mixed: {m_step:.2f} ms/step, eval {m_eval:.2f} ms", file=sys.stderr, flush=True)
-        result["variants"] = {"mixed": mixed, "multi_rhs": multi_rhs_variant(args, dev, not args.no_parity)}
+        result["variants"] = {"mixed": mixed, "multi_rhs": multi_rhs_variant(args, dev, not args.no_parity),
+                              "batched": batched_variant(dev, not args.no_parity)}
 
     if not args.no_parity:
         import oracle

@@ -182,7 +182,7 @@ int dmk_stokes_eval(dmk_plan_t plan, const double* forces, int n_rhs, double* ve
 /*
  * Autotuner: picks the leaf size (maximum points per leaf) and the near-field
  * lane split for this workload by timing plan + evaluation on the caller's
- * points.  Leaf sizes 0.4, 0.55, 0.75, 1 and 1.35 times the starting size
+ * points.  Leaf sizes 0.5, 0.75, 1, 1.35, 1.8 and 2.4 times the starting size
  * (opts->leaf_size, else the tolerance's default) are tried with the starting
  * lane split, then 2 and 8 lanes at the best size; each trial keeps the
  * faster of two runs.  The choice is cached per process for the workload class

@@ -1205,7 +1205,7 @@ int dmk_stokes_autotune(const double* points, int64_t n, const int64_t* offsets,
     const int ns0 = opts && opts->leaf_size > 0 ? opts->leaf_size : prm.ns;
     int best_leaf = ns0, best_lanes = opts && opts->near_lanes > 0 ? opts->near_lanes : 4;
     double best = 1e300;
-    for (double fac : {0.4, 0.55, 0.75, 1.0, 1.35}) {
+    for (double fac : {0.5, 0.75, 1.0, 1.35, 1.8, 2.4}) {
         const int leaf = std::max(32, (int)std::lround(ns0 * fac));
         double ms = 0;
         rc = trial(leaf, best_lanes, &ms);
