@@ -152,6 +152,23 @@ int dmk_stokes_plan_ex(const double* points, int64_t n, int dim, int periodic, d
                        dmk_plan_t* out);
 
 /*
+ * Builds a plan for a target set separate from the sources:
+ *   u(t) = sum_s S(t - x_s) f_s   (a target coinciding with a source: that pair contributes nothing)
+ *   sources   device, (n_sources,3) row-major float64
+ *   targets   device, (n_targets,3) row-major float64
+ * One octree covers both sets (split while a box holds more than leaf_size
+ * points, sources and targets together); within each leaf the sources come first, so proxy
+ * charges and the near field's source side run over sources only and the far
+ * field is evaluated at targets only.  dmk_stokes_eval then takes forces
+ * (n_rhs, n_sources, 3) and writes velocities (n_rhs, n_targets, 3).  Built in
+ * order on opts.stream (DMK_FLAG_CONCURRENT_PLAN is refused); allocates and
+ * frees a temporary device copy of both point sets.  Other arguments as
+ * dmk_stokes_plan_ex; plan_info counts n_points = n_sources + n_targets.
+ */
+int dmk_stokes_plan_targets(const double* sources, int64_t n_sources, const double* targets, int64_t n_targets,
+                            int dim, int periodic, double tol, const dmk_opts* opts, dmk_plan_t* out);
+
+/*
  * Builds one plan over n_problems independent problems (each its own free-space
  * sum, or its own periodic unit cell), evaluated together: every pass of
  * dmk_stokes_eval covers all problems in one launch per stage.
@@ -170,8 +187,10 @@ int dmk_stokes_plan_batch(const double* points, const int64_t* offsets, int n_pr
 
 /*
  * Evaluates the sums for n_rhs force vectors on the plan's points.
- *   forces      device, (n_rhs, n, 3) float64, caller's point order
- *   velocities  device, (n_rhs, n, 3) float64, overwritten
+ *   forces      device, (n_rhs, n, 3) float64, caller's point order (n_sources
+ *               rows per vector for a plan with separate targets)
+ *   velocities  device, (n_rhs, n, 3) float64, overwritten (n_targets rows per
+ *               vector for a plan with separate targets)
  * The vectors are taken in batches of up to dmk_opts.rhs_batch: the far-field
  * passes run per vector, the near field once per batch.  Stream-ordered, no
  * host synchronisation; several calls on one plan must not overlap (they share

@@ -19,7 +19,7 @@ STATUS = {0: "DMK_OK", -1: "DMK_ERR_ARG", -2: "DMK_ERR_UNSUPPORTED", -3: "DMK_ER
           -4: "DMK_ERR_NONFINITE", -5: "DMK_ERR_TOL", -6: "DMK_ERR_OOM", -7: "DMK_ERR_HIP"}
 PREC_FP64, PREC_MIXED = 0, 1
 
-SYMBOLS = ["dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_plan_batch", "dmk_stokes_autotune", "dmk_stokes_eval", "dmk_stokes_plan_info",
+SYMBOLS = ["dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_plan_batch", "dmk_stokes_plan_targets", "dmk_stokes_autotune", "dmk_stokes_eval", "dmk_stokes_plan_info",
            "dmk_stokes_tree_leaves", "dmk_stokes_destroy", "dmk_last_error", "dmk_stokes_params",
            "dmk_stokes_radial", "dmk_stokes_mollifier", "dmk_stokes_residual_sum", "dmk_stokes_phase_ms",
            "dmk_stokes_near_stats", "dmk_stokes_release_cached_memory", "dmk_stokes_host_tree"]
@@ -76,6 +76,8 @@ def lib():
         L.dmk_stokes_plan.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(vp)]
         L.dmk_stokes_plan_ex.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                          ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+        L.dmk_stokes_plan_targets.argtypes = [vp, i64, vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                              ctypes.POINTER(Opts), ctypes.POINTER(vp)]
         L.dmk_stokes_plan_batch.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                             ctypes.POINTER(Opts), ctypes.POINTER(vp)]
         L.dmk_stokes_autotune.argtypes = [vp, i64, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -182,19 +184,31 @@ class Plan:
     def __init__(self, points, periodic: bool = False, tol: float = 1e-6, precision: int = PREC_FP64,
                  leaf_size: int = 0, stream=None, mem_cap_bytes: int = 0, timing: bool = False,
                  near_lanes: int = 0, q: int = 0, p: int = 0, rhs_batch: int = 0, concurrent: bool = False,
-                 offsets=None, graph: bool = False):
+                 offsets=None, graph: bool = False, targets=None):
         """offsets (host int sequence, n_problems + 1 entries) makes a batched
-        plan over independent problems (dmk_stokes_plan_batch)."""
+        plan over independent problems (dmk_stokes_plan_batch); targets (device
+        (m,3)) makes a plan evaluating the sums at a separate target set
+        (dmk_stokes_plan_targets): forces (n_rhs, n, 3) -> velocities (n_rhs, m, 3)."""
         torch = _torch()
         pts = _dev_f64(points)
         self.n = int(pts.shape[0])
+        self.n_out = self.n
         self.stream = stream
         opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), int(mem_cap_bytes),
                     (FLAG_PHASE_TIMING if timing else 0) | (FLAG_CONCURRENT_PLAN if concurrent else 0)
                     | (FLAG_GRAPH if graph else 0),
                     int(near_lanes), int(q), int(p), int(rhs_batch))
         h = ctypes.c_void_p()
-        if offsets is None:
+        if targets is not None:
+            if offsets is not None:
+                raise ValueError("targets and offsets cannot be combined")
+            tg = _dev_f64(targets)
+            self.n_out = int(tg.shape[0])
+            _check(lib().dmk_stokes_plan_targets(ctypes.c_void_p(pts.data_ptr()), self.n,
+                                                 ctypes.c_void_p(tg.data_ptr()), self.n_out, 3,
+                                                 int(bool(periodic)), float(tol), ctypes.byref(opts),
+                                                 ctypes.byref(h)))
+        elif offsets is None:
             _check(lib().dmk_stokes_plan_ex(ctypes.c_void_p(pts.data_ptr()), self.n, 3, int(bool(periodic)),
                                             float(tol), ctypes.byref(opts), ctypes.byref(h)))
         else:
@@ -215,7 +229,8 @@ class Plan:
         if f.shape[-2] != self.n:
             raise ValueError("forces must have shape (n,3) or (n_rhs,n,3)")
         if out is None:
-            out = torch.empty_like(f)
+            shape = (self.n_out, 3) if f.dim() == 2 else (n_rhs, self.n_out, 3)
+            out = torch.empty(shape, dtype=f.dtype, device=f.device)
         _check(lib().dmk_stokes_eval(self._h, ctypes.c_void_p(f.data_ptr()), n_rhs,
                                      ctypes.c_void_p(out.data_ptr())))
         return out

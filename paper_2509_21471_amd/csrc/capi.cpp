@@ -197,6 +197,11 @@ struct dmk_plan_s {
     dmk::RadialPoly poly;
     // far-field structure
     int nf = 0;                       // non-empty boxes (far-field slots)
+    // separate targets: input indices < nsrc are sources, indices >= tofs have
+    // an output (a plan with targets = sources: nsrc = n, tofs = 0)
+    int64_t nsrc = 0, tofs = 0, nout = 0;
+    int64_t near_listed = 0;          // sum over near entries of |targets| * |sources|
+    dmk::LeafDesc* leaves_src = nullptr;  // leaves over their source points (anterpolation)
     // independent problems of a batched plan (one problem for dmk_stokes_plan)
     int nprob = 1;
     std::vector<int64_t> offsets;     // point ranges of the problems, caller's order
@@ -503,6 +508,27 @@ int build_plan(dmk_plan_t P, const double* points)
     }
     lap(2);
     const Tree& T = P->tree;
+    // ---- separate targets: sources first within every leaf ----
+    std::vector<int64_t> box_nsrc(T.boxes.size(), 0);
+    if (P->nsrc < n) {
+        std::vector<int> hperm(n);
+        HIPCHK(hipMemcpyAsync(hperm.data(), P->perm, n * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (size_t i = 0; i < T.boxes.size(); ++i) {
+            const Box& B = T.boxes[i];
+            if (!B.leaf)
+                continue;
+            auto first = hperm.begin() + B.start, last = hperm.begin() + B.end;
+            const int64_t ns = P->nsrc;
+            auto mid = std::stable_partition(first, last, [ns](int o) { return o < ns; });
+            box_nsrc[i] = mid - first;
+        }
+        HIPCHK(upload(P->perm, hperm, st));
+        HIPCHK(hipStreamSynchronize(st));
+    } else {
+        for (size_t i = 0; i < T.boxes.size(); ++i)
+            box_nsrc[i] = T.boxes[i].end - T.boxes[i].start;
+    }
     // ---- sorted points ----
     P->x = P->mem.alloc<double>(n);
     P->y = P->mem.alloc<double>(n);
@@ -526,7 +552,7 @@ int build_plan(dmk_plan_t P, const double* points)
         c[1] = -0.5 + (B.iy + 0.5) * h;
         c[2] = -0.5 + (B.iz + 0.5) * h;
     };
-    std::vector<LeafDesc> hl;
+    std::vector<LeafDesc> hl, hl_src;
     P->leaf_box.clear();
     for (int i = 0; i < nb; ++i) {
         const Box& B = T.boxes[i];
@@ -546,13 +572,20 @@ int build_plan(dmk_plan_t P, const double* points)
         d.cy = c[1];
         d.cz = c[2];
         hl.push_back(d);
+        d.end = d.start + box_nsrc[i];
+        hl_src.push_back(d);
     }
     P->nleaf = (int)hl.size();
     P->leaves = P->mem.alloc<LeafDesc>(hl.size());
+    P->leaves_src = P->nsrc < n ? P->mem.alloc<LeafDesc>(hl_src.size()) : P->leaves;
+    // far field at the target points of each leaf (after its sources)
     std::vector<EvalChunk> ech;
-    for (const LeafDesc& d : hl)
-        for (int64_t s0 = d.start; s0 < d.end; s0 += kEvalChunk)
-            ech.push_back(EvalChunk{d.fid, s0, std::min<int64_t>(s0 + kEvalChunk, d.end)});
+    for (size_t k = 0; k < hl.size(); ++k) {
+        const LeafDesc& d = hl[k];
+        const int64_t t0 = P->nsrc < n ? hl_src[k].end : d.start;
+        for (int64_t s0 = t0; s0 < d.end; s0 += eval_chunk_points(P->prm.p))
+            ech.push_back(EvalChunk{d.fid, s0, std::min<int64_t>(s0 + eval_chunk_points(P->prm.p), d.end)});
+    }
     P->n_echunk = (int)ech.size();
     P->echunks = P->mem.alloc<EvalChunk>(ech.size());
     P->Ltab = P->mem.alloc<double>((size_t)n * 3 * lagrange_pad(P->prm.p));
@@ -617,12 +650,14 @@ int build_plan(dmk_plan_t P, const double* points)
     std::vector<int> leaf_cbase(nb, -1);
     std::vector<int64_t> cstart;
     std::vector<int> clen;
+    const bool split = P->nsrc < n;
     for (int li = 0; li < (int)T.leaves.size(); ++li) {
         const Box& B = T.boxes[T.leaves[li]];
+        const int64_t se = B.start + box_nsrc[T.leaves[li]];
         leaf_cbase[T.leaves[li]] = (int)cstart.size();
-        for (int64_t s = B.start; s < B.end; s += 64) {
+        for (int64_t s = B.start; s < se; s += 64) {
             cstart.push_back(s);
-            clen.push_back((int)std::min<int64_t>(64, B.end - s));
+            clen.push_back((int)std::min<int64_t>(64, se - s));
         }
     }
     std::vector<NearLeaf> nlv;
@@ -631,7 +666,7 @@ int build_plan(dmk_plan_t P, const double* points)
     for (int li = 0; li < (int)T.leaves.size(); ++li) {
         const Box& B = T.boxes[T.leaves[li]];
         NearLeaf L;
-        L.tstart = B.start;
+        L.tstart = split ? B.start + box_nsrc[T.leaves[li]] : B.start;
         L.tend = B.end;
         L.level = B.level;
         L.cbase = leaf_cbase[T.leaves[li]];
@@ -640,17 +675,18 @@ int build_plan(dmk_plan_t P, const double* points)
             const Box& S = T.boxes[e.src];
             NearEntryDev d;
             d.sstart = S.start;
-            d.send = S.end;
+            d.send = S.start + box_nsrc[e.src];
             d.cbase = leaf_cbase[e.src];
             d.sx = e.sx;
             d.sy = e.sy;
             d.sz = e.sz;
             d.lambda = e.lambda;
             nent.push_back(d);
+            P->near_listed += (L.tend - L.tstart) * (d.send - d.sstart);
         }
         L.eend = (int)nent.size();
         const int tg = 64 / P->near_sg;
-        const int nch = (int)((B.end - B.start + tg - 1) / tg);
+        const int nch = (int)((L.tend - L.tstart + tg - 1) / tg);
         for (int c = 0; c < nch; ++c)
             nwk.push_back(NearWork{li, c});
         nlv.push_back(L);
@@ -732,6 +768,8 @@ int build_plan(dmk_plan_t P, const double* points)
     lap(4);
     HIPCHK(upload(P->d_root_fid, P->root_fid, st));
     HIPCHK(upload(P->leaves, hl, st));
+    if (P->leaves_src != P->leaves)
+        HIPCHK(upload(P->leaves_src, hl_src, st));
     HIPCHK(upload(P->echunks, ech, st));
     HIPCHK(upload(P->send_fid, sfid, st));
     HIPCHK(upload(P->recv_fid, rfid, st));
@@ -778,7 +816,7 @@ void far_field(dmk_plan_t P, int r, bool record)
     const long p3 = (long)p * p * p, p2 = (long)p * p;
     const Tree& T = P->tree;
     // Step 2a: proxy charges of the leaves
-    launch_anterp(p, P->leaves, P->nleaf, P->Ltab, fs, n, P->Q, P->f32, st);
+    launch_anterp(p, P->leaves_src, P->nleaf, P->Ltab, fs, n, P->Q, P->f32, st);
     mark(1);
     const int h = (p + 1) / 2, M = q - 1;
     // Step 2b: merge children into parents, finest level first (Q is x-major [a][b][c])
@@ -868,7 +906,7 @@ int eval_batch(dmk_plan_t P, const double* f, int nb, double* vel, bool record)
     if (record)
         (void)hipEventRecord(P->ev[0], st);
     for (int r = 0; r < nb; ++r)
-        launch_gather_forces(f + (size_t)r * 3 * n, n, P->perm, P->fs + (size_t)r * 3 * n, st);
+        launch_gather_forces(f + (size_t)r * 3 * P->nsrc, n, P->nsrc, P->perm, P->fs + (size_t)r * 3 * n, st);
     for (int r = 0; r < nb; ++r)
         far_field(P, r, record && r == 0);
     if (record)
@@ -878,8 +916,9 @@ int eval_batch(dmk_plan_t P, const double* f, int nb, double* vel, bool record)
     if (record)
         (void)hipEventRecord(P->ev[9], st);
     for (int r = 0; r < nb; ++r)
-        launch_finalize(P->u + (size_t)r * 3 * n, n, P->perm, P->pid, P->scale,
-                        P->periodic ? nullptr : P->cst + (size_t)3 * P->nprob * r, vel + (size_t)r * 3 * n, st);
+        launch_finalize(P->u + (size_t)r * 3 * n, n, P->perm, P->tofs, P->pid, P->scale,
+                        P->periodic ? nullptr : P->cst + (size_t)3 * P->nprob * r, vel + (size_t)r * 3 * P->nout,
+                        st);
     if (record) {
         (void)hipEventRecord(P->ev[10], st);
         P->ev_recorded = true;
@@ -952,7 +991,7 @@ namespace {
 
 // Common plan construction for one problem (offsets {0, n}) or a batch.
 int create_plan(const double* points, const std::vector<int64_t>& offsets, int dim, int periodic, double tol,
-                const dmk_opts* opts, dmk_plan_t* out)
+                const dmk_opts* opts, dmk_plan_t* out, int64_t nsrc = -1)
 {
     const int64_t n = offsets.back();
 
@@ -1006,6 +1045,9 @@ int create_plan(const double* points, const std::vector<int64_t>& offsets, int d
     P->periodic = periodic != 0;
     P->nprob = (int)offsets.size() - 1;
     P->offsets = offsets;
+    P->nsrc = nsrc < 0 ? n : nsrc;
+    P->tofs = nsrc < 0 ? 0 : nsrc;
+    P->nout = n - P->tofs;
     rc = build_plan(P, points);
     if (rc != DMK_OK) {
         (void)hipStreamSynchronize(P->concurrent ? plan_stream() : P->stream);
@@ -1033,6 +1075,44 @@ int dmk_stokes_plan_ex(const double* points, int64_t n, int dim, int periodic, d
     if (n > (int64_t)2000000000)
         return fail(DMK_ERR_ARG, "n too large");
     return create_plan(points, {0, n}, dim, periodic, tol, opts, out);
+}
+
+int dmk_stokes_plan_targets(const double* sources, int64_t n_sources, const double* targets, int64_t n_targets,
+                            int dim, int periodic, double tol, const dmk_opts* opts, dmk_plan_t* out)
+{
+    if (!out)
+        return fail(DMK_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!sources || !targets)
+        return fail(DMK_ERR_ARG, "sources or targets is NULL");
+    if (n_sources < 1 || n_targets < 1)
+        return fail(DMK_ERR_ARG, "n_sources and n_targets must be >= 1");
+    if (n_sources + n_targets > (int64_t)2000000000)
+        return fail(DMK_ERR_ARG, "n too large");
+    if (!is_device_ptr(sources) || !is_device_ptr(targets))
+        return fail(DMK_ERR_ARG, "sources and targets must be device pointers");
+    if (opts && (opts->flags & DMK_FLAG_CONCURRENT_PLAN))
+        return fail(DMK_ERR_ARG, "DMK_FLAG_CONCURRENT_PLAN is not available for separate targets");
+    int rc = validate_common(dim, tol, opts);
+    if (rc != DMK_OK)
+        return rc;
+    // one point set: sources then targets, in order on the caller's stream
+    const int64_t n = n_sources + n_targets;
+    hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+    double* pts = nullptr;
+    HIPCHK(hipMalloc((void**)&pts, (size_t)n * 3 * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(pts, sources, (size_t)n_sources * 3 * sizeof(double), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pts + 3 * n_sources, targets, (size_t)n_targets * 3 * sizeof(double),
+                           hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) {
+        (void)hipFree(pts);
+        return fail(DMK_ERR_HIP, std::string("copy of the points failed: ") + hipGetErrorString(e));
+    }
+    rc = create_plan(pts, {0, n}, dim, periodic, tol, opts, out, n_sources);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(pts);
+    return rc;
 }
 
 int dmk_stokes_plan_batch(const double* points, const int64_t* offsets, int n_problems, int dim, int periodic,
@@ -1075,8 +1155,8 @@ int dmk_stokes_eval(dmk_plan_t plan, const double* forces, int n_rhs, double* ve
             int nb = plan->rhs_batch;
             while (nb > n_rhs - r)
                 nb >>= 1;
-            const int rc = eval_batch(plan, forces + (size_t)r * 3 * plan->n, nb,
-                                      velocities + (size_t)r * 3 * plan->n, timing && r == 0);
+            const int rc = eval_batch(plan, forces + (size_t)r * 3 * plan->nsrc, nb,
+                                      velocities + (size_t)r * 3 * plan->nout, timing && r == 0);
             if (rc != DMK_OK)
                 return rc;
             r += nb;
@@ -1264,7 +1344,7 @@ int dmk_stokes_plan_info(dmk_plan_t plan, dmk_plan_info* info)
     info->n_leaves = (int64_t)P.leaf_box.size();
     info->n_nonempty_boxes = P.nf;
     info->n_nonempty_leaves = P.nleaf;
-    info->near_pairs = P.tree.n_near_pairs;
+    info->near_pairs = P.near_listed;
     info->n_senders = P.nsend;
     info->n_receivers = P.nrecv;
     for (int d = 0; d < 3; ++d)
@@ -1334,7 +1414,7 @@ int dmk_stokes_near_stats(dmk_plan_t plan, int64_t* listed, int64_t* evaluated, 
     if (!plan)
         return fail(DMK_ERR_ARG, "plan is NULL");
     if (listed)
-        *listed = plan->tree.n_near_pairs;
+        *listed = plan->near_listed;
     DevMem mem;
     unsigned long long* d = mem.alloc<unsigned long long>(2);
     if (!d)

@@ -261,21 +261,24 @@ void launch_chunk_bbox(const double* x, const double* y, const double* z, const 
 // =============================================================================
 // per evaluation
 // =============================================================================
-__global__ __launch_bounds__(256) void k_gather_forces(const double* __restrict__ f, int64_t n,
+// Sorted forces: points with input index < nsrc are sources (force f[o]),
+// the rest are targets only (zero force).
+__global__ __launch_bounds__(256) void k_gather_forces(const double* __restrict__ f, int64_t n, int64_t nsrc,
                                                        const int* __restrict__ perm, double* __restrict__ fs)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n)
         return;
     const int64_t o = perm[i];
-    fs[i] = f[3 * o];
-    fs[n + i] = f[3 * o + 1];
-    fs[2 * n + i] = f[3 * o + 2];
+    const bool src = o < nsrc;
+    fs[i] = src ? f[3 * o] : 0.0;
+    fs[n + i] = src ? f[3 * o + 1] : 0.0;
+    fs[2 * n + i] = src ? f[3 * o + 2] : 0.0;
 }
 
-void launch_gather_forces(const double* f, int64_t n, const int* perm, double* fs, hipStream_t s)
+void launch_gather_forces(const double* f, int64_t n, int64_t nsrc, const int* perm, double* fs, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gather_forces, dim3(nblocks(n, 256)), dim3(256), 0, s, f, n, perm, fs);
+    hipLaunchKernelGGL(k_gather_forces, dim3(nblocks(n, 256)), dim3(256), 0, s, f, n, nsrc, perm, fs);
 }
 
 // Barycentric Lagrange basis on first-kind Chebyshev nodes.
@@ -393,6 +396,7 @@ __global__ __launch_bounds__(AnterpCfg<P>::threads) void k_anterp(const LeafDesc
     const double* f0 = fs;
     const double* f1 = fs + n;
     const double* f2 = fs + 2 * n;
+    // the per-point x weights and forces are wave-uniform (scalar loads)
 #pragma unroll 2
     for (int64_t pt = L.start; pt < L.end; ++pt) {
         const double* Lp = Ltab + (size_t)pt * 3 * PA;
@@ -420,15 +424,25 @@ __global__ __launch_bounds__(AnterpCfg<P>::threads) void k_anterp(const LeafDesc
 // for every z index c, D[b][pt] = sum_a V[j][c][b][a] Lx[pt][a] (V z-major),
 // then u_j[pt] += Lz[pt][c] sum_b Ly[pt][b] D[b][pt].  A block takes 64 points
 // of one leaf (16 per wave); the z-slab of V sits in LDS.
+// points per leaf-evaluation block (4 lanes per point): 256 where the kernel
+// fits the 128 registers of a 1024-thread block, else 128
+template <int P>
+struct EvalCfg {
+    static constexpr int PTS = (P <= 16 || P == 23 || P == 30) ? 256 : 128;
+};
+int eval_chunk_points(int p) { return (p <= 16 || p == 23 || p == 30) ? 256 : 128; }
+
 template <int P, typename S>
-__global__ __launch_bounds__(kEvalChunk * 4) void k_leaf_eval(const EvalChunk* __restrict__ chunks, int nchunk,
+__global__ __launch_bounds__(EvalCfg<P>::PTS * 4) void k_leaf_eval(const EvalChunk* __restrict__ chunks, int nchunk,
                                                               const double* __restrict__ Ltab,
                                                               const S* __restrict__ V, int64_t n,
                                                               double* __restrict__ u)
 {
     constexpr int PA = MCfg<P>::PA, NK = MCfg<P>::NK, NT = MCfg<P>::NT, RS = MCfg<P>::RS;
     constexpr int PB = 16 * NT;
-    __shared__ double slab[3][PB][RS];
+    constexpr int NTH = EvalCfg<P>::PTS * 4;
+    constexpr int NPRE = (3 * P * P + NTH - 1) / NTH;  // slab elements per thread
+    __shared__ double slab[2][3][PB][RS];               // double-buffered c-slabs
     const EvalChunk C = chunks[blockIdx.x];
     const S* v = V + (size_t)C.fid * 3 * P * P * P;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
@@ -448,16 +462,41 @@ __global__ __launch_bounds__(kEvalChunk * 4) void k_leaf_eval(const EvalChunk* _
             const int b = 16 * t + lk + 4 * r;
             wy[t][r] = (valid && b < P) ? Li[PA + b] : 0.0;
         }
-    for (int e = tid; e < 3 * PB * RS; e += kEvalChunk * 4)
-        (&slab[0][0][0])[e] = 0.0;
-    double u0 = 0, u1 = 0, u2 = 0;
-    for (int c = 0; c < P; ++c) {
-        __syncthreads();
-        for (int e = tid; e < 3 * P * P; e += kEvalChunk * 4) {
-            const int j = e / (P * P), r = e % (P * P);
-            slab[j][r / P][r % P] = (double)v[(size_t)j * P * P * P + (size_t)c * P * P + r];
+    // the padding rows / columns of both buffers stay zero
+    for (int e = tid; e < 2 * 3 * PB * RS; e += NTH)
+        (&slab[0][0][0][0])[e] = 0.0;
+    // slab c+1 is loaded into registers while slab c is used from LDS
+    double pre[NPRE];
+    auto fetch = [&](int c) {
+#pragma unroll
+        for (int k = 0; k < NPRE; ++k) {
+            const int e = tid + k * NTH;
+            if (e < 3 * P * P) {
+                const int j = e / (P * P), r = e % (P * P);
+                pre[k] = (double)v[(size_t)j * P * P * P + (size_t)c * P * P + r];
+            }
         }
-        __syncthreads();
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < NPRE; ++k) {
+            const int e = tid + k * NTH;
+            if (e < 3 * P * P) {
+                const int j = e / (P * P), r = e % (P * P);
+                slab[buf][j][r / P][r % P] = pre[k];
+            }
+        }
+    };
+    __syncthreads();
+    fetch(0);
+    put(0);
+    __syncthreads();
+    double u0 = 0, u1 = 0, u2 = 0;
+#pragma unroll 1
+    for (int c = 0; c < P; ++c) {
+        const int cur = c & 1;
+        if (c + 1 < P)
+            fetch(c + 1);
         const double lz = valid ? Li[2 * PA + c] : 0.0;
         double X[3] = {0, 0, 0};
 #pragma unroll
@@ -467,7 +506,8 @@ __global__ __launch_bounds__(kEvalChunk * 4) void k_leaf_eval(const EvalChunk* _
                 mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int s = 0; s < NK; ++s)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(slab[j][16 * t + lr][4 * s + lk], bx[s], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(slab[cur][j][16 * t + lr][4 * s + lk], bx[s], acc, 0, 0,
+                                                               0);
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     X[j] = fma(wy[t][r], acc[r], X[j]);
@@ -475,6 +515,10 @@ __global__ __launch_bounds__(kEvalChunk * 4) void k_leaf_eval(const EvalChunk* _
         u0 = fma(lz, X[0], u0);
         u1 = fma(lz, X[1], u1);
         u2 = fma(lz, X[2], u2);
+        // the other buffer was last read before the previous barrier
+        if (c + 1 < P)
+            put(cur ^ 1);
+        __syncthreads();
     }
     // the four lanes of a point hold disjoint b rows
     u0 += __shfl_xor(u0, 16);
@@ -548,13 +592,13 @@ void launch_leaf_eval(int p, const EvalChunk* chunks, int nchunk, const double* 
 {
     if (nchunk == 0)
         return;
-#define L_EVAL(P)                                                                                                 \
-    if (f32)                                                                                                      \
-        hipLaunchKernelGGL((k_leaf_eval<P, float>), dim3(nchunk), dim3(kEvalChunk * 4), 0, s, chunks, nchunk, Ltab, \
-                           (const float*)V, n, u);                                                                \
-    else                                                                                                          \
-        hipLaunchKernelGGL((k_leaf_eval<P, double>), dim3(nchunk), dim3(kEvalChunk * 4), 0, s, chunks, nchunk,    \
-                           Ltab, (const double*)V, n, u)
+#define L_EVAL(P)                                                                                               \
+    if (f32)                                                                                                    \
+        hipLaunchKernelGGL((k_leaf_eval<P, float>), dim3(nchunk), dim3(EvalCfg<P>::PTS * 4), 0, s, chunks, nchunk, \
+                           Ltab, (const float*)V, n, u);                                                        \
+    else                                                                                                        \
+        hipLaunchKernelGGL((k_leaf_eval<P, double>), dim3(nchunk), dim3(EvalCfg<P>::PTS * 4), 0, s, chunks,     \
+                           nchunk, Ltab, (const double*)V, n, u)
     DMK_P_DISPATCH(p, L_EVAL)
 #undef L_EVAL
 }
@@ -1342,13 +1386,17 @@ void launch_sum_root(const void* Q, const int* root_fid, int nroot, int p3, doub
 // vel (caller's order) = scale_b (u + c_b), b the point's problem: scale_b
 // undoes that problem's unit-box map, c_b its free-space constant (or none).
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ u, int64_t n, const int* __restrict__ perm,
-                                                  const int* __restrict__ pid, const double* __restrict__ scale,
-                                                  const double* __restrict__ cst, double* __restrict__ vel)
+                                                  int64_t tofs, const int* __restrict__ pid,
+                                                  const double* __restrict__ scale, const double* __restrict__ cst,
+                                                  double* __restrict__ vel)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n)
         return;
-    const int64_t o = perm[i];
+    // input indices below tofs are sources without a velocity output
+    const int64_t o = perm[i] - tofs;
+    if (o < 0)
+        return;
     const int b = pid ? pid[i] : 0;
     const double sc = scale[b];
     const double c0 = cst ? cst[3 * b] : 0.0, c1 = cst ? cst[3 * b + 1] : 0.0, c2 = cst ? cst[3 * b + 2] : 0.0;
@@ -1357,10 +1405,10 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ u, 
     vel[3 * o + 2] = sc * (u[2 * n + i] + c2);
 }
 
-void launch_finalize(const double* u, int64_t n, const int* perm, const int* pid, const double* scale,
+void launch_finalize(const double* u, int64_t n, const int* perm, int64_t tofs, const int* pid, const double* scale,
                      const double* cst, double* vel, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(nblocks(n, 256)), dim3(256), 0, s, u, n, perm, pid, scale, cst, vel);
+    hipLaunchKernelGGL(k_finalize, dim3(nblocks(n, 256)), dim3(256), 0, s, u, n, perm, tofs, pid, scale, cst, vel);
 }
 
 __global__ __launch_bounds__(256) void k_zero(uint32_t* __restrict__ p, size_t count)

@@ -38,7 +38,8 @@ void launch_chunk_bbox(const double* x, const double* y, const double* z, const 
 
 // ---- per evaluation --------------------------------------------------------
 // forces (n,3) original order -> sorted SoA fs[3][n]
-void launch_gather_forces(const double* f, int64_t n, const int* perm, double* fs, hipStream_t s);
+// points with input index < nsrc carry forces, the others (targets only) zero
+void launch_gather_forces(const double* f, int64_t n, int64_t nsrc, const int* perm, double* fs, hipStream_t s);
 
 struct LeafDesc {
     int fid;          // far-field slot of the leaf
@@ -58,9 +59,9 @@ void launch_lagrange_table(int p, const LeafDesc* leaves, int nleaf, const doubl
 void launch_anterp(int p, const LeafDesc* leaves, int nleaf, const double* Ltab, const double* fs, int64_t n,
                    void* Q, bool f32, hipStream_t s);
 // far-field value at the points (final interpolation), V z-major V[fid][j][c][b][a]:
-// u[j][i] = sum V L L L, over chunks of at most kEvalChunk points of one leaf
-// (one block of 4 kEvalChunk threads per chunk)
-constexpr int kEvalChunk = 256;
+// u[j][i] = sum V L L L, over chunks of at most eval_chunk_points(p) points of
+// one leaf (one block of 4 threads per point)
+int eval_chunk_points(int p);
 struct EvalChunk {
     int fid;
     int64_t start, end;
@@ -159,9 +160,9 @@ void launch_residual_direct(const double* tx, const double* ty, const double* tz
 // out[3r + j] = coef * sum_k Q[root_fid[r]][j][k]
 void launch_sum_root(const void* Q, const int* root_fid, int nroot, int p3, double coef, double* out, bool f32,
                      hipStream_t s);
-// u_out[(rhs) n,3 original order] = scale * u[j][i] + cst[j]
-// per point of problem b: vel = scale[b] * (u + cst[3b..]) (cst may be NULL), unpermuted
-void launch_finalize(const double* u, int64_t n, const int* perm, const int* pid, const double* scale,
+// per point of problem b with input index o >= tofs (the points with an output):
+// vel[o - tofs] = scale[b] * (u + cst[3b..]) (cst may be NULL)
+void launch_finalize(const double* u, int64_t n, const int* perm, int64_t tofs, const int* pid, const double* scale,
                      const double* cst, double* vel, hipStream_t s);
 // zero `bytes` (a multiple of 4) at p
 void launch_zero(void* p, size_t bytes, hipStream_t s);

@@ -291,3 +291,62 @@ def test_autotune(dev):
     assert t2 == t1
     u, _ = _eval(x, f, tol=1e-6, leaf_size=t1["leaf_size"], near_lanes=t1["near_lanes"])
     assert oracle.rel_l2(u, oracle.direct(x, f)) < 1e-6
+
+
+def _direct_targets(xs, fs, xt):
+    """Direct sum at separate targets: the oracle on the union of the two sets
+    with zero forces on the targets (zero-force points contribute nothing and
+    coincident pairs are skipped)."""
+    x = np.concatenate([xs, xt])
+    f = np.concatenate([fs, np.zeros_like(xt)])
+    idx = np.arange(xs.shape[0], x.shape[0])
+    return oracle.direct(x, f, idx)
+
+
+@pytest.mark.parametrize("n_rhs", [1, 3])
+def test_separate_targets(dev, n_rhs):
+    """Sums at a separate target set, including targets that coincide with
+    sources, against the direct sum."""
+    xs, fs = workloads.make("clusters", 20000, seed=96, sigma=0.05, n_rhs=n_rhs)
+    rng = np.random.default_rng(97)
+    xt = np.concatenate([rng.random((4000, 3)), xs[rng.choice(20000, 100, replace=False)]])
+    plan = _dmk().Plan(_t(xs), tol=1e-6, leaf_size=200, targets=_t(xt))
+    u = plan.eval(_t(fs)).cpu().numpy()
+    plan.close()
+    assert u.shape == ((xt.shape[0], 3) if n_rhs == 1 else (n_rhs, xt.shape[0], 3))
+    fr = fs if n_rhs == 1 else fs[-1]
+    ur = u if n_rhs == 1 else u[-1]
+    err = oracle.rel_l2(ur, _direct_targets(xs, fr, xt))
+    print("targets", n_rhs, err)
+    assert err < 1e-6
+
+
+def test_separate_targets_periodic(dev):
+    from oracle.ewald import ewald
+    xs, fs = workloads.make("periodic", 3000, seed=98)
+    xt = np.random.default_rng(99).random((600, 3))
+    plan = _dmk().Plan(_t(xs), periodic=True, tol=1e-6, leaf_size=150, targets=_t(xt))
+    u = plan.eval(_t(fs)).cpu().numpy()
+    plan.close()
+    x = np.concatenate([xs, xt])
+    f = np.concatenate([fs, np.zeros_like(xt)])
+    ref = ewald(x, f, np.arange(3000, 3600))
+    assert oracle.rel_l2(u, ref) < 1e-6
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-9])
+def test_sphere_1e6_targets(dev, tol):
+    """1e6 sources and 1e6 separate targets on a perturbed sphere (deep
+    adaptive tree), 500 sampled targets against the direct sum."""
+    cfg = workloads.CONFIGS["sphere_1e6"]
+    xs, fs = workloads.config("sphere_1e6")
+    xt = workloads.sphere_targets(cfg["n_targets"], cfg["seed"])
+    plan = _dmk().Plan(_t(xs), tol=tol, targets=_t(xt))
+    u = plan.eval(_t(fs)).cpu().numpy()
+    info = plan.info()
+    plan.close()
+    idx = workloads.sample_targets(xt.shape[0], 500, cfg["seed"])
+    err = oracle.rel_l2(u[idx], _direct_targets(xs, fs, xt[idx]))
+    print("sphere", tol, info["levels"], err)
+    assert info["levels"] >= 6
+    assert err < tol

@@ -12,6 +12,8 @@ Workloads (all 3D, forces i.i.d. N(0,1) per component):
   fall outside [0,1)^3 are redrawn from the same cluster.
 * ``periodic``   -- uniform points, forces with the per-component mean removed
   (zero net force).
+* ``sphere``     -- points on a perturbed sphere (radius 0.3, relative
+  perturbation 0.15 sin(3 theta) cos(4 phi)), sources and a separate target set.
 * ``batch``      -- many independent problems with N log-uniform in [1e3, 1e5],
   each uniform or a single Gaussian blob (sigma 0.1, centre in [0.25,0.75]^3)
   chosen by a seeded coin.
@@ -65,6 +67,19 @@ def blob_points(rng: np.random.Generator, n: int, sigma: float = 0.1) -> np.ndar
     return np.ascontiguousarray(np.concatenate(pts, axis=0))
 
 
+def sphere_points(rng: np.random.Generator, n: int) -> np.ndarray:
+    """Points on a perturbed sphere: r(theta, phi) = 0.3 (1 + 0.15 sin(3 theta)
+    cos(4 phi)) around (0.5, 0.5, 0.5), (cos theta, phi) uniform.  A surface
+    distribution gives the deep, strongly adaptive trees of the paper's timing
+    setup; the perturbation law is this generator's own choice."""
+    ct = rng.uniform(-1.0, 1.0, n)
+    ph = rng.uniform(0.0, 2.0 * np.pi, n)
+    th = np.arccos(ct)
+    r = 0.3 * (1.0 + 0.15 * np.sin(3.0 * th) * np.cos(4.0 * ph))
+    st = np.sqrt(1.0 - ct * ct)
+    return np.ascontiguousarray(0.5 + np.stack([r * st * np.cos(ph), r * st * np.sin(ph), r * ct], axis=1))
+
+
 def forces(rng: np.random.Generator, n: int, n_rhs: int = 1, zero_mean: bool = False) -> np.ndarray:
     f = rng.standard_normal((n_rhs, n, 3))
     if zero_mean:
@@ -87,9 +102,17 @@ def make(kind: str, n: int, seed: int, sigma: float = 0.02, n_rhs: int = 1):
     elif kind == "blob":
         x = blob_points(rng, n, sigma)
         f = forces(rng, n, n_rhs)
+    elif kind == "sphere":
+        x = sphere_points(rng, n)
+        f = forces(rng, n, n_rhs)
     else:
         raise ValueError(f"unknown workload kind {kind!r}")
     return np.ascontiguousarray(x), np.ascontiguousarray(f)
+
+
+def sphere_targets(m: int, seed: int) -> np.ndarray:
+    """A separate target set on the same perturbed sphere (seed + 200)."""
+    return sphere_points(_rng(seed + 200), m)
 
 
 def sample_targets(n: int, m: int, seed: int) -> np.ndarray:
@@ -118,6 +141,8 @@ CONFIGS = {
     "clusters_1e6": dict(kind="clusters", n=1_000_000, seed=2, sigma=0.02, periodic=False, tol=1e-6),
     "periodic_2e6": dict(kind="periodic", n=2_000_000, seed=3, sigma=0.0, periodic=True, tol=1e-9),
     "clusters_4e6": dict(kind="clusters", n=4_000_000, seed=4, sigma=0.01, periodic=False, tol=1e-6),
+    # sources and separate targets on a perturbed sphere
+    "sphere_1e6": dict(kind="sphere", n=1_000_000, seed=6, sigma=0.0, periodic=False, tol=1e-6, n_targets=1_000_000),
     # one plan, 32 force vectors (forces shaped (32, N, 3))
     "uniform_2e6_rhs32": dict(kind="uniform", n=2_000_000, seed=5, sigma=0.0, periodic=False, tol=1e-6, n_rhs=32),
 }
