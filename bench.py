@@ -48,7 +48,7 @@ def near_traffic(config: str, tol: float, precision: str, kernel: str, leaf_size
     section changed since the counters were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", f"k_near_{config}_{precision}.md")
+    path = os.path.join(ROOT, "profiles", f"k_near_{config}_{precision}_leaf{leaf_size}_lanes{near_lanes}.md")
     if not os.path.exists(path) or abs(tol - workloads_tol(config)) > 0:
         return None
     m = re.search(r'^\{"kernel".*\}$', open(path).read(), re.M)

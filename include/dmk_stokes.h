@@ -204,7 +204,7 @@ int dmk_stokes_eval(dmk_plan_t plan, const double* forces, int n_rhs, double* ve
  * points.  Leaf sizes 0.5, 0.75, 1, 1.35, 1.8 and 2.4 times the starting size
  * (opts->leaf_size, else the tolerance's default) are tried with the starting
  * lane split, then 2 and 8 lanes at the best size; each trial keeps the
- * faster of two runs.  The choice is cached per process for the workload class
+ * fastest of three runs.  The choice is cached per process for the workload class
  * (n and n_problems to the nearest power of two, periodicity, tol, precision,
  * n_rhs, q, p): a later call for the same class returns at once.
  *   points, n                as dmk_stokes_plan_ex (device points)

@@ -1263,7 +1263,7 @@ int dmk_stokes_autotune(const double* points, int64_t n, const int64_t* offsets,
         o.leaf_size = leaf;
         o.near_lanes = lanes;
         double best = 1e300;
-        for (int rep = 0; rep < 2; ++rep) {
+        for (int rep = 0; rep < 3; ++rep) {
             (void)hipStreamSynchronize(st);
             const auto t0 = std::chrono::steady_clock::now();
             dmk_plan_t P = nullptr;
