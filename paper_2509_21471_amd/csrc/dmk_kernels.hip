@@ -534,6 +534,112 @@ __global__ __launch_bounds__(EvalCfg<P>::PTS * 4) void k_leaf_eval(const EvalChu
     }
 }
 
+// Proxy charges (Step 2a) as MFMA contractions over the points:
+//   Q_j[a][n] = sum_pt Lx[pt][a] W_j[pt][n],  W_j[pt][n] = Ly[pt][b] Lz[pt][c] f_j[pt],  n = b P + c,
+// with v_mfma_f64_16x16x4f64: rows = a (16-tile), columns = n (16-tiles of the
+// flattened (b, c) index, so Q's x-major rows are stored contiguously), K = 4
+// points.  One wave per (leaf, a-tile, group of NN n-tiles); lane l feeds the
+// A operand Lx[pt0 + l/16][a0 + l%16] and forms the B operand
+// Ly[pt0 + l/16][b] Lz[pt0 + l/16][c] f_j for its column, all from vector
+// loads; the next 4 points' operands load while the current MFMAs run.
+template <int P>
+struct AMCfg {
+    static constexpr int PA = MCfg<P>::PA;
+    static constexpr int MT = (P + 15) / 16;         // a-tiles
+    static constexpr int NTOT = (P * P + 15) / 16;   // n-tiles
+    static constexpr int NN = 2;                     // n-tiles per wave
+    static constexpr int NG = (NTOT + NN - 1) / NN;  // n-tile groups
+    static constexpr int TASKS = MT * NG;            // waves per leaf
+};
+
+template <int P, typename S>
+__global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__ leaves, int nleaf,
+                                                    const double* __restrict__ Ltab,
+                                                    const double* __restrict__ fs, int64_t n, S* __restrict__ Q)
+{
+    using C = AMCfg<P>;
+    constexpr int PA = C::PA, NN = C::NN;
+    const int task = blockIdx.x % C::TASKS;
+    const LeafDesc L = leaves[blockIdx.x / C::TASKS];
+    const int mt = task % C::MT, ng = task / C::MT;
+    const int l = threadIdx.x;
+    const int li = l & 15, lk = l >> 4;
+    const int a = 16 * mt + li;
+    const bool a_ok = a < P;
+    int bcol[NN], ccol[NN];
+    bool n_ok[NN];
+#pragma unroll
+    for (int t = 0; t < NN; ++t) {
+        const int nn = 16 * (NN * ng + t) + li;
+        n_ok[t] = nn < P * P;
+        bcol[t] = n_ok[t] ? nn / P : 0;
+        ccol[t] = n_ok[t] ? nn % P : 0;
+    }
+    mfma_d4 acc[NN][3];
+#pragma unroll
+    for (int t = 0; t < NN; ++t)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            acc[t][j] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+    // operands of the 4 points starting at pt0 (this lane: point pt0 + lk)
+    double ax0, f00, f10, f20, ly0[NN], lz0[NN];
+    double ax1, f01, f11, f21, ly1[NN], lz1[NN];
+#define DMK_AM_LOAD(AX, F0, F1, F2, LY, LZ, PT0)                                   \
+    {                                                                             \
+        const int64_t pt = (PT0) + lk;                                            \
+        const bool ok = pt < L.end;                                               \
+        const int64_t pc = ok ? pt : L.start;                                     \
+        const double* Lp = Ltab + (size_t)pc * 3 * PA;                            \
+        const double ax = Lp[a_ok ? a : 0];                                       \
+        const double g0 = fs[pc], g1 = fs[n + pc], g2 = fs[2 * n + pc];           \
+        AX = (ok && a_ok) ? ax : 0.0;                                             \
+        F0 = ok ? g0 : 0.0;                                                       \
+        F1 = ok ? g1 : 0.0;                                                       \
+        F2 = ok ? g2 : 0.0;                                                       \
+        _Pragma("unroll") for (int t = 0; t < NN; ++t)                            \
+        {                                                                         \
+            const double yv = Lp[PA + bcol[t]];                                   \
+            LY[t] = n_ok[t] ? yv : 0.0;                                           \
+            LZ[t] = Lp[2 * PA + ccol[t]];                                         \
+        }                                                                         \
+    }
+#define DMK_AM_STEP(AX, F0, F1, F2, LY, LZ)                                                   \
+    _Pragma("unroll") for (int t = 0; t < NN; ++t)                                            \
+    {                                                                                         \
+        const double w = LY[t] * LZ[t];                                                       \
+        acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(AX, w * F0, acc[t][0], 0, 0, 0);     \
+        acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(AX, w * F1, acc[t][1], 0, 0, 0);     \
+        acc[t][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(AX, w * F2, acc[t][2], 0, 0, 0);     \
+    }
+    // branch-free steps of 8 points: operands past the leaf's end load from a
+    // valid row and are zeroed, so they add nothing
+    DMK_AM_LOAD(ax0, f00, f10, f20, ly0, lz0, L.start)
+    for (int64_t p0 = L.start; p0 < L.end; p0 += 8) {
+        DMK_AM_LOAD(ax1, f01, f11, f21, ly1, lz1, p0 + 4)
+        DMK_AM_STEP(ax0, f00, f10, f20, ly0, lz0)
+        DMK_AM_LOAD(ax0, f00, f10, f20, ly0, lz0, p0 + 8)
+        DMK_AM_STEP(ax1, f01, f11, f21, ly1, lz1)
+    }
+#undef DMK_AM_LOAD
+#undef DMK_AM_STEP
+    // D[row = lk + 4 r][col = li] of tile t: a = 16 mt + lk + 4 r, n = 16 (NN ng + t) + li
+    S* q = Q + (size_t)L.fid * 3 * P * P * P;
+#pragma unroll
+    for (int t = 0; t < NN; ++t) {
+        if (!n_ok[t])
+            continue;
+        const int nn = 16 * (NN * ng + t) + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ar = 16 * mt + lk + 4 * r;
+            if (ar < P)
+#pragma unroll
+                for (int j = 0; j < 3; ++j)
+                    q[((size_t)j * P + ar) * P * P + nn] = (S)acc[t][j][r];
+        }
+    }
+}
+
 // Chebyshev orders with compiled point kernels: the Table tab:params values
 // plus intermediate orders for explicit parameter choices.
 #define DMK_P_DISPATCH(p, MACRO) \
@@ -576,13 +682,13 @@ void launch_anterp(int p, const LeafDesc* leaves, int nleaf, const double* Ltab,
 {
     if (nleaf == 0)
         return;
-#define L_ANTERP(P)                                                                                               \
-    if (f32)                                                                                                      \
-        hipLaunchKernelGGL((k_anterp<P, float>), dim3(nleaf * AnterpCfg<P>::NA * AnterpCfg<P>::NBC),            \
-                           dim3(AnterpCfg<P>::threads), 0, s, leaves, nleaf, Ltab, fs, n, (float*)Q);             \
-    else                                                                                                          \
-        hipLaunchKernelGGL((k_anterp<P, double>), dim3(nleaf * AnterpCfg<P>::NA * AnterpCfg<P>::NBC),           \
-                           dim3(AnterpCfg<P>::threads), 0, s, leaves, nleaf, Ltab, fs, n, (double*)Q)
+#define L_ANTERP(P)                                                                                           \
+    if (f32)                                                                                                  \
+        hipLaunchKernelGGL((k_anterp_mfma<P, float>), dim3(nleaf * AMCfg<P>::TASKS), dim3(64), 0, s, leaves, \
+                           nleaf, Ltab, fs, n, (float*)Q);                                                    \
+    else                                                                                                      \
+        hipLaunchKernelGGL((k_anterp_mfma<P, double>), dim3(nleaf * AMCfg<P>::TASKS), dim3(64), 0, s, leaves, \
+                           nleaf, Ltab, fs, n, (double*)Q)
     DMK_P_DISPATCH(p, L_ANTERP)
 #undef L_ANTERP
 }
