@@ -265,15 +265,16 @@ def main():
         leaf, lanes = tuned["leaf_size"], tuned["near_lanes"]
         print(f"# autotuned: leaf {leaf}, lanes {lanes} ({tuned['ms']:.1f} ms)", file=sys.stderr, flush=True)
 
-    def make_plan(prec):
-        return dmk.Plan(xd, periodic=periodic, tol=tol, leaf_size=leaf, timing=True,
-                        near_lanes=lanes, precision=prec, concurrent=True)
+    def make_plan(prec, window=0, leaf_size=None, near_lanes=None):
+        return dmk.Plan(xd, periodic=periodic, tol=tol, leaf_size=leaf if leaf_size is None else leaf_size,
+                        timing=True, near_lanes=lanes if near_lanes is None else near_lanes, precision=prec,
+                        concurrent=True, window=window)
 
-    def timed_steps(prec):
+    def timed_steps(prec, window=0, leaf_size=None, near_lanes=None):
         """Warmup, K timed plan+eval steps, then K eval-only repetitions on the
         last plan.  Returns the measurements and the last plan (open)."""
         for _ in range(args.warmup):
-            p = make_plan(prec)
+            p = make_plan(prec, window, leaf_size, near_lanes)
             p.eval(fd, out)
             torch.cuda.synchronize()
             p.close()
@@ -282,7 +283,7 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            p = make_plan(prec)
+            p = make_plan(prec, window, leaf_size, near_lanes)
             if prev is not None:
                 ph = prev.phase_ms()
                 phases_acc.append(ph)
@@ -361,7 +362,28 @@ def main():
         u32 = out.cpu().numpy()
         mplan.close()
         print(f"# mixed: {m_step:.2f} ms/step, eval {m_eval:.2f} ms", file=sys.stderr, flush=True)
-        result["variants"] = {"mixed": mixed, "multi_rhs": multi_rhs_variant(args, dev, not args.no_parity),
+        # the same method with the Gaussian (Hasimoto) window and its parameter columns
+        # (its leaf size is swept here: 0.75, 1 and 1.35 times the default)
+        best = None
+        for fac in (0.75, 1.0, 1.35):
+            lf = int(round(1200 * fac)) if args.leaf_size == 0 else args.leaf_size
+            st_ms, ev_ms, g_phases, _, gplan = timed_steps(dmk.PREC_FP64, 1, lf, lanes)
+            ginfo = gplan.info()
+            u_g = out.cpu().numpy()
+            gplan.close()
+            if best is None or st_ms < best[0]:
+                best = (st_ms, ev_ms, g_phases, ginfo, lf, u_g)
+            if args.leaf_size != 0:
+                break
+        gaussian = {"window": "gaussian", "workload": args.config, "precision": "fp64", "leaf_size": best[4],
+                    "q": best[3]["q"], "p": best[3]["p"], "n1": best[3]["n1"], "ms_per_step": best[0],
+                    "eval_only_ms": best[1], "phases_ms": best[2],
+                    "gaussian_over_prolate_step": best[0] / ms_per_step}
+        u_gauss = best[5]
+        print(f"# gaussian window: {best[0]:.2f} ms/step, eval {best[1]:.2f} ms (leaf {best[4]})", file=sys.stderr,
+              flush=True)
+        result["variants"] = {"mixed": mixed, "gaussian_window": gaussian,
+                              "multi_rhs": multi_rhs_variant(args, dev, not args.no_parity),
                               "batched": batched_variant(dev, not args.no_parity)}
 
     if not args.no_parity:
@@ -377,6 +399,7 @@ def main():
         if "variants" in result:
             result["variants"]["mixed"]["rel_l2_sampled"] = oracle.rel_l2(u32[idx], ref)
             result["variants"]["mixed"]["rel_l2_vs_fp64"] = oracle.rel_l2(u32, u64)
+            result["variants"]["gaussian_window"]["rel_l2_sampled"] = oracle.rel_l2(u_gauss[idx], ref)
 
     if not args.no_cpu_baseline and not periodic:
         import oracle

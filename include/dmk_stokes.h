@@ -62,6 +62,12 @@ typedef enum {
  * MIXED needs tol >= 1e-6. */
 typedef enum { DMK_PREC_FP64 = 0, DMK_PREC_MIXED = 1 } dmk_precision;
 
+/* Window of the kernel split (eqs. wfunchat_prol_G / wfunc_prol_G):
+ * PROLATE is the PSWF window of the paper's method (Table tab:params, left
+ * columns); GAUSSIAN is the classical Hasimoto window (right columns,
+ * q = (6/pi) sigma^-2), offered for tol in [1e-6, 1e-3]. */
+typedef enum { DMK_WINDOW_PROLATE = 0, DMK_WINDOW_GAUSSIAN = 1 } dmk_window;
+
 typedef struct {
     int precision;        /* dmk_precision */
     int leaf_size;        /* maximum points per leaf; 0 = the tolerance's default */
@@ -74,12 +80,13 @@ typedef struct {
                              counts n1 = 2q-1, nper = 2 ceil(q/6) - 1); 0 = the
                              Table tab:params row chosen by tol, else in [4, 40] */
     int p;                /* Chebyshev points per dimension of every proxy grid;
-                             0 = the row's value, else 12, 16, 20, 23, 26, 30, 33,
-                             36, 40 or 44 */
+                             0 = the row's value, else 12, 14, 16, 20, 23, 26, 28,
+                             30, 33, 36, 40, 43 or 44 */
     int rhs_batch;        /* force vectors evaluated together by one near-field pass
                              (the pair geometry and radial polynomials are shared):
                              1, 2, 4 or 8; 0 = 8.  Sets the size of the plan's
                              force/velocity work buffers (48 bytes per point each) */
+    int window;           /* dmk_window (0 = prolate) */
 } dmk_opts;
 
 /* record HIP events around each phase of dmk_stokes_eval (read back with
@@ -111,7 +118,7 @@ typedef struct {
 #define DMK_NUM_PHASES 10
 
 typedef struct {
-    /* parameters (Table tab:params, Stokeslet, PSWF columns) */
+    /* parameters (Table tab:params, Stokeslet; q, c = K_max = q pi/3) */
     double tol, c;
     int q, p, n1, nper, leaf_size;
     int deg_P, deg_Q;           /* degrees of the near-field radial polynomials */
@@ -129,6 +136,8 @@ typedef struct {
     double plan_phase_ms[6];
     int near_lanes;             /* source lanes per target of the near-field kernel */
     int precision;              /* dmk_precision of the plan */
+    int window;                 /* dmk_window of the plan */
+    double sigma;               /* Gaussian shape parameter (0 for the prolate window) */
 } dmk_plan_info;
 
 /*
@@ -268,6 +277,8 @@ const char* dmk_last_error(void);
 
 /* Parameters the plan would use for tol (other fields zero). */
 int dmk_stokes_params(double tol, dmk_plan_info* info);
+/* The same for a given window (dmk_window). */
+int dmk_stokes_params_ex(double tol, int window, dmk_plan_info* info);
 
 /*
  * Window and near-field radial functions at unit scale for tol, at n radii:

@@ -19,7 +19,7 @@ STATUS = {0: "DMK_OK", -1: "DMK_ERR_ARG", -2: "DMK_ERR_UNSUPPORTED", -3: "DMK_ER
           -4: "DMK_ERR_NONFINITE", -5: "DMK_ERR_TOL", -6: "DMK_ERR_OOM", -7: "DMK_ERR_HIP"}
 PREC_FP64, PREC_MIXED = 0, 1
 
-SYMBOLS = ["dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_plan_batch", "dmk_stokes_plan_targets", "dmk_stokes_autotune", "dmk_stokes_eval", "dmk_stokes_plan_info",
+SYMBOLS = ["dmk_stokes_params_ex", "dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_plan_batch", "dmk_stokes_plan_targets", "dmk_stokes_autotune", "dmk_stokes_eval", "dmk_stokes_plan_info",
            "dmk_stokes_tree_leaves", "dmk_stokes_destroy", "dmk_last_error", "dmk_stokes_params",
            "dmk_stokes_radial", "dmk_stokes_mollifier", "dmk_stokes_residual_sum", "dmk_stokes_phase_ms",
            "dmk_stokes_near_stats", "dmk_stokes_release_cached_memory", "dmk_stokes_host_tree"]
@@ -39,7 +39,7 @@ class DMKError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("leaf_size", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("mem_cap_bytes", ctypes.c_size_t), ("flags", ctypes.c_int), ("near_lanes", ctypes.c_int),
-                ("q", ctypes.c_int), ("p", ctypes.c_int), ("rhs_batch", ctypes.c_int)]
+                ("q", ctypes.c_int), ("p", ctypes.c_int), ("rhs_batch", ctypes.c_int), ("window", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -52,7 +52,8 @@ class PlanInfo(ctypes.Structure):
                 ("n_senders", ctypes.c_int64), ("n_receivers", ctypes.c_int64),
                 ("center", ctypes.c_double * 3), ("box_len", ctypes.c_double),
                 ("device_bytes", ctypes.c_size_t), ("plan_ms", ctypes.c_double),
-                ("plan_phase_ms", ctypes.c_double * 6), ("near_lanes", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("plan_phase_ms", ctypes.c_double * 6), ("near_lanes", ctypes.c_int), ("precision", ctypes.c_int),
+                ("window", ctypes.c_int), ("sigma", ctypes.c_double)]
 
     def as_dict(self):
         d = {}
@@ -91,6 +92,7 @@ def lib():
         L.dmk_last_error.argtypes = []
         L.dmk_last_error.restype = ctypes.c_char_p
         L.dmk_stokes_params.argtypes = [ctypes.c_double, ctypes.POINTER(PlanInfo)]
+        L.dmk_stokes_params_ex.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.POINTER(PlanInfo)]
         L.dmk_stokes_radial.argtypes = [ctypes.c_double, dp, i64, dp]
         L.dmk_stokes_mollifier.argtypes = [ctypes.c_double, dp, i64, dp]
         L.dmk_stokes_residual_sum.argtypes = [vp, i64, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp]
@@ -116,9 +118,9 @@ def _dp(a):
 
 
 # ---- host-only diagnostics ------------------------------------------------------
-def params(tol: float) -> dict:
+def params(tol: float, window: int = 0) -> dict:
     info = PlanInfo()
-    _check(lib().dmk_stokes_params(float(tol), ctypes.byref(info)))
+    _check(lib().dmk_stokes_params_ex(float(tol), int(window), ctypes.byref(info)))
     return info.as_dict()
 
 
@@ -184,7 +186,7 @@ class Plan:
     def __init__(self, points, periodic: bool = False, tol: float = 1e-6, precision: int = PREC_FP64,
                  leaf_size: int = 0, stream=None, mem_cap_bytes: int = 0, timing: bool = False,
                  near_lanes: int = 0, q: int = 0, p: int = 0, rhs_batch: int = 0, concurrent: bool = False,
-                 offsets=None, graph: bool = False, targets=None):
+                 offsets=None, graph: bool = False, targets=None, window: int = 0):
         """offsets (host int sequence, n_problems + 1 entries) makes a batched
         plan over independent problems (dmk_stokes_plan_batch); targets (device
         (m,3)) makes a plan evaluating the sums at a separate target set
@@ -197,7 +199,7 @@ class Plan:
         opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), int(mem_cap_bytes),
                     (FLAG_PHASE_TIMING if timing else 0) | (FLAG_CONCURRENT_PLAN if concurrent else 0)
                     | (FLAG_GRAPH if graph else 0),
-                    int(near_lanes), int(q), int(p), int(rhs_batch))
+                    int(near_lanes), int(q), int(p), int(rhs_batch), int(window))
         h = ctypes.c_void_p()
         if targets is not None:
             if offsets is not None:
@@ -279,7 +281,7 @@ def autotune(points, periodic: bool = False, tol: float = 1e-6, precision: int =
     Plan for this workload, and the best trial's plan + eval milliseconds."""
     pts = _dev_f64(points)
     n = int(pts.shape[0])
-    opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), 0, 0, 0, 0, 0, 0)
+    opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), 0, 0, 0, 0, 0, 0, 0)
     tuned = Opts()
     ms = ctypes.c_double()
     off = None

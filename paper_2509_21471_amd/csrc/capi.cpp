@@ -309,7 +309,11 @@ int validate_common(int dim, double tol, const dmk_opts* opts)
             opts->rhs_batch != 8)
             return fail(DMK_ERR_ARG, "rhs_batch must be 0, 1, 2, 4 or 8");
         if (opts->p != 0 && !dmk::p_supported(opts->p))
-            return fail(DMK_ERR_ARG, "p must be 0 or one of 12, 16, 20, 23, 26, 30, 33, 36, 40, 44");
+            return fail(DMK_ERR_ARG, "p must be 0 or one of 12, 14, 16, 20, 23, 26, 28, 30, 33, 36, 40, 43, 44");
+        if (opts->window != DMK_WINDOW_PROLATE && opts->window != DMK_WINDOW_GAUSSIAN)
+            return fail(DMK_ERR_ARG, "unknown window");
+        if (opts->window == DMK_WINDOW_GAUSSIAN && tol < 1e-6 * (1 - 1e-9))
+            return fail(DMK_ERR_TOL, "the Gaussian window is offered for tol >= 1e-6");
     }
     return DMK_OK;
 }
@@ -932,15 +936,19 @@ extern "C" {
 
 const char* dmk_last_error(void) { return g_err.c_str(); }
 
-int dmk_stokes_params(double tol, dmk_plan_info* info)
+int dmk_stokes_params(double tol, dmk_plan_info* info) { return dmk_stokes_params_ex(tol, DMK_WINDOW_PROLATE, info); }
+
+int dmk_stokes_params_ex(double tol, int window, dmk_plan_info* info)
 {
     if (!info)
         return fail(DMK_ERR_ARG, "info is NULL");
     std::memset(info, 0, sizeof(*info));
+    if (window != DMK_WINDOW_PROLATE && window != DMK_WINDOW_GAUSSIAN)
+        return fail(DMK_ERR_ARG, "unknown window");
     dmk::Params prm;
-    if (!dmk::select_params(tol, &prm))
-        return fail(DMK_ERR_TOL, "tol must lie in [1e-12, 1e-3]");
-    const dmk::Tables* T = dmk::get_tables(tol);
+    if (!dmk::select_params(tol, &prm, window))
+        return fail(DMK_ERR_TOL, "tol outside the window's range");
+    const dmk::Tables* T = dmk::get_tables(prm);
     info->tol = prm.tol;
     info->c = prm.c;
     info->q = prm.q;
@@ -950,6 +958,8 @@ int dmk_stokes_params(double tol, dmk_plan_info* info)
     info->leaf_size = prm.ns;
     info->deg_P = (int)T->fits.P.a.size() - 1;
     info->deg_Q = (int)T->fits.Q.a.size() - 1;
+    info->window = prm.window;
+    info->sigma = prm.sigma;
     return DMK_OK;
 }
 
@@ -1006,7 +1016,7 @@ int create_plan(const double* points, const std::vector<int64_t>& offsets, int d
     dmk_plan_t P = new (std::nothrow) dmk_plan_s();
     if (!P)
         return fail(DMK_ERR_OOM, "host allocation failed");
-    if (!dmk::select_params(tol, &P->prm)) {
+    if (!dmk::select_params(tol, &P->prm, opts ? opts->window : 0)) {
         delete P;
         return fail(DMK_ERR_TOL, "tol must lie in [1e-12, 1e-3]");
     }
@@ -1356,6 +1366,8 @@ int dmk_stokes_plan_info(dmk_plan_t plan, dmk_plan_info* info)
         info->plan_phase_ms[k] = P.plan_phase[k];
     info->near_lanes = P.near_sg;
     info->precision = P.precision;
+    info->window = P.prm.window;
+    info->sigma = P.prm.sigma;
     return DMK_OK;
 }
 

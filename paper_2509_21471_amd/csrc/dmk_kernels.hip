@@ -641,18 +641,22 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
 }
 
 // Chebyshev orders with compiled point kernels: the Table tab:params values
-// plus intermediate orders for explicit parameter choices.
+// (prolate and Gaussian columns) plus intermediate orders for explicit
+// parameter choices.
 #define DMK_P_DISPATCH(p, MACRO) \
     switch (p) {                 \
     case 12: MACRO(12); break;   \
+    case 14: MACRO(14); break;   \
     case 16: MACRO(16); break;   \
     case 20: MACRO(20); break;   \
     case 23: MACRO(23); break;   \
     case 26: MACRO(26); break;   \
+    case 28: MACRO(28); break;   \
     case 30: MACRO(30); break;   \
     case 33: MACRO(33); break;   \
     case 36: MACRO(36); break;   \
     case 40: MACRO(40); break;   \
+    case 43: MACRO(43); break;   \
     case 44: MACRO(44); break;   \
     default: break;              \
     }
@@ -660,7 +664,8 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
 bool p_supported(int p)
 {
     switch (p) {
-    case 12: case 16: case 20: case 23: case 26: case 30: case 33: case 36: case 40: case 44: return true;
+    case 12: case 14: case 16: case 20: case 23: case 26: case 28: case 30: case 33: case 36: case 40: case 43:
+    case 44: return true;
     default: return false;
     }
 }

@@ -30,41 +30,50 @@ const Row kRows[4] = {
     {1e-9, 25, 33, 49, 9, 2000, 36},
     {1e-12, 31, 44, 61, 11, 3000, 44},
 };
+// The Gaussian columns of the same table: q = (6/pi) sigma^-2, p^G, N_1^G,
+// N_per^G.  Only the rows down to 1e-6 are offered: from 1e-9 on the
+// Gaussian's radial fits need more than the 24 coefficients the near-field
+// kernel holds in scalar registers (and the 1e-12 row, p^G = 58, also exceeds
+// the compiled proxy kernels).  As for the prolate 1e-9 row, p^G = 28 at 1e-6
+// leaves periodic and clustered inputs at or above the tolerance and is
+// stepped up to 30 (q unchanged).
+const Row kRowsG[2] = {
+    {1e-3, 14, 14, 27, 5, 600, 14},
+    {1e-6, 25, 28, 49, 9, 1200, 30},
+};
 }  // namespace
 
-bool select_params(double tol, Params* out)
+bool select_params(double tol, Params* out, int window)
 {
-    if (!(tol >= 1e-12 * (1 - 1e-9) && tol <= 1e-3 * (1 + 1e-9)))
+    const Row* rows = window == 1 ? kRowsG : kRows;
+    const int nrow = window == 1 ? 2 : 4;
+    const double tmin = window == 1 ? 1e-6 : 1e-12;
+    if (!(tol >= tmin * (1 - 1e-9) && tol <= 1e-3 * (1 + 1e-9)))
         return false;
     const double lt = std::log10(tol);
-    int q, p, ns;
     int hit = -1;
-    for (int i = 0; i < 4; ++i)
-        if (std::fabs(lt - std::log10(kRows[i].tol)) < 1e-9)
+    for (int i = 0; i < nrow; ++i)
+        if (std::fabs(lt - std::log10(rows[i].tol)) < 1e-9)
             hit = i;
-    if (hit >= 0) {
-        q = kRows[hit].q;
-        p = kRows[hit].p_used;
-        ns = kRows[hit].ns;
-    } else {
+    if (hit < 0) {
         // between rows: the row with the largest tolerance below tol
-        int i = 0;
-        while (i < 3 && kRows[i].tol > tol)
-            ++i;
-        q = kRows[i].q;
-        p = kRows[i].p_used;
-        ns = kRows[i].ns;
+        hit = 0;
+        while (hit < nrow - 1 && rows[hit].tol > tol)
+            ++hit;
     }
+    const int q = rows[hit].q;
     out->tol = tol;
+    out->window = window;
     out->q = q;
     out->c = q * kPi / 3.0;
-    out->p = p;
+    out->sigma = window == 1 ? std::sqrt(6.0 / (kPi * q)) : 0.0;
+    out->p = rows[hit].p_used;
     // strict truncation |k_i| < K_max / r_{l+1} with h_l = 2 pi/(3 r_l)
     // (Sec. "Error control and parameter selection") gives |m_i| <= q-1
     out->n1 = 2 * q - 1;
-    // periodic root k = 2 pi kappa, |k_i| < c
+    // periodic root k = 2 pi kappa, |k_i| < K_max
     out->nper = 2 * ((q + 5) / 6) - 1;
-    out->ns = ns;
+    out->ns = rows[hit].ns;
     return true;
 }
 
@@ -73,6 +82,7 @@ void override_params(Params* prm, int q, int p)
     if (q > 0) {
         prm->q = q;
         prm->c = q * kPi / 3.0;
+        prm->sigma = prm->window == 1 ? std::sqrt(6.0 / (kPi * q)) : 0.0;
         prm->n1 = 2 * q - 1;
         prm->nper = 2 * ((q + 5) / 6) - 1;
     }
@@ -310,7 +320,21 @@ double ChebFit::eval(double s) const
     return t * b1 - b2 + a[0];
 }
 
-RadialFits fit_radial(const Prolate& w, double fit_tol)
+double GaussWindow::phi(double r) const
+{
+    r = std::fabs(r);
+    return r <= 1.0 ? std::exp(-r * r / (s_ * s_)) / (s_ * std::sqrt(kPi)) : 0.0;
+}
+double GaussWindow::dphi(double r) const
+{
+    return std::fabs(r) <= 1.0 ? -2.0 * r / (s_ * s_) * std::exp(-r * r / (s_ * s_)) / (s_ * std::sqrt(kPi)) : 0.0;
+}
+double GaussWindow::Phi(double r) const { return std::erfc(std::fabs(r) / s_); }
+double GaussWindow::phihat(double k) const { return std::exp(-k * k * s_ * s_ / 4.0); }
+double GaussWindow::dphihat(double k) const { return -0.5 * k * s_ * s_ * phihat(k); }
+double GaussWindow::gammahat(double k) const { return phihat(k) - 0.5 * k * dphihat(k); }
+
+RadialFits fit_radial(const Window& w, double fit_tol)
 {
     // E(s) = int_0^1 phi(rho v) dv,  E - G = -rho int_0^1 v phi'(rho v) dv
     // (integration by parts, no cancellation), Q = (E - G)/s.
@@ -482,7 +506,9 @@ Tables* build_tables(const Params& prm)
     const double tol = prm.tol;
     Tables* T = new Tables();
     T->prm = prm;
-    Prolate w(prm.c);
+    Prolate wp(prm.window == 1 ? 1.0 : prm.c);
+    GaussWindow wg(prm.sigma > 0 ? prm.sigma : 1.0);
+    const Window& w = prm.window == 1 ? (const Window&)wg : (const Window&)wp;
     T->phi0 = w.phi(0.0);
     T->fits = fit_radial(w, 1e-3 * tol);
     const int p = prm.p, q = prm.q;
@@ -558,9 +584,9 @@ Tables* build_tables(const Params& prm)
 const Tables* get_tables(const Params& prm)
 {
     static std::mutex mu;
-    static std::map<std::tuple<double, int, int>, Tables*> cache;
+    static std::map<std::tuple<double, int, int, int>, Tables*> cache;
     std::lock_guard<std::mutex> lk(mu);
-    const auto key = std::make_tuple(prm.tol, prm.q, prm.p);
+    const auto key = std::make_tuple(prm.tol, prm.window, prm.q, prm.p);
     auto it = cache.find(key);
     if (it != cache.end())
         return it->second;

@@ -14,33 +14,65 @@ namespace dmk {
 // leaf size from Sec. "Numerical results").
 struct Params {
     double tol;
-    int q;        // 3c/pi
-    double c;     // PSWF bandlimit
+    int window;   // 0: prolate (PSWF), 1: Gaussian
+    int q;        // 3c/pi (prolate) or (6/pi) sigma^-2 (Gaussian)
+    double c;     // Fourier truncation K_max = q pi / 3 (the PSWF band limit; 2/sigma^2 for the Gaussian)
+    double sigma; // Gaussian shape parameter (0 for the prolate)
     int p;        // Chebyshev points per dimension on every proxy grid
     int n1;       // plane-wave modes per dimension, 2q - 1
     int nper;     // periodic root modes per dimension, 2 ceil(q/6) - 1
     int ns;       // maximum points per leaf
 };
 
-// Returns false if tol is outside [1e-12, 1e-3].
-bool select_params(double tol, Params* out);
+// Returns false if tol is outside [1e-12, 1e-3] (Gaussian window: [1e-6, 1e-3]).
+bool select_params(double tol, Params* out, int window = 0);
 // Replaces q (and with it c, n1, nper) and/or p when the value is > 0.
 void override_params(Params* prm, int q, int p);
 
 // Zeroth-order prolate spheroidal wave function psi_0^c as an even Legendre
 // series (Legendre-Galerkin form of the prolate differential operator,
 // smallest eigenvalue; sign psi(0) > 0) and the window phi = psi / int psi.
-class Prolate {
+// The window function of the split and the quantities the tables need
+// (eqs. wfunchat_prol_G / wfunc_prol_G, def_erfc_like_fcn, gammaB_in_phi).
+class Window {
+  public:
+    virtual ~Window() = default;
+    virtual double phi(double r) const = 0;       // |r| <= 1, else 0
+    virtual double dphi(double r) const = 0;
+    virtual double Phi(double r) const = 0;       // 1 - 2 int_0^r phi
+    virtual double phihat(double k) const = 0;
+    virtual double dphihat(double k) const = 0;
+    virtual double gammahat(double k) const = 0;  // phihat - k phihat'/2
+};
+
+// Gaussian window phi(r) = exp(-r^2/sigma^2) / (sigma sqrt(pi)), truncated at
+// r = 1; phihat(k) = exp(-k^2 sigma^2/4), Phi = erfc(r/sigma) (the Hasimoto
+// split, eq. hasimoto-split).
+class GaussWindow : public Window {
+  public:
+    explicit GaussWindow(double sigma) : s_(sigma) {}
+    double phi(double r) const override;
+    double dphi(double r) const override;
+    double Phi(double r) const override;
+    double phihat(double k) const override;
+    double dphihat(double k) const override;
+    double gammahat(double k) const override;
+
+  private:
+    double s_;
+};
+
+class Prolate : public Window {
   public:
     explicit Prolate(double c);
     double c() const { return c_; }
-    double phi(double r) const;       // |r| <= 1, else 0
-    double dphi(double r) const;
-    double int_phi(double r) const;   // int_0^r phi, r in [0,1]
-    double Phi(double r) const;       // 2 int_r^inf phi = 1 - 2 int_0^r phi
-    double phihat(double k) const;    // int phi(t) e^{-ikt} dt
-    double dphihat(double k) const;
-    double gammahat(double k) const;  // phihat - k phihat'/2
+    double phi(double r) const override;       // |r| <= 1, else 0
+    double dphi(double r) const override;
+    double int_phi(double r) const;            // int_0^r phi, r in [0,1]
+    double Phi(double r) const override;       // 2 int_r^inf phi = 1 - 2 int_0^r phi
+    double phihat(double k) const override;    // int phi(t) e^{-ikt} dt
+    double dphihat(double k) const override;
+    double gammahat(double k) const override;  // phihat - k phihat'/2
     double chi() const { return chi_; }
 
   private:
@@ -64,7 +96,7 @@ struct RadialFits {
     ChebFit P, Q;
     double max_err_P, max_err_Q;
 };
-RadialFits fit_radial(const Prolate& w, double fit_tol);
+RadialFits fit_radial(const Window& w, double fit_tol);
 
 // Gauss-Legendre nodes and weights on [-1,1].
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
@@ -119,7 +151,7 @@ struct Tables {
 
 // Builds (and caches per tolerance) the tables.  Returns nullptr on bad tol.
 const Tables* get_tables(double tol);
-// Tables for explicit parameters (cached per (tol, q, p)).
+// Tables for explicit parameters (cached per (tol, window, q, p)).
 const Tables* get_tables(const Params& prm);
 
 }  // namespace dmk

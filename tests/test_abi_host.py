@@ -89,16 +89,20 @@ def test_plan_argument_validation_without_gpu():
     assert lib.dmk_stokes_plan(vp, 10, 3, 0, 1e-2, ctypes.byref(out)) == -5        # tol out of range
     assert lib.dmk_stokes_plan(vp, 10, 3, 0, 1e-13, ctypes.byref(out)) == -5
     assert lib.dmk_stokes_plan(vp, 10, 3, 2, 1e-6, ctypes.byref(out)) == -1        # periodic flag
-    opts = dmk._lib.Opts(1, 0, None, 0, 0, 0, 0, 0, 0)
+    opts = dmk._lib.Opts(1, 0, None, 0, 0, 0, 0, 0, 0, 0)
     assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-9, ctypes.byref(opts), ctypes.byref(out)) == -5  # mixed < 1e-6
     assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 5e-7, ctypes.byref(opts), ctypes.byref(out)) == -5
-    bad_p = dmk._lib.Opts(0, 0, None, 0, 0, 0, 0, 35, 0)
+    bad_p = dmk._lib.Opts(0, 0, None, 0, 0, 0, 0, 35, 0, 0)
     assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-6, ctypes.byref(bad_p), ctypes.byref(out)) == -1  # p not compiled
-    bad_q = dmk._lib.Opts(0, 0, None, 0, 0, 0, 41, 0, 0)
+    bad_q = dmk._lib.Opts(0, 0, None, 0, 0, 0, 41, 0, 0, 0)
     assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-6, ctypes.byref(bad_q), ctypes.byref(out)) == -1  # q too large
-    bad_lanes = dmk._lib.Opts(0, 0, None, 0, 0, 3, 0, 0, 0)
+    bad_lanes = dmk._lib.Opts(0, 0, None, 0, 0, 3, 0, 0, 0, 0)
     assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-6, ctypes.byref(bad_lanes), ctypes.byref(out)) == -1
-    bad_batch = dmk._lib.Opts(0, 0, None, 0, 0, 0, 0, 0, 3)
+    bad_win = dmk._lib.Opts(0, 0, None, 0, 0, 0, 0, 0, 0, 2)
+    assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-6, ctypes.byref(bad_win), ctypes.byref(out)) == -1
+    gauss = dmk._lib.Opts(0, 0, None, 0, 0, 0, 0, 0, 0, 1)
+    assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-9, ctypes.byref(gauss), ctypes.byref(out)) == -5
+    bad_batch = dmk._lib.Opts(0, 0, None, 0, 0, 0, 0, 0, 3, 0)
     assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-6, ctypes.byref(bad_batch), ctypes.byref(out)) == -1
     assert lib.dmk_stokes_plan(vp, 10, 3, 0, 1e-6, None) == -1                     # NULL out
     assert lib.dmk_stokes_plan(vp, 10, 3, 0, 1e-6, ctypes.byref(out)) == -1        # host pointer
@@ -143,3 +147,14 @@ def test_plan_batch_argument_validation():
     assert lib.dmk_stokes_plan_batch(vp, good, 2, 3, 0, 1e-2, None, ctypes.byref(out)) == -5
     assert lib.dmk_stokes_plan_batch(vp, good, 2, 3, 0, 1e-6, None, ctypes.byref(out)) == -1  # host pointer
     assert out.value is None
+
+
+@pytest.mark.parametrize("tol,qg,pg,n1,nper", [(1e-3, 14, 14, 27, 5), (1e-6, 25, 28, 49, 9)])
+def test_gaussian_parameters_follow_table(tol, qg, pg, n1, nper):
+    # Table tab:params, Stokeslet, Gaussian columns: (6/pi) sigma^-2, p^G, N_1^G, N_per^G
+    prm = _dmk().params(tol, window=1)
+    pg_used = 30 if tol == 1e-6 else pg   # the 1e-6 row runs with p = 30 (stepped up from 28)
+    assert (prm["q"], prm["p"], prm["n1"], prm["nper"], prm["window"]) == (qg, pg_used, n1, nper, 1)
+    assert abs(prm["sigma"] - np.sqrt(6.0 / (np.pi * qg))) < 1e-15
+    with pytest.raises(_dmk().DMKError):
+        _dmk().params(1e-9, window=1)

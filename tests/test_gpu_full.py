@@ -350,3 +350,21 @@ def test_sphere_1e6_targets(dev, tol):
     print("sphere", tol, info["levels"], err)
     assert info["levels"] >= 6
     assert err < tol
+
+
+@pytest.mark.parametrize("tol,periodic", [(1e-3, False), (1e-6, False), (1e-6, True)])
+def test_gaussian_window(dev, tol, periodic):
+    """The same DMK with the Gaussian (Hasimoto) window and the Gaussian
+    columns of the parameter table, against the direct / Ewald sum."""
+    kind = "periodic" if periodic else "clusters"
+    x, f = workloads.make(kind, 20000, seed=101, sigma=0.05)
+    u, info = _eval(x, f, tol=tol, periodic=periodic, leaf_size=200, window=1)
+    assert info["window"] == 1 and info["n1"] in (27, 49)
+    if periodic:
+        from oracle.ewald import ewald
+        idx = np.arange(0, x.shape[0], 40)
+        err = oracle.rel_l2(u[idx], ewald(x, f, idx))
+    else:
+        err = oracle.rel_l2(u, oracle.direct(x, f))
+    print("gaussian", tol, periodic, err)
+    assert err < tol
