@@ -9,8 +9,8 @@ evaluation of the kernel-splitting functions used to pin the method's pieces.
 
 Modules
 -------
-direct.c     compiled to ``liboracle.so`` (OpenMP): direct free-space sum and
-             the real-space half of the Gaussian Ewald sum.
+direct.c     compiled to ``liboracle.so`` (OpenMP): direct free-space Stokeslet
+             and stresslet sums and the real-space half of the Gaussian Ewald sum.
 ewald.py     periodic sum: Fourier half (structure factor by numpy matmul),
              self term, real half via the C routine.
 splitting.py PSWF window (scipy's prolate angular function), phi, Phi, the
@@ -55,6 +55,8 @@ def lib():
         L.oracle_stokeslet_ewald_real.argtypes = [dp, dp, ctypes.c_int64, ip, ctypes.c_int64,
                                                   ctypes.c_double, ctypes.c_double, dp]
         L.oracle_stokeslet_ewald_real.restype = ctypes.c_int
+        L.oracle_stresslet_direct.argtypes = [dp, dp, dp, ctypes.c_int64, ip, ctypes.c_int64, dp]
+        L.oracle_stresslet_direct.restype = None
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -102,3 +104,16 @@ def rel_l2(u, ref):
     u = np.asarray(u, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     return float(np.linalg.norm((u - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+
+def stresslet_direct(x, f, nv, targets=None):
+    """Free-space stresslet sum u_b = sum_{a != b} T(x_b - x_a) : (f_a n_a) at
+    the listed target indices (all points if None).  Returns (m,3)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    nv = np.ascontiguousarray(nv, dtype=np.float64)
+    n = x.shape[0]
+    t = np.arange(n, dtype=np.int64) if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
+    u = np.zeros((t.size, 3))
+    lib().oracle_stresslet_direct(_dp(x), _dp(f), _dp(nv), n, _ip(t), t.size, _dp(u))
+    return u

@@ -25,6 +25,11 @@
  *                             The Fourier half and the self term live in
  *                             ewald.py.
  *
+ *   oracle_stresslet_direct   free-space stresslet sum (eq. stokes_stress_sum
+ *                             with the 3D stresslet of eq. stresslet_def_deriv):
+ *                               u_j(x_b) = sum_{a != b} T_jlm(x_b - x_a) f_{a,l} n_{a,m},
+ *                               T_jlm(y) = -(3/4pi) y_j y_l y_m / r^5.
+ *
  * Conventions: points and forces are row-major (n,3) arrays; targets are a
  * list of source indices (the target is also a source, and the pair a == b is
  * skipped).  A pair of distinct but coincident points (r == 0) contributes
@@ -84,6 +89,36 @@ void oracle_stokeslet_direct(const double *x, const double *f, int64_t n,
  * rc (every other image is at least 1/2 away in some coordinate).  The pair
  * (a == b, image 0) is skipped.
  */
+void oracle_stresslet_direct(const double *x, const double *f, const double *nv, int64_t n,
+                             const int64_t *tgt, int64_t m, double *u)
+{
+    const double c = -3.0 / (4.0 * M_PI);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < m; ++t) {
+        const int64_t b = tgt[t];
+        const double xb0 = x[3 * b], xb1 = x[3 * b + 1], xb2 = x[3 * b + 2];
+        double s0 = 0, s1 = 0, s2 = 0, c0 = 0, c1 = 0, c2 = 0;
+        for (int64_t a = 0; a < n; ++a) {
+            if (a == b)
+                continue;
+            const double y0 = xb0 - x[3 * a], y1 = xb1 - x[3 * a + 1], y2 = xb2 - x[3 * a + 2];
+            const double r2 = y0 * y0 + y1 * y1 + y2 * y2;
+            if (r2 == 0.0)
+                continue;
+            const double r = sqrt(r2);
+            const double yf = y0 * f[3 * a] + y1 * f[3 * a + 1] + y2 * f[3 * a + 2];
+            const double yn = y0 * nv[3 * a] + y1 * nv[3 * a + 1] + y2 * nv[3 * a + 2];
+            const double w = c * yf * yn / (r2 * r2 * r);
+            neumaier_add(&s0, &c0, w * y0);
+            neumaier_add(&s1, &c1, w * y1);
+            neumaier_add(&s2, &c2, w * y2);
+        }
+        u[3 * t] = s0 + c0;
+        u[3 * t + 1] = s1 + c1;
+        u[3 * t + 2] = s2 + c2;
+    }
+}
+
 int oracle_stokeslet_ewald_real(const double *x, const double *f, int64_t n,
                                 const int64_t *tgt, int64_t m, double xi, double rc,
                                 double *u)

@@ -88,6 +88,16 @@ class Window:
         rho = np.asarray(rho, dtype=np.float64)
         return self.Phi(rho) + 2.0 * rho * self.phi(rho)
 
+    def Tdiag(self, rho):
+        """R_Tdiag of eq. T-offd."""
+        rho = np.asarray(rho, dtype=np.float64)
+        return -2.0 * rho ** 2 * self.dphi(rho)
+
+    def Toffd(self, rho):
+        """R_Toffd of eq. T-offd."""
+        rho = np.asarray(rho, dtype=np.float64)
+        return self.Phi(rho) + 2.0 * rho * self.phi(rho) - (2.0 / 3.0) * rho ** 2 * self.dphi(rho)
+
 
 def _cheb_lobatto(N):
     """Chebyshev-Lobatto points x_j = cos(j pi/N) and the spectral
@@ -205,6 +215,44 @@ def residual_stokeslet(win: Window, y, nu: float = 1.0):
     I = np.eye(3)
     return (sd[:, None, None] * I[None] / r[:, None, None]
             + so[:, None, None] * y[:, :, None] * y[:, None, :] / r[:, None, None] ** 3) / (8 * np.pi)
+
+
+def stresslet(y):
+    """Free-space stresslet tensors T(y) (eq. stresslet_def_deriv), (m,3) -> (m,3,3,3)."""
+    y = np.asarray(y, dtype=np.float64)
+    r = np.linalg.norm(y, axis=-1)
+    return -3.0 / (4 * np.pi) * np.einsum("ai,aj,ak->aijk", y, y, y) / r[:, None, None, None] ** 5
+
+
+def residual_stresslet(win: Window, y, nu: float = 1.0):
+    """T_R at length scale nu (eq. res_stresslet with R_Tdiag, R_Toffd of eq.
+    T-offd evaluated at r/nu), (m,3) -> (m,3,3,3)."""
+    y = np.asarray(y, dtype=np.float64)
+    r = np.linalg.norm(y, axis=-1)
+    rho = r / nu
+    td = win.Tdiag(rho)
+    to = win.Toffd(rho)
+    I = np.eye(3)
+    sym = (np.einsum("jl,am->ajlm", I, y) + np.einsum("lm,aj->ajlm", I, y) + np.einsum("mj,al->ajlm", I, y))
+    return (td[:, None, None, None] * sym / (8 * np.pi * r[:, None, None, None] ** 3)
+            - 3.0 / (4 * np.pi) * to[:, None, None, None] * np.einsum("ai,aj,ak->aijk", y, y, y)
+            / r[:, None, None, None] ** 5)
+
+
+def residual_stresslet_pair_sum(win: Window, xt, xs, fs, ns, nu):
+    """Brute-force sum_a T_R^nu(x_t - x_a) : (f_a n_a) over all sources
+    (pairs with r = 0 or r >= nu contribute nothing)."""
+    xt = np.asarray(xt, dtype=np.float64)
+    out = np.zeros((xt.shape[0], 3))
+    for t in range(xt.shape[0]):
+        y = xt[t][None, :] - xs
+        r = np.linalg.norm(y, axis=1)
+        keep = (r > 0) & (r < nu)
+        if not np.any(keep):
+            continue
+        T = residual_stresslet(win, y[keep], nu)
+        out[t] = np.einsum("ajlm,al,am->j", T, fs[keep], ns[keep])
+    return out
 
 
 def Btrunc_hat(k, R):
