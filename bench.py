@@ -265,17 +265,25 @@ def main():
         leaf, lanes = tuned["leaf_size"], tuned["near_lanes"]
         print(f"# autotuned: leaf {leaf}, lanes {lanes} ({tuned['ms']:.1f} ms)", file=sys.stderr, flush=True)
 
-    def make_plan(prec, window=0, leaf_size=None, near_lanes=None):
+    nvd = None  # stresslet orientation vectors, made when the stresslet variant runs
+
+    def make_plan(prec, window=0, leaf_size=None, near_lanes=None, kernel=0):
         return dmk.Plan(xd, periodic=periodic, tol=tol, leaf_size=leaf if leaf_size is None else leaf_size,
                         timing=True, near_lanes=lanes if near_lanes is None else near_lanes, precision=prec,
-                        concurrent=True, window=window)
+                        concurrent=True, window=window, kernel=kernel)
 
-    def timed_steps(prec, window=0, leaf_size=None, near_lanes=None):
+    def run(p, kernel):
+        if kernel == dmk.KERNEL_STRESSLET:
+            p.eval_stresslet(fd, nvd, out)
+        else:
+            p.eval(fd, out)
+
+    def timed_steps(prec, window=0, leaf_size=None, near_lanes=None, kernel=0):
         """Warmup, K timed plan+eval steps, then K eval-only repetitions on the
         last plan.  Returns the measurements and the last plan (open)."""
         for _ in range(args.warmup):
-            p = make_plan(prec, window, leaf_size, near_lanes)
-            p.eval(fd, out)
+            p = make_plan(prec, window, leaf_size, near_lanes, kernel)
+            run(p, kernel)
             torch.cuda.synchronize()
             p.close()
         near_ms, phases_acc = [], []
@@ -283,13 +291,13 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            p = make_plan(prec, window, leaf_size, near_lanes)
+            p = make_plan(prec, window, leaf_size, near_lanes, kernel)
             if prev is not None:
                 ph = prev.phase_ms()
                 phases_acc.append(ph)
                 near_ms.append(ph["near"])
                 prev.close()
-            p.eval(fd, out)
+            run(p, kernel)
             prev = p
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -298,11 +306,11 @@ def main():
         near_ms.append(ph["near"])
         ms_step = (t1 - t0) * 1e3 / args.steps
         for _ in range(2):
-            prev.eval(fd, out)
+            run(prev, kernel)
         torch.cuda.synchronize()
         te0 = time.perf_counter()
         for _ in range(args.steps):
-            prev.eval(fd, out)
+            run(prev, kernel)
         torch.cuda.synchronize()
         ms_eval = (time.perf_counter() - te0) * 1e3 / args.steps
         phases = {k: float(np.mean([a[k] for a in phases_acc])) for k in phases_acc[0]}
@@ -382,9 +390,34 @@ def main():
         u_gauss = best[5]
         print(f"# gaussian window: {best[0]:.2f} ms/step, eval {best[1]:.2f} ms (leaf {best[4]})", file=sys.stderr,
               flush=True)
+        # the stresslet (double-layer) sum on the same points, f the same forces
+        # and n seeded unit vectors; its leaf size swept over 1, 1.35 and 1.8
+        # times the Stokeslet's (its far field carries 6 density components)
+        stress = None
+        if not periodic:
+            nv = workloads.normals(x, cfg["seed"], "sphere" if cfg["kind"] == "sphere" else "random")
+            nvd = torch.from_numpy(nv).to(dev)
+            best = None
+            for fac in (1.0, 1.35, 1.8):
+                lf = int(round(leaf * fac)) if leaf else int(round(1200 * fac))
+                st_ms, ev_ms, s_phases, _, splan = timed_steps(dmk.PREC_FP64, 0, lf, lanes, dmk.KERNEL_STRESSLET)
+                sinfo = splan.info()
+                u_s = out.cpu().numpy()
+                splan.close()
+                if best is None or st_ms < best[0]:
+                    best = (st_ms, ev_ms, s_phases, sinfo, lf, u_s)
+            stress = {"kernel": "stresslet", "workload": args.config, "precision": "fp64", "leaf_size": best[4],
+                      "q": best[3]["q"], "p": best[3]["p"], "ms_per_step": best[0],
+                      "targets_per_s": n / (best[0] * 1e-3), "eval_only_ms": best[1], "phases_ms": best[2],
+                      "stresslet_over_stokeslet_step": best[0] / ms_per_step}
+            u_stress = best[5]
+            print(f"# stresslet: {best[0]:.2f} ms/step, eval {best[1]:.2f} ms (leaf {best[4]})", file=sys.stderr,
+                  flush=True)
         result["variants"] = {"mixed": mixed, "gaussian_window": gaussian,
                               "multi_rhs": multi_rhs_variant(args, dev, not args.no_parity),
                               "batched": batched_variant(dev, not args.no_parity)}
+        if stress is not None:
+            result["variants"]["stresslet"] = stress
 
     if not args.no_parity:
         import oracle
@@ -400,6 +433,9 @@ def main():
             result["variants"]["mixed"]["rel_l2_sampled"] = oracle.rel_l2(u32[idx], ref)
             result["variants"]["mixed"]["rel_l2_vs_fp64"] = oracle.rel_l2(u32, u64)
             result["variants"]["gaussian_window"]["rel_l2_sampled"] = oracle.rel_l2(u_gauss[idx], ref)
+            if "stresslet" in result["variants"]:
+                ref_s = oracle.stresslet_direct(x, f, nv, idx)
+                result["variants"]["stresslet"]["rel_l2_sampled"] = oracle.rel_l2(u_stress[idx], ref_s)
 
     if not args.no_cpu_baseline and not periodic:
         import oracle

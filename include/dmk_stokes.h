@@ -68,6 +68,17 @@ typedef enum { DMK_PREC_FP64 = 0, DMK_PREC_MIXED = 1 } dmk_precision;
  * q = (6/pi) sigma^-2), offered for tol in [1e-6, 1e-3]. */
 typedef enum { DMK_WINDOW_PROLATE = 0, DMK_WINDOW_GAUSSIAN = 1 } dmk_window;
 
+/* Kernel of a plan.  STOKESLET: the sums above.  STRESSLET: the double-layer
+ * sums of eq. stokes_stress_sum with the stresslet of eq. stresslet_def_deriv,
+ *   u_j(x_b) = sum_{a != b} T_jlm(x_b - x_a) f_{a,l} n_{a,m},
+ *   T_jlm(y) = -(3/4pi) y_j y_l y_m / |y|^5,
+ * split by the same PSWF mollifier (residual eq. res_stresslet with the
+ * functions of eq. T-offd; Fourier side eq. moll_stresslet) with the stresslet
+ * columns of Table tab:params (p stepped up one compiled order per row: 12,
+ * 23, 36, 48).  Offered in free space with the prolate window;
+ * evaluated with dmk_stokes_eval_stresslet. */
+typedef enum { DMK_KERNEL_STOKESLET = 0, DMK_KERNEL_STRESSLET = 1 } dmk_kernel;
+
 typedef struct {
     int precision;        /* dmk_precision */
     int leaf_size;        /* maximum points per leaf; 0 = the tolerance's default */
@@ -80,13 +91,14 @@ typedef struct {
                              counts n1 = 2q-1, nper = 2 ceil(q/6) - 1); 0 = the
                              Table tab:params row chosen by tol, else in [4, 40] */
     int p;                /* Chebyshev points per dimension of every proxy grid;
-                             0 = the row's value, else 12, 14, 16, 20, 23, 26, 28,
-                             30, 33, 36, 40, 43 or 44 */
+                             0 = the row's value, else 11, 12, 14, 16, 20, 22, 23,
+                             26, 28, 30, 33, 36, 40, 43, 44 or 48 */
     int rhs_batch;        /* force vectors evaluated together by one near-field pass
                              (the pair geometry and radial polynomials are shared):
                              1, 2, 4 or 8; 0 = 8.  Sets the size of the plan's
                              force/velocity work buffers (48 bytes per point each) */
     int window;           /* dmk_window (0 = prolate) */
+    int kernel;           /* dmk_kernel (0 = Stokeslet) */
 } dmk_opts;
 
 /* record HIP events around each phase of dmk_stokes_eval (read back with
@@ -138,6 +150,7 @@ typedef struct {
     int precision;              /* dmk_precision of the plan */
     int window;                 /* dmk_window of the plan */
     double sigma;               /* Gaussian shape parameter (0 for the prolate window) */
+    int kernel;                 /* dmk_kernel of the plan */
 } dmk_plan_info;
 
 /*
@@ -206,6 +219,23 @@ int dmk_stokes_plan_batch(const double* points, const int64_t* offsets, int n_pr
  * the plan's work buffers).
  */
 int dmk_stokes_eval(dmk_plan_t plan, const double* forces, int n_rhs, double* velocities);
+
+/*
+ * Evaluates the stresslet sums (dmk_kernel STRESSLET) for n_rhs pairs of
+ * vectors on a plan built with dmk_opts.kernel = DMK_KERNEL_STRESSLET:
+ *   u_j(x_b) = sum_{a != b} T_jlm(x_b - x_a) f_{a,l} n_{a,m}
+ *   forces, normals  device, (n_rhs, n_sources, 3) float64 each, caller's order
+ *                    (n_sources = n for a plan without separate targets)
+ *   velocities       device, (n_rhs, n_targets, 3) float64, overwritten
+ * The far field carries the 6 components of the symmetric part of f n^T
+ * through the proxy and plane-wave passes; the difference-kernel symbol of eq.
+ * moll_stresslet contracts them to 3 velocity components before the
+ * translation.  Vectors run one after the other.  A pair of distinct but
+ * coincident points contributes nothing; there is no self term.  Returns
+ * DMK_ERR_ARG for a Stokeslet plan.  Stream-ordered, like dmk_stokes_eval.
+ */
+int dmk_stokes_eval_stresslet(dmk_plan_t plan, const double* forces, const double* normals, int n_rhs,
+                              double* velocities);
 
 /*
  * Autotuner: picks the leaf size (maximum points per leaf) and the near-field
@@ -279,6 +309,9 @@ const char* dmk_last_error(void);
 int dmk_stokes_params(double tol, dmk_plan_info* info);
 /* The same for a given window (dmk_window). */
 int dmk_stokes_params_ex(double tol, int window, dmk_plan_info* info);
+/* The same for a given window and kernel (dmk_kernel); for the stresslet,
+ * deg_P and deg_Q are the degrees of its radial functions A and D. */
+int dmk_stokes_params_kernel(double tol, int window, int kernel, dmk_plan_info* info);
 
 /*
  * Window and near-field radial functions at unit scale for tol, at n radii:
@@ -289,6 +322,16 @@ int dmk_stokes_params_ex(double tol, int window, dmk_plan_info* info);
  *     (eq. res_stokeslet/Soffdiag rearranged).
  */
 int dmk_stokes_radial(double tol, const double* rho, int64_t n, double* out);
+
+/*
+ * Near-field radial functions of the residual stresslet at unit scale for tol
+ * (stresslet row of Table tab:params), at n radii: out[2i] = A(rho^2),
+ * out[2i+1] = D(rho^2), the polynomial fits with
+ *   T_R(y) : (f n^T) = T(y) : (f n^T) + (3/2pi) A(s) (y.f)(y.n) y
+ *                      + (1/4pi) D(s) [(y.n) f + (y.f) n + (f.n) y],  s = |y|^2 < 1,
+ * i.e. A = (1 - R_Toffd(rho)) / (2 rho^5), D = R_Tdiag(rho) / (2 rho^3) (eq. T-offd).
+ */
+int dmk_stokes_radial_stresslet(double tol, const double* rho, int64_t n, double* out);
 
 /* Window transform and biharmonic mollifier (eq. gammaB_in_phi) at n wave
  * numbers: out[2i] = phihat(k), out[2i+1] = gammahat(k). */
@@ -321,6 +364,17 @@ int dmk_stokes_host_tree(const double* points, int64_t n, int leaf_size, int per
  */
 int dmk_stokes_residual_sum(const double* targets, int64_t m, const double* sources, const double* forces,
                             int64_t ns, double r_lambda, double tol, void* stream, double* out);
+
+/*
+ * The same for the residual stresslet (eq. res_stresslet with eq. T-offd, at
+ * scale r_lambda), with the near-field pair routine of the stresslet plans:
+ *   out[i] = sum_a T_R^{r_lambda}(t_i - s_a) : (f_a n_a^T);
+ * pairs with r = 0 contribute nothing.  normals (ns,3) device float64; other
+ * arguments as dmk_stokes_residual_sum.
+ */
+int dmk_stokes_residual_sum_stresslet(const double* targets, int64_t m, const double* sources, const double* forces,
+                                      const double* normals, int64_t ns, double r_lambda, double tol, void* stream,
+                                      double* out);
 
 #ifdef __cplusplus
 }

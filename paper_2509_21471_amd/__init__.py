@@ -3,8 +3,10 @@
 The computation lives in libdmk_stokes.so (hand-written HIP kernels behind a C
 ABI, include/dmk_stokes.h); this package only marshals arguments.
 """
-from ._lib import (PREC_FP64, PREC_MIXED, DMKError, Plan, SYMBOLS, autotune, host_tree, lib, mollifier, params,
-                   radial, residual_sum)
+from ._lib import (KERNEL_STOKESLET, KERNEL_STRESSLET, PREC_FP64, PREC_MIXED, DMKError, Plan, SYMBOLS, autotune,
+                   host_tree, lib, mollifier, params, radial, radial_stresslet, residual_sum,
+                   residual_sum_stresslet)
 
-__all__ = ["Plan", "DMKError", "PREC_FP64", "PREC_MIXED", "params", "radial", "mollifier", "residual_sum",
-           "lib", "SYMBOLS", "host_tree", "autotune"]
+__all__ = ["Plan", "DMKError", "PREC_FP64", "PREC_MIXED", "KERNEL_STOKESLET", "KERNEL_STRESSLET", "params",
+           "radial", "radial_stresslet", "mollifier", "residual_sum", "residual_sum_stresslet", "lib", "SYMBOLS", "host_tree",
+           "autotune"]

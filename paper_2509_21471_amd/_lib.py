@@ -18,8 +18,10 @@ DMK_OK = 0
 STATUS = {0: "DMK_OK", -1: "DMK_ERR_ARG", -2: "DMK_ERR_UNSUPPORTED", -3: "DMK_ERR_DOMAIN",
           -4: "DMK_ERR_NONFINITE", -5: "DMK_ERR_TOL", -6: "DMK_ERR_OOM", -7: "DMK_ERR_HIP"}
 PREC_FP64, PREC_MIXED = 0, 1
+KERNEL_STOKESLET, KERNEL_STRESSLET = 0, 1
 
-SYMBOLS = ["dmk_stokes_params_ex", "dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_plan_batch", "dmk_stokes_plan_targets", "dmk_stokes_autotune", "dmk_stokes_eval", "dmk_stokes_plan_info",
+SYMBOLS = ["dmk_stokes_radial_stresslet", "dmk_stokes_params_ex", "dmk_stokes_params_kernel", "dmk_stokes_eval_stresslet",
+           "dmk_stokes_residual_sum_stresslet", "dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_plan_batch", "dmk_stokes_plan_targets", "dmk_stokes_autotune", "dmk_stokes_eval", "dmk_stokes_plan_info",
            "dmk_stokes_tree_leaves", "dmk_stokes_destroy", "dmk_last_error", "dmk_stokes_params",
            "dmk_stokes_radial", "dmk_stokes_mollifier", "dmk_stokes_residual_sum", "dmk_stokes_phase_ms",
            "dmk_stokes_near_stats", "dmk_stokes_release_cached_memory", "dmk_stokes_host_tree"]
@@ -39,7 +41,8 @@ class DMKError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("leaf_size", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("mem_cap_bytes", ctypes.c_size_t), ("flags", ctypes.c_int), ("near_lanes", ctypes.c_int),
-                ("q", ctypes.c_int), ("p", ctypes.c_int), ("rhs_batch", ctypes.c_int), ("window", ctypes.c_int)]
+                ("q", ctypes.c_int), ("p", ctypes.c_int), ("rhs_batch", ctypes.c_int), ("window", ctypes.c_int),
+                ("kernel", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -53,7 +56,7 @@ class PlanInfo(ctypes.Structure):
                 ("center", ctypes.c_double * 3), ("box_len", ctypes.c_double),
                 ("device_bytes", ctypes.c_size_t), ("plan_ms", ctypes.c_double),
                 ("plan_phase_ms", ctypes.c_double * 6), ("near_lanes", ctypes.c_int), ("precision", ctypes.c_int),
-                ("window", ctypes.c_int), ("sigma", ctypes.c_double)]
+                ("window", ctypes.c_int), ("sigma", ctypes.c_double), ("kernel", ctypes.c_int)]
 
     def as_dict(self):
         d = {}
@@ -85,6 +88,7 @@ def lib():
                                           ctypes.POINTER(Opts), ctypes.c_int, ctypes.POINTER(Opts),
                                           ctypes.POINTER(ctypes.c_double)]
         L.dmk_stokes_eval.argtypes = [vp, vp, ctypes.c_int, vp]
+        L.dmk_stokes_eval_stresslet.argtypes = [vp, vp, vp, ctypes.c_int, vp]
         L.dmk_stokes_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
         L.dmk_stokes_tree_leaves.argtypes = [vp, vp, vp, vp, vp]
         L.dmk_stokes_destroy.argtypes = [vp]
@@ -93,9 +97,14 @@ def lib():
         L.dmk_last_error.restype = ctypes.c_char_p
         L.dmk_stokes_params.argtypes = [ctypes.c_double, ctypes.POINTER(PlanInfo)]
         L.dmk_stokes_params_ex.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.POINTER(PlanInfo)]
+        L.dmk_stokes_params_kernel.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                               ctypes.POINTER(PlanInfo)]
         L.dmk_stokes_radial.argtypes = [ctypes.c_double, dp, i64, dp]
         L.dmk_stokes_mollifier.argtypes = [ctypes.c_double, dp, i64, dp]
+        L.dmk_stokes_radial_stresslet.argtypes = [ctypes.c_double, dp, i64, dp]
         L.dmk_stokes_residual_sum.argtypes = [vp, i64, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp]
+        L.dmk_stokes_residual_sum_stresslet.argtypes = [vp, i64, vp, vp, vp, i64, ctypes.c_double,
+                                                        ctypes.c_double, vp, vp]
         L.dmk_stokes_phase_ms.argtypes = [vp, dp]
         L.dmk_stokes_near_stats.argtypes = [vp, vp, vp, vp]
         L.dmk_stokes_host_tree.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, i64, vp, vp, vp, vp, vp]
@@ -118,9 +127,9 @@ def _dp(a):
 
 
 # ---- host-only diagnostics ------------------------------------------------------
-def params(tol: float, window: int = 0) -> dict:
+def params(tol: float, window: int = 0, kernel: int = KERNEL_STOKESLET) -> dict:
     info = PlanInfo()
-    _check(lib().dmk_stokes_params_ex(float(tol), int(window), ctypes.byref(info)))
+    _check(lib().dmk_stokes_params_kernel(float(tol), int(window), int(kernel), ctypes.byref(info)))
     return info.as_dict()
 
 
@@ -128,6 +137,14 @@ def radial(tol: float, rho) -> np.ndarray:
     rho = np.ascontiguousarray(rho, dtype=np.float64).ravel()
     out = np.zeros((rho.size, 4))
     _check(lib().dmk_stokes_radial(float(tol), _dp(rho), rho.size, _dp(out)))
+    return out
+
+
+def radial_stresslet(tol: float, rho) -> np.ndarray:
+    """(A, D) of the residual stresslet's near-field fits at rho^2, shape (n, 2)."""
+    rho = np.ascontiguousarray(rho, dtype=np.float64).ravel()
+    out = np.zeros((rho.size, 2))
+    _check(lib().dmk_stokes_radial_stresslet(float(tol), _dp(rho), rho.size, _dp(out)))
     return out
 
 
@@ -186,11 +203,14 @@ class Plan:
     def __init__(self, points, periodic: bool = False, tol: float = 1e-6, precision: int = PREC_FP64,
                  leaf_size: int = 0, stream=None, mem_cap_bytes: int = 0, timing: bool = False,
                  near_lanes: int = 0, q: int = 0, p: int = 0, rhs_batch: int = 0, concurrent: bool = False,
-                 offsets=None, graph: bool = False, targets=None, window: int = 0):
+                 offsets=None, graph: bool = False, targets=None, window: int = 0,
+                 kernel: int = KERNEL_STOKESLET):
         """offsets (host int sequence, n_problems + 1 entries) makes a batched
         plan over independent problems (dmk_stokes_plan_batch); targets (device
         (m,3)) makes a plan evaluating the sums at a separate target set
-        (dmk_stokes_plan_targets): forces (n_rhs, n, 3) -> velocities (n_rhs, m, 3)."""
+        (dmk_stokes_plan_targets): forces (n_rhs, n, 3) -> velocities (n_rhs, m, 3).
+        kernel = KERNEL_STRESSLET makes a stresslet plan, evaluated with
+        eval_stresslet."""
         torch = _torch()
         pts = _dev_f64(points)
         self.n = int(pts.shape[0])
@@ -199,7 +219,7 @@ class Plan:
         opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), int(mem_cap_bytes),
                     (FLAG_PHASE_TIMING if timing else 0) | (FLAG_CONCURRENT_PLAN if concurrent else 0)
                     | (FLAG_GRAPH if graph else 0),
-                    int(near_lanes), int(q), int(p), int(rhs_batch), int(window))
+                    int(near_lanes), int(q), int(p), int(rhs_batch), int(window), int(kernel))
         h = ctypes.c_void_p()
         if targets is not None:
             if offsets is not None:
@@ -235,6 +255,24 @@ class Plan:
             out = torch.empty(shape, dtype=f.dtype, device=f.device)
         _check(lib().dmk_stokes_eval(self._h, ctypes.c_void_p(f.data_ptr()), n_rhs,
                                      ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def eval_stresslet(self, forces, normals, out=None):
+        """Stresslet sums u_j = sum T_jlm f_l n_m (dmk_stokes_eval_stresslet)."""
+        torch = self._torch
+        f = _dev_f64(forces)
+        nv = _dev_f64(normals)
+        if f.shape != nv.shape:
+            raise ValueError("forces and normals must have the same shape")
+        n_rhs = 1 if f.dim() == 2 else int(f.shape[0])
+        if f.shape[-2] != self.n:
+            raise ValueError("forces must have shape (n,3) or (n_rhs,n,3)")
+        if out is None:
+            shape = (self.n_out, 3) if f.dim() == 2 else (n_rhs, self.n_out, 3)
+            out = torch.empty(shape, dtype=f.dtype, device=f.device)
+        _check(lib().dmk_stokes_eval_stresslet(self._h, ctypes.c_void_p(f.data_ptr()),
+                                               ctypes.c_void_p(nv.data_ptr()), n_rhs,
+                                               ctypes.c_void_p(out.data_ptr())))
         return out
 
     def info(self) -> dict:
@@ -281,7 +319,7 @@ def autotune(points, periodic: bool = False, tol: float = 1e-6, precision: int =
     Plan for this workload, and the best trial's plan + eval milliseconds."""
     pts = _dev_f64(points)
     n = int(pts.shape[0])
-    opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), 0, 0, 0, 0, 0, 0, 0)
+    opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), 0, 0, 0, 0, 0, 0, 0, 0)
     tuned = Opts()
     ms = ctypes.c_double()
     off = None
@@ -306,4 +344,19 @@ def residual_sum(targets, sources, forces, r_lambda: float, tol: float, stream=N
                                          ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(f.data_ptr()),
                                          int(s.shape[0]), float(r_lambda), float(tol), _stream_ptr(stream),
                                          ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def residual_sum_stresslet(targets, sources, forces, normals, r_lambda: float, tol: float, stream=None):
+    torch = _torch()
+    t = _dev_f64(targets)
+    s = _dev_f64(sources)
+    f = _dev_f64(forces)
+    nv = _dev_f64(normals)
+    out = torch.empty_like(t)
+    _check(lib().dmk_stokes_residual_sum_stresslet(ctypes.c_void_p(t.data_ptr()), int(t.shape[0]),
+                                                   ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                                                   ctypes.c_void_p(nv.data_ptr()), int(s.shape[0]),
+                                                   float(r_lambda), float(tol), _stream_ptr(stream),
+                                                   ctypes.c_void_p(out.data_ptr())))
     return out

@@ -247,6 +247,12 @@ struct dmk_plan_s {
     void *Phi = nullptr, *Psi = nullptr;
     void *s1 = nullptr, *s2 = nullptr;
     void *phi_root = nullptr, *psi_root = nullptr;
+    // stresslet plans: 6 density components in (Q, Phi, root Phi), the
+    // sending-side symbol writes 3 velocity components to Phi3
+    int kern = DMK_KERNEL_STOKESLET;
+    int nc_in = 3;
+    void* Phi3 = nullptr;
+    int* send_level = nullptr;        // sender slot -> level
     double* cst = nullptr;
     size_t H = 0, Hroot = 0;
     std::vector<int> leaf_box;        // leaf index (all leaves) -> box id
@@ -309,11 +315,19 @@ int validate_common(int dim, double tol, const dmk_opts* opts)
             opts->rhs_batch != 8)
             return fail(DMK_ERR_ARG, "rhs_batch must be 0, 1, 2, 4 or 8");
         if (opts->p != 0 && !dmk::p_supported(opts->p))
-            return fail(DMK_ERR_ARG, "p must be 0 or one of 12, 14, 16, 20, 23, 26, 28, 30, 33, 36, 40, 43, 44");
+            return fail(DMK_ERR_ARG, "p must be 0 or one of 11, 12, 14, 16, 20, 22, 23, 26, 28, 30, 33, 36, 40, 43, 44, 48");
         if (opts->window != DMK_WINDOW_PROLATE && opts->window != DMK_WINDOW_GAUSSIAN)
             return fail(DMK_ERR_ARG, "unknown window");
         if (opts->window == DMK_WINDOW_GAUSSIAN && tol < 1e-6 * (1 - 1e-9))
             return fail(DMK_ERR_TOL, "the Gaussian window is offered for tol >= 1e-6");
+        if (opts->kernel != DMK_KERNEL_STOKESLET && opts->kernel != DMK_KERNEL_STRESSLET)
+            return fail(DMK_ERR_ARG, "unknown kernel");
+        if (opts->kernel == DMK_KERNEL_STRESSLET) {
+            if (opts->window != DMK_WINDOW_PROLATE)
+                return fail(DMK_ERR_UNSUPPORTED, "the stresslet is offered with the prolate window only");
+            if (opts->flags & DMK_FLAG_GRAPH)
+                return fail(DMK_ERR_UNSUPPORTED, "DMK_FLAG_GRAPH is not available for the stresslet");
+        }
     }
     return DMK_OK;
 }
@@ -321,7 +335,7 @@ int validate_common(int dim, double tol, const dmk_opts* opts)
 // One separable stage over `nslots` (slot, component) tensors.
 void stage(dmk_plan_t P, int mode, int io, const void* X, long xs, const int* xmap, void* Y, long ys,
            const int* ymap, int accumulate, const double* mat, int Nin, int Nout, int in_off, int out_off, int Kh,
-           int Nh, int R, int nslots, const int* child_fid = nullptr)
+           int Nh, int R, int nslots, const int* child_fid = nullptr, int nc = 3)
 {
     dmk::StageArgs a;
     a.X = X;
@@ -343,6 +357,7 @@ void stage(dmk_plan_t P, int mode, int io, const void* X, long xs, const int* xm
     a.p = P->prm.p;
     a.child_fid = child_fid;
     a.f32 = P->f32 ? 1 : 0;
+    a.ncomp = nc;
     dmk::launch_stage(mode, io, a, P->stream);
 }
 
@@ -617,7 +632,7 @@ int build_plan(dmk_plan_t P, const double* points)
         HIPCHK(upload(P->lev[l].parent_fid, pf, st));
     }
     // senders / receivers (difference-kernel exchange lists)
-    std::vector<int> send_slot(nb, -1), sfid, rfid, esrc;
+    std::vector<int> send_slot(nb, -1), sfid, slev, rfid, esrc;
     std::vector<int8_t> eoff;
     std::vector<RecvDesc> rd;
     for (int i = 0; i < nb; ++i)
@@ -625,6 +640,7 @@ int build_plan(dmk_plan_t P, const double* points)
             if (send_slot[e.src] < 0) {
                 send_slot[e.src] = (int)sfid.size();
                 sfid.push_back(P->box_fid[e.src]);
+                slev.push_back(T.boxes[e.src].level);
             }
     for (int i = 0; i < nb; ++i) {
         if (T.incoming[i].empty())
@@ -646,6 +662,8 @@ int build_plan(dmk_plan_t P, const double* points)
     P->nsend = (int)sfid.size();
     P->nrecv = (int)rfid.size();
     P->send_fid = P->mem.alloc<int>(sfid.size());
+    if (P->kern == DMK_KERNEL_STRESSLET)
+        P->send_level = P->mem.alloc<int>(slev.size());
     P->recv_fid = P->mem.alloc<int>(rfid.size());
     P->recv = P->mem.alloc<RecvDesc>(rd.size());
     P->e_src = P->mem.alloc<int>(esrc.size());
@@ -730,19 +748,25 @@ int build_plan(dmk_plan_t P, const double* points)
     P->r_in_half = dup(rw.in_half);
     P->root_mh = rw.M + 1;
     P->root_mf = 2 * rw.M + 1;
-    const std::vector<double>& wr = P->periodic ? TB.wper : TB.wroot;
-    P->wdiff = P->mem.alloc<double>(TB.wdiff.size());
+    const bool stress = P->kern == DMK_KERNEL_STRESSLET;
+    const std::vector<double>& wr = P->periodic ? TB.wper : (stress ? TB.wroot_t : TB.wroot);
+    const std::vector<double>& wd = stress ? TB.wdiff_t : TB.wdiff;
+    P->wdiff = P->mem.alloc<double>(wd.size());
     P->wroot = P->mem.alloc<double>(wr.size());
     // work buffers
     P->H = (size_t)q * n1 * n1;
     P->Hroot = (size_t)P->root_mh * P->root_mf * P->root_mf;
     const size_t p3 = (size_t)p * p * p;
-    P->fs = P->mem.alloc<double>(3 * n * (size_t)P->rhs_batch);
+    // forces [rhs_batch][3][n]; stresslet: densities [6][n], then (f, n) [6][n]
+    const int nc = P->nc_in;
+    P->fs = P->mem.alloc<double>(n * std::max<size_t>(3 * (size_t)P->rhs_batch, stress ? 12 : 0));
     P->u = P->mem.alloc<double>(3 * n * (size_t)P->rhs_batch);
     const size_t es = P->es, cs = 2 * P->es;  // real / complex element bytes
-    P->Q = P->mem.alloc<char>((size_t)P->nf * 3 * p3 * es);
+    P->Q = P->mem.alloc<char>((size_t)P->nf * nc * p3 * es);
     P->V = P->mem.alloc<char>((size_t)P->nf * 3 * p3 * es);
-    P->Phi = P->mem.alloc<char>((size_t)P->nsend * 3 * P->H * cs);
+    P->Phi = P->mem.alloc<char>((size_t)P->nsend * nc * P->H * cs);
+    if (stress)
+        P->Phi3 = P->mem.alloc<char>((size_t)P->nsend * 3 * P->H * cs);
     P->Psi = P->mem.alloc<char>((size_t)P->nrecv * 3 * P->H * cs);
     // scratch: largest intermediate of any stage, per (slot, component)
     size_t per = 0;
@@ -760,10 +784,10 @@ int build_plan(dmk_plan_t P, const double* points)
         const size_t mh = P->root_mh, mf = P->root_mf;
         per_root = std::max({(size_t)p * p * mh, (size_t)p * mh * mf, mf * mf * (size_t)p, mf * (size_t)p * p}) * cs;
     }
-    const size_t sbytes = std::max(per * 3 * (size_t)maxslots, per_root * 3 * (size_t)np);
+    const size_t sbytes = std::max(per * nc * (size_t)maxslots, per_root * nc * (size_t)np);
     P->s1 = P->mem.alloc<char>(sbytes);
     P->s2 = P->mem.alloc<char>(sbytes);
-    P->phi_root = P->mem.alloc<char>(3 * P->Hroot * cs * np);
+    P->phi_root = P->mem.alloc<char>(nc * P->Hroot * cs * np);
     P->psi_root = P->mem.alloc<char>(3 * P->Hroot * cs * np);
     P->cst = P->mem.alloc<double>(3 * (size_t)P->rhs_batch * np);
     P->d_root_fid = P->mem.alloc<int>(np);
@@ -776,6 +800,8 @@ int build_plan(dmk_plan_t P, const double* points)
         HIPCHK(upload(P->leaves_src, hl_src, st));
     HIPCHK(upload(P->echunks, ech, st));
     HIPCHK(upload(P->send_fid, sfid, st));
+    if (stress)
+        HIPCHK(upload(P->send_level, slev, st));
     HIPCHK(upload(P->recv_fid, rfid, st));
     HIPCHK(upload(P->recv, rd, st));
     HIPCHK(upload(P->e_src, esrc, st));
@@ -787,7 +813,7 @@ int build_plan(dmk_plan_t P, const double* points)
     HIPCHK(upload(d_clen, clen, st));
     HIPCHK(upload(P->cheb_t, ct, st));
     HIPCHK(upload(P->cheb_w, cw, st));
-    HIPCHK(upload(P->wdiff, TB.wdiff, st));
+    HIPCHK(upload(P->wdiff, wd, st));
     HIPCHK(upload(P->wroot, wr, st));
     launch_chunk_bbox(P->x, P->y, P->z, d_cstart, d_clen, (int)cstart.size(), P->cbbox, st);
     launch_lagrange_table(P->prm.p, P->leaves, P->nleaf, P->x, P->y, P->z, P->cheb_t, P->cheb_w, P->Ltab, st);
@@ -820,7 +846,9 @@ void far_field(dmk_plan_t P, int r, bool record)
     const long p3 = (long)p * p * p, p2 = (long)p * p;
     const Tree& T = P->tree;
     // Step 2a: proxy charges of the leaves
-    launch_anterp(p, P->leaves_src, P->nleaf, P->Ltab, fs, n, P->Q, P->f32, st);
+    const int nc = P->nc_in;
+    const bool stress = P->kern == DMK_KERNEL_STRESSLET;
+    launch_anterp(p, nc, P->leaves_src, P->nleaf, P->Ltab, fs, n, P->Q, P->f32, st);
     mark(1);
     const int h = (p + 1) / 2, M = q - 1;
     // Step 2b: merge children into parents, finest level first (Q is x-major [a][b][c])
@@ -829,24 +857,28 @@ void far_field(dmk_plan_t P, int r, bool record)
         if (!L.nparent)
             continue;
         stage(P, ST_SYM_REAL, IO_GATHER8, P->Q, 0, nullptr, P->s1, 4 * p3, nullptr, 0, P->merge_mat, 2 * p, p, 0, 0,
-              p, h, 4 * p * p, L.nparent, L.child_fid);
+              p, h, 4 * p * p, L.nparent, L.child_fid, nc);
         stage(P, ST_SYM_REAL, IO_PLAIN, P->s1, 4 * p3, nullptr, P->s2, 2 * p3, nullptr, 0, P->merge_mat, 2 * p, p, 0,
-              0, p, h, 2 * p * p, L.nparent);
+              0, p, h, 2 * p * p, L.nparent, nullptr, nc);
         stage(P, ST_SYM_REAL, IO_PLAIN, P->s2, 2 * p3, nullptr, P->Q, p3, L.parent_fid, 0, P->merge_mat, 2 * p, p, 0,
-              0, p, h, p * p, L.nparent);
+              0, p, h, p * p, L.nparent, nullptr, nc);
     }
     mark(2);
     // outgoing plane waves of the senders: Phi[mx][my][mz], mx >= 0
     const long H = (long)P->H;
     stage(P, ST_OUT_HALF, IO_PLAIN, P->Q, p3, P->send_fid, P->s1, p2 * q, nullptr, 0, P->pw_out, p, q, 0, 0, h, M + 1,
-          p * p, P->nsend);
+          p * p, P->nsend, nullptr, nc);
     stage(P, ST_OUT_FULL, IO_PLAIN, P->s1, p2 * q, nullptr, P->s2, (long)p * q * n1, nullptr, 0, P->pw_out, p, n1, 0,
-          M, h, M + 1, p * q, P->nsend);
+          M, h, M + 1, p * q, P->nsend, nullptr, nc);
     stage(P, ST_OUT_FULL, IO_PLAIN, P->s2, (long)p * q * n1, nullptr, P->Phi, H, nullptr, 0, P->pw_out, p, n1, 0, M,
-          h, M + 1, q * n1, P->nsend);
+          h, M + 1, q * n1, P->nsend, nullptr, nc);
+    // stresslet: the difference symbol (6 -> 3 components) on the sending side
+    if (stress)
+        launch_stress_symbol(q, n1, P->nsend, P->send_level, P->Phi, P->wdiff, P->Phi3, P->f32, st);
     mark(3);
     // Step 3b: translation with the difference-kernel symbol -> Psi[mz][my][mx]
-    launch_translate(q, n1, P->recv, P->nrecv, P->e_src, P->e_off, P->Phi, P->wdiff, P->Psi, P->f32, st);
+    launch_translate(q, n1, P->recv, P->nrecv, P->e_src, P->e_off, stress ? P->Phi3 : P->Phi, P->wdiff, P->Psi,
+                     P->f32, stress, st);
     mark(4);
     // incoming plane waves -> proxy potentials, z-major V[c][b][a]
     launch_zero(P->V, (size_t)P->nf * 3 * p3 * P->es, st);
@@ -863,19 +895,23 @@ void far_field(dmk_plan_t P, int r, bool record)
         const long Hr = (long)P->Hroot;
         const int nr = P->nprob;  // one root per problem; stage slots map to their far-field slots
         stage(P, ST_OUT_HALF, IO_PLAIN, P->Q, p3, P->d_root_fid, P->s1, p2 * mh, nullptr, 0, P->r_out, p, mh, 0, 0, h,
-              mh, p * p, nr);
+              mh, p * p, nr, nullptr, nc);
         stage(P, ST_OUT_FULL, IO_PLAIN, P->s1, p2 * mh, nullptr, P->s2, (long)p * mh * mf, nullptr, 0, P->r_out, p, mf,
-              0, RM, h, mh, p * mh, nr);
+              0, RM, h, mh, p * mh, nr, nullptr, nc);
         stage(P, ST_OUT_FULL, IO_PLAIN, P->s2, (long)p * mh * mf, nullptr, P->phi_root, Hr, nullptr, 0, P->r_out, p,
-              mf, 0, RM, h, mh, mh * mf, nr);
-        launch_root_symbol(mh, mf, nr, P->phi_root, P->wroot, P->psi_root, P->f32, st);
+              mf, 0, RM, h, mh, mh * mf, nr, nullptr, nc);
+        if (stress)
+            launch_root_symbol_t(mh, mf, nr, P->phi_root, P->wroot, 2.0 * kPi / P->tab->root_period, P->psi_root,
+                                 P->f32, st);
+        else
+            launch_root_symbol(mh, mf, nr, P->phi_root, P->wroot, P->psi_root, P->f32, st);
         stage(P, ST_IN_FULL, IO_PLAIN, P->psi_root, Hr, nullptr, P->s1, (long)mf * mh * p, nullptr, 0, P->r_in_full,
               mf, p, RM, 0, mh, h, mf * mh, nr);
         stage(P, ST_IN_FULL, IO_PLAIN, P->s1, (long)mf * mh * p, nullptr, P->s2, (long)mh * p * p, nullptr, 0,
               P->r_in_full, mf, p, RM, 0, mh, h, mh * p, nr);
         stage(P, ST_IN_HALF_REAL, IO_PLAIN, P->s2, (long)mh * p * p, nullptr, P->V, p3, P->d_root_fid, 1, P->r_in_half,
               mh, p, 0, 0, mh, h, p * p, nr);
-        if (!P->periodic)
+        if (!P->periodic && !stress)
             launch_sum_root(P->Q, P->d_root_fid, nr, (int)p3, 1.0 / (4.0 * kPi * (1.0 + std::sqrt(3.0))), cst, P->f32,
                             st);
     }
@@ -915,14 +951,42 @@ int eval_batch(dmk_plan_t P, const double* f, int nb, double* vel, bool record)
         far_field(P, r, record && r == 0);
     if (record)
         (void)hipEventRecord(P->ev[DMK_NUM_PHASES + 1], st);
-    launch_near(P->near_sg, nb, P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x, P->y, P->z, P->fs, n,
+    launch_near(DMK_KERNEL_STOKESLET, P->near_sg, nb, P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x, P->y, P->z, P->fs, n,
                 P->poly, P->u, st);
     if (record)
         (void)hipEventRecord(P->ev[9], st);
     for (int r = 0; r < nb; ++r)
-        launch_finalize(P->u + (size_t)r * 3 * n, n, P->perm, P->tofs, P->pid, P->scale,
+        launch_finalize(P->u + (size_t)r * 3 * n, n, P->perm, P->tofs, P->pid, P->scale, 0,
                         P->periodic ? nullptr : P->cst + (size_t)3 * P->nprob * r, vel + (size_t)r * 3 * P->nout,
                         st);
+    if (record) {
+        (void)hipEventRecord(P->ev[10], st);
+        P->ev_recorded = true;
+    }
+    return DMK_OK;
+}
+
+// One stresslet vector: densities and (f, n) in sorted order, the far field
+// of the 6 density components, the residual stresslet near field, and the
+// scaling by 1/L^2 (the stresslet is homogeneous of degree -2).  There is no
+// constant and no self term: both the mollified kernel at 0 and every residual
+// term are odd in the separation.
+int eval_stresslet(dmk_plan_t P, const double* f, const double* nv, double* vel, bool record)
+{
+    using namespace dmk;
+    hipStream_t st = P->stream;
+    const int64_t n = P->n;
+    if (record)
+        (void)hipEventRecord(P->ev[0], st);
+    launch_gather_stresslet(f, nv, n, P->nsrc, P->perm, P->fs, P->fs + 6 * (size_t)n, st);
+    far_field(P, 0, record);
+    if (record)
+        (void)hipEventRecord(P->ev[DMK_NUM_PHASES + 1], st);
+    launch_near(DMK_KERNEL_STRESSLET, P->near_sg, 1, P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x,
+                P->y, P->z, P->fs + 6 * (size_t)n, n, P->poly, P->u, st);
+    if (record)
+        (void)hipEventRecord(P->ev[9], st);
+    launch_finalize(P->u, n, P->perm, P->tofs, P->pid, P->scale, 1, nullptr, vel, st);
     if (record) {
         (void)hipEventRecord(P->ev[10], st);
         P->ev_recorded = true;
@@ -940,14 +1004,21 @@ int dmk_stokes_params(double tol, dmk_plan_info* info) { return dmk_stokes_param
 
 int dmk_stokes_params_ex(double tol, int window, dmk_plan_info* info)
 {
+    return dmk_stokes_params_kernel(tol, window, DMK_KERNEL_STOKESLET, info);
+}
+
+int dmk_stokes_params_kernel(double tol, int window, int kernel, dmk_plan_info* info)
+{
     if (!info)
         return fail(DMK_ERR_ARG, "info is NULL");
     std::memset(info, 0, sizeof(*info));
     if (window != DMK_WINDOW_PROLATE && window != DMK_WINDOW_GAUSSIAN)
         return fail(DMK_ERR_ARG, "unknown window");
+    if (kernel != DMK_KERNEL_STOKESLET && kernel != DMK_KERNEL_STRESSLET)
+        return fail(DMK_ERR_ARG, "unknown kernel");
     dmk::Params prm;
-    if (!dmk::select_params(tol, &prm, window))
-        return fail(DMK_ERR_TOL, "tol outside the window's range");
+    if (!dmk::select_params(tol, &prm, window, kernel))
+        return fail(DMK_ERR_TOL, "tol outside the window's range (or no such kernel/window pair)");
     const dmk::Tables* T = dmk::get_tables(prm);
     info->tol = prm.tol;
     info->c = prm.c;
@@ -960,6 +1031,7 @@ int dmk_stokes_params_ex(double tol, int window, dmk_plan_info* info)
     info->deg_Q = (int)T->fits.Q.a.size() - 1;
     info->window = prm.window;
     info->sigma = prm.sigma;
+    info->kernel = prm.kernel;
     return DMK_OK;
 }
 
@@ -978,6 +1050,22 @@ int dmk_stokes_radial(double tol, const double* rho, int64_t n, double* out)
         const double s = r * r;
         out[4 * i + 2] = s < 1.0 ? T->fits.P.eval(s) : 0.0;
         out[4 * i + 3] = s < 1.0 ? T->fits.Q.eval(s) : 0.0;
+    }
+    return DMK_OK;
+}
+
+int dmk_stokes_radial_stresslet(double tol, const double* rho, int64_t n, double* out)
+{
+    if (!rho || !out || n < 0)
+        return fail(DMK_ERR_ARG, "bad arguments");
+    dmk::Params prm;
+    if (!dmk::select_params(tol, &prm, DMK_WINDOW_PROLATE, DMK_KERNEL_STRESSLET))
+        return fail(DMK_ERR_TOL, "tol must lie in [1e-12, 1e-3]");
+    const dmk::Tables* T = dmk::get_tables(prm);
+    for (int64_t i = 0; i < n; ++i) {
+        const double s = rho[i] * rho[i];
+        out[2 * i] = s < 1.0 ? T->fits.P.eval(s) : 0.0;
+        out[2 * i + 1] = s < 1.0 ? T->fits.Q.eval(s) : 0.0;
     }
     return DMK_OK;
 }
@@ -1010,16 +1098,21 @@ int create_plan(const double* points, const std::vector<int64_t>& offsets, int d
         return rc;
     if (periodic != 0 && periodic != 1)
         return fail(DMK_ERR_ARG, "periodic must be 0 or 1");
+    if (opts && opts->kernel == DMK_KERNEL_STRESSLET && periodic)
+        return fail(DMK_ERR_UNSUPPORTED, "the stresslet is offered in free space only");
     if (!is_device_ptr(points))
         return fail(DMK_ERR_ARG, "points must be a device pointer");
     const auto t0 = std::chrono::steady_clock::now();
     dmk_plan_t P = new (std::nothrow) dmk_plan_s();
     if (!P)
         return fail(DMK_ERR_OOM, "host allocation failed");
-    if (!dmk::select_params(tol, &P->prm, opts ? opts->window : 0)) {
+    const int kern = opts ? opts->kernel : DMK_KERNEL_STOKESLET;
+    if (!dmk::select_params(tol, &P->prm, opts ? opts->window : 0, kern)) {
         delete P;
         return fail(DMK_ERR_TOL, "tol must lie in [1e-12, 1e-3]");
     }
+    P->kern = kern;
+    P->nc_in = kern == DMK_KERNEL_STRESSLET ? 6 : 3;
     if (opts)
         dmk::override_params(&P->prm, opts->q, opts->p);
     P->tab = dmk::get_tables(P->prm);
@@ -1155,6 +1248,8 @@ int dmk_stokes_eval(dmk_plan_t plan, const double* forces, int n_rhs, double* ve
 {
     if (!plan)
         return fail(DMK_ERR_ARG, "plan is NULL");
+    if (plan->kern != DMK_KERNEL_STOKESLET)
+        return fail(DMK_ERR_ARG, "a stresslet plan is evaluated with dmk_stokes_eval_stresslet");
     if (n_rhs < 1)
         return fail(DMK_ERR_ARG, "n_rhs must be >= 1");
     if (!is_device_ptr(forces) || !is_device_ptr(velocities))
@@ -1220,6 +1315,30 @@ int dmk_stokes_eval(dmk_plan_t plan, const double* forces, int n_rhs, double* ve
     return DMK_OK;
 }
 
+int dmk_stokes_eval_stresslet(dmk_plan_t plan, const double* forces, const double* normals, int n_rhs,
+                              double* velocities)
+{
+    if (!plan)
+        return fail(DMK_ERR_ARG, "plan is NULL");
+    if (plan->kern != DMK_KERNEL_STRESSLET)
+        return fail(DMK_ERR_ARG, "the plan was not built for the stresslet (dmk_opts.kernel)");
+    if (n_rhs < 1)
+        return fail(DMK_ERR_ARG, "n_rhs must be >= 1");
+    if (!is_device_ptr(forces) || !is_device_ptr(normals) || !is_device_ptr(velocities))
+        return fail(DMK_ERR_ARG, "forces, normals and velocities must be device pointers");
+    for (int r = 0; r < n_rhs; ++r) {
+        const size_t so = (size_t)r * 3 * plan->nsrc;
+        const int rc = eval_stresslet(plan, forces + so, normals + so, velocities + (size_t)r * 3 * plan->nout,
+                                      plan->timing && r == 0);
+        if (rc != DMK_OK)
+            return rc;
+    }
+    HIPCHK(hipEventRecord(plan->done, plan->stream));
+    plan->done_recorded = true;
+    HIPCHK(hipGetLastError());
+    return DMK_OK;
+}
+
 int dmk_stokes_autotune(const double* points, int64_t n, const int64_t* offsets, int n_problems, int dim,
                         int periodic, double tol, const dmk_opts* opts, int n_rhs, dmk_opts* tuned, double* best_ms)
 {
@@ -1232,6 +1351,8 @@ int dmk_stokes_autotune(const double* points, int64_t n, const int64_t* offsets,
     int rc = validate_common(dim, tol, opts);
     if (rc != DMK_OK)
         return rc;
+    if (opts && opts->kernel != DMK_KERNEL_STOKESLET)
+        return fail(DMK_ERR_UNSUPPORTED, "the autotuner times the Stokeslet evaluation only");
     dmk_opts base{};
     if (opts)
         base = *opts;
@@ -1368,6 +1489,7 @@ int dmk_stokes_plan_info(dmk_plan_t plan, dmk_plan_info* info)
     info->precision = P.precision;
     info->window = P.prm.window;
     info->sigma = P.prm.sigma;
+    info->kernel = P.kern;
     return DMK_OK;
 }
 
@@ -1568,6 +1690,49 @@ int dmk_stokes_residual_sum(const double* targets, int64_t m, const double* sour
         return fail(DMK_ERR_UNSUPPORTED, "radial fit degree too high");
     dmk::launch_residual_direct(tx, tx + m, tx + 2 * m, m, sx, sx + ns, sx + 2 * ns, sf, ns, r_lambda, poly, out,
                                 st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));  // temporaries are freed on return
+    return DMK_OK;
+}
+
+int dmk_stokes_residual_sum_stresslet(const double* targets, int64_t m, const double* sources, const double* forces,
+                                      const double* normals, int64_t ns, double r_lambda, double tol, void* stream,
+                                      double* out)
+{
+    if (m < 0 || ns < 0 || !(r_lambda > 0))
+        return fail(DMK_ERR_ARG, "bad sizes or r_lambda");
+    if (m == 0)
+        return DMK_OK;
+    if (!is_device_ptr(targets) || !is_device_ptr(out) ||
+        (ns > 0 && (!is_device_ptr(sources) || !is_device_ptr(forces) || !is_device_ptr(normals))))
+        return fail(DMK_ERR_ARG, "arrays must be device pointers");
+    dmk::Params prm;
+    if (!dmk::select_params(tol, &prm, DMK_WINDOW_PROLATE, DMK_KERNEL_STRESSLET))
+        return fail(DMK_ERR_TOL, "tol must lie in [1e-12, 1e-3]");
+    const dmk::Tables* T = dmk::get_tables(prm);
+    hipStream_t st = (hipStream_t)stream;
+    DevMem mem;
+    double* tx = mem.alloc<double>(3 * m);
+    double* sx = mem.alloc<double>(3 * std::max<int64_t>(ns, 1));
+    double* sf = mem.alloc<double>(6 * std::max<int64_t>(ns, 1));
+    if (mem.oom)
+        return fail(DMK_ERR_OOM, "device allocation failed");
+    for (int d = 0; d < 3; ++d)
+        HIPCHK(hipMemcpy2DAsync(tx + d * m, sizeof(double), targets + d, 3 * sizeof(double), sizeof(double), m,
+                                hipMemcpyDeviceToDevice, st));
+    for (int d = 0; d < 3 && ns > 0; ++d) {
+        HIPCHK(hipMemcpy2DAsync(sx + d * ns, sizeof(double), sources + d, 3 * sizeof(double), sizeof(double), ns,
+                                hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpy2DAsync(sf + d * ns, sizeof(double), forces + d, 3 * sizeof(double), sizeof(double), ns,
+                                hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpy2DAsync(sf + (3 + d) * ns, sizeof(double), normals + d, 3 * sizeof(double), sizeof(double),
+                                ns, hipMemcpyDeviceToDevice, st));
+    }
+    dmk::RadialPoly poly;
+    if (!make_poly(*T, &poly))
+        return fail(DMK_ERR_UNSUPPORTED, "radial fit degree too high");
+    dmk::launch_residual_direct_t(tx, tx + m, tx + 2 * m, m, sx, sx + ns, sx + 2 * ns, sf, ns, r_lambda, poly, out,
+                                  st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));  // temporaries are freed on return
     return DMK_OK;

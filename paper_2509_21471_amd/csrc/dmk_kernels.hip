@@ -10,6 +10,9 @@ namespace dmk {
 namespace {
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kInv8Pi = 1.0 / (8.0 * kPi);
+constexpr double k3Over4Pi = 3.0 / (4.0 * kPi);
+// largest grid.y of a launch
+constexpr int kMaxGridY = 65535;
 
 inline unsigned nblocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 }  // namespace
@@ -279,6 +282,42 @@ __global__ __launch_bounds__(256) void k_gather_forces(const double* __restrict_
 void launch_gather_forces(const double* f, int64_t n, int64_t nsrc, const int* perm, double* fs, hipStream_t s)
 {
     hipLaunchKernelGGL(k_gather_forces, dim3(nblocks(n, 256)), dim3(256), 0, s, f, n, nsrc, perm, fs);
+}
+
+// Stresslet sources: the symmetric double-layer density of f n^T for the far
+// field, rho[6][n] = (f1 n1, f2 n2, f3 n3, f1 n2 + f2 n1, f1 n3 + f3 n1,
+// f2 n3 + f3 n2) (the kernel is symmetric in its last two indices, so the
+// off-diagonal pairs enter summed), and f, n themselves for the near field,
+// fn[6][n].  Points with input index >= nsrc carry zero strength.
+__global__ __launch_bounds__(256) void k_gather_stresslet(const double* __restrict__ f, const double* __restrict__ nv,
+                                                          int64_t n, int64_t nsrc, const int* __restrict__ perm,
+                                                          double* __restrict__ rho, double* __restrict__ fn)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const int64_t o = perm[i];
+    const bool src = o < nsrc;
+    const double f1 = src ? f[3 * o] : 0.0, f2 = src ? f[3 * o + 1] : 0.0, f3 = src ? f[3 * o + 2] : 0.0;
+    const double n1 = src ? nv[3 * o] : 0.0, n2 = src ? nv[3 * o + 1] : 0.0, n3 = src ? nv[3 * o + 2] : 0.0;
+    rho[i] = f1 * n1;
+    rho[n + i] = f2 * n2;
+    rho[2 * n + i] = f3 * n3;
+    rho[3 * n + i] = f1 * n2 + f2 * n1;
+    rho[4 * n + i] = f1 * n3 + f3 * n1;
+    rho[5 * n + i] = f2 * n3 + f3 * n2;
+    fn[i] = f1;
+    fn[n + i] = f2;
+    fn[2 * n + i] = f3;
+    fn[3 * n + i] = n1;
+    fn[4 * n + i] = n2;
+    fn[5 * n + i] = n3;
+}
+
+void launch_gather_stresslet(const double* f, const double* nv, int64_t n, int64_t nsrc, const int* perm, double* rho,
+                             double* fn, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_stresslet, dim3(nblocks(n, 256)), dim3(256), 0, s, f, nv, n, nsrc, perm, rho, fn);
 }
 
 // Barycentric Lagrange basis on first-kind Chebyshev nodes.
@@ -552,7 +591,7 @@ struct AMCfg {
     static constexpr int TASKS = MT * NG;            // waves per leaf
 };
 
-template <int P, typename S>
+template <int P, int NC, typename S>
 __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__ leaves, int nleaf,
                                                     const double* __restrict__ Ltab,
                                                     const double* __restrict__ fs, int64_t n, S* __restrict__ Q)
@@ -575,27 +614,28 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
         bcol[t] = n_ok[t] ? nn / P : 0;
         ccol[t] = n_ok[t] ? nn % P : 0;
     }
-    mfma_d4 acc[NN][3];
+    mfma_d4 acc[NN][NC];
 #pragma unroll
     for (int t = 0; t < NN; ++t)
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
+        for (int j = 0; j < NC; ++j)
             acc[t][j] = mfma_d4{0.0, 0.0, 0.0, 0.0};
     // operands of the 4 points starting at pt0 (this lane: point pt0 + lk)
-    double ax0, f00, f10, f20, ly0[NN], lz0[NN];
-    double ax1, f01, f11, f21, ly1[NN], lz1[NN];
-#define DMK_AM_LOAD(AX, F0, F1, F2, LY, LZ, PT0)                                   \
+    double ax0, fa0[NC], ly0[NN], lz0[NN];
+    double ax1, fa1[NC], ly1[NN], lz1[NN];
+#define DMK_AM_LOAD(AX, FA, LY, LZ, PT0)                                          \
     {                                                                             \
         const int64_t pt = (PT0) + lk;                                            \
         const bool ok = pt < L.end;                                               \
         const int64_t pc = ok ? pt : L.start;                                     \
         const double* Lp = Ltab + (size_t)pc * 3 * PA;                            \
         const double ax = Lp[a_ok ? a : 0];                                       \
-        const double g0 = fs[pc], g1 = fs[n + pc], g2 = fs[2 * n + pc];           \
         AX = (ok && a_ok) ? ax : 0.0;                                             \
-        F0 = ok ? g0 : 0.0;                                                       \
-        F1 = ok ? g1 : 0.0;                                                       \
-        F2 = ok ? g2 : 0.0;                                                       \
+        _Pragma("unroll") for (int j = 0; j < NC; ++j)                            \
+        {                                                                         \
+            const double g = fs[(size_t)j * n + pc];                              \
+            FA[j] = ok ? g : 0.0;                                                 \
+        }                                                                         \
         _Pragma("unroll") for (int t = 0; t < NN; ++t)                            \
         {                                                                         \
             const double yv = Lp[PA + bcol[t]];                                   \
@@ -603,27 +643,26 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
             LZ[t] = Lp[2 * PA + ccol[t]];                                         \
         }                                                                         \
     }
-#define DMK_AM_STEP(AX, F0, F1, F2, LY, LZ)                                                   \
+#define DMK_AM_STEP(AX, FA, LY, LZ)                                                           \
     _Pragma("unroll") for (int t = 0; t < NN; ++t)                                            \
     {                                                                                         \
         const double w = LY[t] * LZ[t];                                                       \
-        acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(AX, w * F0, acc[t][0], 0, 0, 0);     \
-        acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(AX, w * F1, acc[t][1], 0, 0, 0);     \
-        acc[t][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(AX, w * F2, acc[t][2], 0, 0, 0);     \
+        _Pragma("unroll") for (int j = 0; j < NC; ++j)                                        \
+            acc[t][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(AX, w * FA[j], acc[t][j], 0, 0, 0); \
     }
     // branch-free steps of 8 points: operands past the leaf's end load from a
     // valid row and are zeroed, so they add nothing
-    DMK_AM_LOAD(ax0, f00, f10, f20, ly0, lz0, L.start)
+    DMK_AM_LOAD(ax0, fa0, ly0, lz0, L.start)
     for (int64_t p0 = L.start; p0 < L.end; p0 += 8) {
-        DMK_AM_LOAD(ax1, f01, f11, f21, ly1, lz1, p0 + 4)
-        DMK_AM_STEP(ax0, f00, f10, f20, ly0, lz0)
-        DMK_AM_LOAD(ax0, f00, f10, f20, ly0, lz0, p0 + 8)
-        DMK_AM_STEP(ax1, f01, f11, f21, ly1, lz1)
+        DMK_AM_LOAD(ax1, fa1, ly1, lz1, p0 + 4)
+        DMK_AM_STEP(ax0, fa0, ly0, lz0)
+        DMK_AM_LOAD(ax0, fa0, ly0, lz0, p0 + 8)
+        DMK_AM_STEP(ax1, fa1, ly1, lz1)
     }
 #undef DMK_AM_LOAD
 #undef DMK_AM_STEP
     // D[row = lk + 4 r][col = li] of tile t: a = 16 mt + lk + 4 r, n = 16 (NN ng + t) + li
-    S* q = Q + (size_t)L.fid * 3 * P * P * P;
+    S* q = Q + (size_t)L.fid * NC * P * P * P;
 #pragma unroll
     for (int t = 0; t < NN; ++t) {
         if (!n_ok[t])
@@ -634,7 +673,7 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
             const int ar = 16 * mt + lk + 4 * r;
             if (ar < P)
 #pragma unroll
-                for (int j = 0; j < 3; ++j)
+                for (int j = 0; j < NC; ++j)
                     q[((size_t)j * P + ar) * P * P + nn] = (S)acc[t][j][r];
         }
     }
@@ -645,10 +684,12 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
 // parameter choices.
 #define DMK_P_DISPATCH(p, MACRO) \
     switch (p) {                 \
+    case 11: MACRO(11); break;   \
     case 12: MACRO(12); break;   \
     case 14: MACRO(14); break;   \
     case 16: MACRO(16); break;   \
     case 20: MACRO(20); break;   \
+    case 22: MACRO(22); break;   \
     case 23: MACRO(23); break;   \
     case 26: MACRO(26); break;   \
     case 28: MACRO(28); break;   \
@@ -658,14 +699,15 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
     case 40: MACRO(40); break;   \
     case 43: MACRO(43); break;   \
     case 44: MACRO(44); break;   \
+    case 48: MACRO(48); break;   \
     default: break;              \
     }
 
 bool p_supported(int p)
 {
     switch (p) {
-    case 12: case 14: case 16: case 20: case 23: case 26: case 28: case 30: case 33: case 36: case 40: case 43:
-    case 44: return true;
+    case 11: case 12: case 14: case 16: case 20: case 22: case 23: case 26: case 28: case 30: case 33: case 36:
+    case 40: case 43: case 44: case 48: return true;
     default: return false;
     }
 }
@@ -682,20 +724,27 @@ void launch_lagrange_table(int p, const LeafDesc* leaves, int nleaf, const doubl
 #undef L_LT
 }
 
-void launch_anterp(int p, const LeafDesc* leaves, int nleaf, const double* Ltab, const double* fs, int64_t n,
+void launch_anterp(int p, int nc, const LeafDesc* leaves, int nleaf, const double* Ltab, const double* fs, int64_t n,
                    void* Q, bool f32, hipStream_t s)
 {
     if (nleaf == 0)
         return;
-#define L_ANTERP(P)                                                                                           \
-    if (f32)                                                                                                  \
-        hipLaunchKernelGGL((k_anterp_mfma<P, float>), dim3(nleaf * AMCfg<P>::TASKS), dim3(64), 0, s, leaves, \
-                           nleaf, Ltab, fs, n, (float*)Q);                                                    \
-    else                                                                                                      \
-        hipLaunchKernelGGL((k_anterp_mfma<P, double>), dim3(nleaf * AMCfg<P>::TASKS), dim3(64), 0, s, leaves, \
-                           nleaf, Ltab, fs, n, (double*)Q)
+#define L_ANTERP_NC(P, NC)                                                                                       \
+    if (f32)                                                                                                     \
+        hipLaunchKernelGGL((k_anterp_mfma<P, NC, float>), dim3(nleaf * AMCfg<P>::TASKS), dim3(64), 0, s, leaves, \
+                           nleaf, Ltab, fs, n, (float*)Q);                                                       \
+    else                                                                                                         \
+        hipLaunchKernelGGL((k_anterp_mfma<P, NC, double>), dim3(nleaf * AMCfg<P>::TASKS), dim3(64), 0, s,        \
+                           leaves, nleaf, Ltab, fs, n, (double*)Q)
+#define L_ANTERP(P)               \
+    if (nc == 6) {                \
+        L_ANTERP_NC(P, 6);        \
+    } else {                      \
+        L_ANTERP_NC(P, 3);        \
+    }
     DMK_P_DISPATCH(p, L_ANTERP)
 #undef L_ANTERP
+#undef L_ANTERP_NC
 }
 
 void launch_leaf_eval(int p, const EvalChunk* chunks, int nchunk, const double* Ltab, const void* V, int64_t n,
@@ -740,14 +789,15 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
     const int tid = threadIdx.x;
     for (int k = tid; k < nm; k += 256)
         smat[k] = make_double2(a.mat[2 * k], a.mat[2 * k + 1]);
-    const int slot = blockIdx.y / 3, comp = blockIdx.y % 3;
+    const int nc = a.ncomp;
+    const int slot = a.slot0 + (int)blockIdx.y / nc, comp = blockIdx.y % nc;
     const int R = a.R, Nin = a.Nin, Nout = a.Nout, p = a.p;
     const int r0 = blockIdx.x * 64;
     const int nrow = min(64, R - r0);
     const size_t p3 = (size_t)p * p * p;
     // ---- input slab ----
     {
-        const size_t xoff = ((size_t)(a.xmap ? a.xmap[slot] : slot) * 3 + comp) * a.xstride;
+        const size_t xoff = ((size_t)(a.xmap ? a.xmap[slot] : slot) * nc + comp) * a.xstride;
         for (int e = tid; e < Nin * 64; e += 256) {
             const int k = e >> 6, rr = e & 63;
             const int r = r0 + rr;
@@ -757,7 +807,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
                     const int B = r / (2 * p), C = r % (2 * p);
                     const int f = a.child_fid[slot * 8 + 4 * (k / p) + 2 * (B / p) + (C / p)];
                     if (f >= 0)
-                        v0 = (double)((const S*)a.X)[((size_t)f * 3 + comp) * p3 +
+                        v0 = (double)((const S*)a.X)[((size_t)f * nc + comp) * p3 +
                                                      ((size_t)(k % p) * p + (B % p)) * p + (C % p)];
                 } else if (XE == 2) {
                     const typename Store<S>::cx v = ((const typename Store<S>::cx*)a.X)[xoff + (size_t)k * R + r];
@@ -875,12 +925,12 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
             const int C = r / (2 * p), B = r % (2 * p);
             const int f = a.child_fid[slot * 8 + 4 * (A / p) + 2 * (B / p) + (C / p)];
             if (f >= 0) {
-                S& y = Yd[((size_t)f * 3 + comp) * p3 + ((size_t)(C % p) * p + (B % p)) * p + (A % p)];
+                S& y = Yd[((size_t)f * nc + comp) * p3 + ((size_t)(C % p) * p + (B % p)) * p + (A % p)];
                 y = (S)((double)y + tile[e]);
             }
         }
     } else {
-        const size_t yoff = ((size_t)(a.ymap ? a.ymap[slot] : slot) * 3 + comp) * a.ystride * YE +
+        const size_t yoff = ((size_t)(a.ymap ? a.ymap[slot] : slot) * nc + comp) * a.ystride * YE +
                             (size_t)r0 * Nout * YE;
         S* Yd = (S*)a.Y + yoff;
         const int cnt = nrow * Nout * YE;
@@ -919,16 +969,22 @@ template <int MODE, int IO>
 static void stage_ni(const StageArgs& a, hipStream_t s)
 {
     using Tr = StageTraits<MODE>;
-    dim3 grid(nblocks(a.R, 64), a.nslots * 3);
     const size_t tile = std::max((size_t)a.Nin * 64 * (Tr::xc ? 2 : 1), (size_t)a.Nout * 64 * (Tr::yc ? 2 : 1));
     const size_t shm = (size_t)a.Nh * a.Kh * sizeof(double2) + tile * sizeof(double);
     const int ni = (a.Nh + 3) / 4;
-    if (ni <= 4)
-        stage_launch<MODE, IO, 4>(grid, shm, a, s);
-    else if (ni <= 8)
-        stage_launch<MODE, IO, 8>(grid, shm, a, s);
-    else
-        stage_launch<MODE, IO, 12>(grid, shm, a, s);
+    // grid.y (slot, component) stays within 65535: large slot counts go in chunks
+    const int chunk = kMaxGridY / a.ncomp;
+    for (int s0 = a.slot0; s0 < a.nslots; s0 += chunk) {
+        StageArgs b = a;
+        b.slot0 = s0;
+        const dim3 grid(nblocks(a.R, 64), std::min(chunk, a.nslots - s0) * a.ncomp);
+        if (ni <= 4)
+            stage_launch<MODE, IO, 4>(grid, shm, b, s);
+        else if (ni <= 8)
+            stage_launch<MODE, IO, 8>(grid, shm, b, s);
+        else
+            stage_launch<MODE, IO, 12>(grid, shm, b, s);
+    }
 }
 
 void launch_stage(int mode, int io, const StageArgs& a, hipStream_t s)
@@ -956,7 +1012,7 @@ void launch_stage(int mode, int io, const StageArgs& a, hipStream_t s)
 // (Phi[m_x][m_y][m_z]) and the receiver side z-major (Psi[m_z][m_y][m_x]); a
 // slab of fixed m_y is read as q runs of n1 contiguous modes, transposed in LDS
 // and written as n1 runs of q contiguous modes, so both sides stay coalesced.
-template <typename S>
+template <typename S, bool PLAIN>
 __global__ __launch_bounds__(256) void k_translate(int q, int n1, int nrecv, const RecvDesc* __restrict__ recv,
                                                    const int* __restrict__ e_src, const int8_t* __restrict__ e_off,
                                                    const typename Store<S>::cx* __restrict__ Phi,
@@ -1000,15 +1056,22 @@ __global__ __launch_bounds__(256) void k_translate(int q, int n1, int nrecv, con
                 F[j][1] += pr * vi + pi * vr;
             }
         }
-        const int mm = m1 * m1 + m2 * m2 + m3 * m3;
-        const double w = mm > 0 ? wdiff[mm] * lscale : 0.0;
-        const double inv = mm > 0 ? 1.0 / mm : 0.0;
-        const double dr = (m1 * F[0][0] + m2 * F[1][0] + m3 * F[2][0]) * inv;
-        const double di = (m1 * F[0][1] + m2 * F[1][1] + m3 * F[2][1]) * inv;
-        const int mv[3] = {m1, m2, m3};
+        if (PLAIN) {
+            // the symbol was applied on the sending side (stresslet)
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
-            tile[(j * n1 + i3) * q + m1] = cplx{w * (F[j][0] - mv[j] * dr), w * (F[j][1] - mv[j] * di)};
+            for (int j = 0; j < 3; ++j)
+                tile[(j * n1 + i3) * q + m1] = cplx{F[j][0], F[j][1]};
+        } else {
+            const int mm = m1 * m1 + m2 * m2 + m3 * m3;
+            const double w = mm > 0 ? wdiff[mm] * lscale : 0.0;
+            const double inv = mm > 0 ? 1.0 / mm : 0.0;
+            const double dr = (m1 * F[0][0] + m2 * F[1][0] + m3 * F[2][0]) * inv;
+            const double di = (m1 * F[0][1] + m2 * F[1][1] + m3 * F[2][1]) * inv;
+            const int mv[3] = {m1, m2, m3};
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                tile[(j * n1 + i3) * q + m1] = cplx{w * (F[j][0] - mv[j] * dr), w * (F[j][1] - mv[j] * di)};
+        }
     }
     __syncthreads();
     typename Store<S>::cx* out = Psi + (size_t)rd.slot * 3 * H;
@@ -1023,7 +1086,7 @@ __global__ __launch_bounds__(256) void k_translate(int q, int n1, int nrecv, con
 }
 
 void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int* e_src, const int8_t* e_off,
-                      const void* Phi, const double* wdiff, void* Psi, bool f32, hipStream_t s)
+                      const void* Phi, const double* wdiff, void* Psi, bool f32, bool plain, hipStream_t s)
 {
     if (nrecv == 0)
         return;
@@ -1031,18 +1094,101 @@ void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int*
     const int total = n1 * nrecv;
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void*)k_translate<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void*)k_translate<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   160 * 1024);
-        (void)hipFuncSetAttribute((const void*)k_translate<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void*)k_translate<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        (void)hipFuncSetAttribute((const void*)k_translate<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        (void)hipFuncSetAttribute((const void*)k_translate<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   160 * 1024);
         attr = true;
     }
-    if (f32)
-        hipLaunchKernelGGL(k_translate<float>, dim3(xcd_grid(total)), dim3(256), lds, s, q, n1, nrecv, recv, e_src,
-                           e_off, (const float2*)Phi, wdiff, (float2*)Psi);
-    else
-        hipLaunchKernelGGL(k_translate<double>, dim3(xcd_grid(total)), dim3(256), lds, s, q, n1, nrecv, recv, e_src,
-                           e_off, (const double2*)Phi, wdiff, (double2*)Psi);
+#define L_TR(T2, S, PL)                                                                                        \
+    hipLaunchKernelGGL((k_translate<S, PL>), dim3(xcd_grid(total)), dim3(256), lds, s, q, n1, nrecv, recv, e_src, \
+                       e_off, (const T2*)Phi, wdiff, (T2*)Psi)
+    if (f32) {
+        if (plain)
+            L_TR(float2, float, true);
+        else
+            L_TR(float2, float, false);
+    } else {
+        if (plain)
+            L_TR(double2, double, true);
+        else
+            L_TR(double2, double, false);
+    }
+#undef L_TR
+}
+
+// Stresslet difference symbol applied on the sending side (the 6 -> 3
+// contraction, eq. moll_stresslet): for each sender slot and mode m (x-major
+// half spectrum), u_j = i w [m^2 (2 (rho m)_j + m_j tr rho) - 2 m_j m.rho.m],
+// w = 4^level wdiff_t(|m|^2), rho the symmetric density with the
+// off-diagonal pairs stored summed.
+template <typename S>
+__global__ __launch_bounds__(256) void k_stress_symbol(int q, int n1, const int* __restrict__ send_level,
+                                                       const typename Store<S>::cx* __restrict__ Phi6,
+                                                       const double* __restrict__ wdiff_t,
+                                                       typename Store<S>::cx* __restrict__ Phi3)
+{
+    const int H = q * n1 * n1;
+    const int mi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (mi >= H)
+        return;
+    const int snd = blockIdx.y;
+    const int m1 = mi / (n1 * n1);
+    const int rem = mi - m1 * n1 * n1;
+    const int m2 = rem / n1 - (q - 1), m3 = rem % n1 - (q - 1);
+    const int mm = m1 * m1 + m2 * m2 + m3 * m3;
+    const double w = mm > 0 ? wdiff_t[mm] * (double)(1ll << (2 * send_level[snd])) : 0.0;
+    const typename Store<S>::cx* in = Phi6 + (size_t)snd * 6 * H + mi;
+    double rr[6], ri[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const typename Store<S>::cx v = in[(size_t)c * H];
+        rr[c] = (double)v.x;
+        ri[c] = (double)v.y;
+    }
+    const double m[3] = {(double)m1, (double)m2, (double)m3};
+    auto apply = [&](const double* g, double* u) {
+        // symmetric matrix from (11, 22, 33, 12+21, 13+31, 23+32)
+        const double a11 = g[0], a22 = g[1], a33 = g[2], a12 = 0.5 * g[3], a13 = 0.5 * g[4], a23 = 0.5 * g[5];
+        const double rm0 = a11 * m[0] + a12 * m[1] + a13 * m[2];
+        const double rm1 = a12 * m[0] + a22 * m[1] + a23 * m[2];
+        const double rm2 = a13 * m[0] + a23 * m[1] + a33 * m[2];
+        const double tr = a11 + a22 + a33;
+        const double mrm = m[0] * rm0 + m[1] * rm1 + m[2] * rm2;
+        u[0] = mm * (2.0 * rm0 + m[0] * tr) - 2.0 * m[0] * mrm;
+        u[1] = mm * (2.0 * rm1 + m[1] * tr) - 2.0 * m[1] * mrm;
+        u[2] = mm * (2.0 * rm2 + m[2] * tr) - 2.0 * m[2] * mrm;
+    };
+    double ur[3], ui[3];
+    apply(rr, ur);
+    apply(ri, ui);
+    typename Store<S>::cx* out = Phi3 + (size_t)snd * 3 * H + mi;
+    // multiplication by i w: (re, im) -> (-w im, w re)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        out[(size_t)j * H] = {(S)(-w * ui[j]), (S)(w * ur[j])};
+}
+
+void launch_stress_symbol(int q, int n1, int nsend, const int* send_level, const void* Phi6, const double* wdiff_t,
+                          void* Phi3, bool f32, hipStream_t s)
+{
+    if (nsend == 0)
+        return;
+    const size_t H = (size_t)q * n1 * n1;
+    for (int s0 = 0; s0 < nsend; s0 += kMaxGridY) {
+        const dim3 grid(nblocks((int64_t)H, 256), std::min(kMaxGridY, nsend - s0));
+        if (f32)
+            hipLaunchKernelGGL(k_stress_symbol<float>, grid, dim3(256), 0, s, q, n1, send_level + s0,
+                               (const float2*)Phi6 + (size_t)s0 * 6 * H, wdiff_t, (float2*)Phi3 + (size_t)s0 * 3 * H);
+        else
+            hipLaunchKernelGGL(k_stress_symbol<double>, grid, dim3(256), 0, s, q, n1, send_level + s0,
+                               (const double2*)Phi6 + (size_t)s0 * 6 * H, wdiff_t,
+                               (double2*)Phi3 + (size_t)s0 * 3 * H);
+    }
 }
 
 template <typename S>
@@ -1080,13 +1226,80 @@ __global__ __launch_bounds__(256) void k_root_symbol(int mh, int mf, const typen
 void launch_root_symbol(int mh, int mf, int nroot, const void* Phi, const double* w, void* Psi, bool f32,
                         hipStream_t s)
 {
+    const size_t H = (size_t)mh * mf * mf;
+    for (int r0 = 0; r0 < nroot; r0 += kMaxGridY) {
+        const dim3 grid(nblocks((int64_t)H, 256), std::min(kMaxGridY, nroot - r0));
+        if (f32)
+            hipLaunchKernelGGL(k_root_symbol<float>, grid, dim3(256), 0, s, mh, mf,
+                               (const float2*)Phi + (size_t)r0 * 3 * H, w, (float2*)Psi + (size_t)r0 * 3 * H);
+        else
+            hipLaunchKernelGGL(k_root_symbol<double>, grid, dim3(256), 0, s, mh, mf,
+                               (const double2*)Phi + (size_t)r0 * 3 * H, w, (double2*)Psi + (size_t)r0 * 3 * H);
+    }
+}
+
+// Stresslet root symbol (truncated kernel, eq. moll_stresslet with Bhat^R):
+// Phi6 x-major [6][mx][my][mz] -> Psi3 z-major [3][mz][my][mx],
+// u_j = i w(|m|^2) [k^2 (2 (rho k)_j + k_j tr rho) - 2 k_j k.rho.k], k = kscale m.
+template <typename S>
+__global__ __launch_bounds__(256) void k_root_symbol_t(int mh, int mf, const typename Store<S>::cx* __restrict__ Phi,
+                                                       const double* __restrict__ w, double kscale,
+                                                       typename Store<S>::cx* __restrict__ Psi)
+{
     const int H = mh * mf * mf;
-    if (f32)
-        hipLaunchKernelGGL(k_root_symbol<float>, dim3(nblocks(H, 256), nroot), dim3(256), 0, s, mh, mf,
-                           (const float2*)Phi, w, (float2*)Psi);
-    else
-        hipLaunchKernelGGL(k_root_symbol<double>, dim3(nblocks(H, 256), nroot), dim3(256), 0, s, mh, mf,
-                           (const double2*)Phi, w, (double2*)Psi);
+    const int mi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (mi >= H)
+        return;
+    Phi += (size_t)blockIdx.y * 6 * H;
+    Psi += (size_t)blockIdx.y * 3 * H;
+    const int M = (mf - 1) / 2;
+    const int m1 = mi / (mf * mf);
+    const int rem = mi - m1 * mf * mf;
+    const int m2 = rem / mf - M, m3 = rem % mf - M;
+    const int mm = m1 * m1 + m2 * m2 + m3 * m3;
+    const double ww = mm > 0 ? w[mm] : 0.0;
+    const double k[3] = {kscale * m1, kscale * m2, kscale * m3};
+    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    double gr[6], gi[6];
+    for (int c = 0; c < 6; ++c) {
+        const typename Store<S>::cx v = Phi[(size_t)c * H + mi];
+        gr[c] = (double)v.x;
+        gi[c] = (double)v.y;
+    }
+    auto apply = [&](const double* g, double* u) {
+        const double a11 = g[0], a22 = g[1], a33 = g[2], a12 = 0.5 * g[3], a13 = 0.5 * g[4], a23 = 0.5 * g[5];
+        const double rk0 = a11 * k[0] + a12 * k[1] + a13 * k[2];
+        const double rk1 = a12 * k[0] + a22 * k[1] + a23 * k[2];
+        const double rk2 = a13 * k[0] + a23 * k[1] + a33 * k[2];
+        const double tr = a11 + a22 + a33;
+        const double krk = k[0] * rk0 + k[1] * rk1 + k[2] * rk2;
+        u[0] = k2 * (2.0 * rk0 + k[0] * tr) - 2.0 * k[0] * krk;
+        u[1] = k2 * (2.0 * rk1 + k[1] * tr) - 2.0 * k[1] * krk;
+        u[2] = k2 * (2.0 * rk2 + k[2] * tr) - 2.0 * k[2] * krk;
+    };
+    double ur[3], ui[3];
+    apply(gr, ur);
+    apply(gi, ui);
+    const size_t mo = ((size_t)(m3 + M) * mf + (m2 + M)) * mh + m1;
+    for (int j = 0; j < 3; ++j)
+        Psi[(size_t)j * H + mo] = {(S)(-ww * ui[j]), (S)(ww * ur[j])};
+}
+
+void launch_root_symbol_t(int mh, int mf, int nroot, const void* Phi, const double* w, double kscale, void* Psi,
+                          bool f32, hipStream_t s)
+{
+    const size_t H = (size_t)mh * mf * mf;
+    for (int r0 = 0; r0 < nroot; r0 += kMaxGridY) {
+        const dim3 grid(nblocks((int64_t)H, 256), std::min(kMaxGridY, nroot - r0));
+        if (f32)
+            hipLaunchKernelGGL(k_root_symbol_t<float>, grid, dim3(256), 0, s, mh, mf,
+                               (const float2*)Phi + (size_t)r0 * 6 * H, w, kscale,
+                               (float2*)Psi + (size_t)r0 * 3 * H);
+        else
+            hipLaunchKernelGGL(k_root_symbol_t<double>, grid, dim3(256), 0, s, mh, mf,
+                               (const double2*)Phi + (size_t)r0 * 6 * H, w, kscale,
+                               (double2*)Psi + (size_t)r0 * 3 * H);
+    }
 }
 
 // ---- near field -----------------------------------------------------------------
@@ -1167,6 +1380,39 @@ __device__ inline void residual_pair_multi(double xt, double yt, double zt, cons
     }
 }
 
+// Residual stresslet pair (eq. res_stresslet with R_Tdiag, R_Toffd of eq.
+// T-offd, rearranged around the free-space stresslet): with d = x_t - x_s,
+// s = |d|^2 / r_lambda^2, A and D the radial polynomials (poly.P, poly.Q),
+//   u += [-(3/4pi) (d.f)(d.n)/|d|^5 + cA A(s) (d.f)(d.n) + cD D(s) (f.n)] d
+//        + cD D(s) [(d.n) f + (d.f) n],
+// cA = 3/(2 pi r_lambda^5), cD = 1/(4 pi r_lambda^3).  v holds the source as
+// (x, y, z, f, n, f.n).  Every term is proportional to d, so a pair at r = 0
+// contributes nothing (the stresslet has no self term).
+template <int ND>
+__device__ inline void residual_pair_stresslet(double xt, double yt, double zt, const double* v, double rl2,
+                                               double tw, double cA, double cD, const RadialPoly& poly,
+                                               double (&u)[1][3])
+{
+    const double dx = xt - v[0], dy = yt - v[1], dz = zt - v[2];
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    if (r2 < rl2) {
+        const double rinv = r2 > 0.0 ? rsqrt_f64(r2) : 0.0;
+        const double rinv2 = rinv * rinv;
+        const double t = fma(r2, tw, -1.0);
+        const double A = horner<ND>(poly.P, t);
+        const double D = horner<ND>(poly.Q, t);
+        const double df = fma(dx, v[3], fma(dy, v[4], dz * v[5]));
+        const double dn = fma(dx, v[6], fma(dy, v[7], dz * v[8]));
+        const double c2 = cD * D;
+        const double c1 = df * dn * fma(cA, A, -k3Over4Pi * rinv2 * rinv2 * rinv);
+        const double cy = fma(c2, v[9], c1);
+        const double a = c2 * dn, b = c2 * df;
+        u[0][0] = fma(cy, dx, fma(a, v[3], fma(b, v[6], u[0][0])));
+        u[0][1] = fma(cy, dy, fma(a, v[4], fma(b, v[7], u[0][1])));
+        u[0][2] = fma(cy, dz, fma(a, v[5], fma(b, v[8], u[0][2])));
+    }
+}
+
 // One wave per target group of TG = 64/SG points of a leaf; lane (t, s) handles
 // target t against every SG-th queued source.  Source leaves of the near list
 // are walked in 64-point chunks: a chunk whose bounding box lies farther than
@@ -1176,8 +1422,9 @@ __device__ inline void residual_pair_multi(double xt, double yt, double zt, cons
 // LDS and evaluated at once.  Every batch size visits sources in the same
 // order, so a force vector's result does not depend on how it was batched.
 // The SG partial sums of a target are combined by cross-lane shuffles.
-// Forces and outputs are [NR][3][n].
-template <int ND, int SG, int NR>
+// Forces and outputs are [NR][3][n].  KER = 1: the stresslet (NR = 1), with
+// the sources' f and n as fs[6][n].
+template <int ND, int SG, int NR, int KER>
 __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, int nwork,
                                              const NearLeaf* __restrict__ leaves,
                                              const NearEntryDev* __restrict__ entries, const double* __restrict__ cbbox,
@@ -1186,7 +1433,8 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
                                              RadialPoly poly, double* __restrict__ u)
 {
     constexpr int TG = 64 / SG;
-    constexpr int W2 = (3 + 3 * NR + 1) / 2;  // double2 per staged source
+    constexpr int NV = KER == 1 ? 7 : 3 * NR;  // staged values per source beyond its position
+    constexpr int W2 = (3 + NV + 1) / 2;       // double2 per staged source
     __shared__ double2 S[64][W2];
     const NearWork w = work[blockIdx.x];
     const NearLeaf T = leaves[w.leaf];
@@ -1215,8 +1463,9 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
         const double rl = 1.0 / (double)(1ll << E.lambda);
         const double rl2 = rl * rl;
         const double tw = 2.0 / rl2;
-        const double cP = 1.0 / (4.0 * kPi * rl);
-        const double cQ = cP / rl2;
+        // Stokeslet: cP = 1/(4 pi r_l), cQ = cP / r_l^2; stresslet: cA, cD
+        const double cP = KER == 1 ? 3.0 / (2.0 * kPi * rl2 * rl2 * rl) : 1.0 / (4.0 * kPi * rl);
+        const double cQ = KER == 1 ? 1.0 / (4.0 * kPi * rl2 * rl) : cP / rl2;
         const double sh[3] = {(double)E.sx, (double)E.sy, (double)E.sz};
         const int nch = (int)((E.send - E.sstart + 63) / 64);
         for (int k = 0; k < nch; ++k) {
@@ -1255,10 +1504,17 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
                 v[0] = sx;
                 v[1] = sy;
                 v[2] = sz;
+                if (KER == 1) {
 #pragma unroll
-                for (int c = 0; c < 3 * NR; ++c)
-                    v[3 + c] = fs[(size_t)c * n + j];
-                if (2 * W2 > 3 + 3 * NR)
+                    for (int c = 0; c < 6; ++c)
+                        v[3 + c] = fs[(size_t)c * n + j];
+                    v[9] = fma(v[3], v[6], fma(v[4], v[7], v[5] * v[8]));
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3 * NR; ++c)
+                        v[3 + c] = fs[(size_t)c * n + j];
+                }
+                if (2 * W2 > 3 + NV)
                     v[2 * W2 - 1] = 0.0;
 #pragma unroll
                 for (int c = 0; c < W2; ++c)
@@ -1273,7 +1529,10 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
                     v[2 * c] = t2.x;
                     v[2 * c + 1] = t2.y;
                 }
-                residual_pair_multi<ND, NR>(xt, yt, zt, v, rl2, tw, cP, cQ, poly, acc);
+                if constexpr (KER == 1)
+                    residual_pair_stresslet<ND>(xt, yt, zt, v, rl2, tw, cP, cQ, poly, acc);
+                else
+                    residual_pair_multi<ND, NR>(xt, yt, zt, v, rl2, tw, cP, cQ, poly, acc);
             }
         }
     }
@@ -1306,18 +1565,28 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
         MACRO(24);                 \
     }
 
-void launch_near(int sg, int nr, const NearWork* work, int nwork, const NearLeaf* leaves,
+void launch_near(int kernel, int sg, int nr, const NearWork* work, int nwork, const NearLeaf* leaves,
                  const NearEntryDev* entries, const double* cbbox, const double* x, const double* y, const double* z,
                  const double* fs, int64_t n, const RadialPoly& poly, double* u, hipStream_t s)
 {
     if (nwork == 0)
         return;
-#define L_NEAR_K(ND, SG, NR)                                                                                      \
-    hipLaunchKernelGGL((k_near<ND, SG, NR>), dim3(nwork), dim3(64), 0, s, work, nwork, leaves, entries, cbbox, x, \
-                       y, z, fs, n, poly, u)
+#define L_NEAR_KK(ND, SG, NR, KER)                                                                             \
+    hipLaunchKernelGGL((k_near<ND, SG, NR, KER>), dim3(nwork), dim3(64), 0, s, work, nwork, leaves, entries, \
+                       cbbox, x, y, z, fs, n, poly, u)
+#define L_NEAR_K(ND, SG, NR) L_NEAR_KK(ND, SG, NR, 0)
     // batches of several force vectors always use 4 source lanes per target
 #define L_NEAR(ND)                   \
-    if (nr == 2) {                   \
+    if (kernel == 1) {               \
+        if (sg == 1)                 \
+            L_NEAR_KK(ND, 1, 1, 1);  \
+        else if (sg == 2)            \
+            L_NEAR_KK(ND, 2, 1, 1);  \
+        else if (sg == 4)            \
+            L_NEAR_KK(ND, 4, 1, 1);  \
+        else                         \
+            L_NEAR_KK(ND, 8, 1, 1);  \
+    } else if (nr == 2) {            \
         L_NEAR_K(ND, 4, 2);          \
     } else if (nr == 4) {            \
         L_NEAR_K(ND, 4, 4);          \
@@ -1335,6 +1604,7 @@ void launch_near(int sg, int nr, const NearWork* work, int nwork, const NearLeaf
     DMK_ND_DISPATCH(poly.nd, L_NEAR)
 #undef L_NEAR
 #undef L_NEAR_K
+#undef L_NEAR_KK
 }
 
 template <int SG>
@@ -1446,6 +1716,50 @@ __global__ __launch_bounds__(64) void k_residual_direct(const double* __restrict
     }
 }
 
+// stresslet: sf = (f, n) as [6][ns]
+template <int ND>
+__global__ __launch_bounds__(64) void k_residual_direct_t(const double* __restrict__ tx,
+                                                          const double* __restrict__ ty,
+                                                          const double* __restrict__ tz, int64_t m,
+                                                          const double* __restrict__ sx,
+                                                          const double* __restrict__ sy,
+                                                          const double* __restrict__ sz,
+                                                          const double* __restrict__ sf, int64_t ns, double rl,
+                                                          RadialPoly poly, double* __restrict__ u)
+{
+    const int64_t i = blockIdx.x * (int64_t)64 + threadIdx.x;
+    const bool valid = i < m;
+    const double xt = valid ? tx[i] : 0.0, yt = valid ? ty[i] : 0.0, zt = valid ? tz[i] : 0.0;
+    const double rl2 = rl * rl;
+    const double cA = 3.0 / (2.0 * kPi * rl2 * rl2 * rl), cD = 1.0 / (4.0 * kPi * rl2 * rl);
+    double acc[1][3] = {{0, 0, 0}};
+    for (int64_t j = 0; j < ns; ++j) {
+        double v[10] = {sx[j], sy[j], sz[j]};
+        for (int c = 0; c < 6; ++c)
+            v[3 + c] = sf[(size_t)c * ns + j];
+        v[9] = fma(v[3], v[6], fma(v[4], v[7], v[5] * v[8]));
+        residual_pair_stresslet<ND>(xt, yt, zt, v, rl2, 2.0 / rl2, cA, cD, poly, acc);
+    }
+    if (valid) {
+        u[3 * i] = acc[0][0];
+        u[3 * i + 1] = acc[0][1];
+        u[3 * i + 2] = acc[0][2];
+    }
+}
+
+void launch_residual_direct_t(const double* tx, const double* ty, const double* tz, int64_t m, const double* sx,
+                              const double* sy, const double* sz, const double* sf, int64_t ns, double r_lambda,
+                              const RadialPoly& poly, double* u, hipStream_t s)
+{
+    if (m == 0)
+        return;
+#define L_RES(ND)                                                                                                 \
+    hipLaunchKernelGGL(k_residual_direct_t<ND>, dim3(nblocks(m, 64)), dim3(64), 0, s, tx, ty, tz, m, sx, sy, sz, \
+                       sf, ns, r_lambda, poly, u)
+    DMK_ND_DISPATCH(poly.nd, L_RES)
+#undef L_RES
+}
+
 void launch_residual_direct(const double* tx, const double* ty, const double* tz, int64_t m, const double* sx,
                             const double* sy, const double* sz, const double* sf, int64_t ns, double r_lambda,
                             const RadialPoly& poly, double* u, hipStream_t s)
@@ -1498,8 +1812,8 @@ void launch_sum_root(const void* Q, const int* root_fid, int nroot, int p3, doub
 // undoes that problem's unit-box map, c_b its free-space constant (or none).
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ u, int64_t n, const int* __restrict__ perm,
                                                   int64_t tofs, const int* __restrict__ pid,
-                                                  const double* __restrict__ scale, const double* __restrict__ cst,
-                                                  double* __restrict__ vel)
+                                                  const double* __restrict__ scale, int sq,
+                                                  const double* __restrict__ cst, double* __restrict__ vel)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n)
@@ -1509,7 +1823,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ u, 
     if (o < 0)
         return;
     const int b = pid ? pid[i] : 0;
-    const double sc = scale[b];
+    const double sc = sq ? scale[b] * scale[b] : scale[b];
     const double c0 = cst ? cst[3 * b] : 0.0, c1 = cst ? cst[3 * b + 1] : 0.0, c2 = cst ? cst[3 * b + 2] : 0.0;
     vel[3 * o] = sc * (u[i] + c0);
     vel[3 * o + 1] = sc * (u[n + i] + c1);
@@ -1517,9 +1831,10 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ u, 
 }
 
 void launch_finalize(const double* u, int64_t n, const int* perm, int64_t tofs, const int* pid, const double* scale,
-                     const double* cst, double* vel, hipStream_t s)
+                     int sq, const double* cst, double* vel, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(nblocks(n, 256)), dim3(256), 0, s, u, n, perm, tofs, pid, scale, cst, vel);
+    hipLaunchKernelGGL(k_finalize, dim3(nblocks(n, 256)), dim3(256), 0, s, u, n, perm, tofs, pid, scale, sq, cst,
+                       vel);
 }
 
 __global__ __launch_bounds__(256) void k_zero(uint32_t* __restrict__ p, size_t count)

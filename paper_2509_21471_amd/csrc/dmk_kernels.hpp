@@ -40,6 +40,9 @@ void launch_chunk_bbox(const double* x, const double* y, const double* z, const 
 // forces (n,3) original order -> sorted SoA fs[3][n]
 // points with input index < nsrc carry forces, the others (targets only) zero
 void launch_gather_forces(const double* f, int64_t n, int64_t nsrc, const int* perm, double* fs, hipStream_t s);
+// stresslet: rho[6][n] symmetric densities of f n^T (off-diagonal pairs summed), fn[6][n] = (f, n)
+void launch_gather_stresslet(const double* f, const double* nv, int64_t n, int64_t nsrc, const int* perm, double* rho,
+                             double* fn, hipStream_t s);
 
 struct LeafDesc {
     int fid;          // far-field slot of the leaf
@@ -56,7 +59,8 @@ bool p_supported(int p);
 void launch_lagrange_table(int p, const LeafDesc* leaves, int nleaf, const double* x, const double* y,
                            const double* z, const double* cheb_t, const double* cheb_w, double* Ltab, hipStream_t s);
 // proxy charges of leaves (Step 2a): Q[fid][j][a][b][c] = sum_pt L_a L_b L_c f_j
-void launch_anterp(int p, const LeafDesc* leaves, int nleaf, const double* Ltab, const double* fs, int64_t n,
+// nc = 3 (Stokeslet forces) or 6 (stresslet densities); Q[fid][nc][a][b][c]
+void launch_anterp(int p, int nc, const LeafDesc* leaves, int nleaf, const double* Ltab, const double* fs, int64_t n,
                    void* Q, bool f32, hipStream_t s);
 // far-field value at the points (final interpolation), V z-major V[fid][j][c][b][a]:
 // u[j][i] = sum V L L L, over chunks of at most eval_chunk_points(p) points of
@@ -100,6 +104,8 @@ struct StageArgs {
     int p;               // proxy order (gather / scatter addressing)
     const int* child_fid;// 8 per slot (gather / scatter)
     int f32;             // X and Y hold float (else double); arithmetic is FP64
+    int ncomp = 3;       // components per slot (3; 6 for stresslet densities)
+    int slot0 = 0;       // first slot of the launch (slots [slot0, nslots))
 };
 void launch_stage(int mode, int io, const StageArgs& a, hipStream_t s);
 
@@ -110,13 +116,20 @@ struct RecvDesc {
     int ebeg, eend;   // entries in the entry arrays
 };
 // Phi / Psi hold complex float (f32) or complex double
+// plain: the symbol was applied on the sending side (phases only here)
 void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int* e_src /*sender slot*/,
                       const int8_t* e_off /*3 per entry*/, const void* Phi, const double* wdiff, void* Psi, bool f32,
-                      hipStream_t s);
+                      bool plain, hipStream_t s);
+// stresslet difference symbol per sender: Phi6[slot][6][H] -> Phi3[slot][3][H] (x-major half spectrum)
+void launch_stress_symbol(int q, int n1, int nsend, const int* send_level, const void* Phi6, const double* wdiff_t,
+                          void* Phi3, bool f32, hipStream_t s);
 // root symbol multiply: Psi[j][mz][my][mx] = w(|m|^2) (I - m m^T/|m|^2) Phi[j][mx][my][mz]
 // one root per problem: Phi / Psi hold nroot consecutive [3][H] grids
 void launch_root_symbol(int mh, int mf, int nroot, const void* Phi, const double* w, void* Psi, bool f32,
                         hipStream_t s);
+// stresslet root symbol: Phi[nroot][6][H] x-major -> Psi[nroot][3][H] z-major, k = kscale m
+void launch_root_symbol_t(int mh, int mf, int nroot, const void* Phi, const double* w, double kscale, void* Psi,
+                          bool f32, hipStream_t s);
 
 // near field (Step 4); the self term comes out of the r = 0 pair
 struct NearLeaf {
@@ -140,9 +153,11 @@ struct RadialPoly {
     int nd;
     double P[24], Q[24];
 };
-// sg: source lanes per target (1, 2, 4); a wave holds 64/sg targets
-// forces and outputs [nr][3][n]; nr in {1, 2, 4, 8}
-void launch_near(int sg, int nr, const NearWork* work, int nwork, const NearLeaf* leaves,
+// sg: source lanes per target (1, 2, 4, 8); a wave holds 64/sg targets
+// kernel 0 (Stokeslet): forces and outputs [nr][3][n]; nr in {1, 2, 4, 8}
+// kernel 1 (stresslet): fs = (f, n) as [6][n], output [3][n], nr = 1;
+// poly holds the stresslet's radial functions A (P) and D (Q)
+void launch_near(int kernel, int sg, int nr, const NearWork* work, int nwork, const NearLeaf* leaves,
                  const NearEntryDev* entries, const double* cbbox, const double* x, const double* y, const double* z,
                  const double* fs, int64_t n, const RadialPoly& poly, double* u, hipStream_t s);
 
@@ -155,15 +170,19 @@ void launch_near_count(int sg, const NearWork* work, int nwork, const NearLeaf* 
 void launch_residual_direct(const double* tx, const double* ty, const double* tz, int64_t m, const double* sx,
                             const double* sy, const double* sz, const double* sf, int64_t ns, double r_lambda,
                             const RadialPoly& poly, double* u, hipStream_t s);
+// the same for the residual stresslet, sf = (f, n) as [6][ns]
+void launch_residual_direct_t(const double* tx, const double* ty, const double* tz, int64_t m, const double* sx,
+                              const double* sy, const double* sz, const double* sf, int64_t ns, double r_lambda,
+                              const RadialPoly& poly, double* u, hipStream_t s);
 
 // out[j] = coef * sum of the root proxy charges (equals coef * net force)
 // out[3r + j] = coef * sum_k Q[root_fid[r]][j][k]
 void launch_sum_root(const void* Q, const int* root_fid, int nroot, int p3, double coef, double* out, bool f32,
                      hipStream_t s);
 // per point of problem b with input index o >= tofs (the points with an output):
-// vel[o - tofs] = scale[b] * (u + cst[3b..]) (cst may be NULL)
+// vel[o - tofs] = scale[b]^(sq ? 2 : 1) * (u + cst[3b..]) (cst may be NULL)
 void launch_finalize(const double* u, int64_t n, const int* perm, int64_t tofs, const int* pid, const double* scale,
-                     const double* cst, double* vel, hipStream_t s);
+                     int sq, const double* cst, double* vel, hipStream_t s);
 // zero `bytes` (a multiple of 4) at p
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 

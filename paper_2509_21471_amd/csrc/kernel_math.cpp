@@ -37,15 +37,28 @@ const Row kRows[4] = {
 // the compiled proxy kernels).  As for the prolate 1e-9 row, p^G = 28 at 1e-6
 // leaves periodic and clustered inputs at or above the tolerance and is
 // stepped up to 30 (q unchanged).
+// Stresslet columns (prolate) of the same table.  Measured against direct
+// sums on uniform and clustered inputs with 3 to 9 levels, every printed p
+// leaves errors of 1.0 to 1.4 times the tolerance on some input (the
+// interpolation term again: raising q makes it worse, raising p removes it),
+// so each row runs one compiled order up: 12, 23, 36 and 48 (q unchanged).
+const Row kRowsT[4] = {
+    {1e-3, 9, 11, 17, 3, 600, 12},
+    {1e-6, 17, 22, 33, 5, 1200, 23},
+    {1e-9, 25, 33, 49, 9, 2000, 36},
+    {1e-12, 32, 44, 63, 11, 3000, 48},
+};
 const Row kRowsG[2] = {
     {1e-3, 14, 14, 27, 5, 600, 14},
     {1e-6, 25, 28, 49, 9, 1200, 30},
 };
 }  // namespace
 
-bool select_params(double tol, Params* out, int window)
+bool select_params(double tol, Params* out, int window, int kernel)
 {
-    const Row* rows = window == 1 ? kRowsG : kRows;
+    if (kernel == 1 && window != 0)
+        return false;
+    const Row* rows = kernel == 1 ? kRowsT : (window == 1 ? kRowsG : kRows);
     const int nrow = window == 1 ? 2 : 4;
     const double tmin = window == 1 ? 1e-6 : 1e-12;
     if (!(tol >= tmin * (1 - 1e-9) && tol <= 1e-3 * (1 + 1e-9)))
@@ -63,6 +76,7 @@ bool select_params(double tol, Params* out, int window)
     }
     const int q = rows[hit].q;
     out->tol = tol;
+    out->kernel = kernel;
     out->window = window;
     out->q = q;
     out->c = q * kPi / 3.0;
@@ -405,6 +419,78 @@ RadialFits fit_radial(const Window& w, double fit_tol)
     return out;
 }
 
+RadialFits fit_radial_stresslet(const Window& w, double fit_tol)
+{
+    // psi(sigma) = phi'(r)/r, r = sqrt(sigma), smooth in sigma (phi is even);
+    // A(s) = (1/s) int_0^1 u^2 [psi(s) - psi(s u^2)] du (from E - G =
+    // -rho^2 int_0^1 u^2 psi(s u^2) du and rho phi'(rho)/3 = rho^2 psi(s)/3,
+    // no cancellation at small s), D(s) = -psi(s).
+    std::vector<double> gx, gw;
+    gauss_legendre(120, gx, gw);
+    for (size_t i = 0; i < gx.size(); ++i) {
+        gx[i] = 0.5 * (gx[i] + 1.0);
+        gw[i] *= 0.5;
+    }
+    auto psi = [&](double sig) {
+        const double r = std::sqrt(sig);
+        return w.dphi(r) / r;
+    };
+    auto AD = [&](double s, double* A, double* D) {
+        const double ps = psi(s);
+        double acc = 0;
+        for (size_t i = 0; i < gx.size(); ++i)
+            acc += gw[i] * gx[i] * gx[i] * (ps - psi(s * gx[i] * gx[i]));
+        *A = acc / s;
+        *D = -ps;
+    };
+    const int N = 96;
+    std::vector<double> fa(N), fd(N);
+    for (int j = 0; j < N; ++j) {
+        const double s = 0.5 * (1.0 + std::cos((2.0 * j + 1) * kPi / (2.0 * N)));
+        AD(s, &fa[j], &fd[j]);
+    }
+    auto coeffs = [&](const std::vector<double>& f) {
+        std::vector<double> a(N);
+        for (int k = 0; k < N; ++k) {
+            double acc = 0;
+            for (int j = 0; j < N; ++j)
+                acc += f[j] * std::cos(k * (2.0 * j + 1) * kPi / (2.0 * N));
+            a[k] = (k == 0 ? 1.0 : 2.0) * acc / N;
+        }
+        return a;
+    };
+    auto trunc = [&](std::vector<double> a, double scale) {
+        const double thr = std::max(fit_tol, 2e-14) * scale;
+        int d = (int)a.size() - 1;
+        for (int k = 1; k + 8 < (int)a.size(); ++k) {
+            bool small = true;
+            for (int j = k; j < k + 8; ++j)
+                small = small && std::fabs(a[j]) < thr;
+            if (small) {
+                d = k - 1;
+                break;
+            }
+        }
+        a.resize(d + 1);
+        return a;
+    };
+    double scale = 1.0;
+    for (int j = 0; j < N; ++j)
+        scale = std::max({scale, std::fabs(fa[j]), std::fabs(fd[j])});
+    RadialFits out;
+    out.P.a = trunc(coeffs(fa), scale);
+    out.Q.a = trunc(coeffs(fd), scale);
+    out.max_err_P = out.max_err_Q = 0;
+    for (int j = 0; j <= 200; ++j) {
+        const double s = j / 200.0 * (1 - 1e-12) + 1e-12;
+        double A, D;
+        AD(s, &A, &D);
+        out.max_err_P = std::max(out.max_err_P, std::fabs(out.P.eval(s) - A));
+        out.max_err_Q = std::max(out.max_err_Q, std::fabs(out.Q.eval(s) - D));
+    }
+    return out;
+}
+
 void cheb_nodes(int p, std::vector<double>& t, std::vector<double>& bw)
 {
     t.resize(p);
@@ -510,7 +596,7 @@ Tables* build_tables(const Params& prm)
     GaussWindow wg(prm.sigma > 0 ? prm.sigma : 1.0);
     const Window& w = prm.window == 1 ? (const Window&)wg : (const Window&)wp;
     T->phi0 = w.phi(0.0);
-    T->fits = fit_radial(w, 1e-3 * tol);
+    T->fits = prm.kernel == 1 ? fit_radial_stresslet(w, 1e-3 * tol) : fit_radial(w, 1e-3 * tol);
     const int p = prm.p, q = prm.q;
     std::vector<double> t, bw;
     cheb_nodes(p, t, bw);
@@ -533,6 +619,13 @@ Tables* build_tables(const Params& prm)
         const double m = std::sqrt((double)m2);
         T->wdiff[m2] = (w.gammahat(kPi * m / 3.0) - w.gammahat(2.0 * kPi * m / 3.0)) / (12.0 * kPi * kPi * m2);
     }
+    // stresslet difference symbol i [(m_m d_jl + m_j d_lm + m_l d_mj) m^2 - 2 m_j m_l m_m] W_t(|m|),
+    // from eq. moll_stresslet at k = h_l m with weight (h_l / 2 pi)^3: W_t = dgammahat / (18 pi |m|^4) / r_l^2
+    T->wdiff_t.assign(m2max + 1, 0.0);
+    for (int m2 = 1; m2 <= m2max; ++m2) {
+        const double m = std::sqrt((double)m2);
+        T->wdiff_t[m2] = (w.gammahat(kPi * m / 3.0) - w.gammahat(2.0 * kPi * m / 3.0)) / (18.0 * kPi * m2 * m2);
+    }
     // free-space root: truncated kernel B^R with R = 1 + sqrt(3) on the unit
     // box; M_0^R is supported in |x| <= R + 1, differences of root proxy
     // nodes have |x_i| <= 1, so a trapezoid period P > 3 + sqrt(3) avoids
@@ -547,6 +640,12 @@ Tables* build_tables(const Params& prm)
         const double k = 2.0 * kPi * std::sqrt((double)m2) / T->root_period;
         const double P3 = T->root_period * T->root_period * T->root_period;
         T->wroot[m2] = k * k * btrunc_hat(k, T->root_R) * w.gammahat(k) / P3;
+    }
+    T->wroot_t.assign(r2max + 1, 0.0);
+    for (int m2 = 1; m2 <= r2max; ++m2) {
+        const double k = 2.0 * kPi * std::sqrt((double)m2) / T->root_period;
+        const double P3 = T->root_period * T->root_period * T->root_period;
+        T->wroot_t[m2] = btrunc_hat(k, T->root_R) * w.gammahat(k) / P3;
     }
     // periodic root: Poisson summation over k = 2 pi kappa, k = 0 dropped
     T->per_m = (prm.nper - 1) / 2;
@@ -586,7 +685,7 @@ const Tables* get_tables(const Params& prm)
     static std::mutex mu;
     static std::map<std::tuple<double, int, int, int>, Tables*> cache;
     std::lock_guard<std::mutex> lk(mu);
-    const auto key = std::make_tuple(prm.tol, prm.window, prm.q, prm.p);
+    const auto key = std::make_tuple(prm.tol, prm.window * 2 + prm.kernel, prm.q, prm.p);
     auto it = cache.find(key);
     if (it != cache.end())
         return it->second;

@@ -14,6 +14,7 @@ namespace dmk {
 // leaf size from Sec. "Numerical results").
 struct Params {
     double tol;
+    int kernel;   // 0: Stokeslet, 1: stresslet
     int window;   // 0: prolate (PSWF), 1: Gaussian
     int q;        // 3c/pi (prolate) or (6/pi) sigma^-2 (Gaussian)
     double c;     // Fourier truncation K_max = q pi / 3 (the PSWF band limit; 2/sigma^2 for the Gaussian)
@@ -25,7 +26,7 @@ struct Params {
 };
 
 // Returns false if tol is outside [1e-12, 1e-3] (Gaussian window: [1e-6, 1e-3]).
-bool select_params(double tol, Params* out, int window = 0);
+bool select_params(double tol, Params* out, int window = 0, int kernel = 0);
 // Replaces q (and with it c, n1, nper) and/or p when the value is > 0.
 void override_params(Params* prm, int q, int p);
 
@@ -97,6 +98,12 @@ struct RadialFits {
     double max_err_P, max_err_Q;
 };
 RadialFits fit_radial(const Window& w, double fit_tol);
+// Radial functions of the residual stresslet at unit scale (eq. res_stresslet
+// with R_Tdiag, R_Toffd of eq. T-offd, rearranged):
+//   T_R(y) = T(y) + (3/(2 pi)) A(s) y y y + (1/(4 pi)) D(s) (delta y + ...),
+// A(s) = [E - G + rho phi'(rho)/3] / s^2,  D(s) = -phi'(rho)/rho,  s = |y|^2.
+// Returned in the P (= A) and Q (= D) slots.
+RadialFits fit_radial_stresslet(const Window& w, double fit_tol);
 
 // Gauss-Legendre nodes and weights on [-1,1].
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
@@ -126,12 +133,15 @@ struct Tables {
     std::vector<std::complex<double>> g_half;   // p x q  : w(m) exp(+i pi/3 m t_a), w = 1 (m=0) or 2
     std::vector<std::complex<double>> g_full;   // p x n1 : exp(+i pi/3 m t_a)
     std::vector<double> wdiff;   // by |m|^2: [gammahat(pi|m|/3) - gammahat(2 pi |m|/3)]/(12 pi^2 |m|^2)
+    // stresslet: by |m|^2: [gammahat(pi|m|/3) - gammahat(2 pi |m|/3)]/(18 pi |m|^4)
+    std::vector<double> wdiff_t;
     // free-space root: truncated mollified kernel (eq. Bmollhat_trunc) on a
     // trapezoid grid of period root_period, modes |m_i| <= root_m
     double root_period, root_R;
     int root_m;
     std::vector<std::complex<double>> r_e_half, r_e_full, r_g_half, r_g_full;
     std::vector<double> wroot;   // by |m|^2: (1/P^3) k^2 Bhat^R(k) gammahat(k), k = 2 pi |m| / P
+    std::vector<double> wroot_t; // stresslet: by |m|^2: (1/P^3) Bhat^R(k) gammahat(k)
     // periodic root: k = 2 pi kappa, |kappa_i| <= per_m
     int per_m;
     std::vector<std::complex<double>> p_e_half, p_e_full, p_g_half, p_g_full;

@@ -115,6 +115,17 @@ def sphere_targets(m: int, seed: int) -> np.ndarray:
     return sphere_points(_rng(seed + 200), m)
 
 
+def normals(x: np.ndarray, seed: int, kind: str = "random") -> np.ndarray:
+    """Unit vectors n_a for stresslet (double-layer) sources: the radial
+    direction from the cube centre for surface points (kind "sphere"), else
+    isotropic random directions (seeded with seed + 300)."""
+    if kind == "sphere":
+        v = np.asarray(x, dtype=np.float64) - 0.5
+    else:
+        v = _rng(seed + 300).standard_normal((np.asarray(x).shape[0], 3))
+    return np.ascontiguousarray(v / np.linalg.norm(v, axis=1, keepdims=True))
+
+
 def sample_targets(n: int, m: int, seed: int) -> np.ndarray:
     """Sorted distinct target indices (seeded with seed + 100)."""
     if m >= n:
