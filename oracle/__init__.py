@@ -57,6 +57,9 @@ def lib():
         L.oracle_stokeslet_ewald_real.restype = ctypes.c_int
         L.oracle_stresslet_direct.argtypes = [dp, dp, dp, ctypes.c_int64, ip, ctypes.c_int64, dp]
         L.oracle_stresslet_direct.restype = None
+        L.oracle_stresslet_ewald_real.argtypes = [dp, dp, dp, ctypes.c_int64, ip, ctypes.c_int64,
+                                                  ctypes.c_double, ctypes.c_double, dp]
+        L.oracle_stresslet_ewald_real.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -116,4 +119,19 @@ def stresslet_direct(x, f, nv, targets=None):
     t = np.arange(n, dtype=np.int64) if targets is None else np.ascontiguousarray(targets, dtype=np.int64)
     u = np.zeros((t.size, 3))
     lib().oracle_stresslet_direct(_dp(x), _dp(f), _dp(nv), n, _ip(t), t.size, _dp(u))
+    return u
+
+
+def stresslet_ewald_real(x, f, nv, targets, xi, rc):
+    """Real-space half of the Gaussian Ewald split of the periodic stresslet
+    sum (minimum-image pairs within rc), at the listed target indices."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    nv = np.ascontiguousarray(nv, dtype=np.float64)
+    tg = np.ascontiguousarray(targets, dtype=np.int64)
+    u = np.zeros((tg.size, 3))
+    rc_ = lib().oracle_stresslet_ewald_real(_dp(x), _dp(f), _dp(nv), x.shape[0], _ip(tg), tg.size, float(xi),
+                                            float(rc), _dp(u))
+    if rc_ != 0:
+        raise ValueError("stresslet_ewald_real: need 0 < rc <= 1/2 and xi > 0")
     return u

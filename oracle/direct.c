@@ -30,6 +30,19 @@
  *                               u_j(x_b) = sum_{a != b} T_jlm(x_b - x_a) f_{a,l} n_{a,m},
  *                               T_jlm(y) = -(3/4pi) y_j y_l y_m / r^5.
  *
+ *   oracle_stresslet_ewald_real
+ *                             the real-space half of the Hasimoto (Gaussian)
+ *                             Ewald split of the periodic stresslet sum, from
+ *                             the general residual stresslet (eq. res_stresslet
+ *                             with R_Tdiag, R_Toffd of eq. T-offd) with the
+ *                             Gaussian window phi_G(r) = (xi/sqrt(pi)) e^{-xi^2 r^2},
+ *                             phi_G'(r) = -2 xi^2 r phi_G(r), Phi_G = erfc(xi r):
+ *                               R_Tdiag = 4 xi^2 r^3 phi_G,
+ *                               R_Toffd = erfc(xi r) + 2 r phi_G + (4/3) xi^2 r^3 phi_G,
+ *                               T_R : (f n^T) = R_Tdiag [(y.n) f + (y.f) n + (f.n) y] / (8 pi r^3)
+ *                                             - (3/4pi) R_Toffd (y.f)(y.n) y / r^5.
+ *                             The Fourier half and the k = 0 term live in ewald.py.
+ *
  * Conventions: points and forces are row-major (n,3) arrays; targets are a
  * list of source indices (the target is also a source, and the pair a == b is
  * skipped).  A pair of distinct but coincident points (r == 0) contributes
@@ -153,6 +166,50 @@ int oracle_stokeslet_ewald_real(const double *x, const double *f, int64_t n,
             neumaier_add(&s0, &c0, a1 * f0 + a2 * y0);
             neumaier_add(&s1, &c1, a1 * f1 + a2 * y1);
             neumaier_add(&s2, &c2, a1 * f2 + a2 * y2);
+        }
+        u[3 * t] = s0 + c0;
+        u[3 * t + 1] = s1 + c1;
+        u[3 * t + 2] = s2 + c2;
+    }
+    return 0;
+}
+
+int oracle_stresslet_ewald_real(const double *x, const double *f, const double *nv, int64_t n,
+                                const int64_t *tgt, int64_t m, double xi, double rc, double *u)
+{
+    if (!(rc > 0.0 && rc <= 0.5) || !(xi > 0.0))
+        return -1;
+    const double c8 = 1.0 / (8.0 * M_PI), c34 = 3.0 / (4.0 * M_PI);
+    const double rc2 = rc * rc;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t t = 0; t < m; ++t) {
+        const int64_t b = tgt[t];
+        const double xb0 = x[3 * b], xb1 = x[3 * b + 1], xb2 = x[3 * b + 2];
+        double s0 = 0, s1 = 0, s2 = 0, c0 = 0, c1 = 0, c2 = 0;
+        for (int64_t a = 0; a < n; ++a) {
+            if (a == b)
+                continue;
+            double y0 = xb0 - x[3 * a], y1 = xb1 - x[3 * a + 1], y2 = xb2 - x[3 * a + 2];
+            y0 -= nearbyint(y0);
+            y1 -= nearbyint(y1);
+            y2 -= nearbyint(y2);
+            const double r2 = y0 * y0 + y1 * y1 + y2 * y2;
+            if (r2 >= rc2 || r2 == 0.0)
+                continue;
+            const double r = sqrt(r2);
+            const double phi = xi / sqrt(M_PI) * exp(-xi * xi * r2);
+            const double tdiag = 4.0 * xi * xi * r2 * r * phi;
+            const double toffd = erfc(xi * r) + 2.0 * r * phi + (4.0 / 3.0) * xi * xi * r2 * r * phi;
+            const double f0 = f[3 * a], f1 = f[3 * a + 1], f2 = f[3 * a + 2];
+            const double n0 = nv[3 * a], n1 = nv[3 * a + 1], n2 = nv[3 * a + 2];
+            const double yf = y0 * f0 + y1 * f1 + y2 * f2;
+            const double yn = y0 * n0 + y1 * n1 + y2 * n2;
+            const double fn = f0 * n0 + f1 * n1 + f2 * n2;
+            const double d = c8 * tdiag / (r2 * r);
+            const double o = c34 * toffd * yf * yn / (r2 * r2 * r);
+            neumaier_add(&s0, &c0, d * (yn * f0 + yf * n0 + fn * y0) - o * y0);
+            neumaier_add(&s1, &c1, d * (yn * f1 + yf * n1 + fn * y1) - o * y1);
+            neumaier_add(&s2, &c2, d * (yn * f2 + yf * n2 + fn * y2) - o * y2);
         }
         u[3 * t] = s0 + c0;
         u[3 * t + 1] = s1 + c1;
