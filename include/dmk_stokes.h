@@ -75,8 +75,13 @@ typedef enum { DMK_WINDOW_PROLATE = 0, DMK_WINDOW_GAUSSIAN = 1 } dmk_window;
  * split by the same PSWF mollifier (residual eq. res_stresslet with the
  * functions of eq. T-offd; Fourier side eq. moll_stresslet) with the stresslet
  * columns of Table tab:params (p stepped up one compiled order per row: 12,
- * 23, 36, 48).  Offered in free space with the prolate window;
- * evaluated with dmk_stokes_eval_stresslet. */
+ * 23, 36, 48).  Offered with the prolate window, in free space and on the
+ * periodic unit cell; there the k = 0 Fourier term is the one the paper fixes
+ * for the stresslet (after eq. ewald_far),
+ *   u^(0)(x_b) = -sum_a (x_b - x_a)(f_a . n_a),
+ * with positions in [0,1)^3 as given (so the sum depends on which image of a
+ * point is passed, by -p (f.n) for a shift p).  Evaluated with
+ * dmk_stokes_eval_stresslet. */
 typedef enum { DMK_KERNEL_STOKESLET = 0, DMK_KERNEL_STRESSLET = 1 } dmk_kernel;
 
 typedef struct {

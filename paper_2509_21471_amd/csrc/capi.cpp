@@ -749,7 +749,8 @@ int build_plan(dmk_plan_t P, const double* points)
     P->root_mh = rw.M + 1;
     P->root_mf = 2 * rw.M + 1;
     const bool stress = P->kern == DMK_KERNEL_STRESSLET;
-    const std::vector<double>& wr = P->periodic ? TB.wper : (stress ? TB.wroot_t : TB.wroot);
+    const std::vector<double>& wr =
+        P->periodic ? (stress ? TB.wper_t : TB.wper) : (stress ? TB.wroot_t : TB.wroot);
     const std::vector<double>& wd = stress ? TB.wdiff_t : TB.wdiff;
     P->wdiff = P->mem.alloc<double>(wd.size());
     P->wroot = P->mem.alloc<double>(wr.size());
@@ -789,7 +790,7 @@ int build_plan(dmk_plan_t P, const double* points)
     P->s2 = P->mem.alloc<char>(sbytes);
     P->phi_root = P->mem.alloc<char>(nc * P->Hroot * cs * np);
     P->psi_root = P->mem.alloc<char>(3 * P->Hroot * cs * np);
-    P->cst = P->mem.alloc<double>(3 * (size_t)P->rhs_batch * np);
+    P->cst = P->mem.alloc<double>(std::max<size_t>(3 * (size_t)P->rhs_batch, 4) * np);
     P->d_root_fid = P->mem.alloc<int>(np);
     if (P->mem.oom)
         return fail(DMK_ERR_OOM, "device allocation failed (or above mem_cap_bytes)");
@@ -901,8 +902,8 @@ void far_field(dmk_plan_t P, int r, bool record)
         stage(P, ST_OUT_FULL, IO_PLAIN, P->s2, (long)p * mh * mf, nullptr, P->phi_root, Hr, nullptr, 0, P->r_out, p,
               mf, 0, RM, h, mh, mh * mf, nr, nullptr, nc);
         if (stress)
-            launch_root_symbol_t(mh, mf, nr, P->phi_root, P->wroot, 2.0 * kPi / P->tab->root_period, P->psi_root,
-                                 P->f32, st);
+            launch_root_symbol_t(mh, mf, nr, P->phi_root, P->wroot,
+                                 P->periodic ? 2.0 * kPi : 2.0 * kPi / P->tab->root_period, P->psi_root, P->f32, st);
         else
             launch_root_symbol(mh, mf, nr, P->phi_root, P->wroot, P->psi_root, P->f32, st);
         stage(P, ST_IN_FULL, IO_PLAIN, P->psi_root, Hr, nullptr, P->s1, (long)mf * mh * p, nullptr, 0, P->r_in_full,
@@ -911,6 +912,8 @@ void far_field(dmk_plan_t P, int r, bool record)
               P->r_in_full, mf, p, RM, 0, mh, h, mh * p, nr);
         stage(P, ST_IN_HALF_REAL, IO_PLAIN, P->s2, (long)mh * p * p, nullptr, P->V, p3, P->d_root_fid, 1, P->r_in_half,
               mh, p, 0, 0, mh, h, p * p, nr);
+        if (P->periodic && stress)
+            launch_stress_moment(P->Q, P->d_root_fid, nr, p, P->cheb_t, cst, P->f32, st);
         if (!P->periodic && !stress)
             launch_sum_root(P->Q, P->d_root_fid, nr, (int)p3, 1.0 / (4.0 * kPi * (1.0 + std::sqrt(3.0))), cst, P->f32,
                             st);
@@ -957,8 +960,8 @@ int eval_batch(dmk_plan_t P, const double* f, int nb, double* vel, bool record)
         (void)hipEventRecord(P->ev[9], st);
     for (int r = 0; r < nb; ++r)
         launch_finalize(P->u + (size_t)r * 3 * n, n, P->perm, P->tofs, P->pid, P->scale, 0,
-                        P->periodic ? nullptr : P->cst + (size_t)3 * P->nprob * r, vel + (size_t)r * 3 * P->nout,
-                        st);
+                        P->periodic ? nullptr : P->cst + (size_t)3 * P->nprob * r, nullptr, nullptr, nullptr, nullptr,
+                        vel + (size_t)r * 3 * P->nout, st);
     if (record) {
         (void)hipEventRecord(P->ev[10], st);
         P->ev_recorded = true;
@@ -969,8 +972,9 @@ int eval_batch(dmk_plan_t P, const double* f, int nb, double* vel, bool record)
 // One stresslet vector: densities and (f, n) in sorted order, the far field
 // of the 6 density components, the residual stresslet near field, and the
 // scaling by 1/L^2 (the stresslet is homogeneous of degree -2).  There is no
-// constant and no self term: both the mollified kernel at 0 and every residual
-// term are odd in the separation.
+// self term (the mollified kernel at 0 and every residual term are odd in the
+// separation) and no free-space constant; a periodic plan adds the k = 0 term
+// the paper fixes for the stresslet (after eq. ewald_far).
 int eval_stresslet(dmk_plan_t P, const double* f, const double* nv, double* vel, bool record)
 {
     using namespace dmk;
@@ -986,7 +990,9 @@ int eval_stresslet(dmk_plan_t P, const double* f, const double* nv, double* vel,
                 P->y, P->z, P->fs + 6 * (size_t)n, n, P->poly, P->u, st);
     if (record)
         (void)hipEventRecord(P->ev[9], st);
-    launch_finalize(P->u, n, P->perm, P->tofs, P->pid, P->scale, 1, nullptr, vel, st);
+    // periodic: the k = 0 term -sum_s (x_t - x_s)(f_s . n_s) from the root moments in cst
+    launch_finalize(P->u, n, P->perm, P->tofs, P->pid, P->scale, 1, nullptr, P->periodic ? P->cst : nullptr, P->x,
+                    P->y, P->z, vel, st);
     if (record) {
         (void)hipEventRecord(P->ev[10], st);
         P->ev_recorded = true;
@@ -1098,8 +1104,6 @@ int create_plan(const double* points, const std::vector<int64_t>& offsets, int d
         return rc;
     if (periodic != 0 && periodic != 1)
         return fail(DMK_ERR_ARG, "periodic must be 0 or 1");
-    if (opts && opts->kernel == DMK_KERNEL_STRESSLET && periodic)
-        return fail(DMK_ERR_UNSUPPORTED, "the stresslet is offered in free space only");
     if (!is_device_ptr(points))
         return fail(DMK_ERR_ARG, "points must be a device pointer");
     const auto t0 = std::chrono::steady_clock::now();

@@ -1808,12 +1808,66 @@ void launch_sum_root(const void* Q, const int* root_fid, int nroot, int p3, doub
                            out);
 }
 
+// Moments of the stresslet densities of each root (one block per root) for
+// the k = 0 term of the periodic stresslet sum: out[4r] = sum_s f_s . n_s,
+// out[4r + 1 + d] = sum_s x_{s,d} (f_s . n_s), both read off the root's proxy
+// densities (their traces), which reproduce the constant and linear moments
+// of the point densities exactly (the Lagrange basis reproduces polynomials
+// of degree < p).  The root is the unit box centred at the origin (the
+// coordinates of the sorted points): node a sits at t_a / 2.  The k = 0 term
+// depends on positions only through differences, so the centring is free.
+template <typename S>
+__global__ __launch_bounds__(256) void k_stress_moment(const S* __restrict__ Q, const int* __restrict__ root_fid,
+                                                       int p, const double* __restrict__ cheb_t,
+                                                       double* __restrict__ out)
+{
+    __shared__ double sh[4][256];
+    const size_t p3 = (size_t)p * p * p;
+    const S* q = Q + (size_t)root_fid[blockIdx.x] * 6 * p3;
+    double m[4] = {0, 0, 0, 0};
+    for (int k = threadIdx.x; k < (int)p3; k += 256) {
+        const int a = k / (p * p), b = (k / p) % p, c = k % p;
+        const double tr = (double)q[k] + (double)q[p3 + k] + (double)q[2 * p3 + k];
+        m[0] += tr;
+        m[1] += 0.5 * cheb_t[a] * tr;
+        m[2] += 0.5 * cheb_t[b] * tr;
+        m[3] += 0.5 * cheb_t[c] * tr;
+    }
+    for (int j = 0; j < 4; ++j)
+        sh[j][threadIdx.x] = m[j];
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st)
+            for (int j = 0; j < 4; ++j)
+                sh[j][threadIdx.x] += sh[j][threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4)
+        out[4 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+void launch_stress_moment(const void* Q, const int* root_fid, int nroot, int p, const double* cheb_t, double* out,
+                          bool f32, hipStream_t s)
+{
+    if (f32)
+        hipLaunchKernelGGL(k_stress_moment<float>, dim3(nroot), dim3(256), 0, s, (const float*)Q, root_fid, p,
+                           cheb_t, out);
+    else
+        hipLaunchKernelGGL(k_stress_moment<double>, dim3(nroot), dim3(256), 0, s, (const double*)Q, root_fid, p,
+                           cheb_t, out);
+}
+
 // vel (caller's order) = scale_b (u + c_b), b the point's problem: scale_b
 // undoes that problem's unit-box map, c_b its free-space constant (or none).
+// lin (periodic stresslet): adds lin[4b+1+d] - x_d lin[4b] at the sorted
+// (centred unit-box) coordinates x: the k = 0 term, in a unit box that is the
+// unit cell.
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ u, int64_t n, const int* __restrict__ perm,
                                                   int64_t tofs, const int* __restrict__ pid,
                                                   const double* __restrict__ scale, int sq,
-                                                  const double* __restrict__ cst, double* __restrict__ vel)
+                                                  const double* __restrict__ cst, const double* __restrict__ lin,
+                                                  const double* __restrict__ x, const double* __restrict__ y,
+                                                  const double* __restrict__ z, double* __restrict__ vel)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n)
@@ -1824,17 +1878,24 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ u, 
         return;
     const int b = pid ? pid[i] : 0;
     const double sc = sq ? scale[b] * scale[b] : scale[b];
-    const double c0 = cst ? cst[3 * b] : 0.0, c1 = cst ? cst[3 * b + 1] : 0.0, c2 = cst ? cst[3 * b + 2] : 0.0;
+    double c0 = cst ? cst[3 * b] : 0.0, c1 = cst ? cst[3 * b + 1] : 0.0, c2 = cst ? cst[3 * b + 2] : 0.0;
+    if (lin) {
+        const double m0 = lin[4 * b];
+        c0 += lin[4 * b + 1] - x[i] * m0;
+        c1 += lin[4 * b + 2] - y[i] * m0;
+        c2 += lin[4 * b + 3] - z[i] * m0;
+    }
     vel[3 * o] = sc * (u[i] + c0);
     vel[3 * o + 1] = sc * (u[n + i] + c1);
     vel[3 * o + 2] = sc * (u[2 * n + i] + c2);
 }
 
 void launch_finalize(const double* u, int64_t n, const int* perm, int64_t tofs, const int* pid, const double* scale,
-                     int sq, const double* cst, double* vel, hipStream_t s)
+                     int sq, const double* cst, const double* lin, const double* x, const double* y, const double* z,
+                     double* vel, hipStream_t s)
 {
     hipLaunchKernelGGL(k_finalize, dim3(nblocks(n, 256)), dim3(256), 0, s, u, n, perm, tofs, pid, scale, sq, cst,
-                       vel);
+                       lin, x, y, z, vel);
 }
 
 __global__ __launch_bounds__(256) void k_zero(uint32_t* __restrict__ p, size_t count)

@@ -179,10 +179,16 @@ void launch_residual_direct_t(const double* tx, const double* ty, const double* 
 // out[3r + j] = coef * sum_k Q[root_fid[r]][j][k]
 void launch_sum_root(const void* Q, const int* root_fid, int nroot, int p3, double coef, double* out, bool f32,
                      hipStream_t s);
+// periodic stresslet, per root r: out[4r] = sum f.n, out[4r+1+d] = sum x_d f.n
+// (unit-box coordinates), from the root's 6-component proxy densities
+void launch_stress_moment(const void* Q, const int* root_fid, int nroot, int p, const double* cheb_t, double* out,
+                          bool f32, hipStream_t s);
 // per point of problem b with input index o >= tofs (the points with an output):
-// vel[o - tofs] = scale[b]^(sq ? 2 : 1) * (u + cst[3b..]) (cst may be NULL)
+// vel[o - tofs] = scale[b]^(sq ? 2 : 1) * (u + cst[3b..] + lin[4b+1..] - x lin[4b])
+// (cst and lin may be NULL; x, y, z: sorted unit-box coordinates, read when lin is set)
 void launch_finalize(const double* u, int64_t n, const int* perm, int64_t tofs, const int* pid, const double* scale,
-                     int sq, const double* cst, double* vel, hipStream_t s);
+                     int sq, const double* cst, const double* lin, const double* x, const double* y, const double* z,
+                     double* vel, hipStream_t s);
 // zero `bytes` (a multiple of 4) at p
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 

@@ -656,6 +656,11 @@ Tables* build_tables(const Params& prm)
         const double k = 2.0 * kPi * std::sqrt((double)m2);
         T->wper[m2] = w.gammahat(k) / (k * k);
     }
+    T->wper_t.assign(p2max + 1, 0.0);
+    for (int m2 = 1; m2 <= p2max; ++m2) {
+        const double k = 2.0 * kPi * std::sqrt((double)m2);
+        T->wper_t[m2] = w.gammahat(k) / (k * k * k * k);
+    }
     // folded stage matrices
     const int h = (p + 1) / 2;
     T->pw = fold_pw(p, q - 1, kPi / 3.0, t);

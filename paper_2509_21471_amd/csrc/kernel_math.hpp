@@ -146,6 +146,7 @@ struct Tables {
     int per_m;
     std::vector<std::complex<double>> p_e_half, p_e_full, p_g_half, p_g_full;
     std::vector<double> wper;    // by |kappa|^2: gammahat(2 pi |kappa|) / (4 pi^2 |kappa|^2)
+    std::vector<double> wper_t;  // stresslet: by |kappa|^2: gammahat(k) / k^4, k = 2 pi |kappa|
     // folded stage matrices, (Me, Mo) pairs, row-major Nh x Kh (see the
     // separable-stage kernel): h = ceil(p/2)
     struct PW {

@@ -6,6 +6,11 @@ against.  Calls only the oracle and the seeded input generators.
                            targets of the 2e6-point periodic workload
   clusters_4e6_direct.npz  direct FP64 sum (oracle.direct) at 10,000 sampled
                            targets of the 4e6-point clustered workload
+  periodic_2e6_stresslet_ewald.npz
+                           periodic stresslet sum (oracle.ewald.stresslet_ewald,
+                           k = 0 term included) at 1,000 sampled targets of the
+                           2e6-point periodic workload, with the seeded random
+                           unit vectors of workloads.normals as n
 
 Each file holds `idx` (target indices) and `u` (velocities, (m,3)).  Run from
 the repository root:  python tests/golden/make_references.py [name ...]
@@ -22,11 +27,12 @@ sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
 import workloads  # noqa: E402
-from oracle.ewald import ewald  # noqa: E402
+from oracle.ewald import ewald, stresslet_ewald  # noqa: E402
 
 REFS = {
     "periodic_2e6_ewald": ("periodic_2e6", 2000),
     "clusters_4e6_direct": ("clusters_4e6", 10000),
+    "periodic_2e6_stresslet_ewald": ("periodic_2e6", 1000),
 }
 
 
@@ -36,7 +42,9 @@ def make(name):
     x, f = workloads.config(cfg_name)
     idx = workloads.sample_targets(x.shape[0], m, cfg["seed"])
     t0 = time.time()
-    if cfg["periodic"]:
+    if name.endswith("stresslet_ewald"):
+        u = stresslet_ewald(x, f, workloads.normals(x, cfg["seed"]), idx, E=30.0)
+    elif cfg["periodic"]:
         u = ewald(x, f, idx, E=30.0)
     else:
         u = oracle.direct(x, f, idx)

@@ -197,3 +197,60 @@ def test_clusters_1e6_sampled(dev):
     err = oracle.rel_l2(u[idx], oracle.stresslet_direct(x, f, nv, idx))
     print("stresslet clusters_1e6", plan.info()["levels"], err)
     assert err < 1e-6
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-6, 1e-9])
+def test_periodic_matches_ewald(dev, tol):
+    """Periodic stresslet sum (k = 0 term of the paper included) vs the
+    oracle's Gaussian Ewald sum."""
+    from oracle.ewald import stresslet_ewald
+    x, f, nv = _inputs("periodic", 4000, seed=99)
+    plan = _plan(x, tol, leaf_size=150, periodic=True)
+    u = plan.eval_stresslet(_t(f), _t(nv)).cpu().numpy()
+    t = np.arange(0, 4000, 9)
+    ref = stresslet_ewald(x, f, nv, t)
+    err = oracle.rel_l2(u[t], ref)
+    print("stresslet periodic", tol, plan.info()["levels"], err / tol)
+    assert err < tol
+
+
+def test_periodic_double_layer_identity(dev):
+    """A closed sphere crossing the cell faces, constant density f0 on a
+    surface quadrature (weights in the forces), outward normals: the periodic
+    stresslet sum is f0 inside the sphere's images and 0 outside, up to the
+    k = 0 term's dependence on the wrapped source positions."""
+    R, c = 0.2, np.array([0.9, 0.15, 0.5])
+    ct, wt = np.polynomial.legendre.leggauss(60)
+    ph = np.arange(120) * 2 * np.pi / 120
+    CT, PH = np.meshgrid(ct, ph, indexing="ij")
+    st = np.sqrt(1 - CT ** 2)
+    nv = np.stack([st * np.cos(PH), st * np.sin(PH), CT], -1).reshape(-1, 3)
+    w = (np.outer(wt, np.full(120, 2 * np.pi / 120)) * R * R).ravel()
+    xs = c + R * nv
+    f0 = np.array([-0.2, 0.4, 0.9])
+    tg = np.array([[0.95, 0.12, 0.45], [0.02, 0.15, 0.5], [0.9, 0.15, 0.5], [0.5, 0.5, 0.5], [0.3, 0.7, 0.1]])
+    inside = np.array([1, 1, 1, 0, 0], dtype=float)
+    dmk = _dmk()
+    xw = xs - np.floor(xs)
+    plan = dmk.Plan(_t(xw), tol=1e-9, periodic=True, targets=_t(tg), kernel=dmk.KERNEL_STRESSLET)
+    u = plan.eval_stresslet(_t(f0 * w[:, None]), _t(nv)).cpu().numpy()
+    p = np.floor(xs)
+    shift = -(p * ((f0 * w[:, None]) * nv).sum(axis=1)[:, None]).sum(axis=0)
+    err = np.abs(u - shift - inside[:, None] * f0).max()
+    print("periodic double layer", err)
+    assert err < 1e-8
+
+
+def test_periodic_2e6_stored_ewald(dev):
+    """The 2e6-point periodic workload at 1e-9 against the oracle's stored
+    periodic stresslet values (tests/golden/make_references.py)."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                             "periodic_2e6_stresslet_ewald.npz"))
+    x, f = workloads.config("periodic_2e6")
+    nv = workloads.normals(x, 3)
+    plan = _plan(x, 1e-9, periodic=True)
+    u = plan.eval_stresslet(_t(f), _t(nv)).cpu().numpy()
+    err = oracle.rel_l2(u[g["idx"]], g["u"])
+    print("stresslet periodic_2e6", plan.info()["levels"], err)
+    assert err < 1e-9

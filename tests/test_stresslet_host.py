@@ -68,8 +68,8 @@ def test_stresslet_argument_validation_without_gpu():
     host = (ctypes.c_double * 30)()
     vp = ctypes.cast(host, ctypes.c_void_p)
     st = dmk._lib.Opts(0, 0, None, 0, 0, 0, 0, 0, 0, 0, 1)
-    # free space only
-    assert lib.dmk_stokes_plan_ex(vp, 10, 3, 1, 1e-6, ctypes.byref(st), ctypes.byref(out)) == -2
+    # periodic stresslet plans pass validation (and stop at the host pointer)
+    assert lib.dmk_stokes_plan_ex(vp, 10, 3, 1, 1e-6, ctypes.byref(st), ctypes.byref(out)) == -1
     # prolate window only
     stg = dmk._lib.Opts(0, 0, None, 0, 0, 0, 0, 0, 0, 1, 1)
     assert lib.dmk_stokes_plan_ex(vp, 10, 3, 0, 1e-6, ctypes.byref(stg), ctypes.byref(out)) == -2
