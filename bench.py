@@ -324,7 +324,7 @@ def main():
     t_near = near_mean * 1e-3
     achieved = stats["in_support"] * fpp / t_near / 1e12
 
-    near_kernel = f"dmk::k_near<{nd_bucket(info['deg_P'], info['deg_Q'])}, {info['near_lanes']}, 1>"
+    near_kernel = f"dmk::k_near<{nd_bucket(info['deg_P'], info['deg_Q'])}, {info['near_lanes']}, 1, 0>"
     traffic = near_traffic(args.config, tol, "fp64", near_kernel, info["leaf_size"], info["near_lanes"])
     result = {
         "metric": METRIC,
