@@ -84,6 +84,20 @@ typedef enum { DMK_WINDOW_PROLATE = 0, DMK_WINDOW_GAUSSIAN = 1 } dmk_window;
  * dmk_stokes_eval_stresslet. */
 typedef enum { DMK_KERNEL_STOKESLET = 0, DMK_KERNEL_STRESSLET = 1 } dmk_kernel;
 
+/* Method of a plan.  DMK: the multilevel method above.  EWALD: the
+ * single-level spectral Ewald sum with the same prolate split, for the
+ * periodic cell (the uniform-data variant the paper's introduction points to,
+ * Sec. "Ewald summation"): with r_c = 2^-L, L the smallest level whose cells
+ * hold at most leaf_size points on average,
+ *   u = sum over neighbouring cells of the residual Stokeslet at scale r_c
+ *     + sum_{0 < |kappa_i| <= K} (I - k k^T/k^2) gammahat(k r_c)/k^2 F(k) e^{i k.x},
+ *   k = 2 pi kappa, |k_i| < c / r_c,
+ * the Fourier sum by spreading to an oversampled M^3 grid with a prolate
+ * gridding kernel, a 3D FFT, scaling, an inverse FFT and interpolation.
+ * Offered for one periodic problem (no batch, no separate targets), the
+ * Stokeslet, the prolate window, FP64, tol in [1e-9, 1e-3]. */
+typedef enum { DMK_METHOD_DMK = 0, DMK_METHOD_EWALD = 1 } dmk_method;
+
 typedef struct {
     int precision;        /* dmk_precision */
     int leaf_size;        /* maximum points per leaf; 0 = the tolerance's default */
@@ -104,6 +118,7 @@ typedef struct {
                              force/velocity work buffers (48 bytes per point each) */
     int window;           /* dmk_window (0 = prolate) */
     int kernel;           /* dmk_kernel (0 = Stokeslet) */
+    int method;           /* dmk_method (0 = DMK) */
 } dmk_opts;
 
 /* record HIP events around each phase of dmk_stokes_eval (read back with
@@ -156,6 +171,10 @@ typedef struct {
     int window;                 /* dmk_window of the plan */
     double sigma;               /* Gaussian shape parameter (0 for the prolate window) */
     int kernel;                 /* dmk_kernel of the plan */
+    int method;                 /* dmk_method of the plan */
+    /* spectral Ewald plans: grid points per dimension M, mode bound K
+     * (|kappa_i| <= K), gridding kernel width in grid points; levels = L + 1 */
+    int ewald_grid, ewald_modes, ewald_width;
 } dmk_plan_info;
 
 /*

@@ -19,6 +19,7 @@ STATUS = {0: "DMK_OK", -1: "DMK_ERR_ARG", -2: "DMK_ERR_UNSUPPORTED", -3: "DMK_ER
           -4: "DMK_ERR_NONFINITE", -5: "DMK_ERR_TOL", -6: "DMK_ERR_OOM", -7: "DMK_ERR_HIP"}
 PREC_FP64, PREC_MIXED = 0, 1
 KERNEL_STOKESLET, KERNEL_STRESSLET = 0, 1
+METHOD_DMK, METHOD_EWALD = 0, 1
 
 SYMBOLS = ["dmk_stokes_radial_stresslet", "dmk_stokes_params_ex", "dmk_stokes_params_kernel", "dmk_stokes_eval_stresslet",
            "dmk_stokes_residual_sum_stresslet", "dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_plan_batch", "dmk_stokes_plan_targets", "dmk_stokes_autotune", "dmk_stokes_eval", "dmk_stokes_plan_info",
@@ -42,7 +43,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("leaf_size", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("mem_cap_bytes", ctypes.c_size_t), ("flags", ctypes.c_int), ("near_lanes", ctypes.c_int),
                 ("q", ctypes.c_int), ("p", ctypes.c_int), ("rhs_batch", ctypes.c_int), ("window", ctypes.c_int),
-                ("kernel", ctypes.c_int)]
+                ("kernel", ctypes.c_int), ("method", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -56,7 +57,9 @@ class PlanInfo(ctypes.Structure):
                 ("center", ctypes.c_double * 3), ("box_len", ctypes.c_double),
                 ("device_bytes", ctypes.c_size_t), ("plan_ms", ctypes.c_double),
                 ("plan_phase_ms", ctypes.c_double * 6), ("near_lanes", ctypes.c_int), ("precision", ctypes.c_int),
-                ("window", ctypes.c_int), ("sigma", ctypes.c_double), ("kernel", ctypes.c_int)]
+                ("window", ctypes.c_int), ("sigma", ctypes.c_double), ("kernel", ctypes.c_int),
+                ("method", ctypes.c_int), ("ewald_grid", ctypes.c_int), ("ewald_modes", ctypes.c_int),
+                ("ewald_width", ctypes.c_int)]
 
     def as_dict(self):
         d = {}
@@ -204,13 +207,14 @@ class Plan:
                  leaf_size: int = 0, stream=None, mem_cap_bytes: int = 0, timing: bool = False,
                  near_lanes: int = 0, q: int = 0, p: int = 0, rhs_batch: int = 0, concurrent: bool = False,
                  offsets=None, graph: bool = False, targets=None, window: int = 0,
-                 kernel: int = KERNEL_STOKESLET):
+                 kernel: int = KERNEL_STOKESLET, method: int = METHOD_DMK):
         """offsets (host int sequence, n_problems + 1 entries) makes a batched
         plan over independent problems (dmk_stokes_plan_batch); targets (device
         (m,3)) makes a plan evaluating the sums at a separate target set
         (dmk_stokes_plan_targets): forces (n_rhs, n, 3) -> velocities (n_rhs, m, 3).
         kernel = KERNEL_STRESSLET makes a stresslet plan, evaluated with
-        eval_stresslet."""
+        eval_stresslet.  method = METHOD_EWALD makes a single-level spectral
+        Ewald plan (periodic, one problem)."""
         torch = _torch()
         pts = _dev_f64(points)
         self.n = int(pts.shape[0])
@@ -219,7 +223,8 @@ class Plan:
         opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), int(mem_cap_bytes),
                     (FLAG_PHASE_TIMING if timing else 0) | (FLAG_CONCURRENT_PLAN if concurrent else 0)
                     | (FLAG_GRAPH if graph else 0),
-                    int(near_lanes), int(q), int(p), int(rhs_batch), int(window), int(kernel))
+                    int(near_lanes), int(q), int(p), int(rhs_batch), int(window), int(kernel),
+                    int(method))
         h = ctypes.c_void_p()
         if targets is not None:
             if offsets is not None:

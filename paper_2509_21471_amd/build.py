@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libdmk_stokes.so")
-SOURCES = ["dmk_kernels.hip", "capi.cpp", "kernel_math.cpp", "tree.cpp"]
+SOURCES = ["dmk_kernels.hip", "ewald_kernels.hip", "capi.cpp", "kernel_math.cpp", "tree.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 
@@ -17,7 +17,7 @@ def build(verbose: bool = False) -> str:
     cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "--offload-arch=gfx950",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wno-unused-command-line-argument", "-I", os.path.join(HERE, "..", "include"),
-           "-o", tmp] + srcs
+           "-o", tmp] + srcs + ["-L/opt/rocm/lib", "-lhipfft"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + r.stderr[-6000:])

@@ -1,5 +1,6 @@
 // C ABI: plan construction (tree, lists, buffers) and the evaluation pass.
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <chrono>
@@ -13,6 +14,7 @@
 
 #include "../../include/dmk_stokes.h"
 #include "dmk_kernels.hpp"
+#include "ewald_kernels.hpp"
 #include "kernel_math.hpp"
 #include "tree.hpp"
 
@@ -253,6 +255,17 @@ struct dmk_plan_s {
     int nc_in = 3;
     void* Phi3 = nullptr;
     int* send_level = nullptr;        // sender slot -> level
+    // single-level spectral Ewald plans (DMK_METHOD_EWALD)
+    int method = DMK_METHOD_DMK;
+    dmk::EwaldGrid eg;
+    dmk::GridPoly gpoly;
+    int64_t* tile_start = nullptr;    // 8^Lt + 1 point ranges of the spreading tiles
+    double* egrid = nullptr;          // [3][M^3] real grid
+    double2* espec = nullptr;         // [3][M][M][M/2+1] half spectrum
+    double *eghat = nullptr, *ewsym = nullptr;
+    hipfftHandle fft_fwd = 0, fft_inv = 0;
+    bool fft_made = false;
+    int64_t n_cells_nonempty = 0;
     double* cst = nullptr;
     size_t H = 0, Hroot = 0;
     std::vector<int> leaf_box;        // leaf index (all leaves) -> box id
@@ -287,6 +300,10 @@ struct dmk_plan_s {
             (void)hipGraphDestroy(graph);
         if (cap_stream)
             (void)hipStreamDestroy(cap_stream);
+        if (fft_made) {
+            (void)hipfftDestroy(fft_fwd);
+            (void)hipfftDestroy(fft_inv);
+        }
     }
 };
 
@@ -322,6 +339,17 @@ int validate_common(int dim, double tol, const dmk_opts* opts)
             return fail(DMK_ERR_TOL, "the Gaussian window is offered for tol >= 1e-6");
         if (opts->kernel != DMK_KERNEL_STOKESLET && opts->kernel != DMK_KERNEL_STRESSLET)
             return fail(DMK_ERR_ARG, "unknown kernel");
+        if (opts->method != DMK_METHOD_DMK && opts->method != DMK_METHOD_EWALD)
+            return fail(DMK_ERR_ARG, "unknown method");
+        if (opts->method == DMK_METHOD_EWALD) {
+            if (opts->kernel != DMK_KERNEL_STOKESLET || opts->window != DMK_WINDOW_PROLATE ||
+                opts->precision != DMK_PREC_FP64)
+                return fail(DMK_ERR_UNSUPPORTED, "the spectral Ewald method takes the FP64 prolate Stokeslet only");
+            if (opts->flags & DMK_FLAG_GRAPH)
+                return fail(DMK_ERR_UNSUPPORTED, "DMK_FLAG_GRAPH is not available for the spectral Ewald method");
+            if (tol < 1e-9 * (1 - 1e-9))
+                return fail(DMK_ERR_TOL, "the spectral Ewald method is offered for tol >= 1e-9");
+        }
         if (opts->kernel == DMK_KERNEL_STRESSLET) {
             if (opts->window != DMK_WINDOW_PROLATE)
                 return fail(DMK_ERR_UNSUPPORTED, "the stresslet is offered with the prolate window only");
@@ -402,6 +430,159 @@ bool make_poly(const dmk::Tables& TB, dmk::RadialPoly* poly)
     conv(TB.fits.P.a, poly->P);
     conv(TB.fits.Q.a, poly->Q);
     return true;
+}
+
+// Morton code at a level <-> integer cell coordinates (digit 4 bx + 2 by + bz)
+uint64_t cell_code(int64_t ix, int64_t iy, int64_t iz, int level)
+{
+    uint64_t c = 0;
+    for (int b = level - 1; b >= 0; --b)
+        c = (c << 3) | (uint64_t)((((ix >> b) & 1) << 2) | (((iy >> b) & 1) << 1) | ((iz >> b) & 1));
+    return c;
+}
+
+// The rest of a spectral Ewald plan once the points are sorted: split level,
+// grid and gridding kernel, tile and cell ranges from the sorted keys, the
+// near lists between cells of the split level (27 neighbours through the
+// periodic wrap, residual at that level), buffers and FFT plans.
+int build_ewald(dmk_plan_t P, const std::vector<uint64_t>& keys, hipStream_t st)
+{
+    using namespace dmk;
+    const int64_t n = P->n;
+    int L = 1;
+    while (L < 8 && (double)n / (double)(1ll << (3 * L)) > (double)P->prm.ns)
+        ++L;
+    if (!ewald_grid(P->prm, L, &P->eg))
+        return fail(DMK_ERR_UNSUPPORTED, "no spectral Ewald grid for this tolerance and size");
+    const EwaldGrid& E = P->eg;
+    if (E.M > 768)
+        return fail(DMK_ERR_UNSUPPORTED, "spectral Ewald grid above 768^3 (use the DMK method)");
+    if ((int)E.g_cheb.size() > (int)(sizeof(P->gpoly.a) / sizeof(double)))
+        return fail(DMK_ERR_UNSUPPORTED, "gridding kernel series too long");
+    P->gpoly.nc = (int)E.g_cheb.size();
+    for (int k = 0; k < P->gpoly.nc; ++k)
+        P->gpoly.a[k] = E.g_cheb[k];
+    auto ranges = [&](int level) {
+        const int64_t nc = 1ll << (3 * level);
+        std::vector<int64_t> r(nc + 1);
+        const int sh = 3 * (kKeyBits - level);
+        for (int64_t c = 0; c <= nc; ++c)
+            r[c] = std::lower_bound(keys.begin(), keys.end(), (uint64_t)c << sh) - keys.begin();
+        return r;
+    };
+    const std::vector<int64_t> ts = ranges(E.Lt);
+    const std::vector<int64_t> cs = ranges(L);
+    // near field: cells of side 2^-L, residual at level L
+    const int NC = 1 << L;
+    std::vector<int> cbase((size_t)1 << (3 * L), -1);
+    std::vector<int64_t> cstart;
+    std::vector<int> clen;
+    for (size_t c = 0; c + 1 < cs.size(); ++c) {
+        if (cs[c + 1] == cs[c])
+            continue;
+        cbase[c] = (int)cstart.size();
+        for (int64_t a = cs[c]; a < cs[c + 1]; a += 64) {
+            cstart.push_back(a);
+            clen.push_back((int)std::min<int64_t>(64, cs[c + 1] - a));
+        }
+    }
+    std::vector<NearLeaf> nlv;
+    std::vector<NearEntryDev> nent;
+    std::vector<NearWork> nwk;
+    P->near_listed = 0;
+    P->n_cells_nonempty = 0;
+    for (int64_t ix = 0; ix < NC; ++ix)
+        for (int64_t iy = 0; iy < NC; ++iy)
+            for (int64_t iz = 0; iz < NC; ++iz) {
+                const uint64_t c = cell_code(ix, iy, iz, L);
+                if (cs[c + 1] == cs[c])
+                    continue;
+                ++P->n_cells_nonempty;
+                NearLeaf T;
+                T.tstart = cs[c];
+                T.tend = cs[c + 1];
+                T.level = L;
+                T.cbase = cbase[c];
+                T.ebeg = (int)nent.size();
+                for (int d = 0; d < 27; ++d) {
+                    const int64_t o[3] = {d / 9 - 1, (d / 3) % 3 - 1, d % 3 - 1};
+                    const int64_t v[3] = {ix + o[0], iy + o[1], iz + o[2]};
+                    int64_t w[3];
+                    int8_t sh[3];
+                    for (int k = 0; k < 3; ++k) {
+                        w[k] = v[k];
+                        sh[k] = 0;
+                        if (w[k] < 0) {
+                            w[k] += NC;
+                            sh[k] = -1;
+                        } else if (w[k] >= NC) {
+                            w[k] -= NC;
+                            sh[k] = 1;
+                        }
+                    }
+                    const uint64_t sc = cell_code(w[0], w[1], w[2], L);
+                    if (cs[sc + 1] == cs[sc])
+                        continue;
+                    NearEntryDev e;
+                    e.sstart = cs[sc];
+                    e.send = cs[sc + 1];
+                    e.cbase = cbase[sc];
+                    e.sx = sh[0];
+                    e.sy = sh[1];
+                    e.sz = sh[2];
+                    e.lambda = (int8_t)L;
+                    nent.push_back(e);
+                    P->near_listed += (T.tend - T.tstart) * (e.send - e.sstart);
+                }
+                T.eend = (int)nent.size();
+                const int li = (int)nlv.size();
+                const int tg = 64 / P->near_sg;
+                const int nch = (int)((T.tend - T.tstart + tg - 1) / tg);
+                for (int k = 0; k < nch; ++k)
+                    nwk.push_back(NearWork{li, k});
+                nlv.push_back(T);
+            }
+    P->n_nwork = (int)nwk.size();
+    P->nleaves = P->mem.alloc<NearLeaf>(nlv.size());
+    P->nentries = P->mem.alloc<NearEntryDev>(nent.size());
+    P->nwork = P->mem.alloc<NearWork>(nwk.size());
+    P->cbbox = P->mem.alloc<double>(cstart.size() * 6);
+    int64_t* d_cstart = P->mem.alloc<int64_t>(cstart.size());
+    int* d_clen = P->mem.alloc<int>(clen.size());
+    P->tile_start = P->mem.alloc<int64_t>(ts.size());
+    const size_t M = E.M, M3 = M * M * M, H = M * M * (M / 2 + 1);
+    P->egrid = P->mem.alloc<double>(3 * M3);
+    P->espec = P->mem.alloc<double2>(3 * H);
+    P->eghat = P->mem.alloc<double>(E.ghat.size());
+    P->ewsym = P->mem.alloc<double>(E.wsym.size());
+    P->fs = P->mem.alloc<double>(3 * (size_t)n);
+    P->u = P->mem.alloc<double>(3 * (size_t)n);
+    if (P->mem.oom)
+        return fail(DMK_ERR_OOM, "device allocation failed (or above mem_cap_bytes)");
+    HIPCHK(upload(P->nleaves, nlv, st));
+    HIPCHK(upload(P->nentries, nent, st));
+    HIPCHK(upload(P->nwork, nwk, st));
+    HIPCHK(upload(d_cstart, cstart, st));
+    HIPCHK(upload(d_clen, clen, st));
+    HIPCHK(upload(P->tile_start, ts, st));
+    HIPCHK(upload(P->eghat, E.ghat, st));
+    HIPCHK(upload(P->ewsym, E.wsym, st));
+    launch_chunk_bbox(P->x, P->y, P->z, d_cstart, d_clen, (int)cstart.size(), P->cbbox, st);
+    if (!make_poly(*P->tab, &P->poly))
+        return fail(DMK_ERR_UNSUPPORTED, "radial fit degree too high");
+    int dims[3] = {(int)M, (int)M, (int)M};
+    if (hipfftPlanMany(&P->fft_fwd, 3, dims, nullptr, 1, (int)M3, nullptr, 1, (int)H, HIPFFT_D2Z, 3) !=
+        HIPFFT_SUCCESS)
+        return fail(DMK_ERR_HIP, "hipfftPlanMany (forward) failed");
+    if (hipfftPlanMany(&P->fft_inv, 3, dims, nullptr, 1, (int)H, nullptr, 1, (int)M3, HIPFFT_Z2D, 3) !=
+        HIPFFT_SUCCESS) {
+        (void)hipfftDestroy(P->fft_fwd);
+        return fail(DMK_ERR_HIP, "hipfftPlanMany (inverse) failed");
+    }
+    P->fft_made = true;
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipGetLastError());
+    return DMK_OK;
 }
 
 int build_plan(dmk_plan_t P, const double* points)
@@ -513,6 +694,17 @@ int build_plan(dmk_plan_t P, const double* points)
     HIPCHK(hipMemcpyAsync(keys.data(), k1, n * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     lap(1);
+    if (P->method == DMK_METHOD_EWALD) {
+        P->x = P->mem.alloc<double>(n);
+        P->y = P->mem.alloc<double>(n);
+        P->z = P->mem.alloc<double>(n);
+        if (P->mem.oom)
+            return fail(DMK_ERR_OOM, "device allocation failed");
+        launch_gather_points(points, n, P->perm, P->pid, P->geo, P->x, P->y, P->z, st);
+        const int rc = build_ewald(P, keys, st);
+        lap(2);
+        return rc;
+    }
     // ---- tree (a forest of one octree per problem) ----
     const int ns = P->prm.ns;
     std::vector<int> roots(1, 0);
@@ -1000,6 +1192,51 @@ int eval_stresslet(dmk_plan_t P, const double* f, const double* nv, double* vel,
     return DMK_OK;
 }
 
+// One force vector by the single-level spectral Ewald method: sorted forces,
+// spreading to the grid, forward FFT, scaling by the mollified kernel and the
+// gridding deconvolution, inverse FFT, interpolation at the points, the
+// residual between neighbouring cells (self term from the r = 0 pair), and
+// unpermute.  Phase events: spreading in the anterpolation slot, the FFTs
+// and scaling in the root slot, interpolation in the leaf-evaluation slot.
+int eval_ewald(dmk_plan_t P, const double* f, double* vel, bool record)
+{
+    using namespace dmk;
+    hipStream_t st = P->stream;
+    const int64_t n = P->n;
+    const EwaldGrid& E = P->eg;
+    auto mark = [&](int k) {
+        if (record)
+            (void)hipEventRecord(P->ev[k], st);
+    };
+    mark(0);
+    launch_gather_forces(f, n, P->nsrc, P->perm, P->fs, st);
+    launch_ewald_spread(E.M, E.B, E.Lt, E.w, P->gpoly, P->tile_start, P->x, P->y, P->z, P->fs, n, P->egrid, st);
+    for (int k = 1; k <= 5; ++k)
+        mark(k);
+    if (hipfftSetStream(P->fft_fwd, st) != HIPFFT_SUCCESS || hipfftSetStream(P->fft_inv, st) != HIPFFT_SUCCESS)
+        return fail(DMK_ERR_HIP, "hipfftSetStream failed");
+    if (hipfftExecD2Z(P->fft_fwd, (hipfftDoubleReal*)P->egrid, (hipfftDoubleComplex*)P->espec) != HIPFFT_SUCCESS)
+        return fail(DMK_ERR_HIP, "forward FFT failed");
+    launch_ewald_scale(E.M, E.K, P->eghat, P->ewsym, P->espec, st);
+    if (hipfftExecZ2D(P->fft_inv, (hipfftDoubleComplex*)P->espec, (hipfftDoubleReal*)P->egrid) != HIPFFT_SUCCESS)
+        return fail(DMK_ERR_HIP, "inverse FFT failed");
+    mark(6);
+    mark(7);
+    launch_ewald_interp(E.M, E.B, E.Lt, E.w, P->gpoly, P->tile_start, P->x, P->y, P->z, n, P->egrid, P->u, st);
+    mark(8);
+    mark(DMK_NUM_PHASES + 1);
+    launch_near(DMK_KERNEL_STOKESLET, P->near_sg, 1, P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x,
+                P->y, P->z, P->fs, n, P->poly, P->u, st);
+    mark(9);
+    launch_finalize(P->u, n, P->perm, P->tofs, P->pid, P->scale, 0, nullptr, nullptr, nullptr, nullptr, nullptr, vel,
+                    st);
+    if (record) {
+        (void)hipEventRecord(P->ev[10], st);
+        P->ev_recorded = true;
+    }
+    return DMK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1117,6 +1354,11 @@ int create_plan(const double* points, const std::vector<int64_t>& offsets, int d
     }
     P->kern = kern;
     P->nc_in = kern == DMK_KERNEL_STRESSLET ? 6 : 3;
+    P->method = opts ? opts->method : DMK_METHOD_DMK;
+    if (P->method == DMK_METHOD_EWALD && (!periodic || offsets.size() != 2 || nsrc >= 0)) {
+        delete P;
+        return fail(DMK_ERR_UNSUPPORTED, "the spectral Ewald method takes one periodic problem without separate targets");
+    }
     if (opts)
         dmk::override_params(&P->prm, opts->q, opts->p);
     P->tab = dmk::get_tables(P->prm);
@@ -1254,6 +1496,22 @@ int dmk_stokes_eval(dmk_plan_t plan, const double* forces, int n_rhs, double* ve
         return fail(DMK_ERR_ARG, "plan is NULL");
     if (plan->kern != DMK_KERNEL_STOKESLET)
         return fail(DMK_ERR_ARG, "a stresslet plan is evaluated with dmk_stokes_eval_stresslet");
+    if (plan->method == DMK_METHOD_EWALD) {
+        if (n_rhs < 1)
+            return fail(DMK_ERR_ARG, "n_rhs must be >= 1");
+        if (!is_device_ptr(forces) || !is_device_ptr(velocities))
+            return fail(DMK_ERR_ARG, "forces and velocities must be device pointers");
+        for (int r = 0; r < n_rhs; ++r) {
+            const int rc = eval_ewald(plan, forces + (size_t)r * 3 * plan->n, velocities + (size_t)r * 3 * plan->n,
+                                      plan->timing && r == 0);
+            if (rc != DMK_OK)
+                return rc;
+        }
+        HIPCHK(hipEventRecord(plan->done, plan->stream));
+        plan->done_recorded = true;
+        HIPCHK(hipGetLastError());
+        return DMK_OK;
+    }
     if (n_rhs < 1)
         return fail(DMK_ERR_ARG, "n_rhs must be >= 1");
     if (!is_device_ptr(forces) || !is_device_ptr(velocities))
@@ -1494,6 +1752,17 @@ int dmk_stokes_plan_info(dmk_plan_t plan, dmk_plan_info* info)
     info->window = P.prm.window;
     info->sigma = P.prm.sigma;
     info->kernel = P.kern;
+    info->method = P.method;
+    if (P.method == DMK_METHOD_EWALD) {
+        info->levels = P.eg.L + 1;
+        info->n_leaves = (int64_t)1 << (3 * P.eg.L);
+        info->n_boxes = info->n_leaves;
+        info->n_nonempty_leaves = P.n_cells_nonempty;
+        info->n_nonempty_boxes = P.n_cells_nonempty;
+        info->ewald_grid = P.eg.M;
+        info->ewald_modes = P.eg.K;
+        info->ewald_width = P.eg.w;
+    }
     return DMK_OK;
 }
 
@@ -1502,6 +1771,8 @@ int dmk_stokes_tree_leaves(dmk_plan_t plan, int32_t* leaf_level, int64_t* leaf_c
 {
     if (!plan)
         return fail(DMK_ERR_ARG, "plan is NULL");
+    if (plan->method != DMK_METHOD_DMK)
+        return fail(DMK_ERR_ARG, "a spectral Ewald plan has no octree");
     const dmk_plan_s& P = *plan;
     const auto& B = P.tree.boxes;
     for (size_t li = 0; li < P.leaf_box.size(); ++li) {

@@ -1,0 +1,338 @@
+// Spreading, Fourier-space scaling and interpolation of the single-level
+// spectral Ewald variant on the periodic unit cell.
+#include "ewald_kernels.hpp"
+
+#include <algorithm>
+
+namespace dmk {
+
+namespace {
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+__device__ inline uint32_t spread3(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ inline uint32_t compact3(uint32_t v)
+{
+    v &= 0x09249249u;
+    v = (v ^ (v >> 2)) & 0x030C30C3u;
+    v = (v ^ (v >> 4)) & 0x0300F00Fu;
+    v = (v ^ (v >> 8)) & 0xFF0000FFu;
+    v = (v ^ (v >> 16)) & 0x000003FFu;
+    return v;
+}
+
+// Morton code of a tile (digit 4 bx + 2 by + bz, as the point keys)
+__device__ inline uint32_t tile_code(int tx, int ty, int tz)
+{
+    return (spread3((uint32_t)tx) << 2) | (spread3((uint32_t)ty) << 1) | spread3((uint32_t)tz);
+}
+
+// gridding kernel, Clenshaw in v = 2 t^2 - 1; 0 for |t| >= 1
+__device__ inline double gker(const GridPoly& g, double t)
+{
+    if (!(fabs(t) < 1.0))
+        return 0.0;
+    const double v = fma(2.0 * t, t, -1.0);
+    double b1 = 0.0, b2 = 0.0;
+    for (int k = g.nc - 1; k >= 1; --k) {
+        const double b0 = fma(2.0 * v, b1, -b2) + g.a[k];
+        b2 = b1;
+        b1 = b0;
+    }
+    return fma(v, b1, -b2) + g.a[0];
+}
+
+// grid coordinate of a point of tile coordinate tc, kept inside that tile
+// (its Morton key and its coordinate agree up to rounding)
+__device__ inline double grid_coord(double x, int M, int B, int tc)
+{
+    const double t0 = (double)(tc * B);
+    const double X = (x + 0.5) * (double)M;
+    return fmin(fmax(X, t0), nextafter(t0 + (double)B, 0.0));
+}
+
+constexpr int kSpreadChunk = 256;
+
+// One block per tile.  The block walks the points of the 27 neighbouring
+// tiles (periodic images included) in chunks: every candidate whose stencil
+// overlaps this tile gets its B weights per axis at this tile's grid lines,
+// and the survivors are packed, in candidate order, into LDS.  Each thread
+// then accumulates its own grid points over the packed candidates, so every
+// grid value is summed in a fixed order and written once.
+template <int B>
+__global__ __launch_bounds__(256) void k_ewald_spread(int M, int Lt, int w, GridPoly g,
+                                                      const int64_t* __restrict__ tile_start,
+                                                      const double* __restrict__ x, const double* __restrict__ y,
+                                                      const double* __restrict__ z, const double* __restrict__ fs,
+                                                      int64_t n, double* __restrict__ grid)
+{
+    constexpr int B3 = B * B * B;
+    constexpr int NO = (B3 + 255) / 256;  // owned grid points per thread
+    __shared__ double wt[kSpreadChunk][3][B];
+    __shared__ double ff[kSpreadChunk][3];
+    __shared__ int wtot[4];
+    const int NT = 1 << Lt;
+    const uint32_t code = blockIdx.x;
+    const int tc[3] = {(int)compact3(code >> 2), (int)compact3(code >> 1), (int)compact3(code)};
+    const int T0[3] = {tc[0] * B, tc[1] * B, tc[2] * B};
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double hw = 0.5 * w;
+    double acc[NO][3];
+#pragma unroll
+    for (int s = 0; s < NO; ++s)
+        acc[s][0] = acc[s][1] = acc[s][2] = 0.0;
+    for (int nb = 0; nb < 27; ++nb) {
+        const int d[3] = {nb / 9 - 1, (nb / 3) % 3 - 1, nb % 3 - 1};
+        int nt[3];
+        double wrap[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            int v = tc[k] + d[k];
+            wrap[k] = 0.0;
+            if (v < 0) {
+                v += NT;
+                wrap[k] = -(double)M;
+            } else if (v >= NT) {
+                v -= NT;
+                wrap[k] = (double)M;
+            }
+            nt[k] = v;
+        }
+        const uint32_t ncode = tile_code(nt[0], nt[1], nt[2]);
+        const int64_t ps = tile_start[ncode], pe = tile_start[ncode + 1];
+        for (int64_t c0 = ps; c0 < pe; c0 += kSpreadChunk) {
+            const int64_t i = c0 + tid;
+            bool keep = false;
+            double X[3] = {0.0, 0.0, 0.0};
+            if (i < pe) {
+                const double pc[3] = {x[i], y[i], z[i]};
+                keep = true;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    X[k] = grid_coord(pc[k], M, B, nt[k]) + wrap[k];
+                    const int n0 = (int)ceil(X[k] - hw);
+                    keep = keep && n0 <= T0[k] + B - 1 && n0 + w - 1 >= T0[k];
+                }
+            }
+            const unsigned long long mask = __ballot(keep);
+            const int pos = __popcll(mask & ((1ull << lane) - 1ull));
+            __syncthreads();  // the previous chunk's accumulation is done with wt / ff
+            if (lane == 0)
+                wtot[wave] = __popcll(mask);
+            __syncthreads();
+            int base = 0;
+            for (int v = 0; v < wave; ++v)
+                base += wtot[v];
+            const int kept = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+            if (keep) {
+                const int slot = base + pos;
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int j = 0; j < B; ++j)
+                        wt[slot][k][j] = gker(g, (X[k] - (double)(T0[k] + j)) / hw);
+                ff[slot][0] = fs[i];
+                ff[slot][1] = fs[n + i];
+                ff[slot][2] = fs[2 * n + i];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < NO; ++s) {
+                const int gp = tid + 256 * s;
+                if (gp < B3) {
+                    const int ix = gp / (B * B), iy = (gp / B) % B, iz = gp % B;
+                    for (int c = 0; c < kept; ++c) {
+                        const double wv = wt[c][0][ix] * wt[c][1][iy] * wt[c][2][iz];
+                        acc[s][0] = fma(wv, ff[c][0], acc[s][0]);
+                        acc[s][1] = fma(wv, ff[c][1], acc[s][1]);
+                        acc[s][2] = fma(wv, ff[c][2], acc[s][2]);
+                    }
+                }
+            }
+        }
+    }
+    const size_t M3 = (size_t)M * M * M;
+#pragma unroll
+    for (int s = 0; s < NO; ++s) {
+        const int gp = tid + 256 * s;
+        if (gp < B3) {
+            const int ix = gp / (B * B), iy = (gp / B) % B, iz = gp % B;
+            const size_t o = ((size_t)(T0[0] + ix) * M + (T0[1] + iy)) * M + (T0[2] + iz);
+            grid[o] = acc[s][0];
+            grid[M3 + o] = acc[s][1];
+            grid[2 * M3 + o] = acc[s][2];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ewald_scale(int M, int K, const double* __restrict__ ghat,
+                                                     const double* __restrict__ wsym, double2* __restrict__ spec)
+{
+    const int Mh = M / 2 + 1;
+    const int64_t H = (int64_t)M * M * Mh;
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= H)
+        return;
+    const int k3 = (int)(e % Mh);
+    const int64_t r = e / Mh;
+    const int j = (int)(r % M), i = (int)(r / M);
+    const int k1 = i <= M / 2 ? i : i - M;
+    const int k2 = j <= M / 2 ? j : j - M;
+    const int a1 = abs(k1), a2 = abs(k2);
+    const int m2 = k1 * k1 + k2 * k2 + k3 * k3;
+    if (a1 > K || a2 > K || k3 > K || m2 == 0) {
+        spec[e] = make_double2(0.0, 0.0);
+        spec[H + e] = make_double2(0.0, 0.0);
+        spec[2 * H + e] = make_double2(0.0, 0.0);
+        return;
+    }
+    const double gg = ghat[a1] * ghat[a2] * ghat[k3];
+    const double wv = wsym[m2] / (gg * gg);
+    const double2 F0 = spec[e], F1 = spec[H + e], F2 = spec[2 * H + e];
+    const double inv = 1.0 / (double)m2;
+    const double dr = (k1 * F0.x + k2 * F1.x + k3 * F2.x) * inv;
+    const double di = (k1 * F0.y + k2 * F1.y + k3 * F2.y) * inv;
+    spec[e] = make_double2(wv * (F0.x - k1 * dr), wv * (F0.y - k1 * di));
+    spec[H + e] = make_double2(wv * (F1.x - k2 * dr), wv * (F1.y - k2 * di));
+    spec[2 * H + e] = make_double2(wv * (F2.x - k3 * dr), wv * (F2.y - k3 * di));
+}
+
+constexpr int kInterpChunk = 32;
+constexpr int kMaxW = 10;
+
+// One block per tile: the tile's grid region [O, O + B + w)^3 (O = T0 - w/2,
+// periodic) of the 3 components goes to LDS; the tile's points follow in
+// chunks: one thread per (point, axis) forms the stencil weights, one per
+// (point, x offset) sums its plane of the stencil, and one per point adds the
+// planes in a fixed order.
+__global__ __launch_bounds__(256) void k_ewald_interp(int M, int B, int Lt, int w, GridPoly g,
+                                                      const int64_t* __restrict__ tile_start,
+                                                      const double* __restrict__ x, const double* __restrict__ y,
+                                                      const double* __restrict__ z, int64_t n,
+                                                      const double* __restrict__ grid, double* __restrict__ u)
+{
+    extern __shared__ double smem[];
+    const int R = B + w;
+    const int R3 = R * R * R;
+    double* reg = smem;                                   // [3][R][R][R]
+    double* wts = reg + 3 * R3;                           // [CH][3][kMaxW]
+    double* part = wts + kInterpChunk * 3 * kMaxW;        // [CH][kMaxW][3]
+    int* a0s = (int*)(part + kInterpChunk * kMaxW * 3);   // [CH][3]
+    const uint32_t code = blockIdx.x;
+    const int tc[3] = {(int)compact3(code >> 2), (int)compact3(code >> 1), (int)compact3(code)};
+    const int hwi = w / 2;
+    const int O[3] = {tc[0] * B - hwi, tc[1] * B - hwi, tc[2] * B - hwi};
+    const int tid = threadIdx.x;
+    const size_t M3 = (size_t)M * M * M;
+    for (int e = tid; e < 3 * R3; e += 256) {
+        const int c = e / R3, r = e - c * R3;
+        const int a = r / (R * R), b = (r / R) % R, cz = r % R;
+        const int gx = ((O[0] + a) % M + M) % M;
+        const int gy = ((O[1] + b) % M + M) % M;
+        const int gz = ((O[2] + cz) % M + M) % M;
+        reg[e] = grid[c * M3 + ((size_t)gx * M + gy) * M + gz];
+    }
+    const int64_t ps = tile_start[code], pe = tile_start[code + 1];
+    const double hw = 0.5 * w;
+    for (int64_t c0 = ps; c0 < pe; c0 += kInterpChunk) {
+        const int cnt = (int)min((int64_t)kInterpChunk, pe - c0);
+        __syncthreads();  // region loaded / previous chunk finished
+        if (tid < 3 * cnt) {
+            const int p = tid / 3, k = tid % 3;
+            const int64_t i = c0 + p;
+            const double pc = k == 0 ? x[i] : (k == 1 ? y[i] : z[i]);
+            const double X = grid_coord(pc, M, B, tc[k]);
+            const int n0 = (int)ceil(X - hw);
+            a0s[p * 3 + k] = n0 - O[k];
+            for (int s = 0; s < kMaxW; ++s)
+                wts[(p * 3 + k) * kMaxW + s] = s < w ? gker(g, (X - (double)(n0 + s)) / hw) : 0.0;
+        }
+        __syncthreads();
+        for (int it = tid; it < cnt * w; it += 256) {
+            const int p = it / w, sx = it % w;
+            const int ax = a0s[p * 3] + sx, ay0 = a0s[p * 3 + 1], az0 = a0s[p * 3 + 2];
+            const double* wy = wts + (p * 3 + 1) * kMaxW;
+            const double* wz = wts + (p * 3 + 2) * kMaxW;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int sy = 0; sy < w; ++sy) {
+                const int rb = (ax * R + ay0 + sy) * R + az0;
+                double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+                for (int sz = 0; sz < w; ++sz) {
+                    const double wv = wz[sz];
+                    t0 = fma(wv, reg[rb + sz], t0);
+                    t1 = fma(wv, reg[R3 + rb + sz], t1);
+                    t2 = fma(wv, reg[2 * R3 + rb + sz], t2);
+                }
+                s0 = fma(wy[sy], t0, s0);
+                s1 = fma(wy[sy], t1, s1);
+                s2 = fma(wy[sy], t2, s2);
+            }
+            const double wx = wts[(p * 3) * kMaxW + sx];
+            part[(p * kMaxW + sx) * 3] = wx * s0;
+            part[(p * kMaxW + sx) * 3 + 1] = wx * s1;
+            part[(p * kMaxW + sx) * 3 + 2] = wx * s2;
+        }
+        __syncthreads();
+        if (tid < cnt) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int sx = 0; sx < w; ++sx) {
+                s0 += part[(tid * kMaxW + sx) * 3];
+                s1 += part[(tid * kMaxW + sx) * 3 + 1];
+                s2 += part[(tid * kMaxW + sx) * 3 + 2];
+            }
+            const int64_t i = c0 + tid;
+            u[i] = s0;
+            u[n + i] = s1;
+            u[2 * n + i] = s2;
+        }
+    }
+}
+
+}  // namespace
+
+void launch_ewald_spread(int M, int B, int Lt, int w, const GridPoly& g, const int64_t* tile_start, const double* x,
+                         const double* y, const double* z, const double* fs, int64_t n, double* grid, hipStream_t s)
+{
+    const unsigned ntile = 1u << (3 * Lt);
+    if (B == 6)
+        hipLaunchKernelGGL(k_ewald_spread<6>, dim3(ntile), dim3(256), 0, s, M, Lt, w, g, tile_start, x, y, z, fs, n,
+                           grid);
+    else
+        hipLaunchKernelGGL(k_ewald_spread<8>, dim3(ntile), dim3(256), 0, s, M, Lt, w, g, tile_start, x, y, z, fs, n,
+                           grid);
+}
+
+void launch_ewald_scale(int M, int K, const double* ghat, const double* wsym, double2* spec, hipStream_t s)
+{
+    const int64_t H = (int64_t)M * M * (M / 2 + 1);
+    hipLaunchKernelGGL(k_ewald_scale, dim3(nblk(H, 256)), dim3(256), 0, s, M, K, ghat, wsym, spec);
+}
+
+void launch_ewald_interp(int M, int B, int Lt, int w, const GridPoly& g, const int64_t* tile_start,
+                         const double* x, const double* y, const double* z, int64_t n, const double* grid,
+                         double* u, hipStream_t s)
+{
+    const int R = B + w;
+    const size_t shm = (size_t)3 * R * R * R * sizeof(double) + (size_t)kInterpChunk * 3 * kMaxW * sizeof(double) +
+                       (size_t)kInterpChunk * kMaxW * 3 * sizeof(double) + (size_t)kInterpChunk * 3 * sizeof(int);
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void*)k_ewald_interp, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        attr = true;
+    }
+    const unsigned ntile = 1u << (3 * Lt);
+    hipLaunchKernelGGL(k_ewald_interp, dim3(ntile), dim3(256), shm, s, M, B, Lt, w, g, tile_start, x, y, z, n, grid,
+                       u);
+}
+
+}  // namespace dmk

@@ -709,3 +709,91 @@ const Tables* get_tables(double tol)
 }
 
 }  // namespace dmk
+
+namespace dmk {
+
+bool ewald_grid(const Params& prm, int L, EwaldGrid* out)
+{
+    if (L < 1 || L > 8 || prm.window != 0 || prm.kernel != 0)
+        return false;
+    EwaldGrid& E = *out;
+    E.L = L;
+    const double rc = 1.0 / (double)(1 << L);
+    // strict |k_i| < c / r_c with k = 2 pi kappa: |kappa_i| < q 2^L / 6
+    const double lim = prm.q * (double)(1 << L) / 6.0;
+    E.K = (int)std::ceil(lim) - 1;
+    // gridding kernel width: the aliasing error of a prolate kernel of width w
+    // at oversampling sigma falls like exp(-pi w (1 - 1/(2 sigma)))
+    E.w = prm.tol >= 1e-3 * (1 - 1e-9) ? 6 : prm.tol >= 1e-6 * (1 - 1e-9) ? 8 : prm.tol >= 1e-9 * (1 - 1e-9) ? 10 : 0;
+    if (E.w == 0)
+        return false;
+    // grid M = B 2^Lt, B in {6, 8}, the smallest with oversampling >= 1.9
+    const int need = (int)std::ceil(1.9 * (2 * E.K + 1));
+    int best = 0, bB = 0, bL = 0;
+    for (int B : {6, 8})
+        for (int Lt = 0; Lt <= 9; ++Lt) {
+            const int M = B << Lt;
+            // the LDS region of a tile holds (B + w)^3 grid values of 3 components
+            const bool fits = (size_t)(B + E.w) * (B + E.w) * (B + E.w) * 3 * 8 <= 150 * 1024;
+            if (M >= need && (best == 0 || M < best) && 2 * B >= E.w && fits) {
+                best = M;
+                bB = B;
+                bL = Lt;
+            }
+        }
+    if (best == 0)
+        return false;
+    E.M = best;
+    E.B = bB;
+    E.Lt = bL;
+    E.sigma = (double)E.M / (2 * E.K + 1);
+    E.beta = kPi * E.w * (1.0 - 1.0 / (2.0 * E.sigma));
+    const Prolate g(E.beta);
+    const double g0 = g.phi(0.0);
+    // Chebyshev coefficients in v = 2 t^2 - 1 on [-1, 1]
+    const int N = 64;
+    std::vector<double> fv(N);
+    for (int j = 0; j < N; ++j) {
+        const double v = std::cos((2.0 * j + 1) * kPi / (2.0 * N));
+        fv[j] = g.phi(std::sqrt(0.5 * (v + 1.0))) / g0;
+    }
+    std::vector<double> a(N);
+    for (int k = 0; k < N; ++k) {
+        double acc = 0;
+        for (int j = 0; j < N; ++j)
+            acc += fv[j] * std::cos(k * (2.0 * j + 1) * kPi / (2.0 * N));
+        a[k] = (k == 0 ? 1.0 : 2.0) * acc / N;
+    }
+    // keep the terms up to where the series first stays below 1e-15 for 6
+    // consecutive terms (beyond it is rounding noise)
+    int d = N - 1;
+    for (int k = 1; k + 6 < N; ++k) {
+        bool small = true;
+        for (int j = k; j < k + 6; ++j)
+            small = small && std::fabs(a[j]) < 1e-15;
+        if (small) {
+            d = k - 1;
+            break;
+        }
+    }
+    a.resize(d + 1);
+    E.g_cheb = a;
+    // ghat: g as a function of x in cell units has half-width alpha = w / (2M):
+    // ghat(k) = alpha phihat(k alpha) / phi(0)
+    const double alpha = E.w / (2.0 * E.M);
+    E.ghat.assign(E.M / 2 + 1, 0.0);
+    for (int kap = 0; kap <= E.M / 2; ++kap)
+        E.ghat[kap] = alpha * g.phihat(2.0 * kPi * kap * alpha) / g0;
+    // symbol with the grid factors h^6 folded in
+    const double h = 1.0 / E.M, h6 = h * h * h * h * h * h;
+    const Prolate win(prm.c);
+    const int m2max = 3 * E.K * E.K;
+    E.wsym.assign(m2max + 1, 0.0);
+    for (int m2 = 1; m2 <= m2max; ++m2) {
+        const double k = 2.0 * kPi * std::sqrt((double)m2);
+        E.wsym[m2] = h6 * win.gammahat(k * rc) / (k * k);
+    }
+    return true;
+}
+
+}  // namespace dmk

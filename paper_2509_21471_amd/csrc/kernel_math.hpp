@@ -105,6 +105,30 @@ RadialFits fit_radial(const Window& w, double fit_tol);
 // Returned in the P (= A) and Q (= D) slots.
 RadialFits fit_radial_stresslet(const Window& w, double fit_tol);
 
+// Single-level spectral Ewald on the periodic unit cell with the prolate
+// split at r_c = 2^-L (the uniform-data variant of the method, Sec.
+// "Ewald summation"): near field = the residual between cells of side r_c;
+// far field = sum over 0 < |kappa_i| <= K of (I - k k^T/k^2) gammahat(k r_c)/k^2
+// F(k) e^{ik.x}, k = 2 pi kappa, by spreading to an M^3 grid with a prolate
+// gridding kernel of w points, FFT, scaling, inverse FFT and interpolation.
+struct EwaldGrid {
+    int L;            // split level
+    int K;            // |kappa_i| <= K (strict |k_i| < c / r_c)
+    int M;            // grid points per dimension, M = B 2^Lt
+    int B, Lt;        // tile side in grid points, tile level
+    int w;            // gridding kernel width in grid points
+    double beta;      // prolate parameter of the gridding kernel
+    double sigma;     // oversampling M / (2K + 1)
+    // gridding kernel g(t) = psi_0^beta(t)/psi_0^beta(0), |t| <= 1, t = (X - n)/(w/2)
+    // in grid units, as sum_k a_k T_k(2 t^2 - 1)
+    std::vector<double> g_cheb;
+    std::vector<double> ghat;   // kappa = 0..M/2: 1D transform of g(x) at k = 2 pi kappa (x in cell units)
+    std::vector<double> wsym;   // by |kappa|^2 <= 3 K^2: h^6 gammahat(k r_c)/k^2 (0 at kappa = 0)
+};
+// Fills the grid parameters for tol's row (q) and split level L (1..8);
+// false when the kernel width the tolerance needs does not fit the LDS tiles.
+bool ewald_grid(const Params& prm, int L, EwaldGrid* out);
+
 // Gauss-Legendre nodes and weights on [-1,1].
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 

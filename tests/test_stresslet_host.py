@@ -85,3 +85,26 @@ def test_stresslet_argument_validation_without_gpu():
     tuned = dmk._lib.Opts()
     assert lib.dmk_stokes_autotune(vp, 10, None, 0, 3, 0, 1e-6, ctypes.byref(st), 1, ctypes.byref(tuned),
                                    None) == -2
+
+
+def test_ewald_method_argument_validation_without_gpu():
+    """DMK_METHOD_EWALD: one periodic FP64 prolate Stokeslet problem, tol >= 1e-9."""
+    dmk = _dmk()
+    lib = dmk.lib()
+    out = ctypes.c_void_p()
+    host = (ctypes.c_double * 30)()
+    vp = ctypes.cast(host, ctypes.c_void_p)
+    O = dmk._lib.Opts
+    ew = O(0, 0, None, 0, 0, 0, 0, 0, 0, 0, 0, 1)
+    # passes validation, stops at the host pointer
+    assert lib.dmk_stokes_plan_ex(vp, 10, 3, 1, 1e-6, ctypes.byref(ew), ctypes.byref(out)) == -1
+    assert lib.dmk_stokes_plan_ex(vp, 10, 3, 1, 1e-12, ctypes.byref(ew), ctypes.byref(out)) == -5
+    mixed = O(1, 0, None, 0, 0, 0, 0, 0, 0, 0, 0, 1)
+    assert lib.dmk_stokes_plan_ex(vp, 10, 3, 1, 1e-6, ctypes.byref(mixed), ctypes.byref(out)) == -2
+    stress = O(0, 0, None, 0, 0, 0, 0, 0, 0, 0, 1, 1)
+    assert lib.dmk_stokes_plan_ex(vp, 10, 3, 1, 1e-6, ctypes.byref(stress), ctypes.byref(out)) == -2
+    graph = O(0, 0, None, 0, 4, 0, 0, 0, 0, 0, 0, 1)
+    assert lib.dmk_stokes_plan_ex(vp, 10, 3, 1, 1e-6, ctypes.byref(graph), ctypes.byref(out)) == -2
+    bad = O(0, 0, None, 0, 0, 0, 0, 0, 0, 0, 0, 2)
+    assert lib.dmk_stokes_plan_ex(vp, 10, 3, 1, 1e-6, ctypes.byref(bad), ctypes.byref(out)) == -1
+    assert out.value is None
