@@ -321,7 +321,8 @@ int dmk_stokes_near_stats(dmk_plan_t plan, int64_t* listed, int64_t* evaluated, 
  * per-process cache and are reused by later plans of similar size. */
 void dmk_stokes_destroy(dmk_plan_t plan);
 
-/* Frees the cached device buffers of destroyed plans (hipFree). */
+/* Frees the cached device buffers of destroyed plans (hipFree) and the
+ * cached FFT plans of destroyed spectral Ewald plans. */
 void dmk_stokes_release_cached_memory(void);
 
 /* Thread-local description of the last failure of this thread. */

@@ -151,6 +151,19 @@ hipError_t upload(T* dst, const std::vector<T>& src, hipStream_t st)
     return hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st);
 }
 
+// Idle FFT plan pairs of destroyed spectral Ewald plans, by (device, grid
+// size): creating a 3D FFT plan costs tens of milliseconds, so a new plan of
+// the same grid reuses one.  A pair belongs to one live plan at a time.
+struct FftPair {
+    hipfftHandle fwd, inv;
+};
+std::mutex g_fft_mu;
+std::multimap<std::pair<int, int>, FftPair>& fft_pool()
+{
+    static auto* m = new std::multimap<std::pair<int, int>, FftPair>();
+    return *m;
+}
+
 // The library's own stream for plans built with DMK_FLAG_CONCURRENT_PLAN
 // (non-blocking: it does not wait for work on the null stream; default
 // priority).  One per device, created on first use.
@@ -301,8 +314,10 @@ struct dmk_plan_s {
         if (cap_stream)
             (void)hipStreamDestroy(cap_stream);
         if (fft_made) {
-            (void)hipfftDestroy(fft_fwd);
-            (void)hipfftDestroy(fft_inv);
+            int dev = 0;
+            (void)hipGetDevice(&dev);
+            std::lock_guard<std::mutex> lk(g_fft_mu);
+            fft_pool().emplace(std::make_pair(dev, eg.M), FftPair{fft_fwd, fft_inv});
         }
     }
 };
@@ -457,11 +472,11 @@ int build_ewald(dmk_plan_t P, const std::vector<uint64_t>& keys, hipStream_t st)
     const EwaldGrid& E = P->eg;
     if (E.M > 768)
         return fail(DMK_ERR_UNSUPPORTED, "spectral Ewald grid above 768^3 (use the DMK method)");
-    if ((int)E.g_cheb.size() > (int)(sizeof(P->gpoly.a) / sizeof(double)))
+    if ((int)E.g_cheb.size() > kGridTerms)
         return fail(DMK_ERR_UNSUPPORTED, "gridding kernel series too long");
     P->gpoly.nc = (int)E.g_cheb.size();
-    for (int k = 0; k < P->gpoly.nc; ++k)
-        P->gpoly.a[k] = E.g_cheb[k];
+    for (int k = 0; k < kGridTerms; ++k)
+        P->gpoly.a[k] = k < P->gpoly.nc ? E.g_cheb[k] : 0.0;
     auto ranges = [&](int level) {
         const int64_t nc = 1ll << (3 * level);
         std::vector<int64_t> r(nc + 1);
@@ -570,16 +585,30 @@ int build_ewald(dmk_plan_t P, const std::vector<uint64_t>& keys, hipStream_t st)
     launch_chunk_bbox(P->x, P->y, P->z, d_cstart, d_clen, (int)cstart.size(), P->cbbox, st);
     if (!make_poly(*P->tab, &P->poly))
         return fail(DMK_ERR_UNSUPPORTED, "radial fit degree too high");
-    int dims[3] = {(int)M, (int)M, (int)M};
-    if (hipfftPlanMany(&P->fft_fwd, 3, dims, nullptr, 1, (int)M3, nullptr, 1, (int)H, HIPFFT_D2Z, 3) !=
-        HIPFFT_SUCCESS)
-        return fail(DMK_ERR_HIP, "hipfftPlanMany (forward) failed");
-    if (hipfftPlanMany(&P->fft_inv, 3, dims, nullptr, 1, (int)H, nullptr, 1, (int)M3, HIPFFT_Z2D, 3) !=
-        HIPFFT_SUCCESS) {
-        (void)hipfftDestroy(P->fft_fwd);
-        return fail(DMK_ERR_HIP, "hipfftPlanMany (inverse) failed");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(g_fft_mu);
+        auto it = fft_pool().find(std::make_pair(dev, E.M));
+        if (it != fft_pool().end()) {
+            P->fft_fwd = it->second.fwd;
+            P->fft_inv = it->second.inv;
+            fft_pool().erase(it);
+            P->fft_made = true;
+        }
     }
-    P->fft_made = true;
+    if (!P->fft_made) {
+        int dims[3] = {(int)M, (int)M, (int)M};
+        if (hipfftPlanMany(&P->fft_fwd, 3, dims, nullptr, 1, (int)M3, nullptr, 1, (int)H, HIPFFT_D2Z, 3) !=
+            HIPFFT_SUCCESS)
+            return fail(DMK_ERR_HIP, "hipfftPlanMany (forward) failed");
+        if (hipfftPlanMany(&P->fft_inv, 3, dims, nullptr, 1, (int)H, nullptr, 1, (int)M3, HIPFFT_Z2D, 3) !=
+            HIPFFT_SUCCESS) {
+            (void)hipfftDestroy(P->fft_fwd);
+            return fail(DMK_ERR_HIP, "hipfftPlanMany (inverse) failed");
+        }
+        P->fft_made = true;
+    }
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipGetLastError());
     return DMK_OK;
@@ -1844,6 +1873,12 @@ int dmk_stokes_near_stats(dmk_plan_t plan, int64_t* listed, int64_t* evaluated, 
 void dmk_stokes_release_cached_memory(void)
 {
     pool().release_all();
+    std::lock_guard<std::mutex> lk(g_fft_mu);
+    for (auto& e : fft_pool()) {
+        (void)hipfftDestroy(e.second.fwd);
+        (void)hipfftDestroy(e.second.inv);
+    }
+    fft_pool().clear();
 }
 
 void dmk_stokes_destroy(dmk_plan_t plan)

@@ -36,14 +36,16 @@ __device__ inline uint32_t tile_code(int tx, int ty, int tz)
     return (spread3((uint32_t)tx) << 2) | (spread3((uint32_t)ty) << 1) | spread3((uint32_t)tz);
 }
 
-// gridding kernel, Clenshaw in v = 2 t^2 - 1; 0 for |t| >= 1
+// gridding kernel, Clenshaw in v = 2 t^2 - 1 over the zero-padded series
+// (fixed length, so the coefficients sit in scalar registers); 0 for |t| >= 1
 __device__ inline double gker(const GridPoly& g, double t)
 {
     if (!(fabs(t) < 1.0))
         return 0.0;
     const double v = fma(2.0 * t, t, -1.0);
     double b1 = 0.0, b2 = 0.0;
-    for (int k = g.nc - 1; k >= 1; --k) {
+#pragma unroll
+    for (int k = kGridTerms - 1; k >= 1; --k) {
         const double b0 = fma(2.0 * v, b1, -b2) + g.a[k];
         b2 = b1;
         b1 = b0;
@@ -79,7 +81,11 @@ __global__ __launch_bounds__(256) void k_ewald_spread(int M, int Lt, int w, Grid
     constexpr int NO = (B3 + 255) / 256;  // owned grid points per thread
     __shared__ double wt[kSpreadChunk][3][B];
     __shared__ double ff[kSpreadChunk][3];
+    __shared__ double xs[kSpreadChunk][3];
     __shared__ int wtot[4];
+    __shared__ int64_t nb_start[27], nb_off[28];   // neighbour ranges and their prefix counts
+    __shared__ int nb_tile[27][3];
+    __shared__ double nb_wrap[27][3];
     const int NT = 1 << Lt;
     const uint32_t code = blockIdx.x;
     const int tc[3] = {(int)compact3(code >> 2), (int)compact3(code >> 1), (int)compact3(code)};
@@ -90,35 +96,56 @@ __global__ __launch_bounds__(256) void k_ewald_spread(int M, int Lt, int w, Grid
 #pragma unroll
     for (int s = 0; s < NO; ++s)
         acc[s][0] = acc[s][1] = acc[s][2] = 0.0;
-    for (int nb = 0; nb < 27; ++nb) {
-        const int d[3] = {nb / 9 - 1, (nb / 3) % 3 - 1, nb % 3 - 1};
+    // the 27 neighbouring tiles (periodic images) as one flat candidate list
+    if (tid < 27) {
+        const int d[3] = {tid / 9 - 1, (tid / 3) % 3 - 1, tid % 3 - 1};
         int nt[3];
-        double wrap[3];
-#pragma unroll
         for (int k = 0; k < 3; ++k) {
             int v = tc[k] + d[k];
-            wrap[k] = 0.0;
+            double wr = 0.0;
             if (v < 0) {
                 v += NT;
-                wrap[k] = -(double)M;
+                wr = -(double)M;
             } else if (v >= NT) {
                 v -= NT;
-                wrap[k] = (double)M;
+                wr = (double)M;
             }
             nt[k] = v;
+            nb_tile[tid][k] = v;
+            nb_wrap[tid][k] = wr;
         }
         const uint32_t ncode = tile_code(nt[0], nt[1], nt[2]);
-        const int64_t ps = tile_start[ncode], pe = tile_start[ncode + 1];
-        for (int64_t c0 = ps; c0 < pe; c0 += kSpreadChunk) {
-            const int64_t i = c0 + tid;
+        nb_start[tid] = tile_start[ncode];
+        nb_off[tid] = tile_start[ncode + 1] - tile_start[ncode];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int64_t acc0 = 0;
+        for (int v = 0; v < 27; ++v) {
+            const int64_t c = nb_off[v];
+            nb_off[v] = acc0;
+            acc0 += c;
+        }
+        nb_off[27] = acc0;
+    }
+    __syncthreads();
+    const int64_t total = nb_off[27];
+    {
+        for (int64_t c0 = 0; c0 < total; c0 += kSpreadChunk) {
+            const int64_t q = c0 + tid;
             bool keep = false;
             double X[3] = {0.0, 0.0, 0.0};
-            if (i < pe) {
+            int64_t i = 0;
+            if (q < total) {
+                int v = 0;
+                while (nb_off[v + 1] <= q)
+                    ++v;
+                i = nb_start[v] + (q - nb_off[v]);
                 const double pc[3] = {x[i], y[i], z[i]};
                 keep = true;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    X[k] = grid_coord(pc[k], M, B, nt[k]) + wrap[k];
+                    X[k] = grid_coord(pc[k], M, B, nb_tile[v][k]) + nb_wrap[v][k];
                     const int n0 = (int)ceil(X[k] - hw);
                     keep = keep && n0 <= T0[k] + B - 1 && n0 + w - 1 >= T0[k];
                 }
@@ -135,14 +162,18 @@ __global__ __launch_bounds__(256) void k_ewald_spread(int M, int Lt, int w, Grid
             const int kept = wtot[0] + wtot[1] + wtot[2] + wtot[3];
             if (keep) {
                 const int slot = base + pos;
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int j = 0; j < B; ++j)
-                        wt[slot][k][j] = gker(g, (X[k] - (double)(T0[k] + j)) / hw);
+                xs[slot][0] = X[0];
+                xs[slot][1] = X[1];
+                xs[slot][2] = X[2];
                 ff[slot][0] = fs[i];
                 ff[slot][1] = fs[n + i];
                 ff[slot][2] = fs[2 * n + i];
+            }
+            __syncthreads();
+            // the weights of the kept candidates at this tile's grid lines, one per thread
+            for (int it = tid; it < kept * 3 * B; it += 256) {
+                const int slot = it / (3 * B), k = (it / B) % 3, j = it % B;
+                wt[slot][k][j] = gker(g, (xs[slot][k] - (double)(T0[k] + j)) / hw);
             }
             __syncthreads();
 #pragma unroll
@@ -211,9 +242,9 @@ constexpr int kMaxW = 10;
 
 // One block per tile: the tile's grid region [O, O + B + w)^3 (O = T0 - w/2,
 // periodic) of the 3 components goes to LDS; the tile's points follow in
-// chunks: one thread per (point, axis) forms the stencil weights, one per
-// (point, x offset) sums its plane of the stencil, and one per point adds the
-// planes in a fixed order.
+// chunks: one thread per (point, axis, offset) forms the stencil weights,
+// then one wave per point has each lane sum the z-lines of its (x, y) stencil
+// columns and the wave adds the lanes by shuffles in a fixed order.
 __global__ __launch_bounds__(256) void k_ewald_interp(int M, int B, int Lt, int w, GridPoly g,
                                                       const int64_t* __restrict__ tile_start,
                                                       const double* __restrict__ x, const double* __restrict__ y,
@@ -225,14 +256,14 @@ __global__ __launch_bounds__(256) void k_ewald_interp(int M, int B, int Lt, int 
     const int R3 = R * R * R;
     double* reg = smem;                                   // [3][R][R][R]
     double* wts = reg + 3 * R3;                           // [CH][3][kMaxW]
-    double* part = wts + kInterpChunk * 3 * kMaxW;        // [CH][kMaxW][3]
-    int* a0s = (int*)(part + kInterpChunk * kMaxW * 3);   // [CH][3]
+    int* a0s = (int*)(wts + kInterpChunk * 3 * kMaxW);    // [CH][3]
     const uint32_t code = blockIdx.x;
     const int tc[3] = {(int)compact3(code >> 2), (int)compact3(code >> 1), (int)compact3(code)};
     const int hwi = w / 2;
     const int O[3] = {tc[0] * B - hwi, tc[1] * B - hwi, tc[2] * B - hwi};
     const int tid = threadIdx.x;
     const size_t M3 = (size_t)M * M * M;
+#pragma unroll 8
     for (int e = tid; e < 3 * R3; e += 256) {
         const int c = e / R3, r = e - c * R3;
         const int a = r / (R * R), b = (r / R) % R, cz = r % R;
@@ -241,30 +272,33 @@ __global__ __launch_bounds__(256) void k_ewald_interp(int M, int B, int Lt, int 
         const int gz = ((O[2] + cz) % M + M) % M;
         reg[e] = grid[c * M3 + ((size_t)gx * M + gy) * M + gz];
     }
+    const int lane = tid & 63, wave = tid >> 6;
     const int64_t ps = tile_start[code], pe = tile_start[code + 1];
     const double hw = 0.5 * w;
     for (int64_t c0 = ps; c0 < pe; c0 += kInterpChunk) {
         const int cnt = (int)min((int64_t)kInterpChunk, pe - c0);
         __syncthreads();  // region loaded / previous chunk finished
-        if (tid < 3 * cnt) {
-            const int p = tid / 3, k = tid % 3;
+        // one thread per (point, axis, stencil offset)
+        for (int it = tid; it < cnt * 3 * kMaxW; it += 256) {
+            const int p = it / (3 * kMaxW), k = (it / kMaxW) % 3, sofs = it % kMaxW;
             const int64_t i = c0 + p;
             const double pc = k == 0 ? x[i] : (k == 1 ? y[i] : z[i]);
             const double X = grid_coord(pc, M, B, tc[k]);
             const int n0 = (int)ceil(X - hw);
-            a0s[p * 3 + k] = n0 - O[k];
-            for (int s = 0; s < kMaxW; ++s)
-                wts[(p * 3 + k) * kMaxW + s] = s < w ? gker(g, (X - (double)(n0 + s)) / hw) : 0.0;
+            if (sofs == 0)
+                a0s[p * 3 + k] = n0 - O[k];
+            wts[(p * 3 + k) * kMaxW + sofs] = sofs < w ? gker(g, (X - (double)(n0 + sofs)) / hw) : 0.0;
         }
         __syncthreads();
-        for (int it = tid; it < cnt * w; it += 256) {
-            const int p = it / w, sx = it % w;
-            const int ax = a0s[p * 3] + sx, ay0 = a0s[p * 3 + 1], az0 = a0s[p * 3 + 2];
+        for (int p = wave; p < cnt; p += 4) {
+            const int ax0 = a0s[p * 3], ay0 = a0s[p * 3 + 1], az0 = a0s[p * 3 + 2];
+            const double* wx = wts + (p * 3) * kMaxW;
             const double* wy = wts + (p * 3 + 1) * kMaxW;
             const double* wz = wts + (p * 3 + 2) * kMaxW;
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-            for (int sy = 0; sy < w; ++sy) {
-                const int rb = (ax * R + ay0 + sy) * R + az0;
+            for (int pr = lane; pr < w * w; pr += 64) {
+                const int sx = pr / w, sy = pr - sx * w;
+                const int rb = ((ax0 + sx) * R + ay0 + sy) * R + az0;
                 double t0 = 0.0, t1 = 0.0, t2 = 0.0;
                 for (int sz = 0; sz < w; ++sz) {
                     const double wv = wz[sz];
@@ -272,27 +306,23 @@ __global__ __launch_bounds__(256) void k_ewald_interp(int M, int B, int Lt, int 
                     t1 = fma(wv, reg[R3 + rb + sz], t1);
                     t2 = fma(wv, reg[2 * R3 + rb + sz], t2);
                 }
-                s0 = fma(wy[sy], t0, s0);
-                s1 = fma(wy[sy], t1, s1);
-                s2 = fma(wy[sy], t2, s2);
+                const double wxy = wx[sx] * wy[sy];
+                s0 = fma(wxy, t0, s0);
+                s1 = fma(wxy, t1, s1);
+                s2 = fma(wxy, t2, s2);
             }
-            const double wx = wts[(p * 3) * kMaxW + sx];
-            part[(p * kMaxW + sx) * 3] = wx * s0;
-            part[(p * kMaxW + sx) * 3 + 1] = wx * s1;
-            part[(p * kMaxW + sx) * 3 + 2] = wx * s2;
-        }
-        __syncthreads();
-        if (tid < cnt) {
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-            for (int sx = 0; sx < w; ++sx) {
-                s0 += part[(tid * kMaxW + sx) * 3];
-                s1 += part[(tid * kMaxW + sx) * 3 + 1];
-                s2 += part[(tid * kMaxW + sx) * 3 + 2];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                s0 += __shfl_xor(s0, off);
+                s1 += __shfl_xor(s1, off);
+                s2 += __shfl_xor(s2, off);
             }
-            const int64_t i = c0 + tid;
-            u[i] = s0;
-            u[n + i] = s1;
-            u[2 * n + i] = s2;
+            if (lane == 0) {
+                const int64_t i = c0 + p;
+                u[i] = s0;
+                u[n + i] = s1;
+                u[2 * n + i] = s2;
+            }
         }
     }
 }
@@ -323,7 +353,7 @@ void launch_ewald_interp(int M, int B, int Lt, int w, const GridPoly& g, const i
 {
     const int R = B + w;
     const size_t shm = (size_t)3 * R * R * R * sizeof(double) + (size_t)kInterpChunk * 3 * kMaxW * sizeof(double) +
-                       (size_t)kInterpChunk * kMaxW * 3 * sizeof(double) + (size_t)kInterpChunk * 3 * sizeof(int);
+                       (size_t)kInterpChunk * 3 * sizeof(int);
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void*)k_ewald_interp, hipFuncAttributeMaxDynamicSharedMemorySize,

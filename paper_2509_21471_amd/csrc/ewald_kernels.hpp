@@ -13,9 +13,10 @@ namespace dmk {
 
 // Gridding kernel g(t) = sum_k a_k T_k(2 t^2 - 1) for |t| < 1, 0 outside
 // (t = (X - n) / (w/2) in grid units).
+constexpr int kGridTerms = 24;
 struct GridPoly {
-    int nc;
-    double a[48];
+    int nc;                 // terms in use (<= kGridTerms); the rest are zero
+    double a[kGridTerms];
 };
 
 // Tiles are the Morton cells of level Lt (side B grid points, M = B 2^Lt):

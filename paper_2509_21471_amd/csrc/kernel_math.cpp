@@ -712,7 +712,31 @@ const Tables* get_tables(double tol)
 
 namespace dmk {
 
+static bool ewald_grid_build(const Params& prm, int L, EwaldGrid* out);
+
 bool ewald_grid(const Params& prm, int L, EwaldGrid* out)
+{
+    // the symbol table costs about 10^4 mollifier evaluations: computed once
+    // per (tolerance, q, split level) and process
+    static std::mutex mu;
+    static std::map<std::tuple<double, int, int>, EwaldGrid> cache;
+    const auto key = std::make_tuple(prm.tol, prm.q, L);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            *out = it->second;
+            return true;
+        }
+    }
+    if (!ewald_grid_build(prm, L, out))
+        return false;
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = *out;
+    return true;
+}
+
+static bool ewald_grid_build(const Params& prm, int L, EwaldGrid* out)
 {
     if (L < 1 || L > 8 || prm.window != 0 || prm.kernel != 0)
         return false;
