@@ -295,9 +295,19 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes three times (the "
                          "reference kernel for scaling HBM byte counters) and exit")
+    ap.add_argument("--only", choices=["spectral_ewald", "multi_rhs", "batched"], default=None,
+                    help="run only this variant and print its JSON record (for profiling; not the benchmark line)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.only:
+        import torch
+        dev = torch.device("cuda:0")
+        fn = {"spectral_ewald": lambda: ewald_variant(args, dev, not args.no_parity),
+              "multi_rhs": lambda: multi_rhs_variant(args, dev, not args.no_parity),
+              "batched": lambda: batched_variant(dev, not args.no_parity)}[args.only]
+        print(json.dumps({"variant": args.only, **fn()}), flush=True)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

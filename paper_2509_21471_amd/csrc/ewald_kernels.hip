@@ -36,6 +36,17 @@ __device__ inline uint32_t tile_code(int tx, int ty, int tz)
     return (spread3((uint32_t)tx) << 2) | (spread3((uint32_t)ty) << 1) | spread3((uint32_t)tz);
 }
 
+// Blocks go round-robin over the 8 XCDs, each with its own L2; this gives
+// every XCD a contiguous Morton range of tiles instead, so the regions and
+// neighbour points that adjacent tiles share are read through one L2.
+// Padding blocks get -1.
+__device__ inline int xcd_tile(int total)
+{
+    const int per = (total + 7) / 8;
+    const int t = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    return t < total ? t : -1;
+}
+
 // gridding kernel, Clenshaw in v = 2 t^2 - 1 over the zero-padded series
 // (fixed length, so the coefficients sit in scalar registers); 0 for |t| >= 1
 __device__ inline double gker(const GridPoly& g, double t)
@@ -62,7 +73,7 @@ __device__ inline double grid_coord(double x, int M, int B, int tc)
     return fmin(fmax(X, t0), nextafter(t0 + (double)B, 0.0));
 }
 
-constexpr int kSpreadChunk = 256;
+constexpr int kSpreadChunk = 128;
 
 // One block per tile.  The block walks the points of the 27 neighbouring
 // tiles (periodic images included) in chunks: every candidate whose stencil
@@ -87,7 +98,10 @@ __global__ __launch_bounds__(256) void k_ewald_spread(int M, int Lt, int w, Grid
     __shared__ int nb_tile[27][3];
     __shared__ double nb_wrap[27][3];
     const int NT = 1 << Lt;
-    const uint32_t code = blockIdx.x;
+    const int tile = xcd_tile(1 << (3 * Lt));
+    if (tile < 0)
+        return;
+    const uint32_t code = (uint32_t)tile;
     const int tc[3] = {(int)compact3(code >> 2), (int)compact3(code >> 1), (int)compact3(code)};
     const int T0[3] = {tc[0] * B, tc[1] * B, tc[2] * B};
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -136,7 +150,7 @@ __global__ __launch_bounds__(256) void k_ewald_spread(int M, int Lt, int w, Grid
             bool keep = false;
             double X[3] = {0.0, 0.0, 0.0};
             int64_t i = 0;
-            if (q < total) {
+            if (tid < kSpreadChunk && q < total) {
                 int v = 0;
                 while (nb_off[v + 1] <= q)
                     ++v;
@@ -237,14 +251,16 @@ __global__ __launch_bounds__(256) void k_ewald_scale(int M, int K, const double*
     spec[2 * H + e] = make_double2(wv * (F2.x - k3 * dr), wv * (F2.y - k3 * di));
 }
 
-constexpr int kInterpChunk = 32;
+constexpr int kInterpChunk = 64;
 constexpr int kMaxW = 10;
 
-// One block per tile: the tile's grid region [O, O + B + w)^3 (O = T0 - w/2,
-// periodic) of the 3 components goes to LDS; the tile's points follow in
-// chunks: one thread per (point, axis, offset) forms the stencil weights,
-// then one wave per point has each lane sum the z-lines of its (x, y) stencil
-// columns and the wave adds the lanes by shuffles in a fixed order.
+// One block per tile, its points in chunks: one thread per (point, axis,
+// offset) forms the stencil weights; then, one component at a time, the
+// tile's grid region [O, O + B + w)^3 (O = T0 - w/2, periodic) is staged in
+// LDS and one wave per point has each lane sum the z-lines of its (x, y)
+// stencil columns, the wave adding the lanes by shuffles in a fixed order.
+// (One component at a time keeps the block at about 63 KB of LDS, two
+// blocks per CU, so region loads of one block overlap the other's work.)
 __global__ __launch_bounds__(256) void k_ewald_interp(int M, int B, int Lt, int w, GridPoly g,
                                                       const int64_t* __restrict__ tile_start,
                                                       const double* __restrict__ x, const double* __restrict__ y,
@@ -254,30 +270,23 @@ __global__ __launch_bounds__(256) void k_ewald_interp(int M, int B, int Lt, int 
     extern __shared__ double smem[];
     const int R = B + w;
     const int R3 = R * R * R;
-    double* reg = smem;                                   // [3][R][R][R]
-    double* wts = reg + 3 * R3;                           // [CH][3][kMaxW]
+    double* reg = smem;                                   // [R][R][R], one component
+    double* wts = reg + R3;                               // [CH][3][kMaxW]
     int* a0s = (int*)(wts + kInterpChunk * 3 * kMaxW);    // [CH][3]
-    const uint32_t code = blockIdx.x;
+    const int tile = xcd_tile(1 << (3 * Lt));
+    if (tile < 0)
+        return;
+    const uint32_t code = (uint32_t)tile;
     const int tc[3] = {(int)compact3(code >> 2), (int)compact3(code >> 1), (int)compact3(code)};
     const int hwi = w / 2;
     const int O[3] = {tc[0] * B - hwi, tc[1] * B - hwi, tc[2] * B - hwi};
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const size_t M3 = (size_t)M * M * M;
-#pragma unroll 8
-    for (int e = tid; e < 3 * R3; e += 256) {
-        const int c = e / R3, r = e - c * R3;
-        const int a = r / (R * R), b = (r / R) % R, cz = r % R;
-        const int gx = ((O[0] + a) % M + M) % M;
-        const int gy = ((O[1] + b) % M + M) % M;
-        const int gz = ((O[2] + cz) % M + M) % M;
-        reg[e] = grid[c * M3 + ((size_t)gx * M + gy) * M + gz];
-    }
-    const int lane = tid & 63, wave = tid >> 6;
     const int64_t ps = tile_start[code], pe = tile_start[code + 1];
     const double hw = 0.5 * w;
     for (int64_t c0 = ps; c0 < pe; c0 += kInterpChunk) {
         const int cnt = (int)min((int64_t)kInterpChunk, pe - c0);
-        __syncthreads();  // region loaded / previous chunk finished
+        __syncthreads();  // previous chunk finished with wts / a0s / reg
         // one thread per (point, axis, stencil offset)
         for (int it = tid; it < cnt * 3 * kMaxW; it += 256) {
             const int p = it / (3 * kMaxW), k = (it / kMaxW) % 3, sofs = it % kMaxW;
@@ -289,39 +298,37 @@ __global__ __launch_bounds__(256) void k_ewald_interp(int M, int B, int Lt, int 
                 a0s[p * 3 + k] = n0 - O[k];
             wts[(p * 3 + k) * kMaxW + sofs] = sofs < w ? gker(g, (X - (double)(n0 + sofs)) / hw) : 0.0;
         }
-        __syncthreads();
-        for (int p = wave; p < cnt; p += 4) {
-            const int ax0 = a0s[p * 3], ay0 = a0s[p * 3 + 1], az0 = a0s[p * 3 + 2];
-            const double* wx = wts + (p * 3) * kMaxW;
-            const double* wy = wts + (p * 3 + 1) * kMaxW;
-            const double* wz = wts + (p * 3 + 2) * kMaxW;
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-            for (int pr = lane; pr < w * w; pr += 64) {
-                const int sx = pr / w, sy = pr - sx * w;
-                const int rb = ((ax0 + sx) * R + ay0 + sy) * R + az0;
-                double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-                for (int sz = 0; sz < w; ++sz) {
-                    const double wv = wz[sz];
-                    t0 = fma(wv, reg[rb + sz], t0);
-                    t1 = fma(wv, reg[R3 + rb + sz], t1);
-                    t2 = fma(wv, reg[2 * R3 + rb + sz], t2);
+        for (int c = 0; c < 3; ++c) {
+            __syncthreads();  // weights ready / previous component consumed
+            const double* gc = grid + c * M3;
+#pragma unroll 8
+            for (int e = tid; e < R3; e += 256) {
+                const int a = e / (R * R), b = (e / R) % R, cz = e % R;
+                const int gx = ((O[0] + a) % M + M) % M;
+                const int gy = ((O[1] + b) % M + M) % M;
+                const int gz = ((O[2] + cz) % M + M) % M;
+                reg[e] = gc[((size_t)gx * M + gy) * M + gz];
+            }
+            __syncthreads();
+            for (int p = wave; p < cnt; p += 4) {
+                const int ax0 = a0s[p * 3], ay0 = a0s[p * 3 + 1], az0 = a0s[p * 3 + 2];
+                const double* wx = wts + (p * 3) * kMaxW;
+                const double* wy = wts + (p * 3 + 1) * kMaxW;
+                const double* wz = wts + (p * 3 + 2) * kMaxW;
+                double s0 = 0.0;
+                for (int pr = lane; pr < w * w; pr += 64) {
+                    const int sx = pr / w, sy = pr - sx * w;
+                    const int rb = ((ax0 + sx) * R + ay0 + sy) * R + az0;
+                    double t0 = 0.0;
+                    for (int sz = 0; sz < w; ++sz)
+                        t0 = fma(wz[sz], reg[rb + sz], t0);
+                    s0 = fma(wx[sx] * wy[sy], t0, s0);
                 }
-                const double wxy = wx[sx] * wy[sy];
-                s0 = fma(wxy, t0, s0);
-                s1 = fma(wxy, t1, s1);
-                s2 = fma(wxy, t2, s2);
-            }
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                s0 += __shfl_xor(s0, off);
-                s1 += __shfl_xor(s1, off);
-                s2 += __shfl_xor(s2, off);
-            }
-            if (lane == 0) {
-                const int64_t i = c0 + p;
-                u[i] = s0;
-                u[n + i] = s1;
-                u[2 * n + i] = s2;
+                for (int off = 32; off >= 1; off >>= 1)
+                    s0 += __shfl_xor(s0, off);
+                if (lane == 0)
+                    u[c * n + c0 + p] = s0;
             }
         }
     }
@@ -332,7 +339,7 @@ __global__ __launch_bounds__(256) void k_ewald_interp(int M, int B, int Lt, int 
 void launch_ewald_spread(int M, int B, int Lt, int w, const GridPoly& g, const int64_t* tile_start, const double* x,
                          const double* y, const double* z, const double* fs, int64_t n, double* grid, hipStream_t s)
 {
-    const unsigned ntile = 1u << (3 * Lt);
+    const unsigned ntile = (((1u << (3 * Lt)) + 7u) / 8u) * 8u;
     if (B == 6)
         hipLaunchKernelGGL(k_ewald_spread<6>, dim3(ntile), dim3(256), 0, s, M, Lt, w, g, tile_start, x, y, z, fs, n,
                            grid);
@@ -352,7 +359,7 @@ void launch_ewald_interp(int M, int B, int Lt, int w, const GridPoly& g, const i
                          double* u, hipStream_t s)
 {
     const int R = B + w;
-    const size_t shm = (size_t)3 * R * R * R * sizeof(double) + (size_t)kInterpChunk * 3 * kMaxW * sizeof(double) +
+    const size_t shm = (size_t)R * R * R * sizeof(double) + (size_t)kInterpChunk * 3 * kMaxW * sizeof(double) +
                        (size_t)kInterpChunk * 3 * sizeof(int);
     static bool attr = false;
     if (!attr) {
@@ -360,7 +367,7 @@ void launch_ewald_interp(int M, int B, int Lt, int w, const GridPoly& g, const i
                                   160 * 1024);
         attr = true;
     }
-    const unsigned ntile = 1u << (3 * Lt);
+    const unsigned ntile = (((1u << (3 * Lt)) + 7u) / 8u) * 8u;
     hipLaunchKernelGGL(k_ewald_interp, dim3(ntile), dim3(256), shm, s, M, B, Lt, w, g, tile_start, x, y, z, n, grid,
                        u);
 }
