@@ -195,6 +195,7 @@ __global__ __launch_bounds__(256) void k_ewald_spread(int M, int Lt, int w, Grid
                 const int gp = tid + 256 * s;
                 if (gp < B3) {
                     const int ix = gp / (B * B), iy = (gp / B) % B, iz = gp % B;
+#pragma unroll 4
                     for (int c = 0; c < kept; ++c) {
                         const double wv = wt[c][0][ix] * wt[c][1][iy] * wt[c][2][iz];
                         acc[s][0] = fma(wv, ff[c][0], acc[s][0]);
@@ -261,12 +262,14 @@ constexpr int kMaxW = 10;
 // stencil columns, the wave adding the lanes by shuffles in a fixed order.
 // (One component at a time keeps the block at about 63 KB of LDS, two
 // blocks per CU, so region loads of one block overlap the other's work.)
-__global__ __launch_bounds__(256) void k_ewald_interp(int M, int B, int Lt, int w, GridPoly g,
+template <int W>
+__global__ __launch_bounds__(256) void k_ewald_interp(int M, int B, int Lt, GridPoly g,
                                                       const int64_t* __restrict__ tile_start,
                                                       const double* __restrict__ x, const double* __restrict__ y,
                                                       const double* __restrict__ z, int64_t n,
                                                       const double* __restrict__ grid, double* __restrict__ u)
 {
+    constexpr int w = W;
     extern __shared__ double smem[];
     const int R = B + w;
     const int R3 = R * R * R;
@@ -316,13 +319,18 @@ __global__ __launch_bounds__(256) void k_ewald_interp(int M, int B, int Lt, int 
                 const double* wy = wts + (p * 3 + 1) * kMaxW;
                 const double* wz = wts + (p * 3 + 2) * kMaxW;
                 double s0 = 0.0;
-                for (int pr = lane; pr < w * w; pr += 64) {
-                    const int sx = pr / w, sy = pr - sx * w;
-                    const int rb = ((ax0 + sx) * R + ay0 + sy) * R + az0;
-                    double t0 = 0.0;
-                    for (int sz = 0; sz < w; ++sz)
-                        t0 = fma(wz[sz], reg[rb + sz], t0);
-                    s0 = fma(wx[sx] * wy[sy], t0, s0);
+#pragma unroll
+                for (int pr0 = 0; pr0 < w * w; pr0 += 64) {
+                    const int pr = pr0 + lane;
+                    if (pr < w * w) {
+                        const int sx = pr / w, sy = pr - sx * w;
+                        const int rb = ((ax0 + sx) * R + ay0 + sy) * R + az0;
+                        double t0 = 0.0;
+#pragma unroll
+                        for (int sz = 0; sz < w; ++sz)
+                            t0 = fma(wz[sz], reg[rb + sz], t0);
+                        s0 = fma(wx[sx] * wy[sy], t0, s0);
+                    }
                 }
 #pragma unroll
                 for (int off = 32; off >= 1; off >>= 1)
@@ -363,13 +371,26 @@ void launch_ewald_interp(int M, int B, int Lt, int w, const GridPoly& g, const i
                        (size_t)kInterpChunk * 3 * sizeof(int);
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void*)k_ewald_interp, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void*)k_ewald_interp<6>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        (void)hipFuncSetAttribute((const void*)k_ewald_interp<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        (void)hipFuncSetAttribute((const void*)k_ewald_interp<10>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   160 * 1024);
         attr = true;
     }
     const unsigned ntile = (((1u << (3 * Lt)) + 7u) / 8u) * 8u;
-    hipLaunchKernelGGL(k_ewald_interp, dim3(ntile), dim3(256), shm, s, M, B, Lt, w, g, tile_start, x, y, z, n, grid,
-                       u);
+#define L_INTERP(W)                                                                                              \
+    hipLaunchKernelGGL(k_ewald_interp<W>, dim3(ntile), dim3(256), shm, s, M, B, Lt, g, tile_start, x, y, z, n, \
+                       grid, u)
+    // the widths the grid parameters produce (6, 8, 10 at 1e-3, 1e-6, 1e-9)
+    if (w == 6)
+        L_INTERP(6);
+    else if (w == 8)
+        L_INTERP(8);
+    else if (w == 10)
+        L_INTERP(10);
+#undef L_INTERP
 }
 
 }  // namespace dmk
