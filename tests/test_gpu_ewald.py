@@ -67,3 +67,17 @@ def test_periodic_2e6_stored_ewald(dev):
     err = oracle.rel_l2(u[g["idx"]], g["u"])
     print("spectral Ewald periodic_2e6:", info["levels"] - 1, info["ewald_grid"], info["ewald_modes"], err)
     assert err < 1e-9
+
+
+@pytest.mark.parametrize("n", [1, 2, 50])
+def test_small_sizes(dev, n):
+    """Tiny periodic inputs (split level 1, 2^3 cells with repeated
+    neighbours through the wrap) against the Gaussian Ewald oracle."""
+    dmk = _dmk()
+    x, f = workloads.make("uniform", n, seed=220 + n)
+    plan = dmk.Plan(_t(x), periodic=True, tol=1e-6, method=dmk.METHOD_EWALD)
+    u = plan.eval(_t(f)).cpu().numpy()
+    ref = ewald(x, f, np.arange(n))
+    err = oracle.rel_l2(u, ref)
+    print("spectral Ewald small", n, plan.info()["ewald_grid"], err)
+    assert err < 1e-6
