@@ -348,6 +348,11 @@ int dmk_stokes_params_kernel(double tol, int window, int kernel, dmk_plan_info* 
  */
 int dmk_stokes_radial(double tol, const double* rho, int64_t n, double* out);
 
+/* Grid of a spectral Ewald plan (DMK_METHOD_EWALD) for n periodic points:
+ * fills method, levels (split level + 1), ewald_grid (M), ewald_modes (K),
+ * ewald_width (w), q, c and leaf_size (0 = the tolerance's default). */
+int dmk_stokes_ewald_params(double tol, int64_t n, int leaf_size, dmk_plan_info* info);
+
 /*
  * Near-field radial functions of the residual stresslet at unit scale for tol
  * (stresslet row of Table tab:params), at n radii: out[2i] = A(rho^2),

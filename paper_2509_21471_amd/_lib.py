@@ -21,7 +21,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 KERNEL_STOKESLET, KERNEL_STRESSLET = 0, 1
 METHOD_DMK, METHOD_EWALD = 0, 1
 
-SYMBOLS = ["dmk_stokes_radial_stresslet", "dmk_stokes_params_ex", "dmk_stokes_params_kernel", "dmk_stokes_eval_stresslet",
+SYMBOLS = ["dmk_stokes_ewald_params", "dmk_stokes_radial_stresslet", "dmk_stokes_params_ex", "dmk_stokes_params_kernel", "dmk_stokes_eval_stresslet",
            "dmk_stokes_residual_sum_stresslet", "dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_plan_batch", "dmk_stokes_plan_targets", "dmk_stokes_autotune", "dmk_stokes_eval", "dmk_stokes_plan_info",
            "dmk_stokes_tree_leaves", "dmk_stokes_destroy", "dmk_last_error", "dmk_stokes_params",
            "dmk_stokes_radial", "dmk_stokes_mollifier", "dmk_stokes_residual_sum", "dmk_stokes_phase_ms",
@@ -105,6 +105,7 @@ def lib():
         L.dmk_stokes_radial.argtypes = [ctypes.c_double, dp, i64, dp]
         L.dmk_stokes_mollifier.argtypes = [ctypes.c_double, dp, i64, dp]
         L.dmk_stokes_radial_stresslet.argtypes = [ctypes.c_double, dp, i64, dp]
+        L.dmk_stokes_ewald_params.argtypes = [ctypes.c_double, i64, ctypes.c_int, ctypes.POINTER(PlanInfo)]
         L.dmk_stokes_residual_sum.argtypes = [vp, i64, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp]
         L.dmk_stokes_residual_sum_stresslet.argtypes = [vp, i64, vp, vp, vp, i64, ctypes.c_double,
                                                         ctypes.c_double, vp, vp]
@@ -141,6 +142,13 @@ def radial(tol: float, rho) -> np.ndarray:
     out = np.zeros((rho.size, 4))
     _check(lib().dmk_stokes_radial(float(tol), _dp(rho), rho.size, _dp(out)))
     return out
+
+
+def ewald_params(tol: float, n: int, leaf_size: int = 0) -> dict:
+    """Split level and grid a spectral Ewald plan would use (host only)."""
+    info = PlanInfo()
+    _check(lib().dmk_stokes_ewald_params(float(tol), int(n), int(leaf_size), ctypes.byref(info)))
+    return info.as_dict()
 
 
 def radial_stresslet(tol: float, rho) -> np.ndarray:

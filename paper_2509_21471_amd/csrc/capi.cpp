@@ -1326,6 +1326,36 @@ int dmk_stokes_radial(double tol, const double* rho, int64_t n, double* out)
     return DMK_OK;
 }
 
+int dmk_stokes_ewald_params(double tol, int64_t n, int leaf_size, dmk_plan_info* info)
+{
+    if (!info || n < 1 || leaf_size < 0)
+        return fail(DMK_ERR_ARG, "bad arguments");
+    std::memset(info, 0, sizeof(*info));
+    dmk::Params prm;
+    if (!dmk::select_params(tol, &prm) || tol < 1e-9 * (1 - 1e-9))
+        return fail(DMK_ERR_TOL, "the spectral Ewald method is offered for tol in [1e-9, 1e-3]");
+    if (leaf_size > 0)
+        prm.ns = leaf_size;
+    int L = 1;
+    while (L < 8 && (double)n / (double)(1ll << (3 * L)) > (double)prm.ns)
+        ++L;
+    dmk::EwaldGrid E;
+    if (!dmk::ewald_grid(prm, L, &E))
+        return fail(DMK_ERR_UNSUPPORTED, "no spectral Ewald grid for this tolerance and size");
+    info->tol = prm.tol;
+    info->c = prm.c;
+    info->q = prm.q;
+    info->leaf_size = prm.ns;
+    info->periodic = 1;
+    info->n_points = n;
+    info->levels = L + 1;
+    info->method = DMK_METHOD_EWALD;
+    info->ewald_grid = E.M;
+    info->ewald_modes = E.K;
+    info->ewald_width = E.w;
+    return DMK_OK;
+}
+
 int dmk_stokes_radial_stresslet(double tol, const double* rho, int64_t n, double* out)
 {
     if (!rho || !out || n < 0)
@@ -1654,7 +1684,8 @@ int dmk_stokes_autotune(const double* points, int64_t n, const int64_t* offsets,
     // cached per workload class: size (powers of 2), problem count, periodicity, tolerance, precision
     const int nb = offsets ? n_problems : 1;
     const auto key = std::make_tuple((int)std::lround(std::log2((double)n)), (int)std::lround(std::log2((double)nb)),
-                                     periodic, tol, base.precision, n_rhs, base.q, base.p);
+                                     periodic, tol, base.precision, n_rhs, base.q, base.p,
+                                     base.window * 4 + base.method);
     static std::mutex mu;
     static std::map<decltype(key), std::pair<dmk_opts, double>> cache;
     {

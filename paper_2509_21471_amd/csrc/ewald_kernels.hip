@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void k_ewald_scale(int M, int K, const double*
 }
 
 constexpr int kInterpChunk = 64;
-constexpr int kMaxW = 10;
+constexpr int kMaxW = 12;
 
 // One block per tile, its points in chunks: one thread per (point, axis,
 // offset) forms the stencil weights; then, one component at a time, the
@@ -375,7 +375,7 @@ void launch_ewald_interp(int M, int B, int Lt, int w, const GridPoly& g, const i
                                   160 * 1024);
         (void)hipFuncSetAttribute((const void*)k_ewald_interp<8>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   160 * 1024);
-        (void)hipFuncSetAttribute((const void*)k_ewald_interp<10>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (void)hipFuncSetAttribute((const void*)k_ewald_interp<11>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   160 * 1024);
         attr = true;
     }
@@ -383,13 +383,13 @@ void launch_ewald_interp(int M, int B, int Lt, int w, const GridPoly& g, const i
 #define L_INTERP(W)                                                                                              \
     hipLaunchKernelGGL(k_ewald_interp<W>, dim3(ntile), dim3(256), shm, s, M, B, Lt, g, tile_start, x, y, z, n, \
                        grid, u)
-    // the widths the grid parameters produce (6, 8, 10 at 1e-3, 1e-6, 1e-9)
+    // the widths the grid parameters produce (6, 8, 11 at 1e-3, 1e-6, 1e-9)
     if (w == 6)
         L_INTERP(6);
     else if (w == 8)
         L_INTERP(8);
-    else if (w == 10)
-        L_INTERP(10);
+    else if (w == 11)
+        L_INTERP(11);
 #undef L_INTERP
 }
 

@@ -38,7 +38,7 @@ void launch_ewald_spread(int M, int B, int Lt, int w, const GridPoly& g, const i
 void launch_ewald_scale(int M, int K, const double* ghat, const double* wsym, double2* spec, hipStream_t s);
 
 // u[c][i] = sum over the stencil of g_x g_y g_z grid[c][..] for every sorted
-// point i (overwrites u); w in {6, 8, 10}.
+// point i (overwrites u); w in {6, 8, 11}.
 void launch_ewald_interp(int M, int B, int Lt, int w, const GridPoly& g, const int64_t* tile_start,
                          const double* x, const double* y, const double* z, int64_t n, const double* grid,
                          double* u, hipStream_t s);

@@ -748,7 +748,7 @@ static bool ewald_grid_build(const Params& prm, int L, EwaldGrid* out)
     E.K = (int)std::ceil(lim) - 1;
     // gridding kernel width: the aliasing error of a prolate kernel of width w
     // at oversampling sigma falls like exp(-pi w (1 - 1/(2 sigma)))
-    E.w = prm.tol >= 1e-3 * (1 - 1e-9) ? 6 : prm.tol >= 1e-6 * (1 - 1e-9) ? 8 : prm.tol >= 1e-9 * (1 - 1e-9) ? 10 : 0;
+    E.w = prm.tol >= 1e-3 * (1 - 1e-9) ? 6 : prm.tol >= 1e-6 * (1 - 1e-9) ? 8 : prm.tol >= 1e-9 * (1 - 1e-9) ? 11 : 0;
     if (E.w == 0)
         return false;
     // grid M = B 2^Lt, B in {6, 8}, the smallest with oversampling >= 1.9
@@ -757,8 +757,10 @@ static bool ewald_grid_build(const Params& prm, int L, EwaldGrid* out)
     for (int B : {6, 8})
         for (int Lt = 0; Lt <= 9; ++Lt) {
             const int M = B << Lt;
-            // the LDS region of a tile holds (B + w)^3 grid values of 3 components
-            const bool fits = (size_t)(B + E.w) * (B + E.w) * (B + E.w) * 3 * 8 <= 150 * 1024;
+            // the interpolation block holds one component's (B + w)^3 region and
+            // the stencil weights of 64 points in LDS: at most 80 KB, two blocks per CU
+            const bool fits =
+                (size_t)(B + E.w) * (B + E.w) * (B + E.w) * 8 + 64 * 3 * 12 * 8 + 64 * 3 * 4 <= 80 * 1024;
             if (M >= need && (best == 0 || M < best) && 2 * B >= E.w && fits) {
                 best = M;
                 bB = B;
