@@ -131,6 +131,20 @@ def test_clusters_1e6(dev, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("leaf", [1620, 2160])
+def test_clusters_1e6_autotuned_configurations(dev, leaf):
+    """The two leaf sizes the autotuner picks for the benchmark input (4
+    source lanes), in the timed concurrent-plan mode, on 1000 sampled targets."""
+    cfg = workloads.CONFIGS["clusters_1e6"]
+    x, f = workloads.config("clusters_1e6")
+    plan = _dmk().Plan(_t(x), tol=1e-6, leaf_size=leaf, near_lanes=4, concurrent=True, timing=True)
+    u = plan.eval(_t(f)).cpu().numpy()
+    idx = workloads.sample_targets(x.shape[0], 1000, cfg["seed"])
+    err = oracle.rel_l2(u[idx], oracle.direct(x, f, idx))
+    print("clusters_1e6 leaf", leaf, plan.info()["levels"], err)
+    assert err < 1e-6
+
+
 def test_periodic_2e6_tol1e9(dev):
     """2e6 uniform periodic points at tol 1e-9 against the Gaussian-Ewald sum
     (converged to about 1e-13) at 2000 sampled targets."""
