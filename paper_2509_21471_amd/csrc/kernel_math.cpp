@@ -15,7 +15,8 @@ constexpr double kPi = 3.14159265358979323846;
 struct Row {
     double tol;
     int q, p, n1, nper, ns;
-    int p_used;  // Chebyshev order the plan uses
+    int p_used;      // Chebyshev order the plan uses
+    int q_used = 0;  // window parameter the plan uses (0: the printed q)
 };
 // Table "tab:params" (Stokeslet, PSWF split) and the 3D leaf sizes of
 // Sec. "Numerical results".  The table was tuned on uniform free-space
@@ -38,15 +39,21 @@ const Row kRows[4] = {
 // leaves periodic and clustered inputs at or above the tolerance and is
 // stepped up to 30 (q unchanged).
 // Stresslet columns (prolate) of the same table.  Measured against direct
-// sums on uniform and clustered inputs with 3 to 9 levels, every printed p
-// leaves errors of 1.0 to 1.4 times the tolerance on some input (the
-// interpolation term again: raising q makes it worse, raising p removes it),
-// so each row runs one compiled order up: 12, 23, 36 and 48 (q unchanged).
+// sums, the printed rows leave errors of 1.0 to 1.9 times the tolerance on
+// some inputs: shallow trees of a few hundred points with random orientation
+// vectors are the hardest (up to 1.9 tol at 1e-3, 1.6 at 1e-6), clustered
+// inputs of 9 levels next.  Both the Fourier truncation (q) and the
+// interpolation (p) contribute; stepping both up, in the spirit of the
+// parameter-selection discussion of Sec. "Error control and parameter
+// selection", gives at most 0.37, 0.26, 0.39 and 0.79 tol on the same
+// inputs: (q, p) = (11, 14), (19, 26), (26, 36), (32, 48).  (At 1e-12 a
+// larger q makes the residual's radial functions need more than the 24
+// coefficients the near-field kernel holds.)
 const Row kRowsT[4] = {
-    {1e-3, 9, 11, 17, 3, 600, 12},
-    {1e-6, 17, 22, 33, 5, 1200, 23},
-    {1e-9, 25, 33, 49, 9, 2000, 36},
-    {1e-12, 32, 44, 63, 11, 3000, 48},
+    {1e-3, 9, 11, 17, 3, 600, 14, 11},
+    {1e-6, 17, 22, 33, 5, 1200, 26, 19},
+    {1e-9, 25, 33, 49, 9, 2000, 36, 26},
+    {1e-12, 32, 44, 63, 11, 3000, 48, 32},
 };
 const Row kRowsG[2] = {
     {1e-3, 14, 14, 27, 5, 600, 14},
@@ -74,7 +81,7 @@ bool select_params(double tol, Params* out, int window, int kernel)
         while (hit < nrow - 1 && rows[hit].tol > tol)
             ++hit;
     }
-    const int q = rows[hit].q;
+    const int q = rows[hit].q_used > 0 ? rows[hit].q_used : rows[hit].q;
     out->tol = tol;
     out->kernel = kernel;
     out->window = window;

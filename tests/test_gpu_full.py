@@ -382,3 +382,44 @@ def test_gaussian_window(dev, tol, periodic):
         err = oracle.rel_l2(u, oracle.direct(x, f))
     print("gaussian", tol, periodic, err)
     assert err < tol
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_batch_with_senders_beyond_grid_y(dev, kernel):
+    """3000 problems of 500 points at leaf size 60: about 24,000 plane-wave
+    senders, so the stage launches over (sender, component) exceed 65535
+    blocks in y and run in chunks; sampled problems against their direct
+    sums (Stokeslet and stresslet)."""
+    rng = np.random.default_rng(95)
+    P, m = 3000, 500
+    x = rng.random((P, m, 3)) * rng.uniform(0.5, 2.0, (P, 1, 1)) + rng.uniform(-5, 5, (P, 1, 3))
+    f = rng.normal(size=(P, m, 3))
+    nv = rng.normal(size=(P, m, 3))
+    off = np.arange(P + 1, dtype=np.int64) * m
+    dmk = _dmk()
+    plan = dmk.Plan(_t(x.reshape(-1, 3)), tol=1e-3, leaf_size=60, offsets=off, kernel=kernel)
+    info = plan.info()
+    assert info["n_senders"] * (6 if kernel else 3) > 65535
+    if kernel:
+        u = plan.eval_stresslet(_t(f.reshape(-1, 3)), _t(nv.reshape(-1, 3))).cpu().numpy().reshape(P, m, 3)
+    else:
+        u = plan.eval(_t(f.reshape(-1, 3))).cpu().numpy().reshape(P, m, 3)
+    for b in range(0, P, 331):
+        ref = oracle.stresslet_direct(x[b], f[b], nv[b]) if kernel else oracle.direct(x[b], f[b])
+        assert oracle.rel_l2(u[b], ref) < 1e-3, b
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-6, 1e-9])
+def test_shallow_random_problems(dev, tol):
+    """150 problems of 500 points (random cube sizes and offsets) in one
+    batched plan at leaf size 60: shallow trees, against their direct sums."""
+    rng = np.random.default_rng(95)
+    P, m = 150, 500
+    x = rng.random((P, m, 3)) * rng.uniform(0.5, 2.0, (P, 1, 1)) + rng.uniform(-5, 5, (P, 1, 3))
+    f = rng.normal(size=(P, m, 3))
+    off = np.arange(P + 1, dtype=np.int64) * m
+    plan = _dmk().Plan(_t(x.reshape(-1, 3)), tol=tol, leaf_size=60, offsets=off)
+    u = plan.eval(_t(f.reshape(-1, 3))).cpu().numpy().reshape(P, m, 3)
+    errs = [oracle.rel_l2(u[b], oracle.direct(x[b], f[b])) for b in range(0, P, 3)]
+    print("stokeslet shallow problems", tol, max(errs) / tol)
+    assert max(errs) < tol

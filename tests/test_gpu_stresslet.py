@@ -31,7 +31,7 @@ def _plan(x, tol, **kw):
     return dmk.Plan(_t(x), tol=tol, kernel=dmk.KERNEL_STRESSLET, **kw)
 
 
-@pytest.mark.parametrize("tol,q", [(1e-6, 17), (1e-9, 25)])
+@pytest.mark.parametrize("tol,q", [(1e-6, 19), (1e-9, 26)])
 def test_residual_stresslet_matches_oracle(dev, tol, q):
     """Near-field stresslet pair routine vs the oracle's residual stresslet
     (eq. res_stresslet with eq. T-offd at scale r_lambda), brute force over
@@ -254,3 +254,22 @@ def test_periodic_2e6_stored_ewald(dev):
     err = oracle.rel_l2(u[g["idx"]], g["u"])
     print("stresslet periodic_2e6", plan.info()["levels"], err)
     assert err < 1e-9
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-6, 1e-9])
+def test_shallow_random_problems(dev, tol):
+    """150 problems of 500 points (random cube sizes and offsets, random
+    orientation vectors) in one batched plan at leaf size 60: the inputs on
+    which the printed parameter rows missed the tolerance."""
+    rng = np.random.default_rng(95)
+    P, m = 150, 500
+    x = rng.random((P, m, 3)) * rng.uniform(0.5, 2.0, (P, 1, 1)) + rng.uniform(-5, 5, (P, 1, 3))
+    f = rng.normal(size=(P, m, 3))
+    nv = rng.normal(size=(P, m, 3))
+    off = np.arange(P + 1, dtype=np.int64) * m
+    dmk = _dmk()
+    plan = dmk.Plan(_t(x.reshape(-1, 3)), tol=tol, leaf_size=60, offsets=off, kernel=dmk.KERNEL_STRESSLET)
+    u = plan.eval_stresslet(_t(f.reshape(-1, 3)), _t(nv.reshape(-1, 3))).cpu().numpy().reshape(P, m, 3)
+    errs = [oracle.rel_l2(u[b], oracle.stresslet_direct(x[b], f[b], nv[b])) for b in range(0, P, 3)]
+    print("stresslet shallow problems", tol, max(errs) / tol)
+    assert max(errs) < tol
