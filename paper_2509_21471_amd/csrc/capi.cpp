@@ -268,6 +268,11 @@ struct dmk_plan_s {
     int nc_in = 3;
     void* Phi3 = nullptr;
     int* send_level = nullptr;        // sender slot -> level
+    // stage pipelines run over slot chunks so that the scratch buffers s1, s2
+    // hold one chunk: ck_slots box slots or ck_roots roots at a time
+    int ck_slots = 1, ck_roots = 1;
+    bool ck_on = false;
+    int ck0 = 0, ck1 = 0;
     // single-level spectral Ewald plans (DMK_METHOD_EWALD)
     int method = DMK_METHOD_DMK;
     dmk::EwaldGrid eg;
@@ -401,6 +406,14 @@ void stage(dmk_plan_t P, int mode, int io, const void* X, long xs, const int* xm
     a.child_fid = child_fid;
     a.f32 = P->f32 ? 1 : 0;
     a.ncomp = nc;
+    if (P->ck_on) {
+        // one chunk of a pipeline: slots [ck0, ck1); the scratch buffers hold
+        // only this chunk's rows
+        a.slot0 = P->ck0;
+        a.nslots = P->ck1;
+        a.xbase = (X == P->s1 || X == P->s2) ? P->ck0 : 0;
+        a.ybase = (Y == P->s1 || Y == P->s2) ? P->ck0 : 0;
+    }
     dmk::launch_stage(mode, io, a, P->stream);
 }
 
@@ -1006,7 +1019,11 @@ int build_plan(dmk_plan_t P, const double* points)
         const size_t mh = P->root_mh, mf = P->root_mf;
         per_root = std::max({(size_t)p * p * mh, (size_t)p * mh * mf, mf * mf * (size_t)p, mf * (size_t)p * p}) * cs;
     }
-    const size_t sbytes = std::max(per * nc * (size_t)maxslots, per_root * nc * (size_t)np);
+    // scratch for one chunk of slots: at most about 1 GiB per buffer
+    const size_t budget = (size_t)1 << 30;
+    P->ck_slots = (int)std::max<size_t>(1, std::min<size_t>((size_t)maxslots, budget / (per * nc)));
+    P->ck_roots = (int)std::max<size_t>(1, std::min<size_t>((size_t)np, budget / (per_root * nc)));
+    const size_t sbytes = std::max(per * nc * (size_t)P->ck_slots, per_root * nc * (size_t)P->ck_roots);
     P->s1 = P->mem.alloc<char>(sbytes);
     P->s2 = P->mem.alloc<char>(sbytes);
     P->phi_root = P->mem.alloc<char>(nc * P->Hroot * cs * np);
@@ -1073,27 +1090,41 @@ void far_field(dmk_plan_t P, int r, bool record)
     launch_anterp(p, nc, P->leaves_src, P->nleaf, P->Ltab, fs, n, P->Q, P->f32, st);
     mark(1);
     const int h = (p + 1) / 2, M = q - 1;
+    // a pipeline of stages over slots [0, ns) in chunks of ck (scratch holds one chunk)
+    auto chunks = [&](int ns, int ck, const auto& body) {
+        for (int c0 = 0; c0 < ns; c0 += ck) {
+            P->ck_on = true;
+            P->ck0 = c0;
+            P->ck1 = std::min(ns, c0 + ck);
+            body();
+        }
+        P->ck_on = false;
+    };
     // Step 2b: merge children into parents, finest level first (Q is x-major [a][b][c])
     for (int l = T.max_level - 1; l >= 0; --l) {
         const auto& L = P->lev[l];
         if (!L.nparent)
             continue;
+        chunks(L.nparent, P->ck_slots, [&] {
         stage(P, ST_SYM_REAL, IO_GATHER8, P->Q, 0, nullptr, P->s1, 4 * p3, nullptr, 0, P->merge_mat, 2 * p, p, 0, 0,
               p, h, 4 * p * p, L.nparent, L.child_fid, nc);
         stage(P, ST_SYM_REAL, IO_PLAIN, P->s1, 4 * p3, nullptr, P->s2, 2 * p3, nullptr, 0, P->merge_mat, 2 * p, p, 0,
               0, p, h, 2 * p * p, L.nparent, nullptr, nc);
         stage(P, ST_SYM_REAL, IO_PLAIN, P->s2, 2 * p3, nullptr, P->Q, p3, L.parent_fid, 0, P->merge_mat, 2 * p, p, 0,
               0, p, h, p * p, L.nparent, nullptr, nc);
+        });
     }
     mark(2);
     // outgoing plane waves of the senders: Phi[mx][my][mz], mx >= 0
     const long H = (long)P->H;
+    chunks(P->nsend, P->ck_slots, [&] {
     stage(P, ST_OUT_HALF, IO_PLAIN, P->Q, p3, P->send_fid, P->s1, p2 * q, nullptr, 0, P->pw_out, p, q, 0, 0, h, M + 1,
           p * p, P->nsend, nullptr, nc);
     stage(P, ST_OUT_FULL, IO_PLAIN, P->s1, p2 * q, nullptr, P->s2, (long)p * q * n1, nullptr, 0, P->pw_out, p, n1, 0,
           M, h, M + 1, p * q, P->nsend, nullptr, nc);
     stage(P, ST_OUT_FULL, IO_PLAIN, P->s2, (long)p * q * n1, nullptr, P->Phi, H, nullptr, 0, P->pw_out, p, n1, 0, M,
           h, M + 1, q * n1, P->nsend, nullptr, nc);
+    });
     // stresslet: the difference symbol (6 -> 3 components) on the sending side
     if (stress)
         launch_stress_symbol(q, n1, P->nsend, P->send_level, P->Phi, P->wdiff, P->Phi3, P->f32, st);
@@ -1104,35 +1135,41 @@ void far_field(dmk_plan_t P, int r, bool record)
     mark(4);
     // incoming plane waves -> proxy potentials, z-major V[c][b][a]
     launch_zero(P->V, (size_t)P->nf * 3 * p3 * P->es, st);
+    chunks(P->nrecv, P->ck_slots, [&] {
     stage(P, ST_IN_FULL, IO_PLAIN, P->Psi, H, nullptr, P->s1, (long)n1 * q * p, nullptr, 0, P->pw_in_full, n1, p, M,
           0, M + 1, h, n1 * q, P->nrecv);
     stage(P, ST_IN_FULL, IO_PLAIN, P->s1, (long)n1 * q * p, nullptr, P->s2, (long)q * p * p, nullptr, 0,
           P->pw_in_full, n1, p, M, 0, M + 1, h, q * p, P->nrecv);
     stage(P, ST_IN_HALF_REAL, IO_PLAIN, P->s2, (long)q * p * p, nullptr, P->V, p3, P->recv_fid, 1, P->pw_in_half, q,
           p, 0, 0, q, h, p * p, P->nrecv);
+    });
     mark(5);
     // Step 3a: root convolution with the (truncated or periodic) mollified kernel
     {
         const int mh = P->root_mh, mf = P->root_mf, RM = mh - 1;
         const long Hr = (long)P->Hroot;
         const int nr = P->nprob;  // one root per problem; stage slots map to their far-field slots
+        chunks(nr, P->ck_roots, [&] {
         stage(P, ST_OUT_HALF, IO_PLAIN, P->Q, p3, P->d_root_fid, P->s1, p2 * mh, nullptr, 0, P->r_out, p, mh, 0, 0, h,
               mh, p * p, nr, nullptr, nc);
         stage(P, ST_OUT_FULL, IO_PLAIN, P->s1, p2 * mh, nullptr, P->s2, (long)p * mh * mf, nullptr, 0, P->r_out, p, mf,
               0, RM, h, mh, p * mh, nr, nullptr, nc);
         stage(P, ST_OUT_FULL, IO_PLAIN, P->s2, (long)p * mh * mf, nullptr, P->phi_root, Hr, nullptr, 0, P->r_out, p,
               mf, 0, RM, h, mh, mh * mf, nr, nullptr, nc);
+        });
         if (stress)
             launch_root_symbol_t(mh, mf, nr, P->phi_root, P->wroot,
                                  P->periodic ? 2.0 * kPi : 2.0 * kPi / P->tab->root_period, P->psi_root, P->f32, st);
         else
             launch_root_symbol(mh, mf, nr, P->phi_root, P->wroot, P->psi_root, P->f32, st);
+        chunks(nr, P->ck_roots, [&] {
         stage(P, ST_IN_FULL, IO_PLAIN, P->psi_root, Hr, nullptr, P->s1, (long)mf * mh * p, nullptr, 0, P->r_in_full,
               mf, p, RM, 0, mh, h, mf * mh, nr);
         stage(P, ST_IN_FULL, IO_PLAIN, P->s1, (long)mf * mh * p, nullptr, P->s2, (long)mh * p * p, nullptr, 0,
               P->r_in_full, mf, p, RM, 0, mh, h, mh * p, nr);
         stage(P, ST_IN_HALF_REAL, IO_PLAIN, P->s2, (long)mh * p * p, nullptr, P->V, p3, P->d_root_fid, 1, P->r_in_half,
               mh, p, 0, 0, mh, h, p * p, nr);
+        });
         if (P->periodic && stress)
             launch_stress_moment(P->Q, P->d_root_fid, nr, p, P->cheb_t, cst, P->f32, st);
         if (!P->periodic && !stress)
@@ -1145,12 +1182,14 @@ void far_field(dmk_plan_t P, int r, bool record)
         const auto& L = P->lev[l];
         if (!L.nparent)
             continue;
+        chunks(L.nparent, P->ck_slots, [&] {
         stage(P, ST_SYM_REAL, IO_PLAIN, P->V, p3, L.parent_fid, P->s1, 2 * p3, nullptr, 0, P->interp_mat, p, 2 * p, 0,
               0, h, p, p * p, L.nparent);
         stage(P, ST_SYM_REAL, IO_PLAIN, P->s1, 2 * p3, nullptr, P->s2, 4 * p3, nullptr, 0, P->interp_mat, p, 2 * p, 0,
               0, h, p, 2 * p * p, L.nparent);
         stage(P, ST_SYM_REAL, IO_SCATTER8, P->s2, 4 * p3, nullptr, P->V, 0, nullptr, 1, P->interp_mat, p, 2 * p, 0, 0,
               h, p, 4 * p * p, L.nparent, L.child_fid);
+        });
     }
     mark(7);
     // far field at the points

@@ -797,7 +797,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
     const size_t p3 = (size_t)p * p * p;
     // ---- input slab ----
     {
-        const size_t xoff = ((size_t)(a.xmap ? a.xmap[slot] : slot) * nc + comp) * a.xstride;
+        const size_t xoff = ((size_t)(a.xmap ? a.xmap[slot] : slot - a.xbase) * nc + comp) * a.xstride;
         for (int e = tid; e < Nin * 64; e += 256) {
             const int k = e >> 6, rr = e & 63;
             const int r = r0 + rr;
@@ -930,7 +930,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
             }
         }
     } else {
-        const size_t yoff = ((size_t)(a.ymap ? a.ymap[slot] : slot) * nc + comp) * a.ystride * YE +
+        const size_t yoff = ((size_t)(a.ymap ? a.ymap[slot] : slot - a.ybase) * nc + comp) * a.ystride * YE +
                             (size_t)r0 * Nout * YE;
         S* Yd = (S*)a.Y + yoff;
         const int cnt = nrow * Nout * YE;

@@ -106,6 +106,8 @@ struct StageArgs {
     int f32;             // X and Y hold float (else double); arithmetic is FP64
     int ncomp = 3;       // components per slot (3; 6 for stresslet densities)
     int slot0 = 0;       // first slot of the launch (slots [slot0, nslots))
+    int xbase = 0;       // X (without xmap) holds slots [xbase, ...): row slot - xbase
+    int ybase = 0;       // the same for Y
 };
 void launch_stage(int mode, int io, const StageArgs& a, hipStream_t s);
 
