@@ -45,7 +45,7 @@ def near_traffic(config: str, tol: float, precision: str, kernel: str, leaf_size
     """HBM bytes per launch of the near-field kernel from the committed
     rocprofv3 summary of this workload, or None when there is none, it was
     taken with another leaf size or lane split, or the near-field source
-    section changed since the counters were taken."""
+    section or the within-leaf reorder changed since the counters were taken."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", f"k_near_{config}_{precision}_leaf{leaf_size}_lanes{near_lanes}.md")
@@ -56,7 +56,9 @@ def near_traffic(config: str, tol: float, precision: str, kernel: str, leaf_size
         return None
     rec = json.loads(m.group(0))
     src = open(os.path.join(ROOT, "paper_2509_21471_amd", "csrc", "dmk_kernels.hip")).read()
-    sec = src[src.index("// ---- near field"):src.index("// ---- finishing")]
+    # the kernel's source and the within-leaf point order it runs on
+    sec = (src[src.index("// ---- near field"):src.index("// ---- finishing")]
+           + src[src.index("// ---- compact point groups"):src.index("size_t sort_temp_bytes")])
     if hashlib.sha256(sec.encode()).hexdigest() != rec["near_section_sha256"] or rec["kernel"] != kernel:
         return None
     if rec.get("leaf_size") != leaf_size or rec.get("near_lanes") != near_lanes:
@@ -427,7 +429,11 @@ def main():
                      "traffic": traffic, "traffic_unit": "bytes/launch",
                      "near_ms": t_near * 1e3, "pairs_in_support": stats["in_support"],
                      "pairs_evaluated": stats["evaluated"], "pairs_listed": stats["listed"],
-                     "flops_per_pair": fpp},
+                     "flops_per_pair": fpp,
+                     # the same flops per pair over every evaluated pair (the kernel's issue
+                     # efficiency) and the in-support share of evaluated pairs
+                     "frac_evaluated": stats["evaluated"] * fpp / t_near / 1e12 / PEAK_FP64_VECTOR_TFLOPS,
+                     "useful_fraction": stats["in_support"] / max(stats["evaluated"], 1)},
         "eval_only_ms": eval_ms,
         "eval_only_targets_per_s": n / (eval_ms * 1e-3),
         "phases_ms": phases,

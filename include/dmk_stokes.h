@@ -135,6 +135,14 @@ typedef struct {
  * opts.stream, for later calls with the same triple (new force values in the
  * same buffer are picked up).  Phase timing is not recorded in this mode. */
 #define DMK_FLAG_GRAPH 4
+/* keep the points of every leaf in Morton order.  By default a plan reorders
+ * them, inside each leaf (sources and targets separately), by recursive
+ * balanced bisection across the longest side of the bounding box, so that the
+ * runs of 8 to 64 points that the near field takes as target groups and source
+ * chunks are compact and its per-group pruning discards more out-of-support
+ * pairs (Step 4 evaluates the residual only within r_lambda).  The sums are
+ * the same up to rounding either way. */
+#define DMK_FLAG_MORTON_ORDER 8
 
 /* phases reported by dmk_stokes_phase_ms, in this order */
 #define DMK_PHASE_ANTERP 0     /* force gather + leaf proxy charges (Step 2a) */

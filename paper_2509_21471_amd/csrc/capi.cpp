@@ -296,6 +296,7 @@ struct dmk_plan_s {
     bool concurrent = false;          // build on the library's plan stream
     // DMK_FLAG_GRAPH: evaluation captured once per (forces, n_rhs, velocities)
     bool use_graph = false;
+    bool leaf_order = true;           // compact groups inside leaves (near-field pruning)
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -789,6 +790,39 @@ int build_plan(dmk_plan_t P, const double* points)
     if (P->mem.oom)
         return fail(DMK_ERR_OOM, "device allocation failed");
     launch_gather_points(points, n, P->perm, P->pid, P->geo, P->x, P->y, P->z, st);
+    // ---- compact groups inside leaves (sources and targets separately) ----
+    std::vector<KdSeg> kseg;
+    if (P->leaf_order) {
+        auto add = [&](int64_t a, int64_t b) {
+            const int64_t len = b - a;
+            if (len <= 8)
+                return;
+            // pieces of at most kKdCap points, cut at 64-point chunk boundaries
+            const int64_t pieces = (len + kKdCap - 1) / kKdCap, chunks = (len + 63) / 64;
+            for (int64_t k = 0; k < pieces; ++k) {
+                const int64_t s = a + 64 * (chunks * k / pieces);
+                const int64_t e = std::min(b, a + 64 * (chunks * (k + 1) / pieces));
+                if (e - s > 8)
+                    kseg.push_back(KdSeg{s, (int)(e - s), 0});
+            }
+        };
+        for (size_t i = 0; i < T.boxes.size(); ++i) {
+            const Box& B = T.boxes[i];
+            if (!B.leaf || B.end == B.start)
+                continue;
+            add(B.start, B.start + box_nsrc[i]);
+            if (box_nsrc[i] < B.end - B.start)
+                add(B.start + box_nsrc[i], B.end);
+        }
+        KdSeg* d_seg = P->mem.alloc<KdSeg>(std::max<size_t>(kseg.size(), 1));
+        if (P->mem.oom)
+            return fail(DMK_ERR_OOM, "device allocation failed");
+        HIPCHK(upload(d_seg, kseg, st));
+        int* perm2 = reinterpret_cast<int*>(k0);  // the sort's key buffers are free now
+        launch_leaf_order(d_seg, (int)kseg.size(), P->perm, P->x, P->y, P->z, n, i0, perm2, st);
+        HIPCHK(hipMemcpyAsync(P->perm, perm2, n * sizeof(int), hipMemcpyDeviceToDevice, st));
+        launch_gather_points(points, n, P->perm, P->pid, P->geo, P->x, P->y, P->z, st);
+    }
     // ---- far-field slots ----
     const int nb = (int)T.boxes.size();
     P->box_fid.assign(nb, -1);
@@ -1475,6 +1509,7 @@ int create_plan(const double* points, const std::vector<int64_t>& offsets, int d
             P->rhs_batch = opts->rhs_batch;
         P->concurrent = (opts->flags & DMK_FLAG_CONCURRENT_PLAN) != 0;
         P->use_graph = (opts->flags & DMK_FLAG_GRAPH) != 0;
+        P->leaf_order = (opts->flags & DMK_FLAG_MORTON_ORDER) == 0;
     }
     if (hipEventCreateWithFlags(&P->done, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();

@@ -199,6 +199,167 @@ void launch_gather_points(const double* pts, int64_t n, const int* perm, const i
     hipLaunchKernelGGL(k_gather_points, dim3(nblocks(n, 256)), dim3(256), 0, s, pts, n, perm, pid, geo, x, y, z);
 }
 
+// ---- compact point groups inside leaves -------------------------------------
+// One block per segment (at most kKdCap points, LDS resident).  Level by
+// level, every segment of more than 8 points is sorted along the longest side
+// of its bounding box and cut after a whole number of 64-point chunks (above
+// 64 points) or 8-point groups (at most 64); children take the ids 2k and
+// 2k + 1, so ids stay in position order and below 2^depth <= 512.  A sort key
+// is (segment id: 9 bits | coordinate quantised to 11 bits | local index:
+// 12 bits); keys are distinct, so the bitonic sort gives one order.
+namespace {
+constexpr int kKdMaxSeg = kKdCap / 8;
+
+__global__ __launch_bounds__(256) void k_leaf_kd(const KdSeg* __restrict__ segs, const double* __restrict__ x,
+                                                 const double* __restrict__ y, const double* __restrict__ z,
+                                                 int* __restrict__ src)
+{
+    __shared__ float c[3][kKdCap];
+    __shared__ uint32_t key[kKdCap];
+    __shared__ int t_lo[2][kKdMaxSeg], t_len[2][kKdMaxSeg];
+    __shared__ float s_min[kKdMaxSeg], s_inv[kKdMaxSeg];
+    __shared__ int s_ax[kKdMaxSeg];
+    __shared__ int more;
+    const KdSeg S = segs[blockIdx.x];
+    const int len = S.len;
+    if (len <= 8 || len > kKdCap)
+        return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const double ox = x[S.start], oy = y[S.start], oz = z[S.start];
+    int P2 = 1;
+    while (P2 < len)
+        P2 <<= 1;
+    for (int i = tid; i < P2; i += 256) {
+        if (i < len) {
+            c[0][i] = (float)(x[S.start + i] - ox);
+            c[1][i] = (float)(y[S.start + i] - oy);
+            c[2][i] = (float)(z[S.start + i] - oz);
+        }
+        key[i] = i < len ? (uint32_t)i : 0xffffffffu;
+    }
+    if (tid == 0) {
+        t_lo[0][0] = 0;
+        t_len[0][0] = len;
+    }
+    __syncthreads();
+    for (int depth = 0, cur = 0; depth < 10; ++depth, cur ^= 1) {
+        const int nid = 1 << depth;
+        // bounding box, cut axis and quantisation of every segment to cut
+        for (int k = wid; k < nid; k += 4) {
+            const int lo = t_lo[cur][k], sl = t_len[cur][k];
+            if (sl <= 8)
+                continue;
+            float mn[3] = {3e38f, 3e38f, 3e38f}, mx[3] = {-3e38f, -3e38f, -3e38f};
+            for (int i = lo + lane; i < lo + sl; i += 64) {
+                const int p = (int)(key[i] & 0xfffu);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    mn[d] = fminf(mn[d], c[d][p]);
+                    mx[d] = fmaxf(mx[d], c[d][p]);
+                }
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    mn[d] = fminf(mn[d], __shfl_xor(mn[d], off));
+                    mx[d] = fmaxf(mx[d], __shfl_xor(mx[d], off));
+                }
+            if (lane == 0) {
+                int ax = 0;
+                if (mx[1] - mn[1] > mx[ax] - mn[ax])
+                    ax = 1;
+                if (mx[2] - mn[2] > mx[ax] - mn[ax])
+                    ax = 2;
+                const float ext = mx[ax] - mn[ax];
+                s_ax[k] = ax;
+                s_min[k] = mn[ax];
+                s_inv[k] = ext > 0.f ? 2047.f / ext : 0.f;
+            }
+        }
+        __syncthreads();
+        // keys of this level
+        for (int k = wid; k < nid; k += 4) {
+            const int lo = t_lo[cur][k], sl = t_len[cur][k];
+            const bool cut = sl > 8;
+            const int ax = cut ? s_ax[k] : 0;
+            const float mn = cut ? s_min[k] : 0.f, inv = cut ? s_inv[k] : 0.f;
+            for (int i = lo + lane; i < lo + sl; i += 64) {
+                const uint32_t p = key[i] & 0xfffu;
+                uint32_t q = 0;
+                if (cut)
+                    q = (uint32_t)min(2047, max(0, (int)((c[ax][p] - mn) * inv)));
+                key[i] = ((uint32_t)k << 23) | (q << 12) | p;
+            }
+        }
+        __syncthreads();
+        // bitonic sort of key[0, P2) (padding keys sort last)
+        for (int kk = 2; kk <= P2; kk <<= 1)
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                for (int t = tid; t < P2 / 2; t += 256) {
+                    const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                    const int l = i + j;
+                    const uint32_t a = key[i], b = key[l];
+                    if ((a > b) == ((i & kk) == 0)) {
+                        key[i] = b;
+                        key[l] = a;
+                    }
+                }
+                __syncthreads();
+            }
+        // cut: children 2k and 2k + 1 of the next level
+        if (tid == 0)
+            more = 0;
+        __syncthreads();
+        for (int k = tid; k < nid; k += 256) {
+            const int lo = t_lo[cur][k], sl = t_len[cur][k];
+            int left = sl;
+            if (sl > 8) {
+                const int unit = sl > 64 ? 64 : 8;
+                left = unit * (((sl + unit - 1) / unit) / 2);
+            }
+            if (2 * k + 1 < kKdMaxSeg) {
+                t_lo[cur ^ 1][2 * k] = lo;
+                t_len[cur ^ 1][2 * k] = left;
+                t_lo[cur ^ 1][2 * k + 1] = lo + left;
+                t_len[cur ^ 1][2 * k + 1] = sl - left;
+            }
+            if (left > 8 || sl - left > 8)
+                more = 1;
+        }
+        __syncthreads();
+        if (!more || 2 * nid > kKdMaxSeg)
+            break;
+    }
+    for (int i = tid; i < len; i += 256)
+        src[S.start + i] = (int)(S.start + (key[i] & 0xfffu));
+}
+
+__global__ __launch_bounds__(256) void k_iota(int* __restrict__ v, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n)
+        v[i] = (int)i;
+}
+
+__global__ __launch_bounds__(256) void k_compose(const int* __restrict__ perm, const int* __restrict__ src,
+                                                 int64_t n, int* __restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n)
+        out[i] = perm[src[i]];
+}
+}  // namespace
+
+void launch_leaf_order(const KdSeg* segs, int nseg, const int* perm, const double* x, const double* y,
+                       const double* z, int64_t n, int* src, int* perm_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_iota, dim3(nblocks(n, 256)), dim3(256), 0, s, src, n);
+    if (nseg > 0)
+        hipLaunchKernelGGL(k_leaf_kd, dim3(nseg), dim3(256), 0, s, segs, x, y, z, src);
+    hipLaunchKernelGGL(k_compose, dim3(nblocks(n, 256)), dim3(256), 0, s, perm, src, n, perm_out);
+}
+
 size_t sort_temp_bytes(int64_t n)
 {
     size_t bytes = 0;
@@ -1460,79 +1621,88 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
         acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
     for (int e = T.ebeg; e < T.eend; ++e) {
         const NearEntryDev E = entries[e];
-        const double rl = 1.0 / (double)(1ll << E.lambda);
-        const double rl2 = rl * rl;
-        const double tw = 2.0 / rl2;
+        // powers of two of the level: exact, and equal to the quotients
+        // 1 / r_l, 1 / (4 pi r_l), ... rounded once
+        const int lam = E.lambda;
+        const double rl2 = ldexp(1.0, -2 * lam);
+        const double tw = ldexp(2.0, 2 * lam);
         // Stokeslet: cP = 1/(4 pi r_l), cQ = cP / r_l^2; stresslet: cA, cD
-        const double cP = KER == 1 ? 3.0 / (2.0 * kPi * rl2 * rl2 * rl) : 1.0 / (4.0 * kPi * rl);
-        const double cQ = KER == 1 ? 1.0 / (4.0 * kPi * rl2 * rl) : cP / rl2;
+        const double cP = KER == 1 ? ldexp(3.0 / (2.0 * kPi), 5 * lam) : ldexp(1.0 / (4.0 * kPi), lam);
+        const double cQ = ldexp(1.0 / (4.0 * kPi), 3 * lam);
         const double sh[3] = {(double)E.sx, (double)E.sy, (double)E.sz};
         const int nch = (int)((E.send - E.sstart + 63) / 64);
-        for (int k = 0; k < nch; ++k) {
-            const double* sb = cbbox + 6 * (size_t)(E.cbase + k);
-            double gap2 = 0;
+        for (int kb = 0; kb < nch; kb += 64) {
+            // the lanes test 64 chunks of the entry against the group's box at
+            // once; the wave then visits the chunks within r_lambda in order
+            bool cnear = false;
+            if (kb + lane < nch) {
+                const double* sb = cbbox + 6 * (size_t)(E.cbase + kb + lane);
+                double gap2 = 0;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const double g = fmax(0.0, fmax(sb[d] + sh[d] - thi[d], tlo[d] - (sb[3 + d] + sh[d])));
-                gap2 += g * g;
-            }
-            if (gap2 >= rl2)
-                continue;
-            const int64_t s0 = E.sstart + 64 * (int64_t)k;
-            const int ccnt = (int)min((int64_t)64, E.send - s0);
-            double sx = 0, sy = 0, sz = 0;
-            bool keep = false;
-            if (lane < ccnt) {
-                const int64_t j = s0 + lane;
-                sx = x[j] + sh[0];
-                sy = y[j] + sh[1];
-                sz = z[j] + sh[2];
-                const double gx = fmax(0.0, fmax(tlo[0] - sx, sx - thi[0]));
-                const double gy = fmax(0.0, fmax(tlo[1] - sy, sy - thi[1]));
-                const double gz = fmax(0.0, fmax(tlo[2] - sz, sz - thi[2]));
-                keep = fma(gx, gx, fma(gy, gy, gz * gz)) < rl2;
-            }
-            const unsigned long long mask = __ballot(keep);
-            const int kept = __popcll(mask);
-            if (kept == 0)
-                continue;
-            const int pos = __popcll(mask & ((1ull << lane) - 1ull));
-            __syncthreads();
-            if (keep) {
-                const int64_t j = s0 + lane;
-                double v[2 * W2];
-                v[0] = sx;
-                v[1] = sy;
-                v[2] = sz;
-                if (KER == 1) {
-#pragma unroll
-                    for (int c = 0; c < 6; ++c)
-                        v[3 + c] = fs[(size_t)c * n + j];
-                    v[9] = fma(v[3], v[6], fma(v[4], v[7], v[5] * v[8]));
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 3 * NR; ++c)
-                        v[3 + c] = fs[(size_t)c * n + j];
+                for (int d = 0; d < 3; ++d) {
+                    const double g = fmax(0.0, fmax(sb[d] + sh[d] - thi[d], tlo[d] - (sb[3 + d] + sh[d])));
+                    gap2 += g * g;
                 }
-                if (2 * W2 > 3 + NV)
-                    v[2 * W2 - 1] = 0.0;
-#pragma unroll
-                for (int c = 0; c < W2; ++c)
-                    S[pos][c] = make_double2(v[2 * c], v[2 * c + 1]);
+                cnear = gap2 < rl2;
             }
-            __syncthreads();
-            for (int jj = sl; jj < kept; jj += SG) {
-                double v[2 * W2];
-#pragma unroll
-                for (int c = 0; c < W2; ++c) {
-                    const double2 t2 = S[jj][c];
-                    v[2 * c] = t2.x;
-                    v[2 * c + 1] = t2.y;
+            for (unsigned long long cm = __ballot(cnear); cm != 0; cm &= cm - 1) {
+                const int k = kb + __ffsll((long long)cm) - 1;
+                const int64_t s0 = E.sstart + 64 * (int64_t)k;
+                const int ccnt = (int)min((int64_t)64, E.send - s0);
+                double sx = 0, sy = 0, sz = 0;
+                bool keep = false;
+                if (lane < ccnt) {
+                    const int64_t j = s0 + lane;
+                    sx = x[j] + sh[0];
+                    sy = y[j] + sh[1];
+                    sz = z[j] + sh[2];
+                    const double gx = fmax(0.0, fmax(tlo[0] - sx, sx - thi[0]));
+                    const double gy = fmax(0.0, fmax(tlo[1] - sy, sy - thi[1]));
+                    const double gz = fmax(0.0, fmax(tlo[2] - sz, sz - thi[2]));
+                    keep = fma(gx, gx, fma(gy, gy, gz * gz)) < rl2;
                 }
-                if constexpr (KER == 1)
-                    residual_pair_stresslet<ND>(xt, yt, zt, v, rl2, tw, cP, cQ, poly, acc);
-                else
-                    residual_pair_multi<ND, NR>(xt, yt, zt, v, rl2, tw, cP, cQ, poly, acc);
+                const unsigned long long mask = __ballot(keep);
+                const int kept = __popcll(mask);
+                if (kept == 0)
+                    continue;
+                const int pos = __popcll(mask & ((1ull << lane) - 1ull));
+                __syncthreads();
+                if (keep) {
+                    const int64_t j = s0 + lane;
+                    double v[2 * W2];
+                    v[0] = sx;
+                    v[1] = sy;
+                    v[2] = sz;
+                    if (KER == 1) {
+#pragma unroll
+                        for (int c = 0; c < 6; ++c)
+                            v[3 + c] = fs[(size_t)c * n + j];
+                        v[9] = fma(v[3], v[6], fma(v[4], v[7], v[5] * v[8]));
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < 3 * NR; ++c)
+                            v[3 + c] = fs[(size_t)c * n + j];
+                    }
+                    if (2 * W2 > 3 + NV)
+                        v[2 * W2 - 1] = 0.0;
+#pragma unroll
+                    for (int c = 0; c < W2; ++c)
+                        S[pos][c] = make_double2(v[2 * c], v[2 * c + 1]);
+                }
+                __syncthreads();
+                for (int jj = sl; jj < kept; jj += SG) {
+                    double v[2 * W2];
+#pragma unroll
+                    for (int c = 0; c < W2; ++c) {
+                        const double2 t2 = S[jj][c];
+                        v[2 * c] = t2.x;
+                        v[2 * c + 1] = t2.y;
+                    }
+                    if constexpr (KER == 1)
+                        residual_pair_stresslet<ND>(xt, yt, zt, v, rl2, tw, cP, cQ, poly, acc);
+                    else
+                        residual_pair_multi<ND, NR>(xt, yt, zt, v, rl2, tw, cP, cQ, poly, acc);
+                }
             }
         }
     }

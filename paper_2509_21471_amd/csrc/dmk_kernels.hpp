@@ -24,6 +24,21 @@ void launch_morton(const double* pts, int64_t n, const int* pid, const double* g
 // sorted SoA unit coordinates
 void launch_gather_points(const double* pts, int64_t n, const int* perm, const int* pid, const double* geo,
                           double* x, double* y, double* z, hipStream_t s);
+// Reorder of the points inside leaves so that runs of 8, 16, 32 and 64 points
+// (the near field's target groups and source chunks) are spatially compact:
+// recursive balanced bisection across the longest side of each segment's
+// bounding box, cutting after whole 64-point chunks, then whole 8-point groups.
+// A segment starts where a leaf's sources (or targets) start and holds at
+// most kKdCap points.  src[i] = sorted position whose point moves to i
+// (identity outside the segments); perm_out[i] = perm[src[i]].
+constexpr int kKdCap = 4096;
+struct KdSeg {
+    int64_t start;
+    int len;          // 9 .. kKdCap
+    int pad;
+};
+void launch_leaf_order(const KdSeg* segs, int nseg, const int* perm, const double* x, const double* y,
+                       const double* z, int64_t n, int* src, int* perm_out, hipStream_t s);
 // radix sort of (key, index) pairs; temp storage is allocated by the caller
 size_t sort_temp_bytes(int64_t n);
 void launch_sort(void* temp, size_t temp_bytes, const uint64_t* kin, uint64_t* kout, const int* vin, int* vout,
