@@ -405,7 +405,9 @@ def main():
     t_near = near_mean * 1e-3
     achieved = stats["in_support"] * fpp / t_near / 1e12
 
-    near_kernel = f"dmk::k_near<{nd_bucket(info['deg_P'], info['deg_Q'])}, {info['near_lanes']}, 1, 0>"
+    nd = nd_bucket(info['deg_P'], info['deg_Q'])
+    refine = "false" if (nd == 14 and tol >= 1e-6 * (1 - 1e-9)) else "true"
+    near_kernel = f"dmk::k_near<{nd}, {info['near_lanes']}, 1, 0, {refine}>"
     traffic = near_traffic(args.config, tol, "fp64", near_kernel, info["leaf_size"], info["near_lanes"])
     result = {
         "metric": METRIC,

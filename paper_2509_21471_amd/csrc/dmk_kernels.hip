@@ -1488,6 +1488,18 @@ __device__ inline double horner(const double* __restrict__ m, double t)
     return p;
 }
 
+// The same with the leading coefficient already in a vector register (a
+// fused multiply-add reads at most one scalar register).
+template <int ND>
+__device__ inline double horner_v(const double* __restrict__ m, double top, double t)
+{
+    double p = top;
+#pragma unroll
+    for (int k = ND - 2; k >= 0; --k)
+        p = fma(p, t, m[k]);
+    return p;
+}
+
 template <int ND>
 __device__ inline void residual_pair(double dx, double dy, double dz, double fx, double fy, double fz, double rl2,
                                      double tw, double cP, double cQ, const RadialPoly& poly, double& u0,
@@ -1515,21 +1527,28 @@ __device__ inline void residual_pair(double dx, double dy, double dz, double fx,
 
 // The same pair for NR force vectors: the geometry, the square root and both
 // radial polynomials are shared, only the projections onto the forces repeat.
-// v holds the source as (x, y, z, f_0, ..., f_{NR-1}) (already shifted).
-template <int ND, int NR>
+// v holds the source as (x, y, z, f_0, ..., f_{NR-1}) (already shifted) with
+// the forces pre-scaled by 1/(8 pi), so that with c2 = 8 pi cP = 2 / r_l and
+// c3 = 8 pi cQ = 2 / r_l^3 the pair adds
+//   a f' + (d.f') b d,   a = 1/r - c2 P(s),   b = 1/r^3 - c3 Q(s).
+// pt, qt: the leading coefficients of P and Q in vector registers.  RF = false
+// uses the hardware reciprocal square root unrefined (relative error below
+// 6e-8, measured on gfx950), enough for tolerances of 1e-6 and above.
+template <int ND, int NR, bool RF>
 __device__ inline void residual_pair_multi(double xt, double yt, double zt, const double* v, double rl2, double tw,
-                                           double cP, double cQ, const RadialPoly& poly, double (&u)[NR][3])
+                                           double c2, double c3, double pt, double qt, const RadialPoly& poly,
+                                           double (&u)[NR][3])
 {
     const double dx = xt - v[0], dy = yt - v[1], dz = zt - v[2];
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     if (r2 < rl2) {
-        const double rinv = r2 > 0.0 ? rsqrt_f64(r2) : 0.0;
+        const double rq = RF ? rsqrt_f64(r2) : __builtin_amdgcn_rsq(r2);
+        const double rinv = r2 > 0.0 ? rq : 0.0;
         const double t = fma(r2, tw, -1.0);
-        const double P = horner<ND>(poly.P, t);
-        const double Q = horner<ND>(poly.Q, t);
-        const double cr = kInv8Pi * rinv;
-        const double a = fma(-cP, P, cr);
-        const double bq = fma(-cQ, Q, cr * rinv * rinv);
+        const double P = horner_v<ND>(poly.P, pt, t);
+        const double Q = horner_v<ND>(poly.Q, qt, t);
+        const double a = fma(-c2, P, rinv);
+        const double bq = fma(-c3, Q, rinv * rinv * rinv);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             const double fx = v[3 + 3 * r], fy = v[4 + 3 * r], fz = v[5 + 3 * r];
@@ -1584,8 +1603,10 @@ __device__ inline void residual_pair_stresslet(double xt, double yt, double zt, 
 // order, so a force vector's result does not depend on how it was batched.
 // The SG partial sums of a target are combined by cross-lane shuffles.
 // Forces and outputs are [NR][3][n].  KER = 1: the stresslet (NR = 1), with
-// the sources' f and n as fs[6][n].
-template <int ND, int SG, int NR, int KER>
+// the sources' f and n as fs[6][n].  RF: refined reciprocal square root (the
+// Stokeslet pair routine).  The packed tile is padded with up to SG - 1 far
+// away dummy sources, so every lane runs the same number of pair steps.
+template <int ND, int SG, int NR, int KER, bool RF>
 __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, int nwork,
                                              const NearLeaf* __restrict__ leaves,
                                              const NearEntryDev* __restrict__ entries, const double* __restrict__ cbbox,
@@ -1596,7 +1617,7 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
     constexpr int TG = 64 / SG;
     constexpr int NV = KER == 1 ? 7 : 3 * NR;  // staged values per source beyond its position
     constexpr int W2 = (3 + NV + 1) / 2;       // double2 per staged source
-    __shared__ double2 S[64][W2];
+    __shared__ double2 S[64 + SG - 1][W2];
     const NearWork w = work[blockIdx.x];
     const NearLeaf T = leaves[w.leaf];
     const int lane = threadIdx.x;
@@ -1619,6 +1640,9 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
 #pragma unroll
     for (int r = 0; r < NR; ++r)
         acc[r][0] = acc[r][1] = acc[r][2] = 0.0;
+    // leading radial coefficients, held in vector registers
+    double pt = poly.P[ND - 1], qt = poly.Q[ND - 1];
+    asm volatile("" : "+v"(pt), "+v"(qt));
     for (int e = T.ebeg; e < T.eend; ++e) {
         const NearEntryDev E = entries[e];
         // powers of two of the level: exact, and equal to the quotients
@@ -1626,9 +1650,10 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
         const int lam = E.lambda;
         const double rl2 = ldexp(1.0, -2 * lam);
         const double tw = ldexp(2.0, 2 * lam);
-        // Stokeslet: cP = 1/(4 pi r_l), cQ = cP / r_l^2; stresslet: cA, cD
-        const double cP = KER == 1 ? ldexp(3.0 / (2.0 * kPi), 5 * lam) : ldexp(1.0 / (4.0 * kPi), lam);
-        const double cQ = ldexp(1.0 / (4.0 * kPi), 3 * lam);
+        // Stokeslet (forces staged times 1/(8 pi)): c2 = 2 / r_l, c3 = 2 / r_l^3;
+        // stresslet: cA = 3/(2 pi r_l^5), cD = 1/(4 pi r_l^3)
+        const double cP = KER == 1 ? ldexp(3.0 / (2.0 * kPi), 5 * lam) : ldexp(2.0, lam);
+        const double cQ = KER == 1 ? ldexp(1.0 / (4.0 * kPi), 3 * lam) : ldexp(2.0, 3 * lam);
         const double sh[3] = {(double)E.sx, (double)E.sy, (double)E.sz};
         const int nch = (int)((E.send - E.sstart + 63) / 64);
         for (int kb = 0; kb < nch; kb += 64) {
@@ -1681,7 +1706,7 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
                     } else {
 #pragma unroll
                         for (int c = 0; c < 3 * NR; ++c)
-                            v[3 + c] = fs[(size_t)c * n + j];
+                            v[3 + c] = fs[(size_t)c * n + j] * kInv8Pi;
                     }
                     if (2 * W2 > 3 + NV)
                         v[2 * W2 - 1] = 0.0;
@@ -1689,8 +1714,17 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
                     for (int c = 0; c < W2; ++c)
                         S[pos][c] = make_double2(v[2 * c], v[2 * c + 1]);
                 }
+                if (SG > 1 && lane < SG - 1) {
+                    // dummies far outside every support: r^2 >= r_lambda^2
+                    S[kept + lane][0] = make_double2(1e100, 1e100);
+#pragma unroll
+                    for (int c = 1; c < W2; ++c)
+                        S[kept + lane][c] = make_double2(1e100, 0.0);
+                }
                 __syncthreads();
-                for (int jj = sl; jj < kept; jj += SG) {
+                const int steps = (kept + SG - 1) / SG;
+                for (int it = 0; it < steps; ++it) {
+                    const int jj = it * SG + sl;
                     double v[2 * W2];
 #pragma unroll
                     for (int c = 0; c < W2; ++c) {
@@ -1701,7 +1735,7 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
                     if constexpr (KER == 1)
                         residual_pair_stresslet<ND>(xt, yt, zt, v, rl2, tw, cP, cQ, poly, acc);
                     else
-                        residual_pair_multi<ND, NR>(xt, yt, zt, v, rl2, tw, cP, cQ, poly, acc);
+                        residual_pair_multi<ND, NR, RF>(xt, yt, zt, v, rl2, tw, cP, cQ, pt, qt, poly, acc);
                 }
             }
         }
@@ -1735,45 +1769,51 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
         MACRO(24);                 \
     }
 
-void launch_near(int kernel, int sg, int nr, const NearWork* work, int nwork, const NearLeaf* leaves,
+void launch_near(int kernel, int sg, int nr, bool refine, const NearWork* work, int nwork, const NearLeaf* leaves,
                  const NearEntryDev* entries, const double* cbbox, const double* x, const double* y, const double* z,
                  const double* fs, int64_t n, const RadialPoly& poly, double* u, hipStream_t s)
 {
     if (nwork == 0)
         return;
-#define L_NEAR_KK(ND, SG, NR, KER)                                                                             \
-    hipLaunchKernelGGL((k_near<ND, SG, NR, KER>), dim3(nwork), dim3(64), 0, s, work, nwork, leaves, entries, \
+#define L_NEAR_KK(ND, SG, NR, KER, RF)                                                                             \
+    hipLaunchKernelGGL((k_near<ND, SG, NR, KER, RF>), dim3(nwork), dim3(64), 0, s, work, nwork, leaves, entries, \
                        cbbox, x, y, z, fs, n, poly, u)
-#define L_NEAR_K(ND, SG, NR) L_NEAR_KK(ND, SG, NR, 0)
     // batches of several force vectors always use 4 source lanes per target
-#define L_NEAR(ND)                   \
-    if (kernel == 1) {               \
-        if (sg == 1)                 \
-            L_NEAR_KK(ND, 1, 1, 1);  \
-        else if (sg == 2)            \
-            L_NEAR_KK(ND, 2, 1, 1);  \
-        else if (sg == 4)            \
-            L_NEAR_KK(ND, 4, 1, 1);  \
-        else                         \
-            L_NEAR_KK(ND, 8, 1, 1);  \
-    } else if (nr == 2) {            \
-        L_NEAR_K(ND, 4, 2);          \
-    } else if (nr == 4) {            \
-        L_NEAR_K(ND, 4, 4);          \
-    } else if (nr == 8) {            \
-        L_NEAR_K(ND, 4, 8);          \
-    } else if (sg == 1) {            \
-        L_NEAR_K(ND, 1, 1);          \
-    } else if (sg == 2) {            \
-        L_NEAR_K(ND, 2, 1);          \
-    } else if (sg == 4) {            \
-        L_NEAR_K(ND, 4, 1);          \
-    } else {                         \
-        L_NEAR_K(ND, 8, 1);          \
+#define L_STOKES(ND, RF)                     \
+    if (nr == 2) {                           \
+        L_NEAR_KK(ND, 4, 2, 0, RF);          \
+    } else if (nr == 4) {                    \
+        L_NEAR_KK(ND, 4, 4, 0, RF);          \
+    } else if (nr == 8) {                    \
+        L_NEAR_KK(ND, 4, 8, 0, RF);          \
+    } else if (sg == 1) {                    \
+        L_NEAR_KK(ND, 1, 1, 0, RF);          \
+    } else if (sg == 2) {                    \
+        L_NEAR_KK(ND, 2, 1, 0, RF);          \
+    } else if (sg == 4) {                    \
+        L_NEAR_KK(ND, 4, 1, 0, RF);          \
+    } else {                                 \
+        L_NEAR_KK(ND, 8, 1, 0, RF);          \
+    }
+    // the unrefined square root only with the shortest fits (tol >= 1e-6)
+#define L_NEAR(ND)                           \
+    if (kernel == 1) {                       \
+        if (sg == 1)                         \
+            L_NEAR_KK(ND, 1, 1, 1, true);    \
+        else if (sg == 2)                    \
+            L_NEAR_KK(ND, 2, 1, 1, true);    \
+        else if (sg == 4)                    \
+            L_NEAR_KK(ND, 4, 1, 1, true);    \
+        else                                 \
+            L_NEAR_KK(ND, 8, 1, 1, true);    \
+    } else if (ND == 14 && !refine) {        \
+        L_STOKES(14, false);                 \
+    } else {                                 \
+        L_STOKES(ND, true);                  \
     }
     DMK_ND_DISPATCH(poly.nd, L_NEAR)
 #undef L_NEAR
-#undef L_NEAR_K
+#undef L_STOKES
 #undef L_NEAR_KK
 }
 

@@ -174,7 +174,9 @@ struct RadialPoly {
 // kernel 0 (Stokeslet): forces and outputs [nr][3][n]; nr in {1, 2, 4, 8}
 // kernel 1 (stresslet): fs = (f, n) as [6][n], output [3][n], nr = 1;
 // poly holds the stresslet's radial functions A (P) and D (Q)
-void launch_near(int kernel, int sg, int nr, const NearWork* work, int nwork, const NearLeaf* leaves,
+// refine = false (Stokeslet, tol >= 1e-6 only): the hardware reciprocal square
+// root without the Newton step (relative error below 6e-8)
+void launch_near(int kernel, int sg, int nr, bool refine, const NearWork* work, int nwork, const NearLeaf* leaves,
                  const NearEntryDev* entries, const double* cbbox, const double* x, const double* y, const double* z,
                  const double* fs, int64_t n, const RadialPoly& poly, double* u, hipStream_t s);
 
