@@ -209,8 +209,9 @@ void launch_gather_points(const double* pts, int64_t n, const int* perm, const i
 // 12 bits); keys are distinct, so the bitonic sort gives one order.
 namespace {
 constexpr int kKdMaxSeg = kKdCap / 8;
+constexpr int kKdThreads = 1024;  // 16 waves: the sort stages are latency bound
 
-__global__ __launch_bounds__(256) void k_leaf_kd(const KdSeg* __restrict__ segs, const double* __restrict__ x,
+__global__ __launch_bounds__(kKdThreads) void k_leaf_kd(const KdSeg* __restrict__ segs, const double* __restrict__ x,
                                                  const double* __restrict__ y, const double* __restrict__ z,
                                                  int* __restrict__ src)
 {
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(256) void k_leaf_kd(const KdSeg* __restrict__ segs,
     __shared__ int t_lo[2][kKdMaxSeg], t_len[2][kKdMaxSeg];
     __shared__ float s_min[kKdMaxSeg], s_inv[kKdMaxSeg];
     __shared__ int s_ax[kKdMaxSeg];
-    __shared__ int more;
+    __shared__ int seg_max;   // longest segment of the current level
     const KdSeg S = segs[blockIdx.x];
     const int len = S.len;
     if (len <= 8 || len > kKdCap)
@@ -229,7 +230,7 @@ __global__ __launch_bounds__(256) void k_leaf_kd(const KdSeg* __restrict__ segs,
     int P2 = 1;
     while (P2 < len)
         P2 <<= 1;
-    for (int i = tid; i < P2; i += 256) {
+    for (int i = tid; i < P2; i += kKdThreads) {
         if (i < len) {
             c[0][i] = (float)(x[S.start + i] - ox);
             c[1][i] = (float)(y[S.start + i] - oy);
@@ -240,12 +241,13 @@ __global__ __launch_bounds__(256) void k_leaf_kd(const KdSeg* __restrict__ segs,
     if (tid == 0) {
         t_lo[0][0] = 0;
         t_len[0][0] = len;
+        seg_max = len;
     }
     __syncthreads();
     for (int depth = 0, cur = 0; depth < 10; ++depth, cur ^= 1) {
         const int nid = 1 << depth;
         // bounding box, cut axis and quantisation of every segment to cut
-        for (int k = wid; k < nid; k += 4) {
+        for (int k = wid; k < nid; k += kKdThreads / 64) {
             const int lo = t_lo[cur][k], sl = t_len[cur][k];
             if (sl <= 8)
                 continue;
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(256) void k_leaf_kd(const KdSeg* __restrict__ segs,
         }
         __syncthreads();
         // keys of this level
-        for (int k = wid; k < nid; k += 4) {
+        for (int k = wid; k < nid; k += kKdThreads / 64) {
             const int lo = t_lo[cur][k], sl = t_len[cur][k];
             const bool cut = sl > 8;
             const int ax = cut ? s_ax[k] : 0;
@@ -293,14 +295,18 @@ __global__ __launch_bounds__(256) void k_leaf_kd(const KdSeg* __restrict__ segs,
             }
         }
         __syncthreads();
-        // bitonic sort of key[0, P2) (padding keys sort last)
-        for (int kk = 2; kk <= P2; kk <<= 1)
+        // bitonic sort of key[0, P2) (padding keys sort last); once every
+        // segment has at most 64 points it lies inside one aligned 64-block
+        // (cuts above 64 points fall on chunk boundaries), and sorting each
+        // block on its own, ascending, is enough
+        const int kmax = seg_max <= 64 ? min(64, P2) : P2;
+        for (int kk = 2; kk <= kmax; kk <<= 1)
             for (int j = kk >> 1; j > 0; j >>= 1) {
-                for (int t = tid; t < P2 / 2; t += 256) {
+                for (int t = tid; t < P2 / 2; t += kKdThreads) {
                     const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
                     const int l = i + j;
                     const uint32_t a = key[i], b = key[l];
-                    if ((a > b) == ((i & kk) == 0)) {
+                    if ((a > b) == (kk == kmax || (i & kk) == 0)) {
                         key[i] = b;
                         key[l] = a;
                     }
@@ -308,10 +314,11 @@ __global__ __launch_bounds__(256) void k_leaf_kd(const KdSeg* __restrict__ segs,
                 __syncthreads();
             }
         // cut: children 2k and 2k + 1 of the next level
-        if (tid == 0)
-            more = 0;
         __syncthreads();
-        for (int k = tid; k < nid; k += 256) {
+        if (tid == 0)
+            seg_max = 0;
+        __syncthreads();
+        for (int k = tid; k < nid; k += kKdThreads) {
             const int lo = t_lo[cur][k], sl = t_len[cur][k];
             int left = sl;
             if (sl > 8) {
@@ -324,14 +331,13 @@ __global__ __launch_bounds__(256) void k_leaf_kd(const KdSeg* __restrict__ segs,
                 t_lo[cur ^ 1][2 * k + 1] = lo + left;
                 t_len[cur ^ 1][2 * k + 1] = sl - left;
             }
-            if (left > 8 || sl - left > 8)
-                more = 1;
+            atomicMax(&seg_max, max(left, sl - left));
         }
         __syncthreads();
-        if (!more || 2 * nid > kKdMaxSeg)
+        if (seg_max <= 8 || 2 * nid > kKdMaxSeg)
             break;
     }
-    for (int i = tid; i < len; i += 256)
+    for (int i = tid; i < len; i += kKdThreads)
         src[S.start + i] = (int)(S.start + (key[i] & 0xfffu));
 }
 
@@ -356,7 +362,7 @@ void launch_leaf_order(const KdSeg* segs, int nseg, const int* perm, const doubl
 {
     hipLaunchKernelGGL(k_iota, dim3(nblocks(n, 256)), dim3(256), 0, s, src, n);
     if (nseg > 0)
-        hipLaunchKernelGGL(k_leaf_kd, dim3(nseg), dim3(256), 0, s, segs, x, y, z, src);
+        hipLaunchKernelGGL(k_leaf_kd, dim3(nseg), dim3(kKdThreads), 0, s, segs, x, y, z, src);
     hipLaunchKernelGGL(k_compose, dim3(nblocks(n, 256)), dim3(256), 0, s, perm, src, n, perm_out);
 }
 
@@ -759,8 +765,14 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
 {
     using C = AMCfg<P>;
     constexpr int PA = C::PA, NN = C::NN;
-    const int task = blockIdx.x % C::TASKS;
-    const LeafDesc L = leaves[blockIdx.x / C::TASKS];
+    // workgroups go to the 8 XCDs in turn: leaf k runs all its waves on XCD
+    // k % 8, so its Lagrange rows and forces are read into one L2 only
+    const int xcd = blockIdx.x % 8, sx = blockIdx.x / 8;
+    const int task = sx % C::TASKS;
+    const int leaf = xcd + 8 * (sx / C::TASKS);
+    if (leaf >= nleaf)
+        return;
+    const LeafDesc L = leaves[leaf];
     const int mt = task % C::MT, ng = task / C::MT;
     const int l = threadIdx.x;
     const int li = l & 15, lk = l >> 4;
@@ -890,12 +902,13 @@ void launch_anterp(int p, int nc, const LeafDesc* leaves, int nleaf, const doubl
 {
     if (nleaf == 0)
         return;
+    const int nleaf8 = (nleaf + 7) / 8 * 8;
 #define L_ANTERP_NC(P, NC)                                                                                       \
     if (f32)                                                                                                     \
-        hipLaunchKernelGGL((k_anterp_mfma<P, NC, float>), dim3(nleaf * AMCfg<P>::TASKS), dim3(64), 0, s, leaves, \
+        hipLaunchKernelGGL((k_anterp_mfma<P, NC, float>), dim3(nleaf8 * AMCfg<P>::TASKS), dim3(64), 0, s, leaves,\
                            nleaf, Ltab, fs, n, (float*)Q);                                                       \
     else                                                                                                         \
-        hipLaunchKernelGGL((k_anterp_mfma<P, NC, double>), dim3(nleaf * AMCfg<P>::TASKS), dim3(64), 0, s,        \
+        hipLaunchKernelGGL((k_anterp_mfma<P, NC, double>), dim3(nleaf8 * AMCfg<P>::TASKS), dim3(64), 0, s,       \
                            leaves, nleaf, Ltab, fs, n, (double*)Q)
 #define L_ANTERP(P)               \
     if (nc == 6) {                \
