@@ -462,6 +462,44 @@ bool make_poly(const dmk::Tables& TB, dmk::RadialPoly* poly)
     return true;
 }
 
+// Near-field work items in launch order.  Workgroups go to the 8 XCDs of the
+// device in turn (workgroup g to XCD g % 8), and each XCD has its own L2.  The
+// leaves, in Morton order, are cut into 8 * kPieces runs of about equal cost
+// (listed pairs); run r goes to XCD r % 8, so all target groups of a leaf and
+// most of its neighbours' sources meet in one L2, and the XCDs get equal work.
+// Each XCD's items sit at positions x, x + 8, x + 16, ...; the shorter lists
+// are padded with empty items (leaf -1).
+std::vector<dmk::NearWork> xcd_work_order(const std::vector<dmk::NearWork>& items, const std::vector<double>& cost)
+{
+    constexpr int kXcd = 8, kPieces = 16;
+    const size_t nl = cost.size();
+    if (items.empty() || nl == 0)
+        return items;
+    double total = 0;
+    for (double c : cost)
+        total += c;
+    std::vector<int> xcd_of(nl);
+    double run = 0;
+    for (size_t l = 0; l < nl; ++l) {
+        // run index of the leaf's cost midpoint
+        const double mid = run + 0.5 * cost[l];
+        const int r = total > 0 ? std::min(kXcd * kPieces - 1, (int)(mid / total * kXcd * kPieces)) : (int)(l % kXcd);
+        xcd_of[l] = r % kXcd;
+        run += cost[l];
+    }
+    std::vector<std::vector<dmk::NearWork>> lists(kXcd);
+    for (const dmk::NearWork& w : items)
+        lists[xcd_of[w.leaf]].push_back(w);
+    size_t len = 0;
+    for (const auto& v : lists)
+        len = std::max(len, v.size());
+    std::vector<dmk::NearWork> out(kXcd * len, dmk::NearWork{-1, 0});
+    for (int x = 0; x < kXcd; ++x)
+        for (size_t k = 0; k < lists[x].size(); ++k)
+            out[kXcd * k + x] = lists[x][k];
+    return out;
+}
+
 // Morton code at a level <-> integer cell coordinates (digit 4 bx + 2 by + bz)
 uint64_t cell_code(int64_t ix, int64_t iy, int64_t iz, int level)
 {
@@ -519,6 +557,7 @@ int build_ewald(dmk_plan_t P, const std::vector<uint64_t>& keys, hipStream_t st)
     std::vector<NearLeaf> nlv;
     std::vector<NearEntryDev> nent;
     std::vector<NearWork> nwk;
+    std::vector<double> cell_cost;
     P->near_listed = 0;
     P->n_cells_nonempty = 0;
     for (int64_t ix = 0; ix < NC; ++ix)
@@ -528,6 +567,7 @@ int build_ewald(dmk_plan_t P, const std::vector<uint64_t>& keys, hipStream_t st)
                 if (cs[c + 1] == cs[c])
                     continue;
                 ++P->n_cells_nonempty;
+                const int64_t listed0 = P->near_listed;
                 NearLeaf T;
                 T.tstart = cs[c];
                 T.tend = cs[c + 1];
@@ -571,7 +611,9 @@ int build_ewald(dmk_plan_t P, const std::vector<uint64_t>& keys, hipStream_t st)
                 for (int k = 0; k < nch; ++k)
                     nwk.push_back(NearWork{li, k});
                 nlv.push_back(T);
+                cell_cost.push_back((double)(P->near_listed - listed0));
             }
+    nwk = xcd_work_order(nwk, cell_cost);
     P->n_nwork = (int)nwk.size();
     P->nleaves = P->mem.alloc<NearLeaf>(nlv.size());
     P->nentries = P->mem.alloc<NearEntryDev>(nent.size());
@@ -954,8 +996,10 @@ int build_plan(dmk_plan_t P, const double* points)
     std::vector<NearLeaf> nlv;
     std::vector<NearEntryDev> nent;
     std::vector<NearWork> nwk;
+    std::vector<double> leaf_cost;
     for (int li = 0; li < (int)T.leaves.size(); ++li) {
         const Box& B = T.boxes[T.leaves[li]];
+        const int64_t listed0 = P->near_listed;
         NearLeaf L;
         L.tstart = split ? B.start + box_nsrc[T.leaves[li]] : B.start;
         L.tend = B.end;
@@ -981,7 +1025,9 @@ int build_plan(dmk_plan_t P, const double* points)
         for (int c = 0; c < nch; ++c)
             nwk.push_back(NearWork{li, c});
         nlv.push_back(L);
+        leaf_cost.push_back((double)(P->near_listed - listed0));
     }
+    nwk = xcd_work_order(nwk, leaf_cost);
     P->n_nwork = (int)nwk.size();
     lap(3);
     P->nleaves = P->mem.alloc<NearLeaf>(nlv.size());

@@ -1632,6 +1632,8 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
     constexpr int W2 = (3 + NV + 1) / 2;       // double2 per staged source
     __shared__ double2 S[64 + SG - 1][W2];
     const NearWork w = work[blockIdx.x];
+    if (w.leaf < 0)  // padding of the per-XCD work lists
+        return;
     const NearLeaf T = leaves[w.leaf];
     const int lane = threadIdx.x;
     const int tl = lane / SG, sl = lane % SG;
@@ -1840,6 +1842,8 @@ __global__ __launch_bounds__(64) void k_near_count(const NearWork* __restrict__ 
 {
     constexpr int TG = 64 / SG;
     const NearWork w = work[blockIdx.x];
+    if (w.leaf < 0)  // padding of the per-XCD work lists
+        return;
     const NearLeaf T = leaves[w.leaf];
     const int lane = threadIdx.x;
     const int tl = lane / SG, sl = lane % SG;

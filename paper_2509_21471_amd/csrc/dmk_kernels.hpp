@@ -161,7 +161,7 @@ struct NearEntryDev {
     int8_t sx, sy, sz, lambda;
 };
 struct NearWork {
-    int leaf;
+    int leaf;         // -1: an empty item (padding)
     int chunk;        // target group index within the leaf (groups of 64/sg points)
 };
 // P and Q as monomials in t = 2s - 1, both padded with zero leading
