@@ -698,29 +698,34 @@ __global__ __launch_bounds__(EvalCfg<P>::PTS * 4) void k_leaf_eval(const EvalChu
     put(0);
     __syncthreads();
     double u0 = 0, u1 = 0, u2 = 0;
+    // a wave whose 16 points all lie past the chunk's end (the tail chunk of
+    // a leaf) only helps to stage the slabs
+    const bool busy = __ballot(valid) != 0ull;
 #pragma unroll 1
     for (int c = 0; c < P; ++c) {
         const int cur = c & 1;
         if (c + 1 < P)
             fetch(c + 1);
-        const double lz = valid ? Li[2 * PA + c] : 0.0;
-        double X[3] = {0, 0, 0};
+        if (busy) {
+            const double lz = valid ? Li[2 * PA + c] : 0.0;
+            double X[3] = {0, 0, 0};
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
+            for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
+                for (int t = 0; t < NT; ++t) {
+                    mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int s = 0; s < NK; ++s)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(slab[cur][j][16 * t + lr][4 * s + lk], bx[s], acc, 0, 0,
-                                                               0);
+                    for (int s = 0; s < NK; ++s)
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(slab[cur][j][16 * t + lr][4 * s + lk], bx[s], acc,
+                                                                   0, 0, 0);
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    X[j] = fma(wy[t][r], acc[r], X[j]);
-            }
-        u0 = fma(lz, X[0], u0);
-        u1 = fma(lz, X[1], u1);
-        u2 = fma(lz, X[2], u2);
+                    for (int r = 0; r < 4; ++r)
+                        X[j] = fma(wy[t][r], acc[r], X[j]);
+                }
+            u0 = fma(lz, X[0], u0);
+            u1 = fma(lz, X[1], u1);
+            u2 = fma(lz, X[2], u2);
+        }
         // the other buffer was last read before the previous barrier
         if (c + 1 < P)
             put(cur ^ 1);
