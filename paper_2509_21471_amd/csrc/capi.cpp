@@ -289,9 +289,12 @@ struct dmk_plan_s {
     std::vector<int> leaf_box;        // leaf index (all leaves) -> box id
     // phase timing
     bool timing = false;
-    // ev[0..10]: phase boundaries; ev[11]: start of the near field (the far
-    // field of the batch's other vectors runs between ev[8] and ev[11])
-    hipEvent_t ev[DMK_NUM_PHASES + 2] = {};
+    // ev[0..8]: far-field phase boundaries (first vector of a batch); ev[11]
+    // to ev[9]: the near field (with the force gather); ev[12] to ev[10]:
+    // finalize.  The near field runs first, so an evaluation ends with many
+    // short far-field launches, between which the work of a plan being built
+    // concurrently on another stream gets onto the device.
+    hipEvent_t ev[DMK_NUM_PHASES + 3] = {};
     int rhs_batch = 8;                // force vectors per near-field pass
     bool concurrent = false;          // build on the library's plan stream
     // DMK_FLAG_GRAPH: evaluation captured once per (forces, n_rhs, velocities)
@@ -1148,7 +1151,7 @@ int build_plan(dmk_plan_t P, const double* points)
 
 // Far field of force vector r of the current batch (sorted forces at
 // fs + 3nr): every pass from the proxy charges to the potential at the points
-// (u + 3nr, overwritten).  The work buffers are shared, so the passes of the
+// (added to u + 3nr).  The work buffers are shared, so the passes of the
 // batch's vectors run one vector after the other.
 void far_field(dmk_plan_t P, int r, bool record)
 {
@@ -1278,27 +1281,31 @@ void far_field(dmk_plan_t P, int r, bool record)
     mark(8);
 }
 
-// Evaluates nb (1, 2, 4 or 8) force vectors: gather, far field per vector,
-// one near-field pass for the whole batch (Step 4, self term included), then
-// the constant, scaling and unpermutation per vector.  Phase events cover the
-// first vector's far field and the batch's near field and finish.
+// Evaluates nb (1, 2, 4 or 8) force vectors: gather, one near-field pass for
+// the whole batch (Step 4, self term included), the far field per vector
+// (added), then the constant, scaling and unpermutation per vector.  Phase
+// events cover the batch's near field, the first vector's far field and the
+// finish.
 int eval_batch(dmk_plan_t P, const double* f, int nb, double* vel, bool record)
 {
     using namespace dmk;
     hipStream_t st = P->stream;
     const int64_t n = P->n;
     if (record)
-        (void)hipEventRecord(P->ev[0], st);
+        (void)hipEventRecord(P->ev[DMK_NUM_PHASES + 1], st);
     for (int r = 0; r < nb; ++r)
         launch_gather_forces(f + (size_t)r * 3 * P->nsrc, n, P->nsrc, P->perm, P->fs + (size_t)r * 3 * n, st);
+    launch_zero(P->u, (size_t)nb * 3 * n * sizeof(double), st);
+    launch_near(DMK_KERNEL_STOKESLET, P->near_sg, nb, P->near_refine, P->nwork, P->n_nwork, P->nleaves, P->nentries,
+                P->cbbox, P->x, P->y, P->z, P->fs, n, P->poly, P->u, st);
+    if (record) {
+        (void)hipEventRecord(P->ev[9], st);
+        (void)hipEventRecord(P->ev[0], st);
+    }
     for (int r = 0; r < nb; ++r)
         far_field(P, r, record && r == 0);
     if (record)
-        (void)hipEventRecord(P->ev[DMK_NUM_PHASES + 1], st);
-    launch_near(DMK_KERNEL_STOKESLET, P->near_sg, nb, P->near_refine, P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x, P->y, P->z, P->fs, n,
-                P->poly, P->u, st);
-    if (record)
-        (void)hipEventRecord(P->ev[9], st);
+        (void)hipEventRecord(P->ev[DMK_NUM_PHASES + 2], st);
     for (int r = 0; r < nb; ++r)
         launch_finalize(P->u + (size_t)r * 3 * n, n, P->perm, P->tofs, P->pid, P->scale, 0,
                         P->periodic ? nullptr : P->cst + (size_t)3 * P->nprob * r, nullptr, nullptr, nullptr, nullptr,
@@ -1322,15 +1329,18 @@ int eval_stresslet(dmk_plan_t P, const double* f, const double* nv, double* vel,
     hipStream_t st = P->stream;
     const int64_t n = P->n;
     if (record)
-        (void)hipEventRecord(P->ev[0], st);
-    launch_gather_stresslet(f, nv, n, P->nsrc, P->perm, P->fs, P->fs + 6 * (size_t)n, st);
-    far_field(P, 0, record);
-    if (record)
         (void)hipEventRecord(P->ev[DMK_NUM_PHASES + 1], st);
+    launch_gather_stresslet(f, nv, n, P->nsrc, P->perm, P->fs, P->fs + 6 * (size_t)n, st);
+    launch_zero(P->u, 3 * (size_t)n * sizeof(double), st);
     launch_near(DMK_KERNEL_STRESSLET, P->near_sg, 1, true, P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x,
                 P->y, P->z, P->fs + 6 * (size_t)n, n, P->poly, P->u, st);
-    if (record)
+    if (record) {
         (void)hipEventRecord(P->ev[9], st);
+        (void)hipEventRecord(P->ev[0], st);
+    }
+    far_field(P, 0, record);
+    if (record)
+        (void)hipEventRecord(P->ev[DMK_NUM_PHASES + 2], st);
     // periodic: the k = 0 term -sum_s (x_t - x_s)(f_s . n_s) from the root moments in cst
     launch_finalize(P->u, n, P->perm, P->tofs, P->pid, P->scale, 1, nullptr, P->periodic ? P->cst : nullptr, P->x,
                     P->y, P->z, vel, st);
@@ -1377,6 +1387,7 @@ int eval_ewald(dmk_plan_t P, const double* f, double* vel, bool record)
     launch_near(DMK_KERNEL_STOKESLET, P->near_sg, 1, P->near_refine, P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x,
                 P->y, P->z, P->fs, n, P->poly, P->u, st);
     mark(9);
+    mark(DMK_NUM_PHASES + 2);
     launch_finalize(P->u, n, P->perm, P->tofs, P->pid, P->scale, 0, nullptr, nullptr, nullptr, nullptr, nullptr, vel,
                     st);
     if (record) {
@@ -1995,6 +2006,8 @@ int dmk_stokes_phase_ms(dmk_plan_t plan, double* out)
         float ms = 0;
         if (k == DMK_PHASE_NEAR)
             HIPCHK(hipEventElapsedTime(&ms, plan->ev[DMK_NUM_PHASES + 1], plan->ev[k + 1]));
+        else if (k == DMK_PHASE_FINALIZE)
+            HIPCHK(hipEventElapsedTime(&ms, plan->ev[DMK_NUM_PHASES + 2], plan->ev[k + 1]));
         else
             HIPCHK(hipEventElapsedTime(&ms, plan->ev[k], plan->ev[k + 1]));
         out[k] = ms;

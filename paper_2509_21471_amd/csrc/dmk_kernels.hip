@@ -739,9 +739,9 @@ __global__ __launch_bounds__(EvalCfg<P>::PTS * 4) void k_leaf_eval(const EvalChu
     u1 += __shfl_xor(u1, 32);
     u2 += __shfl_xor(u2, 32);
     if (valid && lk == 0) {
-        u[i] = u0;
-        u[n + i] = u1;
-        u[2 * n + i] = u2;
+        u[i] += u0;
+        u[n + i] += u1;
+        u[2 * n + i] += u2;
     }
 }
 

@@ -78,7 +78,7 @@ void launch_lagrange_table(int p, const LeafDesc* leaves, int nleaf, const doubl
 void launch_anterp(int p, int nc, const LeafDesc* leaves, int nleaf, const double* Ltab, const double* fs, int64_t n,
                    void* Q, bool f32, hipStream_t s);
 // far-field value at the points (final interpolation), V z-major V[fid][j][c][b][a]:
-// u[j][i] = sum V L L L, over chunks of at most eval_chunk_points(p) points of
+// u[j][i] += sum V L L L, over chunks of at most eval_chunk_points(p) points of
 // one leaf (one block of 4 threads per point)
 int eval_chunk_points(int p);
 struct EvalChunk {
