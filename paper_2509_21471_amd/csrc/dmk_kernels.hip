@@ -550,12 +550,16 @@ __global__ __launch_bounds__(256) void k_lagrange_table(const LeafDesc* __restri
     const double* crd[3] = {x, y, z};
     for (int64_t i = L.start + threadIdx.x; i < L.end; i += 256) {
         for (int d = 0; d < 3; ++d) {
-            double Lv[P];
+            double Lv[PA];
             lagrange<P>((crd[d][i] - cen[d]) * sc, ct, cw, Lv);
-            double* o = Ltab + ((size_t)i * 3 + d) * PA;
 #pragma unroll
-            for (int a = 0; a < PA; ++a)
-                o[a] = a < P ? Lv[a] : 0.0;
+            for (int a = P; a < PA; ++a)
+                Lv[a] = 0.0;
+            // PA is a multiple of 4, so each row is 32-byte aligned: 16-byte stores
+            double2* o = reinterpret_cast<double2*>(Ltab + ((size_t)i * 3 + d) * PA);
+#pragma unroll
+            for (int a = 0; a < PA / 2; ++a)
+                o[a] = make_double2(Lv[2 * a], Lv[2 * a + 1]);
         }
     }
 }
