@@ -954,14 +954,18 @@ struct StageTraits {
     static constexpr bool fold = (MODE != ST_IN_HALF_REAL);
 };
 
-// 256 threads per 64-row tile: the input slab X[0..Nin)[r0..r0+64) is staged
-// in LDS with all loads in flight, thread (row, g) accumulates the half
-// outputs g, g+4, ... from it, and the output tile Y[r0..r0+64)[0..Nout) is
-// staged in LDS again and written as one contiguous block (or scatter-added to
-// the children's grids, one contiguous run of p per row and child).
-template <int MODE, int IO, int NI, typename S>
+// 256 threads per RT-row tile (RT = 64 or 32): the input slab
+// X[0..Nin)[r0..r0+RT) is staged in LDS with all loads in flight, thread
+// (row, g) accumulates the half outputs g, g+NG, ... (NG = 256/RT groups)
+// from it, and the output tile Y[r0..r0+RT)[0..Nout) is staged in LDS again
+// and written as one contiguous block (or scatter-added to the children's
+// grids, one contiguous run of p per row and child).  Long axes take RT = 32:
+// half the LDS and half the accumulators per thread, twice the workgroups per
+// CU to keep loads in flight.
+template <int MODE, int IO, int NI, int RT, typename S>
 __global__ __launch_bounds__(256) void k_stage(StageArgs a)
 {
+    constexpr int NG = 256 / RT;
     using Tr = StageTraits<MODE>;
     constexpr int XE = Tr::xc ? 2 : 1;
     constexpr int YE = Tr::yc ? 2 : 1;
@@ -975,14 +979,14 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
     const int nc = a.ncomp;
     const int slot = a.slot0 + (int)blockIdx.y / nc, comp = blockIdx.y % nc;
     const int R = a.R, Nin = a.Nin, Nout = a.Nout, p = a.p;
-    const int r0 = blockIdx.x * 64;
-    const int nrow = min(64, R - r0);
+    const int r0 = blockIdx.x * RT;
+    const int nrow = min(RT, R - r0);
     const size_t p3 = (size_t)p * p * p;
     // ---- input slab ----
     {
         const size_t xoff = ((size_t)(a.xmap ? a.xmap[slot] : slot - a.xbase) * nc + comp) * a.xstride;
-        for (int e = tid; e < Nin * 64; e += 256) {
-            const int k = e >> 6, rr = e & 63;
+        for (int e = tid; e < Nin * RT; e += 256) {
+            const int k = e / RT, rr = e % RT;
             const int r = r0 + rr;
             double v0 = 0.0, v1 = 0.0;
             if (rr < nrow) {
@@ -1007,7 +1011,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
         }
     }
     __syncthreads();
-    const int lane = tid & 63, g = tid >> 6;
+    const int lane = tid % RT, g = tid / RT;
     double Ur[NI], Ui[NI], Wr[NI], Wi[NI];
 #pragma unroll
     for (int t = 0; t < NI; ++t)
@@ -1017,18 +1021,18 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
         const int k2 = Nin - 1 - k1;
         double x1r, x1i = 0, x2r = 0, x2i = 0;
         if (XE == 2) {
-            const double2 v1 = ((const double2*)tile)[k1 * 64 + lane];
+            const double2 v1 = ((const double2*)tile)[k1 * RT + lane];
             x1r = v1.x;
             x1i = v1.y;
             if (Tr::fold && k2 != k1) {
-                const double2 v2 = ((const double2*)tile)[k2 * 64 + lane];
+                const double2 v2 = ((const double2*)tile)[k2 * RT + lane];
                 x2r = v2.x;
                 x2i = v2.y;
             }
         } else {
-            x1r = tile[k1 * 64 + lane];
+            x1r = tile[k1 * RT + lane];
             if (k2 != k1)
-                x2r = tile[k2 * 64 + lane];
+                x2r = tile[k2 * RT + lane];
         }
         double er, ei, orr, oi;
         if (Tr::fold) {
@@ -1044,7 +1048,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
         }
 #pragma unroll
         for (int t = 0; t < NI; ++t) {
-            const int i = g + 4 * t;
+            const int i = g + NG * t;
             if (i < a.Nh) {
                 const double2 m = smat[i * a.Kh + j];
                 Ur[t] = fma(m.x, er, Ur[t]);
@@ -1059,7 +1063,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
     __syncthreads();  // input slab consumed; the tile now holds outputs [row][n]
 #pragma unroll
     for (int t = 0; t < NI; ++t) {
-        const int i = g + 4 * t;
+        const int i = g + NG * t;
         if (i >= a.Nh)
             continue;
         const int n1 = i + a.out_off;
@@ -1127,46 +1131,60 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
     }
 }
 
-template <int MODE, int IO, int NI, typename S>
+template <int MODE, int IO, int NI, int RT, typename S>
 static void stage_launch_t(dim3 grid, size_t shm, const StageArgs& a, hipStream_t s)
 {
     static bool attr = false;
     if (!attr) {
-        (void)hipFuncSetAttribute((const void*)k_stage<MODE, IO, NI, S>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
+        (void)hipFuncSetAttribute((const void*)k_stage<MODE, IO, NI, RT, S>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr = true;
     }
-    hipLaunchKernelGGL((k_stage<MODE, IO, NI, S>), grid, dim3(256), shm, s, a);
+    hipLaunchKernelGGL((k_stage<MODE, IO, NI, RT, S>), grid, dim3(256), shm, s, a);
 }
 
-template <int MODE, int IO, int NI>
+template <int MODE, int IO, int NI, int RT>
 static void stage_launch(dim3 grid, size_t shm, const StageArgs& a, hipStream_t s)
 {
     if (a.f32)
-        stage_launch_t<MODE, IO, NI, float>(grid, shm, a, s);
+        stage_launch_t<MODE, IO, NI, RT, float>(grid, shm, a, s);
     else
-        stage_launch_t<MODE, IO, NI, double>(grid, shm, a, s);
+        stage_launch_t<MODE, IO, NI, RT, double>(grid, shm, a, s);
 }
+
+// LDS of a 64-row tile above which the stage runs 32-row tiles
+constexpr size_t kStageLdsSplit = 32 * 1024;
 
 template <int MODE, int IO>
 static void stage_ni(const StageArgs& a, hipStream_t s)
 {
     using Tr = StageTraits<MODE>;
-    const size_t tile = std::max((size_t)a.Nin * 64 * (Tr::xc ? 2 : 1), (size_t)a.Nout * 64 * (Tr::yc ? 2 : 1));
-    const size_t shm = (size_t)a.Nh * a.Kh * sizeof(double2) + tile * sizeof(double);
-    const int ni = (a.Nh + 3) / 4;
+    auto lds = [&](int rt) {
+        const size_t tile =
+            std::max((size_t)a.Nin * rt * (Tr::xc ? 2 : 1), (size_t)a.Nout * rt * (Tr::yc ? 2 : 1));
+        return (size_t)a.Nh * a.Kh * sizeof(double2) + tile * sizeof(double);
+    };
+    const int rt = lds(64) > kStageLdsSplit ? 32 : 64;
+    const size_t shm = lds(rt);
+    const int ni = (a.Nh + 256 / rt - 1) / (256 / rt);
     // grid.y (slot, component) stays within 65535: large slot counts go in chunks
     const int chunk = kMaxGridY / a.ncomp;
     for (int s0 = a.slot0; s0 < a.nslots; s0 += chunk) {
         StageArgs b = a;
         b.slot0 = s0;
-        const dim3 grid(nblocks(a.R, 64), std::min(chunk, a.nslots - s0) * a.ncomp);
-        if (ni <= 4)
-            stage_launch<MODE, IO, 4>(grid, shm, b, s);
-        else if (ni <= 8)
-            stage_launch<MODE, IO, 8>(grid, shm, b, s);
-        else
-            stage_launch<MODE, IO, 12>(grid, shm, b, s);
+        const dim3 grid(nblocks(a.R, rt), std::min(chunk, a.nslots - s0) * a.ncomp);
+        if (rt == 32) {
+            if (ni <= 4)
+                stage_launch<MODE, IO, 4, 32>(grid, shm, b, s);
+            else
+                stage_launch<MODE, IO, 8, 32>(grid, shm, b, s);
+        } else if (ni <= 4) {
+            stage_launch<MODE, IO, 4, 64>(grid, shm, b, s);
+        } else if (ni <= 8) {
+            stage_launch<MODE, IO, 8, 64>(grid, shm, b, s);
+        } else {
+            stage_launch<MODE, IO, 12, 64>(grid, shm, b, s);
+        }
     }
 }
 
