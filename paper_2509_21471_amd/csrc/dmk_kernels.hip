@@ -1153,7 +1153,7 @@ static void stage_launch(dim3 grid, size_t shm, const StageArgs& a, hipStream_t 
 }
 
 // LDS of a 64-row tile above which the stage runs 32-row tiles
-constexpr size_t kStageLdsSplit = 32 * 1024;
+constexpr size_t kStageLdsSplit = 16 * 1024;
 
 template <int MODE, int IO>
 static void stage_ni(const StageArgs& a, hipStream_t s)
