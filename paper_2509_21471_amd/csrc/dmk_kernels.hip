@@ -564,72 +564,6 @@ __global__ __launch_bounds__(256) void k_lagrange_table(const LeafDesc* __restri
     }
 }
 
-// Proxy charges (Step 2a): Q[j][a][b][c] = sum_pt Lx[pt][a] Ly[pt][b] Lz[pt][c] f_j[pt].
-// A block owns (leaf, a-range, bc-range); each thread owns one row (b, c) and
-// accumulates its a-range and the three components.  The per-point values
-// every thread needs (x Lagrange values, forces) have wave-uniform addresses
-// and arrive through scalar loads; each thread reads only its own y/z values.
-template <int P>
-struct AnterpCfg {
-    static constexpr int NA = P <= 12 ? 1 : (P <= 23 ? 2 : (P <= 33 ? 3 : 4));  // a-ranges
-    static constexpr int NBC = P <= 23 ? 1 : (P <= 33 ? 2 : 4);                 // bc-ranges
-    static constexpr int AR = (P + NA - 1) / NA;
-    static constexpr int BCR = (P * P + NBC - 1) / NBC;
-    static constexpr int threads = ((BCR + 63) / 64) * 64;
-};
-
-template <int P, typename S>
-__global__ __launch_bounds__(AnterpCfg<P>::threads) void k_anterp(const LeafDesc* __restrict__ leaves, int nleaf,
-                                                                  const double* __restrict__ Ltab,
-                                                                  const double* __restrict__ fs, int64_t n,
-                                                                  S* __restrict__ Q)
-{
-    using C = AnterpCfg<P>;
-    constexpr int PA = MCfg<P>::PA, AR = C::AR;
-    constexpr int G = C::NA * C::NBC;
-    const int lb = blockIdx.x;
-    if (lb >= nleaf * G)
-        return;
-    const LeafDesc L = leaves[lb / G];
-    const int gi = lb % G;
-    const int ar = gi % C::NA, bcr = gi / C::NA;
-    const int a0 = ar * AR;
-    const int tid = threadIdx.x;
-    const int pair = bcr * C::BCR + tid;
-    const bool valid = tid < C::BCR && pair < P * P;
-    const int b = valid ? pair / P : 0;
-    const int c = valid ? pair % P : 0;
-    double acc[AR][3];
-#pragma unroll
-    for (int t = 0; t < AR; ++t)
-        acc[t][0] = acc[t][1] = acc[t][2] = 0.0;
-    const double* f0 = fs;
-    const double* f1 = fs + n;
-    const double* f2 = fs + 2 * n;
-    // the per-point x weights and forces are wave-uniform (scalar loads)
-#pragma unroll 2
-    for (int64_t pt = L.start; pt < L.end; ++pt) {
-        const double* Lp = Ltab + (size_t)pt * 3 * PA;
-        const double wbc = Lp[PA + b] * Lp[2 * PA + c];
-        const double w0 = wbc * f0[pt], w1 = wbc * f1[pt], w2 = wbc * f2[pt];
-#pragma unroll
-        for (int t = 0; t < AR; ++t) {
-            const double la = (a0 + t < P) ? Lp[a0 + t] : 0.0;
-            acc[t][0] = fma(la, w0, acc[t][0]);
-            acc[t][1] = fma(la, w1, acc[t][1]);
-            acc[t][2] = fma(la, w2, acc[t][2]);
-        }
-    }
-    if (valid) {
-        S* q = Q + (size_t)L.fid * 3 * P * P * P;
-#pragma unroll
-        for (int t = 0; t < AR; ++t)
-            if (a0 + t < P)
-                for (int j = 0; j < 3; ++j)
-                    q[((size_t)j * P + a0 + t) * P * P + b * P + c] = (S)acc[t][j];
-    }
-}
-
 // Far-field potential at the points (final interpolation) as MFMA GEMMs:
 // for every z index c, D[b][pt] = sum_a V[j][c][b][a] Lx[pt][a] (V z-major),
 // then u_j[pt] += Lz[pt][c] sum_b Ly[pt][b] D[b][pt].  A block takes 64 points
