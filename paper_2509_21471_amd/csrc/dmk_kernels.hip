@@ -1148,31 +1148,37 @@ void launch_stage(int mode, int io, const StageArgs& a, hipStream_t s)
 // slab of fixed m_y is read as q runs of n1 contiguous modes, transposed in LDS
 // and written as n1 runs of q contiguous modes, so both sides stay coalesced.
 template <typename S, bool PLAIN>
-__global__ __launch_bounds__(256) void k_translate(int q, int n1, int nrecv, const RecvDesc* __restrict__ recv,
-                                                   const int* __restrict__ e_src, const int8_t* __restrict__ e_off,
+__global__ __launch_bounds__(256) void k_translate(int q, int n1, int nparts, int nrecv,
+                                                   const RecvDesc* __restrict__ recv, const int* __restrict__ e_src,
+                                                   const int8_t* __restrict__ e_off,
                                                    const typename Store<S>::cx* __restrict__ Phi,
                                                    const double* __restrict__ wdiff,
                                                    typename Store<S>::cx* __restrict__ Psi)
 {
-    extern __shared__ cplx tile[];  // [3][m_z][m_x]
+    extern __shared__ cplx tile[];  // [3][m_z][m_x] over this block's m_z range
     const int H = q * n1 * n1;
-    const int NS = q * n1;          // modes in the slab
     // Blocks go round-robin over the 8 XCDs; give each XCD a contiguous run
-    // of (slab, receiver) pairs with the receiver fastest, so that receivers
-    // adjacent in Morton order -- which share most of their colleagues -- read
-    // the same sender slabs through the same L2.
-    const int total = n1 * nrecv;
+    // of (part, slab, receiver) triples with the receiver fastest, so that
+    // receivers adjacent in Morton order -- which share most of their
+    // colleagues -- read the same sender slabs through the same L2.  A slab
+    // is split into nparts ranges of m_z where its LDS tile would be large.
+    const int total = nparts * n1 * nrecv;
     const int lg = xcd_block(total);
     if (lg < 0)
         return;
-    const int iy = lg / nrecv;
-    const RecvDesc rd = recv[lg - iy * nrecv];
+    const int part = lg / (n1 * nrecv);
+    const int rem = lg - part * (n1 * nrecv);
+    const int iy = rem / nrecv;
+    const RecvDesc rd = recv[rem - iy * nrecv];
+    const int h3 = (n1 + nparts - 1) / nparts;
+    const int z0 = part * h3, nz = min(h3, n1 - z0);
+    const int NS = q * nz;          // modes of the slab in this block
     const int m2 = iy - (q - 1);
     const double s3 = 0.86602540378443864676;
     const double lscale = (double)(1ll << rd.level);
     for (int idx = threadIdx.x; idx < NS; idx += blockDim.x) {
-        const int m1 = idx / n1;
-        const int i3 = idx - m1 * n1;
+        const int m1 = idx / nz;
+        const int i3 = z0 + idx - m1 * nz;
         const int m3 = i3 - (q - 1);
         const size_t mi = ((size_t)m1 * n1 + iy) * n1 + i3;
         double F[3][2] = {{0, 0}, {0, 0}, {0, 0}};
@@ -1195,7 +1201,7 @@ __global__ __launch_bounds__(256) void k_translate(int q, int n1, int nrecv, con
             // the symbol was applied on the sending side (stresslet)
 #pragma unroll
             for (int j = 0; j < 3; ++j)
-                tile[(j * n1 + i3) * q + m1] = cplx{F[j][0], F[j][1]};
+                tile[(j * nz + i3 - z0) * q + m1] = cplx{F[j][0], F[j][1]};
         } else {
             const int mm = m1 * m1 + m2 * m2 + m3 * m3;
             const double w = mm > 0 ? wdiff[mm] * lscale : 0.0;
@@ -1205,7 +1211,7 @@ __global__ __launch_bounds__(256) void k_translate(int q, int n1, int nrecv, con
             const int mv[3] = {m1, m2, m3};
 #pragma unroll
             for (int j = 0; j < 3; ++j)
-                tile[(j * n1 + i3) * q + m1] = cplx{w * (F[j][0] - mv[j] * dr), w * (F[j][1] - mv[j] * di)};
+                tile[(j * nz + i3 - z0) * q + m1] = cplx{w * (F[j][0] - mv[j] * dr), w * (F[j][1] - mv[j] * di)};
         }
     }
     __syncthreads();
@@ -1213,8 +1219,8 @@ __global__ __launch_bounds__(256) void k_translate(int q, int n1, int nrecv, con
     for (int idx = threadIdx.x; idx < 3 * NS; idx += blockDim.x) {
         const int j = idx / NS;
         const int r = idx - j * NS;
-        const int i3 = r / q;
-        const int m1 = r - i3 * q;
+        const int i3 = z0 + r / q;
+        const int m1 = r - (i3 - z0) * q;
         const cplx t = tile[idx];
         out[(size_t)j * H + ((size_t)i3 * n1 + iy) * q + m1] = {(S)t.re, (S)t.im};
     }
@@ -1225,8 +1231,10 @@ void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int*
 {
     if (nrecv == 0)
         return;
-    const size_t lds = (size_t)3 * q * n1 * sizeof(cplx);
-    const int total = n1 * nrecv;
+    // two m_z ranges per slab where one tile would exceed 32 KB of LDS
+    const int nparts = (size_t)3 * q * n1 * sizeof(cplx) > 32 * 1024 ? 2 : 1;
+    const size_t lds = (size_t)3 * q * ((n1 + nparts - 1) / nparts) * sizeof(cplx);
+    const int total = nparts * n1 * nrecv;
     static bool attr = false;
     if (!attr) {
         (void)hipFuncSetAttribute((const void*)k_translate<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1240,7 +1248,7 @@ void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int*
         attr = true;
     }
 #define L_TR(T2, S, PL)                                                                                        \
-    hipLaunchKernelGGL((k_translate<S, PL>), dim3(xcd_grid(total)), dim3(256), lds, s, q, n1, nrecv, recv, e_src, \
+    hipLaunchKernelGGL((k_translate<S, PL>), dim3(xcd_grid(total)), dim3(256), lds, s, q, n1, nparts, nrecv, recv, e_src, \
                        e_off, (const T2*)Phi, wdiff, (T2*)Psi)
     if (f32) {
         if (plain)
