@@ -144,8 +144,9 @@ typedef struct {
  * the same up to rounding either way. */
 #define DMK_FLAG_MORTON_ORDER 8
 
-/* phases reported by dmk_stokes_phase_ms, in this order */
-#define DMK_PHASE_ANTERP 0     /* force gather + leaf proxy charges (Step 2a) */
+/* phases reported by dmk_stokes_phase_ms (an evaluation runs the near field
+ * first, then the far-field phases in index order, then the finish) */
+#define DMK_PHASE_ANTERP 0     /* leaf proxy charges (Step 2a) */
 #define DMK_PHASE_MERGE 1      /* upward merge (Step 2b) */
 #define DMK_PHASE_OUTGOING 2   /* outgoing plane waves */
 #define DMK_PHASE_TRANSLATE 3  /* colleague translation + difference symbol (Step 3b) */
@@ -153,7 +154,7 @@ typedef struct {
 #define DMK_PHASE_ROOT 5       /* root convolution (Step 3a) */
 #define DMK_PHASE_INTERP 6     /* downward interpolation */
 #define DMK_PHASE_LEAF_EVAL 7  /* far field at the points */
-#define DMK_PHASE_NEAR 8       /* residual pair sums + self term (Step 4) */
+#define DMK_PHASE_NEAR 8       /* force gather + residual pair sums + self term (Step 4) */
 #define DMK_PHASE_FINALIZE 9   /* constant, scaling, unpermute */
 #define DMK_NUM_PHASES 10
 
