@@ -1552,8 +1552,8 @@ __device__ inline void residual_pair_multi(double xt, double yt, double zt, cons
 // contributes nothing (the stresslet has no self term).
 template <int ND>
 __device__ inline void residual_pair_stresslet(double xt, double yt, double zt, const double* v, double rl2,
-                                               double tw, double cA, double cD, const RadialPoly& poly,
-                                               double (&u)[1][3])
+                                               double tw, double cA, double cD, double pt, double qt,
+                                               const RadialPoly& poly, double (&u)[1][3])
 {
     const double dx = xt - v[0], dy = yt - v[1], dz = zt - v[2];
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
@@ -1561,8 +1561,8 @@ __device__ inline void residual_pair_stresslet(double xt, double yt, double zt, 
         const double rinv = r2 > 0.0 ? rsqrt_f64(r2) : 0.0;
         const double rinv2 = rinv * rinv;
         const double t = fma(r2, tw, -1.0);
-        const double A = horner<ND>(poly.P, t);
-        const double D = horner<ND>(poly.Q, t);
+        const double A = horner_v<ND>(poly.P, pt, t);
+        const double D = horner_v<ND>(poly.Q, qt, t);
         const double df = fma(dx, v[3], fma(dy, v[4], dz * v[5]));
         const double dn = fma(dx, v[6], fma(dy, v[7], dz * v[8]));
         const double c2 = cD * D;
@@ -1717,7 +1717,7 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
                         v[2 * c + 1] = t2.y;
                     }
                     if constexpr (KER == 1)
-                        residual_pair_stresslet<ND>(xt, yt, zt, v, rl2, tw, cP, cQ, poly, acc);
+                        residual_pair_stresslet<ND>(xt, yt, zt, v, rl2, tw, cP, cQ, pt, qt, poly, acc);
                     else
                         residual_pair_multi<ND, NR, RF>(xt, yt, zt, v, rl2, tw, cP, cQ, pt, qt, poly, acc);
                 }
@@ -1934,7 +1934,7 @@ __global__ __launch_bounds__(64) void k_residual_direct_t(const double* __restri
         for (int c = 0; c < 6; ++c)
             v[3 + c] = sf[(size_t)c * ns + j];
         v[9] = fma(v[3], v[6], fma(v[4], v[7], v[5] * v[8]));
-        residual_pair_stresslet<ND>(xt, yt, zt, v, rl2, 2.0 / rl2, cA, cD, poly, acc);
+        residual_pair_stresslet<ND>(xt, yt, zt, v, rl2, 2.0 / rl2, cA, cD, poly.P[ND - 1], poly.Q[ND - 1], poly, acc);
     }
     if (valid) {
         u[3 * i] = acc[0][0];
