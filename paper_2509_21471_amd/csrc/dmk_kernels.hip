@@ -204,9 +204,10 @@ void launch_gather_points(const double* pts, int64_t n, const int* perm, const i
 // level, every segment of more than 8 points is sorted along the longest side
 // of its bounding box and cut after a whole number of 64-point chunks (above
 // 64 points) or 8-point groups (at most 64); children take the ids 2k and
-// 2k + 1, so ids stay in position order and below 2^depth <= 512.  A sort key
-// is (segment id: 9 bits | coordinate quantised to 11 bits | local index:
-// 12 bits); keys are distinct, so the bitonic sort gives one order.
+// 2k + 1, so ids stay in position order and below 2^depth <= kKdCap / 8
+// (at most 8 cut levels for 2048 points).  A sort key is (segment id: 9 bits |
+// coordinate quantised to 11 bits | local index: 12 bits); keys are distinct,
+// so the bitonic sort gives one order.
 namespace {
 constexpr int kKdMaxSeg = kKdCap / 8;
 constexpr int kKdThreads = 1024;  // 16 waves: the sort stages are latency bound

@@ -31,7 +31,7 @@ void launch_gather_points(const double* pts, int64_t n, const int* perm, const i
 // A segment starts where a leaf's sources (or targets) start and holds at
 // most kKdCap points.  src[i] = sorted position whose point moves to i
 // (identity outside the segments); perm_out[i] = perm[src[i]].
-constexpr int kKdCap = 4096;
+constexpr int kKdCap = 2048;
 struct KdSeg {
     int64_t start;
     int len;          // 9 .. kKdCap

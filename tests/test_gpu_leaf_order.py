@@ -32,7 +32,7 @@ def _run(x, f, leaf_order, **kw):
 
 @pytest.mark.parametrize("name,n,leaf,lanes,tol", [
     ("clusters", 60000, 1200, 4, 1e-6),
-    ("clusters", 60000, 5000, 8, 1e-6),     # leaves above 4096 points: two bisection pieces
+    ("clusters", 60000, 5000, 8, 1e-6),     # leaves above 2048 points: several bisection pieces
     ("uniform", 30000, 700, 1, 1e-9),
     ("periodic", 40000, 900, 2, 1e-6),
 ])
