@@ -699,7 +699,25 @@ struct AMCfg {
     static constexpr int NTOT = (P * P + 15) / 16;   // n-tiles
     static constexpr int NN = 2;                     // n-tiles per wave
     static constexpr int NG = (NTOT + NN - 1) / NN;  // n-tile groups
-    static constexpr int TASKS = MT * NG;            // waves per leaf
+    // the last, partial a-tile of every component: its rows (j, a) packed
+    // into row tiles of their own
+    static constexpr int A0 = 16 * (MT - 1);
+    static constexpr int REM = P - A0;
+};
+template <int P, int NC>
+struct AMRem {
+    static constexpr int ROWS = NC * AMCfg<P>::REM;
+    static constexpr int RT = (ROWS + 15) / 16;
+    static constexpr int TASKS = RT * AMCfg<P>::NG;
+    // pack the partial tiles of the three force components where that saves
+    // at least two of nine row tiles per n-tile (p = 33, 36: 8.3 -> 7.9 ms
+    // at 1e-9); at p = 23 one tile saved, and for the six stresslet
+    // densities at p = 26 two of twelve, do not pay for the second, less
+    // loaded launch (measured slower)
+    static constexpr bool SPLIT = NC == 3 && AMCfg<P>::MT * NC - ((AMCfg<P>::MT - 1) * NC + RT) >= 2;
+    // tiles and waves per leaf of k_anterp_mfma
+    static constexpr int MF = SPLIT ? AMCfg<P>::MT - 1 : AMCfg<P>::MT;
+    static constexpr int FULL_TASKS = MF * AMCfg<P>::NG;
 };
 
 template <int P, int NC, typename S>
@@ -709,15 +727,17 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
 {
     using C = AMCfg<P>;
     constexpr int PA = C::PA, NN = C::NN;
+    constexpr int MF = AMRem<P, NC>::MF > 0 ? AMRem<P, NC>::MF : 1;  // a-tiles of this kernel
+    constexpr int TASKS = MF * C::NG;
     // workgroups go to the 8 XCDs in turn: leaf k runs all its waves on XCD
     // k % 8, so its Lagrange rows and forces are read into one L2 only
     const int xcd = blockIdx.x % 8, sx = blockIdx.x / 8;
-    const int task = sx % C::TASKS;
-    const int leaf = xcd + 8 * (sx / C::TASKS);
+    const int task = sx % TASKS;
+    const int leaf = xcd + 8 * (sx / TASKS);
     if (leaf >= nleaf)
         return;
     const LeafDesc L = leaves[leaf];
-    const int mt = task % C::MT, ng = task / C::MT;
+    const int mt = task % MF, ng = task / MF;
     const int l = threadIdx.x;
     const int li = l & 15, lk = l >> 4;
     const int a = 16 * mt + li;
@@ -796,6 +816,92 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
     }
 }
 
+// The rows of the last, partial a-tile, for every component at once: row
+// (j, a), a in [A0, P), packed NC * REM to a column of row tiles (21 rows in
+// two tiles at p = 23 instead of one mostly empty tile per component).  Here
+// the A operand carries the force, Lx[pt][a] f_j[pt], and the B operand is
+// Ly[pt][b] Lz[pt][c] for every component.  Same wave layout, point steps and
+// XCD placement as k_anterp_mfma.
+template <int P, int NC, typename S>
+__global__ __launch_bounds__(64) void k_anterp_rem(const LeafDesc* __restrict__ leaves, int nleaf,
+                                                   const double* __restrict__ Ltab, const double* __restrict__ fs,
+                                                   int64_t n, S* __restrict__ Q)
+{
+    using C = AMCfg<P>;
+    using R = AMRem<P, NC>;
+    constexpr int PA = C::PA, NN = C::NN, A0 = C::A0, REM = C::REM;
+    const int xcd = blockIdx.x % 8, sx = blockIdx.x / 8;
+    const int task = sx % R::TASKS;
+    const int leaf = xcd + 8 * (sx / R::TASKS);
+    if (leaf >= nleaf)
+        return;
+    const LeafDesc L = leaves[leaf];
+    const int rt = task % R::RT, ng = task / R::RT;
+    const int l = threadIdx.x;
+    const int li = l & 15, lk = l >> 4;
+    // this lane's A row
+    const int row = 16 * rt + li;
+    const bool r_ok = row < R::ROWS;
+    const int rj = r_ok ? row / REM : 0;
+    const int ra = A0 + (r_ok ? row % REM : 0);
+    int bcol[NN], ccol[NN];
+    bool n_ok[NN];
+#pragma unroll
+    for (int t = 0; t < NN; ++t) {
+        const int nn = 16 * (NN * ng + t) + li;
+        n_ok[t] = nn < P * P;
+        bcol[t] = n_ok[t] ? nn / P : 0;
+        ccol[t] = n_ok[t] ? nn % P : 0;
+    }
+    mfma_d4 acc[NN];
+#pragma unroll
+    for (int t = 0; t < NN; ++t)
+        acc[t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+    double ar0, ly0[NN], lz0[NN];
+    double ar1, ly1[NN], lz1[NN];
+#define DMK_AR_LOAD(AR, LY, LZ, PT0)                                              \
+    {                                                                             \
+        const int64_t pt = (PT0) + lk;                                            \
+        const bool ok = pt < L.end;                                               \
+        const int64_t pc = ok ? pt : L.start;                                     \
+        const double* Lp = Ltab + (size_t)pc * 3 * PA;                            \
+        const double av = Lp[ra] * fs[(size_t)rj * n + pc];                       \
+        AR = (ok && r_ok) ? av : 0.0;                                             \
+        _Pragma("unroll") for (int t = 0; t < NN; ++t)                            \
+        {                                                                         \
+            const double yv = Lp[PA + bcol[t]];                                   \
+            LY[t] = n_ok[t] ? yv : 0.0;                                           \
+            LZ[t] = Lp[2 * PA + ccol[t]];                                         \
+        }                                                                         \
+    }
+#define DMK_AR_STEP(AR, LY, LZ)                                                              \
+    _Pragma("unroll") for (int t = 0; t < NN; ++t)                                           \
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(AR, LY[t] * LZ[t], acc[t], 0, 0, 0);
+    DMK_AR_LOAD(ar0, ly0, lz0, L.start)
+    for (int64_t p0 = L.start; p0 < L.end; p0 += 8) {
+        DMK_AR_LOAD(ar1, ly1, lz1, p0 + 4)
+        DMK_AR_STEP(ar0, ly0, lz0)
+        DMK_AR_LOAD(ar0, ly0, lz0, p0 + 8)
+        DMK_AR_STEP(ar1, ly1, lz1)
+    }
+#undef DMK_AR_LOAD
+#undef DMK_AR_STEP
+    // D[row = lk + 4 r][col = li] of tile t: remainder row 16 rt + lk + 4 r, n = 16 (NN ng + t) + li
+    S* q = Q + (size_t)L.fid * NC * P * P * P;
+#pragma unroll
+    for (int t = 0; t < NN; ++t) {
+        if (!n_ok[t])
+            continue;
+        const int nn = 16 * (NN * ng + t) + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int rr = 16 * rt + lk + 4 * r;
+            if (rr < R::ROWS)
+                q[((size_t)(rr / REM) * P + A0 + rr % REM) * P * P + nn] = (S)acc[t][r];
+        }
+    }
+}
+
 // Chebyshev orders with compiled point kernels: the Table tab:params values
 // (prolate and Gaussian columns) plus intermediate orders for explicit
 // parameter choices.
@@ -848,12 +954,21 @@ void launch_anterp(int p, int nc, const LeafDesc* leaves, int nleaf, const doubl
         return;
     const int nleaf8 = (nleaf + 7) / 8 * 8;
 #define L_ANTERP_NC(P, NC)                                                                                       \
-    if (f32)                                                                                                     \
-        hipLaunchKernelGGL((k_anterp_mfma<P, NC, float>), dim3(nleaf8 * AMCfg<P>::TASKS), dim3(64), 0, s, leaves,\
-                           nleaf, Ltab, fs, n, (float*)Q);                                                       \
-    else                                                                                                         \
-        hipLaunchKernelGGL((k_anterp_mfma<P, NC, double>), dim3(nleaf8 * AMCfg<P>::TASKS), dim3(64), 0, s,       \
-                           leaves, nleaf, Ltab, fs, n, (double*)Q)
+    if (f32) {                                                                                                   \
+        if constexpr (AMRem<P, NC>::FULL_TASKS > 0)                                                              \
+            hipLaunchKernelGGL((k_anterp_mfma<P, NC, float>), dim3(nleaf8 * AMRem<P, NC>::FULL_TASKS), dim3(64), \
+                               0, s, leaves, nleaf, Ltab, fs, n, (float*)Q);                                     \
+        if constexpr (AMRem<P, NC>::SPLIT)                                                                       \
+            hipLaunchKernelGGL((k_anterp_rem<P, NC, float>), dim3(nleaf8 * AMRem<P, NC>::TASKS), dim3(64), 0, s, \
+                               leaves, nleaf, Ltab, fs, n, (float*)Q);                                           \
+    } else {                                                                                                     \
+        if constexpr (AMRem<P, NC>::FULL_TASKS > 0)                                                              \
+            hipLaunchKernelGGL((k_anterp_mfma<P, NC, double>), dim3(nleaf8 * AMRem<P, NC>::FULL_TASKS),          \
+                               dim3(64), 0, s, leaves, nleaf, Ltab, fs, n, (double*)Q);                          \
+        if constexpr (AMRem<P, NC>::SPLIT)                                                                       \
+            hipLaunchKernelGGL((k_anterp_rem<P, NC, double>), dim3(nleaf8 * AMRem<P, NC>::TASKS), dim3(64), 0,   \
+                               s, leaves, nleaf, Ltab, fs, n, (double*)Q);                                       \
+    }
 #define L_ANTERP(P)               \
     if (nc == 6) {                \
         L_ANTERP_NC(P, 6);        \
