@@ -1202,8 +1202,10 @@ static void stage_launch(dim3 grid, size_t shm, const StageArgs& a, hipStream_t 
         stage_launch_t<MODE, IO, NI, RT, double>(grid, shm, a, s);
 }
 
-// LDS of a 64-row tile above which the stage runs 32-row tiles
+// LDS of a 64-row tile above which the stage runs 32-row tiles, and above
+// which 16-row tiles (the grids of tol 1e-9 and tighter)
 constexpr size_t kStageLdsSplit = 16 * 1024;
+constexpr size_t kStageLdsSplit16 = 45 * 1024;
 
 template <int MODE, int IO>
 static void stage_ni(const StageArgs& a, hipStream_t s)
@@ -1214,7 +1216,7 @@ static void stage_ni(const StageArgs& a, hipStream_t s)
             std::max((size_t)a.Nin * rt * (Tr::xc ? 2 : 1), (size_t)a.Nout * rt * (Tr::yc ? 2 : 1));
         return (size_t)a.Nh * a.Kh * sizeof(double2) + tile * sizeof(double);
     };
-    const int rt = lds(64) > kStageLdsSplit ? 32 : 64;
+    const int rt = lds(64) > kStageLdsSplit16 ? 16 : (lds(64) > kStageLdsSplit ? 32 : 64);
     const size_t shm = lds(rt);
     const int ni = (a.Nh + 256 / rt - 1) / (256 / rt);
     // grid.y (slot, component) stays within 65535: large slot counts go in chunks
@@ -1223,7 +1225,9 @@ static void stage_ni(const StageArgs& a, hipStream_t s)
         StageArgs b = a;
         b.slot0 = s0;
         const dim3 grid(nblocks(a.R, rt), std::min(chunk, a.nslots - s0) * a.ncomp);
-        if (rt == 32) {
+        if (rt == 16) {
+            stage_launch<MODE, IO, 4, 16>(grid, shm, b, s);  // ni <= 3: at most 48 half outputs
+        } else if (rt == 32) {
             if (ni <= 4)
                 stage_launch<MODE, IO, 4, 32>(grid, shm, b, s);
             else
