@@ -35,10 +35,29 @@ def nd_bucket(deg_P: int, deg_Q: int) -> int:
 
 
 def near_flops_per_pair(deg_P: int, deg_Q: int) -> int:
-    """Algorithmic flops of one residual-kernel pair (difference 3, r^2 5,
-    rsqrt 1, s 1, y.f 5, the two scalar coefficients 8, update 12, and a
-    degree-d polynomial 2d each)."""
-    return 35 + 2 * (deg_P + deg_Q)
+    """Algorithmic flops of one residual-kernel pair: 33 for the difference,
+    r^2, s, y.f, the two scalar coefficients and the update, 2 d for each
+    degree-d radial polynomial (Horner, one multiply-add per degree), and the
+    reciprocal square root counted as one."""
+    return 33 + 2 * (deg_P + deg_Q) + 1
+
+
+def near_profile_ms(config: str, precision: str, kernel: str, leaf_size: int, near_lanes: int):
+    """Average duration (ms) of the near-field kernel in the committed
+    rocprofv3 kernel-trace summary of this workload, or None (same conditions
+    as near_traffic)."""
+    rec = _near_profile_record(config, precision, kernel, leaf_size, near_lanes)
+    return None if rec is None or "avg_us" not in rec else rec["avg_us"] * 1e-3
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def near_traffic(config: str, tol: float, precision: str, kernel: str, leaf_size: int, near_lanes: int):
@@ -46,10 +65,17 @@ def near_traffic(config: str, tol: float, precision: str, kernel: str, leaf_size
     rocprofv3 summary of this workload, or None when there is none, it was
     taken with another leaf size or lane split, or the near-field source
     section or the within-leaf reorder changed since the counters were taken."""
+    if abs(tol - workloads_tol(config)) > 0:
+        return None
+    rec = _near_profile_record(config, precision, kernel, leaf_size, near_lanes)
+    return None if rec is None else rec["hbm_bytes_per_launch"]
+
+
+def _near_profile_record(config: str, precision: str, kernel: str, leaf_size: int, near_lanes: int):
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", f"k_near_{config}_{precision}_leaf{leaf_size}_lanes{near_lanes}.md")
-    if not os.path.exists(path) or abs(tol - workloads_tol(config)) > 0:
+    if not os.path.exists(path):
         return None
     m = re.search(r'^\{"kernel".*\}$', open(path).read(), re.M)
     if not m:
@@ -63,7 +89,7 @@ def near_traffic(config: str, tol: float, precision: str, kernel: str, leaf_size
         return None
     if rec.get("leaf_size") != leaf_size or rec.get("near_lanes") != near_lanes:
         return None
-    return rec["hbm_bytes_per_launch"]
+    return rec
 
 
 def workloads_tol(config: str) -> float:
@@ -73,9 +99,10 @@ def workloads_tol(config: str) -> float:
 
 def batched_variant(dev, parity: bool) -> dict:
     """256 independent problems (N log-uniform in [1e3, 1e5], about 5.5e6
-    points): one batched mixed-precision plan + evaluation (autotuned leaf
-    size), against one FP64 plan + evaluation per problem; plus evaluation
-    alone with and without hipGraph replay."""
+    points): one batched plan + evaluation against one plan + evaluation per
+    problem, both in mixed precision and both in FP64, every plan with the same
+    leaf size and lane split (the autotuner's choice for the batch); plus
+    evaluation alone on the batched plan with and without hipGraph replay."""
     import torch
 
     import paper_2509_21471_amd as dmk
@@ -90,41 +117,50 @@ def batched_variant(dev, parity: bool) -> dict:
     out = torch.empty_like(fd)
     tol = 1e-6
     tune = dmk.autotune(xd, tol=tol, precision=dmk.PREC_MIXED, offsets=off)
-    res = {"workload": "batch_256", "n_problems": len(probs), "n": n, "tol": tol, "autotuned": tune}
-
-    def batched_step():
-        p = dmk.Plan(xd, tol=tol, precision=dmk.PREC_MIXED, offsets=off, leaf_size=tune["leaf_size"],
-                     near_lanes=tune["near_lanes"])
-        p.eval(fd, out)
-        return p
-
-    batched_step().close()
-    torch.cuda.synchronize()
-    reps = 3
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        p = batched_step()
-        p.close()
-    torch.cuda.synchronize()
-    ms_b = (time.perf_counter() - t0) * 1e3 / reps
-    u_b = out.cpu().numpy()
-    # one FP64 plan per problem (inputs resident on the device)
+    leaf, lanes = tune["leaf_size"], tune["near_lanes"]
+    res = {"workload": "batch_256", "n_problems": len(probs), "n": n, "tol": tol, "autotuned": tune,
+           "leaf_policy": "every plan (batched and separate) uses the autotuned leaf size and lane split"}
     xs = [xd[off[b]:off[b + 1]] for b in range(len(probs))]
     fs = [fd[off[b]:off[b + 1]] for b in range(len(probs))]
     outs = [torch.empty_like(t) for t in fs]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for b in range(len(probs)):
-        p = dmk.Plan(xs[b], tol=tol)
-        p.eval(fs[b], outs[b])
-        p.close()
-    torch.cuda.synchronize()
-    ms_s = (time.perf_counter() - t0) * 1e3
+
+    def batched_step(prec):
+        p = dmk.Plan(xd, tol=tol, precision=prec, offsets=off, leaf_size=leaf, near_lanes=lanes)
+        p.eval(fd, out)
+        return p
+
+    def separate_steps(prec):
+        for b in range(len(probs)):
+            p = dmk.Plan(xs[b], tol=tol, precision=prec, leaf_size=leaf, near_lanes=lanes)
+            p.eval(fs[b], outs[b])
+            p.close()
+
+    u_b = {}
+    for name, prec in (("mixed", dmk.PREC_MIXED), ("fp64", dmk.PREC_FP64)):
+        batched_step(prec).close()
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            batched_step(prec).close()
+        torch.cuda.synchronize()
+        ms_b = (time.perf_counter() - t0) * 1e3 / reps
+        u_b[name] = out.cpu().numpy()
+        separate_steps(prec)  # warm the buffer cache and tables
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        separate_steps(prec)
+        torch.cuda.synchronize()
+        ms_s = (time.perf_counter() - t0) * 1e3
+        res[name] = {"batched_ms_per_step": ms_b, "batched_targets_per_s": n / (ms_b * 1e-3),
+                     "separate_ms": ms_s, "separate_targets_per_s": n / (ms_s * 1e-3),
+                     "speedup_batched_vs_separate": ms_s / ms_b}
+    res["mixed_over_fp64_batched_step"] = res["mixed"]["batched_ms_per_step"] / res["fp64"]["batched_ms_per_step"]
     # evaluation alone on one batched plan, eager and replayed
     evals = {}
     for graph in (False, True):
-        p = dmk.Plan(xd, tol=tol, precision=dmk.PREC_MIXED, offsets=off, leaf_size=tune["leaf_size"],
-                     near_lanes=tune["near_lanes"], graph=graph)
+        p = dmk.Plan(xd, tol=tol, precision=dmk.PREC_MIXED, offsets=off, leaf_size=leaf, near_lanes=lanes,
+                     graph=graph)
         for _ in range(2):
             p.eval(fd, out)
         torch.cuda.synchronize()
@@ -134,20 +170,21 @@ def batched_variant(dev, parity: bool) -> dict:
         torch.cuda.synchronize()
         evals["graph" if graph else "eager"] = (time.perf_counter() - t0) * 1e3 / 5
         p.close()
-    res.update({"batched_mixed_ms_per_step": ms_b, "batched_targets_per_s": n / (ms_b * 1e-3),
-                "separate_fp64_ms": ms_s, "separate_fp64_targets_per_s": n / (ms_s * 1e-3),
-                "speedup_batched_vs_separate": ms_s / ms_b, "eval_only_ms": evals})
+    res["mixed_eval_only_ms"] = evals
     if parity:
         import oracle
-        errs = []
-        for b in range(0, len(probs), 8):
-            xb, fb = probs[b]
-            idx = workloads.sample_targets(xb.shape[0], 100, 5000 + b)
-            errs.append(oracle.rel_l2(u_b[off[b]:off[b + 1]][idx], oracle.direct(xb, fb, idx)))
-        res["rel_l2_sampled_max"] = max(errs)
+        for name in u_b:
+            errs = []
+            for b in range(0, len(probs), 8):
+                xb, fb = probs[b]
+                idx = workloads.sample_targets(xb.shape[0], 100, 5000 + b)
+                errs.append(oracle.rel_l2(u_b[name][off[b]:off[b + 1]][idx], oracle.direct(xb, fb, idx)))
+            res[name]["rel_l2_sampled_max"] = max(errs)
+        res["mixed"]["rel_l2_vs_fp64"] = oracle.rel_l2(u_b["mixed"], u_b["fp64"])
         res["parity_sample"] = "100 targets in each of 32 problems (every 8th)"
-    print(f"# batched: {ms_b:.1f} ms for {len(probs)} problems (separate FP64 plans {ms_s:.1f} ms)",
-          file=sys.stderr, flush=True)
+    print(f"# batched: mixed {res['mixed']['batched_ms_per_step']:.1f} ms (separate {res['mixed']['separate_ms']:.1f}), "
+          f"fp64 {res['fp64']['batched_ms_per_step']:.1f} ms (separate {res['fp64']['separate_ms']:.1f}) "
+          f"for {len(probs)} problems", file=sys.stderr, flush=True)
     del xd, fd, out
     torch.cuda.empty_cache()
     return res
@@ -168,9 +205,10 @@ def copy_calibration(mib: int):
 
 
 def multi_rhs_variant(args, dev, parity: bool) -> dict:
-    """One plan on 2e6 uniform points with 32 force vectors: evaluation rate in
-    target-vectors per second with the near field batched over 8 vectors, and
-    the same plan with one vector per near-field pass."""
+    """One plan on 2e6 uniform points with 32 force vectors, in mixed
+    precision and in FP64: evaluation rate in target-vectors per second with
+    the near field batched over 8 vectors, and the same plan with one vector
+    per near-field pass."""
     import torch
 
     import paper_2509_21471_amd as dmk
@@ -182,28 +220,98 @@ def multi_rhs_variant(args, dev, parity: bool) -> dict:
     xd = torch.from_numpy(x).to(dev)
     fd = torch.from_numpy(f).to(dev)
     out = torch.empty_like(fd)
-    res = {"workload": name, "n": n, "n_rhs": k, "tol": cfg["tol"], "precision": "fp64"}
-    for batch in (8, 1):
-        plan = dmk.Plan(xd, tol=cfg["tol"], rhs_batch=batch)
-        plan.eval(fd, out)
-        torch.cuda.synchronize()
-        reps = 2
-        t0 = time.perf_counter()
-        for _ in range(reps):
+    res = {"workload": name, "n": n, "n_rhs": k, "tol": cfg["tol"]}
+    idx = workloads.sample_targets(n, 200, cfg["seed"])
+    u_last = {}
+    for pname, prec in (("mixed", dmk.PREC_MIXED), ("fp64", dmk.PREC_FP64)):
+        r = {}
+        for batch in (8, 1):
+            plan = dmk.Plan(xd, tol=cfg["tol"], rhs_batch=batch, precision=prec)
             plan.eval(fd, out)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / reps
-        res[f"rhs_batch_{batch}"] = {"eval_ms": ms, "target_rhs_per_s": n * k / (ms * 1e-3)}
-        plan.close()
-    res["batching_speedup"] = res["rhs_batch_1"]["eval_ms"] / res["rhs_batch_8"]["eval_ms"]
+            torch.cuda.synchronize()
+            reps = 2
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                plan.eval(fd, out)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            r[f"rhs_batch_{batch}"] = {"eval_ms": ms, "target_rhs_per_s": n * k / (ms * 1e-3)}
+            plan.close()
+        r["batching_speedup"] = r["rhs_batch_1"]["eval_ms"] / r["rhs_batch_8"]["eval_ms"]
+        u_last[pname] = out[k - 1].cpu().numpy()
+        res[pname] = r
+    res["mixed_over_fp64_eval"] = res["mixed"]["rhs_batch_8"]["eval_ms"] / res["fp64"]["rhs_batch_8"]["eval_ms"]
     if parity:
         import oracle
-        idx = workloads.sample_targets(n, 200, cfg["seed"])
-        u = out[k - 1].cpu().numpy()
-        res["rel_l2_sampled_last_rhs"] = oracle.rel_l2(u[idx], oracle.direct(x, f[k - 1], idx))
-    print(f"# multi-rhs: {res['rhs_batch_8']['eval_ms']:.1f} ms for {k} vectors "
-          f"(unbatched {res['rhs_batch_1']['eval_ms']:.1f} ms)", file=sys.stderr, flush=True)
+        ref = oracle.direct(x, f[k - 1], idx)
+        for pname in u_last:
+            res[pname]["rel_l2_sampled_last_rhs"] = oracle.rel_l2(u_last[pname][idx], ref)
+        res["mixed"]["rel_l2_vs_fp64_last_rhs"] = oracle.rel_l2(u_last["mixed"], u_last["fp64"])
+        res["parity_sample"] = f"{idx.size} targets of the last vector"
+    print(f"# multi-rhs: mixed {res['mixed']['rhs_batch_8']['eval_ms']:.1f} ms, fp64 "
+          f"{res['fp64']['rhs_batch_8']['eval_ms']:.1f} ms for {k} vectors (unbatched fp64 "
+          f"{res['fp64']['rhs_batch_1']['eval_ms']:.1f} ms)", file=sys.stderr, flush=True)
     del fd, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def clusters_4e6_variant(args, dev, parity: bool) -> dict:
+    """4e6 clustered points (sigma 0.01) at 1e-6: plan + eval steps and
+    evaluation alone in FP64 and in mixed precision, with errors against the
+    stored direct sums at 10,000 sampled targets and mixed against FP64."""
+    import torch
+
+    import paper_2509_21471_amd as dmk
+    import workloads
+    name = "clusters_4e6"
+    cfg = workloads.CONFIGS[name]
+    x, f = workloads.config(name)
+    n = x.shape[0]
+    xd = torch.from_numpy(x).to(dev)
+    fd = torch.from_numpy(f).to(dev)
+    out = torch.empty_like(fd)
+    steps = max(2, min(args.steps, 5))
+    res = {"workload": name, "n": n, "tol": cfg["tol"], "steps": steps}
+    u = {}
+    for pname, prec in (("fp64", dmk.PREC_FP64), ("mixed", dmk.PREC_MIXED)):
+        def plan():
+            return dmk.Plan(xd, tol=cfg["tol"], precision=prec, timing=True)
+        p = plan()
+        p.eval(fd, out)
+        torch.cuda.synchronize()
+        p.close()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            p = plan()
+            p.eval(fd, out)
+            torch.cuda.synchronize()
+            if i < steps - 1:
+                p.close()
+        step_ms = (time.perf_counter() - t0) * 1e3 / steps
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            p.eval(fd, out)
+        torch.cuda.synchronize()
+        eval_ms = (time.perf_counter() - t0) * 1e3 / steps
+        info = p.info()
+        res[pname] = {"ms_per_step": step_ms, "targets_per_s": n / (step_ms * 1e-3), "eval_only_ms": eval_ms,
+                      "eval_only_targets_per_s": n / (eval_ms * 1e-3), "levels": info["levels"],
+                      "leaf_size": info["leaf_size"], "phases_ms": p.phase_ms()}
+        u[pname] = out.cpu().numpy()
+        p.close()
+    res["mixed_speedup_step"] = res["fp64"]["ms_per_step"] / res["mixed"]["ms_per_step"]
+    res["mixed_speedup_eval"] = res["fp64"]["eval_only_ms"] / res["mixed"]["eval_only_ms"]
+    if parity:
+        import oracle
+        g = np.load(os.path.join(ROOT, "tests", "golden", "clusters_4e6_direct.npz"))
+        for pname in u:
+            res[pname]["rel_l2_sampled"] = oracle.rel_l2(u[pname][g["idx"]], g["u"])
+        res["mixed"]["rel_l2_vs_fp64"] = oracle.rel_l2(u["mixed"], u["fp64"])
+        res["parity_sample"] = f"{g['idx'].size} stored direct-sum targets"
+    print(f"# clusters_4e6: fp64 {res['fp64']['ms_per_step']:.1f} ms/step, mixed {res['mixed']['ms_per_step']:.1f} "
+          f"ms/step", file=sys.stderr, flush=True)
+    del xd, fd, out
     torch.cuda.empty_cache()
     return res
 
@@ -297,7 +405,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes three times (the "
                          "reference kernel for scaling HBM byte counters) and exit")
-    ap.add_argument("--only", choices=["spectral_ewald", "multi_rhs", "batched"], default=None,
+    ap.add_argument("--only", choices=["spectral_ewald", "multi_rhs", "batched", "clusters_4e6"], default=None,
                     help="run only this variant and print its JSON record (for profiling; not the benchmark line)")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -308,7 +416,8 @@ def main():
         dev = torch.device("cuda:0")
         fn = {"spectral_ewald": lambda: ewald_variant(args, dev, not args.no_parity),
               "multi_rhs": lambda: multi_rhs_variant(args, dev, not args.no_parity),
-              "batched": lambda: batched_variant(dev, not args.no_parity)}[args.only]
+              "batched": lambda: batched_variant(dev, not args.no_parity),
+              "clusters_4e6": lambda: clusters_4e6_variant(args, dev, not args.no_parity)}[args.only]
         print(json.dumps({"variant": args.only, **fn()}), flush=True)
         return
 
@@ -534,6 +643,7 @@ def main():
         result["variants"] = {"mixed": mixed, "gaussian_window": gaussian,
                               "multi_rhs": multi_rhs_variant(args, dev, not args.no_parity),
                               "batched": batched_variant(dev, not args.no_parity),
+                              "clusters_4e6": clusters_4e6_variant(args, dev, not args.no_parity),
                               "spectral_ewald": ewald_variant(args, dev, not args.no_parity)}
         if stress is not None:
             result["variants"]["stresslet"] = stress
@@ -563,13 +673,23 @@ def main():
     if not args.no_cpu_baseline and not periodic:
         import oracle
         idx = workloads.sample_targets(n, args.cpu_sample, cfg["seed"] + 1)
+        cores = oracle.num_threads()
         tc0 = time.perf_counter()
         oracle.direct(x, f, idx)
         tc = time.perf_counter() - tc0
-        result["cpu_baseline"] = {"value": idx.size / tc, "unit": "targets/s", "cores": oracle.num_threads(),
-                                  "kind": "oracle",
+        # the same sum on one core, over the first sixteenth of the sample
+        idx1 = idx[:max(1, idx.size // 16)]
+        oracle.set_num_threads(1)
+        t10 = time.perf_counter()
+        oracle.direct(x, f, idx1)
+        t1 = time.perf_counter() - t10
+        oracle.set_num_threads(cores)
+        result["cpu_baseline"] = {"value": idx.size / tc, "unit": "targets/s", "cores": cores,
+                                  "kind": "oracle", "cpu_model": cpu_model(),
+                                  "value_1_core": idx1.size / t1,
                                   "sample": f"{idx.size} seeded targets of the {n}-point input, each summing "
-                                            f"all {n} sources (direct O(N^2) FP64 sum), {tc:.1f} s"}
+                                            f"all {n} sources (direct O(N^2) FP64 sum), {tc:.1f} s on {cores} "
+                                            f"threads; {idx1.size} of them on 1 thread, {t1:.1f} s"}
     print(json.dumps(result), flush=True)
 
 

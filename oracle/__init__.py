@@ -13,9 +13,10 @@ direct.c     compiled to ``liboracle.so`` (OpenMP): direct free-space Stokeslet
              and stresslet sums and the real-space half of the Gaussian Ewald sum.
 ewald.py     periodic sum: Fourier half (structure factor by numpy matmul),
              self term, real half via the C routine.
-splitting.py PSWF window (scipy's prolate angular function), phi, Phi, the
-             biharmonic mollifier, residual / mollified Stokeslets and a brute
-             force residual pair sum.
+splitting.py PSWF window (Chebyshev collocation of the prolate differential
+             operator, lowest eigenfunction), phi, Phi, the biharmonic
+             mollifier, residual / mollified Stokeslets and a brute force
+             residual pair sum.
 """
 from __future__ import annotations
 
@@ -62,6 +63,8 @@ def lib():
         L.oracle_stresslet_ewald_real.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -76,6 +79,11 @@ def _ip(a):
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(nt: int) -> None:
+    """Threads of later oracle calls (timing only: results do not depend on it)."""
+    lib().oracle_set_num_threads(int(nt))
 
 
 def direct(x, f, targets=None):

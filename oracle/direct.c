@@ -233,3 +233,15 @@ int oracle_num_threads(void)
     }
     return nt;
 }
+
+/* Sets the number of OpenMP threads later oracle calls use (timing only; the
+ * per-target sums do not depend on it). */
+void oracle_set_num_threads(int nt)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(nt > 0 ? nt : 1);
+#else
+    (void)nt;
+#endif
+}

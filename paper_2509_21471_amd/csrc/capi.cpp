@@ -49,6 +49,15 @@ bool is_device_ptr(const void* p)
     return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
+// Newton step on the Stokeslet near field's reciprocal square root: the
+// unrefined hardware estimate (relative error below 6e-8) is used where the
+// row's tolerance is 1e-6 or looser (and the fits are the shortest compiled
+// length); the stresslet (1/r^5) always refines.
+bool stokes_near_refine(double row_tol)
+{
+    return !(row_tol >= 1e-6 * (1 - 1e-9));
+}
+
 // Process-wide cache of device buffers: destroyed plans hand their buffers
 // back and later plans reuse any cached block of at least the requested size
 // (and at most twice it).  Sizes are rounded to 2 MiB above 1 MiB.
@@ -1552,9 +1561,7 @@ int create_plan(const double* points, const std::vector<int64_t>& offsets, int d
     if (opts)
         dmk::override_params(&P->prm, opts->q, opts->p);
     P->tab = dmk::get_tables(P->prm);
-    // the unrefined hardware estimate (relative error below 6e-8) leaves the
-    // Stokeslet near field well inside tolerances of 1e-6 and above
-    P->near_refine = !(P->prm.kernel == DMK_KERNEL_STOKESLET && P->prm.tol >= 1e-6 * (1 - 1e-9));
+    P->near_refine = P->prm.kernel != DMK_KERNEL_STOKESLET || stokes_near_refine(P->prm.tol);
     if (opts) {
         P->stream = (hipStream_t)opts->stream;
         P->precision = opts->precision;
@@ -2131,8 +2138,14 @@ int dmk_stokes_host_tree(const double* points, int64_t n, int leaf_size, int per
     return DMK_OK;
 }
 
-int dmk_stokes_residual_sum(const double* targets, int64_t m, const double* sources, const double* forces,
-                            int64_t ns, double r_lambda, double tol, void* stream, double* out)
+}  // extern "C"
+
+namespace {
+
+// Argument checks shared by the residual-sum entry points; *T receives the
+// tolerance's tables.
+int residual_sum_check(const double* targets, int64_t m, const double* sources, const double* forces, int64_t ns,
+                       double r_lambda, double tol, const double* out, const dmk::Tables** T)
 {
     if (m < 0 || ns < 0 || !(r_lambda > 0))
         return fail(DMK_ERR_ARG, "bad sizes or r_lambda");
@@ -2140,23 +2153,22 @@ int dmk_stokes_residual_sum(const double* targets, int64_t m, const double* sour
         return DMK_OK;
     if (!is_device_ptr(targets) || !is_device_ptr(out) || (ns > 0 && (!is_device_ptr(sources) || !is_device_ptr(forces))))
         return fail(DMK_ERR_ARG, "arrays must be device pointers");
-    const dmk::Tables* T = dmk::get_tables(tol);
-    if (!T)
+    *T = dmk::get_tables(tol);
+    if (!*T)
         return fail(DMK_ERR_TOL, "tol must lie in [1e-12, 1e-3]");
-    hipStream_t st = (hipStream_t)stream;
-    DevMem mem;
-    double* tx = mem.alloc<double>(3 * m);
-    double* sx = mem.alloc<double>(3 * std::max<int64_t>(ns, 1));
-    double* sf = mem.alloc<double>(3 * std::max<int64_t>(ns, 1));
-    if (mem.oom)
-        return fail(DMK_ERR_OOM, "device allocation failed");
+    return DMK_OK;
+}
+
+// Copies targets, sources and forces to SoA staging (tx: 3m, sx, sf: 3ns
+// doubles each) and launches the brute-force residual kernel, all on st.
+int residual_sum_enqueue(const double* targets, int64_t m, const double* sources, const double* forces, int64_t ns,
+                         double r_lambda, const dmk::Tables& T, hipStream_t st, double* tx, double* sx, double* sf,
+                         double* out)
+{
     // (k,3) row-major -> SoA by strided 2D copies
-    HIPCHK(hipMemcpy2DAsync(tx, sizeof(double), targets, 3 * sizeof(double), sizeof(double), m,
-                            hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpy2DAsync(tx + m, sizeof(double), targets + 1, 3 * sizeof(double), sizeof(double), m,
-                            hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpy2DAsync(tx + 2 * m, sizeof(double), targets + 2, 3 * sizeof(double), sizeof(double), m,
-                            hipMemcpyDeviceToDevice, st));
+    for (int d = 0; d < 3; ++d)
+        HIPCHK(hipMemcpy2DAsync(tx + d * m, sizeof(double), targets + d, 3 * sizeof(double), sizeof(double), m,
+                                hipMemcpyDeviceToDevice, st));
     for (int d = 0; d < 3 && ns > 0; ++d) {
         HIPCHK(hipMemcpy2DAsync(sx + d * ns, sizeof(double), sources + d, 3 * sizeof(double), sizeof(double), ns,
                                 hipMemcpyDeviceToDevice, st));
@@ -2164,11 +2176,35 @@ int dmk_stokes_residual_sum(const double* targets, int64_t m, const double* sour
                                 hipMemcpyDeviceToDevice, st));
     }
     dmk::RadialPoly poly;
-    if (!make_poly(*T, &poly))
+    if (!make_poly(T, &poly))
         return fail(DMK_ERR_UNSUPPORTED, "radial fit degree too high");
-    dmk::launch_residual_direct(tx, tx + m, tx + 2 * m, m, sx, sx + ns, sx + 2 * ns, sf, ns, r_lambda, poly, out,
-                                st);
+    dmk::launch_residual_direct(tx, tx + m, tx + 2 * m, m, sx, sx + ns, sx + 2 * ns, sf, ns, r_lambda,
+                                stokes_near_refine(T.prm.tol), poly, out, st);
     HIPCHK(hipGetLastError());
+    return DMK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dmk_stokes_residual_sum(const double* targets, int64_t m, const double* sources, const double* forces,
+                            int64_t ns, double r_lambda, double tol, void* stream, double* out)
+{
+    const dmk::Tables* T = nullptr;
+    const int chk = residual_sum_check(targets, m, sources, forces, ns, r_lambda, tol, out, &T);
+    if (chk != DMK_OK || m == 0)
+        return chk;
+    hipStream_t st = (hipStream_t)stream;
+    DevMem mem;
+    double* tx = mem.alloc<double>(3 * m);
+    double* sx = mem.alloc<double>(3 * std::max<int64_t>(ns, 1));
+    double* sf = mem.alloc<double>(3 * std::max<int64_t>(ns, 1));
+    if (mem.oom)
+        return fail(DMK_ERR_OOM, "device allocation failed");
+    const int rc = residual_sum_enqueue(targets, m, sources, forces, ns, r_lambda, *T, st, tx, sx, sf, out);
+    if (rc != DMK_OK)
+        return rc;
     HIPCHK(hipStreamSynchronize(st));  // temporaries are freed on return
     return DMK_OK;
 }

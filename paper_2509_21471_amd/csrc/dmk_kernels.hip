@@ -1602,31 +1602,6 @@ __device__ inline double horner_v(const double* __restrict__ m, double top, doub
     return p;
 }
 
-template <int ND>
-__device__ inline void residual_pair(double dx, double dy, double dz, double fx, double fy, double fz, double rl2,
-                                     double tw, double cP, double cQ, const RadialPoly& poly, double& u0,
-                                     double& u1, double& u2)
-{
-    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    if (r2 < rl2) {
-        // r = 0 (the self pair, or distinct coincident points): only the
-        // smooth part -S_M(0) f = -(P(0)/(4 pi r_lambda)) f remains, which
-        // cancels the far field's S_M(0) f, so such a pair contributes nothing
-        // to the total and the self term of eq. S_self needs no separate pass.
-        const double rinv = r2 > 0.0 ? rsqrt_f64(r2) : 0.0;
-        const double t = fma(r2, tw, -1.0);
-        const double P = horner<ND>(poly.P, t);
-        const double Q = horner<ND>(poly.Q, t);
-        const double dot = fma(dx, fx, fma(dy, fy, dz * fz));
-        const double cr = kInv8Pi * rinv;
-        const double a = fma(-cP, P, cr);
-        const double b = dot * fma(-cQ, Q, cr * rinv * rinv);
-        u0 = fma(a, fx, fma(b, dx, u0));
-        u1 = fma(a, fy, fma(b, dy, u1));
-        u2 = fma(a, fz, fma(b, dz, u2));
-    }
-}
-
 // The same pair for NR force vectors: the geometry, the square root and both
 // radial polynomials are shared, only the projections onto the forces repeat.
 // v holds the source as (x, y, z, f_0, ..., f_{NR-1}) (already shifted) with
@@ -2009,7 +1984,12 @@ void launch_near_count(int sg, const NearWork* work, int nwork, const NearLeaf* 
                            x, y, z, out);
 }
 
-template <int ND>
+// Brute-force residual sums over all sources with the near field's own pair
+// routine and source staging: forces scaled by 1/(8 pi) as they are read, the
+// leading radial coefficients in vector registers, c2 = 2 / r_l and
+// c3 = 2 / r_l^3 (powers of two when r_l is), and the same choice RF of the
+// reciprocal square root as the near field of a plan at this tolerance.
+template <int ND, bool RF>
 __global__ __launch_bounds__(64) void k_residual_direct(const double* __restrict__ tx, const double* __restrict__ ty,
                                                         const double* __restrict__ tz, int64_t m,
                                                         const double* __restrict__ sx, const double* __restrict__ sy,
@@ -2019,16 +1999,19 @@ __global__ __launch_bounds__(64) void k_residual_direct(const double* __restrict
     const int64_t i = blockIdx.x * (int64_t)64 + threadIdx.x;
     const bool valid = i < m;
     const double xt = valid ? tx[i] : 0.0, yt = valid ? ty[i] : 0.0, zt = valid ? tz[i] : 0.0;
-    const double rl2 = rl * rl, inv_rl2 = 1.0 / rl2;
-    const double cP = 1.0 / (4.0 * kPi * rl), cQ = cP * inv_rl2;
-    double u0 = 0, u1 = 0, u2 = 0;
-    for (int64_t j = 0; j < ns; ++j)
-        residual_pair<ND>(xt - sx[j], yt - sy[j], zt - sz[j], sf[j], sf[ns + j], sf[2 * ns + j], rl2, 2.0 * inv_rl2,
-                          cP, cQ, poly, u0, u1, u2);
+    const double rl2 = rl * rl, tw = 2.0 / rl2;
+    const double c2 = 2.0 / rl, c3 = c2 / rl2;
+    double pt = poly.P[ND - 1], qt = poly.Q[ND - 1];
+    asm volatile("" : "+v"(pt), "+v"(qt));
+    double acc[1][3] = {{0, 0, 0}};
+    for (int64_t j = 0; j < ns; ++j) {
+        const double v[6] = {sx[j], sy[j], sz[j], sf[j] * kInv8Pi, sf[ns + j] * kInv8Pi, sf[2 * ns + j] * kInv8Pi};
+        residual_pair_multi<ND, 1, RF>(xt, yt, zt, v, rl2, tw, c2, c3, pt, qt, poly, acc);
+    }
     if (valid) {
-        u[3 * i] = u0;
-        u[3 * i + 1] = u1;
-        u[3 * i + 2] = u2;
+        u[3 * i] = acc[0][0];
+        u[3 * i + 1] = acc[0][1];
+        u[3 * i + 2] = acc[0][2];
     }
 }
 
@@ -2078,15 +2061,23 @@ void launch_residual_direct_t(const double* tx, const double* ty, const double* 
 
 void launch_residual_direct(const double* tx, const double* ty, const double* tz, int64_t m, const double* sx,
                             const double* sy, const double* sz, const double* sf, int64_t ns, double r_lambda,
-                            const RadialPoly& poly, double* u, hipStream_t s)
+                            bool refine, const RadialPoly& poly, double* u, hipStream_t s)
 {
     if (m == 0)
         return;
-#define L_RES(ND)                                                                                               \
-    hipLaunchKernelGGL(k_residual_direct<ND>, dim3(nblocks(m, 64)), dim3(64), 0, s, tx, ty, tz, m, sx, sy, sz, sf, \
-                       ns, r_lambda, poly, u)
+#define L_RES_RF(ND, RF)                                                                                      \
+    hipLaunchKernelGGL((k_residual_direct<ND, RF>), dim3(nblocks(m, 64)), dim3(64), 0, s, tx, ty, tz, m, sx, sy, \
+                       sz, sf, ns, r_lambda, poly, u)
+    // the same rule as launch_near: the unrefined estimate only with the shortest fits
+#define L_RES(ND)                    \
+    if (ND == 14 && !refine) {       \
+        L_RES_RF(14, false);         \
+    } else {                         \
+        L_RES_RF(ND, true);          \
+    }
     DMK_ND_DISPATCH(poly.nd, L_RES)
 #undef L_RES
+#undef L_RES_RF
 }
 
 // ---- finishing --------------------------------------------------------------------

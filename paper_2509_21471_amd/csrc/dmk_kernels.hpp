@@ -185,10 +185,11 @@ void launch_near_count(int sg, const NearWork* work, int nwork, const NearLeaf* 
                        const double* cbbox, const double* x, const double* y, const double* z,
                        unsigned long long* out, hipStream_t s);
 
-// brute-force residual sum over all source points (stage entry point)
+// brute-force residual sum over all source points (stage entry point), with
+// the near field's pair routine; refine: Newton step on 1/r as in launch_near
 void launch_residual_direct(const double* tx, const double* ty, const double* tz, int64_t m, const double* sx,
                             const double* sy, const double* sz, const double* sf, int64_t ns, double r_lambda,
-                            const RadialPoly& poly, double* u, hipStream_t s);
+                            bool refine, const RadialPoly& poly, double* u, hipStream_t s);
 // the same for the residual stresslet, sf = (f, n) as [6][ns]
 void launch_residual_direct_t(const double* tx, const double* ty, const double* tz, int64_t m, const double* sx,
                               const double* sy, const double* sz, const double* sf, int64_t ns, double r_lambda,

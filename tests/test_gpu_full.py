@@ -93,6 +93,24 @@ def test_multiple_rhs_match_single(dev, n_rhs, batch):
     assert oracle.rel_l2(u[n_rhs - 1], oracle.direct(x, f[n_rhs - 1])) < 1e-6
 
 
+@pytest.mark.parametrize("n_rhs,batch", [(4, 0), (11, 0), (5, 2)])
+def test_multiple_rhs_mixed_precision(dev, n_rhs, batch):
+    """Mixed precision with several force vectors per call: each vector within
+    1e-6 of the direct sum, and bit for bit equal to one mixed call per vector
+    (the near field's batches visit the sources in the same order)."""
+    dmk = _dmk()
+    x, f = workloads.make("clusters", 20000, seed=79, sigma=0.05, n_rhs=n_rhs)
+    plan = dmk.Plan(_t(x), tol=1e-6, leaf_size=200, rhs_batch=batch, precision=dmk.PREC_MIXED)
+    u = plan.eval(_t(f)).cpu().numpy()
+    for r in range(n_rhs):
+        ur = plan.eval(_t(f[r])).cpu().numpy()
+        assert np.array_equal(u[r], ur), r
+    plan.close()
+    for r in range(n_rhs):
+        err = oracle.rel_l2(u[r], oracle.direct(x, f[r]))
+        assert err < 1e-6, (r, err)
+
+
 def test_periodic_translation_invariance(dev):
     """A shift of all points modulo the cell changes the tree, not the sum."""
     x, f = workloads.make("periodic", 20000, seed=75)
