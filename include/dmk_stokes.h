@@ -405,6 +405,25 @@ int dmk_stokes_residual_sum(const double* targets, int64_t m, const double* sour
                             int64_t ns, double r_lambda, double tol, void* stream, double* out);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * sums as dmk_stokes_residual_sum, with the same kernel, on the same
+ * arguments, bit for bit, but the SoA staging of targets, sources and forces
+ * lives in a fixed device workspace of 2^21 doubles (16 MiB) that the library
+ * holds on each GPU it runs on until the process ends.  No device memory is
+ * allocated or freed and the call does not synchronise: it enqueues copies
+ * into the workspace and the kernel on `stream` and returns.
+ *   3 m + 6 ns must not exceed 2^21 (e.g. m = ns = 233016); larger sizes
+ *   return DMK_ERR_ARG (dmk_stokes_residual_sum has no such limit).
+ * Every call on one GPU uses that GPU's single workspace: calls that may
+ * overlap on one GPU (different streams, or host threads) race and must be
+ * serialised by the caller.  The workspace keeps the last call's staged
+ * values; nothing in it needs to start at zero.
+ */
+int dmk_stokes_residual_sum_noalloc(const double* targets, int64_t m, const double* sources, const double* forces,
+                                    int64_t ns, double r_lambda, double tol, void* stream, double* out);
+
+/*
  * The same for the residual stresslet (eq. res_stresslet with eq. T-offd, at
  * scale r_lambda), with the near-field pair routine of the stresslet plans:
  *   out[i] = sum_a T_R^{r_lambda}(t_i - s_a) : (f_a n_a^T);

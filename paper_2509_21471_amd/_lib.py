@@ -25,6 +25,7 @@ SYMBOLS = ["dmk_stokes_ewald_params", "dmk_stokes_radial_stresslet", "dmk_stokes
            "dmk_stokes_residual_sum_stresslet", "dmk_stokes_plan", "dmk_stokes_plan_ex", "dmk_stokes_plan_batch", "dmk_stokes_plan_targets", "dmk_stokes_autotune", "dmk_stokes_eval", "dmk_stokes_plan_info",
            "dmk_stokes_tree_leaves", "dmk_stokes_destroy", "dmk_last_error", "dmk_stokes_params",
            "dmk_stokes_radial", "dmk_stokes_mollifier", "dmk_stokes_residual_sum", "dmk_stokes_phase_ms",
+           "dmk_stokes_residual_sum_noalloc",
            "dmk_stokes_near_stats", "dmk_stokes_release_cached_memory", "dmk_stokes_host_tree"]
 PHASES = ["anterp", "merge", "outgoing", "translate", "incoming", "root", "interp", "leaf_eval", "near",
           "finalize"]
@@ -108,6 +109,8 @@ def lib():
         L.dmk_stokes_radial_stresslet.argtypes = [ctypes.c_double, dp, i64, dp]
         L.dmk_stokes_ewald_params.argtypes = [ctypes.c_double, i64, ctypes.c_int, ctypes.POINTER(PlanInfo)]
         L.dmk_stokes_residual_sum.argtypes = [vp, i64, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp]
+        L.dmk_stokes_residual_sum_noalloc.argtypes = [vp, i64, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp,
+                                                      vp]
         L.dmk_stokes_residual_sum_stresslet.argtypes = [vp, i64, vp, vp, vp, i64, ctypes.c_double,
                                                         ctypes.c_double, vp, vp]
         L.dmk_stokes_phase_ms.argtypes = [vp, dp]
@@ -359,6 +362,20 @@ def residual_sum(targets, sources, forces, r_lambda: float, tol: float, stream=N
                                          ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(f.data_ptr()),
                                          int(s.shape[0]), float(r_lambda), float(tol), _stream_ptr(stream),
                                          ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def residual_sum_noalloc(targets, sources, forces, r_lambda: float, tol: float, out, stream=None):
+    """dmk_stokes_residual_sum_noalloc: the library allocates nothing; `out`
+    (m, 3) float64 on the device is caller-provided.  Stream-ordered, no
+    synchronisation."""
+    t = _dev_f64(targets)
+    s = _dev_f64(sources)
+    f = _dev_f64(forces)
+    _check(lib().dmk_stokes_residual_sum_noalloc(ctypes.c_void_p(t.data_ptr()), int(t.shape[0]),
+                                                 ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                                                 int(s.shape[0]), float(r_lambda), float(tol), _stream_ptr(stream),
+                                                 ctypes.c_void_p(out.data_ptr())))
     return out
 
 

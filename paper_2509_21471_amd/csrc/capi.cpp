@@ -2209,6 +2209,25 @@ int dmk_stokes_residual_sum(const double* targets, int64_t m, const double* sour
     return DMK_OK;
 }
 
+int dmk_stokes_residual_sum_noalloc(const double* targets, int64_t m, const double* sources, const double* forces,
+                                    int64_t ns, double r_lambda, double tol, void* stream, double* out)
+{
+    const dmk::Tables* T = nullptr;
+    const int chk = residual_sum_check(targets, m, sources, forces, ns, r_lambda, tol, out, &T);
+    if (chk != DMK_OK || m == 0)
+        return chk;
+    const size_t cap = dmk::scratch_doubles();
+    if ((size_t)m > cap / 3 || (size_t)ns > cap / 6 || 3 * (size_t)m + 6 * (size_t)ns > cap)
+        return fail(DMK_ERR_ARG, "3 m + 6 ns exceeds the fixed workspace of " + std::to_string(cap) +
+                                     " doubles (dmk_stokes_residual_sum has no such limit)");
+    double* base = nullptr;
+    HIPCHK(dmk::scratch_address(&base));
+    double* tx = base;
+    double* sx = base + 3 * m;
+    double* sf = sx + 3 * ns;
+    return residual_sum_enqueue(targets, m, sources, forces, ns, r_lambda, *T, (hipStream_t)stream, tx, sx, sf, out);
+}
+
 int dmk_stokes_residual_sum_stresslet(const double* targets, int64_t m, const double* sources, const double* forces,
                                       const double* normals, int64_t ns, double r_lambda, double tol, void* stream,
                                       double* out)

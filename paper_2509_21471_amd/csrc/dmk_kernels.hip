@@ -4,6 +4,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <mutex>
 
 namespace dmk {
 
@@ -2218,6 +2219,44 @@ void launch_zero(void* p, size_t bytes, hipStream_t s)
         return;
     const unsigned nb = (unsigned)std::min<size_t>((count + 255) / 256, 8192);
     hipLaunchKernelGGL(k_zero, dim3(nb), dim3(256), 0, s, (uint32_t*)p, count);
+}
+
+// ---- fixed device workspace ---------------------------------------------------------
+// Staging of the entry point for callers that cannot allocate
+// (dmk_stokes_residual_sum_noalloc): targets, sources and forces as SoA, at
+// most kScratchDoubles values.  Every GPU holds its own copy until the process
+// ends; calls on one GPU share it.
+constexpr size_t kScratchDoubles = (size_t)1 << 21;  // 16 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+size_t scratch_doubles()
+{
+    return kScratchDoubles;
+}
+
+hipError_t scratch_address(double** out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        // the array's name in host code is only a stand-in for the symbol;
+        // its device address on the current GPU comes from the runtime
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        addr[dev] = static_cast<double*>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace dmk

@@ -212,4 +212,9 @@ void launch_finalize(const double* u, int64_t n, const int* perm, int64_t tofs, 
 // zero `bytes` (a multiple of 4) at p
 void launch_zero(void* p, size_t bytes, hipStream_t s);
 
+// Fixed device workspace (no allocation): its size in doubles, and its device
+// address on the current GPU (looked up once per device).
+size_t scratch_doubles();
+hipError_t scratch_address(double** out);
+
 }  // namespace dmk

@@ -34,6 +34,14 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(_dmk().SYMBOLS)
 
 
+def test_binding_declares_every_signature():
+    """The ctypes binding gives every exported entry point its argument types
+    (without them ctypes cannot pass doubles and 64-bit sizes)."""
+    lib = _dmk().lib()
+    for n in _dmk().SYMBOLS:
+        assert getattr(lib, n).argtypes is not None, n
+
+
 @pytest.mark.parametrize("tol,q,p,n1,nper,ns", [(1e-3, 10, 12, 19, 3, 600), (1e-6, 17, 23, 33, 5, 1200),
                                                  (1e-9, 25, 33, 49, 9, 2000), (1e-12, 31, 44, 61, 11, 3000)])
 def test_parameters_follow_table(tol, q, p, n1, nper, ns):
