@@ -56,10 +56,14 @@ typedef enum {
 
 /* FP64: every buffer and operation in double precision.
  * MIXED: the far-field buffers (proxy charges and potentials, plane-wave
- * expansions, stage intermediates) are stored as float, halving their memory
- * and traffic; all arithmetic, the near field, the tree geometry and the
- * accumulation at the points stay FP64.  Relative errors gain about 1.2e-7, so
- * MIXED needs tol >= 1e-6. */
+ * expansions, stage intermediates, the points' Lagrange values) are stored as
+ * float, halving their memory and traffic, and the two point <-> proxy-grid
+ * contractions run on FP32 matrix cores: the proxy charges (Step 2a) with FP32
+ * products summed in blocks of 64 points into FP64 sums, the far field at the
+ * points with the contraction over one grid axis in FP32 and the rest in FP64.
+ * The near field (whose radial polynomials are evaluated in FP64), the tree
+ * geometry and the accumulation at the points stay FP64.  Relative errors
+ * gain about 2e-7, so MIXED needs tol >= 1e-6. */
 typedef enum { DMK_PREC_FP64 = 0, DMK_PREC_MIXED = 1 } dmk_precision;
 
 /* Window of the kernel split (eqs. wfunchat_prol_G / wfunc_prol_G):

@@ -239,7 +239,7 @@ struct dmk_plan_s {
     std::vector<int> box_fid;         // box id -> fid or -1
     dmk::LeafDesc* leaves = nullptr;  // non-empty leaves
     int nleaf = 0;
-    double* Ltab = nullptr;           // Lagrange values of the points on their leaf grids
+    void* Ltab = nullptr;             // Lagrange values of the points on their leaf grids (float when f32)
     dmk::EvalChunk* echunks = nullptr;
     int n_echunk = 0;
     struct LevelLists {
@@ -930,7 +930,10 @@ int build_plan(dmk_plan_t P, const double* points)
     }
     P->n_echunk = (int)ech.size();
     P->echunks = P->mem.alloc<EvalChunk>(ech.size());
-    P->Ltab = P->mem.alloc<double>((size_t)n * 3 * lagrange_pad(P->prm.p));
+    if (P->f32)
+        P->Ltab = P->mem.alloc<float>((size_t)n * 3 * lagrange_pad(P->prm.p));
+    else
+        P->Ltab = P->mem.alloc<double>((size_t)n * 3 * lagrange_pad(P->prm.p));
     // per-level parent lists (non-empty, non-leaf)
     P->lev.assign(T.max_level + 1, {});
     // host sources of the stream-ordered uploads stay alive until the final sync
@@ -1148,7 +1151,8 @@ int build_plan(dmk_plan_t P, const double* points)
     HIPCHK(upload(P->wdiff, wd, st));
     HIPCHK(upload(P->wroot, wr, st));
     launch_chunk_bbox(P->x, P->y, P->z, d_cstart, d_clen, (int)cstart.size(), P->cbbox, st);
-    launch_lagrange_table(P->prm.p, P->leaves, P->nleaf, P->x, P->y, P->z, P->cheb_t, P->cheb_w, P->Ltab, st);
+    launch_lagrange_table(P->prm.p, P->leaves, P->nleaf, P->x, P->y, P->z, P->cheb_t, P->cheb_w, P->Ltab, P->f32,
+                          st);
     // radial polynomials
     if (!make_poly(TB, &P->poly))
         return fail(DMK_ERR_UNSUPPORTED, "radial fit degree too high");

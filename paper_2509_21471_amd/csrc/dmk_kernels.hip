@@ -539,11 +539,11 @@ struct MCfg {
     static constexpr int RS = PA + 1;            // LDS row stride (odd: conflict-free column reads)
 };
 
-template <int P>
+template <int P, typename LT>
 __global__ __launch_bounds__(256) void k_lagrange_table(const LeafDesc* __restrict__ leaves,
                                                         const double* __restrict__ x, const double* __restrict__ y,
                                                         const double* __restrict__ z, const double* __restrict__ ct,
-                                                        const double* __restrict__ cw, double* __restrict__ Ltab)
+                                                        const double* __restrict__ cw, LT* __restrict__ Ltab)
 {
     constexpr int PA = MCfg<P>::PA;
     const LeafDesc L = leaves[blockIdx.x];
@@ -557,11 +557,19 @@ __global__ __launch_bounds__(256) void k_lagrange_table(const LeafDesc* __restri
 #pragma unroll
             for (int a = P; a < PA; ++a)
                 Lv[a] = 0.0;
-            // PA is a multiple of 4, so each row is 32-byte aligned: 16-byte stores
-            double2* o = reinterpret_cast<double2*>(Ltab + ((size_t)i * 3 + d) * PA);
+            // PA is a multiple of 4, so each row is 16-byte aligned: 16-byte stores
+            if constexpr (sizeof(LT) == 8) {
+                double2* o = reinterpret_cast<double2*>(Ltab + ((size_t)i * 3 + d) * PA);
 #pragma unroll
-            for (int a = 0; a < PA / 2; ++a)
-                o[a] = make_double2(Lv[2 * a], Lv[2 * a + 1]);
+                for (int a = 0; a < PA / 2; ++a)
+                    o[a] = make_double2(Lv[2 * a], Lv[2 * a + 1]);
+            } else {
+                float4* o = reinterpret_cast<float4*>(Ltab + ((size_t)i * 3 + d) * PA);
+#pragma unroll
+                for (int a = 0; a < PA / 4; ++a)
+                    o[a] = make_float4((float)Lv[4 * a], (float)Lv[4 * a + 1], (float)Lv[4 * a + 2],
+                                       (float)Lv[4 * a + 3]);
+            }
         }
     }
 }
@@ -672,6 +680,114 @@ __global__ __launch_bounds__(EvalCfg<P>::PTS * 4) void k_leaf_eval(const EvalChu
         __syncthreads();
     }
     // the four lanes of a point hold disjoint b rows
+    u0 += __shfl_xor(u0, 16);
+    u1 += __shfl_xor(u1, 16);
+    u2 += __shfl_xor(u2, 16);
+    u0 += __shfl_xor(u0, 32);
+    u1 += __shfl_xor(u1, 32);
+    u2 += __shfl_xor(u2, 32);
+    if (valid && lk == 0) {
+        u[i] += u0;
+        u[n + i] += u1;
+        u[2 * n + i] += u2;
+    }
+}
+
+// The same evaluation for plans whose far field is stored in FP32: the
+// contractions over a run on v_mfma_f32_16x16x4f32 (twice the FP64 MFMA rate)
+// with the proxy potentials and Lagrange values in FP32; the b and c weights
+// and the accumulation at the points stay FP64.  The f32 MFMA returns row
+// 4 (l/16) + r of its 16 x 16 tile in register r of lane l.
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+template <int P>
+__global__ __launch_bounds__(EvalCfg<P>::PTS * 4) void k_leaf_eval32(const EvalChunk* __restrict__ chunks,
+                                                                     int nchunk, const float* __restrict__ Ltab,
+                                                                     const float* __restrict__ V, int64_t n,
+                                                                     double* __restrict__ u)
+{
+    constexpr int PA = MCfg<P>::PA, NK = MCfg<P>::NK, NT = MCfg<P>::NT, RS = MCfg<P>::RS;
+    constexpr int PB = 16 * NT;
+    constexpr int NTH = EvalCfg<P>::PTS * 4;
+    constexpr int NPRE = (3 * P * P + NTH - 1) / NTH;  // slab elements per thread
+    __shared__ float slab[2][3][PB][RS];                // double-buffered c-slabs
+    const EvalChunk C = chunks[blockIdx.x];
+    const float* v = V + (size_t)C.fid * 3 * P * P * P;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int lr = l & 15, lk = l >> 4;
+    const int64_t i = C.start + 16 * w + lr;
+    const bool valid = i < C.end;
+    const float* Li = Ltab + (size_t)(valid ? i : C.start) * 3 * PA;
+    float bx[NK];
+#pragma unroll
+    for (int s = 0; s < NK; ++s)
+        bx[s] = valid ? Li[4 * s + lk] : 0.0f;
+    double wy[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int b = 16 * t + 4 * lk + r;
+            wy[t][r] = (valid && b < P) ? (double)Li[PA + b] : 0.0;
+        }
+    for (int e = tid; e < 2 * 3 * PB * RS; e += NTH)
+        (&slab[0][0][0][0])[e] = 0.0f;
+    float pre[NPRE];
+    auto fetch = [&](int c) {
+#pragma unroll
+        for (int k = 0; k < NPRE; ++k) {
+            const int e = tid + k * NTH;
+            if (e < 3 * P * P) {
+                const int j = e / (P * P), r = e % (P * P);
+                pre[k] = v[(size_t)j * P * P * P + (size_t)c * P * P + r];
+            }
+        }
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < NPRE; ++k) {
+            const int e = tid + k * NTH;
+            if (e < 3 * P * P) {
+                const int j = e / (P * P), r = e % (P * P);
+                slab[buf][j][r / P][r % P] = pre[k];
+            }
+        }
+    };
+    __syncthreads();
+    fetch(0);
+    put(0);
+    __syncthreads();
+    double u0 = 0, u1 = 0, u2 = 0;
+    const bool busy = __ballot(valid) != 0ull;
+#pragma unroll 1
+    for (int c = 0; c < P; ++c) {
+        const int cur = c & 1;
+        if (c + 1 < P)
+            fetch(c + 1);
+        if (busy) {
+            const double lz = valid ? (double)Li[2 * PA + c] : 0.0;
+            double X[3] = {0, 0, 0};
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    mfma_f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int s = 0; s < NK; ++s)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(slab[cur][j][16 * t + lr][4 * s + lk], bx[s], acc,
+                                                                   0, 0, 0);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        X[j] = fma(wy[t][r], (double)acc[r], X[j]);
+                }
+            u0 = fma(lz, X[0], u0);
+            u1 = fma(lz, X[1], u1);
+            u2 = fma(lz, X[2], u2);
+        }
+        if (c + 1 < P)
+            put(cur ^ 1);
+        __syncthreads();
+    }
     u0 += __shfl_xor(u0, 16);
     u1 += __shfl_xor(u1, 16);
     u2 += __shfl_xor(u2, 16);
@@ -817,6 +933,124 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
     }
 }
 
+// Proxy charges for plans whose far field is stored in FP32: the same
+// contraction on v_mfma_f32_16x16x4f32 with FP32 Lagrange values and forces.
+// The FP32 accumulators are folded into FP64 sums every 64 points (blocked
+// summation: the rounding error grows with 64 terms, not with the leaf's
+// size), and the FP64 sums are rounded once to the stored FP32 charges.  Every
+// a-tile, the partial last one included, runs here.
+template <int P, int NC>
+__global__ __launch_bounds__(64) void k_anterp_mfma32(const LeafDesc* __restrict__ leaves, int nleaf,
+                                                      const float* __restrict__ Ltab, const double* __restrict__ fs,
+                                                      int64_t n, float* __restrict__ Q)
+{
+    using C = AMCfg<P>;
+    constexpr int PA = C::PA, NN = C::NN, MF = C::MT;
+    constexpr int TASKS = MF * C::NG;
+    const int xcd = blockIdx.x % 8, sx = blockIdx.x / 8;
+    const int task = sx % TASKS;
+    const int leaf = xcd + 8 * (sx / TASKS);
+    if (leaf >= nleaf)
+        return;
+    const LeafDesc L = leaves[leaf];
+    const int mt = task % MF, ng = task / MF;
+    const int l = threadIdx.x;
+    const int li = l & 15, lk = l >> 4;
+    const int a = 16 * mt + li;
+    const bool a_ok = a < P;
+    int bcol[NN], ccol[NN];
+    bool n_ok[NN];
+#pragma unroll
+    for (int t = 0; t < NN; ++t) {
+        const int nn = 16 * (NN * ng + t) + li;
+        n_ok[t] = nn < P * P;
+        bcol[t] = n_ok[t] ? nn / P : 0;
+        ccol[t] = n_ok[t] ? nn % P : 0;
+    }
+    mfma_f4 acc[NN][NC];
+    double sum[NN][NC][4];
+#pragma unroll
+    for (int t = 0; t < NN; ++t)
+#pragma unroll
+        for (int j = 0; j < NC; ++j) {
+            acc[t][j] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                sum[t][j][r] = 0.0;
+        }
+    float ax0, fa0[NC], ly0[NN], lz0[NN];
+    float ax1, fa1[NC], ly1[NN], lz1[NN];
+#define DMK_AM_LOAD(AX, FA, LY, LZ, PT0)                                          \
+    {                                                                             \
+        const int64_t pt = (PT0) + lk;                                            \
+        const bool ok = pt < L.end;                                               \
+        const int64_t pc = ok ? pt : L.start;                                     \
+        const float* Lp = Ltab + (size_t)pc * 3 * PA;                             \
+        const float ax = Lp[a_ok ? a : 0];                                        \
+        AX = (ok && a_ok) ? ax : 0.0f;                                            \
+        _Pragma("unroll") for (int j = 0; j < NC; ++j)                            \
+        {                                                                         \
+            const float g = (float)fs[(size_t)j * n + pc];                        \
+            FA[j] = ok ? g : 0.0f;                                                \
+        }                                                                         \
+        _Pragma("unroll") for (int t = 0; t < NN; ++t)                            \
+        {                                                                         \
+            const float yv = Lp[PA + bcol[t]];                                    \
+            LY[t] = n_ok[t] ? yv : 0.0f;                                          \
+            LZ[t] = Lp[2 * PA + ccol[t]];                                         \
+        }                                                                         \
+    }
+#define DMK_AM_STEP(AX, FA, LY, LZ)                                                           \
+    _Pragma("unroll") for (int t = 0; t < NN; ++t)                                            \
+    {                                                                                         \
+        const float w = LY[t] * LZ[t];                                                        \
+        _Pragma("unroll") for (int j = 0; j < NC; ++j)                                        \
+            acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(AX, w * FA[j], acc[t][j], 0, 0, 0); \
+    }
+    auto fold = [&]() {
+#pragma unroll
+        for (int t = 0; t < NN; ++t)
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    sum[t][j][r] += (double)acc[t][j][r];
+                acc[t][j] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+            }
+    };
+    DMK_AM_LOAD(ax0, fa0, ly0, lz0, L.start)
+    int steps = 0;
+    for (int64_t p0 = L.start; p0 < L.end; p0 += 8) {
+        DMK_AM_LOAD(ax1, fa1, ly1, lz1, p0 + 4)
+        DMK_AM_STEP(ax0, fa0, ly0, lz0)
+        DMK_AM_LOAD(ax0, fa0, ly0, lz0, p0 + 8)
+        DMK_AM_STEP(ax1, fa1, ly1, lz1)
+        if (++steps == 8) {  // 64 points
+            fold();
+            steps = 0;
+        }
+    }
+    fold();
+#undef DMK_AM_LOAD
+#undef DMK_AM_STEP
+    // D[row = 4 lk + r][col = li] of tile t: a = 16 mt + 4 lk + r, n = 16 (NN ng + t) + li
+    float* q = Q + (size_t)L.fid * NC * P * P * P;
+#pragma unroll
+    for (int t = 0; t < NN; ++t) {
+        if (!n_ok[t])
+            continue;
+        const int nn = 16 * (NN * ng + t) + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ar = 16 * mt + 4 * lk + r;
+            if (ar < P)
+#pragma unroll
+                for (int j = 0; j < NC; ++j)
+                    q[((size_t)j * P + ar) * P * P + nn] = (float)sum[t][j][r];
+        }
+    }
+}
+
 // The rows of the last, partial a-tile, for every component at once: row
 // (j, a), a in [A0, P), packed NC * REM to a column of row tiles (21 rows in
 // two tiles at p = 23 instead of one mostly empty tile per component).  Here
@@ -939,16 +1173,23 @@ bool p_supported(int p)
 int lagrange_pad(int p) { return (p + 3) / 4 * 4; }
 
 void launch_lagrange_table(int p, const LeafDesc* leaves, int nleaf, const double* x, const double* y,
-                           const double* z, const double* cheb_t, const double* cheb_w, double* Ltab, hipStream_t s)
+                           const double* z, const double* cheb_t, const double* cheb_w, void* Ltab, bool f32,
+                           hipStream_t s)
 {
     if (nleaf == 0)
         return;
-#define L_LT(P) hipLaunchKernelGGL(k_lagrange_table<P>, dim3(nleaf), dim3(256), 0, s, leaves, x, y, z, cheb_t, cheb_w, Ltab)
+#define L_LT(P)                                                                                              \
+    if (f32)                                                                                                 \
+        hipLaunchKernelGGL((k_lagrange_table<P, float>), dim3(nleaf), dim3(256), 0, s, leaves, x, y, z, cheb_t, \
+                           cheb_w, (float*)Ltab);                                                            \
+    else                                                                                                     \
+        hipLaunchKernelGGL((k_lagrange_table<P, double>), dim3(nleaf), dim3(256), 0, s, leaves, x, y, z,      \
+                           cheb_t, cheb_w, (double*)Ltab)
     DMK_P_DISPATCH(p, L_LT)
 #undef L_LT
 }
 
-void launch_anterp(int p, int nc, const LeafDesc* leaves, int nleaf, const double* Ltab, const double* fs, int64_t n,
+void launch_anterp(int p, int nc, const LeafDesc* leaves, int nleaf, const void* Ltab, const double* fs, int64_t n,
                    void* Q, bool f32, hipStream_t s)
 {
     if (nleaf == 0)
@@ -956,19 +1197,15 @@ void launch_anterp(int p, int nc, const LeafDesc* leaves, int nleaf, const doubl
     const int nleaf8 = (nleaf + 7) / 8 * 8;
 #define L_ANTERP_NC(P, NC)                                                                                       \
     if (f32) {                                                                                                   \
-        if constexpr (AMRem<P, NC>::FULL_TASKS > 0)                                                              \
-            hipLaunchKernelGGL((k_anterp_mfma<P, NC, float>), dim3(nleaf8 * AMRem<P, NC>::FULL_TASKS), dim3(64), \
-                               0, s, leaves, nleaf, Ltab, fs, n, (float*)Q);                                     \
-        if constexpr (AMRem<P, NC>::SPLIT)                                                                       \
-            hipLaunchKernelGGL((k_anterp_rem<P, NC, float>), dim3(nleaf8 * AMRem<P, NC>::TASKS), dim3(64), 0, s, \
-                               leaves, nleaf, Ltab, fs, n, (float*)Q);                                           \
+        hipLaunchKernelGGL((k_anterp_mfma32<P, NC>), dim3(nleaf8 * AMCfg<P>::MT * AMCfg<P>::NG), dim3(64), 0, s, \
+                           leaves, nleaf, (const float*)Ltab, fs, n, (float*)Q);                                 \
     } else {                                                                                                     \
         if constexpr (AMRem<P, NC>::FULL_TASKS > 0)                                                              \
             hipLaunchKernelGGL((k_anterp_mfma<P, NC, double>), dim3(nleaf8 * AMRem<P, NC>::FULL_TASKS),          \
-                               dim3(64), 0, s, leaves, nleaf, Ltab, fs, n, (double*)Q);                          \
+                               dim3(64), 0, s, leaves, nleaf, (const double*)Ltab, fs, n, (double*)Q);           \
         if constexpr (AMRem<P, NC>::SPLIT)                                                                       \
             hipLaunchKernelGGL((k_anterp_rem<P, NC, double>), dim3(nleaf8 * AMRem<P, NC>::TASKS), dim3(64), 0,   \
-                               s, leaves, nleaf, Ltab, fs, n, (double*)Q);                                       \
+                               s, leaves, nleaf, (const double*)Ltab, fs, n, (double*)Q);                        \
     }
 #define L_ANTERP(P)               \
     if (nc == 6) {                \
@@ -981,18 +1218,18 @@ void launch_anterp(int p, int nc, const LeafDesc* leaves, int nleaf, const doubl
 #undef L_ANTERP_NC
 }
 
-void launch_leaf_eval(int p, const EvalChunk* chunks, int nchunk, const double* Ltab, const void* V, int64_t n,
+void launch_leaf_eval(int p, const EvalChunk* chunks, int nchunk, const void* Ltab, const void* V, int64_t n,
                       double* u, bool f32, hipStream_t s)
 {
     if (nchunk == 0)
         return;
 #define L_EVAL(P)                                                                                               \
     if (f32)                                                                                                    \
-        hipLaunchKernelGGL((k_leaf_eval<P, float>), dim3(nchunk), dim3(EvalCfg<P>::PTS * 4), 0, s, chunks, nchunk, \
-                           Ltab, (const float*)V, n, u);                                                        \
+        hipLaunchKernelGGL((k_leaf_eval32<P>), dim3(nchunk), dim3(EvalCfg<P>::PTS * 4), 0, s, chunks, nchunk,   \
+                           (const float*)Ltab, (const float*)V, n, u);                                          \
     else                                                                                                        \
         hipLaunchKernelGGL((k_leaf_eval<P, double>), dim3(nchunk), dim3(EvalCfg<P>::PTS * 4), 0, s, chunks,     \
-                           nchunk, Ltab, (const double*)V, n, u)
+                           nchunk, (const double*)Ltab, (const double*)V, n, u)
     DMK_P_DISPATCH(p, L_EVAL)
 #undef L_EVAL
 }

@@ -67,15 +67,18 @@ struct LeafDesc {
 };
 
 // Lagrange values of each sorted point on its leaf's proxy grid:
-// Ltab[i][d][0..lagrange_pad(p)) for d = x, y, z (zero padded)
+// Ltab[i][d][0..lagrange_pad(p)) for d = x, y, z (zero padded); float when
+// f32 (plans whose far field is stored in FP32), else double
 int lagrange_pad(int p);
 // Chebyshev orders p the point kernels are compiled for
 bool p_supported(int p);
 void launch_lagrange_table(int p, const LeafDesc* leaves, int nleaf, const double* x, const double* y,
-                           const double* z, const double* cheb_t, const double* cheb_w, double* Ltab, hipStream_t s);
+                           const double* z, const double* cheb_t, const double* cheb_w, void* Ltab, bool f32,
+                           hipStream_t s);
 // proxy charges of leaves (Step 2a): Q[fid][j][a][b][c] = sum_pt L_a L_b L_c f_j
-// nc = 3 (Stokeslet forces) or 6 (stresslet densities); Q[fid][nc][a][b][c]
-void launch_anterp(int p, int nc, const LeafDesc* leaves, int nleaf, const double* Ltab, const double* fs, int64_t n,
+// nc = 3 (Stokeslet forces) or 6 (stresslet densities); Q[fid][nc][a][b][c].
+// f32: FP32 Ltab and Q, contraction on FP32 MFMA with FP64 blocked sums
+void launch_anterp(int p, int nc, const LeafDesc* leaves, int nleaf, const void* Ltab, const double* fs, int64_t n,
                    void* Q, bool f32, hipStream_t s);
 // far-field value at the points (final interpolation), V z-major V[fid][j][c][b][a]:
 // u[j][i] += sum V L L L, over chunks of at most eval_chunk_points(p) points of
@@ -85,7 +88,8 @@ struct EvalChunk {
     int fid;
     int64_t start, end;
 };
-void launch_leaf_eval(int p, const EvalChunk* chunks, int nchunk, const double* Ltab, const void* V, int64_t n,
+// f32: FP32 Ltab and V, contraction over a on FP32 MFMA, the rest FP64
+void launch_leaf_eval(int p, const EvalChunk* chunks, int nchunk, const void* Ltab, const void* V, int64_t n,
                       double* u, bool f32, hipStream_t s);
 
 // ---- separable tensor stages ------------------------------------------------
