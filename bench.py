@@ -83,13 +83,20 @@ def _near_profile_record(config: str, precision: str, kernel: str, leaf_size: in
     rec = json.loads(m.group(0))
     src = open(os.path.join(ROOT, "paper_2509_21471_amd", "csrc", "dmk_kernels.hip")).read()
     # the kernel's source and the within-leaf point order it runs on
-    sec = (src[src.index("// ---- near field"):src.index("// ---- finishing")]
-           + src[src.index("// ---- compact point groups"):src.index("size_t sort_temp_bytes")])
+    sec = near_source_section(src)
     if hashlib.sha256(sec.encode()).hexdigest() != rec["near_section_sha256"] or rec["kernel"] != kernel:
         return None
     if rec.get("leaf_size") != leaf_size or rec.get("near_lanes") != near_lanes:
         return None
     return rec
+
+
+def near_source_section(src: str) -> str:
+    """The near-field kernels and the within-leaf reorder they run on (the
+    text whose hash a near-field profile records)."""
+    lo = src.index("void launch_leaf_order(")
+    return (src[src.index("// ---- near field"):src.index("// ---- finishing")]
+            + src[src.index("// ---- compact point groups"):src.index("\n}\n", lo) + 3])
 
 
 def workloads_tol(config: str) -> float:

@@ -147,6 +147,11 @@ typedef struct {
  * pairs (Step 4 evaluates the residual only within r_lambda).  The sums are
  * the same up to rounding either way. */
 #define DMK_FLAG_MORTON_ORDER 8
+/* build the octree, its level restriction and the neighbour lists on the host
+ * (sequential construction, from the same device-sorted keys) instead of on
+ * the device.  Both constructions give the same tree and lists; the flag is a
+ * reference for checks. */
+#define DMK_FLAG_HOST_TREE 16
 
 /* phases reported by dmk_stokes_phase_ms (an evaluation runs the near field
  * first, then the far-field phases in index order, then the finish) */

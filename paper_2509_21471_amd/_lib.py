@@ -33,6 +33,7 @@ FLAG_PHASE_TIMING = 1
 FLAG_CONCURRENT_PLAN = 2
 FLAG_GRAPH = 4
 FLAG_MORTON_ORDER = 8
+FLAG_HOST_TREE = 16
 
 
 class DMKError(RuntimeError):
@@ -219,7 +220,8 @@ class Plan:
                  leaf_size: int = 0, stream=None, mem_cap_bytes: int = 0, timing: bool = False,
                  near_lanes: int = 0, q: int = 0, p: int = 0, rhs_batch: int = 0, concurrent: bool = False,
                  offsets=None, graph: bool = False, targets=None, window: int = 0,
-                 kernel: int = KERNEL_STOKESLET, method: int = METHOD_DMK, leaf_order: bool = True):
+                 kernel: int = KERNEL_STOKESLET, method: int = METHOD_DMK, leaf_order: bool = True,
+                 host_tree: bool = False):
         """offsets (host int sequence, n_problems + 1 entries) makes a batched
         plan over independent problems (dmk_stokes_plan_batch); targets (device
         (m,3)) makes a plan evaluating the sums at a separate target set
@@ -227,7 +229,9 @@ class Plan:
         kernel = KERNEL_STRESSLET makes a stresslet plan, evaluated with
         eval_stresslet.  method = METHOD_EWALD makes a single-level spectral
         Ewald plan (periodic, one problem).  leaf_order = False keeps the
-        points of every leaf in Morton order (DMK_FLAG_MORTON_ORDER)."""
+        points of every leaf in Morton order (DMK_FLAG_MORTON_ORDER).
+        host_tree = True builds the octree and lists on the host
+        (DMK_FLAG_HOST_TREE, the reference construction)."""
         torch = _torch()
         pts = _dev_f64(points)
         self.n = int(pts.shape[0])
@@ -235,7 +239,8 @@ class Plan:
         self.stream = stream
         opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), int(mem_cap_bytes),
                     (FLAG_PHASE_TIMING if timing else 0) | (FLAG_CONCURRENT_PLAN if concurrent else 0)
-                    | (FLAG_GRAPH if graph else 0) | (0 if leaf_order else FLAG_MORTON_ORDER),
+                    | (FLAG_GRAPH if graph else 0) | (0 if leaf_order else FLAG_MORTON_ORDER)
+                    | (FLAG_HOST_TREE if host_tree else 0),
                     int(near_lanes), int(q), int(p), int(rhs_batch), int(window), int(kernel),
                     int(method))
         h = ctypes.c_void_p()

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libdmk_stokes.so")
-SOURCES = ["dmk_kernels.hip", "ewald_kernels.hip", "capi.cpp", "kernel_math.cpp", "tree.cpp"]
+SOURCES = ["dmk_kernels.hip", "tree_gpu.hip", "ewald_kernels.hip", "capi.cpp", "kernel_math.cpp", "tree.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

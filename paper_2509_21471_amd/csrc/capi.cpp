@@ -309,6 +309,7 @@ struct dmk_plan_s {
     // DMK_FLAG_GRAPH: evaluation captured once per (forces, n_rhs, velocities)
     bool use_graph = false;
     bool leaf_order = true;           // compact groups inside leaves (near-field pruning)
+    bool host_tree = false;           // octree and lists built on the host (reference construction)
     bool near_refine = true;          // Newton step on the near field's reciprocal square root
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -787,10 +788,14 @@ int build_plan(dmk_plan_t P, const double* points)
     if (np == 1)
         launch_sort(tmp, tb, k0, k1, i0, P->perm, n, 3 * kKeyBits, st);
     else
-        launch_seg_sort(tmp, tb, k0, k1, i0, P->perm, n, np, P->d_off, 3 * kKeyBits, st);
-    std::vector<uint64_t> keys(n);
-    HIPCHK(hipMemcpyAsync(keys.data(), k1, n * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+        launch_seg_sort(tmp, tb, k0, k1, i0, P->perm, n, np, P->pid, 3 * kKeyBits, st);
+    HIPCHK(hipGetLastError());
+    std::vector<uint64_t> keys;
+    if (P->method == DMK_METHOD_EWALD || P->host_tree) {
+        keys.resize(n);
+        HIPCHK(hipMemcpyAsync(keys.data(), k1, n * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
     lap(1);
     if (P->method == DMK_METHOD_EWALD) {
         P->x = P->mem.alloc<double>(n);
@@ -803,17 +808,48 @@ int build_plan(dmk_plan_t P, const double* points)
         lap(2);
         return rc;
     }
-    // ---- tree (a forest of one octree per problem) ----
+    // ---- tree (a forest of one octree per problem), built on the device ----
     const int ns = P->prm.ns;
-    std::vector<int> roots(1, 0);
-    if (np == 1) {
-        build_tree(keys.data(), n, ns, P->periodic, &P->tree);
-    } else {
-        std::vector<Tree> parts(np);
+    std::vector<int> roots(np);
+    for (int b = 0; b < np; ++b)
+        roots[b] = b;  // level 0 holds the roots in problem order
+    bool host = P->host_tree;
+    if (!host) {
+        const int64_t* d_off = P->d_off;
+        if (np == 1) {
+            int64_t* o = P->mem.alloc<int64_t>(2);
+            if (!o)
+                return fail(DMK_ERR_OOM, "device allocation failed");
+            const std::vector<int64_t> h_off = {0, n};
+            HIPCHK(upload(o, h_off, st));  // h_off outlives the build, which synchronises st
+            d_off = o;
+        }
+        DevMem scratch;
+        auto alloc = [](void* ctx, size_t bytes) -> void* { return static_cast<DevMem*>(ctx)->alloc<char>(bytes); };
+        std::string err;
+        const int rc = build_tree_device(k1, d_off, np, n, ns, P->periodic, alloc, &scratch, st, &P->tree, &err);
+        if (rc == DMK_TREE_UNSUPPORTED)
+            host = true;  // a forest too deep for the device construction's packed keys
+        else if (rc != 0)
+            return fail(rc == DMK_TREE_OOM ? DMK_ERR_OOM : DMK_ERR_HIP, "octree: " + err);
+    }
+    if (host) {
+        // the sequential construction from the same sorted keys
+        if (keys.empty()) {
+            keys.resize(n);
+            HIPCHK(hipMemcpyAsync(keys.data(), k1, n * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        if (np == 1) {
+            build_tree(keys.data(), n, ns, P->periodic, &P->tree);
+        } else {
+            std::vector<Tree> parts(np);
 #pragma omp parallel for schedule(dynamic)
-        for (int b = 0; b < np; ++b)
-            build_tree(keys.data() + P->offsets[b], P->offsets[b + 1] - P->offsets[b], ns, P->periodic, &parts[b]);
-        merge_forest(parts, P->offsets, &P->tree, &roots);
+            for (int b = 0; b < np; ++b)
+                build_tree(keys.data() + P->offsets[b], P->offsets[b + 1] - P->offsets[b], ns, P->periodic,
+                           &parts[b]);
+            merge_forest(parts, P->offsets, &P->tree, &roots);
+        }
     }
     lap(2);
     const Tree& T = P->tree;
@@ -1582,6 +1618,7 @@ int create_plan(const double* points, const std::vector<int64_t>& offsets, int d
         P->concurrent = (opts->flags & DMK_FLAG_CONCURRENT_PLAN) != 0;
         P->use_graph = (opts->flags & DMK_FLAG_GRAPH) != 0;
         P->leaf_order = (opts->flags & DMK_FLAG_MORTON_ORDER) == 0;
+        P->host_tree = (opts->flags & DMK_FLAG_HOST_TREE) != 0;
     }
     if (hipEventCreateWithFlags(&P->done, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();

@@ -1,7 +1,6 @@
 // Device kernels of the DMK Stokeslet path (gfx950, double precision).
 #include "dmk_kernels.hpp"
 
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <mutex>
@@ -368,35 +367,6 @@ void launch_leaf_order(const KdSeg* segs, int nseg, const int* perm, const doubl
     hipLaunchKernelGGL(k_compose, dim3(nblocks(n, 256)), dim3(256), 0, s, perm, src, n, perm_out);
 }
 
-size_t sort_temp_bytes(int64_t n)
-{
-    size_t bytes = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                       (const int*)nullptr, (int*)nullptr, (int)n, 0, 57);
-    return bytes;
-}
-
-void launch_sort(void* temp, size_t temp_bytes, const uint64_t* kin, uint64_t* kout, const int* vin, int* vout,
-                 int64_t n, int end_bit, hipStream_t s)
-{
-    (void)hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, kin, kout, vin, vout, (int)n, 0, end_bit, s);
-}
-
-size_t seg_sort_temp_bytes(int64_t n, int nseg)
-{
-    size_t bytes = 0;
-    (void)hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                                      (const int*)nullptr, (int*)nullptr, (int)n, nseg,
-                                                      (const int64_t*)nullptr, (const int64_t*)nullptr, 0, 57);
-    return bytes;
-}
-
-void launch_seg_sort(void* temp, size_t temp_bytes, const uint64_t* kin, uint64_t* kout, const int* vin, int* vout,
-                     int64_t n, int nseg, const int64_t* off, int end_bit, hipStream_t s)
-{
-    (void)hipcub::DeviceSegmentedRadixSort::SortPairs(temp, temp_bytes, kin, kout, vin, vout, (int)n, nseg, off,
-                                                      off + 1, 0, end_bit, s);
-}
 
 __global__ __launch_bounds__(256) void k_chunk_bbox(const double* __restrict__ x, const double* __restrict__ y,
                                                     const double* __restrict__ z, const int64_t* __restrict__ cstart,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 namespace dmk {
 
@@ -39,14 +40,31 @@ struct KdSeg {
 };
 void launch_leaf_order(const KdSeg* segs, int nseg, const int* perm, const double* x, const double* y,
                        const double* z, int64_t n, int* src, int* perm_out, hipStream_t s);
-// radix sort of (key, index) pairs; temp storage is allocated by the caller
+// radix sort of (key, index) pairs by the low end_bit key bits (stable, 8-bit
+// digits); temp storage is allocated by the caller
 size_t sort_temp_bytes(int64_t n);
 void launch_sort(void* temp, size_t temp_bytes, const uint64_t* kin, uint64_t* kout, const int* vin, int* vout,
                  int64_t n, int end_bit, hipStream_t s);
-// radix sort within each segment [off[b], off[b+1])
+// the same within each problem: points of problem b are contiguous in the
+// input and pid[v] is the problem of value v (the input positions)
 size_t seg_sort_temp_bytes(int64_t n, int nseg);
 void launch_seg_sort(void* temp, size_t temp_bytes, const uint64_t* kin, uint64_t* kout, const int* vin, int* vout,
-                     int64_t n, int nseg, const int64_t* off, int end_bit, hipStream_t s);
+                     int64_t n, int nseg, const int* pid, int end_bit, hipStream_t s);
+// Level-restricted octree (a forest over np problems) of the sorted Morton
+// keys, built on the device, and its exchange and near lists (Step 1); the
+// result is mirrored into *T (boxes level-major, problem and Morton order
+// within a level, as build_tree / merge_forest order them; colleague lists are
+// not mirrored).  d_off: device offsets of the problems (np + 1).  alloc
+// returns device scratch that stays valid until the call returns.  Returns 0,
+// or DMK_TREE_OOM / DMK_TREE_HIP / DMK_TREE_UNSUPPORTED with *err set.
+// Synchronises s.
+struct Tree;
+using DeviceAlloc = void* (*)(void* ctx, size_t bytes);
+constexpr int DMK_TREE_OOM = 1;
+constexpr int DMK_TREE_HIP = 2;
+constexpr int DMK_TREE_UNSUPPORTED = 3;  // too deep for the packed keys: use the host construction
+int build_tree_device(const uint64_t* keys, const int64_t* d_off, int np, int64_t n, int ns, bool periodic,
+                      DeviceAlloc alloc, void* actx, hipStream_t s, Tree* T, std::string* err);
 // per 64-point chunk bounding boxes (chunk list given as starts/ends)
 void launch_chunk_bbox(const double* x, const double* y, const double* z, const int64_t* cstart,
                        const int* clen, int nchunk, double* bbox /*nchunk*6*/, hipStream_t s);
