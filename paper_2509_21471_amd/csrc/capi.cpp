@@ -311,6 +311,8 @@ struct dmk_plan_s {
     bool leaf_order = true;           // compact groups inside leaves (near-field pruning)
     bool host_tree = false;           // octree and lists built on the host (reference construction)
     bool near_refine = true;          // Newton step on the near field's reciprocal square root
+    bool no_coincident = false;       // no two distinct points coincide (near field skips r = 0 pairs)
+    int h_coincident = 1;             // host copy of the plan-time coincidence flag
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -472,6 +474,11 @@ bool make_poly(const dmk::Tables& TB, dmk::RadialPoly* poly)
     poly->nd = nd;
     conv(TB.fits.P.a, poly->P);
     conv(TB.fits.Q.a, poly->Q);
+    // P at t = -1: T_k(-1) = (-1)^k
+    long double ps = 0.0L;
+    for (size_t k = 0; k < TB.fits.P.a.size(); ++k)
+        ps += (k % 2 ? -1.0L : 1.0L) * (long double)TB.fits.P.a[k];
+    poly->p_self = (double)ps;
     return true;
 }
 
@@ -790,6 +797,13 @@ int build_plan(dmk_plan_t P, const double* points)
     else
         launch_seg_sort(tmp, tb, k0, k1, i0, P->perm, n, np, P->pid, 3 * kKeyBits, st);
     HIPCHK(hipGetLastError());
+    // coincident points: the flag reaches the host with the tree (the build synchronises st)
+    int* d_coinc = P->mem.alloc<int>(1);
+    if (!d_coinc)
+        return fail(DMK_ERR_OOM, "device allocation failed");
+    launch_zero(d_coinc, sizeof(int), st);
+    launch_find_coincident(k1, P->perm, points, n, d_coinc, st);
+    HIPCHK(hipMemcpyAsync(&P->h_coincident, d_coinc, sizeof(int), hipMemcpyDeviceToHost, st));
     std::vector<uint64_t> keys;
     if (P->method == DMK_METHOD_EWALD || P->host_tree) {
         keys.resize(n);
@@ -851,6 +865,8 @@ int build_plan(dmk_plan_t P, const double* points)
             merge_forest(parts, P->offsets, &P->tree, &roots);
         }
     }
+    HIPCHK(hipStreamSynchronize(st));  // (already reached by the tree build)
+    P->no_coincident = P->h_coincident == 0;
     lap(2);
     const Tree& T = P->tree;
     // ---- separate targets: sources first within every leaf ----
@@ -1345,7 +1361,8 @@ int eval_batch(dmk_plan_t P, const double* f, int nb, double* vel, bool record)
     for (int r = 0; r < nb; ++r)
         launch_gather_forces(f + (size_t)r * 3 * P->nsrc, n, P->nsrc, P->perm, P->fs + (size_t)r * 3 * n, st);
     launch_zero(P->u, (size_t)nb * 3 * n * sizeof(double), st);
-    launch_near(DMK_KERNEL_STOKESLET, P->near_sg, nb, P->near_refine, P->nwork, P->n_nwork, P->nleaves, P->nentries,
+    launch_near(DMK_KERNEL_STOKESLET, P->near_sg, nb, P->near_refine, P->no_coincident, P->nsrc == n, P->nwork,
+                P->n_nwork, P->nleaves, P->nentries,
                 P->cbbox, P->x, P->y, P->z, P->fs, n, P->poly, P->u, st);
     if (record) {
         (void)hipEventRecord(P->ev[9], st);
@@ -1381,7 +1398,7 @@ int eval_stresslet(dmk_plan_t P, const double* f, const double* nv, double* vel,
         (void)hipEventRecord(P->ev[DMK_NUM_PHASES + 1], st);
     launch_gather_stresslet(f, nv, n, P->nsrc, P->perm, P->fs, P->fs + 6 * (size_t)n, st);
     launch_zero(P->u, 3 * (size_t)n * sizeof(double), st);
-    launch_near(DMK_KERNEL_STRESSLET, P->near_sg, 1, true, P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x,
+    launch_near(DMK_KERNEL_STRESSLET, P->near_sg, 1, true, false, false, P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x,
                 P->y, P->z, P->fs + 6 * (size_t)n, n, P->poly, P->u, st);
     if (record) {
         (void)hipEventRecord(P->ev[9], st);
@@ -1433,7 +1450,8 @@ int eval_ewald(dmk_plan_t P, const double* f, double* vel, bool record)
     launch_ewald_interp(E.M, E.B, E.Lt, E.w, P->gpoly, P->tile_start, P->x, P->y, P->z, n, P->egrid, P->u, st);
     mark(8);
     mark(DMK_NUM_PHASES + 1);
-    launch_near(DMK_KERNEL_STOKESLET, P->near_sg, 1, P->near_refine, P->nwork, P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x,
+    launch_near(DMK_KERNEL_STOKESLET, P->near_sg, 1, P->near_refine, P->no_coincident, P->nsrc == n, P->nwork,
+                P->n_nwork, P->nleaves, P->nentries, P->cbbox, P->x,
                 P->y, P->z, P->fs, n, P->poly, P->u, st);
     mark(9);
     mark(DMK_NUM_PHASES + 2);

@@ -1819,16 +1819,19 @@ __device__ inline double horner_v(const double* __restrict__ m, double top, doub
 // pt, qt: the leading coefficients of P and Q in vector registers.  RF = false
 // uses the hardware reciprocal square root unrefined (relative error below
 // 6e-8, measured on gfx950), enough for tolerances of 1e-6 and above.
-template <int ND, int NR, bool RF>
+// NZ: no two distinct points of the plan coincide, so the only pair at r = 0
+// is a target with itself; such pairs are skipped here and the kernel adds
+// the self term -S_M(0) f separately (saving the r = 0 select on every pair).
+template <int ND, int NR, bool RF, bool NZ = false>
 __device__ inline void residual_pair_multi(double xt, double yt, double zt, const double* v, double rl2, double tw,
                                            double c2, double c3, double pt, double qt, const RadialPoly& poly,
                                            double (&u)[NR][3])
 {
     const double dx = xt - v[0], dy = yt - v[1], dz = zt - v[2];
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    if (r2 < rl2) {
+    if (NZ ? (r2 < rl2 && r2 > 0.0) : (r2 < rl2)) {
         const double rq = RF ? rsqrt_f64(r2) : __builtin_amdgcn_rsq(r2);
-        const double rinv = r2 > 0.0 ? rq : 0.0;
+        const double rinv = NZ ? rq : (r2 > 0.0 ? rq : 0.0);
         const double t = fma(r2, tw, -1.0);
         const double P = horner_v<ND>(poly.P, pt, t);
         const double Q = horner_v<ND>(poly.Q, qt, t);
@@ -1891,13 +1894,13 @@ __device__ inline void residual_pair_stresslet(double xt, double yt, double zt, 
 // the sources' f and n as fs[6][n].  RF: refined reciprocal square root (the
 // Stokeslet pair routine).  The packed tile is padded with up to SG - 1 far
 // away dummy sources, so every lane runs the same number of pair steps.
-template <int ND, int SG, int NR, int KER, bool RF>
+template <int ND, int SG, int NR, int KER, bool RF, bool NZ>
 __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, int nwork,
                                              const NearLeaf* __restrict__ leaves,
                                              const NearEntryDev* __restrict__ entries, const double* __restrict__ cbbox,
                                              const double* __restrict__ x, const double* __restrict__ y,
                                              const double* __restrict__ z, const double* __restrict__ fs, int64_t n,
-                                             RadialPoly poly, double* __restrict__ u)
+                                             RadialPoly poly, int self_term, double* __restrict__ u)
 {
     constexpr int TG = 64 / SG;
     constexpr int NV = KER == 1 ? 7 : 3 * NR;  // staged values per source beyond its position
@@ -2010,6 +2013,7 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
                 }
                 __syncthreads();
                 const int steps = (kept + SG - 1) / SG;
+#pragma unroll 2
                 for (int it = 0; it < steps; ++it) {
                     const int jj = it * SG + sl;
                     double v[2 * W2];
@@ -2022,7 +2026,7 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
                     if constexpr (KER == 1)
                         residual_pair_stresslet<ND>(xt, yt, zt, v, rl2, tw, cP, cQ, pt, qt, poly, acc);
                     else
-                        residual_pair_multi<ND, NR, RF>(xt, yt, zt, v, rl2, tw, cP, cQ, pt, qt, poly, acc);
+                        residual_pair_multi<ND, NR, RF, NZ>(xt, yt, zt, v, rl2, tw, cP, cQ, pt, qt, poly, acc);
                 }
             }
         }
@@ -2035,6 +2039,16 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
             acc[r][1] += __shfl_xor(acc[r][1], off);
             acc[r][2] += __shfl_xor(acc[r][2], off);
         }
+    if (NZ && self_term && valid && sl == 0) {
+        // the pair of the target with itself (eq. S_self at the leaf's scale):
+        // -(2 / r_l) P(-1) f / (8 pi)
+        const double a = -ldexp(2.0 * poly.p_self, T.level);
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                acc[r][c] = fma(a, fs[(size_t)(3 * r + c) * n + i] * kInv8Pi, acc[r][c]);
+    }
     if (valid && sl == 0) {
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
@@ -2056,15 +2070,23 @@ __global__ __launch_bounds__(64) void k_near(const NearWork* __restrict__ work, 
         MACRO(24);                 \
     }
 
-void launch_near(int kernel, int sg, int nr, bool refine, const NearWork* work, int nwork, const NearLeaf* leaves,
-                 const NearEntryDev* entries, const double* cbbox, const double* x, const double* y, const double* z,
-                 const double* fs, int64_t n, const RadialPoly& poly, double* u, hipStream_t s)
+void launch_near(int kernel, int sg, int nr, bool refine, bool no_coincident, bool self_term, const NearWork* work,
+                 int nwork, const NearLeaf* leaves, const NearEntryDev* entries, const double* cbbox, const double* x,
+                 const double* y, const double* z, const double* fs, int64_t n, const RadialPoly& poly, double* u,
+                 hipStream_t s)
 {
     if (nwork == 0)
         return;
-#define L_NEAR_KK(ND, SG, NR, KER, RF)                                                                             \
-    hipLaunchKernelGGL((k_near<ND, SG, NR, KER, RF>), dim3(nwork), dim3(64), 0, s, work, nwork, leaves, entries, \
-                       cbbox, x, y, z, fs, n, poly, u)
+#define L_NEAR_KZ(ND, SG, NR, KER, RF, NZ)                                                                             \
+    hipLaunchKernelGGL((k_near<ND, SG, NR, KER, RF, NZ>), dim3(nwork), dim3(64), 0, s, work, nwork, leaves, entries, \
+                       cbbox, x, y, z, fs, n, poly, self_term ? 1 : 0, u)
+#define L_NEAR_KK(ND, SG, NR, KER, RF)             \
+    do {                                           \
+        if (KER == 0 && no_coincident)             \
+            L_NEAR_KZ(ND, SG, NR, KER, RF, true);  \
+        else                                       \
+            L_NEAR_KZ(ND, SG, NR, KER, RF, false); \
+    } while (0)
     // batches of several force vectors always use 4 source lanes per target
 #define L_STOKES(ND, RF)                     \
     if (nr == 2) {                           \
@@ -2102,6 +2124,7 @@ void launch_near(int kernel, int sg, int nr, bool refine, const NearWork* work, 
 #undef L_NEAR
 #undef L_STOKES
 #undef L_NEAR_KK
+#undef L_NEAR_KZ
 }
 
 template <int SG>

@@ -191,6 +191,7 @@ struct NearWork {
 struct RadialPoly {
     int nd;
     double P[24], Q[24];
+    double p_self;  // P at t = -1 (s = 0): the self pair's -S_M(0) f = -(2 / r_l) P(-1) f / (8 pi)
 };
 // sg: source lanes per target (1, 2, 4, 8); a wave holds 64/sg targets
 // kernel 0 (Stokeslet): forces and outputs [nr][3][n]; nr in {1, 2, 4, 8}
@@ -198,9 +199,18 @@ struct RadialPoly {
 // poly holds the stresslet's radial functions A (P) and D (Q)
 // refine = false (Stokeslet, tol >= 1e-6 only): the hardware reciprocal square
 // root without the Newton step (relative error below 6e-8)
-void launch_near(int kernel, int sg, int nr, bool refine, const NearWork* work, int nwork, const NearLeaf* leaves,
-                 const NearEntryDev* entries, const double* cbbox, const double* x, const double* y, const double* z,
-                 const double* fs, int64_t n, const RadialPoly& poly, double* u, hipStream_t s);
+// no_coincident (Stokeslet): no two distinct points coincide, so pairs at
+// r = 0 are skipped and, with self_term (sources = targets), the self pair's
+// term is added per target instead
+void launch_near(int kernel, int sg, int nr, bool refine, bool no_coincident, bool self_term, const NearWork* work,
+                 int nwork, const NearLeaf* leaves, const NearEntryDev* entries, const double* cbbox, const double* x,
+                 const double* y, const double* z, const double* fs, int64_t n, const RadialPoly& poly, double* u,
+                 hipStream_t s);
+// flag = 1 if two of the points coincide (exact equality), else unchanged:
+// points with equal Morton keys are compared within runs of the sorted keys
+// (a run longer than 64 keys sets the flag without comparing)
+void launch_find_coincident(const uint64_t* sorted_keys, const int* perm, const double* pts, int64_t n, int* flag,
+                            hipStream_t s);
 
 // pair counts of the near field: out[0] += evaluated pairs, out[1] += pairs in support
 void launch_near_count(int sg, const NearWork* work, int nwork, const NearLeaf* leaves, const NearEntryDev* entries,

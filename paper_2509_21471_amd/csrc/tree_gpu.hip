@@ -139,6 +139,29 @@ __global__ __launch_bounds__(256) void k_apply_perm(const int* __restrict__ perm
     }
 }
 
+// Coincident points share a Morton key, so they sit in runs of equal sorted
+// keys: every point compares its coordinates with the earlier points of its
+// run (at most 64 of them; a longer run sets the flag unchecked).
+__global__ __launch_bounds__(256) void k_coincident(const uint64_t* __restrict__ keys, const int* __restrict__ perm,
+                                                   const double* __restrict__ pts, int64_t n, int* __restrict__ flag)
+{
+    const int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x;
+    if (i == 0 || i >= n || keys[i] != keys[i - 1])
+        return;
+    const double* a = pts + 3 * (size_t)perm[i];
+    for (int64_t j = i - 1, k = 0; j >= 0 && keys[j] == keys[i]; --j, ++k) {
+        if (k == 64) {
+            *flag = 1;
+            return;
+        }
+        const double* b = pts + 3 * (size_t)perm[j];
+        if (a[0] == b[0] && a[1] == b[1] && a[2] == b[2]) {
+            *flag = 1;
+            return;
+        }
+    }
+}
+
 int64_t rs_tiles(int64_t n) { return (n + kRsTile - 1) / kRsTile; }
 
 // Sorts (kin, vin) by the low `bits` bits of the keys into (kout, vout).
@@ -712,6 +735,13 @@ __global__ __launch_bounds__(256) void k_fill_u64(uint64_t* __restrict__ a, int6
 size_t sort_temp_bytes(int64_t n)
 {
     return rs_temp_bytes(n);
+}
+
+void launch_find_coincident(const uint64_t* sorted_keys, const int* perm, const double* pts, int64_t n, int* flag,
+                            hipStream_t s)
+{
+    if (n > 1)
+        hipLaunchKernelGGL(k_coincident, dim3(nblocks(n, 256)), dim3(256), 0, s, sorted_keys, perm, pts, n, flag);
 }
 
 void launch_sort(void* temp, size_t temp_bytes, const uint64_t* kin, uint64_t* kout, const int* vin, int* vout,
