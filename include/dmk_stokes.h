@@ -193,6 +193,9 @@ typedef struct {
     /* spectral Ewald plans: grid points per dimension M, mode bound K
      * (|kappa_i| <= K), gridding kernel width in grid points; levels = L + 1 */
     int ewald_grid, ewald_modes, ewald_width;
+    /* 1 when no two distinct points coincide (found at plan time): the near
+     * field then skips pairs at r = 0 and adds the self term per target */
+    int no_coincident;
 } dmk_plan_info;
 
 /*

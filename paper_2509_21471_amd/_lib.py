@@ -62,7 +62,7 @@ class PlanInfo(ctypes.Structure):
                 ("plan_phase_ms", ctypes.c_double * 6), ("near_lanes", ctypes.c_int), ("precision", ctypes.c_int),
                 ("window", ctypes.c_int), ("sigma", ctypes.c_double), ("kernel", ctypes.c_int),
                 ("method", ctypes.c_int), ("ewald_grid", ctypes.c_int), ("ewald_modes", ctypes.c_int),
-                ("ewald_width", ctypes.c_int)]
+                ("ewald_width", ctypes.c_int), ("no_coincident", ctypes.c_int)]
 
     def as_dict(self):
         d = {}

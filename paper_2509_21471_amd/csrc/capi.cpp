@@ -1998,6 +1998,7 @@ int dmk_stokes_plan_info(dmk_plan_t plan, dmk_plan_info* info)
     info->n_leaves = (int64_t)P.leaf_box.size();
     info->n_nonempty_boxes = P.nf;
     info->n_nonempty_leaves = P.nleaf;
+    info->no_coincident = P.no_coincident ? 1 : 0;
     info->near_pairs = P.near_listed;
     info->n_senders = P.nsend;
     info->n_receivers = P.nrecv;
