@@ -44,41 +44,85 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t* __restri
     hist[(size_t)threadIdx.x * ntile + blockIdx.x] = h[threadIdx.x];
 }
 
-// in-place exclusive scan of m counters by one block of 1024 threads
-__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* __restrict__ a, int64_t m)
+// exclusive scan of the 256-thread block's values; *total receives the sum
+__device__ inline uint32_t block_scan_256(uint32_t v, uint32_t* wsum, uint32_t* total)
 {
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t seg = (m + 1023) / 1024;
-    const int64_t b = t * seg, e = std::min<int64_t>(m, b + seg);
-    uint32_t s = 0;
-    for (int64_t i = b; i < e; ++i)
-        s += a[i];
-    part[t] = s;
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (l >= off)
+            x += y;
+    }
+    if (l == 63)
+        wsum[w] = x;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = t >= off ? part[t - off] : 0u;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    uint32_t before = 0;
+    for (int k = 0; k < w; ++k)
+        before += wsum[k];
+    *total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    return before + x - v;
+}
+
+// in-place exclusive scan of m counters by one block, in coalesced chunks
+__global__ __launch_bounds__(256) void k_scan_u32(uint32_t* __restrict__ a, int64_t m)
+{
+    __shared__ uint32_t wsum[4];
+    uint32_t carry = 0;
+    for (int64_t b = 0; b < m; b += 256) {
+        const int64_t i = b + threadIdx.x;
+        const uint32_t v = i < m ? a[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_scan_256(v, wsum, &tot);
+        if (i < m)
+            a[i] = carry + ex;
+        carry += tot;
     }
-    uint32_t run = part[t] - s;
-    for (int64_t i = b; i < e; ++i) {
-        const uint32_t v = a[i];
-        a[i] = run;
-        run += v;
+}
+
+// the radix histograms [digit][tile]: block d scans digit d's tiles in place
+// and writes the digit's total
+__global__ __launch_bounds__(256) void k_rs_scan_digit(uint32_t* __restrict__ hist, int ntile,
+                                                      uint32_t* __restrict__ dtot)
+{
+    __shared__ uint32_t wsum[4];
+    uint32_t* h = hist + (size_t)blockIdx.x * ntile;
+    uint32_t carry = 0;
+    for (int b = 0; b < ntile; b += 256) {
+        const int i = b + threadIdx.x;
+        const uint32_t v = i < ntile ? h[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_scan_256(v, wsum, &tot);
+        if (i < ntile)
+            h[i] = carry + ex;
+        carry += tot;
     }
+    if (threadIdx.x == 0)
+        dtot[blockIdx.x] = carry;
+}
+
+// digit totals -> digit offsets (exclusive), one block of 256
+__global__ __launch_bounds__(256) void k_rs_scan_totals(uint32_t* __restrict__ dtot)
+{
+    __shared__ uint32_t wsum[4];
+    const uint32_t v = dtot[threadIdx.x];
+    uint32_t tot;
+    const uint32_t ex = block_scan_256(v, wsum, &tot);
+    dtot[threadIdx.x] = ex;
 }
 
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __restrict__ kin,
                                                           const int* __restrict__ vin, int64_t n, int shift,
-                                                          const uint32_t* __restrict__ hist, int ntile,
+                                                          const uint32_t* __restrict__ hist,
+                                                          const uint32_t* __restrict__ doff, int ntile,
                                                           uint64_t* __restrict__ kout, int* __restrict__ vout)
 {
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[4][256];
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
-    base[t] = hist[(size_t)t * ntile + blockIdx.x];
+    base[t] = doff[t] + hist[(size_t)t * ntile + blockIdx.x];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
         wcnt[k][t] = 0;
@@ -177,6 +221,7 @@ hipError_t radix_sort(char* temp, const uint64_t* kin, const int* vin, uint64_t*
     int* va = reinterpret_cast<int*>(kb + n);
     int* vb = va + n;
     uint32_t* hist = reinterpret_cast<uint32_t*>(vb + n + (n & 1));
+    uint32_t* doff = hist + (size_t)256 * ntile;
     const int passes = std::max(1, (bits + 7) / 8);
     const uint64_t* ksrc = kin;
     const int* vsrc = vin;
@@ -185,9 +230,10 @@ hipError_t radix_sort(char* temp, const uint64_t* kin, const int* vin, uint64_t*
         uint64_t* kd = p == passes - 1 ? kout : ((p & 1) ? kb : ka);
         int* vd = p == passes - 1 ? vout : ((p & 1) ? vb : va);
         hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntile), dim3(kRsThreads), 0, s, ksrc, n, 8 * p, hist, (int)ntile);
-        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, hist, (int64_t)256 * ntile);
+        hipLaunchKernelGGL(k_rs_scan_digit, dim3(256), dim3(256), 0, s, hist, (int)ntile, doff);
+        hipLaunchKernelGGL(k_rs_scan_totals, dim3(1), dim3(256), 0, s, doff);
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntile), dim3(kRsThreads), 0, s, ksrc, vsrc, n, 8 * p, hist,
-                           (int)ntile, kd, vd);
+                           doff, (int)ntile, kd, vd);
         ksrc = kd;
         vsrc = vd;
     }
@@ -197,7 +243,7 @@ hipError_t radix_sort(char* temp, const uint64_t* kin, const int* vin, uint64_t*
 size_t rs_temp_bytes(int64_t n)
 {
     return (size_t)n * 2 * sizeof(uint64_t) + (size_t)(2 * n + 2) * sizeof(int) +
-           (size_t)256 * rs_tiles(std::max<int64_t>(n, 1)) * sizeof(uint32_t) + 256;
+           (size_t)256 * (rs_tiles(std::max<int64_t>(n, 1)) + 1) * sizeof(uint32_t) + 256;
 }
 
 // ---- octree ------------------------------------------------------------------------
@@ -925,8 +971,8 @@ int build_tree_device(const uint64_t* keys, const int64_t* d_off, int np, int64_
         if (!onear || !oinc || !pnear || !pinc)
             return fail_oom();
         hipLaunchKernelGGL(k_list_counts, dim3(kGrid), dim3(kBlk), 0, s, D, LD, onear, oinc);
-        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, onear, (int64_t)nb);
-        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, s, oinc, (int64_t)nb);
+        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(256), 0, s, onear, (int64_t)nb);
+        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(256), 0, s, oinc, (int64_t)nb);
         hipLaunchKernelGGL(k_list_pack, dim3(kGrid), dim3(kBlk), 0, s, D, LD, onear, oinc, pnear, pinc);
         // download
         std::vector<uint64_t> key(nb);
