@@ -125,6 +125,7 @@ def batched_variant(dev, parity: bool) -> dict:
     tol = 1e-6
     tune = dmk.autotune(xd, tol=tol, precision=dmk.PREC_MIXED, offsets=off)
     leaf, lanes = tune["leaf_size"], tune["near_lanes"]
+    shape = {"stage_rows": tune["stage_rows"], "eval_points": tune["eval_points"]}
     res = {"workload": "batch_256", "n_problems": len(probs), "n": n, "tol": tol, "autotuned": tune,
            "leaf_policy": "every plan (batched and separate) uses the autotuned leaf size and lane split"}
     xs = [xd[off[b]:off[b + 1]] for b in range(len(probs))]
@@ -132,13 +133,13 @@ def batched_variant(dev, parity: bool) -> dict:
     outs = [torch.empty_like(t) for t in fs]
 
     def batched_step(prec):
-        p = dmk.Plan(xd, tol=tol, precision=prec, offsets=off, leaf_size=leaf, near_lanes=lanes)
+        p = dmk.Plan(xd, tol=tol, precision=prec, offsets=off, leaf_size=leaf, near_lanes=lanes, **shape)
         p.eval(fd, out)
         return p
 
     def separate_steps(prec):
         for b in range(len(probs)):
-            p = dmk.Plan(xs[b], tol=tol, precision=prec, leaf_size=leaf, near_lanes=lanes)
+            p = dmk.Plan(xs[b], tol=tol, precision=prec, leaf_size=leaf, near_lanes=lanes, **shape)
             p.eval(fs[b], outs[b])
             p.close()
 
@@ -167,7 +168,7 @@ def batched_variant(dev, parity: bool) -> dict:
     evals = {}
     for graph in (False, True):
         p = dmk.Plan(xd, tol=tol, precision=dmk.PREC_MIXED, offsets=off, leaf_size=leaf, near_lanes=lanes,
-                     graph=graph)
+                     graph=graph, **shape)
         for _ in range(2):
             p.eval(fd, out)
         torch.cuda.synchronize()
@@ -259,6 +260,58 @@ def multi_rhs_variant(args, dev, parity: bool) -> dict:
           f"{res['fp64']['rhs_batch_8']['eval_ms']:.1f} ms for {k} vectors (unbatched fp64 "
           f"{res['fp64']['rhs_batch_1']['eval_ms']:.1f} ms)", file=sys.stderr, flush=True)
     del fd, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def uniform_1e4_variant(args, dev, parity: bool) -> dict:
+    """10^4 uniform points at 1e-6 (a small problem, where launches rather
+    than kernels set the evaluation time): plan + eval per step, evaluation
+    alone with eager launches and with hipGraph replay, and the error against
+    the direct sum at every target."""
+    import torch
+
+    import paper_2509_21471_amd as dmk
+    import workloads
+    name = "uniform_1e4"
+    cfg = workloads.CONFIGS[name]
+    x, f = workloads.config(name)
+    n = x.shape[0]
+    xd = torch.from_numpy(x).to(dev)
+    fd = torch.from_numpy(f).to(dev)
+    out = torch.empty_like(fd)
+    reps = 50
+    res = {"workload": name, "n": n, "tol": cfg["tol"], "precision": "fp64"}
+    for _ in range(3):
+        dmk.Plan(xd, tol=cfg["tol"]).eval(fd, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        p = dmk.Plan(xd, tol=cfg["tol"])
+        p.eval(fd, out)
+        p.close()
+    torch.cuda.synchronize()
+    res["ms_per_step"] = (time.perf_counter() - t0) * 1e3 / reps
+    res["targets_per_s"] = n / (res["ms_per_step"] * 1e-3)
+    for graph in (False, True):
+        p = dmk.Plan(xd, tol=cfg["tol"], graph=graph)
+        for _ in range(3):
+            p.eval(fd, out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            p.eval(fd, out)
+        torch.cuda.synchronize()
+        res["eval_graph_ms" if graph else "eval_eager_ms"] = (time.perf_counter() - t0) * 1e3 / reps
+        u = out.cpu().numpy()
+        p.close()
+    res["graph_speedup"] = res["eval_eager_ms"] / res["eval_graph_ms"]
+    if parity:
+        import oracle
+        res["rel_l2_all_targets"] = oracle.rel_l2(u, oracle.direct(x, f))
+    print(f"# uniform_1e4: {res['ms_per_step']:.2f} ms/step, eval eager {res['eval_eager_ms']:.3f} ms, "
+          f"graph {res['eval_graph_ms']:.3f} ms", file=sys.stderr, flush=True)
+    del xd, fd, out
     torch.cuda.empty_cache()
     return res
 
@@ -414,7 +467,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes three times (the "
                          "reference kernel for scaling HBM byte counters) and exit")
-    ap.add_argument("--only", choices=["spectral_ewald", "multi_rhs", "batched", "clusters_4e6"], default=None,
+    ap.add_argument("--only", choices=["spectral_ewald", "multi_rhs", "batched", "clusters_4e6", "uniform_1e4"],
+                    default=None,
                     help="run only this variant and print its JSON record (for profiling; not the benchmark line)")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -426,7 +480,8 @@ def main():
         fn = {"spectral_ewald": lambda: ewald_variant(args, dev, not args.no_parity),
               "multi_rhs": lambda: multi_rhs_variant(args, dev, not args.no_parity),
               "batched": lambda: batched_variant(dev, not args.no_parity),
-              "clusters_4e6": lambda: clusters_4e6_variant(args, dev, not args.no_parity)}[args.only]
+              "clusters_4e6": lambda: clusters_4e6_variant(args, dev, not args.no_parity),
+              "uniform_1e4": lambda: uniform_1e4_variant(args, dev, not args.no_parity)}[args.only]
         print(json.dumps({"variant": args.only, **fn()}), flush=True)
         return
 
@@ -457,20 +512,26 @@ def main():
     print(f"# input ready: {args.config} n={n} tol={tol}", file=sys.stderr, flush=True)
 
     leaf, lanes = args.leaf_size, args.near_lanes
+    rows, pts = 0, 0
     tuned = None
     if not args.no_autotune and leaf == 0 and lanes == 0:
-        # outside the timed region: picks the leaf size and near-field lane split
+        # outside the timed region: picks the leaf size, near-field lane split and tile shapes
         tuned = dmk.autotune(xd, periodic=periodic, tol=tol)
         leaf, lanes = tuned["leaf_size"], tuned["near_lanes"]
-        print(f"# autotuned: leaf {leaf}, lanes {lanes} ({tuned['ms']:.1f} ms)", file=sys.stderr, flush=True)
+        rows, pts = tuned["stage_rows"], tuned["eval_points"]
+        print(f"# autotuned: leaf {leaf}, lanes {lanes}, stage rows {rows}, eval points {pts} ({tuned['ms']:.1f} ms)",
+              file=sys.stderr, flush=True)
 
     nvd = None  # stresslet orientation vectors, made when the stresslet variant runs
 
     def make_plan(prec, window=0, leaf_size=None, near_lanes=None, kernel=0, ptol=None):
+        # the tuned tile shapes go with the tuned leaf size and tolerance only
+        tuned_shape = leaf_size is None and ptol is None and window == 0 and kernel == 0
         return dmk.Plan(xd, periodic=periodic, tol=tol if ptol is None else ptol,
                         leaf_size=leaf if leaf_size is None else leaf_size,
                         timing=True, near_lanes=lanes if near_lanes is None else near_lanes, precision=prec,
-                        concurrent=True, window=window, kernel=kernel)
+                        concurrent=True, window=window, kernel=kernel,
+                        stage_rows=rows if tuned_shape else 0, eval_points=pts if tuned_shape else 0)
 
     def run(p, kernel):
         if kernel == dmk.KERNEL_STRESSLET:
@@ -546,7 +607,7 @@ def main():
         "config": {"workload": args.config, "n": n, "kind": cfg["kind"], "sigma": cfg["sigma"],
                    "periodic": periodic, "tol": tol, "precision": args.precision, "step": "plan+eval",
                    "leaf_size": info["leaf_size"], "near_lanes": info["near_lanes"],
-                   "autotuned": tuned is not None},
+                   "stage_rows": rows, "eval_points": pts, "autotuned": tuned is not None},
         "roofline": {"bound": "alu", "kernel": "k_near", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
                      "traffic": traffic, "traffic_unit": "bytes/launch",
@@ -655,6 +716,7 @@ def main():
                               "multi_rhs": multi_rhs_variant(args, dev, not args.no_parity),
                               "batched": batched_variant(dev, not args.no_parity),
                               "clusters_4e6": clusters_4e6_variant(args, dev, not args.no_parity),
+                              "uniform_1e4": uniform_1e4_variant(args, dev, not args.no_parity),
                               "spectral_ewald": ewald_variant(args, dev, not args.no_parity)}
         if stress is not None:
             result["variants"]["stresslet"] = stress

@@ -123,6 +123,12 @@ typedef struct {
     int window;           /* dmk_window (0 = prolate) */
     int kernel;           /* dmk_kernel (0 = Stokeslet) */
     int method;           /* dmk_method (0 = DMK) */
+    int stage_rows;       /* rows per workgroup of the separable proxy / plane-wave stages:
+                             16, 32 or 64; 0 = chosen per stage by its LDS footprint
+                             (a value a stage cannot take falls back to that choice) */
+    int eval_points;      /* points per workgroup of the far-field evaluation at the
+                             points: 128 or 256 (256 only for p <= 16, 23, 30); 0 = the
+                             largest that fits */
 } dmk_opts;
 
 /* record HIP events around each phase of dmk_stokes_eval (read back with
@@ -283,19 +289,22 @@ int dmk_stokes_eval_stresslet(dmk_plan_t plan, const double* forces, const doubl
                               double* velocities);
 
 /*
- * Autotuner: picks the leaf size (maximum points per leaf) and the near-field
- * lane split for this workload by timing plan + evaluation on the caller's
+ * Autotuner: picks the leaf size (maximum points per leaf), the near-field
+ * lane split and the tile shapes of the far-field kernels (stage_rows,
+ * eval_points) for this workload by timing plan + evaluation on the caller's
  * points.  Leaf sizes 0.5, 0.75, 1, 1.35, 1.8 and 2.4 times the starting size
  * (opts->leaf_size, else the tolerance's default) are tried with the starting
- * lane split, then 2 and 8 lanes at the best size; each trial keeps the
- * fastest of three runs.  The choice is cached per process for the workload class
+ * lane split, then 2 and 8 lanes at the best size, then stage rows 16, 32 and
+ * 64 and 128 / 256 evaluation points at the best size and split; each trial
+ * keeps the fastest of three runs.  The choice is cached per process for the workload class
  * (n and n_problems to the nearest power of two, periodicity, tol, precision,
  * n_rhs, q, p): a later call for the same class returns at once.
  *   points, n                as dmk_stokes_plan_ex (device points)
  *   offsets, n_problems      as dmk_stokes_plan_batch, or offsets = NULL for one problem
  *   opts                     starting options (may be NULL); copied into *tuned
  *   n_rhs                    force vectors per evaluation to tune for (1..64)
- *   tuned                    receives opts with leaf_size and near_lanes set
+ *   tuned                    receives opts with leaf_size, near_lanes, stage_rows and
+ *                            eval_points set
  *   best_ms                  receives the best trial's plan + eval milliseconds (may be NULL)
  * Allocates and frees two (n_rhs, n, 3) device buffers; synchronises opts->stream.
  */

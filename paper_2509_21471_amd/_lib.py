@@ -46,7 +46,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("leaf_size", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("mem_cap_bytes", ctypes.c_size_t), ("flags", ctypes.c_int), ("near_lanes", ctypes.c_int),
                 ("q", ctypes.c_int), ("p", ctypes.c_int), ("rhs_batch", ctypes.c_int), ("window", ctypes.c_int),
-                ("kernel", ctypes.c_int), ("method", ctypes.c_int)]
+                ("kernel", ctypes.c_int), ("method", ctypes.c_int), ("stage_rows", ctypes.c_int),
+                ("eval_points", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -221,7 +222,7 @@ class Plan:
                  near_lanes: int = 0, q: int = 0, p: int = 0, rhs_batch: int = 0, concurrent: bool = False,
                  offsets=None, graph: bool = False, targets=None, window: int = 0,
                  kernel: int = KERNEL_STOKESLET, method: int = METHOD_DMK, leaf_order: bool = True,
-                 host_tree: bool = False):
+                 host_tree: bool = False, stage_rows: int = 0, eval_points: int = 0):
         """offsets (host int sequence, n_problems + 1 entries) makes a batched
         plan over independent problems (dmk_stokes_plan_batch); targets (device
         (m,3)) makes a plan evaluating the sums at a separate target set
@@ -242,7 +243,7 @@ class Plan:
                     | (FLAG_GRAPH if graph else 0) | (0 if leaf_order else FLAG_MORTON_ORDER)
                     | (FLAG_HOST_TREE if host_tree else 0),
                     int(near_lanes), int(q), int(p), int(rhs_batch), int(window), int(kernel),
-                    int(method))
+                    int(method), int(stage_rows), int(eval_points))
         h = ctypes.c_void_p()
         if targets is not None:
             if offsets is not None:
@@ -338,11 +339,12 @@ class Plan:
 
 def autotune(points, periodic: bool = False, tol: float = 1e-6, precision: int = PREC_FP64, offsets=None,
              n_rhs: int = 1, leaf_size: int = 0, stream=None) -> dict:
-    """dmk_stokes_autotune: the leaf size and near-field lane split to pass to
-    Plan for this workload, and the best trial's plan + eval milliseconds."""
+    """dmk_stokes_autotune: the leaf size, near-field lane split and far-field
+    tile shapes (stage_rows, eval_points) to pass to Plan for this workload, and
+    the best trial's plan + eval milliseconds."""
     pts = _dev_f64(points)
     n = int(pts.shape[0])
-    opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), 0, 0, 0, 0, 0, 0, 0, 0)
+    opts = Opts(int(precision), int(leaf_size), _stream_ptr(stream), 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0)
     tuned = Opts()
     ms = ctypes.c_double()
     off = None
@@ -354,7 +356,8 @@ def autotune(points, periodic: bool = False, tol: float = 1e-6, precision: int =
                                      None if off is None else off.ctypes.data_as(ctypes.c_void_p), nprob, 3,
                                      int(bool(periodic)), float(tol), ctypes.byref(opts), int(n_rhs),
                                      ctypes.byref(tuned), ctypes.byref(ms)))
-    return {"leaf_size": tuned.leaf_size, "near_lanes": tuned.near_lanes, "ms": ms.value}
+    return {"leaf_size": tuned.leaf_size, "near_lanes": tuned.near_lanes, "stage_rows": tuned.stage_rows,
+            "eval_points": tuned.eval_points, "ms": ms.value}
 
 
 def residual_sum(targets, sources, forces, r_lambda: float, tol: float, stream=None):

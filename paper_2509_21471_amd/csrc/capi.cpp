@@ -311,6 +311,8 @@ struct dmk_plan_s {
     bool leaf_order = true;           // compact groups inside leaves (near-field pruning)
     bool host_tree = false;           // octree and lists built on the host (reference construction)
     bool near_refine = true;          // Newton step on the near field's reciprocal square root
+    int stage_rows = 0;               // requested rows per stage tile (0 = by LDS footprint)
+    int eval_pts = 0;                 // points per leaf-evaluation block
     bool no_coincident = false;       // no two distinct points coincide (near field skips r = 0 pairs)
     int h_coincident = 1;             // host copy of the plan-time coincidence flag
     hipStream_t cap_stream = nullptr;
@@ -370,6 +372,10 @@ int validate_common(int dim, double tol, const dmk_opts* opts)
             return fail(DMK_ERR_ARG, "rhs_batch must be 0, 1, 2, 4 or 8");
         if (opts->p != 0 && !dmk::p_supported(opts->p))
             return fail(DMK_ERR_ARG, "p must be 0 or one of 11, 12, 14, 16, 20, 22, 23, 26, 28, 30, 33, 36, 40, 43, 44, 48");
+        if (opts->stage_rows != 0 && opts->stage_rows != 16 && opts->stage_rows != 32 && opts->stage_rows != 64)
+            return fail(DMK_ERR_ARG, "stage_rows must be 0, 16, 32 or 64");
+        if (opts->eval_points != 0 && opts->eval_points != 128 && opts->eval_points != 256)
+            return fail(DMK_ERR_ARG, "eval_points must be 0, 128 or 256");
         if (opts->window != DMK_WINDOW_PROLATE && opts->window != DMK_WINDOW_GAUSSIAN)
             return fail(DMK_ERR_ARG, "unknown window");
         if (opts->window == DMK_WINDOW_GAUSSIAN && tol < 1e-6 * (1 - 1e-9))
@@ -423,6 +429,7 @@ void stage(dmk_plan_t P, int mode, int io, const void* X, long xs, const int* xm
     a.child_fid = child_fid;
     a.f32 = P->f32 ? 1 : 0;
     a.ncomp = nc;
+    a.rt_request = P->stage_rows;
     if (P->ck_on) {
         // one chunk of a pipeline: slots [ck0, ck1); the scratch buffers hold
         // only this chunk's rows
@@ -977,8 +984,8 @@ int build_plan(dmk_plan_t P, const double* points)
     for (size_t k = 0; k < hl.size(); ++k) {
         const LeafDesc& d = hl[k];
         const int64_t t0 = P->nsrc < n ? hl_src[k].end : d.start;
-        for (int64_t s0 = t0; s0 < d.end; s0 += eval_chunk_points(P->prm.p))
-            ech.push_back(EvalChunk{d.fid, s0, std::min<int64_t>(s0 + eval_chunk_points(P->prm.p), d.end)});
+        for (int64_t s0 = t0; s0 < d.end; s0 += P->eval_pts)
+            ech.push_back(EvalChunk{d.fid, s0, std::min<int64_t>(s0 + P->eval_pts, d.end)});
     }
     P->n_echunk = (int)ech.size();
     P->echunks = P->mem.alloc<EvalChunk>(ech.size());
@@ -1342,7 +1349,7 @@ void far_field(dmk_plan_t P, int r, bool record)
     }
     mark(7);
     // far field at the points
-    launch_leaf_eval(p, P->echunks, P->n_echunk, P->Ltab, P->V, n, u, P->f32, st);
+    launch_leaf_eval(p, P->eval_pts, P->echunks, P->n_echunk, P->Ltab, P->V, n, u, P->f32, st);
     mark(8);
 }
 
@@ -1637,7 +1644,9 @@ int create_plan(const double* points, const std::vector<int64_t>& offsets, int d
         P->use_graph = (opts->flags & DMK_FLAG_GRAPH) != 0;
         P->leaf_order = (opts->flags & DMK_FLAG_MORTON_ORDER) == 0;
         P->host_tree = (opts->flags & DMK_FLAG_HOST_TREE) != 0;
+        P->stage_rows = opts->stage_rows;
     }
+    P->eval_pts = dmk::eval_chunk_points(P->prm.p, opts ? opts->eval_points : 0);
     if (hipEventCreateWithFlags(&P->done, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         delete P;
@@ -1896,6 +1905,8 @@ int dmk_stokes_autotune(const double* points, int64_t n, const int64_t* offsets,
             *tuned = base;
             tuned->leaf_size = it->second.first.leaf_size;
             tuned->near_lanes = it->second.first.near_lanes;
+            tuned->stage_rows = it->second.first.stage_rows;
+            tuned->eval_points = it->second.first.eval_points;
             if (best_ms)
                 *best_ms = it->second.second;
             return DMK_OK;
@@ -1912,10 +1923,14 @@ int dmk_stokes_autotune(const double* points, int64_t n, const int64_t* offsets,
     (void)hipMemset(f, 0, bytes);
     hipStream_t st = (hipStream_t)base.stream;
     // one trial: plan + evaluation, wall time (the plan part includes its host work)
+    const int p_used = base.p > 0 ? base.p : prm.p;
+    int best_rows = base.stage_rows, best_pts = dmk::eval_chunk_points(p_used, base.eval_points);
     auto trial = [&](int leaf, int lanes, double* ms) {
         dmk_opts o = base;
         o.leaf_size = leaf;
         o.near_lanes = lanes;
+        o.stage_rows = best_rows;
+        o.eval_points = best_pts;
         double best = 1e300;
         for (int rep = 0; rep < 3; ++rep) {
             (void)hipStreamSynchronize(st);
@@ -1960,6 +1975,35 @@ int dmk_stokes_autotune(const double* points, int64_t n, const int64_t* offsets,
             best_lanes = lanes;
         }
     }
+    // tile shapes of the far-field kernels at the chosen leaf size and split
+    for (int rows : {16, 32, 64}) {
+        if (rc != DMK_OK)
+            break;
+        if (rows == best_rows)
+            continue;
+        const int keep = best_rows;
+        best_rows = rows;
+        double ms = 0;
+        rc = trial(best_leaf, best_lanes, &ms);
+        if (rc == DMK_OK && ms < best)
+            best = ms;
+        else
+            best_rows = keep;
+    }
+    for (int pts : {128, 256}) {
+        if (rc != DMK_OK)
+            break;
+        if (pts == best_pts || dmk::eval_chunk_points(p_used, pts) != pts)
+            continue;
+        const int keep = best_pts;
+        best_pts = pts;
+        double ms = 0;
+        rc = trial(best_leaf, best_lanes, &ms);
+        if (rc == DMK_OK && ms < best)
+            best = ms;
+        else
+            best_pts = keep;
+    }
     (void)hipFree(f);
     (void)hipFree(v);
     if (rc != DMK_OK)
@@ -1967,6 +2011,8 @@ int dmk_stokes_autotune(const double* points, int64_t n, const int64_t* offsets,
     *tuned = base;
     tuned->leaf_size = best_leaf;
     tuned->near_lanes = best_lanes;
+    tuned->stage_rows = best_rows;
+    tuned->eval_points = best_pts;
     if (opts)
         tuned->flags = opts->flags;
     if (best_ms)

@@ -550,21 +550,25 @@ __global__ __launch_bounds__(256) void k_lagrange_table(const LeafDesc* __restri
 // of one leaf (16 per wave); the z-slab of V sits in LDS.
 // points per leaf-evaluation block (4 lanes per point): 256 where the kernel
 // fits the 128 registers of a 1024-thread block, else 128
-template <int P>
-struct EvalCfg {
-    static constexpr int PTS = (P <= 16 || P == 23 || P == 30) ? 256 : 128;
-};
-int eval_chunk_points(int p) { return (p <= 16 || p == 23 || p == 30) ? 256 : 128; }
+// 256 points per block only where the kernel fits the registers of a
+// 1024-thread block
+constexpr bool eval256_fits(int p) { return p <= 16 || p == 23 || p == 30; }
+int eval_chunk_points(int p, int request)
+{
+    if (request == 128 || !eval256_fits(p))
+        return 128;
+    return 256;
+}
 
-template <int P, typename S>
-__global__ __launch_bounds__(EvalCfg<P>::PTS * 4) void k_leaf_eval(const EvalChunk* __restrict__ chunks, int nchunk,
+template <int P, typename S, int PTS>
+__global__ __launch_bounds__(PTS * 4) void k_leaf_eval(const EvalChunk* __restrict__ chunks, int nchunk,
                                                               const double* __restrict__ Ltab,
                                                               const S* __restrict__ V, int64_t n,
                                                               double* __restrict__ u)
 {
     constexpr int PA = MCfg<P>::PA, NK = MCfg<P>::NK, NT = MCfg<P>::NT, RS = MCfg<P>::RS;
     constexpr int PB = 16 * NT;
-    constexpr int NTH = EvalCfg<P>::PTS * 4;
+    constexpr int NTH = PTS * 4;
     constexpr int NPRE = (3 * P * P + NTH - 1) / NTH;  // slab elements per thread
     __shared__ double slab[2][3][PB][RS];               // double-buffered c-slabs
     const EvalChunk C = chunks[blockIdx.x];
@@ -670,15 +674,15 @@ __global__ __launch_bounds__(EvalCfg<P>::PTS * 4) void k_leaf_eval(const EvalChu
 // 4 (l/16) + r of its 16 x 16 tile in register r of lane l.
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 
-template <int P>
-__global__ __launch_bounds__(EvalCfg<P>::PTS * 4) void k_leaf_eval32(const EvalChunk* __restrict__ chunks,
+template <int P, int PTS>
+__global__ __launch_bounds__(PTS * 4) void k_leaf_eval32(const EvalChunk* __restrict__ chunks,
                                                                      int nchunk, const float* __restrict__ Ltab,
                                                                      const float* __restrict__ V, int64_t n,
                                                                      double* __restrict__ u)
 {
     constexpr int PA = MCfg<P>::PA, NK = MCfg<P>::NK, NT = MCfg<P>::NT, RS = MCfg<P>::RS;
     constexpr int PB = 16 * NT;
-    constexpr int NTH = EvalCfg<P>::PTS * 4;
+    constexpr int NTH = PTS * 4;
     constexpr int NPRE = (3 * P * P + NTH - 1) / NTH;  // slab elements per thread
     __shared__ float slab[2][3][PB][RS];                // double-buffered c-slabs
     const EvalChunk C = chunks[blockIdx.x];
@@ -1188,20 +1192,31 @@ void launch_anterp(int p, int nc, const LeafDesc* leaves, int nleaf, const void*
 #undef L_ANTERP_NC
 }
 
-void launch_leaf_eval(int p, const EvalChunk* chunks, int nchunk, const void* Ltab, const void* V, int64_t n,
-                      double* u, bool f32, hipStream_t s)
+void launch_leaf_eval(int p, int pts, const EvalChunk* chunks, int nchunk, const void* Ltab, const void* V,
+                      int64_t n, double* u, bool f32, hipStream_t s)
 {
     if (nchunk == 0)
         return;
-#define L_EVAL(P)                                                                                               \
-    if (f32)                                                                                                    \
-        hipLaunchKernelGGL((k_leaf_eval32<P>), dim3(nchunk), dim3(EvalCfg<P>::PTS * 4), 0, s, chunks, nchunk,   \
-                           (const float*)Ltab, (const float*)V, n, u);                                          \
-    else                                                                                                        \
-        hipLaunchKernelGGL((k_leaf_eval<P, double>), dim3(nchunk), dim3(EvalCfg<P>::PTS * 4), 0, s, chunks,     \
-                           nchunk, (const double*)Ltab, (const double*)V, n, u)
+#define L_EVAL_T(P, PTS)                                                                                    \
+    if (f32)                                                                                                \
+        hipLaunchKernelGGL((k_leaf_eval32<P, PTS>), dim3(nchunk), dim3(PTS * 4), 0, s, chunks, nchunk,      \
+                           (const float*)Ltab, (const float*)V, n, u);                                      \
+    else                                                                                                    \
+        hipLaunchKernelGGL((k_leaf_eval<P, double, PTS>), dim3(nchunk), dim3(PTS * 4), 0, s, chunks, nchunk, \
+                           (const double*)Ltab, (const double*)V, n, u)
+#define L_EVAL(P)                                      \
+    if constexpr (eval256_fits(P)) {                   \
+        if (pts == 256) {                              \
+            L_EVAL_T(P, 256);                          \
+        } else {                                       \
+            L_EVAL_T(P, 128);                          \
+        }                                              \
+    } else {                                           \
+        L_EVAL_T(P, 128);                              \
+    }
     DMK_P_DISPATCH(p, L_EVAL)
 #undef L_EVAL
+#undef L_EVAL_T
 }
 
 // ---- separable tensor stages ---------------------------------------------------
@@ -1424,7 +1439,15 @@ static void stage_ni(const StageArgs& a, hipStream_t s)
             std::max((size_t)a.Nin * rt * (Tr::xc ? 2 : 1), (size_t)a.Nout * rt * (Tr::yc ? 2 : 1));
         return (size_t)a.Nh * a.Kh * sizeof(double2) + tile * sizeof(double);
     };
-    const int rt = lds(64) > kStageLdsSplit16 ? 16 : (lds(64) > kStageLdsSplit ? 32 : 64);
+    int rt = lds(64) > kStageLdsSplit16 ? 16 : (lds(64) > kStageLdsSplit ? 32 : 64);
+    // a requested tile height where the compiled accumulator counts and the
+    // LDS allow it (NI <= 4 at 16 rows, <= 8 at 32, <= 12 at 64)
+    if (a.rt_request == 16 || a.rt_request == 32 || a.rt_request == 64) {
+        const int r = a.rt_request;
+        const int nir = (a.Nh + 256 / r - 1) / (256 / r);
+        if (nir <= (r == 16 ? 4 : r == 32 ? 8 : 12) && lds(r) <= 150 * 1024)
+            rt = r;
+    }
     const size_t shm = lds(rt);
     const int ni = (a.Nh + 256 / rt - 1) / (256 / rt);
     // grid.y (slot, component) stays within 65535: large slot counts go in chunks

@@ -101,14 +101,15 @@ void launch_anterp(int p, int nc, const LeafDesc* leaves, int nleaf, const void*
 // far-field value at the points (final interpolation), V z-major V[fid][j][c][b][a]:
 // u[j][i] += sum V L L L, over chunks of at most eval_chunk_points(p) points of
 // one leaf (one block of 4 threads per point)
-int eval_chunk_points(int p);
+// points per block: `request` (128 or 256) where the kernel takes it, else the largest that fits
+int eval_chunk_points(int p, int request = 0);
 struct EvalChunk {
     int fid;
     int64_t start, end;
 };
 // f32: FP32 Ltab and V, contraction over a on FP32 MFMA, the rest FP64
-void launch_leaf_eval(int p, const EvalChunk* chunks, int nchunk, const void* Ltab, const void* V, int64_t n,
-                      double* u, bool f32, hipStream_t s);
+void launch_leaf_eval(int p, int pts, const EvalChunk* chunks, int nchunk, const void* Ltab, const void* V,
+                      int64_t n, double* u, bool f32, hipStream_t s);
 
 // ---- separable tensor stages ------------------------------------------------
 // Every far-field tensor stage contracts the leading axis of a per-(slot,
@@ -145,6 +146,7 @@ struct StageArgs {
     int slot0 = 0;       // first slot of the launch (slots [slot0, nslots))
     int xbase = 0;       // X (without xmap) holds slots [xbase, ...): row slot - xbase
     int ybase = 0;       // the same for Y
+    int rt_request = 0;  // requested rows per tile (16, 32, 64; 0 = by LDS footprint)
 };
 void launch_stage(int mode, int io, const StageArgs& a, hipStream_t s);
 

@@ -111,6 +111,24 @@ def test_multiple_rhs_mixed_precision(dev, n_rhs, batch):
         assert err < 1e-6, (r, err)
 
 
+@pytest.mark.parametrize("rows,pts", [(16, 0), (32, 128), (64, 256), (0, 128)])
+def test_tile_shapes_agree(dev, rows, pts):
+    """Every stage tile height and leaf-evaluation block size the autotuner
+    may pick gives the same sums (the tiles only partition the rows and the
+    points; each output is summed in the same order)."""
+    x, f = workloads.make("clusters", 20000, seed=80, sigma=0.04)
+    u0, _ = _eval(x, f, tol=1e-6, leaf_size=200)
+    u1, _ = _eval(x, f, tol=1e-6, leaf_size=200, stage_rows=rows, eval_points=pts)
+    assert oracle.rel_l2(u1, u0) < 1e-14
+
+
+def test_autotune_reports_tile_shapes(dev):
+    x, _ = workloads.make("uniform", 30000, seed=81)
+    t = _dmk().autotune(_t(x), tol=1e-6)
+    assert t["stage_rows"] in (0, 16, 32, 64) and t["eval_points"] in (128, 256)
+    assert t["leaf_size"] > 0 and t["near_lanes"] in (1, 2, 4, 8)
+
+
 def test_periodic_translation_invariance(dev):
     """A shift of all points modulo the cell changes the tree, not the sum."""
     x, f = workloads.make("periodic", 20000, seed=75)
