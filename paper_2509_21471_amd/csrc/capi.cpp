@@ -252,8 +252,7 @@ struct dmk_plan_s {
     int* send_fid = nullptr;          // sender slot -> fid
     int* recv_fid = nullptr;          // receiver slot -> fid
     dmk::RecvDesc* recv = nullptr;
-    int* e_src = nullptr;
-    int8_t* e_off = nullptr;
+    int* e_pk = nullptr;  // translation entries: 32 * sender slot + offset code
     // near field
     dmk::NearLeaf* nleaves = nullptr;
     dmk::NearEntryDev* nentries = nullptr;
@@ -1017,8 +1016,7 @@ int build_plan(dmk_plan_t P, const double* points)
         HIPCHK(upload(P->lev[l].parent_fid, pf, st));
     }
     // senders / receivers (difference-kernel exchange lists)
-    std::vector<int> send_slot(nb, -1), sfid, slev, rfid, esrc;
-    std::vector<int8_t> eoff;
+    std::vector<int> send_slot(nb, -1), sfid, slev, rfid, epk;
     std::vector<RecvDesc> rd;
     for (int i = 0; i < nb; ++i)
         for (const FarEntry& e : T.incoming[i])
@@ -1033,14 +1031,14 @@ int build_plan(dmk_plan_t P, const double* points)
         RecvDesc r;
         r.slot = (int)rfid.size();
         r.level = T.boxes[i].level;
-        r.ebeg = (int)esrc.size();
+        r.ebeg = (int)epk.size();
         for (const FarEntry& e : T.incoming[i]) {
-            esrc.push_back(send_slot[e.src]);
-            eoff.push_back(e.ox);
-            eoff.push_back(e.oy);
-            eoff.push_back(e.oz);
+            // colleagues only: offsets within one box width, slots below 2^26
+            if (std::abs(e.ox) > 1 || std::abs(e.oy) > 1 || std::abs(e.oz) > 1 || send_slot[e.src] >= (1 << 26))
+                return fail(DMK_ERR_UNSUPPORTED, "translation entry out of range (more than 2^26 senders)");
+            epk.push_back(32 * send_slot[e.src] + 9 * (e.ox + 1) + 3 * (e.oy + 1) + (e.oz + 1));
         }
-        r.eend = (int)esrc.size();
+        r.eend = (int)epk.size();
         rfid.push_back(P->box_fid[i]);
         rd.push_back(r);
     }
@@ -1051,8 +1049,7 @@ int build_plan(dmk_plan_t P, const double* points)
         P->send_level = P->mem.alloc<int>(slev.size());
     P->recv_fid = P->mem.alloc<int>(rfid.size());
     P->recv = P->mem.alloc<RecvDesc>(rd.size());
-    P->e_src = P->mem.alloc<int>(esrc.size());
-    P->e_off = P->mem.alloc<int8_t>(eoff.size());
+    P->e_pk = P->mem.alloc<int>(epk.size());
     // near field: chunks of 64 sorted points per non-empty leaf
     std::vector<int> leaf_cbase(nb, -1);
     std::vector<int64_t> cstart;
@@ -1198,8 +1195,7 @@ int build_plan(dmk_plan_t P, const double* points)
         HIPCHK(upload(P->send_level, slev, st));
     HIPCHK(upload(P->recv_fid, rfid, st));
     HIPCHK(upload(P->recv, rd, st));
-    HIPCHK(upload(P->e_src, esrc, st));
-    HIPCHK(upload(P->e_off, eoff, st));
+    HIPCHK(upload(P->e_pk, epk, st));
     HIPCHK(upload(P->nleaves, nlv, st));
     HIPCHK(upload(P->nentries, nent, st));
     HIPCHK(upload(P->nwork, nwk, st));
@@ -1286,7 +1282,7 @@ void far_field(dmk_plan_t P, int r, bool record)
         launch_stress_symbol(q, n1, P->nsend, P->send_level, P->Phi, P->wdiff, P->Phi3, P->f32, st);
     mark(3);
     // Step 3b: translation with the difference-kernel symbol -> Psi[mz][my][mx]
-    launch_translate(q, n1, P->recv, P->nrecv, P->e_src, P->e_off, stress ? P->Phi3 : P->Phi, P->wdiff, P->Psi,
+    launch_translate(q, n1, P->recv, P->nrecv, P->e_pk, stress ? P->Phi3 : P->Phi, P->wdiff, P->Psi,
                      P->f32, stress, st);
     mark(4);
     // incoming plane waves -> proxy potentials, z-major V[c][b][a]

@@ -1498,14 +1498,18 @@ void launch_stage(int mode, int io, const StageArgs& a, hipStream_t s)
 // (Phi[m_x][m_y][m_z]) and the receiver side z-major (Psi[m_z][m_y][m_x]); a
 // slab of fixed m_y is read as q runs of n1 contiguous modes, transposed in LDS
 // and written as n1 runs of q contiguous modes, so both sides stay coalesced.
+// An entry is packed as 32 * (sender slot) + 9 (o_x + 1) + 3 (o_y + 1) + (o_z + 1)
+// with the colleague offset o in {-1, 0, 1}^3.  Its phase exp(-2 pi i m.o / 3)
+// depends on m only through m mod 3: each thread keeps 2 (m_k mod 3) and reads
+// the phase index from a 2-bit table.
 template <typename S, bool PLAIN>
 __global__ __launch_bounds__(256) void k_translate(int q, int n1, int nparts, int nrecv,
-                                                   const RecvDesc* __restrict__ recv, const int* __restrict__ e_src,
-                                                   const int8_t* __restrict__ e_off,
+                                                   const RecvDesc* __restrict__ recv, const int* __restrict__ e_pk,
                                                    const typename Store<S>::cx* __restrict__ Phi,
                                                    const double* __restrict__ wdiff,
                                                    typename Store<S>::cx* __restrict__ Psi)
 {
+    using cx = typename Store<S>::cx;
     extern __shared__ cplx tile[];  // [3][m_z][m_x] over this block's m_z range
     const int H = q * n1 * n1;
     // Blocks go round-robin over the 8 XCDs; give each XCD a contiguous run
@@ -1527,26 +1531,58 @@ __global__ __launch_bounds__(256) void k_translate(int q, int n1, int nparts, in
     const int m2 = iy - (q - 1);
     const double s3 = 0.86602540378443864676;
     const double lscale = (double)(1ll << rd.level);
+    const int w2 = 2 * (((m2 % 3) + 3) % 3);
+    const size_t H3 = (size_t)3 * H;
     for (int idx = threadIdx.x; idx < NS; idx += blockDim.x) {
         const int m1 = idx / nz;
         const int i3 = z0 + idx - m1 * nz;
         const int m3 = i3 - (q - 1);
-        const size_t mi = ((size_t)m1 * n1 + iy) * n1 + i3;
+        const cx* base = Phi + ((size_t)m1 * n1 + iy) * n1 + i3;
+        const int w1 = 2 * (m1 % 3), w3 = 2 * (((m3 % 3) + 3) % 3);
         double F[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-        for (int e = rd.ebeg; e < rd.eend; ++e) {
-            const int src = e_src[e];
-            const int t = m1 * e_off[3 * e] + m2 * e_off[3 * e + 1] + m3 * e_off[3 * e + 2];
-            const int tm = ((t % 3) + 3) % 3;
-            // exp(-i 2 pi t / 3)
-            const double pr = tm == 0 ? 1.0 : -0.5;
-            const double pi = tm == 0 ? 0.0 : (tm == 1 ? -s3 : s3);
+        cx va[3], vb[3];
+        // sums one entry: F += exp(-2 pi i m.o / 3) v
+        auto add = [&](int pk, const cx (&v)[3]) {
+            const int c = pk & 31;
+            const int sh = w1 * (c / 9 - 1) + w2 * ((c / 3) % 3 - 1) + w3 * (c % 3 - 1) + 12;
+            // (k mod 3) at bits 2k, k = 0..12
+            const int ph = (0x924924 >> sh) & 3;
+            const double pr = ph ? -0.5 : 1.0;
+            const double pi = ph == 0 ? 0.0 : (ph == 1 ? -s3 : s3);
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const typename Store<S>::cx v = Phi[((size_t)src * 3 + j) * H + mi];
-                const double vr = (double)v.x, vi = (double)v.y;
-                F[j][0] += pr * vr - pi * vi;
-                F[j][1] += pr * vi + pi * vr;
+                const double vr = (double)v[j].x, vi = (double)v[j].y;
+                F[j][0] = fma(-pi, vi, fma(pr, vr, F[j][0]));
+                F[j][1] = fma(pi, vr, fma(pr, vi, F[j][1]));
             }
+        };
+        auto load = [&](int pk, cx (&v)[3]) {
+            const cx* ps = base + (size_t)(pk >> 5) * H3;
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                v[j] = ps[(size_t)j * H];
+        };
+        // two entries' loads in flight: each sum waits only for the older
+        // one.  The loop body has no branch and its loads are unconditional
+        // (indices past the end re-read the last entry), so the compiler's
+        // wait before a sum never has to cover the newer loads.
+        const int ne = rd.eend - rd.ebeg;
+        if (ne > 0) {
+            const int* ep = e_pk + rd.ebeg;
+            int pa = ep[0];
+            load(pa, va);
+            int pb = ep[min(1, ne - 1)];
+            load(pb, vb);
+            for (int k = 0; k + 1 < ne; k += 2) {
+                add(pa, va);
+                pa = ep[min(k + 2, ne - 1)];
+                load(pa, va);
+                add(pb, vb);
+                pb = ep[min(k + 3, ne - 1)];
+                load(pb, vb);
+            }
+            if (ne & 1)
+                add(pa, va);
         }
         if (PLAIN) {
             // the symbol was applied on the sending side (stresslet)
@@ -1577,8 +1613,8 @@ __global__ __launch_bounds__(256) void k_translate(int q, int n1, int nparts, in
     }
 }
 
-void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int* e_src, const int8_t* e_off,
-                      const void* Phi, const double* wdiff, void* Psi, bool f32, bool plain, hipStream_t s)
+void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int* e_pk, const void* Phi,
+                      const double* wdiff, void* Psi, bool f32, bool plain, hipStream_t s)
 {
     if (nrecv == 0)
         return;
@@ -1599,8 +1635,8 @@ void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int*
         attr = true;
     }
 #define L_TR(T2, S, PL)                                                                                        \
-    hipLaunchKernelGGL((k_translate<S, PL>), dim3(xcd_grid(total)), dim3(256), lds, s, q, n1, nparts, nrecv, recv, e_src, \
-                       e_off, (const T2*)Phi, wdiff, (T2*)Psi)
+    hipLaunchKernelGGL((k_translate<S, PL>), dim3(xcd_grid(total)), dim3(256), lds, s, q, n1, nparts, nrecv, recv, e_pk, \
+                       (const T2*)Phi, wdiff, (T2*)Psi)
     if (f32) {
         if (plain)
             L_TR(float2, float, true);

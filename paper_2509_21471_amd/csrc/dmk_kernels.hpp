@@ -158,9 +158,10 @@ struct RecvDesc {
 };
 // Phi / Psi hold complex float (f32) or complex double
 // plain: the symbol was applied on the sending side (phases only here)
-void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int* e_src /*sender slot*/,
-                      const int8_t* e_off /*3 per entry*/, const void* Phi, const double* wdiff, void* Psi, bool f32,
-                      bool plain, hipStream_t s);
+// e_pk: one int per entry, 32 * (sender slot) + 9 (o_x + 1) + 3 (o_y + 1) + (o_z + 1)
+// with the sender's offset o from the receiver in box widths, each in {-1, 0, 1}
+void launch_translate(int q, int n1, const RecvDesc* recv, int nrecv, const int* e_pk, const void* Phi,
+                      const double* wdiff, void* Psi, bool f32, bool plain, hipStream_t s);
 // stresslet difference symbol per sender: Phi6[slot][6][H] -> Phi3[slot][3][H] (x-major half spectrum)
 void launch_stress_symbol(int q, int n1, int nsend, const int* send_level, const void* Phi6, const double* wdiff_t,
                           void* Phi3, bool f32, hipStream_t s);
