@@ -1219,6 +1219,11 @@ void launch_leaf_eval(int p, int pts, const EvalChunk* chunks, int nchunk, const
 #undef L_EVAL_T
 }
 
+// x / d for 0 <= x < 2^20 and d >= 1 given inv_d = 1/d (rounded to float):
+// (x + 1/2) / d is at least 1/(2d) from an integer, and the float error is at
+// most about 2^-22 (x / d) < 1/(4d), so truncation gives the exact quotient.
+__device__ inline int div_small(int x, float inv_d) { return (int)(((float)x + 0.5f) * inv_d); }
+
 // ---- separable tensor stages ---------------------------------------------------
 template <int MODE>
 struct StageTraits {
@@ -1256,20 +1261,34 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
     const int nrow = min(RT, R - r0);
     const size_t p3 = (size_t)p * p * p;
     // ---- input slab ----
-    {
+    if (IO == IO_GATHER8) {
+        // the children's 2p x 2p x 2p grid: with e = tid + 256 i the row
+        // rr = tid % RT (= (B, C), B and C in [0, 2p)) is the thread's own and
+        // k = tid / RT + NG i, so the row's child offsets are found once
+        const int rr = tid % RT;
+        const int r = r0 + rr;
+        const int B = div_small(r, 1.0f / (float)(2 * p)), C = r - 2 * p * B;
+        const int bh = B >= p, ch = C >= p;
+        const size_t bc = (size_t)(B - p * bh) * p + (C - p * ch);
+        const int* cf = a.child_fid + slot * 8 + 2 * bh + ch;
+        for (int k = tid / RT; k < Nin; k += NG) {
+            double v0 = 0.0;
+            if (rr < nrow) {
+                const int kh = k >= p;
+                const int f = cf[4 * kh];
+                if (f >= 0)
+                    v0 = (double)((const S*)a.X)[((size_t)f * nc + comp) * p3 + (size_t)(k - p * kh) * p * p + bc];
+            }
+            tile[k * RT + rr] = v0;
+        }
+    } else {
         const size_t xoff = ((size_t)(a.xmap ? a.xmap[slot] : slot - a.xbase) * nc + comp) * a.xstride;
         for (int e = tid; e < Nin * RT; e += 256) {
             const int k = e / RT, rr = e % RT;
             const int r = r0 + rr;
             double v0 = 0.0, v1 = 0.0;
             if (rr < nrow) {
-                if (IO == IO_GATHER8) {
-                    const int B = r / (2 * p), C = r % (2 * p);
-                    const int f = a.child_fid[slot * 8 + 4 * (k / p) + 2 * (B / p) + (C / p)];
-                    if (f >= 0)
-                        v0 = (double)((const S*)a.X)[((size_t)f * nc + comp) * p3 +
-                                                     ((size_t)(k % p) * p + (B % p)) * p + (C % p)];
-                } else if (XE == 2) {
+                if (XE == 2) {
                     const typename Store<S>::cx v = ((const typename Store<S>::cx*)a.X)[xoff + (size_t)k * R + r];
                     v0 = (double)v.x;
                     v1 = (double)v.y;
@@ -1379,13 +1398,15 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
     if (IO == IO_SCATTER8) {
         // rows r = (C, B) of the child grid, output axis A; child (A/p, B/p, C/p)
         S* Yd = (S*)a.Y;
+        const float inv_out = 1.0f / (float)Nout, inv_2p = 1.0f / (float)(2 * p);
         for (int e = tid; e < nrow * Nout; e += 256) {
-            const int rr = e / Nout, A = e % Nout;
+            const int rr = div_small(e, inv_out), A = e - Nout * rr;
             const int r = r0 + rr;
-            const int C = r / (2 * p), B = r % (2 * p);
-            const int f = a.child_fid[slot * 8 + 4 * (A / p) + 2 * (B / p) + (C / p)];
+            const int C = div_small(r, inv_2p), B = r - 2 * p * C;
+            const int ah = A >= p, bh = B >= p, ch = C >= p;
+            const int f = a.child_fid[slot * 8 + 4 * ah + 2 * bh + ch];
             if (f >= 0) {
-                S& y = Yd[((size_t)f * nc + comp) * p3 + ((size_t)(C % p) * p + (B % p)) * p + (A % p)];
+                S& y = Yd[((size_t)f * nc + comp) * p3 + ((size_t)(C - p * ch) * p + (B - p * bh)) * p + (A - p * ah)];
                 y = (S)((double)y + tile[e]);
             }
         }
