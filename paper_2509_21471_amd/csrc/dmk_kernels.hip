@@ -848,47 +848,88 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
 #pragma unroll
         for (int j = 0; j < NC; ++j)
             acc[t][j] = mfma_d4{0.0, 0.0, 0.0, 0.0};
-    // operands of the 4 points starting at pt0 (this lane: point pt0 + lk)
-    double ax0, fa0[NC], ly0[NN], lz0[NN];
-    double ax1, fa1[NC], ly1[NN], lz1[NN];
-#define DMK_AM_LOAD(AX, FA, LY, LZ, PT0)                                          \
-    {                                                                             \
-        const int64_t pt = (PT0) + lk;                                            \
-        const bool ok = pt < L.end;                                               \
-        const int64_t pc = ok ? pt : L.start;                                     \
-        const double* Lp = Ltab + (size_t)pc * 3 * PA;                            \
-        const double ax = Lp[a_ok ? a : 0];                                       \
-        AX = (ok && a_ok) ? ax : 0.0;                                             \
-        _Pragma("unroll") for (int j = 0; j < NC; ++j)                            \
-        {                                                                         \
-            const double g = fs[(size_t)j * n + pc];                              \
-            FA[j] = ok ? g : 0.0;                                                 \
-        }                                                                         \
-        _Pragma("unroll") for (int t = 0; t < NN; ++t)                            \
-        {                                                                         \
-            const double yv = Lp[PA + bcol[t]];                                   \
-            LY[t] = n_ok[t] ? yv : 0.0;                                           \
-            LZ[t] = Lp[2 * PA + ccol[t]];                                         \
-        }                                                                         \
+    // The leaf's points go in blocks of KB: the block's Lagrange rows (one
+    // contiguous run of the table) and forces are loaded by the whole wave
+    // with 16-byte loads into registers while the previous block's products
+    // run, then written to LDS, from which each lane reads its operands.  The
+    // force goes on the A side (A = Lx f_j, B = Ly Lz shared by the
+    // components); rows a >= P and columns n >= P^2 are never stored, so only
+    // the forces past the leaf's end need to be zero.  The workgroup is one
+    // wave: its LDS accesses complete in order.
+    constexpr int ROW = 3 * PA;           // doubles per point of the table
+    constexpr int KB = ROW <= 72 ? 16 : 8;  // points per block (4 or 2 MFMA steps; fewer registers at large P)
+    constexpr int BLK2 = KB * ROW / 2;    // 16-byte words per block of rows
+    constexpr int PER = (BLK2 + 63) / 64;
+    constexpr int FPER = (NC * KB + 63) / 64;
+    __shared__ double2 sL[BLK2];
+    __shared__ double sF[NC * KB];
+    const int npt = (int)(L.end - L.start);
+    const double* Lb = Ltab + (size_t)L.start * ROW;
+    const int ao = a_ok ? a : 0;
+    double st0[PER], st1[PER];  // the next block (the two halves of its 16-byte words)
+    double sf[FPER], sm[FPER];  // its forces and their 0/1 masks (applied at the LDS store)
+    // unconditional loads from clamped indices: a row past the table's end
+    // repeats its last row (finite, and its force is zero), and a leaf
+    // without sources (a target-only leaf) reads its first row and force,
+    // which exist as the leaf is not empty; the forces are
+    // masked by a product at the LDS store (a select would turn the load into
+    // a branch, and an early product would wait for the load)
+#define DMK_AM_GLOAD(I0)                                                                     \
+    {                                                                                        \
+        const int i0_ = (I0);                                                                \
+        const double2* src = (const double2*)(Lb + (size_t)i0_ * ROW);                       \
+        const int64_t rows = n - (L.start + i0_);                                            \
+        const int lim = (int)min((int64_t)BLK2, rows * (ROW / 2)) - 1;                       \
+        _Pragma("unroll") for (int u = 0; u < PER; ++u)                                      \
+        {                                                                                    \
+            const double2 v = src[min(l + 64 * u, lim)];                                     \
+            st0[u] = v.x;                                                                    \
+            st1[u] = v.y;                                                                    \
+        }                                                                                    \
+        _Pragma("unroll") for (int u = 0; u < FPER; ++u)                                     \
+        {                                                                                    \
+            const int e = l + 64 * u;                                                        \
+            const int j = min(e / KB, NC - 1), k = e % KB;                                   \
+            sf[u] = fs[(size_t)j * n + L.start + max(min(i0_ + k, npt - 1), 0)];             \
+            sm[u] = (e < NC * KB && i0_ + k < npt) ? 1.0 : 0.0;                              \
+        }                                                                                    \
     }
-#define DMK_AM_STEP(AX, FA, LY, LZ)                                                           \
-    _Pragma("unroll") for (int t = 0; t < NN; ++t)                                            \
-    {                                                                                         \
-        const double w = LY[t] * LZ[t];                                                       \
-        _Pragma("unroll") for (int j = 0; j < NC; ++j)                                        \
-            acc[t][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(AX, w * FA[j], acc[t][j], 0, 0, 0); \
+#define DMK_AM_LSTORE()                                                                      \
+    {                                                                                        \
+        _Pragma("unroll") for (int u = 0; u < PER; ++u) if (l + 64 * u < BLK2) sL[l + 64 * u] = make_double2(st0[u], st1[u]); \
+        _Pragma("unroll") for (int u = 0; u < FPER; ++u) if (l + 64 * u < NC * KB) sF[l + 64 * u] = sf[u] * sm[u]; \
     }
-    // branch-free steps of 8 points: operands past the leaf's end load from a
-    // valid row and are zeroed, so they add nothing
-    DMK_AM_LOAD(ax0, fa0, ly0, lz0, L.start)
-    for (int64_t p0 = L.start; p0 < L.end; p0 += 8) {
-        DMK_AM_LOAD(ax1, fa1, ly1, lz1, p0 + 4)
-        DMK_AM_STEP(ax0, fa0, ly0, lz0)
-        DMK_AM_LOAD(ax0, fa0, ly0, lz0, p0 + 8)
-        DMK_AM_STEP(ax1, fa1, ly1, lz1)
+    const double* sLd = (const double*)sL;
+    const int nblk = (npt + KB - 1) / KB;
+    DMK_AM_GLOAD(0)
+    DMK_AM_LSTORE()
+    for (int blk = 0; blk < nblk; ++blk) {
+        const bool more = blk + 1 < nblk;
+        if (more)
+            DMK_AM_GLOAD((blk + 1) * KB)
+#pragma unroll
+        for (int ks = 0; ks < KB / 4; ++ks) {
+            const int pl = 4 * ks + lk;
+            const double* row = sLd + pl * ROW;
+            const double ax = row[ao];
+            double w[NN], af[NC];
+#pragma unroll
+            for (int t = 0; t < NN; ++t)
+                w[t] = row[PA + bcol[t]] * row[2 * PA + ccol[t]];
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                af[j] = ax * sF[j * KB + pl];
+#pragma unroll
+            for (int t = 0; t < NN; ++t)
+#pragma unroll
+                for (int j = 0; j < NC; ++j)
+                    acc[t][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[j], w[t], acc[t][j], 0, 0, 0);
+        }
+        if (more)
+            DMK_AM_LSTORE()
     }
-#undef DMK_AM_LOAD
-#undef DMK_AM_STEP
+#undef DMK_AM_GLOAD
+#undef DMK_AM_LSTORE
     // D[row = lk + 4 r][col = li] of tile t: a = 16 mt + lk + 4 r, n = 16 (NN ng + t) + li
     S* q = Q + (size_t)L.fid * NC * P * P * P;
 #pragma unroll
