@@ -993,35 +993,6 @@ __global__ __launch_bounds__(64) void k_anterp_mfma32(const LeafDesc* __restrict
             for (int r = 0; r < 4; ++r)
                 sum[t][j][r] = 0.0;
         }
-    float ax0, fa0[NC], ly0[NN], lz0[NN];
-    float ax1, fa1[NC], ly1[NN], lz1[NN];
-#define DMK_AM_LOAD(AX, FA, LY, LZ, PT0)                                          \
-    {                                                                             \
-        const int64_t pt = (PT0) + lk;                                            \
-        const bool ok = pt < L.end;                                               \
-        const int64_t pc = ok ? pt : L.start;                                     \
-        const float* Lp = Ltab + (size_t)pc * 3 * PA;                             \
-        const float ax = Lp[a_ok ? a : 0];                                        \
-        AX = (ok && a_ok) ? ax : 0.0f;                                            \
-        _Pragma("unroll") for (int j = 0; j < NC; ++j)                            \
-        {                                                                         \
-            const float g = (float)fs[(size_t)j * n + pc];                        \
-            FA[j] = ok ? g : 0.0f;                                                \
-        }                                                                         \
-        _Pragma("unroll") for (int t = 0; t < NN; ++t)                            \
-        {                                                                         \
-            const float yv = Lp[PA + bcol[t]];                                    \
-            LY[t] = n_ok[t] ? yv : 0.0f;                                          \
-            LZ[t] = Lp[2 * PA + ccol[t]];                                         \
-        }                                                                         \
-    }
-#define DMK_AM_STEP(AX, FA, LY, LZ)                                                           \
-    _Pragma("unroll") for (int t = 0; t < NN; ++t)                                            \
-    {                                                                                         \
-        const float w = LY[t] * LZ[t];                                                        \
-        _Pragma("unroll") for (int j = 0; j < NC; ++j)                                        \
-            acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(AX, w * FA[j], acc[t][j], 0, 0, 0); \
-    }
     auto fold = [&]() {
 #pragma unroll
         for (int t = 0; t < NN; ++t)
@@ -1033,21 +1004,86 @@ __global__ __launch_bounds__(64) void k_anterp_mfma32(const LeafDesc* __restrict
                 acc[t][j] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
             }
     };
-    DMK_AM_LOAD(ax0, fa0, ly0, lz0, L.start)
-    int steps = 0;
-    for (int64_t p0 = L.start; p0 < L.end; p0 += 8) {
-        DMK_AM_LOAD(ax1, fa1, ly1, lz1, p0 + 4)
-        DMK_AM_STEP(ax0, fa0, ly0, lz0)
-        DMK_AM_LOAD(ax0, fa0, ly0, lz0, p0 + 8)
-        DMK_AM_STEP(ax1, fa1, ly1, lz1)
-        if (++steps == 8) {  // 64 points
-            fold();
-            steps = 0;
+    // Blocks of KB points staged through LDS as in the FP64 kernel (16-byte
+    // loads of the block's table rows and forces while the previous block's
+    // products run; the force on the A side; indices clamped, forces past
+    // the leaf's end masked at the LDS store).
+    constexpr int ROW = 3 * PA;          // floats per point of the table
+    constexpr int KB = 16;               // points per block (4 MFMA steps)
+    constexpr int BLK4 = KB * ROW / 4;   // 16-byte words per block of rows
+    constexpr int PER = (BLK4 + 63) / 64;
+    constexpr int FPER = (NC * KB + 63) / 64;
+    constexpr int FOLD = 64 / KB;        // blocks per FP64 fold (64 points)
+    __shared__ float4 sL[BLK4];
+    __shared__ float sF[NC * KB];
+    const int npt = (int)(L.end - L.start);
+    const float* Lb = Ltab + (size_t)L.start * ROW;
+    const int ao = a_ok ? a : 0;
+    float st0[PER], st1[PER], st2[PER], st3[PER];
+    double sf[FPER], sm[FPER];
+#define DMK_AM_GLOAD(I0)                                                                     \
+    {                                                                                        \
+        const int i0_ = (I0);                                                                \
+        const float4* src = (const float4*)(Lb + (size_t)i0_ * ROW);                         \
+        const int64_t rows = n - (L.start + i0_);                                            \
+        const int lim = (int)min((int64_t)BLK4, rows * (ROW / 4)) - 1;                       \
+        _Pragma("unroll") for (int u = 0; u < PER; ++u)                                      \
+        {                                                                                    \
+            const float4 v = src[min(l + 64 * u, lim)];                                      \
+            st0[u] = v.x;                                                                    \
+            st1[u] = v.y;                                                                    \
+            st2[u] = v.z;                                                                    \
+            st3[u] = v.w;                                                                    \
+        }                                                                                    \
+        _Pragma("unroll") for (int u = 0; u < FPER; ++u)                                     \
+        {                                                                                    \
+            const int e = l + 64 * u;                                                        \
+            const int j = min(e / KB, NC - 1), k = e % KB;                                   \
+            sf[u] = fs[(size_t)j * n + L.start + max(min(i0_ + k, npt - 1), 0)];             \
+            sm[u] = (e < NC * KB && i0_ + k < npt) ? 1.0 : 0.0;                              \
+        }                                                                                    \
+    }
+#define DMK_AM_LSTORE()                                                                      \
+    {                                                                                        \
+        _Pragma("unroll") for (int u = 0; u < PER; ++u) if (l + 64 * u < BLK4)               \
+            sL[l + 64 * u] = make_float4(st0[u], st1[u], st2[u], st3[u]);                    \
+        _Pragma("unroll") for (int u = 0; u < FPER; ++u) if (l + 64 * u < NC * KB)           \
+            sF[l + 64 * u] = (float)(sf[u] * sm[u]);                                         \
+    }
+    const float* sLf = (const float*)sL;
+    const int nblk = (npt + KB - 1) / KB;
+    DMK_AM_GLOAD(0)
+    DMK_AM_LSTORE()
+    for (int blk = 0; blk < nblk; ++blk) {
+        const bool more = blk + 1 < nblk;
+        if (more)
+            DMK_AM_GLOAD((blk + 1) * KB)
+#pragma unroll
+        for (int ks = 0; ks < KB / 4; ++ks) {
+            const int pl = 4 * ks + lk;
+            const float* row = sLf + pl * ROW;
+            const float ax = row[ao];
+            float w[NN], af[NC];
+#pragma unroll
+            for (int t = 0; t < NN; ++t)
+                w[t] = row[PA + bcol[t]] * row[2 * PA + ccol[t]];
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+                af[j] = ax * sF[j * KB + pl];
+#pragma unroll
+            for (int t = 0; t < NN; ++t)
+#pragma unroll
+                for (int j = 0; j < NC; ++j)
+                    acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[j], w[t], acc[t][j], 0, 0, 0);
         }
+        if (blk % FOLD == FOLD - 1)
+            fold();
+        if (more)
+            DMK_AM_LSTORE()
     }
     fold();
-#undef DMK_AM_LOAD
-#undef DMK_AM_STEP
+#undef DMK_AM_GLOAD
+#undef DMK_AM_LSTORE
     // D[row = 4 lk + r][col = li] of tile t: a = 16 mt + 4 lk + r, n = 16 (NN ng + t) + li
     float* q = Q + (size_t)L.fid * NC * P * P * P;
 #pragma unroll
