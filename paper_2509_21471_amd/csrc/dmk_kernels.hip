@@ -566,11 +566,16 @@ __global__ __launch_bounds__(PTS * 4) void k_leaf_eval(const EvalChunk* __restri
                                                               const S* __restrict__ V, int64_t n,
                                                               double* __restrict__ u)
 {
-    constexpr int PA = MCfg<P>::PA, NK = MCfg<P>::NK, NT = MCfg<P>::NT, RS = MCfg<P>::RS;
-    constexpr int PB = 16 * NT;
+    constexpr int PA = MCfg<P>::PA, NK = MCfg<P>::NK, RS = MCfg<P>::RS;
+    // the A rows are the (component j, b) pairs rho = j P + b of the slab,
+    // packed into NTP tiles of 16 (5 instead of 6 at P = 23, 7 instead of 9
+    // at P = 36); rows past 3 P are zero
+    constexpr int NR = 3 * P;
+    constexpr int NTP = (NR + 15) / 16;
+    constexpr int PB = 16 * NTP;
     constexpr int NTH = PTS * 4;
     constexpr int NPRE = (3 * P * P + NTH - 1) / NTH;  // slab elements per thread
-    __shared__ double slab[2][3][PB][RS];               // double-buffered c-slabs
+    __shared__ double slab[2][PB][RS];                  // double-buffered c-slabs
     const EvalChunk C = chunks[blockIdx.x];
     const S* v = V + (size_t)C.fid * 3 * P * P * P;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
@@ -582,17 +587,18 @@ __global__ __launch_bounds__(PTS * 4) void k_leaf_eval(const EvalChunk* __restri
 #pragma unroll
     for (int s = 0; s < NK; ++s)
         bx[s] = valid ? Li[4 * s + lk] : 0.0;
-    double wy[NT][4];
+    // b weights of this lane's output rows rho = 16 T + lk + 4 r
+    double wy[NTP][4];
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int T = 0; T < NTP; ++T)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int b = 16 * t + lk + 4 * r;
-            wy[t][r] = (valid && b < P) ? Li[PA + b] : 0.0;
+            const int rho = 16 * T + lk + 4 * r;
+            wy[T][r] = (valid && rho < NR) ? Li[PA + rho % P] : 0.0;
         }
     // the padding rows / columns of both buffers stay zero
-    for (int e = tid; e < 2 * 3 * PB * RS; e += NTH)
-        (&slab[0][0][0][0])[e] = 0.0;
+    for (int e = tid; e < 2 * PB * RS; e += NTH)
+        (&slab[0][0][0])[e] = 0.0;
     // slab c+1 is loaded into registers while slab c is used from LDS
     double pre[NPRE];
     auto fetch = [&](int c) {
@@ -610,8 +616,8 @@ __global__ __launch_bounds__(PTS * 4) void k_leaf_eval(const EvalChunk* __restri
         for (int k = 0; k < NPRE; ++k) {
             const int e = tid + k * NTH;
             if (e < 3 * P * P) {
-                const int j = e / (P * P), r = e % (P * P);
-                slab[buf][j][r / P][r % P] = pre[k];
+                // e = (j P + b) P + a
+                slab[buf][e / P][e % P] = pre[k];
             }
         }
     };
@@ -632,18 +638,28 @@ __global__ __launch_bounds__(PTS * 4) void k_leaf_eval(const EvalChunk* __restri
             const double lz = valid ? Li[2 * PA + c] : 0.0;
             double X[3] = {0, 0, 0};
 #pragma unroll
-            for (int j = 0; j < 3; ++j)
+            for (int T = 0; T < NTP; ++T) {
+                mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
+                for (int s = 0; s < NK; ++s)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(slab[cur][16 * T + lr][4 * s + lk], bx[s], acc, 0, 0, 0);
 #pragma unroll
-                    for (int s = 0; s < NK; ++s)
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(slab[cur][j][16 * t + lr][4 * s + lk], bx[s], acc,
-                                                                   0, 0, 0);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        X[j] = fma(wy[t][r], acc[r], X[j]);
+                for (int r = 0; r < 4; ++r) {
+                    // rows 16 T + 4 r + (0..3) over the lanes: one component,
+                    // or two where a component ends among them
+                    const int j0 = (16 * T + 4 * r) / P, j1 = (16 * T + 4 * r + 3) / P;
+                    if (j0 >= 3)
+                        continue;  // padding rows
+                    const double t = wy[T][r] * acc[r];
+                    if (j0 == j1 || j1 >= 3) {
+                        X[j0] += t;
+                    } else {
+                        const bool hi = 16 * T + 4 * r + lk >= j1 * P;
+                        X[j0] += hi ? 0.0 : t;
+                        X[j1] += hi ? t : 0.0;
+                    }
                 }
+            }
             u0 = fma(lz, X[0], u0);
             u1 = fma(lz, X[1], u1);
             u2 = fma(lz, X[2], u2);
@@ -653,7 +669,7 @@ __global__ __launch_bounds__(PTS * 4) void k_leaf_eval(const EvalChunk* __restri
             put(cur ^ 1);
         __syncthreads();
     }
-    // the four lanes of a point hold disjoint b rows
+    // the four lanes of a point hold disjoint rows
     u0 += __shfl_xor(u0, 16);
     u1 += __shfl_xor(u1, 16);
     u2 += __shfl_xor(u2, 16);
