@@ -3,6 +3,7 @@
 
 
 #include <algorithm>
+#include <type_traits>
 #include <mutex>
 
 namespace dmk {
@@ -515,32 +516,41 @@ __global__ __launch_bounds__(256) void k_lagrange_table(const LeafDesc* __restri
                                                         const double* __restrict__ z, const double* __restrict__ ct,
                                                         const double* __restrict__ cw, LT* __restrict__ Ltab)
 {
+    // The rows of CP consecutive points (3 PA values each, contiguous in the
+    // table) are formed in LDS, one (point, axis) row per thread, then
+    // written out as one contiguous run with 16-byte stores.
     constexpr int PA = MCfg<P>::PA;
+    constexpr int ROW = 3 * PA;
+    constexpr int CP = PA <= 24 ? 128 : 64;  // points per chunk (at most 72 KB of LDS)
+    constexpr int V = 16 / sizeof(LT);       // values per 16-byte store
+    static_assert(ROW % V == 0, "rows are a whole number of 16-byte words");
+    __shared__ __align__(16) LT tile[CP * ROW];
     const LeafDesc L = leaves[blockIdx.x];
     const double sc = (double)(2ll << L.level);
     const double cen[3] = {L.cx, L.cy, L.cz};
     const double* crd[3] = {x, y, z};
-    for (int64_t i = L.start + threadIdx.x; i < L.end; i += 256) {
-        for (int d = 0; d < 3; ++d) {
+    for (int64_t c0 = L.start; c0 < L.end; c0 += CP) {
+        const int np = (int)min((int64_t)CP, L.end - c0);
+        for (int w = threadIdx.x; w < 3 * np; w += 256) {
+            const int pt = w / 3, d = w - 3 * pt;
             double Lv[PA];
-            lagrange<P>((crd[d][i] - cen[d]) * sc, ct, cw, Lv);
+            lagrange<P>((crd[d][c0 + pt] - cen[d]) * sc, ct, cw, Lv);
 #pragma unroll
             for (int a = P; a < PA; ++a)
                 Lv[a] = 0.0;
-            // PA is a multiple of 4, so each row is 16-byte aligned: 16-byte stores
-            if constexpr (sizeof(LT) == 8) {
-                double2* o = reinterpret_cast<double2*>(Ltab + ((size_t)i * 3 + d) * PA);
+            LT* o = tile + pt * ROW + d * PA;
 #pragma unroll
-                for (int a = 0; a < PA / 2; ++a)
-                    o[a] = make_double2(Lv[2 * a], Lv[2 * a + 1]);
-            } else {
-                float4* o = reinterpret_cast<float4*>(Ltab + ((size_t)i * 3 + d) * PA);
-#pragma unroll
-                for (int a = 0; a < PA / 4; ++a)
-                    o[a] = make_float4((float)Lv[4 * a], (float)Lv[4 * a + 1], (float)Lv[4 * a + 2],
-                                       (float)Lv[4 * a + 3]);
-            }
+            for (int a = 0; a < PA; ++a)
+                o[a] = (LT)Lv[a];
         }
+        __syncthreads();
+        // 16-byte words of the chunk's rows, contiguous in the table
+        using W = typename std::conditional<sizeof(LT) == 8, double2, float4>::type;
+        const W* src = reinterpret_cast<const W*>(tile);
+        W* dst = reinterpret_cast<W*>(Ltab + (size_t)c0 * ROW);
+        for (int e = threadIdx.x; e < np * ROW / V; e += 256)
+            dst[e] = src[e];
+        __syncthreads();
     }
 }
 
