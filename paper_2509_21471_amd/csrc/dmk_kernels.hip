@@ -211,7 +211,7 @@ void launch_gather_points(const double* pts, int64_t n, const int* perm, const i
 // so the bitonic sort gives one order.
 namespace {
 constexpr int kKdMaxSeg = kKdCap / 8;
-constexpr int kKdThreads = 1024;  // 16 waves: the sort stages are latency bound
+constexpr int kKdThreads = 512;  // 8 waves: twice the blocks per CU of 1024 threads, whose stages are latency bound
 
 __global__ __launch_bounds__(kKdThreads) void k_leaf_kd(const KdSeg* __restrict__ segs, const double* __restrict__ x,
                                                  const double* __restrict__ y, const double* __restrict__ z,
