@@ -802,39 +802,44 @@ __global__ __launch_bounds__(PTS * 4) void k_leaf_eval32(const EvalChunk* __rest
 }
 
 // Proxy charges (Step 2a) as MFMA contractions over the points:
-//   Q_j[a][n] = sum_pt Lx[pt][a] W_j[pt][n],  W_j[pt][n] = Ly[pt][b] Lz[pt][c] f_j[pt],  n = b P + c,
-// with v_mfma_f64_16x16x4f64: rows = a (16-tile), columns = n (16-tiles of the
-// flattened (b, c) index, so Q's x-major rows are stored contiguously), K = 4
-// points.  One wave per (leaf, a-tile, group of NN n-tiles); lane l feeds the
-// A operand Lx[pt0 + l/16][a0 + l%16] and forms the B operand
-// Ly[pt0 + l/16][b] Lz[pt0 + l/16][c] f_j for its column, all from vector
-// loads; the next 4 points' operands load while the current MFMAs run.
+//   Q[j][a][n] = sum_pt Lx[pt][a] f_j[pt] W[pt][n],  W[pt][n] = Ly[pt][b] Lz[pt][c],  n = b P + c,
+// with v_mfma_f64_16x16x4f64: rows = the NC P pairs (j, a) in Q's order,
+// packed into 16-row tiles across the components (69 rows in 5 tiles at
+// p = 23, not 3 x 2), columns = 16-tiles of the flattened (b, c) index (Q's
+// rows stored contiguously), K = 4 points.  A row (j, a) is Q's row j P + a,
+// so the output stores run along n.  The A operand carries the force,
+// Lx[pt][a] f_j[pt]; the B operand W is shared by the components.
 template <int P>
 struct AMCfg {
     static constexpr int PA = MCfg<P>::PA;
-    static constexpr int MT = (P + 15) / 16;         // a-tiles
     static constexpr int NTOT = (P * P + 15) / 16;   // n-tiles
-    static constexpr int NN = 2;                     // n-tiles per wave
-    static constexpr int NG = (NTOT + NN - 1) / NN;  // n-tile groups
-    // the last, partial a-tile of every component: its rows (j, a) packed
-    // into row tiles of their own
-    static constexpr int A0 = 16 * (MT - 1);
-    static constexpr int REM = P - A0;
 };
 template <int P, int NC>
-struct AMRem {
-    static constexpr int ROWS = NC * AMCfg<P>::REM;
+struct AMPack {
+    static constexpr int ROWS = NC * P;                      // (j, a) rows
+    static constexpr int RT = (ROWS + 15) / 16;              // row tiles
+    // at most 8 row tiles per wave (their A operands share each B operand);
+    // 3 n-tiles per wave where the row tiles are few enough for the registers
+    static constexpr int RG = (RT + 7) / 8;                  // row-tile groups
+    static constexpr int TPW = (RT + RG - 1) / RG;           // row tiles per wave
+    static constexpr int NN = NC == 6 && TPW <= 5 ? 3 : 2;   // n-tiles per wave
+    static constexpr int NG = (AMCfg<P>::NTOT + NN - 1) / NN;  // n-tile groups
+    static constexpr int TASKS = RG * NG;                    // waves per leaf
+};
+
+// The FP32 kernel's tiling: its FP64 fold sums double the registers per
+// accumulator tile, so the six stresslet densities go in groups of two row
+// tiles with three n-tiles each.
+template <int P, int NC>
+struct AMPack32 {
+    static constexpr int ROWS = NC * P;
     static constexpr int RT = (ROWS + 15) / 16;
-    static constexpr int TASKS = RT * AMCfg<P>::NG;
-    // pack the partial tiles of the three force components where that saves
-    // at least two of nine row tiles per n-tile (p = 33, 36: 8.3 -> 7.9 ms
-    // at 1e-9); at p = 23 one tile saved, and for the six stresslet
-    // densities at p = 26 two of twelve, do not pay for the second, less
-    // loaded launch (measured slower)
-    static constexpr bool SPLIT = NC == 3 && AMCfg<P>::MT * NC - ((AMCfg<P>::MT - 1) * NC + RT) >= 2;
-    // tiles and waves per leaf of k_anterp_mfma
-    static constexpr int MF = SPLIT ? AMCfg<P>::MT - 1 : AMCfg<P>::MT;
-    static constexpr int FULL_TASKS = MF * AMCfg<P>::NG;
+    static constexpr int MAXT = NC == 6 ? 2 : 8;
+    static constexpr int RG = (RT + MAXT - 1) / MAXT;
+    static constexpr int TPW = (RT + RG - 1) / RG;
+    static constexpr int NN = NC == 6 ? 3 : 2;
+    static constexpr int NG = (AMCfg<P>::NTOT + NN - 1) / NN;
+    static constexpr int TASKS = RG * NG;
 };
 
 template <int P, int NC, typename S>
@@ -843,22 +848,29 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
                                                     const double* __restrict__ fs, int64_t n, S* __restrict__ Q)
 {
     using C = AMCfg<P>;
-    constexpr int PA = C::PA, NN = C::NN;
-    constexpr int MF = AMRem<P, NC>::MF > 0 ? AMRem<P, NC>::MF : 1;  // a-tiles of this kernel
-    constexpr int TASKS = MF * C::NG;
+    using K = AMPack<P, NC>;
+    constexpr int PA = C::PA, NN = K::NN, TPW = K::TPW;
     // workgroups go to the 8 XCDs in turn: leaf k runs all its waves on XCD
     // k % 8, so its Lagrange rows and forces are read into one L2 only
     const int xcd = blockIdx.x % 8, sx = blockIdx.x / 8;
-    const int task = sx % TASKS;
-    const int leaf = xcd + 8 * (sx / TASKS);
+    const int task = sx % K::TASKS;
+    const int leaf = xcd + 8 * (sx / K::TASKS);
     if (leaf >= nleaf)
         return;
     const LeafDesc L = leaves[leaf];
-    const int mt = task % MF, ng = task / MF;
+    const int rg = task % K::RG, ng = task / K::RG;
     const int l = threadIdx.x;
     const int li = l & 15, lk = l >> 4;
-    const int a = 16 * mt + li;
-    const bool a_ok = a < P;
+    // row tiles 16 (TPW rg + T) ...: this lane's A rows (j, a); rows past
+    // NC P read a valid entry and are never stored
+    const int t0 = TPW * rg;
+    int arow[TPW], frow[TPW];
+#pragma unroll
+    for (int T = 0; T < TPW; ++T) {
+        const int row = min(16 * (t0 + T) + li, K::ROWS - 1);
+        arow[T] = row % P;
+        frow[T] = row / P;
+    }
     int bcol[NN], ccol[NN];
     bool n_ok[NN];
 #pragma unroll
@@ -868,18 +880,17 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
         bcol[t] = n_ok[t] ? nn / P : 0;
         ccol[t] = n_ok[t] ? nn % P : 0;
     }
-    mfma_d4 acc[NN][NC];
+    mfma_d4 acc[TPW][NN];
 #pragma unroll
-    for (int t = 0; t < NN; ++t)
+    for (int T = 0; T < TPW; ++T)
 #pragma unroll
-        for (int j = 0; j < NC; ++j)
-            acc[t][j] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < NN; ++t)
+            acc[T][t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
     // The leaf's points go in blocks of KB: the block's Lagrange rows (one
     // contiguous run of the table) and forces are loaded by the whole wave
     // with 16-byte loads into registers while the previous block's products
-    // run, then written to LDS, from which each lane reads its operands.  The
-    // force goes on the A side (A = Lx f_j, B = Ly Lz shared by the
-    // components); rows a >= P and columns n >= P^2 are never stored, so only
+    // run, then written to LDS, from which each lane reads its operands.
+    // Rows (j, a) past NC P and columns n >= P^2 are never stored, so only
     // the forces past the leaf's end need to be zero.  The workgroup is one
     // wave: its LDS accesses complete in order.
     constexpr int ROW = 3 * PA;           // doubles per point of the table
@@ -891,7 +902,6 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
     __shared__ double sF[NC * KB];
     const int npt = (int)(L.end - L.start);
     const double* Lb = Ltab + (size_t)L.start * ROW;
-    const int ao = a_ok ? a : 0;
     double st0[PER], st1[PER];  // the next block (the two halves of its 16-byte words)
     double sf[FPER], sm[FPER];  // its forces and their 0/1 masks (applied at the LDS store)
     // unconditional loads from clamped indices: a row past the table's end
@@ -927,6 +937,8 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
     }
     const double* sLd = (const double*)sL;
     const int nblk = (npt + KB - 1) / KB;
+    // a wave of the last row group may own fewer than TPW tiles
+    const int tv = min(TPW, K::RT - t0);
     DMK_AM_GLOAD(0)
     DMK_AM_LSTORE()
     for (int blk = 0; blk < nblk; ++blk) {
@@ -937,26 +949,25 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
         for (int ks = 0; ks < KB / 4; ++ks) {
             const int pl = 4 * ks + lk;
             const double* row = sLd + pl * ROW;
-            const double ax = row[ao];
-            double w[NN], af[NC];
+            double w[NN];
 #pragma unroll
             for (int t = 0; t < NN; ++t)
                 w[t] = row[PA + bcol[t]] * row[2 * PA + ccol[t]];
 #pragma unroll
-            for (int j = 0; j < NC; ++j)
-                af[j] = ax * sF[j * KB + pl];
+            for (int T = 0; T < TPW; ++T)
+                if (T < tv) {
+                    const double af = row[arow[T]] * sF[frow[T] * KB + pl];
 #pragma unroll
-            for (int t = 0; t < NN; ++t)
-#pragma unroll
-                for (int j = 0; j < NC; ++j)
-                    acc[t][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[j], w[t], acc[t][j], 0, 0, 0);
+                    for (int t = 0; t < NN; ++t)
+                        acc[T][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, w[t], acc[T][t], 0, 0, 0);
+                }
         }
         if (more)
             DMK_AM_LSTORE()
     }
 #undef DMK_AM_GLOAD
 #undef DMK_AM_LSTORE
-    // D[row = lk + 4 r][col = li] of tile t: a = 16 mt + lk + 4 r, n = 16 (NN ng + t) + li
+    // D[row = lk + 4 r][col = li] of tile (T, t): Q row 16 (t0 + T) + lk + 4 r, n = 16 (NN ng + t) + li
     S* q = Q + (size_t)L.fid * NC * P * P * P;
 #pragma unroll
     for (int t = 0; t < NN; ++t) {
@@ -964,41 +975,46 @@ __global__ __launch_bounds__(64) void k_anterp_mfma(const LeafDesc* __restrict__
             continue;
         const int nn = 16 * (NN * ng + t) + li;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int ar = 16 * mt + lk + 4 * r;
-            if (ar < P)
+        for (int T = 0; T < TPW; ++T)
 #pragma unroll
-                for (int j = 0; j < NC; ++j)
-                    q[((size_t)j * P + ar) * P * P + nn] = (S)acc[t][j][r];
-        }
+            for (int r = 0; r < 4; ++r) {
+                const int rr = 16 * (t0 + T) + lk + 4 * r;
+                if (rr < K::ROWS)
+                    q[(size_t)rr * P * P + nn] = (S)acc[T][t][r];
+            }
     }
 }
 
 // Proxy charges for plans whose far field is stored in FP32: the same
-// contraction on v_mfma_f32_16x16x4f32 with FP32 Lagrange values and forces.
-// The FP32 accumulators are folded into FP64 sums every 64 points (blocked
-// summation: the rounding error grows with 64 terms, not with the leaf's
-// size), and the FP64 sums are rounded once to the stored FP32 charges.  Every
-// a-tile, the partial last one included, runs here.
+// packed contraction on v_mfma_f32_16x16x4f32 with FP32 Lagrange values and
+// forces.  The FP32 accumulators are folded into FP64 sums every 64 points
+// (blocked summation: the rounding error grows with 64 terms, not with the
+// leaf's size), and the FP64 sums are rounded once to the stored FP32 charges.
 template <int P, int NC>
 __global__ __launch_bounds__(64) void k_anterp_mfma32(const LeafDesc* __restrict__ leaves, int nleaf,
                                                       const float* __restrict__ Ltab, const double* __restrict__ fs,
                                                       int64_t n, float* __restrict__ Q)
 {
     using C = AMCfg<P>;
-    constexpr int PA = C::PA, NN = C::NN, MF = C::MT;
-    constexpr int TASKS = MF * C::NG;
+    using K = AMPack32<P, NC>;
+    constexpr int PA = C::PA, NN = K::NN, TPW = K::TPW;
     const int xcd = blockIdx.x % 8, sx = blockIdx.x / 8;
-    const int task = sx % TASKS;
-    const int leaf = xcd + 8 * (sx / TASKS);
+    const int task = sx % K::TASKS;
+    const int leaf = xcd + 8 * (sx / K::TASKS);
     if (leaf >= nleaf)
         return;
     const LeafDesc L = leaves[leaf];
-    const int mt = task % MF, ng = task / MF;
+    const int rg = task % K::RG, ng = task / K::RG;
     const int l = threadIdx.x;
     const int li = l & 15, lk = l >> 4;
-    const int a = 16 * mt + li;
-    const bool a_ok = a < P;
+    const int t0 = TPW * rg;
+    int arow[TPW], frow[TPW];
+#pragma unroll
+    for (int T = 0; T < TPW; ++T) {
+        const int row = min(16 * (t0 + T) + li, K::ROWS - 1);
+        arow[T] = row % P;
+        frow[T] = row / P;
+    }
     int bcol[NN], ccol[NN];
     bool n_ok[NN];
 #pragma unroll
@@ -1008,26 +1024,26 @@ __global__ __launch_bounds__(64) void k_anterp_mfma32(const LeafDesc* __restrict
         bcol[t] = n_ok[t] ? nn / P : 0;
         ccol[t] = n_ok[t] ? nn % P : 0;
     }
-    mfma_f4 acc[NN][NC];
-    double sum[NN][NC][4];
+    mfma_f4 acc[TPW][NN];
+    double sum[TPW][NN][4];
 #pragma unroll
-    for (int t = 0; t < NN; ++t)
+    for (int T = 0; T < TPW; ++T)
 #pragma unroll
-        for (int j = 0; j < NC; ++j) {
-            acc[t][j] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int t = 0; t < NN; ++t) {
+            acc[T][t] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                sum[t][j][r] = 0.0;
+                sum[T][t][r] = 0.0;
         }
     auto fold = [&]() {
 #pragma unroll
-        for (int t = 0; t < NN; ++t)
+        for (int T = 0; T < TPW; ++T)
 #pragma unroll
-            for (int j = 0; j < NC; ++j) {
+            for (int t = 0; t < NN; ++t) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    sum[t][j][r] += (double)acc[t][j][r];
-                acc[t][j] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+                    sum[T][t][r] += (double)acc[T][t][r];
+                acc[T][t] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
             }
     };
     // Blocks of KB points staged through LDS as in the FP64 kernel (16-byte
@@ -1044,7 +1060,6 @@ __global__ __launch_bounds__(64) void k_anterp_mfma32(const LeafDesc* __restrict
     __shared__ float sF[NC * KB];
     const int npt = (int)(L.end - L.start);
     const float* Lb = Ltab + (size_t)L.start * ROW;
-    const int ao = a_ok ? a : 0;
     float st0[PER], st1[PER], st2[PER], st3[PER];
     double sf[FPER], sm[FPER];
 #define DMK_AM_GLOAD(I0)                                                                     \
@@ -1078,6 +1093,7 @@ __global__ __launch_bounds__(64) void k_anterp_mfma32(const LeafDesc* __restrict
     }
     const float* sLf = (const float*)sL;
     const int nblk = (npt + KB - 1) / KB;
+    const int tv = min(TPW, K::RT - t0);
     DMK_AM_GLOAD(0)
     DMK_AM_LSTORE()
     for (int blk = 0; blk < nblk; ++blk) {
@@ -1088,19 +1104,18 @@ __global__ __launch_bounds__(64) void k_anterp_mfma32(const LeafDesc* __restrict
         for (int ks = 0; ks < KB / 4; ++ks) {
             const int pl = 4 * ks + lk;
             const float* row = sLf + pl * ROW;
-            const float ax = row[ao];
-            float w[NN], af[NC];
+            float w[NN];
 #pragma unroll
             for (int t = 0; t < NN; ++t)
                 w[t] = row[PA + bcol[t]] * row[2 * PA + ccol[t]];
 #pragma unroll
-            for (int j = 0; j < NC; ++j)
-                af[j] = ax * sF[j * KB + pl];
+            for (int T = 0; T < TPW; ++T)
+                if (T < tv) {
+                    const float af = row[arow[T]] * sF[frow[T] * KB + pl];
 #pragma unroll
-            for (int t = 0; t < NN; ++t)
-#pragma unroll
-                for (int j = 0; j < NC; ++j)
-                    acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[j], w[t], acc[t][j], 0, 0, 0);
+                    for (int t = 0; t < NN; ++t)
+                        acc[T][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, w[t], acc[T][t], 0, 0, 0);
+                }
         }
         if (blk % FOLD == FOLD - 1)
             fold();
@@ -1110,7 +1125,7 @@ __global__ __launch_bounds__(64) void k_anterp_mfma32(const LeafDesc* __restrict
     fold();
 #undef DMK_AM_GLOAD
 #undef DMK_AM_LSTORE
-    // D[row = 4 lk + r][col = li] of tile t: a = 16 mt + 4 lk + r, n = 16 (NN ng + t) + li
+    // D[row = 4 lk + r][col = li] of tile (T, t): Q row 16 (t0 + T) + 4 lk + r, n = 16 (NN ng + t) + li
     float* q = Q + (size_t)L.fid * NC * P * P * P;
 #pragma unroll
     for (int t = 0; t < NN; ++t) {
@@ -1118,99 +1133,13 @@ __global__ __launch_bounds__(64) void k_anterp_mfma32(const LeafDesc* __restrict
             continue;
         const int nn = 16 * (NN * ng + t) + li;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int ar = 16 * mt + 4 * lk + r;
-            if (ar < P)
+        for (int T = 0; T < TPW; ++T)
 #pragma unroll
-                for (int j = 0; j < NC; ++j)
-                    q[((size_t)j * P + ar) * P * P + nn] = (float)sum[t][j][r];
-        }
-    }
-}
-
-// The rows of the last, partial a-tile, for every component at once: row
-// (j, a), a in [A0, P), packed NC * REM to a column of row tiles (21 rows in
-// two tiles at p = 23 instead of one mostly empty tile per component).  Here
-// the A operand carries the force, Lx[pt][a] f_j[pt], and the B operand is
-// Ly[pt][b] Lz[pt][c] for every component.  Same wave layout, point steps and
-// XCD placement as k_anterp_mfma.
-template <int P, int NC, typename S>
-__global__ __launch_bounds__(64) void k_anterp_rem(const LeafDesc* __restrict__ leaves, int nleaf,
-                                                   const double* __restrict__ Ltab, const double* __restrict__ fs,
-                                                   int64_t n, S* __restrict__ Q)
-{
-    using C = AMCfg<P>;
-    using R = AMRem<P, NC>;
-    constexpr int PA = C::PA, NN = C::NN, A0 = C::A0, REM = C::REM;
-    const int xcd = blockIdx.x % 8, sx = blockIdx.x / 8;
-    const int task = sx % R::TASKS;
-    const int leaf = xcd + 8 * (sx / R::TASKS);
-    if (leaf >= nleaf)
-        return;
-    const LeafDesc L = leaves[leaf];
-    const int rt = task % R::RT, ng = task / R::RT;
-    const int l = threadIdx.x;
-    const int li = l & 15, lk = l >> 4;
-    // this lane's A row
-    const int row = 16 * rt + li;
-    const bool r_ok = row < R::ROWS;
-    const int rj = r_ok ? row / REM : 0;
-    const int ra = A0 + (r_ok ? row % REM : 0);
-    int bcol[NN], ccol[NN];
-    bool n_ok[NN];
-#pragma unroll
-    for (int t = 0; t < NN; ++t) {
-        const int nn = 16 * (NN * ng + t) + li;
-        n_ok[t] = nn < P * P;
-        bcol[t] = n_ok[t] ? nn / P : 0;
-        ccol[t] = n_ok[t] ? nn % P : 0;
-    }
-    mfma_d4 acc[NN];
-#pragma unroll
-    for (int t = 0; t < NN; ++t)
-        acc[t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
-    double ar0, ly0[NN], lz0[NN];
-    double ar1, ly1[NN], lz1[NN];
-#define DMK_AR_LOAD(AR, LY, LZ, PT0)                                              \
-    {                                                                             \
-        const int64_t pt = (PT0) + lk;                                            \
-        const bool ok = pt < L.end;                                               \
-        const int64_t pc = ok ? pt : L.start;                                     \
-        const double* Lp = Ltab + (size_t)pc * 3 * PA;                            \
-        const double av = Lp[ra] * fs[(size_t)rj * n + pc];                       \
-        AR = (ok && r_ok) ? av : 0.0;                                             \
-        _Pragma("unroll") for (int t = 0; t < NN; ++t)                            \
-        {                                                                         \
-            const double yv = Lp[PA + bcol[t]];                                   \
-            LY[t] = n_ok[t] ? yv : 0.0;                                           \
-            LZ[t] = Lp[2 * PA + ccol[t]];                                         \
-        }                                                                         \
-    }
-#define DMK_AR_STEP(AR, LY, LZ)                                                              \
-    _Pragma("unroll") for (int t = 0; t < NN; ++t)                                           \
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(AR, LY[t] * LZ[t], acc[t], 0, 0, 0);
-    DMK_AR_LOAD(ar0, ly0, lz0, L.start)
-    for (int64_t p0 = L.start; p0 < L.end; p0 += 8) {
-        DMK_AR_LOAD(ar1, ly1, lz1, p0 + 4)
-        DMK_AR_STEP(ar0, ly0, lz0)
-        DMK_AR_LOAD(ar0, ly0, lz0, p0 + 8)
-        DMK_AR_STEP(ar1, ly1, lz1)
-    }
-#undef DMK_AR_LOAD
-#undef DMK_AR_STEP
-    // D[row = lk + 4 r][col = li] of tile t: remainder row 16 rt + lk + 4 r, n = 16 (NN ng + t) + li
-    S* q = Q + (size_t)L.fid * NC * P * P * P;
-#pragma unroll
-    for (int t = 0; t < NN; ++t) {
-        if (!n_ok[t])
-            continue;
-        const int nn = 16 * (NN * ng + t) + li;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int rr = 16 * rt + lk + 4 * r;
-            if (rr < R::ROWS)
-                q[((size_t)(rr / REM) * P + A0 + rr % REM) * P * P + nn] = (S)acc[t][r];
-        }
+            for (int r = 0; r < 4; ++r) {
+                const int rr = 16 * (t0 + T) + 4 * lk + r;
+                if (rr < K::ROWS)
+                    q[(size_t)rr * P * P + nn] = (float)sum[T][t][r];
+            }
     }
 }
 
@@ -1274,15 +1203,11 @@ void launch_anterp(int p, int nc, const LeafDesc* leaves, int nleaf, const void*
     const int nleaf8 = (nleaf + 7) / 8 * 8;
 #define L_ANTERP_NC(P, NC)                                                                                       \
     if (f32) {                                                                                                   \
-        hipLaunchKernelGGL((k_anterp_mfma32<P, NC>), dim3(nleaf8 * AMCfg<P>::MT * AMCfg<P>::NG), dim3(64), 0, s, \
+        hipLaunchKernelGGL((k_anterp_mfma32<P, NC>), dim3(nleaf8 * AMPack32<P, NC>::TASKS), dim3(64), 0, s,    \
                            leaves, nleaf, (const float*)Ltab, fs, n, (float*)Q);                                 \
     } else {                                                                                                     \
-        if constexpr (AMRem<P, NC>::FULL_TASKS > 0)                                                              \
-            hipLaunchKernelGGL((k_anterp_mfma<P, NC, double>), dim3(nleaf8 * AMRem<P, NC>::FULL_TASKS),          \
-                               dim3(64), 0, s, leaves, nleaf, (const double*)Ltab, fs, n, (double*)Q);           \
-        if constexpr (AMRem<P, NC>::SPLIT)                                                                       \
-            hipLaunchKernelGGL((k_anterp_rem<P, NC, double>), dim3(nleaf8 * AMRem<P, NC>::TASKS), dim3(64), 0,   \
-                               s, leaves, nleaf, (const double*)Ltab, fs, n, (double*)Q);                        \
+        hipLaunchKernelGGL((k_anterp_mfma<P, NC, double>), dim3(nleaf8 * AMPack<P, NC>::TASKS), dim3(64), 0, s,  \
+                           leaves, nleaf, (const double*)Ltab, fs, n, (double*)Q);                               \
     }
 #define L_ANTERP(P)               \
     if (nc == 6) {                \
