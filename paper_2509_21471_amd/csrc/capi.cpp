@@ -1171,8 +1171,12 @@ int build_plan(dmk_plan_t P, const double* points)
         const size_t mh = P->root_mh, mf = P->root_mf;
         per_root = std::max({(size_t)p * p * mh, (size_t)p * mh * mf, mf * mf * (size_t)p, mf * (size_t)p * p}) * cs;
     }
-    // scratch for one chunk of slots: at most about 1 GiB per buffer
-    const size_t budget = (size_t)1 << 30;
+    // scratch for one chunk of slots: at most about 4 GiB per buffer (fewer,
+    // larger stage launches; a sixteenth of this GPU's 288 GB for both), or an
+    // eighth of the caller's memory cap
+    size_t budget = (size_t)4 << 30;
+    if (P->mem.cap)
+        budget = std::min(budget, std::max<size_t>((size_t)64 << 20, P->mem.cap / 8));
     P->ck_slots = (int)std::max<size_t>(1, std::min<size_t>((size_t)maxslots, budget / (per * nc)));
     P->ck_roots = (int)std::max<size_t>(1, std::min<size_t>((size_t)np, budget / (per_root * nc)));
     const size_t sbytes = std::max(per * nc * (size_t)P->ck_slots, per_root * nc * (size_t)P->ck_roots);
