@@ -277,8 +277,9 @@ struct dmk_plan_s {
     void* Phi3 = nullptr;
     int* send_level = nullptr;        // sender slot -> level
     // stage pipelines run over slot chunks so that the scratch buffers s1, s2
-    // hold one chunk: ck_slots box slots or ck_roots roots at a time
-    int ck_slots = 1, ck_roots = 1;
+    // hold one chunk: ck_slots merge / interpolation slots, ck_pw plane-wave
+    // slots or ck_roots roots at a time
+    int ck_slots = 1, ck_pw = 1, ck_roots = 1;
     bool ck_on = false;
     int ck0 = 0, ck1 = 0;
     // single-level spectral Ewald plans (DMK_METHOD_EWALD)
@@ -1155,17 +1156,18 @@ int build_plan(dmk_plan_t P, const double* points)
     if (stress)
         P->Phi3 = P->mem.alloc<char>((size_t)P->nsend * 3 * P->H * cs);
     P->Psi = P->mem.alloc<char>((size_t)P->nrecv * 3 * P->H * cs);
-    // scratch: largest intermediate of any stage, per (slot, component)
-    size_t per = 0;
-    per = std::max(per, (size_t)p * p * q * cs);                 // outgoing stage 1
-    per = std::max(per, (size_t)p * q * n1 * cs);                // outgoing stage 2
-    per = std::max(per, (size_t)n1 * n1 * p * cs);               // incoming stage 1
-    per = std::max(per, (size_t)n1 * p * p * cs);                // incoming stage 2
-    per = std::max(per, (size_t)8 * p3 * es);                    // merge/interp stages
-    int maxslots = std::max(P->nsend, P->nrecv);
+    // scratch: largest intermediate of the plane-wave and of the merge /
+    // interpolation stages, per (slot, component)
+    size_t per_pw = 0;
+    per_pw = std::max(per_pw, (size_t)p * p * q * cs);           // outgoing stage 1
+    per_pw = std::max(per_pw, (size_t)p * q * n1 * cs);          // outgoing stage 2
+    per_pw = std::max(per_pw, (size_t)n1 * n1 * p * cs);         // incoming stage 1
+    per_pw = std::max(per_pw, (size_t)n1 * p * p * cs);          // incoming stage 2
+    const size_t per_mg = (size_t)8 * p3 * es;                   // merge/interp stages
+    const int pwslots = std::max({P->nsend, P->nrecv, 1});
+    int mgslots = 1;
     for (auto& L : P->lev)
-        maxslots = std::max(maxslots, L.nparent);
-    maxslots = std::max(maxslots, 1);
+        mgslots = std::max(mgslots, L.nparent);
     size_t per_root = 0;
     {
         const size_t mh = P->root_mh, mf = P->root_mf;
@@ -1177,9 +1179,11 @@ int build_plan(dmk_plan_t P, const double* points)
     size_t budget = (size_t)4 << 30;
     if (P->mem.cap)
         budget = std::min(budget, std::max<size_t>((size_t)64 << 20, P->mem.cap / 8));
-    P->ck_slots = (int)std::max<size_t>(1, std::min<size_t>((size_t)maxslots, budget / (per * nc)));
+    P->ck_slots = (int)std::max<size_t>(1, std::min<size_t>((size_t)mgslots, budget / (per_mg * nc)));
+    P->ck_pw = (int)std::max<size_t>(1, std::min<size_t>((size_t)pwslots, budget / (per_pw * nc)));
     P->ck_roots = (int)std::max<size_t>(1, std::min<size_t>((size_t)np, budget / (per_root * nc)));
-    const size_t sbytes = std::max(per * nc * (size_t)P->ck_slots, per_root * nc * (size_t)P->ck_roots);
+    const size_t sbytes = std::max({per_mg * nc * (size_t)P->ck_slots, per_pw * nc * (size_t)P->ck_pw,
+                                    per_root * nc * (size_t)P->ck_roots});
     P->s1 = P->mem.alloc<char>(sbytes);
     P->s2 = P->mem.alloc<char>(sbytes);
     P->phi_root = P->mem.alloc<char>(nc * P->Hroot * cs * np);
@@ -1273,7 +1277,7 @@ void far_field(dmk_plan_t P, int r, bool record)
     mark(2);
     // outgoing plane waves of the senders: Phi[mx][my][mz], mx >= 0
     const long H = (long)P->H;
-    chunks(P->nsend, P->ck_slots, [&] {
+    chunks(P->nsend, P->ck_pw, [&] {
     stage(P, ST_OUT_HALF, IO_PLAIN, P->Q, p3, P->send_fid, P->s1, p2 * q, nullptr, 0, P->pw_out, p, q, 0, 0, h, M + 1,
           p * p, P->nsend, nullptr, nc);
     stage(P, ST_OUT_FULL, IO_PLAIN, P->s1, p2 * q, nullptr, P->s2, (long)p * q * n1, nullptr, 0, P->pw_out, p, n1, 0,
@@ -1291,7 +1295,7 @@ void far_field(dmk_plan_t P, int r, bool record)
     mark(4);
     // incoming plane waves -> proxy potentials, z-major V[c][b][a]
     launch_zero(P->V, (size_t)P->nf * 3 * p3 * P->es, st);
-    chunks(P->nrecv, P->ck_slots, [&] {
+    chunks(P->nrecv, P->ck_pw, [&] {
     stage(P, ST_IN_FULL, IO_PLAIN, P->Psi, H, nullptr, P->s1, (long)n1 * q * p, nullptr, 0, P->pw_in_full, n1, p, M,
           0, M + 1, h, n1 * q, P->nrecv);
     stage(P, ST_IN_FULL, IO_PLAIN, P->s1, (long)n1 * q * p, nullptr, P->s2, (long)q * p * p, nullptr, 0,
