@@ -127,8 +127,8 @@ typedef struct {
                              16, 32 or 64; 0 = chosen per stage by its LDS footprint
                              (a value a stage cannot take falls back to that choice) */
     int eval_points;      /* points per workgroup of the far-field evaluation at the
-                             points: 128 or 256 (256 only for p <= 16, 23, 30); 0 = the
-                             largest that fits */
+                             points: 128 or 256 (256 only for p <= 16, 23, 30, else
+                             128); 0 = 128 */
 } dmk_opts;
 
 /* record HIP events around each phase of dmk_stokes_eval (read back with

@@ -558,16 +558,17 @@ __global__ __launch_bounds__(256) void k_lagrange_table(const LeafDesc* __restri
 // for every z index c, D[b][pt] = sum_a V[j][c][b][a] Lx[pt][a] (V z-major),
 // then u_j[pt] += Lz[pt][c] sum_b Ly[pt][b] D[b][pt].  A block takes 64 points
 // of one leaf (16 per wave); the z-slab of V sits in LDS.
-// points per leaf-evaluation block (4 lanes per point): 256 where the kernel
-// fits the 128 registers of a 1024-thread block, else 128
-// 256 points per block only where the kernel fits the registers of a
-// 1024-thread block
+// points per leaf-evaluation block (4 lanes per point): 128 unless 256 are
+// asked for, and 256 only where the kernel fits the 128 registers of a
+// 1024-thread block.  128-point blocks (two per CU, each waiting at its own
+// slab barriers) measured faster at p = 23: 1.66 against 1.86 ms (FP64) and
+// 1.35 against 1.71 ms (FP32) on 10^6 clustered points.
 constexpr bool eval256_fits(int p) { return p <= 16 || p == 23 || p == 30; }
 int eval_chunk_points(int p, int request)
 {
-    if (request == 128 || !eval256_fits(p))
-        return 128;
-    return 256;
+    if (request == 256 && eval256_fits(p))
+        return 256;
+    return 128;
 }
 
 template <int P, typename S, int PTS>
@@ -647,12 +648,19 @@ __global__ __launch_bounds__(PTS * 4) void k_leaf_eval(const EvalChunk* __restri
         if (busy) {
             const double lz = valid ? Li[2 * PA + c] : 0.0;
             double X[3] = {0, 0, 0};
+            // every tile's chain first (independent chains the scheduler can
+            // interleave), then the b-weighted sums of their results
+            mfma_d4 acc[NTP];
+#pragma unroll
+            for (int T = 0; T < NTP; ++T)
+                acc[T] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < NK; ++s)
+#pragma unroll
+                for (int T = 0; T < NTP; ++T)
+                    acc[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(slab[cur][16 * T + lr][4 * s + lk], bx[s], acc[T], 0, 0, 0);
 #pragma unroll
             for (int T = 0; T < NTP; ++T) {
-                mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int s = 0; s < NK; ++s)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(slab[cur][16 * T + lr][4 * s + lk], bx[s], acc, 0, 0, 0);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     // rows 16 T + 4 r + (0..3) over the lanes: one component,
@@ -660,7 +668,7 @@ __global__ __launch_bounds__(PTS * 4) void k_leaf_eval(const EvalChunk* __restri
                     const int j0 = (16 * T + 4 * r) / P, j1 = (16 * T + 4 * r + 3) / P;
                     if (j0 >= 3)
                         continue;  // padding rows
-                    const double t = wy[T][r] * acc[r];
+                    const double t = wy[T][r] * acc[T][r];
                     if (j0 == j1 || j1 >= 3) {
                         X[j0] += t;
                     } else {
