@@ -448,8 +448,8 @@ def ewald_variant(args, dev, parity: bool) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="clusters_1e6")
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
